@@ -1,0 +1,277 @@
+"""Seeded synthetic linear systems with outlying singular values / eigenvalues.
+
+This module only draws inputs.  It holds none of the solver's arithmetic and is
+the one piece of code shared by the CPU oracle (``oracle/``), the tests and the
+benchmark.  Every system is consistent (b = A x*), as the convergence theory of
+the paper assumes (Section 2, Theorem 2.1).
+
+Recipes (all seeded; numpy ``default_rng(seed)`` on the CPU, a seeded
+``torch.Generator`` when a torch device is requested for the large sizes):
+
+* Haar-random orthonormal columns: QR of a standard Gaussian matrix with the
+  signs of R's diagonal moved into Q (Mezzadri's fix), so the result is
+  Haar-distributed.
+* General systems (Kaczmarz++): A = U diag(sigma) V^T with U (m x r) and
+  V (n x r) Haar columns, r = min(m, n).  x* ~ N(0, I) (over-determined) or
+  x* = V g, g ~ N(0, I_r) (under-determined, so x* is the minimum-norm
+  solution).  b = A x*.
+* PSD systems (CD++): A = Q diag(lambda) Q^T, symmetrised as (A + A^T)/2,
+  x* ~ N(0, I), b = A x*.
+
+The spectra follow the paper's experimental premise (Section 6): a few large
+outliers over a flat or decaying bulk.  The paper's own matrices (the
+scikit-learn low-rank generator and four ML data sets, Section 6.1) are not
+available; these seeded systems stand in for them.
+
+Draw order inside one recipe is fixed: spectrum bulk, then U (or Q), then V,
+then x* -- so a change to one size never silently reshuffles another.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+__all__ = [
+    "System",
+    "haar_columns",
+    "svd_system",
+    "psd_system",
+    "spectrum_c1",
+    "spectrum_c2",
+    "spectrum_c3",
+    "spectrum_c4",
+    "config",
+    "CONFIGS",
+    "tiny_system",
+    "serving_workload",
+]
+
+
+@dataclasses.dataclass
+class System:
+    """A consistent system A x = b with its planted solution and metadata."""
+
+    A: object          # numpy (m, n) float64, or a torch tensor on `device`
+    b: object          # (m,)
+    xstar: object      # (n,)
+    kind: str          # "general" (Kaczmarz++) or "psd" (CD++)
+    name: str
+    spectrum: np.ndarray
+    params: dict
+
+    @property
+    def shape(self):
+        return tuple(self.A.shape)
+
+
+# ----------------------------------------------------------------------------
+# spectra (numpy, always on the CPU: they are small)
+# ----------------------------------------------------------------------------
+
+def spectrum_c1(rng: np.random.Generator, n: int = 200, n_out: int = 10) -> np.ndarray:
+    """10 outliers log-spaced in [1e2, 1e3], the rest i.i.d. U[1, 2]."""
+    bulk = rng.uniform(1.0, 2.0, size=n - n_out)
+    return np.concatenate([np.geomspace(1e2, 1e3, n_out), bulk])
+
+
+def spectrum_c2(rng: np.random.Generator, n: int = 4096, n_out: int = 32) -> np.ndarray:
+    """Eigenvalues: 32 outliers log-spaced in [1e3, 1e5], the rest U[1, 10]."""
+    bulk = rng.uniform(1.0, 10.0, size=n - n_out)
+    return np.concatenate([np.geomspace(1e3, 1e5, n_out), bulk])
+
+
+def spectrum_c3(rng: np.random.Generator, r: int = 2048, n_out: int = 50) -> np.ndarray:
+    """50 outliers log-spaced in [1e2, 1e4], the rest 1/(1 + 0.01 i), i = 0.."""
+    del rng  # deterministic spectrum
+    tail = 1.0 / (1.0 + 0.01 * np.arange(r - n_out))
+    return np.concatenate([np.geomspace(1e2, 1e4, n_out), tail])
+
+
+def spectrum_c4(rng: np.random.Generator, r: int = 2048, n_out: int = 20) -> np.ndarray:
+    """20 outliers log-spaced in [1e3, 1e4], the rest i.i.d. U[0.5, 1]."""
+    bulk = rng.uniform(0.5, 1.0, size=r - n_out)
+    return np.concatenate([np.geomspace(1e3, 1e4, n_out), bulk])
+
+
+# ----------------------------------------------------------------------------
+# random orthonormal factors
+# ----------------------------------------------------------------------------
+
+def haar_columns(rng: np.random.Generator, n: int, k: int) -> np.ndarray:
+    """n x k matrix with Haar-distributed orthonormal columns (k <= n)."""
+    g = rng.standard_normal((n, k))
+    q, r = np.linalg.qr(g, mode="reduced")
+    d = np.sign(np.diag(r))
+    d[d == 0] = 1.0
+    return q * d
+
+
+def _torch_haar_columns(gen, n: int, k: int, device):
+    import torch
+
+    g = torch.randn((n, k), dtype=torch.float64, device=device, generator=gen)
+    q, r = torch.linalg.qr(g, mode="reduced")
+    d = torch.sign(torch.diagonal(r))
+    d[d == 0] = 1.0
+    return q * d
+
+
+# ----------------------------------------------------------------------------
+# systems
+# ----------------------------------------------------------------------------
+
+def svd_system(m: int, n: int, sigma_fn, seed: int, *, x_in_rowspace: bool = False,
+               device: Optional[str] = None, name: str = "svd") -> System:
+    """A = U diag(sigma) V^T (m x n, rank r = min(m, n)), b = A x*."""
+    r = min(m, n)
+    rng = np.random.default_rng(seed)
+    sigma = np.asarray(sigma_fn(rng, r), dtype=np.float64)
+    assert sigma.shape == (r,)
+    if device is None:
+        U = haar_columns(rng, m, r)
+        V = haar_columns(rng, n, r)
+        A = (U * sigma) @ V.T
+        if x_in_rowspace:
+            xstar = V @ rng.standard_normal(r)
+        else:
+            xstar = rng.standard_normal(n)
+        b = A @ xstar
+    else:
+        import torch
+
+        gen = torch.Generator(device=device)
+        gen.manual_seed(int(seed))
+        U = _torch_haar_columns(gen, m, r, device)
+        V = _torch_haar_columns(gen, n, r, device)
+        sig = torch.as_tensor(sigma, device=device)
+        A = ((U * sig) @ V.T).contiguous()
+        del U
+        if x_in_rowspace:
+            xstar = V @ torch.randn(r, dtype=torch.float64, device=device, generator=gen)
+        else:
+            xstar = torch.randn(n, dtype=torch.float64, device=device, generator=gen)
+        del V
+        b = A @ xstar
+    return System(A=A, b=b, xstar=xstar, kind="general", name=name, spectrum=sigma,
+                  params=dict(m=m, n=n, seed=seed, x_in_rowspace=x_in_rowspace))
+
+
+def psd_system(n: int, eig_fn, seed: int, *, device: Optional[str] = None,
+               name: str = "psd") -> System:
+    """A = Q diag(lambda) Q^T symmetrised, b = A x*, x* ~ N(0, I)."""
+    rng = np.random.default_rng(seed)
+    lam = np.asarray(eig_fn(rng, n), dtype=np.float64)
+    assert lam.shape == (n,)
+    if device is None:
+        Q = haar_columns(rng, n, n)
+        A = (Q * lam) @ Q.T
+        A = 0.5 * (A + A.T)
+        xstar = rng.standard_normal(n)
+        b = A @ xstar
+    else:
+        import torch
+
+        gen = torch.Generator(device=device)
+        gen.manual_seed(int(seed))
+        Q = _torch_haar_columns(gen, n, n, device)
+        A = (Q * torch.as_tensor(lam, device=device)) @ Q.T
+        A = (0.5 * (A + A.T)).contiguous()
+        del Q
+        xstar = torch.randn(n, dtype=torch.float64, device=device, generator=gen)
+        b = A @ xstar
+    return System(A=A, b=b, xstar=xstar, kind="psd", name=name, spectrum=lam,
+                  params=dict(n=n, seed=seed))
+
+
+# ----------------------------------------------------------------------------
+# named workloads
+# ----------------------------------------------------------------------------
+# Each entry: builder + the solver parameters the workload is run with.
+# "scale" variants keep the spectrum's shape (same outlier count and ranges)
+# at sizes the CPU oracle finishes in seconds.
+
+CONFIGS = {
+    # dense consistent 1000 x 200, Kaczmarz++, block 20, lambda 1e-3, online memo
+    "c1": dict(kind="general", m=1000, n=200, spectrum=spectrum_c1, seed=1,
+               s=20, lam=1e-3, memo="online", schedule_seed=101, eta=None),
+    # SPD n = 4096, CD++, block 128, fixed partition into 32 blocks, lambda 1e-8
+    "c2": dict(kind="psd", n=4096, spectrum=spectrum_c2, seed=2,
+               s=128, lam=1e-8, memo="fixed", partition=True, schedule_seed=202, eta=None),
+    # over-determined 65536 x 2048, Kaczmarz++, block 256, fixed partition (256 blocks)
+    "c3": dict(kind="general", m=65536, n=2048, spectrum=spectrum_c3, seed=3,
+               s=256, lam=1e-8, memo="fixed", partition=True, schedule_seed=303, eta=None),
+    # under-determined 2048 x 32768, Kaczmarz++, block 128, lambda 1e-4, online memo
+    "c4": dict(kind="general", m=2048, n=32768, spectrum=spectrum_c4, seed=4,
+               s=128, lam=1e-4, memo="online", schedule_seed=404, eta=None, x_in_rowspace=True),
+    # reduced sizes with the same spectral shape (parity cases the oracle runs in seconds);
+    # sizes chosen so blocks and tiles have ragged tails
+    "c2_small": dict(kind="psd", n=1000, spectrum=spectrum_c2, seed=12,
+                     s=128, lam=1e-8, memo="fixed", partition=True, schedule_seed=212, eta=None),
+    "c3_small": dict(kind="general", m=6000, n=700, spectrum=spectrum_c3, seed=13,
+                     s=256, lam=1e-8, memo="fixed", partition=True, schedule_seed=313, eta=None),
+    "c4_small": dict(kind="general", m=300, n=5000, spectrum=spectrum_c4, seed=14,
+                     s=64, lam=1e-4, memo="online", schedule_seed=414, eta=None, x_in_rowspace=True),
+}
+
+
+def config(name: str, device: Optional[str] = None) -> System:
+    """Build the named workload (see CONFIGS)."""
+    c = CONFIGS[name]
+    if c["kind"] == "psd":
+        n_out = 32
+        fn = lambda rng, n: c["spectrum"](rng, n, n_out)  # noqa: E731
+        sysm = psd_system(c["n"], fn, c["seed"], device=device, name=name)
+    else:
+        sysm = svd_system(c["m"], c["n"], c["spectrum"], c["seed"],
+                          x_in_rowspace=c.get("x_in_rowspace", False),
+                          device=device, name=name)
+    sysm.params.update({k: v for k, v in c.items() if k not in ("spectrum",)})
+    return sysm
+
+
+def tiny_system(kind: str, m: int, n: int, seed: int, cond: float = 10.0,
+                x_in_rowspace: Optional[bool] = None) -> System:
+    """Small well-conditioned system (kappa(A) <= cond) for exact-arithmetic pins.
+
+    Singular values (or eigenvalues) are log-spaced in [1, cond].
+    """
+    if kind == "psd":
+        assert m == n
+        fn = lambda rng, r: np.geomspace(1.0, cond, r)  # noqa: E731
+        return psd_system(n, fn, seed, name=f"tiny_psd_{n}")
+    if x_in_rowspace is None:
+        x_in_rowspace = m < n
+    fn = lambda rng, r: np.geomspace(1.0, cond, r)  # noqa: E731
+    return svd_system(m, n, fn, seed, x_in_rowspace=x_in_rowspace,
+                      name=f"tiny_general_{m}x{n}")
+
+
+def serving_workload(num_requests: int = 512, rate_per_s: float = 200.0, seed: int = 5,
+                     sizes=(512, 1024, 2048, 4096, 8192), tols=(1e-6, 1e-10),
+                     pool_per_size: int = 8):
+    """Arrival process for the serving workload.
+
+    Returns a list of dicts {arrival_s, n, pool_index, tol, x_seed}: Poisson
+    arrivals (exponential gaps of mean 1/rate), sizes and tolerances uniform
+    over the given sets, each request pointing at one of `pool_per_size`
+    distinct PSD matrices of its size (spectrum as in the n = 4096 CD++
+    workload: 32 outliers in [1e3, 1e5], bulk U[1, 10]).
+    """
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate_per_s, size=num_requests)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    ns = rng.choice(np.asarray(sizes), size=num_requests)
+    pools = rng.integers(0, pool_per_size, size=num_requests)
+    tl = rng.choice(np.asarray(tols), size=num_requests)
+    return [dict(arrival_s=float(arrivals[i]), n=int(ns[i]), pool_index=int(pools[i]),
+                 tol=float(tl[i]), x_seed=int(seed * 100003 + i))
+            for i in range(num_requests)]
+
+
+def serving_matrix(n: int, pool_index: int, device: Optional[str] = None) -> System:
+    """The pool_index-th PSD matrix of size n used by the serving workload."""
+    fn = lambda rng, nn: spectrum_c2(rng, nn, 32)  # noqa: E731
+    return psd_system(n, fn, seed=50_000 + 97 * n + pool_index, device=device,
+                      name=f"serve_{n}_{pool_index}")
