@@ -1,0 +1,189 @@
+/*
+ * kpp.h -- C ABI of the MI355X Kaczmarz++ / CD++ block-step library.
+ *
+ * The library solves a consistent linear system A x = b by the accelerated,
+ * Tikhonov-regularized, memoized randomized block step of
+ *   M. Derezinski, D. Needell, E. Rebrova, J. Yang,
+ *   "Randomized Kaczmarz Methods with Beyond-Krylov Convergence" (arXiv 2501.11673):
+ *   - Kaczmarz++ (general m x n, over- or under-determined; Algorithm 5 with the
+ *     exact Cholesky projection, "K++(Cholesky)" of Appendix F.1), and
+ *   - CD++ (square positive semidefinite A; Algorithm 2 without the randomized
+ *     Hadamard preprocessing, "CD++ w/o RHT" of Section 6.3).
+ * One step, for a row block S of size s (Section 1.1, eq. (bk), eq. (momentum)):
+ *   r = A_S x - b_S
+ *   y = (A_S A_S^T + lambda I)^{-1} r      (CD++: (A_SS + lambda I)^{-1} r)
+ *         through the memoized Cholesky factor of that block (Section 4.2, 5.2)
+ *   w = A_S^T y                            (CD++: w = I_S^T y, eq. (cd-update))
+ *   m <- (1 - rho)/(1 + rho) (m - w);  x <- x - w + eta m
+ * with rho revised every 2*zeta steps from block-residual window sums
+ * (Section 5.4, eq. (residual), eq. (weighted)).
+ *
+ * Conventions
+ *   - Every pointer named *_dev is device memory of the context's device
+ *     (for example a torch tensor's data_ptr()).  Host pointers are named *_host.
+ *   - Matrices are row-major FP64 with a leading dimension (lda >= n).
+ *   - The caller owns A, b and x; the library never frees them and they must
+ *     outlive the kpp_system (or the served request) that refers to them.
+ *     The library owns memo caches, low-precision copies, state and workspaces.
+ *   - All work is enqueued on the context's stream (borrowed, never destroyed;
+ *     NULL means the device's null stream).  Calls return after that stream's
+ *     work for the call has completed.
+ *   - Every call returns a kpp_status; negative values are errors, after which
+ *     outputs are unspecified and kpp_last_error() describes the failure.
+ *     No C++ exception crosses this boundary.
+ *   - A context, and the systems created on it, must be used by one host
+ *     thread at a time.
+ */
+#ifndef KPP_H_
+#define KPP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KPP_API __attribute__((visibility("default")))
+#define KPP_ABI_VERSION 1
+
+typedef enum kpp_status {
+  KPP_OK = 0,
+  KPP_NOT_CONVERGED = 1,      /* max_iters reached; x holds the last iterate            */
+  KPP_ERR_INVALID_ARG = -1,   /* a parameter is out of range or a pointer is NULL       */
+  KPP_ERR_SHAPE = -2,         /* inconsistent sizes (lda < n, CD++ with m != n, ...)    */
+  KPP_ERR_NOT_SPD = -3,       /* a regularized block Gram has no Cholesky factor        */
+  KPP_ERR_NONFINITE = -4,     /* A or b holds NaN or Inf                                 */
+  KPP_ERR_OOM = -5,           /* device allocation failed                                */
+  KPP_ERR_HIP = -6,           /* a HIP runtime call failed                               */
+  KPP_ERR_REJECTED = -7,      /* serving: the request does not fit the HBM budget        */
+  KPP_ERR_DEVICE = -8         /* a device-side wait exceeded its bound (never expected)  */
+} kpp_status;
+
+typedef enum kpp_kind {
+  KPP_KACZMARZ = 0,           /* general m x n system: Kaczmarz++                        */
+  KPP_CD_PSD = 1              /* square PSD system: CD++                                 */
+} kpp_kind;
+
+typedef enum kpp_memo {
+  KPP_MEMO_OFF = 0,           /* a new random block at every step, factor not kept
+                                 ("w/o Memo", Section 6.2)                                */
+  KPP_MEMO_ONLINE = 1,        /* Bernoulli(min(1, B0/t)) new blocks (Section 5.2)        */
+  KPP_MEMO_FIXED = 2          /* collection drawn up front (Algorithm 1): a random
+                                 partition, or num_blocks random s-subsets               */
+} kpp_memo;
+
+typedef enum kpp_precision {
+  KPP_FP64 = 0,               /* every product in FP64                                   */
+  KPP_MIXED_FP32 = 1,         /* FP32 block products and Grams, FP64 residual, factor
+                                 of ill-conditioned blocks and x accumulation, with
+                                 iterative refinement (outer loop FP64)                  */
+  KPP_MIXED_BF16 = 2          /* as MIXED_FP32 with BF16 storage of A (FP32 accumulate)  */
+} kpp_precision;
+
+/* Solver parameters.  kpp_params_default() fills every field. */
+typedef struct kpp_params {
+  int32_t block_size;         /* s, 1 <= s <= rows (m for Kaczmarz++, n for CD++)       */
+  int32_t memo;               /* kpp_memo                                                */
+  int32_t num_blocks;         /* FIXED without partition: B >= 1                         */
+  int32_t fixed_partition;    /* FIXED: 1 = random partition into ceil(rows/s) blocks    */
+  int32_t accel;              /* 0: eta = 0 ("w/o Accel", Table 1)                       */
+  int32_t adaptive_rho;       /* 1: revise rho at checkpoints (Section 5.4)              */
+  int32_t precision;          /* kpp_precision                                           */
+  int32_t confirm_true_residual; /* 1: a candidate stop is confirmed by ||Ax-b|| (FP64) */
+  double lambda;              /* lambda >= 0 (default 1e-8, Section 6.2)                */
+  double tol;                 /* eps: stop when ||Ax - b|| <= eps ||b|| (eq. (residual-error)) */
+  double eta;                 /* < 0: default s / (2 min(m, n)) (CD++: s / (2n))         */
+  double rho0;                /* initial rho (default 0, Algorithm 2)                    */
+  int64_t max_iters;          /* upper bound on block steps                              */
+  uint64_t seed;              /* schedule seed (SplitMix64 draws; see kpp_schedule_generate) */
+  int32_t keep_memo;          /* 1: keep factors from an earlier solve with the same
+                                 schedule settings; 0: start with an empty cache          */
+  int32_t refine_max_rounds;  /* mixed precision: outer refinement rounds (default 12)   */
+  double inner_tol;           /* mixed precision: inner relative tolerance (default 1e-5) */
+  int32_t engine;             /* 0: auto, 1: one launch per phase, 2: fused persistent  */
+  int32_t reserved0;
+  double reserved1[4];
+} kpp_params;
+
+/* Per-solve report. */
+typedef struct kpp_result {
+  int64_t iters;              /* block steps executed (all refinement rounds)            */
+  int64_t memo_hits;
+  int64_t memo_misses;        /* factorizations performed                               */
+  int64_t factors_fp64;       /* mixed precision: blocks factored in FP64                */
+  int32_t converged;
+  int32_t refinements;        /* outer refinement rounds (mixed precision)               */
+  int32_t checkpoints;
+  int32_t engine_used;
+  double est_rel_res;         /* sqrt(E1) / ||b|| at the last checkpoint                 */
+  double true_rel_res;        /* ||A x - b|| / ||b|| in FP64 at return                   */
+  double rho_final;
+  double seconds_total;
+  double seconds_factor;      /* time in Gram + Cholesky                                 */
+  double flops;               /* 2sn (+2sn K++) + 2s^2 + 5n per step; s^3/3 (+s^2 n) per factor */
+  double bytes_algorithmic;   /* s n b_A + factor + vectors per step (see kpp_step_bytes) */
+  double reserved[4];
+} kpp_result;
+
+typedef struct kpp_context kpp_context;
+typedef struct kpp_system kpp_system;
+typedef struct kpp_server kpp_server;
+
+/* ABI version (KPP_ABI_VERSION). */
+KPP_API int32_t kpp_abi_version(void);
+
+/* Message for the last failed call on this host thread (never NULL). */
+KPP_API const char* kpp_last_error(void);
+
+/* Defaults of Algorithms 2 and 5: lambda 1e-8, rho0 0, eta from s and the
+ * shape, zeta = ceil(rows / s), online memoization, acceleration on. */
+KPP_API kpp_status kpp_params_default(kpp_params* p, int32_t kind);
+
+/* Context on HIP device `device`, enqueueing on `hip_stream` (a hipStream_t,
+ * borrowed; may be NULL). */
+KPP_API kpp_status kpp_context_create(int32_t device, void* hip_stream, kpp_context** out);
+KPP_API kpp_status kpp_context_destroy(kpp_context* ctx);
+
+/* A system A x = b (Section 1.1).  A_dev: m x n row-major FP64 with leading
+ * dimension lda >= n; b_dev: m values.  kind = KPP_CD_PSD requires m == n and
+ * A symmetric positive semidefinite (only the entries the blocks touch are
+ * read).  Checks that A and b are finite (KPP_ERR_NONFINITE). */
+KPP_API kpp_status kpp_system_create(kpp_context* ctx, int32_t kind, int64_t m, int64_t n,
+                                     const double* A_dev, int64_t lda, const double* b_dev,
+                                     kpp_system** out);
+KPP_API kpp_status kpp_system_destroy(kpp_system* sys);
+
+/* Run the solver from x_dev (in: x0, out: final iterate; n FP64 values).
+ * Returns KPP_OK when ||A x - b|| <= tol ||b|| was confirmed, KPP_NOT_CONVERGED
+ * when max_iters steps ran first.  `res` may be NULL. */
+KPP_API kpp_status kpp_solve(kpp_system* sys, const kpp_params* p, double* x_dev,
+                             kpp_result* res);
+
+/* The block schedule kpp_solve uses for these settings, on the host (Section
+ * 5.2; Algorithms 1, 2, 5).  rows = m (Kaczmarz++) or n (CD++).  Writes the
+ * block id of each of the T steps to step_block_host[T] and each block's rows
+ * (sorted ascending) to block_rows_host[b * s + i], its size to
+ * block_len_host[b], for b < *num_blocks_out (at most blocks_cap blocks).
+ * SplitMix64 draws as documented in the library's schedule source. */
+KPP_API kpp_status kpp_schedule_generate(int32_t kind, int64_t m, int64_t n, const kpp_params* p,
+                                         int64_t T, int32_t* step_block_host,
+                                         int32_t* block_rows_host, int32_t* block_len_host,
+                                         int32_t blocks_cap, int32_t* num_blocks_out);
+
+/* Regularized block Grams and their Cholesky factors on the device (the memo
+ * miss path, Algorithm 1 and Algorithm 2).  rows_host[b * s + i], i <
+ * len_host[b]: the rows of block b.  L_dev receives nb column-major s x s
+ * lower factors (entry (i, j) of block b at L_dev[b*s*s + j*s + i]; the strict
+ * upper triangle is zeroed).  Returns KPP_ERR_NOT_SPD if a Gram has no factor. */
+KPP_API kpp_status kpp_block_factor(kpp_system* sys, int32_t s, double lambda, int32_t nb,
+                                    const int32_t* rows_host, const int32_t* len_host,
+                                    double* L_dev);
+
+/* ||A x - b||_2 in FP64 (eq. (residual-error)); x_dev device, result on host. */
+KPP_API kpp_status kpp_residual_norm(kpp_system* sys, const double* x_dev, double* out_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KPP_H_ */

@@ -1,0 +1,210 @@
+"""Python binding of libkpp (include/kpp.h): MI355X Kaczmarz++ / CD++ block step.
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+The functions keep the C names.  Device buffers are passed as integer device
+addresses (for example ``tensor.data_ptr()``); streams as ``hipStream_t``
+handles (``torch.cuda.current_stream().cuda_stream``).  Import fails loudly if
+the library has not been built (``python paper_2501_11673_amd/build.py``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkpp.so")
+
+KPP_OK = 0
+KPP_NOT_CONVERGED = 1
+KPP_ERR_INVALID_ARG = -1
+KPP_ERR_SHAPE = -2
+KPP_ERR_NOT_SPD = -3
+KPP_ERR_NONFINITE = -4
+KPP_ERR_OOM = -5
+KPP_ERR_HIP = -6
+KPP_ERR_REJECTED = -7
+KPP_ERR_DEVICE = -8
+
+KPP_KACZMARZ = 0
+KPP_CD_PSD = 1
+
+KPP_MEMO_OFF = 0
+KPP_MEMO_ONLINE = 1
+KPP_MEMO_FIXED = 2
+
+KPP_FP64 = 0
+KPP_MIXED_FP32 = 1
+KPP_MIXED_BF16 = 2
+
+KPP_ENGINE_AUTO = 0
+KPP_ENGINE_LAUNCH = 1
+KPP_ENGINE_FUSED = 2
+
+_STATUS_NAMES = {v: k for k, v in globals().items() if k.startswith(("KPP_OK", "KPP_NOT", "KPP_ERR"))}
+
+
+class kpp_params(ctypes.Structure):
+    _fields_ = [
+        ("block_size", ctypes.c_int32),
+        ("memo", ctypes.c_int32),
+        ("num_blocks", ctypes.c_int32),
+        ("fixed_partition", ctypes.c_int32),
+        ("accel", ctypes.c_int32),
+        ("adaptive_rho", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("confirm_true_residual", ctypes.c_int32),
+        ("lambda_", ctypes.c_double),
+        ("tol", ctypes.c_double),
+        ("eta", ctypes.c_double),
+        ("rho0", ctypes.c_double),
+        ("max_iters", ctypes.c_int64),
+        ("seed", ctypes.c_uint64),
+        ("keep_memo", ctypes.c_int32),
+        ("refine_max_rounds", ctypes.c_int32),
+        ("inner_tol", ctypes.c_double),
+        ("engine", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("reserved1", ctypes.c_double * 4),
+    ]
+
+
+class kpp_result(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int64),
+        ("memo_hits", ctypes.c_int64),
+        ("memo_misses", ctypes.c_int64),
+        ("factors_fp64", ctypes.c_int64),
+        ("converged", ctypes.c_int32),
+        ("refinements", ctypes.c_int32),
+        ("checkpoints", ctypes.c_int32),
+        ("engine_used", ctypes.c_int32),
+        ("est_rel_res", ctypes.c_double),
+        ("true_rel_res", ctypes.c_double),
+        ("rho_final", ctypes.c_double),
+        ("seconds_total", ctypes.c_double),
+        ("seconds_factor", ctypes.c_double),
+        ("flops", ctypes.c_double),
+        ("bytes_algorithmic", ctypes.c_double),
+        ("reserved", ctypes.c_double * 4),
+    ]
+
+    def as_dict(self):
+        return {k: (getattr(self, k) if k != "reserved" else None) for k, _ in self._fields_
+                if k != "reserved"}
+
+
+class KppError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build the HIP library first "
+            "(python paper_2501_11673_amd/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "kpp_abi_version": (i32, []),
+        "kpp_last_error": (ctypes.c_char_p, []),
+        "kpp_params_default": (i32, [P(kpp_params), i32]),
+        "kpp_context_create": (i32, [i32, vp, P(vp)]),
+        "kpp_context_destroy": (i32, [vp]),
+        "kpp_system_create": (i32, [vp, i32, i64, i64, vp, i64, vp, P(vp)]),
+        "kpp_system_destroy": (i32, [vp]),
+        "kpp_solve": (i32, [vp, P(kpp_params), vp, P(kpp_result)]),
+        "kpp_schedule_generate": (i32, [i32, i64, i64, P(kpp_params), i64, P(i32), P(i32), P(i32),
+                                        i32, P(i32)]),
+        "kpp_block_factor": (i32, [vp, i32, f64, i32, P(i32), P(i32), vp]),
+        "kpp_residual_norm": (i32, [vp, vp, P(f64)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("kpp_abi_version", "kpp_last_error", "kpp_params_default", "kpp_context_create",
+            "kpp_context_destroy", "kpp_system_create", "kpp_system_destroy", "kpp_solve",
+            "kpp_schedule_generate", "kpp_block_factor", "kpp_residual_norm")
+
+
+def _check(status):
+    if status < 0:
+        raise KppError(status, kpp_last_error())
+    return status
+
+
+def kpp_abi_version() -> int:
+    return _lib.kpp_abi_version()
+
+
+def kpp_last_error() -> str:
+    return _lib.kpp_last_error().decode()
+
+
+def kpp_params_default(kind: int) -> kpp_params:
+    p = kpp_params()
+    _check(_lib.kpp_params_default(ctypes.byref(p), kind))
+    return p
+
+
+def kpp_context_create(device: int = 0, hip_stream: int = 0) -> int:
+    out = ctypes.c_void_p()
+    _check(_lib.kpp_context_create(device, ctypes.c_void_p(hip_stream), ctypes.byref(out)))
+    return out.value
+
+
+def kpp_context_destroy(ctx: int) -> None:
+    _check(_lib.kpp_context_destroy(ctypes.c_void_p(ctx)))
+
+
+def kpp_system_create(ctx: int, kind: int, m: int, n: int, A_dev: int, lda: int, b_dev: int) -> int:
+    out = ctypes.c_void_p()
+    _check(_lib.kpp_system_create(ctypes.c_void_p(ctx), kind, m, n, ctypes.c_void_p(A_dev), lda,
+                                  ctypes.c_void_p(b_dev), ctypes.byref(out)))
+    return out.value
+
+
+def kpp_system_destroy(sys_: int) -> None:
+    _check(_lib.kpp_system_destroy(ctypes.c_void_p(sys_)))
+
+
+def kpp_solve(sys_: int, params: kpp_params, x_dev: int):
+    """Returns (status, kpp_result); raises KppError on a negative status."""
+    res = kpp_result()
+    st = _check(_lib.kpp_solve(ctypes.c_void_p(sys_), ctypes.byref(params), ctypes.c_void_p(x_dev),
+                               ctypes.byref(res)))
+    return st, res
+
+
+def kpp_schedule_generate(kind: int, m: int, n: int, params: kpp_params, T: int, blocks_cap: int):
+    """Returns (step_block[T], block_rows[nb][s], block_len[nb]) as Python lists."""
+    s = params.block_size
+    steps = (ctypes.c_int32 * max(T, 1))()
+    rows = (ctypes.c_int32 * max(blocks_cap * s, 1))()
+    lens = (ctypes.c_int32 * max(blocks_cap, 1))()
+    nb = ctypes.c_int32()
+    _check(_lib.kpp_schedule_generate(kind, m, n, ctypes.byref(params), T, steps, rows, lens,
+                                      blocks_cap, ctypes.byref(nb)))
+    k = nb.value
+    return (list(steps[:T]), [list(rows[b * s:(b + 1) * s]) for b in range(k)], list(lens[:k]))
+
+
+def kpp_block_factor(sys_: int, s: int, lam: float, rows, lens, L_dev: int) -> None:
+    nb = len(lens)
+    r = (ctypes.c_int32 * max(nb * s, 1))(*[int(v) for v in rows])
+    ln = (ctypes.c_int32 * max(nb, 1))(*[int(v) for v in lens])
+    _check(_lib.kpp_block_factor(ctypes.c_void_p(sys_), s, lam, nb, r, ln, ctypes.c_void_p(L_dev)))
+
+
+def kpp_residual_norm(sys_: int, x_dev: int) -> float:
+    out = ctypes.c_double()
+    _check(_lib.kpp_residual_norm(ctypes.c_void_p(sys_), ctypes.c_void_p(x_dev), ctypes.byref(out)))
+    return out.value

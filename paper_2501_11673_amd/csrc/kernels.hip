@@ -1,0 +1,427 @@
+// HIP kernels (gfx950) of the block step: one launch per phase.
+//
+//   block gemv        r = A_S x - b_S                    (Algorithm 5 / 2: "r_t <- A_S x_t - b_S")
+//   block project     y = (L L^T)^{-1} r, window sums, checkpoint (Section 5.4)
+//   update            m <- c (m - w), x <- x - w + eta m  (eq. (momentum)) with
+//                     w = A_S^T y (eq. (bk)) or I_S^T y (eq. (cd-update))
+//   gram / cholesky   memo miss: G = A_S A_S^T + lam I or A_SS + lam I, L = chol(G)
+//   residual          ||A x - b||^2 (eq. (residual-error))
+//
+// Every reduction runs in a fixed order so that a run is bitwise repeatable.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace kpp {
+namespace {
+
+constexpr int kT = 256;  // threads per workgroup (4 waves of 64)
+
+// Sum over the 256 threads of a workgroup; the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = (red[0] + red[1]) + (red[2] + red[3]);
+  return r;
+}
+
+__device__ __forceinline__ double rho_from_rate(double rhat, int zeta) {
+  if (!(rhat < 1.0)) return 0.0;
+  double r = 1.0 - pow(rhat, 1.0 / static_cast<double>(zeta));
+  return fmin(1.0, fmax(0.0, r));
+}
+
+// --------------------------------------------------------------------------
+// r-partials: grid (P, sb); workgroup (p, i) sums columns [p*chunk, (p+1)*chunk)
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(kT) void k_block_gemv_partial(
+    const double* __restrict__ A, int64_t lda, int64_t n, const int32_t* __restrict__ rows,
+    const double* __restrict__ x, double* __restrict__ rpart, int32_t P, int64_t chunk) {
+  __shared__ double red[4];
+  const int i = blockIdx.y;
+  const int p = blockIdx.x;
+  const double* Ai = A + static_cast<int64_t>(rows[i]) * lda;
+  const int64_t j0 = static_cast<int64_t>(p) * chunk;
+  const int64_t j1 = min(n, j0 + chunk);
+  double acc = 0.0;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += kT) acc = fma(Ai[j], x[j], acc);
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) rpart[static_cast<int64_t>(i) * P + p] = acc;
+}
+
+// --------------------------------------------------------------------------
+// projection solve and checkpoint bookkeeping: one workgroup
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(kT) void k_block_project(
+    const double* __restrict__ rpart, int32_t P, const double* __restrict__ b,
+    const int32_t* __restrict__ rows, int32_t sb, const double* __restrict__ L, int32_t ldl,
+    double* __restrict__ y, DevState* __restrict__ ds, int32_t zeta, int32_t adaptive) {
+  __shared__ double r[kMaxBlock];
+  __shared__ double z[kMaxBlock];
+  __shared__ double yy[kMaxBlock];
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  double part = 0.0;
+  for (int i = tid; i < sb; i += kT) {
+    const double* rp = rpart + static_cast<int64_t>(i) * P;
+    double acc = 0.0;
+    for (int p = 0; p < P; ++p) acc += rp[p];
+    const double ri = acc - b[rows[i]];
+    r[i] = ri;
+    part = fma(ri, ri, part);
+  }
+  const double rr = block_sum(part, red);
+  // forward substitution z = L^{-1} r, column by column
+  for (int j = 0; j < sb; ++j) {
+    __syncthreads();
+    const double zj = r[j] / L[static_cast<int64_t>(j) * ldl + j];
+    for (int i = j + 1 + tid; i < sb; i += kT)
+      r[i] = fma(-L[static_cast<int64_t>(j) * ldl + i], zj, r[i]);
+    if (tid == 0) z[j] = zj;
+  }
+  // back substitution y = L^{-T} z
+  for (int j = sb - 1; j >= 0; --j) {
+    __syncthreads();
+    const double yj = z[j] / L[static_cast<int64_t>(j) * ldl + j];
+    for (int i = tid; i < j; i += kT) z[i] = fma(-L[static_cast<int64_t>(i) * ldl + j], yj, z[i]);
+    if (tid == 0) yy[j] = yj;
+  }
+  __syncthreads();
+  for (int i = tid; i < sb; i += kT) y[i] = yy[i];
+  if (tid == 0) {
+    DevState s = *ds;
+    const double rho = s.rho;
+    s.c = (1.0 - rho) / (1.0 + rho);
+    const int64_t period = 2 * static_cast<int64_t>(zeta);
+    const int64_t ph = s.t % period;
+    if (ph < zeta)
+      s.E0 += rr;
+    else
+      s.E1 += rr;
+    if (ph == period - 1) {
+      s.ckpts += 1;
+      s.last_E1 = s.E1;
+      s.rho_before = rho;
+      s.cand = (s.E1 <= s.thr) ? 1 : 0;
+      if (adaptive && s.E0 > 0.0) {
+        const double q = s.E1 / s.E0;
+        if (!s.have_rhat) {
+          s.rhat = q;
+          s.have_rhat = 1;
+        } else {
+          const double li = log(static_cast<double>(s.ckpt));
+          const double li1 = log(static_cast<double>(s.ckpt) + 1.0);
+          const double w = exp(li * li - li1 * li1);
+          s.rhat = w * s.rhat + (1.0 - w) * q;
+        }
+        s.ckpt += 1;
+        s.rho = rho_from_rate(s.rhat, zeta);
+      }
+      s.E0 = 0.0;
+      s.E1 = 0.0;
+    }
+    s.t += 1;
+    *ds = s;
+  }
+}
+
+// --------------------------------------------------------------------------
+// momentum + iterate update over all n coordinates
+// --------------------------------------------------------------------------
+template <int KIND>
+__global__ __launch_bounds__(kT) void k_update(const double* __restrict__ A, int64_t lda,
+                                               int64_t n, const int32_t* __restrict__ rows,
+                                               int32_t sb, const double* __restrict__ y,
+                                               const DevState* __restrict__ ds, double eta,
+                                               double* __restrict__ x, double* __restrict__ mom) {
+  __shared__ double ys[kMaxBlock];
+  __shared__ int32_t rs[kMaxBlock];
+  for (int i = threadIdx.x; i < sb; i += kT) {
+    ys[i] = y[i];
+    rs[i] = rows[i];
+  }
+  __syncthreads();
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+  if (j >= n) return;
+  double w = 0.0;
+  if (KIND == 0) {
+    for (int i = 0; i < sb; ++i) w = fma(A[static_cast<int64_t>(rs[i]) * lda + j], ys[i], w);
+  } else {
+    int lo = 0, hi = sb;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (rs[mid] < j)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    if (lo < sb && rs[lo] == j) w = ys[lo];
+  }
+  const double c = ds->c;
+  const double mn = __dmul_rn(c, __dsub_rn(mom[j], w));
+  mom[j] = mn;
+  x[j] = __dadd_rn(__dsub_rn(x[j], w), __dmul_rn(eta, mn));
+}
+
+// --------------------------------------------------------------------------
+// memo miss: regularized Grams (lower part, column-major slots)
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(kT) void k_gram_kpp(const double* __restrict__ A, int64_t lda,
+                                                 int64_t n, const int32_t* __restrict__ rows,
+                                                 const int32_t* __restrict__ lens, int32_t s,
+                                                 double lambda, double* __restrict__ G,
+                                                 const int32_t* __restrict__ slot_of) {
+  __shared__ double As[32][33];
+  __shared__ double Bs[32][33];
+  const int blk = blockIdx.z;
+  const int sb = lens[blk];
+  const int ti = blockIdx.x, tk = blockIdx.y;
+  const int i0 = ti * 32, k0 = tk * 32;
+  if (ti < tk || i0 >= sb || k0 >= sb) return;  // uniform over the workgroup
+  const int32_t* R = rows + static_cast<int64_t>(blk) * s;
+  double* Gb = G + static_cast<int64_t>(slot_of[blk]) * s * s;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double a00 = 0, a01 = 0, a10 = 0, a11 = 0;
+  for (int64_t j0 = 0; j0 < n; j0 += 32) {
+    for (int e = threadIdx.x; e < 1024; e += kT) {
+      const int rr = e >> 5, cc = e & 31;
+      const int64_t j = j0 + cc;
+      double va = 0.0, vb = 0.0;
+      if (j < n) {
+        if (i0 + rr < sb) va = A[static_cast<int64_t>(R[i0 + rr]) * lda + j];
+        if (k0 + rr < sb) vb = A[static_cast<int64_t>(R[k0 + rr]) * lda + j];
+      }
+      As[rr][cc] = va;
+      Bs[rr][cc] = vb;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int cc = 0; cc < 32; ++cc) {
+      const double p0 = As[ty * 2][cc], p1 = As[ty * 2 + 1][cc];
+      const double q0 = Bs[tx * 2][cc], q1 = Bs[tx * 2 + 1][cc];
+      a00 = fma(p0, q0, a00);
+      a01 = fma(p0, q1, a01);
+      a10 = fma(p1, q0, a10);
+      a11 = fma(p1, q1, a11);
+    }
+    __syncthreads();
+  }
+  const double acc[2][2] = {{a00, a01}, {a10, a11}};
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int i = i0 + ty * 2 + a, k = k0 + tx * 2 + c;
+      if (i < sb && k < sb && i >= k) Gb[static_cast<int64_t>(k) * s + i] = acc[a][c] + (i == k ? lambda : 0.0);
+    }
+}
+
+__global__ __launch_bounds__(kT) void k_gram_cd(const double* __restrict__ A, int64_t lda,
+                                                const int32_t* __restrict__ rows,
+                                                const int32_t* __restrict__ lens, int32_t s,
+                                                double lambda, double* __restrict__ G,
+                                                const int32_t* __restrict__ slot_of) {
+  const int blk = blockIdx.x;
+  const int sb = lens[blk];
+  const int32_t* R = rows + static_cast<int64_t>(blk) * s;
+  double* Gb = G + static_cast<int64_t>(slot_of[blk]) * s * s;
+  for (int e = threadIdx.x; e < sb * sb; e += kT) {
+    const int k = e / sb, i = e - k * sb;
+    if (i >= k) Gb[static_cast<int64_t>(k) * s + i] = A[static_cast<int64_t>(R[i]) * lda + R[k]] + (i == k ? lambda : 0.0);
+  }
+}
+
+// --------------------------------------------------------------------------
+// memo miss: Cholesky, one workgroup per block (right-looking, column by column)
+// --------------------------------------------------------------------------
+template <bool IN_LDS>
+__global__ __launch_bounds__(kT) void k_cholesky(double* __restrict__ G, int32_t s,
+                                                 const int32_t* __restrict__ lens,
+                                                 const int32_t* __restrict__ slot_of,
+                                                 int32_t* __restrict__ err) {
+  extern __shared__ double lds[];
+  const int blk = blockIdx.x;
+  const int sb = lens[blk];
+  double* Gb = G + static_cast<int64_t>(slot_of[blk]) * s * s;
+  double* M;
+  int ld;
+  if (IN_LDS) {
+    M = lds;
+    ld = sb;
+    for (int e = threadIdx.x; e < sb * sb; e += kT) {
+      const int k = e / sb, i = e - k * sb;
+      M[k * sb + i] = (i >= k) ? Gb[static_cast<int64_t>(k) * s + i] : 0.0;
+    }
+  } else {
+    M = Gb;
+    ld = s;
+  }
+  int bad = 0;
+  for (int j = 0; j < sb; ++j) {
+    __syncthreads();
+    double d = M[static_cast<int64_t>(j) * ld + j];
+    if (!(d > 0.0)) bad = 1;
+    d = sqrt(d);
+    for (int i = j + 1 + threadIdx.x; i < sb; i += kT) M[static_cast<int64_t>(j) * ld + i] /= d;
+    __syncthreads();
+    if (threadIdx.x == 0) M[static_cast<int64_t>(j) * ld + j] = d;
+    const int rem = sb - j - 1;
+    for (int idx = threadIdx.x; idx < rem * rem; idx += kT) {
+      const int kk = idx / rem, ii = idx - kk * rem;
+      if (ii >= kk) {
+        const int k = j + 1 + kk, i = j + 1 + ii;
+        M[static_cast<int64_t>(k) * ld + i] =
+            fma(-M[static_cast<int64_t>(j) * ld + i], M[static_cast<int64_t>(j) * ld + k],
+                M[static_cast<int64_t>(k) * ld + i]);
+      }
+    }
+  }
+  __syncthreads();
+  if (bad && threadIdx.x == 0) atomicOr(err, 1);
+  // write back L with zero strict upper triangle and zero padding
+  for (int e = threadIdx.x; e < s * s; e += kT) {
+    const int k = e / s, i = e - k * s;
+    double v = 0.0;
+    if (i < sb && k < sb && i >= k) v = IN_LDS ? M[k * sb + i] : Gb[static_cast<int64_t>(k) * s + i];
+    if (IN_LDS || !(i < sb && k < sb && i >= k)) Gb[static_cast<int64_t>(k) * s + i] = v;
+  }
+}
+
+// --------------------------------------------------------------------------
+// ||A x - b||^2: one wave per row, 4 rows per workgroup; then a fixed-order sum
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(kT) void k_residual_rows(const double* __restrict__ A, int64_t lda,
+                                                      int64_t m, int64_t n,
+                                                      const double* __restrict__ x,
+                                                      const double* __restrict__ b,
+                                                      double* __restrict__ rowsq) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= m) return;
+  const double* Ai = A + i * lda;
+  double acc = 0.0;
+  for (int64_t j = lane; j < n; j += 64) acc = fma(Ai[j], x[j], acc);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) {
+    const double r = acc - b[i];
+    rowsq[i] = r * r;
+  }
+}
+
+__global__ __launch_bounds__(kT) void k_sum(const double* __restrict__ v, int64_t len,
+                                            double* __restrict__ out) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < len; i += kT) acc += v[i];
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) *out = acc;
+}
+
+__global__ __launch_bounds__(kT) void k_check_finite(const double* __restrict__ A, int64_t lda,
+                                                     int64_t m, int64_t n,
+                                                     const double* __restrict__ b,
+                                                     int32_t* __restrict__ flag) {
+  const int64_t i = blockIdx.x;
+  int bad = 0;
+  for (int64_t j = threadIdx.x; j < n; j += kT) bad |= !isfinite(A[i * lda + j]);
+  if (threadIdx.x == 0) bad |= !isfinite(b[i]);
+  if (bad) atomicOr(flag, 1);
+  (void)m;
+}
+
+__global__ void k_state_init(DevState* ds, double rho0, double thr) {
+  DevState s{};
+  s.rho = rho0;
+  s.c = (1.0 - rho0) / (1.0 + rho0);
+  s.thr = thr;
+  s.rho_before = rho0;
+  *ds = s;
+}
+
+}  // namespace
+
+void launch_block_gemv_partial(const double* A, int64_t lda, int64_t n, const int32_t* rows,
+                               int32_t sb, const double* x, double* rpart, int32_t P,
+                               int64_t chunk, hipStream_t st) {
+  dim3 grid(P, sb);
+  hipLaunchKernelGGL(k_block_gemv_partial, grid, dim3(kT), 0, st, A, lda, n, rows, x, rpart, P,
+                     chunk);
+}
+
+void launch_block_project(const double* rpart, int32_t P, const double* b, const int32_t* rows,
+                          int32_t sb, const double* L, int32_t ldl, double* y, DevState* ds,
+                          int32_t zeta, int32_t adaptive, hipStream_t st) {
+  hipLaunchKernelGGL(k_block_project, dim3(1), dim3(kT), 0, st, rpart, P, b, rows, sb, L, ldl, y,
+                     ds, zeta, adaptive);
+}
+
+void launch_update(int32_t kind, const double* A, int64_t lda, int64_t n, const int32_t* rows,
+                   int32_t sb, const double* y, const DevState* ds, double eta, double* x,
+                   double* mom, hipStream_t st) {
+  dim3 grid(static_cast<unsigned>((n + kT - 1) / kT));
+  if (kind == 0)
+    hipLaunchKernelGGL(k_update<0>, grid, dim3(kT), 0, st, A, lda, n, rows, sb, y, ds, eta, x, mom);
+  else
+    hipLaunchKernelGGL(k_update<1>, grid, dim3(kT), 0, st, A, lda, n, rows, sb, y, ds, eta, x, mom);
+}
+
+void launch_gram(int32_t kind, const double* A, int64_t lda, int64_t n, const int32_t* rows,
+                 const int32_t* lens, int32_t s, int32_t nb, double lambda, double* G,
+                 const int32_t* slot_of, hipStream_t st) {
+  if (nb <= 0) return;
+  if (kind == 0) {
+    const int nt = (s + 31) / 32;
+    hipLaunchKernelGGL(k_gram_kpp, dim3(nt, nt, nb), dim3(kT), 0, st, A, lda, n, rows, lens, s,
+                       lambda, G, slot_of);
+  } else {
+    hipLaunchKernelGGL(k_gram_cd, dim3(nb), dim3(kT), 0, st, A, lda, rows, lens, s, lambda, G,
+                       slot_of);
+  }
+}
+
+void launch_cholesky(double* G, int32_t s, const int32_t* lens, int32_t nb, const int32_t* slot_of,
+                     int32_t* err, hipStream_t st) {
+  if (nb <= 0) return;
+  if (s <= kLdsCholMax) {
+    const size_t lds = static_cast<size_t>(s) * s * sizeof(double);
+    static bool attr_set = false;
+    if (!attr_set) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cholesky<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                static_cast<int>(kLdsCholMax * kLdsCholMax * sizeof(double)));
+      attr_set = true;
+    }
+    hipLaunchKernelGGL(k_cholesky<true>, dim3(nb), dim3(kT), lds, st, G, s, lens, slot_of, err);
+  } else {
+    hipLaunchKernelGGL(k_cholesky<false>, dim3(nb), dim3(kT), 0, st, G, s, lens, slot_of, err);
+  }
+}
+
+void launch_residual_sq(const double* A, int64_t lda, int64_t m, int64_t n, const double* x,
+                        const double* b, double* part, int32_t nparts, double* out,
+                        hipStream_t st) {
+  (void)nparts;
+  const unsigned g = static_cast<unsigned>((m + 3) / 4);
+  hipLaunchKernelGGL(k_residual_rows, dim3(g), dim3(kT), 0, st, A, lda, m, n, x, b, part);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(kT), 0, st, part, m, out);
+}
+
+void launch_check_finite(const double* A, int64_t lda, int64_t m, int64_t n, const double* b,
+                         int32_t* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_check_finite, dim3(static_cast<unsigned>(m)), dim3(kT), 0, st, A, lda, m, n,
+                     b, flag);
+}
+
+void launch_state_init(DevState* ds, double rho0, double thr, hipStream_t st) {
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, st, ds, rho0, thr);
+}
+
+}  // namespace kpp

@@ -1,0 +1,67 @@
+// Internal kernel launchers of the block-step library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace kpp {
+
+// Solver scalars kept on the device so that no step needs the host
+// (Section 5.4: window sums, checkpoint counter, running rate estimate).
+struct DevState {
+  double rho;        // momentum parameter for the next step
+  double rhat;       // weighted average of window ratios (eq. (weighted))
+  double E0, E1;     // window sums of ||r_t||^2 (Algorithms 2 and 5)
+  double c;          // (1 - rho)/(1 + rho) used by the current step's update
+  double thr;        // eps^2 ||b||^2
+  double last_E1;    // E1 of the last checkpoint (estimated residual)
+  double rho_before; // rho before the last checkpoint's revision
+  int64_t t;         // steps completed
+  int32_t ckpt;      // checkpoints that revised rho
+  int32_t have_rhat;
+  int32_t cand;      // the last checkpoint met E1 <= thr (host confirms)
+  int32_t ckpts;     // checkpoints seen
+  int32_t err;       // device-side error code (0 = none)
+  int32_t pad;
+};
+
+constexpr int kMaxBlock = 512;      // largest supported block size s
+constexpr int kLdsCholMax = 128;    // blocks up to this size are factored in LDS
+
+// r-partials of the block residual: rpart[i * P + p] = sum_{j in chunk p} A[rows[i], j] x[j]
+void launch_block_gemv_partial(const double* A, int64_t lda, int64_t n, const int32_t* rows,
+                               int32_t sb, const double* x, double* rpart, int32_t P,
+                               int64_t chunk, hipStream_t st);
+
+// r = sum_p rpart - b_S; E-sum and checkpoint bookkeeping; y = (L L^T)^{-1} r
+void launch_block_project(const double* rpart, int32_t P, const double* b, const int32_t* rows,
+                          int32_t sb, const double* L, int32_t ldl, double* y, DevState* ds,
+                          int32_t zeta, int32_t adaptive, hipStream_t st);
+
+// x, m update with w = A_S^T y (Kaczmarz++) or w = I_S^T y (CD++)
+void launch_update(int32_t kind, const double* A, int64_t lda, int64_t n, const int32_t* rows,
+                   int32_t sb, const double* y, const DevState* ds, double eta, double* x,
+                   double* mom, hipStream_t st);
+
+// Regularized Grams of nb blocks into column-major s x s slots (lower part).
+void launch_gram(int32_t kind, const double* A, int64_t lda, int64_t n, const int32_t* rows,
+                 const int32_t* lens, int32_t s, int32_t nb, double lambda, double* G,
+                 const int32_t* slot_of, hipStream_t st);
+
+// In-place Cholesky of nb slots; breakdown sets *err = 1.
+void launch_cholesky(double* G, int32_t s, const int32_t* lens, int32_t nb,
+                     const int32_t* slot_of, int32_t* err, hipStream_t st);
+
+// ||A x - b||^2 partial sums per row group (deterministic), then a final sum.
+void launch_residual_sq(const double* A, int64_t lda, int64_t m, int64_t n, const double* x,
+                        const double* b, double* part, int32_t nparts, double* out,
+                        hipStream_t st);
+
+// finiteness check of an m x n strided matrix and a vector; sets *flag = 1 on NaN/Inf
+void launch_check_finite(const double* A, int64_t lda, int64_t m, int64_t n, const double* b,
+                         int32_t* flag, hipStream_t st);
+
+void launch_state_init(DevState* ds, double rho0, double thr, hipStream_t st);
+
+}  // namespace kpp

@@ -1,0 +1,596 @@
+// Host runtime behind the C ABI (include/kpp.h): contexts, systems, the memo
+// cache of block factors and the solver loop (Algorithms 2 and 5 of the paper,
+// exact memoized Cholesky projection).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "kpp.h"
+#include "schedule.hpp"
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+kpp_status fail(kpp_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(e_ == hipErrorOutOfMemory ? KPP_ERR_OOM : KPP_ERR_HIP, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                    \
+  } while (0)
+
+#define KPP_TRY(expr)                   \
+  do {                                  \
+    kpp_status s_ = (expr);             \
+    if (s_ < 0) return s_;              \
+  } while (0)
+
+template <class T>
+kpp_status dev_alloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return KPP_OK;
+  HIP_TRY(hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)));
+  return KPP_OK;
+}
+
+template <class T>
+void dev_free(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+}  // namespace
+
+struct kpp_context {
+  int32_t device = 0;
+  hipStream_t stream = nullptr;
+  int32_t cu_count = 0;
+};
+
+struct kpp_system {
+  kpp_context* ctx = nullptr;
+  int32_t kind = 0;
+  int64_t m = 0, n = 0, lda = 0;
+  const double* A = nullptr;
+  const double* b = nullptr;
+  double bnorm = 0.0;
+  // device work buffers
+  double* mom = nullptr;
+  kpp::DevState* ds = nullptr;
+  double* rpart = nullptr;
+  int64_t rpart_cap = 0;
+  double* y = nullptr;
+  double* rowsq = nullptr;
+  double* scal = nullptr;
+  int32_t* err = nullptr;
+  // memo cache: slot table of factors (column-major s x s) and block rows
+  double* L = nullptr;
+  int32_t* rows = nullptr;
+  int32_t* lens = nullptr;
+  int32_t* slot_ids = nullptr;
+  int32_t cap_slots = 0;
+  int32_t slot_s = 0;
+  int32_t used_slots = 0;
+  std::vector<int32_t> slot_of_block;
+  // signature of the schedule the cache belongs to
+  bool memo_valid = false;
+  int32_t sig_s = 0, sig_memo = 0, sig_nb = 0, sig_part = 0;
+  uint64_t sig_seed = 0;
+  double sig_lambda = 0.0;
+  // host staging
+  std::vector<int32_t> h_rows, h_lens, h_slot;
+};
+
+namespace {
+
+void destroy_buffers(kpp_system* s) {
+  dev_free(s->mom);
+  dev_free(s->ds);
+  dev_free(s->rpart);
+  dev_free(s->y);
+  dev_free(s->rowsq);
+  dev_free(s->scal);
+  dev_free(s->err);
+  dev_free(s->L);
+  dev_free(s->rows);
+  dev_free(s->lens);
+  dev_free(s->slot_ids);
+  s->cap_slots = 0;
+}
+
+// Grow the slot table to hold `need` slots of size s x s (keeps contents).
+kpp_status ensure_slots(kpp_system* sys, int32_t need, int32_t s) {
+  hipStream_t st = sys->ctx->stream;
+  if (sys->slot_s != s) {
+    dev_free(sys->L);
+    dev_free(sys->rows);
+    dev_free(sys->lens);
+    dev_free(sys->slot_ids);
+    sys->cap_slots = 0;
+    sys->slot_s = s;
+    sys->used_slots = 0;
+  }
+  if (need <= sys->cap_slots) return KPP_OK;
+  int32_t cap = std::max<int32_t>(need, std::max<int32_t>(16, sys->cap_slots * 2));
+  double* L = nullptr;
+  int32_t *rows = nullptr, *lens = nullptr, *ids = nullptr;
+  const size_t ss = static_cast<size_t>(s) * s;
+  KPP_TRY(dev_alloc(&L, ss * cap));
+  KPP_TRY(dev_alloc(&rows, static_cast<size_t>(s) * cap));
+  KPP_TRY(dev_alloc(&lens, cap));
+  KPP_TRY(dev_alloc(&ids, cap));
+  if (sys->cap_slots > 0) {
+    HIP_TRY(hipMemcpyAsync(L, sys->L, ss * sys->cap_slots * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(rows, sys->rows, static_cast<size_t>(s) * sys->cap_slots * sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(lens, sys->lens, sys->cap_slots * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  dev_free(sys->L);
+  dev_free(sys->rows);
+  dev_free(sys->lens);
+  dev_free(sys->slot_ids);
+  sys->L = L;
+  sys->rows = rows;
+  sys->lens = lens;
+  sys->slot_ids = ids;
+  sys->cap_slots = cap;
+  return KPP_OK;
+}
+
+// Factor the blocks listed in `pending` (block ids of `sch`) into their slots.
+kpp_status factor_blocks(kpp_system* sys, const kpp::BlockSchedule& sch, double lambda,
+                         const std::vector<int32_t>& pending, const std::vector<int32_t>& slots) {
+  const int32_t nb = static_cast<int32_t>(pending.size());
+  if (nb == 0) return KPP_OK;
+  const int32_t s = sch.block_size();
+  hipStream_t st = sys->ctx->stream;
+  // stage rows/lens of the pending blocks contiguously, then scatter into slots
+  sys->h_rows.assign(static_cast<size_t>(nb) * s, 0);
+  sys->h_lens.resize(nb);
+  sys->h_slot.resize(nb);
+  for (int32_t k = 0; k < nb; ++k) {
+    const int32_t b = pending[k];
+    const int32_t l = sch.len(b);
+    std::copy(sch.rows(b), sch.rows(b) + l, sys->h_rows.begin() + static_cast<size_t>(k) * s);
+    sys->h_lens[k] = l;
+    sys->h_slot[k] = slots[k];
+  }
+  // rows of slot q live at sys->rows[q * s]; the staged copy goes there directly
+  for (int32_t k = 0; k < nb; ++k) {
+    HIP_TRY(hipMemcpyAsync(sys->rows + static_cast<size_t>(slots[k]) * s,
+                           sys->h_rows.data() + static_cast<size_t>(k) * s, s * sizeof(int32_t),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(sys->lens + slots[k], &sys->h_lens[k], sizeof(int32_t),
+                           hipMemcpyHostToDevice, st));
+  }
+  // the factor kernels read rows/lens by staged index k through slot_of[k]
+  int32_t* d_stage_rows = nullptr;
+  int32_t* d_stage_lens = nullptr;
+  KPP_TRY(dev_alloc(&d_stage_rows, static_cast<size_t>(nb) * s));
+  KPP_TRY(dev_alloc(&d_stage_lens, nb));
+  HIP_TRY(hipMemcpyAsync(d_stage_rows, sys->h_rows.data(), static_cast<size_t>(nb) * s * sizeof(int32_t),
+                         hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_stage_lens, sys->h_lens.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(sys->slot_ids, sys->h_slot.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  kpp::launch_gram(sys->kind, sys->A, sys->lda, sys->n, d_stage_rows, d_stage_lens, s, nb, lambda,
+                   sys->L, sys->slot_ids, st);
+  HIP_TRY(hipGetLastError());
+  kpp::launch_cholesky(sys->L, s, d_stage_lens, nb, sys->slot_ids, sys->err, st);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  dev_free(d_stage_rows);
+  dev_free(d_stage_lens);
+  return KPP_OK;
+}
+
+kpp_status check_params(const kpp_system* sys, const kpp_params* p) {
+  if (!p) return fail(KPP_ERR_INVALID_ARG, "params is NULL");
+  const int64_t rows = sys->kind == KPP_CD_PSD ? sys->n : sys->m;
+  if (p->block_size < 1 || p->block_size > rows || p->block_size > kpp::kMaxBlock)
+    return fail(KPP_ERR_INVALID_ARG, "block_size %d must be in [1, min(rows=%lld, %d)]",
+                p->block_size, static_cast<long long>(rows), kpp::kMaxBlock);
+  if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda))
+    return fail(KPP_ERR_INVALID_ARG, "lambda must be finite and >= 0");
+  if (!(p->tol >= 0.0)) return fail(KPP_ERR_INVALID_ARG, "tol must be >= 0");
+  if (p->max_iters < 0) return fail(KPP_ERR_INVALID_ARG, "max_iters must be >= 0");
+  if (p->memo < 0 || p->memo > 2) return fail(KPP_ERR_INVALID_ARG, "unknown memo mode %d", p->memo);
+  if (p->memo == KPP_MEMO_FIXED && !p->fixed_partition && p->num_blocks < 1)
+    return fail(KPP_ERR_INVALID_ARG, "fixed collection needs num_blocks >= 1");
+  if (!(p->rho0 >= 0.0 && p->rho0 <= 1.0)) return fail(KPP_ERR_INVALID_ARG, "rho0 must be in [0, 1]");
+  if (p->precision != KPP_FP64)
+    return fail(KPP_ERR_INVALID_ARG, "precision %d is not available in this build", p->precision);
+  return KPP_OK;
+}
+
+double default_eta(int32_t kind, int64_t m, int64_t n, int32_t s) {
+  if (kind == KPP_CD_PSD) return s / (2.0 * static_cast<double>(n));
+  return s / (2.0 * static_cast<double>(std::min(m, n)));
+}
+
+kpp_status residual_norm(kpp_system* sys, const double* x, double* out) {
+  hipStream_t st = sys->ctx->stream;
+  kpp::launch_residual_sq(sys->A, sys->lda, sys->m, sys->n, x, sys->b, sys->rowsq, 0, sys->scal, st);
+  HIP_TRY(hipGetLastError());
+  double v = 0.0;
+  HIP_TRY(hipMemcpyAsync(&v, sys->scal, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *out = std::sqrt(v);
+  return KPP_OK;
+}
+
+kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_result* res) {
+  using clock = std::chrono::steady_clock;
+  const auto t_start = clock::now();
+  double t_factor = 0.0;
+  hipStream_t st = sys->ctx->stream;
+  const int32_t kind = sys->kind;
+  const int64_t m = sys->m, n = sys->n;
+  const int64_t N = kind == KPP_CD_PSD ? n : m;
+  const int32_t s = p->block_size;
+  const int32_t zeta = static_cast<int32_t>((N + s - 1) / s);
+  double eta = p->eta < 0.0 ? default_eta(kind, m, n, s) : p->eta;
+  if (!p->accel) eta = 0.0;
+  const kpp::MemoMode mode = static_cast<kpp::MemoMode>(p->memo);
+  const double B0 = kpp::online_rate(kind, m, n, s);
+  std::unique_ptr<kpp::BlockSchedule> sch;
+  try {
+    sch.reset(new kpp::BlockSchedule(mode, N, s, p->seed, B0, p->num_blocks, p->fixed_partition != 0));
+  } catch (const std::exception& e) {
+    return fail(KPP_ERR_INVALID_ARG, "%s", e.what());
+  }
+  // memo cache: reuse only for an identical schedule definition
+  const bool same_sig = sys->memo_valid && p->keep_memo && sys->sig_s == s && sys->sig_memo == p->memo &&
+                        sys->sig_nb == p->num_blocks && sys->sig_part == p->fixed_partition &&
+                        sys->sig_seed == p->seed && sys->sig_lambda == p->lambda && mode != kpp::MemoMode::Off;
+  if (!same_sig) {
+    sys->slot_of_block.clear();
+    sys->used_slots = 0;
+    sys->memo_valid = mode != kpp::MemoMode::Off;
+    sys->sig_s = s;
+    sys->sig_memo = p->memo;
+    sys->sig_nb = p->num_blocks;
+    sys->sig_part = p->fixed_partition;
+    sys->sig_seed = p->seed;
+    sys->sig_lambda = p->lambda;
+  }
+  if (mode == kpp::MemoMode::Fixed) KPP_TRY(ensure_slots(sys, sch->num_blocks(), s));
+  // column chunks of the block gemv
+  const int64_t chunk = 2048;
+  const int32_t P = static_cast<int32_t>((n + chunk - 1) / chunk);
+  if (static_cast<int64_t>(s) * P > sys->rpart_cap) {
+    dev_free(sys->rpart);
+    KPP_TRY(dev_alloc(&sys->rpart, static_cast<size_t>(s) * P));
+    sys->rpart_cap = static_cast<int64_t>(s) * P;
+  }
+  HIP_TRY(hipMemsetAsync(sys->mom, 0, n * sizeof(double), st));
+  HIP_TRY(hipMemsetAsync(sys->err, 0, sizeof(int32_t), st));
+  const double thr = p->tol * p->tol * sys->bnorm * sys->bnorm;
+  kpp::launch_state_init(sys->ds, p->rho0, thr, st);
+  HIP_TRY(hipGetLastError());
+
+  int64_t hits = 0, misses = 0, t = 0;
+  bool converged = false;
+  double true_rel = NAN;
+  kpp::DevState hs{};
+  std::vector<int32_t> step_block, pending, pending_slots, step_slot;
+  const int64_t period = 2 * static_cast<int64_t>(zeta);
+  while (t < p->max_iters && !converged) {
+    const int64_t W = std::min<int64_t>(period - (t % period), p->max_iters - t);
+    step_block.resize(W);
+    step_slot.resize(W);
+    pending.clear();
+    pending_slots.clear();
+    if (mode == kpp::MemoMode::Off) KPP_TRY(ensure_slots(sys, static_cast<int32_t>(W), s));
+    for (int64_t k = 0; k < W; ++k) {
+      bool is_new = false;
+      const int32_t b = sch->next(&is_new);
+      step_block[k] = b;
+      if (mode == kpp::MemoMode::Off) {
+        step_slot[k] = static_cast<int32_t>(k);
+        pending.push_back(b);
+        pending_slots.push_back(static_cast<int32_t>(k));
+        ++misses;
+        continue;
+      }
+      if (static_cast<int32_t>(sys->slot_of_block.size()) <= b) sys->slot_of_block.resize(b + 1, -1);
+      int32_t q = sys->slot_of_block[b];
+      if (q < 0) {
+        q = sys->used_slots++;
+        sys->slot_of_block[b] = q;
+        pending.push_back(b);
+        pending_slots.push_back(q);
+        ++misses;
+      } else {
+        ++hits;
+      }
+      step_slot[k] = q;
+    }
+    if (mode != kpp::MemoMode::Off) KPP_TRY(ensure_slots(sys, sys->used_slots, s));
+    if (!pending.empty()) {
+      const auto f0 = clock::now();
+      KPP_TRY(factor_blocks(sys, *sch, p->lambda, pending, pending_slots));
+      int32_t herr = 0;
+      HIP_TRY(hipMemcpy(&herr, sys->err, sizeof(int32_t), hipMemcpyDeviceToHost));
+      if (herr) return fail(KPP_ERR_NOT_SPD, "a regularized block Gram has no Cholesky factor (lambda=%g)", p->lambda);
+      t_factor += std::chrono::duration<double>(clock::now() - f0).count();
+    }
+    const size_t ss = static_cast<size_t>(s) * s;
+    for (int64_t k = 0; k < W; ++k) {
+      const int32_t q = step_slot[k];
+      const int32_t sb = sch->len(step_block[k]);
+      const int32_t* rows = sys->rows + static_cast<size_t>(q) * s;
+      kpp::launch_block_gemv_partial(sys->A, sys->lda, n, rows, sb, x, sys->rpart, P, chunk, st);
+      kpp::launch_block_project(sys->rpart, P, sys->b, rows, sb, sys->L + ss * q, s, sys->y, sys->ds,
+                                zeta, p->adaptive_rho, st);
+      kpp::launch_update(kind, sys->A, sys->lda, n, rows, sb, sys->y, sys->ds, eta, x, sys->mom, st);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(&hs, sys->ds, sizeof(hs), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    t += W;
+    if ((t % period) == 0 && hs.cand) {
+      if (p->confirm_true_residual) {
+        double rn = 0.0;
+        KPP_TRY(residual_norm(sys, x, &rn));
+        true_rel = sys->bnorm > 0 ? rn / sys->bnorm : rn;
+        if (rn <= p->tol * sys->bnorm) converged = true;
+      } else {
+        converged = true;
+      }
+    }
+  }
+  if (!converged || std::isnan(true_rel)) {
+    double rn = 0.0;
+    KPP_TRY(residual_norm(sys, x, &rn));
+    true_rel = sys->bnorm > 0 ? rn / sys->bnorm : rn;
+  }
+  if (res) {
+    res->iters = t;
+    res->memo_hits = hits;
+    res->memo_misses = misses;
+    res->factors_fp64 = misses;
+    res->converged = converged ? 1 : 0;
+    res->refinements = 0;
+    res->checkpoints = hs.ckpts;
+    res->engine_used = 1;
+    res->est_rel_res = sys->bnorm > 0 ? std::sqrt(hs.last_E1) / sys->bnorm : std::sqrt(hs.last_E1);
+    res->true_rel_res = true_rel;
+    res->rho_final = converged ? hs.rho_before : hs.rho;
+    res->seconds_total = std::chrono::duration<double>(clock::now() - t_start).count();
+    res->seconds_factor = t_factor;
+    const double sd = s;
+    const double nn = static_cast<double>(n);
+    const double per_step = 2.0 * sd * nn + 2.0 * sd * sd + (kind == KPP_CD_PSD ? 0.0 : 2.0 * sd * nn) + 5.0 * nn;
+    const double per_fact = sd * sd * sd / 3.0 + (kind == KPP_CD_PSD ? 0.0 : sd * sd * nn);
+    res->flops = per_step * static_cast<double>(t) + per_fact * static_cast<double>(misses);
+    res->bytes_algorithmic = static_cast<double>(t) * (sd * nn * 8.0 + 0.5 * sd * (sd + 1) * 8.0 + 12.0 * sd);
+  }
+  return converged ? KPP_OK : KPP_NOT_CONVERGED;
+}
+
+}  // namespace
+
+extern "C" {
+
+KPP_API int32_t kpp_abi_version(void) { return KPP_ABI_VERSION; }
+
+KPP_API const char* kpp_last_error(void) { return g_last_error.c_str(); }
+
+KPP_API kpp_status kpp_params_default(kpp_params* p, int32_t kind) {
+  if (!p) return fail(KPP_ERR_INVALID_ARG, "params is NULL");
+  if (kind != KPP_KACZMARZ && kind != KPP_CD_PSD) return fail(KPP_ERR_INVALID_ARG, "unknown kind %d", kind);
+  std::memset(p, 0, sizeof(*p));
+  p->block_size = 128;
+  p->memo = KPP_MEMO_ONLINE;
+  p->num_blocks = 0;
+  p->fixed_partition = 1;
+  p->accel = 1;
+  p->adaptive_rho = 1;
+  p->precision = KPP_FP64;
+  p->confirm_true_residual = 1;
+  p->lambda = 1e-8;
+  p->tol = 1e-10;
+  p->eta = -1.0;
+  p->rho0 = 0.0;
+  p->max_iters = 1000000;
+  p->seed = 0x2501116730ull;
+  p->keep_memo = 0;
+  p->refine_max_rounds = 12;
+  p->inner_tol = 1e-5;
+  p->engine = 0;
+  return KPP_OK;
+}
+
+KPP_API kpp_status kpp_context_create(int32_t device, void* hip_stream, kpp_context** out) {
+  if (!out) return fail(KPP_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  HIP_TRY(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(KPP_ERR_INVALID_ARG, "device %d of %d", device, count);
+  HIP_TRY(hipSetDevice(device));
+  auto* c = new (std::nothrow) kpp_context;
+  if (!c) return fail(KPP_ERR_OOM, "host allocation failed");
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->cu_count = prop.multiProcessorCount;
+  *out = c;
+  return KPP_OK;
+}
+
+KPP_API kpp_status kpp_context_destroy(kpp_context* ctx) {
+  delete ctx;
+  return KPP_OK;
+}
+
+KPP_API kpp_status kpp_system_create(kpp_context* ctx, int32_t kind, int64_t m, int64_t n,
+                                     const double* A_dev, int64_t lda, const double* b_dev,
+                                     kpp_system** out) {
+  if (!out) return fail(KPP_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!ctx || !A_dev || !b_dev) return fail(KPP_ERR_INVALID_ARG, "NULL context, A or b");
+  if (kind != KPP_KACZMARZ && kind != KPP_CD_PSD) return fail(KPP_ERR_INVALID_ARG, "unknown kind %d", kind);
+  if (m < 1 || n < 1) return fail(KPP_ERR_SHAPE, "empty system (m=%lld, n=%lld)", (long long)m, (long long)n);
+  if (lda < n) return fail(KPP_ERR_SHAPE, "lda=%lld < n=%lld", (long long)lda, (long long)n);
+  if (kind == KPP_CD_PSD && m != n) return fail(KPP_ERR_SHAPE, "CD++ needs a square matrix");
+  if (m > (int64_t{1} << 31) - 1 || n > (int64_t{1} << 31) - 1) return fail(KPP_ERR_SHAPE, "dimension above 2^31-1");
+  HIP_TRY(hipSetDevice(ctx->device));
+  std::unique_ptr<kpp_system> sys(new (std::nothrow) kpp_system);
+  if (!sys) return fail(KPP_ERR_OOM, "host allocation failed");
+  sys->ctx = ctx;
+  sys->kind = kind;
+  sys->m = m;
+  sys->n = n;
+  sys->lda = lda;
+  sys->A = A_dev;
+  sys->b = b_dev;
+  kpp_status stt;
+  if ((stt = dev_alloc(&sys->mom, n)) < 0 || (stt = dev_alloc(&sys->ds, 1)) < 0 ||
+      (stt = dev_alloc(&sys->y, kpp::kMaxBlock)) < 0 || (stt = dev_alloc(&sys->rowsq, m)) < 0 ||
+      (stt = dev_alloc(&sys->scal, 4)) < 0 || (stt = dev_alloc(&sys->err, 4)) < 0) {
+    destroy_buffers(sys.get());
+    return stt;
+  }
+  hipStream_t st = ctx->stream;
+  // finiteness of A and b, and ||b||
+  HIP_TRY(hipMemsetAsync(sys->err, 0, sizeof(int32_t), st));
+  kpp::launch_check_finite(A_dev, lda, m, n, b_dev, sys->err, st);
+  HIP_TRY(hipGetLastError());
+  int32_t bad = 0;
+  HIP_TRY(hipMemcpyAsync(&bad, sys->err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (bad) {
+    destroy_buffers(sys.get());
+    return fail(KPP_ERR_NONFINITE, "A or b holds NaN or Inf");
+  }
+  std::vector<double> hb(m);
+  HIP_TRY(hipMemcpyAsync(hb.data(), b_dev, m * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double bb = 0.0;
+  for (double v : hb) bb += v * v;
+  sys->bnorm = std::sqrt(bb);
+  *out = sys.release();
+  return KPP_OK;
+}
+
+KPP_API kpp_status kpp_system_destroy(kpp_system* sys) {
+  if (!sys) return KPP_OK;
+  if (sys->ctx) (void)hipSetDevice(sys->ctx->device);
+  if (sys->ctx) (void)hipStreamSynchronize(sys->ctx->stream);
+  destroy_buffers(sys);
+  delete sys;
+  return KPP_OK;
+}
+
+KPP_API kpp_status kpp_solve(kpp_system* sys, const kpp_params* p, double* x_dev, kpp_result* res) {
+  if (!sys || !x_dev) return fail(KPP_ERR_INVALID_ARG, "NULL system or x");
+  if (res) std::memset(res, 0, sizeof(*res));
+  KPP_TRY(check_params(sys, p));
+  HIP_TRY(hipSetDevice(sys->ctx->device));
+  try {
+    return solve_fp64(sys, p, x_dev, res);
+  } catch (const std::bad_alloc&) {
+    return fail(KPP_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(KPP_ERR_INVALID_ARG, "%s", e.what());
+  }
+}
+
+KPP_API kpp_status kpp_schedule_generate(int32_t kind, int64_t m, int64_t n, const kpp_params* p,
+                                         int64_t T, int32_t* step_block_host,
+                                         int32_t* block_rows_host, int32_t* block_len_host,
+                                         int32_t blocks_cap, int32_t* num_blocks_out) {
+  if (!p || T < 0 || (T > 0 && !step_block_host) || !num_blocks_out)
+    return fail(KPP_ERR_INVALID_ARG, "bad arguments");
+  if (kind != KPP_KACZMARZ && kind != KPP_CD_PSD) return fail(KPP_ERR_INVALID_ARG, "unknown kind");
+  const int64_t N = kind == KPP_CD_PSD ? n : m;
+  const int32_t s = p->block_size;
+  try {
+    kpp::BlockSchedule sch(static_cast<kpp::MemoMode>(p->memo), N, s, p->seed,
+                           kpp::online_rate(kind, m, n, s), p->num_blocks, p->fixed_partition != 0);
+    for (int64_t t = 0; t < T; ++t) step_block_host[t] = sch.next(nullptr);
+    const int32_t nb = sch.num_blocks();
+    *num_blocks_out = nb;
+    if (nb > blocks_cap) return fail(KPP_ERR_INVALID_ARG, "blocks_cap %d < %d blocks", blocks_cap, nb);
+    for (int32_t b = 0; b < nb; ++b) {
+      if (block_len_host) block_len_host[b] = sch.len(b);
+      if (block_rows_host)
+        for (int32_t i = 0; i < s; ++i) block_rows_host[static_cast<size_t>(b) * s + i] = i < sch.len(b) ? sch.rows(b)[i] : -1;
+    }
+  } catch (const std::exception& e) {
+    return fail(KPP_ERR_INVALID_ARG, "%s", e.what());
+  }
+  return KPP_OK;
+}
+
+KPP_API kpp_status kpp_block_factor(kpp_system* sys, int32_t s, double lambda, int32_t nb,
+                                    const int32_t* rows_host, const int32_t* len_host, double* L_dev) {
+  if (!sys || !rows_host || !len_host || !L_dev || nb < 0) return fail(KPP_ERR_INVALID_ARG, "bad arguments");
+  const int64_t N = sys->kind == KPP_CD_PSD ? sys->n : sys->m;
+  if (s < 1 || s > kpp::kMaxBlock) return fail(KPP_ERR_INVALID_ARG, "block size %d out of range", s);
+  if (!(lambda >= 0.0)) return fail(KPP_ERR_INVALID_ARG, "lambda must be >= 0");
+  for (int32_t b = 0; b < nb; ++b) {
+    if (len_host[b] < 1 || len_host[b] > s) return fail(KPP_ERR_INVALID_ARG, "block %d length %d", b, len_host[b]);
+    for (int32_t i = 0; i < len_host[b]; ++i) {
+      const int32_t r = rows_host[static_cast<size_t>(b) * s + i];
+      if (r < 0 || r >= N) return fail(KPP_ERR_INVALID_ARG, "block %d row %d out of range", b, r);
+    }
+  }
+  if (nb == 0) return KPP_OK;
+  HIP_TRY(hipSetDevice(sys->ctx->device));
+  hipStream_t st = sys->ctx->stream;
+  int32_t *d_rows = nullptr, *d_lens = nullptr, *d_ids = nullptr;
+  KPP_TRY(dev_alloc(&d_rows, static_cast<size_t>(nb) * s));
+  KPP_TRY(dev_alloc(&d_lens, nb));
+  KPP_TRY(dev_alloc(&d_ids, nb));
+  std::vector<int32_t> ids(nb);
+  for (int32_t b = 0; b < nb; ++b) ids[b] = b;
+  HIP_TRY(hipMemcpyAsync(d_rows, rows_host, static_cast<size_t>(nb) * s * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_lens, len_host, nb * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_ids, ids.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemsetAsync(sys->err, 0, sizeof(int32_t), st));
+  HIP_TRY(hipMemsetAsync(L_dev, 0, static_cast<size_t>(nb) * s * s * sizeof(double), st));
+  kpp::launch_gram(sys->kind, sys->A, sys->lda, sys->n, d_rows, d_lens, s, nb, lambda, L_dev, d_ids, st);
+  HIP_TRY(hipGetLastError());
+  kpp::launch_cholesky(L_dev, s, d_lens, nb, d_ids, sys->err, st);
+  HIP_TRY(hipGetLastError());
+  int32_t herr = 0;
+  HIP_TRY(hipMemcpyAsync(&herr, sys->err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  dev_free(d_rows);
+  dev_free(d_lens);
+  dev_free(d_ids);
+  if (herr) return fail(KPP_ERR_NOT_SPD, "a regularized block Gram has no Cholesky factor");
+  return KPP_OK;
+}
+
+KPP_API kpp_status kpp_residual_norm(kpp_system* sys, const double* x_dev, double* out_host) {
+  if (!sys || !x_dev || !out_host) return fail(KPP_ERR_INVALID_ARG, "bad arguments");
+  HIP_TRY(hipSetDevice(sys->ctx->device));
+  return residual_norm(sys, x_dev, out_host);
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// Block schedule generator; see schedule.hpp for the exact draw order.
+#include "schedule.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <stdexcept>
+
+namespace kpp {
+
+double online_rate(int32_t kind, int64_t m, int64_t n, int32_t s) {
+  if (kind == 1) return (static_cast<double>(n) / static_cast<double>(s)) * std::log(static_cast<double>(n));
+  return (static_cast<double>(std::min(m, n)) / static_cast<double>(s)) *
+         std::log(static_cast<double>(m));
+}
+
+BlockSchedule::BlockSchedule(MemoMode mode, int64_t N, int32_t s, uint64_t seed, double B0,
+                             int32_t num_blocks, bool partition)
+    : mode_(mode), N_(N), s_(s), B0_(B0), g_(seed) {
+  if (s < 1 || N < s) throw std::invalid_argument("block size must satisfy 1 <= s <= rows");
+  perm_.resize(static_cast<size_t>(N));
+  if (mode_ == MemoMode::Fixed) {
+    if (partition) {
+      std::iota(perm_.begin(), perm_.end(), 0);
+      for (int64_t j = 0; j + 1 < N; ++j) {
+        int64_t k = j + static_cast<int64_t>(g_.bounded(static_cast<uint64_t>(N - j)));
+        std::swap(perm_[j], perm_[k]);
+      }
+      for (int64_t lo = 0; lo < N; lo += s) {
+        int32_t l = static_cast<int32_t>(std::min<int64_t>(s, N - lo));
+        size_t base = rows_.size();
+        rows_.resize(base + s, -1);
+        std::copy(perm_.begin() + lo, perm_.begin() + lo + l, rows_.begin() + base);
+        std::sort(rows_.begin() + base, rows_.begin() + base + l);
+        len_.push_back(l);
+      }
+    } else {
+      if (num_blocks < 1) throw std::invalid_argument("fixed collection needs num_blocks >= 1");
+      for (int32_t b = 0; b < num_blocks; ++b) add_subset();
+    }
+    used_.assign(len_.size(), 0);
+  }
+}
+
+void BlockSchedule::add_subset() {
+  std::iota(perm_.begin(), perm_.end(), 0);
+  for (int32_t j = 0; j < s_; ++j) {
+    int64_t k = j + static_cast<int64_t>(g_.bounded(static_cast<uint64_t>(N_ - j)));
+    std::swap(perm_[j], perm_[k]);
+  }
+  size_t base = rows_.size();
+  rows_.resize(base + s_);
+  std::copy(perm_.begin(), perm_.begin() + s_, rows_.begin() + base);
+  std::sort(rows_.begin() + base, rows_.end());
+  len_.push_back(s_);
+}
+
+int32_t BlockSchedule::next(bool* is_new) {
+  int32_t b;
+  bool fresh = false;
+  switch (mode_) {
+    case MemoMode::Fixed: {
+      b = static_cast<int32_t>(g_.bounded(len_.size()));
+      fresh = !used_[b];
+      used_[b] = 1;
+      break;
+    }
+    case MemoMode::Online: {
+      double u = g_.uniform();
+      if (t_ == 0 || u < B0_ / static_cast<double>(t_)) {
+        add_subset();
+        b = static_cast<int32_t>(len_.size()) - 1;
+        fresh = true;
+      } else {
+        b = static_cast<int32_t>(g_.bounded(len_.size()));
+      }
+      break;
+    }
+    case MemoMode::Off:
+    default: {
+      add_subset();
+      b = static_cast<int32_t>(len_.size()) - 1;
+      fresh = true;
+      break;
+    }
+  }
+  ++t_;
+  if (is_new) *is_new = fresh;
+  return b;
+}
+
+}  // namespace kpp

@@ -1,0 +1,259 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle on the
+same seeded inputs and the same seeded block schedule.
+
+Bar (FP64): iterates agree to 1e-10 relative after the same number of block
+steps; factors of well-conditioned blocks agree to 1e-12 relative.  Floating
+point never decides an integer here except the stop step, so iterate
+comparisons use fixed step counts (tol = 0) and convergence is checked as a
+property (true residual, distance to the planted solution).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import kpp as okpp
+from oracle import schedule as osch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import paper_2501_11673_amd as kpp
+
+    assert torch.cuda.is_available()
+    dev = torch.device("cuda:0")
+    ctx = kpp.kpp_context_create(0, torch.cuda.current_stream(dev).cuda_stream)
+    yield kpp, torch, dev, ctx
+    kpp.kpp_context_destroy(ctx)
+
+
+def relerr(a, b):
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b))) / (nb if nb > 0 else 1.0)
+
+
+MODES = {"online": 1, "fixed": 2, "off": 0}
+
+
+def gpu_solve(env, A, b, kind, s, *, lam, T, tol=0.0, mode="online", seed=7, num_blocks=0,
+              partition=True, accel=True, eta=None, x0=None, adaptive=True, keep_memo=False):
+    kpp, torch, dev, ctx = env
+    m, n = A.shape
+    ck = kpp.KPP_CD_PSD if kind == "psd" else kpp.KPP_KACZMARZ
+    p = kpp.kpp_params_default(ck)
+    p.block_size = s
+    p.lambda_ = lam
+    p.tol = tol
+    p.max_iters = T
+    p.seed = seed
+    p.memo = MODES[mode]
+    p.num_blocks = num_blocks
+    p.fixed_partition = 1 if partition else 0
+    p.accel = 1 if accel else 0
+    p.adaptive_rho = 1 if adaptive else 0
+    p.keep_memo = 1 if keep_memo else 0
+    if eta is not None:
+        p.eta = eta
+    Ad = A if hasattr(A, "data_ptr") else torch.from_numpy(np.ascontiguousarray(A)).to(dev)
+    bd = b if hasattr(b, "data_ptr") else torch.from_numpy(np.ascontiguousarray(b)).to(dev)
+    if x0 is None:
+        xd = torch.zeros(n, dtype=torch.float64, device=dev)
+    else:
+        xd = torch.from_numpy(np.array(x0, dtype=np.float64)).to(dev)
+    h = kpp.kpp_system_create(ctx, ck, m, n, Ad.data_ptr(), n, bd.data_ptr())
+    try:
+        st, res = kpp.kpp_solve(h, p, xd.data_ptr())
+    finally:
+        kpp.kpp_system_destroy(h)
+    return xd.cpu().numpy(), st, res
+
+
+def oracle_solve(A, b, kind, s, *, lam, T, tol=0.0, mode="online", seed=7, num_blocks=0,
+                 partition=True, accel=True, eta=None, x0=None, adaptive=True, snapshot_steps=()):
+    m, n = A.shape
+    N = n if kind == "psd" else m
+    schd = osch.make_schedule(mode, N, s, T, seed, B0=osch.online_rate(kind, m, n, s),
+                              num_blocks=num_blocks, partition=partition)
+    p = okpp.Params(s=s, lam=lam, tol=tol, max_iters=T, accel=accel, eta=eta,
+                    adaptive_rho=adaptive, memo=(mode != "off"))
+    return okpp.solve(A, b, kind, p, schd, x0=x0, snapshot_steps=snapshot_steps)
+
+
+# ---------------------------------------------------------------------------
+# memo-miss path: Gram + Cholesky
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind,m,n,s,lam", [
+    ("general", 300, 150, 20, 1e-3),
+    ("general", 700, 300, 37, 1e-2),     # ragged tiles
+    ("general", 1200, 400, 256, 1e-1),   # factor in global memory (s > 128)
+    ("psd", 500, 500, 128, 1e-8),
+    ("psd", 300, 300, 1, 1e-8),
+])
+def test_block_factor_matches_oracle(env, kind, m, n, s, lam):
+    kpp, torch, dev, ctx = env
+    sysm = synth.tiny_system("psd", n, n, seed=3, cond=20.0) if kind == "psd" else \
+        synth.tiny_system("general", m, n, seed=3, cond=20.0)
+    A, b = sysm.A, sysm.b
+    N = n if kind == "psd" else m
+    g = osch.SplitMix64(99)
+    blocks = [osch.random_subset(g, N, s) for _ in range(5)]
+    blocks.append(osch.random_subset(g, N, max(1, s - 3)))  # a short block
+    rows = []
+    for blk in blocks:
+        rows += blk.tolist() + [0] * (s - len(blk))
+    lens = [len(blk) for blk in blocks]
+    Ad = torch.from_numpy(A).to(dev)
+    bd = torch.from_numpy(b).to(dev)
+    ck = kpp.KPP_CD_PSD if kind == "psd" else kpp.KPP_KACZMARZ
+    h = kpp.kpp_system_create(ctx, ck, A.shape[0], n, Ad.data_ptr(), n, bd.data_ptr())
+    L = torch.full((len(blocks), s, s), float("nan"), dtype=torch.float64, device=dev)
+    try:
+        kpp.kpp_block_factor(h, s, lam, rows, lens, L.data_ptr())
+    finally:
+        kpp.kpp_system_destroy(h)
+    Lh = L.cpu().numpy()
+    for q, blk in enumerate(blocks):
+        ref = okpp.cholesky_lower(okpp.regularized_gram(A, blk, lam, kind))
+        sb = len(blk)
+        got = Lh[q].T[:sb, :sb]  # column-major slot -> row-major view
+        assert relerr(got, ref) < 1e-12
+        full = Lh[q].T
+        assert np.all(full[np.triu_indices(s, 1)] == 0.0)
+        assert np.all(full[sb:, :] == 0.0) and np.all(full[:, sb:] == 0.0)
+
+
+def test_block_factor_reports_breakdown(env):
+    kpp, torch, dev, ctx = env
+    A = np.random.default_rng(0).standard_normal((20, 6))
+    A[7] = A[3]
+    b = np.ones(20)
+    Ad = torch.from_numpy(A).to(dev)
+    bd = torch.from_numpy(b).to(dev)
+    h = kpp.kpp_system_create(ctx, kpp.KPP_KACZMARZ, 20, 6, Ad.data_ptr(), 6, bd.data_ptr())
+    L = torch.zeros((1, 4, 4), dtype=torch.float64, device=dev)
+    try:
+        with pytest.raises(kpp.KppError) as e:
+            kpp.kpp_block_factor(h, 4, 0.0, [1, 3, 7, 9], [4], L.data_ptr())
+        assert e.value.status == kpp.KPP_ERR_NOT_SPD
+    finally:
+        kpp.kpp_system_destroy(h)
+
+
+def test_residual_norm(env):
+    kpp, torch, dev, ctx = env
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((333, 77))
+    b = rng.standard_normal(333)
+    x = rng.standard_normal(77)
+    Ad, bd, xd = (torch.from_numpy(v).to(dev) for v in (A, b, x))
+    h = kpp.kpp_system_create(ctx, 0, 333, 77, Ad.data_ptr(), 77, bd.data_ptr())
+    try:
+        got = kpp.kpp_residual_norm(h, xd.data_ptr())
+    finally:
+        kpp.kpp_system_destroy(h)
+    assert got == pytest.approx(np.linalg.norm(A @ x - b), rel=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# iterate parity at fixed step counts
+# ---------------------------------------------------------------------------
+
+ITER_CASES = [
+    # name, kind, builder, s, lam, mode, T, extra
+    ("c1", "general", lambda: synth.config("c1"), 20, 1e-3, "online", 600, {}),
+    ("c2_small", "psd", lambda: synth.config("c2_small"), 128, 1e-8, "online", 320, {}),
+    ("c2_small_partition", "psd", lambda: synth.config("c2_small"), 128, 1e-8, "fixed", 160, {}),
+    ("c3_small", "general", lambda: synth.config("c3_small"), 256, 1e-8, "fixed", 200, {}),
+    ("c4_small", "general", lambda: synth.config("c4_small"), 64, 1e-4, "online", 200, {}),
+    ("tiny_over_s1", "general", lambda: synth.tiny_system("general", 50, 9, seed=5), 1, 1e-6, "online", 300, {}),
+    ("tiny_psd_sN", "psd", lambda: synth.tiny_system("psd", 24, 24, seed=6), 24, 1e-6, "online", 40, {}),
+    ("tiny_under_off", "general", lambda: synth.tiny_system("general", 30, 90, seed=8), 7, 1e-5, "off", 150, {}),
+    ("tiny_fixed_subsets", "general", lambda: synth.tiny_system("general", 80, 30, seed=9), 9, 1e-5, "fixed", 200,
+     dict(num_blocks=11, partition=False)),
+    ("tiny_noaccel", "psd", lambda: synth.tiny_system("psd", 60, 60, seed=10, cond=100.0), 8, 1e-8, "online", 300,
+     dict(accel=False)),
+    ("tiny_eta_rho_fixed", "general", lambda: synth.tiny_system("general", 90, 40, seed=11), 10, 1e-6, "online", 300,
+     dict(eta=0.1, adaptive=False)),
+]
+
+
+@pytest.mark.parametrize("case", ITER_CASES, ids=[c[0] for c in ITER_CASES])
+def test_iterates_match_oracle(env, case):
+    name, kind, build, s, lam, mode, T, extra = case
+    sysm = build()
+    A, b = sysm.A, sysm.b
+    print(f"[parity] {name} shape={A.shape} s={s} T={T}", flush=True)
+    for Tk in (T // 2, T):
+        x, st, res = gpu_solve(env, A, b, kind, s, lam=lam, T=Tk, mode=mode, seed=31, **extra)
+        ref = oracle_solve(A, b, kind, s, lam=lam, T=Tk, mode=mode, seed=31, **extra)
+        err = relerr(x, ref.x)
+        assert err <= 1e-10, f"{name} after {Tk} steps: relative difference {err:.3e}"
+        assert res.iters == Tk
+        assert res.memo_misses == ref.factorizations
+        assert res.rho_final == pytest.approx(ref.rho_final, rel=1e-8, abs=1e-12)
+
+
+def test_converges_like_oracle_c1(env):
+    sysm = synth.config("c1")
+    A, b = sysm.A, sysm.b
+    x, st, res = gpu_solve(env, A, b, "general", 20, lam=1e-3, T=20000, tol=1e-10, seed=101)
+    ref = oracle_solve(A, b, "general", 20, lam=1e-3, T=20000, tol=1e-10, seed=101)
+    assert st == 0 and res.converged == 1 and ref.converged
+    assert res.true_rel_res <= 1e-10
+    assert np.linalg.norm(A @ x - b) <= 1.01e-10 * np.linalg.norm(b)
+    assert relerr(x, sysm.xstar) < 1e-8
+    assert abs(res.iters - ref.iters) <= 2 * 50 * 2  # same or a neighbouring checkpoint
+
+
+def test_bitwise_repeatable(env):
+    sysm = synth.config("c2_small")
+    x1, _, _ = gpu_solve(env, sysm.A, sysm.b, "psd", 128, lam=1e-8, T=200, seed=3)
+    x2, _, _ = gpu_solve(env, sysm.A, sysm.b, "psd", 128, lam=1e-8, T=200, seed=3)
+    assert np.array_equal(x1, x2)
+
+
+# ---------------------------------------------------------------------------
+# edge cases and error paths
+# ---------------------------------------------------------------------------
+
+def test_zero_steps_and_zero_rhs(env):
+    sysm = synth.tiny_system("general", 40, 10, seed=1)
+    x0 = np.arange(10, dtype=np.float64)
+    x, st, res = gpu_solve(env, sysm.A, sysm.b, "general", 4, lam=1e-6, T=0, x0=x0)
+    assert st == 1 and res.iters == 0 and np.array_equal(x, x0)
+    x, st, res = gpu_solve(env, sysm.A, np.zeros(40), "general", 4, lam=1e-6, T=100, tol=1e-10)
+    assert st == 0 and res.converged == 1 and np.all(x == 0.0)
+
+
+def test_one_by_one_system(env):
+    A = np.array([[4.0]])
+    b = np.array([2.0])
+    x, st, res = gpu_solve(env, A, b, "psd", 1, lam=0.0, T=10, tol=1e-12)
+    assert st == 0 and x[0] == pytest.approx(0.5, rel=1e-15)
+
+
+def test_errors(env):
+    kpp, torch, dev, ctx = env
+    sysm = synth.tiny_system("general", 20, 6, seed=2)
+    A = sysm.A.copy()
+    A[3, 2] = math.nan
+    with pytest.raises(kpp.KppError) as e:
+        gpu_solve(env, A, sysm.b, "general", 4, lam=1e-6, T=10)
+    assert e.value.status == kpp.KPP_ERR_NONFINITE
+    A = sysm.A.copy()
+    A[5] = A[2]
+    with pytest.raises(kpp.KppError) as e:
+        gpu_solve(env, A, sysm.b, "general", 20, lam=0.0, T=10, mode="fixed")
+    assert e.value.status == kpp.KPP_ERR_NOT_SPD
+    with pytest.raises(kpp.KppError) as e:
+        gpu_solve(env, sysm.A, sysm.b, "general", 21, lam=1e-6, T=10)
+    assert e.value.status == kpp.KPP_ERR_INVALID_ARG
+    with pytest.raises(kpp.KppError) as e:
+        gpu_solve(env, np.ones((5, 6)), np.ones(5), "psd", 2, lam=1e-6, T=10)
+    assert e.value.status == kpp.KPP_ERR_SHAPE
