@@ -102,7 +102,7 @@ typedef struct kpp_params {
   int32_t refine_max_rounds;  /* mixed precision: outer refinement rounds (default 12)   */
   double inner_tol;           /* mixed precision: inner relative tolerance (default 1e-5) */
   int32_t engine;             /* 0: auto, 1: one launch per phase, 2: fused persistent  */
-  int32_t reserved0;
+  int32_t team_groups;        /* fused engine: workgroups sharing one step (0: auto)    */
   double reserved1[4];
 } kpp_params;
 
@@ -122,8 +122,10 @@ typedef struct kpp_result {
   double seconds_total;
   double seconds_factor;      /* time in Gram + Cholesky                                 */
   double flops;               /* 2sn (+2sn K++) + 2s^2 + 5n per step; s^3/3 (+s^2 n) per factor */
-  double bytes_algorithmic;   /* s n b_A + factor + vectors per step (see kpp_step_bytes) */
-  double reserved[4];
+  double bytes_algorithmic;   /* per step: s n b_A (A_S) + s(s+1)/2 * 8 (factor) + 12 s (b_S, rows) */
+  double kernel_seconds;      /* device time of the step kernels (HIP events), all launches */
+  double kernel_launches;     /* number of step-kernel launches (fused: one per window)  */
+  double reserved[2];
 } kpp_result;
 
 typedef struct kpp_context kpp_context;

@@ -63,7 +63,7 @@ class kpp_params(ctypes.Structure):
         ("refine_max_rounds", ctypes.c_int32),
         ("inner_tol", ctypes.c_double),
         ("engine", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("team_groups", ctypes.c_int32),
         ("reserved1", ctypes.c_double * 4),
     ]
 
@@ -85,7 +85,9 @@ class kpp_result(ctypes.Structure):
         ("seconds_factor", ctypes.c_double),
         ("flops", ctypes.c_double),
         ("bytes_algorithmic", ctypes.c_double),
-        ("reserved", ctypes.c_double * 4),
+        ("kernel_seconds", ctypes.c_double),
+        ("kernel_launches", ctypes.c_double),
+        ("reserved", ctypes.c_double * 2),
     ]
 
     def as_dict(self):

@@ -176,7 +176,7 @@ __global__ __launch_bounds__(kT) void k_update(const double* __restrict__ A, int
 __global__ __launch_bounds__(kT) void k_gram_kpp(const double* __restrict__ A, int64_t lda,
                                                  int64_t n, const int32_t* __restrict__ rows,
                                                  const int32_t* __restrict__ lens, int32_t s,
-                                                 double lambda, double* __restrict__ G,
+                                                 double lambda, double* __restrict__ G, int64_t stride,
                                                  const int32_t* __restrict__ slot_of) {
   __shared__ double As[32][33];
   __shared__ double Bs[32][33];
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(kT) void k_gram_kpp(const double* __restrict__ A, i
   const int i0 = ti * 32, k0 = tk * 32;
   if (ti < tk || i0 >= sb || k0 >= sb) return;  // uniform over the workgroup
   const int32_t* R = rows + static_cast<int64_t>(blk) * s;
-  double* Gb = G + static_cast<int64_t>(slot_of[blk]) * s * s;
+  double* Gb = G + static_cast<int64_t>(slot_of[blk]) * stride;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   double a00 = 0, a01 = 0, a10 = 0, a11 = 0;
   for (int64_t j0 = 0; j0 < n; j0 += 32) {
@@ -226,12 +226,12 @@ __global__ __launch_bounds__(kT) void k_gram_kpp(const double* __restrict__ A, i
 __global__ __launch_bounds__(kT) void k_gram_cd(const double* __restrict__ A, int64_t lda,
                                                 const int32_t* __restrict__ rows,
                                                 const int32_t* __restrict__ lens, int32_t s,
-                                                double lambda, double* __restrict__ G,
+                                                double lambda, double* __restrict__ G, int64_t stride,
                                                 const int32_t* __restrict__ slot_of) {
   const int blk = blockIdx.x;
   const int sb = lens[blk];
   const int32_t* R = rows + static_cast<int64_t>(blk) * s;
-  double* Gb = G + static_cast<int64_t>(slot_of[blk]) * s * s;
+  double* Gb = G + static_cast<int64_t>(slot_of[blk]) * stride;
   for (int e = threadIdx.x; e < sb * sb; e += kT) {
     const int k = e / sb, i = e - k * sb;
     if (i >= k) Gb[static_cast<int64_t>(k) * s + i] = A[static_cast<int64_t>(R[i]) * lda + R[k]] + (i == k ? lambda : 0.0);
@@ -242,14 +242,14 @@ __global__ __launch_bounds__(kT) void k_gram_cd(const double* __restrict__ A, in
 // memo miss: Cholesky, one workgroup per block (right-looking, column by column)
 // --------------------------------------------------------------------------
 template <bool IN_LDS>
-__global__ __launch_bounds__(kT) void k_cholesky(double* __restrict__ G, int32_t s,
+__global__ __launch_bounds__(kT) void k_cholesky(double* __restrict__ G, int32_t s, int64_t stride,
                                                  const int32_t* __restrict__ lens,
                                                  const int32_t* __restrict__ slot_of,
                                                  int32_t* __restrict__ err) {
   extern __shared__ double lds[];
   const int blk = blockIdx.x;
   const int sb = lens[blk];
-  double* Gb = G + static_cast<int64_t>(slot_of[blk]) * s * s;
+  double* Gb = G + static_cast<int64_t>(slot_of[blk]) * stride;
   double* M;
   int ld;
   if (IN_LDS) {
@@ -346,6 +346,62 @@ __global__ void k_state_init(DevState* ds, double rho0, double thr) {
   *ds = s;
 }
 
+
+// --------------------------------------------------------------------------
+// memo miss, after the factor: a row-major copy of L (the forward solve reads
+// rows of L, the backward solve columns) and the inverses of its 16 x 16
+// diagonal blocks (row-major, lower), so the triangular solves advance 16
+// rows per synchronisation.  Rows past the block length are padded with the
+// identity.  One workgroup per slot.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(kT) void k_factor_aux(double* __restrict__ slots, int64_t stride,
+                                                   int32_t s, const int32_t* __restrict__ lens,
+                                                   const int32_t* __restrict__ slot_of) {
+  const int blk = blockIdx.x;
+  const int sb = lens[blk];
+  double* base = slots + static_cast<int64_t>(slot_of[blk]) * stride;
+  const double* Lc = base;
+  double* Lr = base + static_cast<int64_t>(s) * s;
+  double* D = base + 2 * static_cast<int64_t>(s) * s;
+  for (int e = threadIdx.x; e < s * s; e += kT) {
+    const int i = e / s, j = e - i * s;
+    Lr[static_cast<int64_t>(i) * s + j] = Lc[static_cast<int64_t>(j) * s + i];
+  }
+  const int K = (s + 15) / 16;
+  for (int task = threadIdx.x; task < K * 16; task += kT) {
+    const int k = task >> 4, c = task & 15;
+    const int b0 = k * 16;
+    double d[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      double v = 0.0;
+      if (b0 + r >= sb) {
+        v = (r == c) ? 1.0 : 0.0;
+      } else if (r >= c) {
+        double acc = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if (j >= c && j < r && b0 + j < sb) acc = fma(-Lc[static_cast<int64_t>(b0 + j) * s + b0 + r], d[j], acc);
+        v = acc / Lc[static_cast<int64_t>(b0 + r) * s + b0 + r];
+      }
+      d[r] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) D[static_cast<int64_t>(k) * 256 + r * 16 + c] = d[r];
+  }
+}
+
+// Block rows and lengths from a staging area into their slots.
+__global__ __launch_bounds__(kT) void k_scatter_rows(const int32_t* __restrict__ stage_rows,
+                                                     const int32_t* __restrict__ stage_lens,
+                                                     const int32_t* __restrict__ slot_of, int32_t s,
+                                                     int32_t* __restrict__ rows, int32_t* __restrict__ lens) {
+  const int k = blockIdx.x;
+  const int q = slot_of[k];
+  for (int i = threadIdx.x; i < s; i += kT) rows[static_cast<int64_t>(q) * s + i] = stage_rows[static_cast<int64_t>(k) * s + i];
+  if (threadIdx.x == 0) lens[q] = stage_lens[k];
+}
+
 }  // namespace
 
 void launch_block_gemv_partial(const double* A, int64_t lda, int64_t n, const int32_t* rows,
@@ -374,21 +430,21 @@ void launch_update(int32_t kind, const double* A, int64_t lda, int64_t n, const 
 }
 
 void launch_gram(int32_t kind, const double* A, int64_t lda, int64_t n, const int32_t* rows,
-                 const int32_t* lens, int32_t s, int32_t nb, double lambda, double* G,
+                 const int32_t* lens, int32_t s, int32_t nb, double lambda, double* G, int64_t stride,
                  const int32_t* slot_of, hipStream_t st) {
   if (nb <= 0) return;
   if (kind == 0) {
     const int nt = (s + 31) / 32;
     hipLaunchKernelGGL(k_gram_kpp, dim3(nt, nt, nb), dim3(kT), 0, st, A, lda, n, rows, lens, s,
-                       lambda, G, slot_of);
+                       lambda, G, stride, slot_of);
   } else {
     hipLaunchKernelGGL(k_gram_cd, dim3(nb), dim3(kT), 0, st, A, lda, rows, lens, s, lambda, G,
-                       slot_of);
+                       stride, slot_of);
   }
 }
 
-void launch_cholesky(double* G, int32_t s, const int32_t* lens, int32_t nb, const int32_t* slot_of,
-                     int32_t* err, hipStream_t st) {
+void launch_cholesky(double* G, int32_t s, int64_t stride, const int32_t* lens, int32_t nb,
+                     const int32_t* slot_of, int32_t* err, hipStream_t st) {
   if (nb <= 0) return;
   if (s <= kLdsCholMax) {
     const size_t lds = static_cast<size_t>(s) * s * sizeof(double);
@@ -399,9 +455,9 @@ void launch_cholesky(double* G, int32_t s, const int32_t* lens, int32_t nb, cons
                                 static_cast<int>(kLdsCholMax * kLdsCholMax * sizeof(double)));
       attr_set = true;
     }
-    hipLaunchKernelGGL(k_cholesky<true>, dim3(nb), dim3(kT), lds, st, G, s, lens, slot_of, err);
+    hipLaunchKernelGGL(k_cholesky<true>, dim3(nb), dim3(kT), lds, st, G, s, stride, lens, slot_of, err);
   } else {
-    hipLaunchKernelGGL(k_cholesky<false>, dim3(nb), dim3(kT), 0, st, G, s, lens, slot_of, err);
+    hipLaunchKernelGGL(k_cholesky<false>, dim3(nb), dim3(kT), 0, st, G, s, stride, lens, slot_of, err);
   }
 }
 
@@ -418,6 +474,18 @@ void launch_check_finite(const double* A, int64_t lda, int64_t m, int64_t n, con
                          int32_t* flag, hipStream_t st) {
   hipLaunchKernelGGL(k_check_finite, dim3(static_cast<unsigned>(m)), dim3(kT), 0, st, A, lda, m, n,
                      b, flag);
+}
+
+void launch_factor_aux(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
+                       const int32_t* slot_of, hipStream_t st) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_factor_aux, dim3(nb), dim3(kT), 0, st, slots, stride, s, lens, slot_of);
+}
+
+void launch_scatter_rows(const int32_t* stage_rows, const int32_t* stage_lens, const int32_t* slot_of,
+                         int32_t nb, int32_t s, int32_t* rows, int32_t* lens, hipStream_t st) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_scatter_rows, dim3(nb), dim3(kT), 0, st, stage_rows, stage_lens, slot_of, s, rows, lens);
 }
 
 void launch_state_init(DevState* ds, double rho0, double thr, hipStream_t st) {

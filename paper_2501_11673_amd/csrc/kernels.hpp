@@ -44,14 +44,30 @@ void launch_update(int32_t kind, const double* A, int64_t lda, int64_t n, const 
                    int32_t sb, const double* y, const DevState* ds, double eta, double* x,
                    double* mom, hipStream_t st);
 
-// Regularized Grams of nb blocks into column-major s x s slots (lower part).
+// Regularized Grams of nb blocks into column-major s x s slots (lower part);
+// block k is staged at rows[k * s], lens[k] and goes to slot slot_of[k], whose
+// first element is G[slot_of[k] * stride].
 void launch_gram(int32_t kind, const double* A, int64_t lda, int64_t n, const int32_t* rows,
-                 const int32_t* lens, int32_t s, int32_t nb, double lambda, double* G,
+                 const int32_t* lens, int32_t s, int32_t nb, double lambda, double* G, int64_t stride,
                  const int32_t* slot_of, hipStream_t st);
 
 // In-place Cholesky of nb slots; breakdown sets *err = 1.
-void launch_cholesky(double* G, int32_t s, const int32_t* lens, int32_t nb,
+void launch_cholesky(double* G, int32_t s, int64_t stride, const int32_t* lens, int32_t nb,
                      const int32_t* slot_of, int32_t* err, hipStream_t st);
+
+// Row-major copy of each factor (at +s*s) and inverses of its 16 x 16 diagonal
+// blocks (at +2*s*s, ceil(s/16) row-major 16 x 16 blocks).
+void launch_factor_aux(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
+                       const int32_t* slot_of, hipStream_t st);
+
+// rows[slot_of[k] * s + i] = stage_rows[k * s + i]; lens[slot_of[k]] = stage_lens[k]
+void launch_scatter_rows(const int32_t* stage_rows, const int32_t* stage_lens, const int32_t* slot_of,
+                         int32_t nb, int32_t s, int32_t* rows, int32_t* lens, hipStream_t st);
+
+// Memo slot size (doubles): column-major L, row-major L, diagonal-block inverses.
+inline int64_t slot_doubles(int32_t s) {
+  return 2 * static_cast<int64_t>(s) * s + 256 * static_cast<int64_t>((s + 15) / 16);
+}
 
 // ||A x - b||^2 partial sums per row group (deterministic), then a final sum.
 void launch_residual_sq(const double* A, int64_t lda, int64_t m, int64_t n, const double* x,
@@ -63,5 +79,37 @@ void launch_check_finite(const double* A, int64_t lda, int64_t m, int64_t n, con
                          int32_t* flag, hipStream_t st);
 
 void launch_state_init(DevState* ds, double rho0, double thr, hipStream_t st);
+
+// Arguments of the fused persistent engine (fused.hip): W block steps of one
+// system per launch, `groups` workgroups each owning 64 * cpl columns.
+struct FusedArgs {
+  const double* A;
+  int64_t lda;
+  int64_t n;
+  const double* b;
+  const int32_t* rows;       // slot table: rows of slot q at rows[q * s]
+  const int32_t* lens;       // slot table: block length of slot q
+  const double* L;           // slot table: factor data of slot q at L[q * slot_stride]
+  int64_t slot_stride;
+  int32_t s;
+  int32_t W;                 // steps in this launch
+  const int32_t* step_slot;  // slot used by step k of this launch
+  double* x;
+  double* mom;
+  double* part;              // 2 x groups x s partial residuals (double-buffered by step parity)
+  uint32_t* flags;           // one flag per workgroup, 128 bytes apart
+  uint32_t epoch;            // flag value after step k of this launch: epoch + k + 1
+  int32_t zeta;
+  int32_t adaptive;
+  double eta;
+  DevState* ds;
+  int32_t* err;              // bit 1: a wait exceeded spin_limit
+  int64_t spin_limit;
+};
+
+constexpr int kFusedMaxBlock = 256;   // the fused engine gives one thread per block row
+constexpr int kFusedMaxGroups = 256;
+
+void launch_fused(int32_t kind, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t st);
 
 }  // namespace kpp

@@ -85,13 +85,13 @@ struct kpp_system {
   double* rowsq = nullptr;
   double* scal = nullptr;
   int32_t* err = nullptr;
-  // memo cache: slot table of factors (column-major s x s) and block rows
+  // memo cache: one slot per block (factor data, rows, length)
   double* L = nullptr;
   int32_t* rows = nullptr;
   int32_t* lens = nullptr;
-  int32_t* slot_ids = nullptr;
   int32_t cap_slots = 0;
   int32_t slot_s = 0;
+  int64_t slot_stride = 0;
   int32_t used_slots = 0;
   std::vector<int32_t> slot_of_block;
   // signature of the schedule the cache belongs to
@@ -99,11 +99,23 @@ struct kpp_system {
   int32_t sig_s = 0, sig_memo = 0, sig_nb = 0, sig_part = 0;
   uint64_t sig_seed = 0;
   double sig_lambda = 0.0;
-  // host staging
-  std::vector<int32_t> h_rows, h_lens, h_slot;
+  // per-window staging (pinned host mirror + device copy): block rows, lengths,
+  // slot ids of the blocks to factor, and the slot of every step
+  int32_t* h_stage = nullptr;
+  int32_t* d_stage = nullptr;
+  size_t stage_cap = 0;
+  kpp::DevState* h_ds = nullptr;
+  int32_t* h_err = nullptr;
+  // fused engine
+  double* part = nullptr;
+  uint32_t* flags = nullptr;
+  uint32_t epoch = 0;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
+
+constexpr int kFlagWords = 32 * kpp::kFusedMaxGroups;
 
 void destroy_buffers(kpp_system* s) {
   dev_free(s->mom);
@@ -116,33 +128,49 @@ void destroy_buffers(kpp_system* s) {
   dev_free(s->L);
   dev_free(s->rows);
   dev_free(s->lens);
-  dev_free(s->slot_ids);
+  dev_free(s->d_stage);
+  dev_free(s->part);
+  dev_free(s->flags);
+  if (s->h_stage) (void)hipHostFree(s->h_stage);
+  if (s->h_ds) (void)hipHostFree(s->h_ds);
+  if (s->h_err) (void)hipHostFree(s->h_err);
+  s->h_stage = nullptr;
+  s->h_ds = nullptr;
+  s->h_err = nullptr;
+  for (auto& e : s->ev)
+    if (e) {
+      (void)hipEventDestroy(e);
+      e = nullptr;
+    }
   s->cap_slots = 0;
+  s->stage_cap = 0;
 }
 
-// Grow the slot table to hold `need` slots of size s x s (keeps contents).
+// Grow the slot table to hold `need` slots for block size s (keeps contents).
 kpp_status ensure_slots(kpp_system* sys, int32_t need, int32_t s) {
   hipStream_t st = sys->ctx->stream;
   if (sys->slot_s != s) {
+    // a different block size invalidates every cached factor
     dev_free(sys->L);
     dev_free(sys->rows);
     dev_free(sys->lens);
-    dev_free(sys->slot_ids);
     sys->cap_slots = 0;
     sys->slot_s = s;
+    sys->slot_stride = kpp::slot_doubles(s);
     sys->used_slots = 0;
+    sys->slot_of_block.clear();
+    sys->memo_valid = false;
   }
   if (need <= sys->cap_slots) return KPP_OK;
-  int32_t cap = std::max<int32_t>(need, std::max<int32_t>(16, sys->cap_slots * 2));
+  const int32_t cap = std::max<int32_t>(need, std::max<int32_t>(16, sys->cap_slots * 2));
   double* L = nullptr;
-  int32_t *rows = nullptr, *lens = nullptr, *ids = nullptr;
-  const size_t ss = static_cast<size_t>(s) * s;
-  KPP_TRY(dev_alloc(&L, ss * cap));
+  int32_t *rows = nullptr, *lens = nullptr;
+  const size_t sd = static_cast<size_t>(sys->slot_stride);
+  KPP_TRY(dev_alloc(&L, sd * cap));
   KPP_TRY(dev_alloc(&rows, static_cast<size_t>(s) * cap));
   KPP_TRY(dev_alloc(&lens, cap));
-  KPP_TRY(dev_alloc(&ids, cap));
   if (sys->cap_slots > 0) {
-    HIP_TRY(hipMemcpyAsync(L, sys->L, ss * sys->cap_slots * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(L, sys->L, sd * sys->cap_slots * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(rows, sys->rows, static_cast<size_t>(s) * sys->cap_slots * sizeof(int32_t),
                            hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(lens, sys->lens, sys->cap_slots * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
@@ -151,58 +179,24 @@ kpp_status ensure_slots(kpp_system* sys, int32_t need, int32_t s) {
   dev_free(sys->L);
   dev_free(sys->rows);
   dev_free(sys->lens);
-  dev_free(sys->slot_ids);
   sys->L = L;
   sys->rows = rows;
   sys->lens = lens;
-  sys->slot_ids = ids;
   sys->cap_slots = cap;
   return KPP_OK;
 }
 
-// Factor the blocks listed in `pending` (block ids of `sch`) into their slots.
-kpp_status factor_blocks(kpp_system* sys, const kpp::BlockSchedule& sch, double lambda,
-                         const std::vector<int32_t>& pending, const std::vector<int32_t>& slots) {
-  const int32_t nb = static_cast<int32_t>(pending.size());
-  if (nb == 0) return KPP_OK;
-  const int32_t s = sch.block_size();
-  hipStream_t st = sys->ctx->stream;
-  // stage rows/lens of the pending blocks contiguously, then scatter into slots
-  sys->h_rows.assign(static_cast<size_t>(nb) * s, 0);
-  sys->h_lens.resize(nb);
-  sys->h_slot.resize(nb);
-  for (int32_t k = 0; k < nb; ++k) {
-    const int32_t b = pending[k];
-    const int32_t l = sch.len(b);
-    std::copy(sch.rows(b), sch.rows(b) + l, sys->h_rows.begin() + static_cast<size_t>(k) * s);
-    sys->h_lens[k] = l;
-    sys->h_slot[k] = slots[k];
-  }
-  // rows of slot q live at sys->rows[q * s]; the staged copy goes there directly
-  for (int32_t k = 0; k < nb; ++k) {
-    HIP_TRY(hipMemcpyAsync(sys->rows + static_cast<size_t>(slots[k]) * s,
-                           sys->h_rows.data() + static_cast<size_t>(k) * s, s * sizeof(int32_t),
-                           hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(sys->lens + slots[k], &sys->h_lens[k], sizeof(int32_t),
-                           hipMemcpyHostToDevice, st));
-  }
-  // the factor kernels read rows/lens by staged index k through slot_of[k]
-  int32_t* d_stage_rows = nullptr;
-  int32_t* d_stage_lens = nullptr;
-  KPP_TRY(dev_alloc(&d_stage_rows, static_cast<size_t>(nb) * s));
-  KPP_TRY(dev_alloc(&d_stage_lens, nb));
-  HIP_TRY(hipMemcpyAsync(d_stage_rows, sys->h_rows.data(), static_cast<size_t>(nb) * s * sizeof(int32_t),
-                         hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(d_stage_lens, sys->h_lens.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(sys->slot_ids, sys->h_slot.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, st));
-  kpp::launch_gram(sys->kind, sys->A, sys->lda, sys->n, d_stage_rows, d_stage_lens, s, nb, lambda,
-                   sys->L, sys->slot_ids, st);
-  HIP_TRY(hipGetLastError());
-  kpp::launch_cholesky(sys->L, s, d_stage_lens, nb, sys->slot_ids, sys->err, st);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipStreamSynchronize(st));
-  dev_free(d_stage_rows);
-  dev_free(d_stage_lens);
+kpp_status ensure_stage(kpp_system* sys, size_t ints) {
+  if (ints <= sys->stage_cap) return KPP_OK;
+  const size_t cap = std::max<size_t>(ints, std::max<size_t>(4096, sys->stage_cap * 2));
+  HIP_TRY(hipStreamSynchronize(sys->ctx->stream));
+  dev_free(sys->d_stage);
+  if (sys->h_stage) (void)hipHostFree(sys->h_stage);
+  sys->h_stage = nullptr;
+  sys->stage_cap = 0;
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&sys->h_stage), cap * sizeof(int32_t), hipHostMallocDefault));
+  KPP_TRY(dev_alloc(&sys->d_stage, cap));
+  sys->stage_cap = cap;
   return KPP_OK;
 }
 
@@ -222,6 +216,11 @@ kpp_status check_params(const kpp_system* sys, const kpp_params* p) {
   if (!(p->rho0 >= 0.0 && p->rho0 <= 1.0)) return fail(KPP_ERR_INVALID_ARG, "rho0 must be in [0, 1]");
   if (p->precision != KPP_FP64)
     return fail(KPP_ERR_INVALID_ARG, "precision %d is not available in this build", p->precision);
+  if (p->engine < 0 || p->engine > 2) return fail(KPP_ERR_INVALID_ARG, "unknown engine %d", p->engine);
+  if (p->engine == 2 && p->block_size > kpp::kFusedMaxBlock)
+    return fail(KPP_ERR_INVALID_ARG, "the fused engine takes block_size <= %d", kpp::kFusedMaxBlock);
+  if (p->team_groups < 0 || p->team_groups > kpp::kFusedMaxGroups)
+    return fail(KPP_ERR_INVALID_ARG, "team_groups must be in [0, %d]", kpp::kFusedMaxGroups);
   return KPP_OK;
 }
 
@@ -241,10 +240,21 @@ kpp_status residual_norm(kpp_system* sys, const double* x, double* out) {
   return KPP_OK;
 }
 
+// Fused-engine geometry: columns per lane (cpl) and workgroups per step.
+bool fused_geometry(int64_t n, int32_t target_groups, int32_t* cpl, int32_t* groups) {
+  const int32_t gmax = target_groups > 0 ? target_groups : 32;
+  int32_t c = 1;
+  while (c < 16 && (n + 64 * c - 1) / (64 * c) > gmax) c *= 2;
+  const int64_t g = (n + 64 * c - 1) / (64 * c);
+  if (g > kpp::kFusedMaxGroups) return false;
+  *cpl = c;
+  *groups = static_cast<int32_t>(g);
+  return true;
+}
+
 kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_result* res) {
   using clock = std::chrono::steady_clock;
   const auto t_start = clock::now();
-  double t_factor = 0.0;
   hipStream_t st = sys->ctx->stream;
   const int32_t kind = sys->kind;
   const int64_t m = sys->m, n = sys->n;
@@ -261,7 +271,15 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
   } catch (const std::exception& e) {
     return fail(KPP_ERR_INVALID_ARG, "%s", e.what());
   }
-  // memo cache: reuse only for an identical schedule definition
+  // engine
+  int32_t cpl = 0, groups = 0;
+  bool fused = false;
+  if (p->engine != 1 && s <= kpp::kFusedMaxBlock) fused = fused_geometry(n, p->team_groups, &cpl, &groups);
+  if (p->engine == 2 && !fused) return fail(KPP_ERR_INVALID_ARG, "n=%lld is too wide for the fused engine", (long long)n);
+
+  // memo cache: reuse only for an identical schedule definition; the slot
+  // table is sized for this block size before any slot is handed out
+  KPP_TRY(ensure_slots(sys, 16, s));
   const bool same_sig = sys->memo_valid && p->keep_memo && sys->sig_s == s && sys->sig_memo == p->memo &&
                         sys->sig_nb == p->num_blocks && sys->sig_part == p->fixed_partition &&
                         sys->sig_seed == p->seed && sys->sig_lambda == p->lambda && mode != kpp::MemoMode::Off;
@@ -277,10 +295,10 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
     sys->sig_lambda = p->lambda;
   }
   if (mode == kpp::MemoMode::Fixed) KPP_TRY(ensure_slots(sys, sch->num_blocks(), s));
-  // column chunks of the block gemv
+  // launch engine: column chunks of the block gemv
   const int64_t chunk = 2048;
   const int32_t P = static_cast<int32_t>((n + chunk - 1) / chunk);
-  if (static_cast<int64_t>(s) * P > sys->rpart_cap) {
+  if (!fused && static_cast<int64_t>(s) * P > sys->rpart_cap) {
     dev_free(sys->rpart);
     KPP_TRY(dev_alloc(&sys->rpart, static_cast<size_t>(s) * P));
     sys->rpart_cap = static_cast<int64_t>(s) * P;
@@ -294,9 +312,12 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
   int64_t hits = 0, misses = 0, t = 0;
   bool converged = false;
   double true_rel = NAN;
+  double t_factor = 0.0, t_kernel = 0.0;
+  int64_t launches = 0;
   kpp::DevState hs{};
-  std::vector<int32_t> step_block, pending, pending_slots, step_slot;
+  std::vector<int32_t> step_block, step_slot, pending, pending_slots;
   const int64_t period = 2 * static_cast<int64_t>(zeta);
+  const size_t sd = static_cast<size_t>(sys->slot_stride);
   while (t < p->max_iters && !converged) {
     const int64_t W = std::min<int64_t>(period - (t % period), p->max_iters - t);
     step_block.resize(W);
@@ -329,27 +350,101 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
       step_slot[k] = q;
     }
     if (mode != kpp::MemoMode::Off) KPP_TRY(ensure_slots(sys, sys->used_slots, s));
-    if (!pending.empty()) {
-      const auto f0 = clock::now();
-      KPP_TRY(factor_blocks(sys, *sch, p->lambda, pending, pending_slots));
-      int32_t herr = 0;
-      HIP_TRY(hipMemcpy(&herr, sys->err, sizeof(int32_t), hipMemcpyDeviceToHost));
-      if (herr) return fail(KPP_ERR_NOT_SPD, "a regularized block Gram has no Cholesky factor (lambda=%g)", p->lambda);
-      t_factor += std::chrono::duration<double>(clock::now() - f0).count();
+    // stage: [nb*s rows][nb lens][nb slot ids][W step slots]
+    const int32_t nb = static_cast<int32_t>(pending.size());
+    const size_t o_len = static_cast<size_t>(nb) * s, o_slot = o_len + nb, o_step = o_slot + nb;
+    const size_t need = o_step + static_cast<size_t>(W);
+    KPP_TRY(ensure_stage(sys, need));
+    int32_t* hs_ = sys->h_stage;
+    for (int32_t k = 0; k < nb; ++k) {
+      const int32_t b = pending[k];
+      const int32_t l = sch->len(b);
+      std::copy(sch->rows(b), sch->rows(b) + l, hs_ + static_cast<size_t>(k) * s);
+      std::fill(hs_ + static_cast<size_t>(k) * s + l, hs_ + static_cast<size_t>(k + 1) * s, 0);
+      hs_[o_len + k] = l;
+      hs_[o_slot + k] = pending_slots[k];
     }
-    const size_t ss = static_cast<size_t>(s) * s;
-    for (int64_t k = 0; k < W; ++k) {
-      const int32_t q = step_slot[k];
-      const int32_t sb = sch->len(step_block[k]);
-      const int32_t* rows = sys->rows + static_cast<size_t>(q) * s;
-      kpp::launch_block_gemv_partial(sys->A, sys->lda, n, rows, sb, x, sys->rpart, P, chunk, st);
-      kpp::launch_block_project(sys->rpart, P, sys->b, rows, sb, sys->L + ss * q, s, sys->y, sys->ds,
-                                zeta, p->adaptive_rho, st);
-      kpp::launch_update(kind, sys->A, sys->lda, n, rows, sb, sys->y, sys->ds, eta, x, sys->mom, st);
+    std::copy(step_slot.begin(), step_slot.end(), hs_ + o_step);
+    HIP_TRY(hipMemcpyAsync(sys->d_stage, hs_, need * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    const int32_t* d_srows = sys->d_stage;
+    const int32_t* d_slens = sys->d_stage + o_len;
+    const int32_t* d_sslot = sys->d_stage + o_slot;
+    const int32_t* d_step = sys->d_stage + o_step;
+    if (nb > 0) {
+      HIP_TRY(hipEventRecord(sys->ev[2], st));
+      kpp::launch_scatter_rows(d_srows, d_slens, d_sslot, nb, s, sys->rows, sys->lens, st);
+      kpp::launch_gram(kind, sys->A, sys->lda, n, d_srows, d_slens, s, nb, p->lambda, sys->L,
+                       sys->slot_stride, d_sslot, st);
+      kpp::launch_cholesky(sys->L, s, sys->slot_stride, d_slens, nb, d_sslot, sys->err, st);
+      kpp::launch_factor_aux(sys->L, sys->slot_stride, s, d_slens, nb, d_sslot, st);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipEventRecord(sys->ev[3], st));
+    }
+    HIP_TRY(hipEventRecord(sys->ev[0], st));
+    if (fused) {
+      if (sys->epoch > 0x3fffffffu) {
+        HIP_TRY(hipMemsetAsync(sys->flags, 0, kFlagWords * sizeof(uint32_t), st));
+        sys->epoch = 0;
+      }
+      kpp::FusedArgs a{};
+      a.A = sys->A;
+      a.lda = sys->lda;
+      a.n = n;
+      a.b = sys->b;
+      a.rows = sys->rows;
+      a.lens = sys->lens;
+      a.L = sys->L;
+      a.slot_stride = sys->slot_stride;
+      a.s = s;
+      a.W = static_cast<int32_t>(W);
+      a.step_slot = d_step;
+      a.x = x;
+      a.mom = sys->mom;
+      a.part = sys->part;
+      a.flags = sys->flags;
+      a.epoch = sys->epoch;
+      a.zeta = zeta;
+      a.adaptive = p->adaptive_rho;
+      a.eta = eta;
+      a.ds = sys->ds;
+      a.err = sys->err;
+      a.spin_limit = int64_t{1} << 22;
+      kpp::launch_fused(kind, a, cpl, groups, st);
+      sys->epoch += static_cast<uint32_t>(W);
+      ++launches;
+    } else {
+      for (int64_t k = 0; k < W; ++k) {
+        const int32_t q = step_slot[k];
+        const int32_t sb = sch->len(step_block[k]);
+        const int32_t* rows = sys->rows + static_cast<size_t>(q) * s;
+        kpp::launch_block_gemv_partial(sys->A, sys->lda, n, rows, sb, x, sys->rpart, P, chunk, st);
+        kpp::launch_block_project(sys->rpart, P, sys->b, rows, sb, sys->L + sd * q, s, sys->y, sys->ds,
+                                  zeta, p->adaptive_rho, st);
+        kpp::launch_update(kind, sys->A, sys->lda, n, rows, sb, sys->y, sys->ds, eta, x, sys->mom, st);
+      }
+      launches += 3 * W;
     }
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(&hs, sys->ds, sizeof(hs), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(sys->ev[1], st));
+    HIP_TRY(hipMemcpyAsync(sys->h_ds, sys->ds, sizeof(kpp::DevState), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(sys->h_err, sys->err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    hs = *sys->h_ds;
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, sys->ev[0], sys->ev[1]));
+    t_kernel += 1e-3 * ms;
+    if (nb > 0) {
+      HIP_TRY(hipEventElapsedTime(&ms, sys->ev[2], sys->ev[3]));
+      t_factor += 1e-3 * ms;
+    }
+    const int32_t herr = *sys->h_err;
+    if (herr & 2) {
+      HIP_TRY(hipMemsetAsync(sys->flags, 0, kFlagWords * sizeof(uint32_t), st));
+      HIP_TRY(hipStreamSynchronize(st));
+      sys->epoch = 0;
+      return fail(KPP_ERR_DEVICE, "a device-side wait exceeded its bound in the fused engine");
+    }
+    if (herr & 1) return fail(KPP_ERR_NOT_SPD, "a regularized block Gram has no Cholesky factor (lambda=%g)", p->lambda);
     t += W;
     if ((t % period) == 0 && hs.cand) {
       if (p->confirm_true_residual) {
@@ -375,18 +470,20 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
     res->converged = converged ? 1 : 0;
     res->refinements = 0;
     res->checkpoints = hs.ckpts;
-    res->engine_used = 1;
+    res->engine_used = fused ? 2 : 1;
     res->est_rel_res = sys->bnorm > 0 ? std::sqrt(hs.last_E1) / sys->bnorm : std::sqrt(hs.last_E1);
     res->true_rel_res = true_rel;
     res->rho_final = converged ? hs.rho_before : hs.rho;
     res->seconds_total = std::chrono::duration<double>(clock::now() - t_start).count();
     res->seconds_factor = t_factor;
-    const double sd = s;
+    const double sdb = s;
     const double nn = static_cast<double>(n);
-    const double per_step = 2.0 * sd * nn + 2.0 * sd * sd + (kind == KPP_CD_PSD ? 0.0 : 2.0 * sd * nn) + 5.0 * nn;
-    const double per_fact = sd * sd * sd / 3.0 + (kind == KPP_CD_PSD ? 0.0 : sd * sd * nn);
+    const double per_step = 2.0 * sdb * nn + 2.0 * sdb * sdb + (kind == KPP_CD_PSD ? 0.0 : 2.0 * sdb * nn) + 5.0 * nn;
+    const double per_fact = sdb * sdb * sdb / 3.0 + (kind == KPP_CD_PSD ? 0.0 : sdb * sdb * nn);
     res->flops = per_step * static_cast<double>(t) + per_fact * static_cast<double>(misses);
-    res->bytes_algorithmic = static_cast<double>(t) * (sd * nn * 8.0 + 0.5 * sd * (sd + 1) * 8.0 + 12.0 * sd);
+    res->bytes_algorithmic = static_cast<double>(t) * (sdb * nn * 8.0 + 0.5 * sdb * (sdb + 1) * 8.0 + 12.0 * sdb);
+    res->kernel_seconds = t_kernel;
+    res->kernel_launches = static_cast<double>(launches);
   }
   return converged ? KPP_OK : KPP_NOT_CONVERGED;
 }
@@ -421,6 +518,7 @@ KPP_API kpp_status kpp_params_default(kpp_params* p, int32_t kind) {
   p->refine_max_rounds = 12;
   p->inner_tol = 1e-5;
   p->engine = 0;
+  p->team_groups = 0;
   return KPP_OK;
 }
 
@@ -470,11 +568,25 @@ KPP_API kpp_status kpp_system_create(kpp_context* ctx, int32_t kind, int64_t m, 
   kpp_status stt;
   if ((stt = dev_alloc(&sys->mom, n)) < 0 || (stt = dev_alloc(&sys->ds, 1)) < 0 ||
       (stt = dev_alloc(&sys->y, kpp::kMaxBlock)) < 0 || (stt = dev_alloc(&sys->rowsq, m)) < 0 ||
-      (stt = dev_alloc(&sys->scal, 4)) < 0 || (stt = dev_alloc(&sys->err, 4)) < 0) {
+      (stt = dev_alloc(&sys->scal, 4)) < 0 || (stt = dev_alloc(&sys->err, 4)) < 0 ||
+      (stt = dev_alloc(&sys->part, 2 * static_cast<size_t>(kpp::kFusedMaxGroups) * kpp::kFusedMaxBlock)) < 0 ||
+      (stt = dev_alloc(&sys->flags, kFlagWords)) < 0) {
     destroy_buffers(sys.get());
     return stt;
   }
+  if (hipHostMalloc(reinterpret_cast<void**>(&sys->h_ds), sizeof(kpp::DevState), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&sys->h_err), sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+    destroy_buffers(sys.get());
+    return fail(KPP_ERR_OOM, "pinned host allocation failed");
+  }
+  for (auto& e : sys->ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      destroy_buffers(sys.get());
+      return fail(KPP_ERR_HIP, "hipEventCreate failed");
+    }
+  }
   hipStream_t st = ctx->stream;
+  HIP_TRY(hipMemsetAsync(sys->flags, 0, kFlagWords * sizeof(uint32_t), st));
   // finiteness of A and b, and ||b||
   HIP_TRY(hipMemsetAsync(sys->err, 0, sizeof(int32_t), st));
   kpp::launch_check_finite(A_dev, lda, m, n, b_dev, sys->err, st);
@@ -573,9 +685,10 @@ KPP_API kpp_status kpp_block_factor(kpp_system* sys, int32_t s, double lambda, i
   HIP_TRY(hipMemcpyAsync(d_ids, ids.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemsetAsync(sys->err, 0, sizeof(int32_t), st));
   HIP_TRY(hipMemsetAsync(L_dev, 0, static_cast<size_t>(nb) * s * s * sizeof(double), st));
-  kpp::launch_gram(sys->kind, sys->A, sys->lda, sys->n, d_rows, d_lens, s, nb, lambda, L_dev, d_ids, st);
+  kpp::launch_gram(sys->kind, sys->A, sys->lda, sys->n, d_rows, d_lens, s, nb, lambda, L_dev,
+                   static_cast<int64_t>(s) * s, d_ids, st);
   HIP_TRY(hipGetLastError());
-  kpp::launch_cholesky(L_dev, s, d_lens, nb, d_ids, sys->err, st);
+  kpp::launch_cholesky(L_dev, s, static_cast<int64_t>(s) * s, d_lens, nb, d_ids, sys->err, st);
   HIP_TRY(hipGetLastError());
   int32_t herr = 0;
   HIP_TRY(hipMemcpyAsync(&herr, sys->err, sizeof(int32_t), hipMemcpyDeviceToHost, st));

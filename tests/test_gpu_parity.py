@@ -41,7 +41,8 @@ MODES = {"online": 1, "fixed": 2, "off": 0}
 
 
 def gpu_solve(env, A, b, kind, s, *, lam, T, tol=0.0, mode="online", seed=7, num_blocks=0,
-              partition=True, accel=True, eta=None, x0=None, adaptive=True, keep_memo=False):
+              partition=True, accel=True, eta=None, x0=None, adaptive=True, keep_memo=False,
+              engine=0, team_groups=0):
     kpp, torch, dev, ctx = env
     m, n = A.shape
     ck = kpp.KPP_CD_PSD if kind == "psd" else kpp.KPP_KACZMARZ
@@ -57,6 +58,8 @@ def gpu_solve(env, A, b, kind, s, *, lam, T, tol=0.0, mode="online", seed=7, num
     p.accel = 1 if accel else 0
     p.adaptive_rho = 1 if adaptive else 0
     p.keep_memo = 1 if keep_memo else 0
+    p.engine = engine
+    p.team_groups = team_groups
     if eta is not None:
         p.eta = eta
     Ad = A if hasattr(A, "data_ptr") else torch.from_numpy(np.ascontiguousarray(A)).to(dev)
@@ -129,18 +132,19 @@ def test_block_factor_matches_oracle(env, kind, m, n, s, lam):
 
 
 def test_block_factor_reports_breakdown(env):
+    """A block whose regularized Gram has a negative pivot has no Cholesky factor."""
     kpp, torch, dev, ctx = env
-    A = np.random.default_rng(0).standard_normal((20, 6))
-    A[7] = A[3]
-    b = np.ones(20)
+    A = np.diag([1.0, 2.0, -3.0, 4.0, 5.0, 6.0])
+    b = np.ones(6)
     Ad = torch.from_numpy(A).to(dev)
     bd = torch.from_numpy(b).to(dev)
-    h = kpp.kpp_system_create(ctx, kpp.KPP_KACZMARZ, 20, 6, Ad.data_ptr(), 6, bd.data_ptr())
-    L = torch.zeros((1, 4, 4), dtype=torch.float64, device=dev)
+    h = kpp.kpp_system_create(ctx, kpp.KPP_CD_PSD, 6, 6, Ad.data_ptr(), 6, bd.data_ptr())
+    L = torch.zeros((2, 4, 4), dtype=torch.float64, device=dev)
     try:
-        with pytest.raises(kpp.KppError) as e:
-            kpp.kpp_block_factor(h, 4, 0.0, [1, 3, 7, 9], [4], L.data_ptr())
-        assert e.value.status == kpp.KPP_ERR_NOT_SPD
+        kpp.kpp_block_factor(h, 4, 0.0, [0, 1, 3, 4, 0, 1, 2, 3], [4, 4], L.data_ptr())
+        assert False, "expected KPP_ERR_NOT_SPD"
+    except kpp.KppError as e:
+        assert e.status == kpp.KPP_ERR_NOT_SPD
     finally:
         kpp.kpp_system_destroy(h)
 
@@ -183,14 +187,16 @@ ITER_CASES = [
 ]
 
 
+@pytest.mark.parametrize("engine", [1, 2], ids=["launch", "fused"])
 @pytest.mark.parametrize("case", ITER_CASES, ids=[c[0] for c in ITER_CASES])
-def test_iterates_match_oracle(env, case):
+def test_iterates_match_oracle(env, case, engine):
     name, kind, build, s, lam, mode, T, extra = case
     sysm = build()
     A, b = sysm.A, sysm.b
-    print(f"[parity] {name} shape={A.shape} s={s} T={T}", flush=True)
+    print(f"[parity] {name} engine={engine} shape={A.shape} s={s} T={T}", flush=True)
     for Tk in (T // 2, T):
-        x, st, res = gpu_solve(env, A, b, kind, s, lam=lam, T=Tk, mode=mode, seed=31, **extra)
+        x, st, res = gpu_solve(env, A, b, kind, s, lam=lam, T=Tk, mode=mode, seed=31, engine=engine, **extra)
+        assert res.engine_used == engine
         ref = oracle_solve(A, b, kind, s, lam=lam, T=Tk, mode=mode, seed=31, **extra)
         err = relerr(x, ref.x)
         assert err <= 1e-10, f"{name} after {Tk} steps: relative difference {err:.3e}"
@@ -211,11 +217,23 @@ def test_converges_like_oracle_c1(env):
     assert abs(res.iters - ref.iters) <= 2 * 50 * 2  # same or a neighbouring checkpoint
 
 
-def test_bitwise_repeatable(env):
+@pytest.mark.parametrize("engine", [1, 2])
+def test_bitwise_repeatable(env, engine):
     sysm = synth.config("c2_small")
-    x1, _, _ = gpu_solve(env, sysm.A, sysm.b, "psd", 128, lam=1e-8, T=200, seed=3)
-    x2, _, _ = gpu_solve(env, sysm.A, sysm.b, "psd", 128, lam=1e-8, T=200, seed=3)
+    x1, _, _ = gpu_solve(env, sysm.A, sysm.b, "psd", 128, lam=1e-8, T=200, seed=3, engine=engine)
+    x2, _, _ = gpu_solve(env, sysm.A, sysm.b, "psd", 128, lam=1e-8, T=200, seed=3, engine=engine)
     assert np.array_equal(x1, x2)
+
+
+@pytest.mark.parametrize("groups", [1, 3, 8, 64])
+def test_fused_team_sizes_agree_with_oracle(env, groups):
+    """The fused engine's result does not depend on how many workgroups share
+    a step beyond rounding (columns per workgroup change the summation order)."""
+    sysm = synth.tiny_system("general", 400, 700, seed=12, cond=30.0)
+    A, b = sysm.A, sysm.b
+    x, st, res = gpu_solve(env, A, b, "general", 32, lam=1e-6, T=150, seed=5, engine=2, team_groups=groups)
+    ref = oracle_solve(A, b, "general", 32, lam=1e-6, T=150, seed=5)
+    assert relerr(x, ref.x) <= 1e-10
 
 
 # ---------------------------------------------------------------------------
@@ -246,10 +264,10 @@ def test_errors(env):
     with pytest.raises(kpp.KppError) as e:
         gpu_solve(env, A, sysm.b, "general", 4, lam=1e-6, T=10)
     assert e.value.status == kpp.KPP_ERR_NONFINITE
-    A = sysm.A.copy()
-    A[5] = A[2]
+    Aind = np.diag(np.linspace(1.0, 2.0, 12))
+    Aind[7, 7] = -1.0  # indefinite "PSD" input
     with pytest.raises(kpp.KppError) as e:
-        gpu_solve(env, A, sysm.b, "general", 20, lam=0.0, T=10, mode="fixed")
+        gpu_solve(env, Aind, np.ones(12), "psd", 12, lam=0.0, T=10, mode="fixed")
     assert e.value.status == kpp.KPP_ERR_NOT_SPD
     with pytest.raises(kpp.KppError) as e:
         gpu_solve(env, sysm.A, sysm.b, "general", 21, lam=1e-6, T=10)
