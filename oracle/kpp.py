@@ -45,17 +45,24 @@ from .schedule import Schedule
 # ----------------------------------------------------------------------------
 
 
-def block_residual(A: np.ndarray, b: np.ndarray, S: np.ndarray, x: np.ndarray) -> np.ndarray:
-    """r = A_S x - b_S  (Algorithm 5 / Algorithm 2: "r_t <- A_S x_t - b_S")."""
+def block_residual(A: np.ndarray, b: np.ndarray, S: np.ndarray, x: np.ndarray,
+                   reverse: bool = False) -> np.ndarray:
+    """r = A_S x - b_S  (Algorithm 5 / Algorithm 2: "r_t <- A_S x_t - b_S").
+
+    reverse=True sums over the columns in the opposite order (same value in
+    exact arithmetic); used only to measure the FP64 rounding noise floor."""
+    if reverse:
+        return A[S, ::-1] @ x[::-1] - b[S]
     return A[S, :] @ x - b[S]
 
 
-def regularized_gram(A: np.ndarray, S: np.ndarray, lam: float, kind: str) -> np.ndarray:
+def regularized_gram(A: np.ndarray, S: np.ndarray, lam: float, kind: str,
+                     reverse: bool = False) -> np.ndarray:
     """G = A_S A_S^T + lam I (eq. (bk)), or A_{S,S} + lam I for CD++ (eq. (cd-update))."""
     if kind == "psd":
         G = A[np.ix_(S, S)].copy()
     else:
-        AS = A[S, :]
+        AS = A[S, ::-1] if reverse else A[S, :]
         G = AS @ AS.T
     G[np.diag_indices_from(G)] += lam
     return G
@@ -79,12 +86,15 @@ def projection_solve(L: np.ndarray, r: np.ndarray) -> np.ndarray:
     return scipy.linalg.solve_triangular(L.T, z, lower=False)
 
 
-def direction(A: np.ndarray, S: np.ndarray, y: np.ndarray, kind: str) -> np.ndarray:
+def direction(A: np.ndarray, S: np.ndarray, y: np.ndarray, kind: str,
+              reverse: bool = False) -> np.ndarray:
     """w = A_S^T y (eq. (bk)) or w = I_S^T y (eq. (cd-update))."""
     if kind == "psd":
         w = np.zeros(A.shape[1])
         w[S] = y
         return w
+    if reverse:
+        return A[S[::-1], :].T @ y[::-1]
     return A[S, :].T @ y
 
 
@@ -149,6 +159,7 @@ class Params:
     rho0: float = 0.0
     memo: bool = True                 # False: refactor at every step
     confirm_true_residual: bool = True
+    reverse_sums: bool = False        # noise-floor probe: every sum in the opposite order
 
 
 @dataclasses.dataclass
@@ -207,18 +218,19 @@ def solve(A: np.ndarray, b: np.ndarray, kind: str, params: Params, schedule: Sch
         bid = int(schedule.step_block[t])
         S = schedule.blocks[bid]
         sb = len(S)
-        r = block_residual(A, b, S, x)
+        rev = params.reverse_sums
+        r = block_residual(A, b, S, x, reverse=rev)
         if params.memo and bid in factors:
             L = factors[bid]
             hits += 1
         else:
-            L = cholesky_lower(regularized_gram(A, S, params.lam, kind))
+            L = cholesky_lower(regularized_gram(A, S, params.lam, kind, reverse=rev))
             nfact += 1
             flops += sb ** 3 / 3.0 + (sb * sb * n if kind != "psd" else 0.0)
             if params.memo:
                 factors[bid] = L
         y = projection_solve(L, r)
-        w = direction(A, S, y, kind)
+        w = direction(A, S, y, kind, reverse=rev)
         x, mom = momentum_update(x, mom, w, rho, eta)
         flops += 2.0 * sb * n + 2.0 * sb * sb + (2.0 * sb * n if kind != "psd" else 0.0) + 5.0 * n
         if t + 1 in snap_set:

@@ -77,14 +77,25 @@ def gpu_solve(env, A, b, kind, s, *, lam, T, tol=0.0, mode="online", seed=7, num
 
 
 def oracle_solve(A, b, kind, s, *, lam, T, tol=0.0, mode="online", seed=7, num_blocks=0,
-                 partition=True, accel=True, eta=None, x0=None, adaptive=True, snapshot_steps=()):
+                 partition=True, accel=True, eta=None, x0=None, adaptive=True, snapshot_steps=(),
+                 reverse_sums=False):
     m, n = A.shape
     N = n if kind == "psd" else m
     schd = osch.make_schedule(mode, N, s, T, seed, B0=osch.online_rate(kind, m, n, s),
                               num_blocks=num_blocks, partition=partition)
     p = okpp.Params(s=s, lam=lam, tol=tol, max_iters=T, accel=accel, eta=eta,
-                    adaptive_rho=adaptive, memo=(mode != "off"))
+                    adaptive_rho=adaptive, memo=(mode != "off"), reverse_sums=reverse_sums)
     return okpp.solve(A, b, kind, p, schd, x0=x0, snapshot_steps=snapshot_steps)
+
+
+def parity_bound(A, b, kind, s, ref, **kw):
+    """max(1e-10, 10 nf): nf is the FP64 noise floor of the trajectory, the
+    oracle's distance to itself with every sum taken in the opposite order.
+    Ill-conditioned block Grams (kappa ~ 1e9) amplify rounding past 1e-10 for
+    any two valid FP64 implementations; well-conditioned cases keep 1e-10."""
+    alt = oracle_solve(A, b, kind, s, reverse_sums=True, **kw)
+    nf = relerr(alt.x, ref.x)
+    return max(1e-10, 10.0 * nf), nf
 
 
 # ---------------------------------------------------------------------------
@@ -198,8 +209,10 @@ def test_iterates_match_oracle(env, case, engine):
         x, st, res = gpu_solve(env, A, b, kind, s, lam=lam, T=Tk, mode=mode, seed=31, engine=engine, **extra)
         assert res.engine_used == engine
         ref = oracle_solve(A, b, kind, s, lam=lam, T=Tk, mode=mode, seed=31, **extra)
+        bound, nf = parity_bound(A, b, kind, s, ref, lam=lam, T=Tk, mode=mode, seed=31, **extra)
         err = relerr(x, ref.x)
-        assert err <= 1e-10, f"{name} after {Tk} steps: relative difference {err:.3e}"
+        print(f"[parity] {name} T={Tk}: |x_gpu - x_orc|/|x_orc| = {err:.3e}, noise floor {nf:.3e}", flush=True)
+        assert err <= bound, f"{name} after {Tk} steps: relative difference {err:.3e} (noise floor {nf:.3e})"
         assert res.iters == Tk
         assert res.memo_misses == ref.factorizations
         assert res.rho_final == pytest.approx(ref.rho_final, rel=1e-8, abs=1e-12)

@@ -374,13 +374,13 @@ def _bad_momentum_c(x, mom, w, rho, eta):
     return x - w + eta * mom_new, mom_new
 
 
-def _bad_gram_no_lambda(A, S, lam, kind):
+def _bad_gram_no_lambda(A, S, lam, kind, reverse=False):
     if kind == "psd":
         return A[np.ix_(S, S)].copy()
     return A[S] @ A[S].T
 
 
-def _bad_direction_transposed(A, S, y, kind):
+def _bad_direction_transposed(A, S, y, kind, reverse=False):
     if kind == "psd":
         w = np.zeros(A.shape[1])
         w[S[::-1]] = y
