@@ -2,23 +2,26 @@
 //
 // One launch runs W consecutive block steps of Kaczmarz++ (Algorithm 5, exact
 // projection) or CD++ (Algorithm 2) for one system.  Workgroup g owns a
-// contiguous column slice of x and of the momentum m and keeps it in
-// registers for the whole launch.  Per step:
-//   1. partial block residual over the slice: p_g = A_S[:, J_g] x[J_g]
-//      (coalesced: the 64 lanes of a wave read consecutive columns of a row);
-//   2. publish p_g, then wait until every workgroup has published (one
-//      all-gather through per-workgroup flags: the only cross-CU sync of the
-//      step) and form r = sum_g p_g - b_S in a fixed order, identically in
-//      every workgroup;
-//   3. every workgroup solves y = (L L^T)^{-1} r itself with the memoized
-//      factor (blocked forward/back substitution, 16 rows per step through
-//      the inverted diagonal blocks), so no second sync is needed;
-//   4. w on the slice: A_S[:, J_g]^T y (Kaczmarz++, the A_S tile is still in
-//      L2) or the entries of y whose rows fall in the slice (CD++), then
-//      m <- c (m - w), x <- x - w + eta m (eq. (momentum));
+// contiguous column slice J_g of x and of the momentum m (64 * CPL columns,
+// CPL per lane) and keeps it in registers for the whole launch.  Per step:
+//   1. the workgroup's tile A_S[:, J_g] sits in registers (wave v holds block
+//      rows v, v+4, ...; the 64 lanes of a wave read consecutive columns of a
+//      row, so every load is coalesced); partial residuals p_g = A_S[:, J_g]
+//      x[J_g] are reduced across lanes by a butterfly (RMAX rows at once);
+//   2. publish p_g; wait until every workgroup has published (one
+//      all-gather through per-workgroup flags: the step's only cross-CU
+//      sync); r = sum_g p_g - b_S, summed in the same order in every
+//      workgroup.  CD++ issues the loads of the next step's tile before it
+//      waits, so HBM latency hides behind the sync (the block sequence never
+//      depends on x);
+//   3. y = (A_S A_S^T + lam I)^{-1} r through the memoized inverse
+//      G^{-1} = L^{-T} L^{-1} of the block's Cholesky factor: CD++ needs only
+//      the rows of y whose coordinates fall into J_g (w = I_S^T y), Kaczmarz++
+//      needs all of y (w = A_S^T y) and forms it in every workgroup;
+//   4. w on the slice, then m <- c (m - w), x <- x - w + eta m (eq. (momentum));
 //   5. window sums and the checkpoint of Section 5.4 (identical scalars in
 //      every workgroup; workgroup 0 writes them back).
-// Every wait is bounded; on time-out the kernel sets err = 2 and all
+// Every wait is bounded; on time-out the kernel sets err bit 2 and all
 // workgroups leave, so a launch always ends.
 #include <hip/hip_runtime.h>
 
@@ -31,6 +34,7 @@ namespace {
 
 constexpr int kT = 256;
 constexpr int kFlagStride = 32;  // uint32 words between flags (128 bytes)
+constexpr int kTileMax = 64;     // tile doubles per lane
 
 __device__ __forceinline__ double ld_coherent(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -51,79 +55,56 @@ __device__ __forceinline__ double rho_from_rate(double rhat, int zeta) {
   return fmin(1.0, fmax(0.0, r));
 }
 
-// y = (L L^T)^{-1} r for one block, 256 threads, thread i owns row i (sb <= 256).
-// In: rv[i] = r_i.  Out: rv[i] = y_i.  zv is scratch.  Lc: column-major L,
-// Lr: row-major L, D: inverses of the 16 x 16 diagonal blocks (row-major).
-__device__ __forceinline__ void block_solve(double* rv, double* zv, const double* __restrict__ Lc,
-                                            const double* __restrict__ Lr,
-                                            const double* __restrict__ D, int s, int sb) {
-  const int i = threadIdx.x;
-  const int K = (sb + 15) >> 4;
-  double ri = (i < sb) ? rv[i] : 0.0;
-  // forward: z = L^{-1} r
-  for (int k = 0; k < K; ++k) {
-    const int b0 = k << 4;
-    const bool mine = (i >= b0) && (i < b0 + 16);
-    if (mine) zv[i] = ri;
-    __syncthreads();
-    if (mine) {
-      const int ii = i - b0;
-      const double* Dk = D + k * 256 + ii * 16;
-      double acc = 0.0;
-      for (int c = 0; c <= ii; ++c) acc = fma(Dk[c], zv[b0 + c], acc);
-      rv[i] = acc;
-    }
-    __syncthreads();
-    if (i >= b0 + 16 && i < sb) {
-      const double* Li = Lr + static_cast<int64_t>(i) * s + b0;
-      const int cmax = min(16, sb - b0);
-      for (int c = 0; c < cmax; ++c) ri = fma(-Li[c], rv[b0 + c], ri);
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Load this wave's rows of the block tile: tile[r * CPL + e] = A[rows[wv + 4r], col0 + e].
+template <int CPL>
+__device__ __forceinline__ void load_tile(double (&tile)[kTileMax], const double* __restrict__ A,
+                                          int64_t lda, int64_t n, const int32_t* __restrict__ rows,
+                                          int sb, int wv, int64_t col0) {
+  constexpr int RMAX = kTileMax / CPL;
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r) {
+    const int i = wv + 4 * r;
+    if (i < sb) {
+      const double* Ai = A + static_cast<int64_t>(rows[i]) * lda;
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) tile[r * CPL + e] = (col0 + e < n) ? Ai[col0 + e] : 0.0;
+    } else {
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) tile[r * CPL + e] = 0.0;
     }
   }
-  __syncthreads();
-  // backward: y = L^{-T} z
-  double zi = (i < sb) ? rv[i] : 0.0;
-  for (int k = K - 1; k >= 0; --k) {
-    const int b0 = k << 4;
-    const bool mine = (i >= b0) && (i < b0 + 16);
-    if (mine) zv[i] = zi;
-    __syncthreads();
-    if (mine) {
-      const int ii = i - b0;
-      const double* Dk = D + k * 256;
-      double acc = 0.0;
-      for (int c = 15; c >= ii; --c) acc = fma(Dk[c * 16 + ii], zv[b0 + c], acc);
-      rv[i] = acc;
-    }
-    __syncthreads();
-    if (i < b0) {
-      const double* Lci = Lc + static_cast<int64_t>(i) * s + b0;
-      const int cmax = min(16, sb - b0);
-      for (int c = 0; c < cmax; ++c) zi = fma(-Lci[c], rv[b0 + c], zi);
-    }
-  }
-  __syncthreads();
 }
 
 template <int KIND, int CPL>
 __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
+  constexpr int RMAX = kTileMax / CPL;   // rows per wave held in registers (power of two)
+  constexpr int RSHIFT = (RMAX == 64) ? 0 : (RMAX == 32) ? 1 : (RMAX == 16) ? 2 : (RMAX == 8) ? 3 : 4;
   __shared__ int32_t rs[256];
   __shared__ double rv[256];
-  __shared__ double zv[256];
+  __shared__ double yv[256];
   __shared__ double stage[256];
   __shared__ double wred[KIND == 0 ? 4 * 64 * CPL : 1];
   __shared__ double red[4];
   __shared__ double bc_c;
   __shared__ int abort_flag;
+  __shared__ int slice_lo, slice_hi;
 
   const int G = gridDim.x;
   const int wg = blockIdx.x;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
-  const int64_t col0 = static_cast<int64_t>(wg) * 64 * CPL + static_cast<int64_t>(lane) * CPL;
   const int64_t n = a.n;
   const int s = a.s;
+  const int64_t slice0 = static_cast<int64_t>(wg) * 64 * CPL;
+  const int64_t slice1 = min(n, slice0 + 64 * CPL);
+  const int64_t col0 = slice0 + static_cast<int64_t>(lane) * CPL;
 
   double xr[CPL], mr[CPL];
 #pragma unroll
@@ -137,37 +118,76 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
     st = *a.ds;
     abort_flag = 0;
   }
+  double tile[kTileMax];
+  int q = a.step_slot[0];
+  int sb = a.lens[q];
+  load_tile<CPL>(tile, a.A, a.lda, n, a.rows + static_cast<int64_t>(q) * s, sb, wv, col0);
   __syncthreads();
 
   for (int k = 0; k < a.W; ++k) {
-    const int q = a.step_slot[k];
-    const int sb = a.lens[q];
+    if (KIND == 0 && k > 0) {
+      q = a.step_slot[k];
+      sb = a.lens[q];
+      load_tile<CPL>(tile, a.A, a.lda, n, a.rows + static_cast<int64_t>(q) * s, sb, wv, col0);
+    }
     const int32_t* R = a.rows + static_cast<int64_t>(q) * s;
-    const double* Lc = a.L + static_cast<int64_t>(q) * a.slot_stride;
+    const double* Ginv = a.L + static_cast<int64_t>(q) * a.slot_stride + static_cast<int64_t>(s) * s;
     if (tid < sb) rs[tid] = R[tid];
-    __syncthreads();
 
-    // 1. partial block residual over this workgroup's columns
-    for (int i = wv; i < sb; i += 4) {
-      const double* Ai = a.A + static_cast<int64_t>(rs[i]) * a.lda;
+    // 1. partial residuals of this wave's rows, butterfly across the lanes
+    double v[RMAX];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
       double acc = 0.0;
 #pragma unroll
-      for (int e = 0; e < CPL; ++e) {
-        const int64_t j = col0 + e;
-        if (j < n) acc = fma(Ai[j], xr[e], acc);
-      }
+      for (int e = 0; e < CPL; ++e) acc = fma(tile[r * CPL + e], xr[e], acc);
+      v[r] = acc;
+    }
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-      if (lane == 0) stage[i] = acc;
+    for (int cnt = RMAX, o = 32; cnt > 1; cnt >>= 1, o >>= 1) {
+      const bool up = (lane & o) != 0;
+#pragma unroll
+      for (int r = 0; r < cnt / 2; ++r) {
+        const double send = up ? v[r] : v[r + cnt / 2];
+        const double keep = up ? v[r + cnt / 2] : v[r];
+        v[r] = keep + __shfl_xor(send, o, 64);
+      }
+    }
+#pragma unroll
+    for (int o = 32 / RMAX; o >= 1; o >>= 1) v[0] += __shfl_xor(v[0], o, 64);
+    {
+      const int row = wv + 4 * (lane >> RSHIFT);
+      if ((lane & ((1 << RSHIFT) - 1)) == 0 && row < sb) stage[row] = v[0];
     }
     __syncthreads();
 
-    // 2. publish, all-gather, reduce in a fixed order
+    // 2. publish, prefetch the next tile (CD++), all-gather, reduce in a fixed order
     const uint32_t ep = a.epoch + static_cast<uint32_t>(k) + 1u;
     double* Pb = a.part + static_cast<size_t>(ep & 1u) * G * s;
     if (wv == 0) {
       for (int i = lane; i < sb; i += 64) st_coherent(&Pb[static_cast<size_t>(wg) * s + i], stage[i]);
       if (lane == 0) st_flag_release(&a.flags[wg * kFlagStride], ep);
+    }
+    int qn = q, sbn = sb;
+    if (KIND == 1 && k + 1 < a.W) {
+      qn = a.step_slot[k + 1];
+      sbn = a.lens[qn];
+      load_tile<CPL>(tile, a.A, a.lda, n, a.rows + static_cast<int64_t>(qn) * s, sbn, wv, col0);
+    }
+    if (tid == 0) {
+      // block rows whose coordinates fall into this slice (rows are sorted)
+      int lo = 0, hi = sb;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (rs[mid] < slice0) lo = mid + 1; else hi = mid;
+      }
+      int lo2 = lo, hi2 = sb;
+      while (lo2 < hi2) {
+        const int mid = (lo2 + hi2) >> 1;
+        if (rs[mid] < slice1) lo2 = mid + 1; else hi2 = mid;
+      }
+      slice_lo = lo;
+      slice_hi = lo2;
     }
     if (tid < G) {
       int64_t spins = 0;
@@ -184,18 +204,49 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
     double ri = 0.0;
     if (tid < sb) {
       double acc = 0.0;
-      for (int g = 0; g < G; ++g) acc += ld_coherent(&Pb[static_cast<size_t>(g) * s + tid]);
+      int g = 0;
+      for (; g + 8 <= G; g += 8) {
+        double t8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t8[u] = ld_coherent(&Pb[static_cast<size_t>(g + u) * s + tid]);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += t8[u];
+      }
+      for (; g < G; ++g) acc += ld_coherent(&Pb[static_cast<size_t>(g) * s + tid]);
       ri = acc - a.b[rs[tid]];
       rv[tid] = ri;
     }
-    double part = fma(ri, ri, 0.0);
+    {
+      double part = fma(ri, ri, 0.0);
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
-    if (lane == 0) red[wv] = part;
+      for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
+      if (lane == 0) red[wv] = part;
+    }
     __syncthreads();
 
-    // 3. projection solve (every workgroup, same arithmetic)
-    block_solve(rv, zv, Lc, Lc + static_cast<int64_t>(s) * s, Lc + 2 * static_cast<int64_t>(s) * s, s, sb);
+    // 3. y through the memoized inverse
+    if (KIND == 1) {
+      const int lo = slice_lo, hi = slice_hi;
+      for (int i = lo + wv; i < hi; i += 4) {
+        const double* Gi = Ginv + static_cast<int64_t>(i) * s;
+        double acc = 0.0;
+        for (int kk = lane; kk < sb; kk += 64) acc = fma(Gi[kk], rv[kk], acc);
+        acc = wave_sum(acc);
+        if (lane == 0) yv[i] = acc;
+      }
+    } else if (tid < sb) {
+      double acc = 0.0;
+      int kk = 0;
+      for (; kk + 16 <= sb; kk += 16) {
+        double g16[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) g16[u] = Ginv[static_cast<int64_t>(kk + u) * s + tid];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc = fma(g16[u], rv[kk + u], acc);
+      }
+      for (; kk < sb; ++kk) acc = fma(Ginv[static_cast<int64_t>(kk) * s + tid], rv[kk], acc);
+      yv[tid] = acc;
+    }
 
     // 5. scalars: c for this step, window sums, checkpoint
     if (tid == 0) {
@@ -241,14 +292,12 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
 #pragma unroll
     for (int e = 0; e < CPL; ++e) w[e] = 0.0;
     if (KIND == 0) {
-      for (int i = wv; i < sb; i += 4) {
-        const double* Ai = a.A + static_cast<int64_t>(rs[i]) * a.lda;
-        const double yi = rv[i];
 #pragma unroll
-        for (int e = 0; e < CPL; ++e) {
-          const int64_t j = col0 + e;
-          if (j < n) w[e] = fma(Ai[j], yi, w[e]);
-        }
+      for (int r = 0; r < RMAX; ++r) {
+        const int i = wv + 4 * r;
+        const double yi = (i < sb) ? yv[i] : 0.0;
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) w[e] = fma(tile[r * CPL + e], yi, w[e]);
       }
 #pragma unroll
       for (int e = 0; e < CPL; ++e) wred[wv * 64 * CPL + lane * CPL + e] = w[e];
@@ -259,18 +308,16 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
         w[e] = ((wred[o] + wred[64 * CPL + o]) + wred[128 * CPL + o]) + wred[192 * CPL + o];
       }
     } else {
+      const int lo = slice_lo, hi = slice_hi;
 #pragma unroll
       for (int e = 0; e < CPL; ++e) {
         const int64_t j = col0 + e;
-        int lo = 0, hi = sb;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (rs[mid] < j)
-            lo = mid + 1;
-          else
-            hi = mid;
+        int l = lo, h = hi;
+        while (l < h) {
+          const int mid = (l + h) >> 1;
+          if (rs[mid] < j) l = mid + 1; else h = mid;
         }
-        if (lo < sb && rs[lo] == j) w[e] = rv[lo];
+        if (l < hi && rs[l] == j) w[e] = yv[l];
       }
     }
 #pragma unroll
@@ -279,6 +326,8 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
       mr[e] = mn;
       xr[e] = __dadd_rn(__dsub_rn(xr[e], w[e]), __dmul_rn(a.eta, mn));
     }
+    q = qn;
+    sb = sbn;
     __syncthreads();
   }
 

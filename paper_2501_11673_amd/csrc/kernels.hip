@@ -57,15 +57,13 @@ __global__ __launch_bounds__(kT) void k_block_gemv_partial(
 }
 
 // --------------------------------------------------------------------------
-// projection solve and checkpoint bookkeeping: one workgroup
+// projection through the memoized inverse and checkpoint bookkeeping: one workgroup
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(kT) void k_block_project(
     const double* __restrict__ rpart, int32_t P, const double* __restrict__ b,
-    const int32_t* __restrict__ rows, int32_t sb, const double* __restrict__ L, int32_t ldl,
+    const int32_t* __restrict__ rows, int32_t sb, const double* __restrict__ Ginv, int32_t ldl,
     double* __restrict__ y, DevState* __restrict__ ds, int32_t zeta, int32_t adaptive) {
   __shared__ double r[kMaxBlock];
-  __shared__ double z[kMaxBlock];
-  __shared__ double yy[kMaxBlock];
   __shared__ double red[4];
   const int tid = threadIdx.x;
   double part = 0.0;
@@ -78,23 +76,13 @@ __global__ __launch_bounds__(kT) void k_block_project(
     part = fma(ri, ri, part);
   }
   const double rr = block_sum(part, red);
-  // forward substitution z = L^{-1} r, column by column
-  for (int j = 0; j < sb; ++j) {
-    __syncthreads();
-    const double zj = r[j] / L[static_cast<int64_t>(j) * ldl + j];
-    for (int i = j + 1 + tid; i < sb; i += kT)
-      r[i] = fma(-L[static_cast<int64_t>(j) * ldl + i], zj, r[i]);
-    if (tid == 0) z[j] = zj;
-  }
-  // back substitution y = L^{-T} z
-  for (int j = sb - 1; j >= 0; --j) {
-    __syncthreads();
-    const double yj = z[j] / L[static_cast<int64_t>(j) * ldl + j];
-    for (int i = tid; i < j; i += kT) z[i] = fma(-L[static_cast<int64_t>(i) * ldl + j], yj, z[i]);
-    if (tid == 0) yy[j] = yj;
-  }
   __syncthreads();
-  for (int i = tid; i < sb; i += kT) y[i] = yy[i];
+  // y = G^{-1} r with the memoized inverse (symmetric: column i = row i)
+  for (int i = tid; i < sb; i += kT) {
+    double acc = 0.0;
+    for (int k = 0; k < sb; ++k) acc = fma(Ginv[static_cast<int64_t>(k) * ldl + i], r[k], acc);
+    y[i] = acc;
+  }
   if (tid == 0) {
     DevState s = *ds;
     const double rho = s.rho;
@@ -272,15 +260,11 @@ __global__ __launch_bounds__(kT) void k_cholesky(double* __restrict__ G, int32_t
     for (int i = j + 1 + threadIdx.x; i < sb; i += kT) M[static_cast<int64_t>(j) * ld + i] /= d;
     __syncthreads();
     if (threadIdx.x == 0) M[static_cast<int64_t>(j) * ld + j] = d;
-    const int rem = sb - j - 1;
-    for (int idx = threadIdx.x; idx < rem * rem; idx += kT) {
-      const int kk = idx / rem, ii = idx - kk * rem;
-      if (ii >= kk) {
-        const int k = j + 1 + kk, i = j + 1 + ii;
-        M[static_cast<int64_t>(k) * ld + i] =
-            fma(-M[static_cast<int64_t>(j) * ld + i], M[static_cast<int64_t>(j) * ld + k],
-                M[static_cast<int64_t>(k) * ld + i]);
-      }
+    // trailing update, one row per thread: M(i, k) -= L(i, j) L(k, j), j < k <= i
+    for (int i = j + 1 + threadIdx.x; i < sb; i += kT) {
+      const double lij = M[static_cast<int64_t>(j) * ld + i];
+      for (int k = j + 1; k <= i; ++k)
+        M[static_cast<int64_t>(k) * ld + i] = fma(-lij, M[static_cast<int64_t>(j) * ld + k], M[static_cast<int64_t>(k) * ld + i]);
     }
   }
   __syncthreads();
@@ -348,46 +332,63 @@ __global__ void k_state_init(DevState* ds, double rho0, double thr) {
 
 
 // --------------------------------------------------------------------------
-// memo miss, after the factor: a row-major copy of L (the forward solve reads
-// rows of L, the backward solve columns) and the inverses of its 16 x 16
-// diagonal blocks (row-major, lower), so the triangular solves advance 16
-// rows per synchronisation.  Rows past the block length are padded with the
-// identity.  One workgroup per slot.
+// memo miss, after the factor: G^{-1} = L^{-T} L^{-1} of the block (stored
+// after L in the slot, full symmetric, row = column).  L^{-1} comes from an
+// in-place triangular inversion (column j from the right: the inverse's column
+// j is -(1/L_jj) times the already inverted trailing triangle applied to
+// L's column j below the diagonal); then G^{-1}(i, k) = sum_{r >= max(i,k)}
+// L^{-1}(r, i) L^{-1}(r, k).  Blocks up to kLdsCholMax rows work in LDS
+// (leading dimension sb + 1 against bank conflicts), larger ones in the
+// slot's scratch third.  One workgroup per slot.
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(kT) void k_factor_aux(double* __restrict__ slots, int64_t stride,
-                                                   int32_t s, const int32_t* __restrict__ lens,
-                                                   const int32_t* __restrict__ slot_of) {
+template <bool IN_LDS>
+__global__ __launch_bounds__(kT) void k_factor_inverse(double* __restrict__ slots, int64_t stride,
+                                                       int32_t s, const int32_t* __restrict__ lens,
+                                                       const int32_t* __restrict__ slot_of) {
+  extern __shared__ double lds[];
   const int blk = blockIdx.x;
   const int sb = lens[blk];
   double* base = slots + static_cast<int64_t>(slot_of[blk]) * stride;
   const double* Lc = base;
-  double* Lr = base + static_cast<int64_t>(s) * s;
-  double* D = base + 2 * static_cast<int64_t>(s) * s;
-  for (int e = threadIdx.x; e < s * s; e += kT) {
-    const int i = e / s, j = e - i * s;
-    Lr[static_cast<int64_t>(i) * s + j] = Lc[static_cast<int64_t>(j) * s + i];
+  double* Gi = base + static_cast<int64_t>(s) * s;
+  double* M;
+  double* tmp;
+  int64_t ld;
+  if (IN_LDS) {
+    M = lds;
+    ld = sb + 1;
+    tmp = lds + static_cast<int64_t>(sb) * ld;
+  } else {
+    M = base + 2 * static_cast<int64_t>(s) * s;
+    ld = s;
+    tmp = Gi;  // G^{-1} is written only after the inversion; its first column is free until then
   }
-  const int K = (s + 15) / 16;
-  for (int task = threadIdx.x; task < K * 16; task += kT) {
-    const int k = task >> 4, c = task & 15;
-    const int b0 = k * 16;
-    double d[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      double v = 0.0;
-      if (b0 + r >= sb) {
-        v = (r == c) ? 1.0 : 0.0;
-      } else if (r >= c) {
-        double acc = (r == c) ? 1.0 : 0.0;
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-          if (j >= c && j < r && b0 + j < sb) acc = fma(-Lc[static_cast<int64_t>(b0 + j) * s + b0 + r], d[j], acc);
-        v = acc / Lc[static_cast<int64_t>(b0 + r) * s + b0 + r];
-      }
-      d[r] = v;
+  // M = L (column-major, lower)
+  for (int e = threadIdx.x; e < sb * sb; e += kT) {
+    const int k = e / sb, i = e - k * sb;
+    M[k * ld + i] = (i >= k) ? Lc[static_cast<int64_t>(k) * s + i] : 0.0;
+  }
+  for (int j = sb - 1; j >= 0; --j) {
+    __syncthreads();
+    const double d = 1.0 / M[static_cast<int64_t>(j) * ld + j];
+    for (int i = j + 1 + threadIdx.x; i < sb; i += kT) {
+      double acc = 0.0;
+      for (int k = j + 1; k <= i; ++k) acc = fma(M[static_cast<int64_t>(k) * ld + i], M[static_cast<int64_t>(j) * ld + k], acc);
+      tmp[i] = acc;
     }
-#pragma unroll
-    for (int r = 0; r < 16; ++r) D[static_cast<int64_t>(k) * 256 + r * 16 + c] = d[r];
+    __syncthreads();
+    for (int i = j + 1 + threadIdx.x; i < sb; i += kT) M[static_cast<int64_t>(j) * ld + i] = -d * tmp[i];
+    if (threadIdx.x == 0) M[static_cast<int64_t>(j) * ld + j] = d;
+  }
+  __syncthreads();
+  // G^{-1} = M^T M; thread owns column k, entries i >= k, mirrored to (k, i)
+  for (int k = threadIdx.x; k < sb; k += kT) {
+    for (int i = k; i < sb; ++i) {
+      double acc = 0.0;
+      for (int r = i; r < sb; ++r) acc = fma(M[static_cast<int64_t>(i) * ld + r], M[static_cast<int64_t>(k) * ld + r], acc);
+      Gi[static_cast<int64_t>(i) * s + k] = acc;
+      Gi[static_cast<int64_t>(k) * s + i] = acc;
+    }
   }
 }
 
@@ -476,10 +477,22 @@ void launch_check_finite(const double* A, int64_t lda, int64_t m, int64_t n, con
                      b, flag);
 }
 
-void launch_factor_aux(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
-                       const int32_t* slot_of, hipStream_t st) {
+void launch_factor_inverse(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
+                           const int32_t* slot_of, hipStream_t st) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL(k_factor_aux, dim3(nb), dim3(kT), 0, st, slots, stride, s, lens, slot_of);
+  if (s <= kLdsCholMax) {
+    const size_t lds = (static_cast<size_t>(s) * (s + 1) + s) * sizeof(double);
+    static bool attr_set = false;
+    if (!attr_set) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_factor_inverse<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                static_cast<int>((kLdsCholMax * (kLdsCholMax + 1) + kLdsCholMax) * sizeof(double)));
+      attr_set = true;
+    }
+    hipLaunchKernelGGL(k_factor_inverse<true>, dim3(nb), dim3(kT), lds, st, slots, stride, s, lens, slot_of);
+  } else {
+    hipLaunchKernelGGL(k_factor_inverse<false>, dim3(nb), dim3(kT), 0, st, slots, stride, s, lens, slot_of);
+  }
 }
 
 void launch_scatter_rows(const int32_t* stage_rows, const int32_t* stage_lens, const int32_t* slot_of,

@@ -34,9 +34,9 @@ void launch_block_gemv_partial(const double* A, int64_t lda, int64_t n, const in
                                int32_t sb, const double* x, double* rpart, int32_t P,
                                int64_t chunk, hipStream_t st);
 
-// r = sum_p rpart - b_S; E-sum and checkpoint bookkeeping; y = (L L^T)^{-1} r
+// r = sum_p rpart - b_S; E-sum and checkpoint bookkeeping; y = G^{-1} r
 void launch_block_project(const double* rpart, int32_t P, const double* b, const int32_t* rows,
-                          int32_t sb, const double* L, int32_t ldl, double* y, DevState* ds,
+                          int32_t sb, const double* Ginv, int32_t ldl, double* y, DevState* ds,
                           int32_t zeta, int32_t adaptive, hipStream_t st);
 
 // x, m update with w = A_S^T y (Kaczmarz++) or w = I_S^T y (CD++)
@@ -55,19 +55,17 @@ void launch_gram(int32_t kind, const double* A, int64_t lda, int64_t n, const in
 void launch_cholesky(double* G, int32_t s, int64_t stride, const int32_t* lens, int32_t nb,
                      const int32_t* slot_of, int32_t* err, hipStream_t st);
 
-// Row-major copy of each factor (at +s*s) and inverses of its 16 x 16 diagonal
-// blocks (at +2*s*s, ceil(s/16) row-major 16 x 16 blocks).
-void launch_factor_aux(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
-                       const int32_t* slot_of, hipStream_t st);
+// G^{-1} = L^{-T} L^{-1} of each slot's factor (at +s*s, full symmetric);
+// blocks larger than kLdsCholMax use the slot's last s*s doubles as scratch.
+void launch_factor_inverse(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
+                           const int32_t* slot_of, hipStream_t st);
 
 // rows[slot_of[k] * s + i] = stage_rows[k * s + i]; lens[slot_of[k]] = stage_lens[k]
 void launch_scatter_rows(const int32_t* stage_rows, const int32_t* stage_lens, const int32_t* slot_of,
                          int32_t nb, int32_t s, int32_t* rows, int32_t* lens, hipStream_t st);
 
-// Memo slot size (doubles): column-major L, row-major L, diagonal-block inverses.
-inline int64_t slot_doubles(int32_t s) {
-  return 2 * static_cast<int64_t>(s) * s + 256 * static_cast<int64_t>((s + 15) / 16);
-}
+// Memo slot size (doubles): column-major L, G^{-1}, scratch.
+inline int64_t slot_doubles(int32_t s) { return 3 * static_cast<int64_t>(s) * s; }
 
 // ||A x - b||^2 partial sums per row group (deterministic), then a final sum.
 void launch_residual_sq(const double* A, int64_t lda, int64_t m, int64_t n, const double* x,

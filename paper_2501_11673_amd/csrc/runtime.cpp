@@ -240,11 +240,18 @@ kpp_status residual_norm(kpp_system* sys, const double* x, double* out) {
   return KPP_OK;
 }
 
-// Fused-engine geometry: columns per lane (cpl) and workgroups per step.
-bool fused_geometry(int64_t n, int32_t target_groups, int32_t* cpl, int32_t* groups) {
+// Fused-engine geometry: columns per lane (cpl) and workgroups per step.  A
+// wave holds ceil(s/4) block rows of cpl columns in registers (at most 64
+// doubles per lane), so cpl <= 256/s; the smallest cpl that brings the team
+// down to the target size is taken.
+bool fused_geometry(int64_t n, int32_t s, int32_t target_groups, int32_t* cpl, int32_t* groups) {
+  if (s > kpp::kFusedMaxBlock) return false;
   const int32_t gmax = target_groups > 0 ? target_groups : 32;
+  const int32_t rows_per_wave = (s + 3) / 4;
+  int32_t cmax = 1;
+  while (cmax < 16 && 2 * cmax * rows_per_wave <= 64) cmax *= 2;
   int32_t c = 1;
-  while (c < 16 && (n + 64 * c - 1) / (64 * c) > gmax) c *= 2;
+  while (c < cmax && (n + 64 * c - 1) / (64 * c) > gmax) c *= 2;
   const int64_t g = (n + 64 * c - 1) / (64 * c);
   if (g > kpp::kFusedMaxGroups) return false;
   *cpl = c;
@@ -274,7 +281,7 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
   // engine
   int32_t cpl = 0, groups = 0;
   bool fused = false;
-  if (p->engine != 1 && s <= kpp::kFusedMaxBlock) fused = fused_geometry(n, p->team_groups, &cpl, &groups);
+  if (p->engine != 1) fused = fused_geometry(n, s, p->team_groups, &cpl, &groups);
   if (p->engine == 2 && !fused) return fail(KPP_ERR_INVALID_ARG, "n=%lld is too wide for the fused engine", (long long)n);
 
   // memo cache: reuse only for an identical schedule definition; the slot
@@ -376,7 +383,7 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
       kpp::launch_gram(kind, sys->A, sys->lda, n, d_srows, d_slens, s, nb, p->lambda, sys->L,
                        sys->slot_stride, d_sslot, st);
       kpp::launch_cholesky(sys->L, s, sys->slot_stride, d_slens, nb, d_sslot, sys->err, st);
-      kpp::launch_factor_aux(sys->L, sys->slot_stride, s, d_slens, nb, d_sslot, st);
+      kpp::launch_factor_inverse(sys->L, sys->slot_stride, s, d_slens, nb, d_sslot, st);
       HIP_TRY(hipGetLastError());
       HIP_TRY(hipEventRecord(sys->ev[3], st));
     }
@@ -418,7 +425,7 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
         const int32_t sb = sch->len(step_block[k]);
         const int32_t* rows = sys->rows + static_cast<size_t>(q) * s;
         kpp::launch_block_gemv_partial(sys->A, sys->lda, n, rows, sb, x, sys->rpart, P, chunk, st);
-        kpp::launch_block_project(sys->rpart, P, sys->b, rows, sb, sys->L + sd * q, s, sys->y, sys->ds,
+        kpp::launch_block_project(sys->rpart, P, sys->b, rows, sb, sys->L + sd * q + static_cast<size_t>(s) * s, s, sys->y, sys->ds,
                                   zeta, p->adaptive_rho, st);
         kpp::launch_update(kind, sys->A, sys->lda, n, rows, sb, sys->y, sys->ds, eta, x, sys->mom, st);
       }
