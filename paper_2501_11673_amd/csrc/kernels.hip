@@ -392,6 +392,169 @@ __global__ __launch_bounds__(kT) void k_factor_inverse(double* __restrict__ slot
   }
 }
 
+// --------------------------------------------------------------------------
+// memo miss for blocks of up to 128 rows, register resident: Cholesky
+// L L^T = G, then L^{-1} by Gauss-Jordan elimination on [L | I] (stored in
+// place), then G^{-1} = L^{-T} L^{-1}.  Thread (ty, tx) of a 16 x 16 grid
+// holds entries (ty + 16a, tx + 16b), a, b < 8, of the block in registers;
+// every phase is s rank-1 updates whose vectors travel through LDS, so each
+// step costs two barriers and 64 FMAs per thread, with no dependent chains.
+// Entries outside the lower triangle or the block are never read back.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(kT) void k_factor_small(double* __restrict__ slots, int64_t stride,
+                                                     int32_t s, const int32_t* __restrict__ lens,
+                                                     const int32_t* __restrict__ slot_of,
+                                                     int32_t want_inverse, int32_t* __restrict__ err) {
+  __shared__ double colbuf[128];
+  __shared__ double rowbuf[128];
+  __shared__ double piv;
+  const int blk = blockIdx.x;
+  const int sb = lens[blk];
+  double* Lc = slots + static_cast<int64_t>(slot_of[blk]) * stride;
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  double g[8][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int i = ty + 16 * a, k = tx + 16 * b;
+      g[a][b] = (i < sb && k < sb && i >= k) ? Lc[static_cast<int64_t>(k) * s + i] : 0.0;
+    }
+  int bad = 0;
+  // Cholesky, right-looking
+  for (int j = 0; j < sb; ++j) {
+    if (ty == (j & 15) && tx == (j & 15)) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+          if (a == b && ty + 16 * a == j) {
+            const double d = g[a][b];
+            if (!(d > 0.0)) bad = 1;
+            g[a][b] = sqrt(d);
+            piv = g[a][b];
+          }
+    }
+    __syncthreads();
+    const double rinv = 1.0 / piv;
+    if (tx == (j & 15)) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+          if (tx + 16 * b == j) {
+            const int i = ty + 16 * a;
+            if (i > j && i < sb) g[a][b] *= rinv;
+            colbuf[i] = (i > j && i < sb) ? g[a][b] : 0.0;
+          }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const double ci = colbuf[ty + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) g[a][b] = fma(-ci, colbuf[tx + 16 * b], g[a][b]);
+    }
+    __syncthreads();
+  }
+  // the trailing updates leave column j untouched below the diagonal only if
+  // colbuf[j] == 0, which holds (row j is not > j); write L back
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int i = ty + 16 * a, k = tx + 16 * b;
+      if (i < s && k < s) Lc[static_cast<int64_t>(k) * s + i] = (i < sb && k < sb && i >= k) ? g[a][b] : 0.0;
+    }
+  if (bad) atomicOr(err, 1);
+  if (!want_inverse) return;
+  // L^{-1} in place: at step j, row j is scaled by 1/L_jj and eliminated from
+  // the rows below (their left entries in column j are still L's)
+  for (int j = 0; j < sb; ++j) {
+    __syncthreads();
+    if (ty == (j & 15) && tx == (j & 15)) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+          if (a == b && ty + 16 * a == j) {
+            g[a][b] = 1.0 / g[a][b];
+            piv = g[a][b];
+          }
+    }
+    __syncthreads();
+    const double pinv = piv;
+    if (ty == (j & 15)) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        if (ty + 16 * a == j) {
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            const int k = tx + 16 * b;
+            if (k < j) g[a][b] *= pinv;
+            rowbuf[k] = (k < j) ? g[a][b] : (k == j ? pinv : 0.0);
+          }
+        }
+    }
+    if (tx == (j & 15)) {
+#pragma unroll
+      for (int b = 0; b < 8; ++b)
+        if (tx + 16 * b == j) {
+#pragma unroll
+          for (int a = 0; a < 8; ++a) {
+            const int i = ty + 16 * a;
+            colbuf[i] = (i > j && i < sb) ? g[a][b] : 0.0;
+          }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const double ci = colbuf[ty + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int k = tx + 16 * b;
+        g[a][b] = (k == j && ty + 16 * a > j) ? -ci * pinv : fma(-ci, rowbuf[k], g[a][b]);
+      }
+    }
+  }
+  // G^{-1} = X^T X with X = L^{-1}: rank-1 update per row r of X
+  double h[8][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) h[a][b] = 0.0;
+  for (int r = 0; r < sb; ++r) {
+    __syncthreads();
+    if (ty == (r & 15)) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        if (ty + 16 * a == r) {
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            const int k = tx + 16 * b;
+            rowbuf[k] = (k <= r) ? g[a][b] : 0.0;
+          }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const double xi = rowbuf[ty + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) h[a][b] = fma(xi, rowbuf[tx + 16 * b], h[a][b]);
+    }
+  }
+  double* Gi = Lc + static_cast<int64_t>(s) * s;
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int i = ty + 16 * a, k = tx + 16 * b;
+      if (i < sb && k < sb) Gi[static_cast<int64_t>(k) * s + i] = h[a][b];
+    }
+}
+
 // Block rows and lengths from a staging area into their slots.
 __global__ __launch_bounds__(kT) void k_scatter_rows(const int32_t* __restrict__ stage_rows,
                                                      const int32_t* __restrict__ stage_lens,
@@ -493,6 +656,13 @@ void launch_factor_inverse(double* slots, int64_t stride, int32_t s, const int32
   } else {
     hipLaunchKernelGGL(k_factor_inverse<false>, dim3(nb), dim3(kT), 0, st, slots, stride, s, lens, slot_of);
   }
+}
+
+void launch_factor_small(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
+                         const int32_t* slot_of, int32_t want_inverse, int32_t* err, hipStream_t st) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_factor_small, dim3(nb), dim3(kT), 0, st, slots, stride, s, lens, slot_of,
+                     want_inverse, err);
 }
 
 void launch_scatter_rows(const int32_t* stage_rows, const int32_t* stage_lens, const int32_t* slot_of,

@@ -60,6 +60,13 @@ void launch_cholesky(double* G, int32_t s, int64_t stride, const int32_t* lens, 
 void launch_factor_inverse(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
                            const int32_t* slot_of, hipStream_t st);
 
+// Blocks of at most kFactorSmallMax rows: Cholesky in place (breakdown sets
+// *err = 1) and, if want_inverse, G^{-1} at +s*s, one register-resident
+// workgroup per block.
+constexpr int kFactorSmallMax = 128;
+void launch_factor_small(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
+                         const int32_t* slot_of, int32_t want_inverse, int32_t* err, hipStream_t st);
+
 // rows[slot_of[k] * s + i] = stage_rows[k * s + i]; lens[slot_of[k]] = stage_lens[k]
 void launch_scatter_rows(const int32_t* stage_rows, const int32_t* stage_lens, const int32_t* slot_of,
                          int32_t nb, int32_t s, int32_t* rows, int32_t* lens, hipStream_t st);

@@ -382,8 +382,12 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
       kpp::launch_scatter_rows(d_srows, d_slens, d_sslot, nb, s, sys->rows, sys->lens, st);
       kpp::launch_gram(kind, sys->A, sys->lda, n, d_srows, d_slens, s, nb, p->lambda, sys->L,
                        sys->slot_stride, d_sslot, st);
-      kpp::launch_cholesky(sys->L, s, sys->slot_stride, d_slens, nb, d_sslot, sys->err, st);
-      kpp::launch_factor_inverse(sys->L, sys->slot_stride, s, d_slens, nb, d_sslot, st);
+      if (s <= kpp::kFactorSmallMax) {
+        kpp::launch_factor_small(sys->L, sys->slot_stride, s, d_slens, nb, d_sslot, 1, sys->err, st);
+      } else {
+        kpp::launch_cholesky(sys->L, s, sys->slot_stride, d_slens, nb, d_sslot, sys->err, st);
+        kpp::launch_factor_inverse(sys->L, sys->slot_stride, s, d_slens, nb, d_sslot, st);
+      }
       HIP_TRY(hipGetLastError());
       HIP_TRY(hipEventRecord(sys->ev[3], st));
     }
@@ -695,7 +699,10 @@ KPP_API kpp_status kpp_block_factor(kpp_system* sys, int32_t s, double lambda, i
   kpp::launch_gram(sys->kind, sys->A, sys->lda, sys->n, d_rows, d_lens, s, nb, lambda, L_dev,
                    static_cast<int64_t>(s) * s, d_ids, st);
   HIP_TRY(hipGetLastError());
-  kpp::launch_cholesky(L_dev, s, static_cast<int64_t>(s) * s, d_lens, nb, d_ids, sys->err, st);
+  if (s <= kpp::kFactorSmallMax)
+    kpp::launch_factor_small(L_dev, static_cast<int64_t>(s) * s, s, d_lens, nb, d_ids, 0, sys->err, st);
+  else
+    kpp::launch_cholesky(L_dev, s, static_cast<int64_t>(s) * s, d_lens, nb, d_ids, sys->err, st);
   HIP_TRY(hipGetLastError());
   int32_t herr = 0;
   HIP_TRY(hipMemcpyAsync(&herr, sys->err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
