@@ -102,6 +102,14 @@ class KppError(RuntimeError):
 
 
 def _load():
+    # Device pointers and streams handed to the library come from torch, whose
+    # wheel ships its own HIP runtime.  Loading torch first makes the
+    # library's libamdhip64 dependency resolve to that same runtime instance
+    # (two runtimes in one process do not share devices or streams).
+    try:
+        import torch  # noqa: F401
+    except ImportError:  # pragma: no cover - the library also runs without torch
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build the HIP library first "

@@ -11,9 +11,11 @@
 //   2. publish p_g; wait until every workgroup has published (one
 //      all-gather through per-workgroup flags: the step's only cross-CU
 //      sync); r = sum_g p_g - b_S, summed in the same order in every
-//      workgroup.  CD++ issues the loads of the next step's tile before it
-//      waits, so HBM latency hides behind the sync (the block sequence never
-//      depends on x);
+//      workgroup.  CD++ loads the next step's tile, rows and b values while
+//      it waits (the block sequence never depends on x): waves 1-3 issue
+//      their loads before the wait, wave 0 polls the flags (a wave's loads
+//      complete in order, so a polling wave must not have loads in flight)
+//      and issues its share right after;
 //   3. y = (A_S A_S^T + lam I)^{-1} r through the memoized inverse
 //      G^{-1} = L^{-T} L^{-1} of the block's Cholesky factor: CD++ needs only
 //      the rows of y whose coordinates fall into J_g (w = I_S^T y), Kaczmarz++
@@ -32,9 +34,20 @@
 namespace kpp {
 namespace {
 
+#ifndef KPP_FLAG_STRIDE
+#define KPP_FLAG_STRIDE 32
+#endif
+#ifndef KPP_POLL_SLEEP
+#define KPP_POLL_SLEEP 0
+#endif
+#ifndef KPP_PREFETCH
+#define KPP_PREFETCH 1
+#endif
+
 constexpr int kT = 256;
-constexpr int kFlagStride = 32;  // uint32 words between flags (128 bytes)
-constexpr int kTileMax = 64;     // tile doubles per lane
+constexpr int kFlagStride = KPP_FLAG_STRIDE;  // uint32 words between flags
+constexpr int kTileMax = 64;                  // tile doubles per lane
+static_assert(kFlagStride * kFusedMaxGroups <= kFlagWordsAlloc, "flag area too small");
 
 __device__ __forceinline__ double ld_coherent(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -62,38 +75,50 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Load this wave's rows of the block tile: tile[r * CPL + e] = A[rows[wv + 4r], col0 + e].
+// One vector load fetches the wave's row indices (lane r holds row wv + 4r),
+// read back lane by lane, so every tile load issues at once.  Row indices past
+// the block and columns past the matrix are clamped, not masked: those entries
+// always meet a zero (x is zero beyond n, y is zero beyond the block), and A
+// is finite (checked when the system is created), so they contribute nothing.
 template <int CPL>
 __device__ __forceinline__ void load_tile(double (&tile)[kTileMax], const double* __restrict__ A,
                                           int64_t lda, int64_t n, const int32_t* __restrict__ rows,
-                                          int sb, int wv, int64_t col0) {
+                                          int sb, int wv, int lane, int64_t col0) {
   constexpr int RMAX = kTileMax / CPL;
+  const int myrow = rows[min(wv + 4 * (lane & (RMAX - 1)), sb - 1)];
 #pragma unroll
   for (int r = 0; r < RMAX; ++r) {
-    const int i = wv + 4 * r;
-    if (i < sb) {
-      const double* Ai = A + static_cast<int64_t>(rows[i]) * lda;
+    const int row = __builtin_amdgcn_readlane(myrow, r);
+    const double* Ai = A + static_cast<int64_t>(row) * lda;
 #pragma unroll
-      for (int e = 0; e < CPL; ++e) tile[r * CPL + e] = (col0 + e < n) ? Ai[col0 + e] : 0.0;
-    } else {
-#pragma unroll
-      for (int e = 0; e < CPL; ++e) tile[r * CPL + e] = 0.0;
-    }
+    for (int e = 0; e < CPL; ++e) tile[r * CPL + e] = Ai[min(col0 + e, n - 1)];
   }
 }
 
 template <int KIND, int CPL>
 __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
+  // optional phase profile (workgroup 0, thread 0): ticks[p] accumulates the
+  // wall-clock time from mark p-1 to mark p
+  uint64_t tick_last = 0, ticks[kFusedPhases];
+  const bool prof = a.phase_ticks != nullptr && blockIdx.x == 0 && threadIdx.x == 0;
+#pragma unroll
+  for (int p = 0; p < kFusedPhases; ++p) ticks[p] = 0;
+#define KPP_MARK(p)                                   \
+  if (prof) {                                         \
+    const uint64_t now_ = wall_clock64();             \
+    ticks[p] += now_ - tick_last;                     \
+    tick_last = now_;                                 \
+  }
   constexpr int RMAX = kTileMax / CPL;   // rows per wave held in registers (power of two)
   constexpr int RSHIFT = (RMAX == 64) ? 0 : (RMAX == 32) ? 1 : (RMAX == 16) ? 2 : (RMAX == 8) ? 3 : 4;
-  __shared__ int32_t rs[256];
+  __shared__ int32_t rsbuf[2][256];
   __shared__ double rv[256];
   __shared__ double yv[256];
   __shared__ double stage[256];
   __shared__ double wred[KIND == 0 ? 4 * 64 * CPL : 1];
-  __shared__ double red[4];
+  __shared__ double red[1];
   __shared__ double bc_c;
   __shared__ int abort_flag;
-  __shared__ int slice_lo, slice_hi;
 
   const int G = gridDim.x;
   const int wg = blockIdx.x;
@@ -121,18 +146,28 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
   double tile[kTileMax];
   int q = a.step_slot[0];
   int sb = a.lens[q];
-  load_tile<CPL>(tile, a.A, a.lda, n, a.rows + static_cast<int64_t>(q) * s, sb, wv, col0);
+  int cur = 0;
+  load_tile<CPL>(tile, a.A, a.lda, n, a.rows + static_cast<int64_t>(q) * s, sb, wv, lane, col0);
+  // wave 0 forms r: its lane holds b at block rows lane + 64 u of the current step
+  double bval[4] = {0.0, 0.0, 0.0, 0.0};
+  if (tid < sb) rsbuf[0][tid] = a.rows[static_cast<int64_t>(q) * s + tid];
+  if (wv == 0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = lane + 64 * u;
+      if (i < sb) bval[u] = a.b[a.rows[static_cast<int64_t>(q) * s + i]];
+    }
+  }
   __syncthreads();
 
+  if (prof) tick_last = wall_clock64();
   for (int k = 0; k < a.W; ++k) {
-    if (KIND == 0 && k > 0) {
-      q = a.step_slot[k];
-      sb = a.lens[q];
-      load_tile<CPL>(tile, a.A, a.lda, n, a.rows + static_cast<int64_t>(q) * s, sb, wv, col0);
+    const int32_t* rs = rsbuf[cur];
+    if ((KIND == 0 || !KPP_PREFETCH) && k > 0) {
+      load_tile<CPL>(tile, a.A, a.lda, n, a.rows + static_cast<int64_t>(q) * s, sb, wv, lane, col0);
     }
-    const int32_t* R = a.rows + static_cast<int64_t>(q) * s;
     const double* Ginv = a.L + static_cast<int64_t>(q) * a.slot_stride + static_cast<int64_t>(s) * s;
-    if (tid < sb) rs[tid] = R[tid];
+    KPP_MARK(0)
 
     // 1. partial residuals of this wave's rows, butterfly across the lanes
     double v[RMAX];
@@ -160,38 +195,54 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
       if ((lane & ((1 << RSHIFT) - 1)) == 0 && row < sb) stage[row] = v[0];
     }
     __syncthreads();
+    KPP_MARK(1)
 
-    // 2. publish, prefetch the next tile (CD++), all-gather, reduce in a fixed order
+    // 2. publish; prefetch (CD++); all-gather; reduce in a fixed order
     const uint32_t ep = a.epoch + static_cast<uint32_t>(k) + 1u;
     double* Pb = a.part + static_cast<size_t>(ep & 1u) * G * s;
     if (wv == 0) {
       for (int i = lane; i < sb; i += 64) st_coherent(&Pb[static_cast<size_t>(wg) * s + i], stage[i]);
       if (lane == 0) st_flag_release(&a.flags[wg * kFlagStride], ep);
     }
-    int qn = q, sbn = sb;
-    if (KIND == 1 && k + 1 < a.W) {
-      qn = a.step_slot[k + 1];
-      sbn = a.lens[qn];
-      load_tile<CPL>(tile, a.A, a.lda, n, a.rows + static_cast<int64_t>(qn) * s, sbn, wv, col0);
+    KPP_MARK(2)
+    // block rows whose coordinates fall into this slice (rows are sorted)
+    int lo = 0, hi = sb;
+    if (KIND == 1) {
+      int l = 0, h = sb;
+      while (l < h) {
+        const int mid = (l + h) >> 1;
+        if (rs[mid] < slice0) l = mid + 1; else h = mid;
+      }
+      lo = l;
+      h = sb;
+      while (l < h) {
+        const int mid = (l + h) >> 1;
+        if (rs[mid] < slice1) l = mid + 1; else h = mid;
+      }
+      hi = l;
     }
-    if (tid == 0) {
-      // block rows whose coordinates fall into this slice (rows are sorted)
-      int lo = 0, hi = sb;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (rs[mid] < slice0) lo = mid + 1; else hi = mid;
+    const bool have_next = k + 1 < a.W;
+    const int qn = have_next ? a.step_slot[k + 1] : q;
+    const int sbn = a.lens[qn];
+    const int32_t* Rn = a.rows + static_cast<int64_t>(qn) * s;
+    // CD++: the memoized inverse's rows for this slice; slice row lo + t
+    // belongs to wave 1 + t % 3 (wave 0 polls), lanes hold entries k = lane + 64 u
+    double grow[4] = {0.0, 0.0, 0.0, 0.0};
+    const int my_first = (KIND == 1 && wv > 0) ? lo + (wv - 1) : hi;
+    if (KIND == 1 && wv > 0) {
+      if (my_first < hi) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int kk = lane + 64 * u;
+          grow[u] = Ginv[static_cast<int64_t>(my_first) * s + min(kk, sb - 1)];
+        }
       }
-      int lo2 = lo, hi2 = sb;
-      while (lo2 < hi2) {
-        const int mid = (lo2 + hi2) >> 1;
-        if (rs[mid] < slice1) lo2 = mid + 1; else hi2 = mid;
-      }
-      slice_lo = lo;
-      slice_hi = lo2;
+      if (KPP_PREFETCH && have_next) load_tile<CPL>(tile, a.A, a.lda, n, Rn, sbn, wv, lane, col0);
     }
     if (tid < G) {
       int64_t spins = 0;
       while (static_cast<int32_t>(ld_flag(&a.flags[tid * kFlagStride]) - ep) < 0) {
+        if (KPP_POLL_SLEEP > 0) __builtin_amdgcn_s_sleep(KPP_POLL_SLEEP);
         if (++spins > a.spin_limit) {
           atomicOr(a.err, 2);
           abort_flag = 1;
@@ -200,39 +251,79 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
       }
     }
     __syncthreads();
+    KPP_MARK(3)
     if (abort_flag) break;
-    double ri = 0.0;
-    if (tid < sb) {
-      double acc = 0.0;
-      int g = 0;
-      for (; g + 8 <= G; g += 8) {
-        double t8[8];
+    // r = sum_g p_g - b_S by wave 0 (it has no loads in flight), the
+    // next step's rows and b values right after (used after this step)
+    double bnext[4] = {0.0, 0.0, 0.0, 0.0};
+    if (wv == 0) {
+      double rr_lane = 0.0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) t8[u] = ld_coherent(&Pb[static_cast<size_t>(g + u) * s + tid]);
+      for (int u = 0; u < 4; ++u) {
+        const int i = lane + 64 * u;
+        if (i < sb) {
+          double acc = 0.0;
+          int g = 0;
+          for (; g + 32 <= G; g += 32) {
+            double t32[32];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc += t8[u];
+            for (int uu = 0; uu < 32; ++uu) t32[uu] = ld_coherent(&Pb[static_cast<size_t>(g + uu) * s + i]);
+#pragma unroll
+            for (int uu = 0; uu < 32; ++uu) acc += t32[uu];
+          }
+          for (; g + 8 <= G; g += 8) {
+            double t8[8];
+#pragma unroll
+            for (int uu = 0; uu < 8; ++uu) t8[uu] = ld_coherent(&Pb[static_cast<size_t>(g + uu) * s + i]);
+#pragma unroll
+            for (int uu = 0; uu < 8; ++uu) acc += t8[uu];
+          }
+          for (; g < G; ++g) acc += ld_coherent(&Pb[static_cast<size_t>(g) * s + i]);
+          const double ri = acc - bval[u];
+          rv[i] = ri;
+          rr_lane = fma(ri, ri, rr_lane);
+        }
       }
-      for (; g < G; ++g) acc += ld_coherent(&Pb[static_cast<size_t>(g) * s + tid]);
-      ri = acc - a.b[rs[tid]];
-      rv[tid] = ri;
-    }
-    {
-      double part = fma(ri, ri, 0.0);
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
-      if (lane == 0) red[wv] = part;
+      for (int off = 32; off > 0; off >>= 1) rr_lane += __shfl_down(rr_lane, off, 64);
+      if (lane == 0) red[0] = rr_lane;
+      // next step's rows and b (a dependent pair: issued before the tile loads
+      // so that waiting for the row indices does not wait for the tile)
+      if (have_next) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = lane + 64 * u;
+          if (i < sbn) {
+            const int32_t row = Rn[i];
+            rsbuf[cur ^ 1][i] = row;
+            bnext[u] = a.b[row];
+          }
+        }
+      }
+      // wave 0's share of the next tile, after its partial loads have landed
+      if (KIND == 1 && KPP_PREFETCH && have_next) load_tile<CPL>(tile, a.A, a.lda, n, Rn, sbn, wv, lane, col0);
     }
     __syncthreads();
+    KPP_MARK(4)
 
     // 3. y through the memoized inverse
     if (KIND == 1) {
-      const int lo = slice_lo, hi = slice_hi;
-      for (int i = lo + wv; i < hi; i += 4) {
-        const double* Gi = Ginv + static_cast<int64_t>(i) * s;
-        double acc = 0.0;
-        for (int kk = lane; kk < sb; kk += 64) acc = fma(Gi[kk], rv[kk], acc);
-        acc = wave_sum(acc);
-        if (lane == 0) yv[i] = acc;
+      if (wv > 0) {
+        for (int i = my_first; i < hi; i += 3) {
+          double acc = 0.0;
+          if (i == my_first) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int kk = lane + 64 * u;
+              if (kk < sb) acc = fma(grow[u], rv[kk], acc);
+            }
+          } else {
+            const double* Gi = Ginv + static_cast<int64_t>(i) * s;
+            for (int kk = lane; kk < sb; kk += 64) acc = fma(Gi[kk], rv[kk], acc);
+          }
+          acc = wave_sum(acc);
+          if (lane == 0) yv[i] = acc;
+        }
       }
     } else if (tid < sb) {
       double acc = 0.0;
@@ -250,7 +341,7 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
 
     // 5. scalars: c for this step, window sums, checkpoint
     if (tid == 0) {
-      const double rr = (red[0] + red[1]) + (red[2] + red[3]);
+      const double rr = red[0];
       const double rho = st.rho;
       st.c = (1.0 - rho) / (1.0 + rho);
       bc_c = st.c;
@@ -285,6 +376,7 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
       st.t += 1;
     }
     __syncthreads();
+    KPP_MARK(5)
     const double c = bc_c;
 
     // 4. direction on the slice and the momentum update
@@ -308,7 +400,6 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
         w[e] = ((wred[o] + wred[64 * CPL + o]) + wred[128 * CPL + o]) + wred[192 * CPL + o];
       }
     } else {
-      const int lo = slice_lo, hi = slice_hi;
 #pragma unroll
       for (int e = 0; e < CPL; ++e) {
         const int64_t j = col0 + e;
@@ -320,6 +411,9 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
         if (l < hi && rs[l] == j) w[e] = yv[l];
       }
     }
+    // columns past n keep x = m = 0 (the clamped tile entries there are not A's)
+#pragma unroll
+    for (int e = 0; e < CPL; ++e) w[e] = (col0 + e < n) ? w[e] : 0.0;
 #pragma unroll
     for (int e = 0; e < CPL; ++e) {
       const double mn = __dmul_rn(c, __dsub_rn(mr[e], w[e]));
@@ -328,7 +422,17 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
     }
     q = qn;
     sb = sbn;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) bval[u] = bnext[u];
+    cur ^= 1;
     __syncthreads();
+    KPP_MARK(6)
+  }
+#undef KPP_MARK
+  if (prof) {
+#pragma unroll
+    for (int p = 0; p < kFusedPhases; ++p) atomicAdd(reinterpret_cast<unsigned long long*>(&a.phase_ticks[p]),
+                                                    static_cast<unsigned long long>(ticks[p]));
   }
 
   if (wv == 0) {

@@ -397,8 +397,9 @@ __global__ __launch_bounds__(kT) void k_factor_inverse(double* __restrict__ slot
 // L L^T = G, then L^{-1} by Gauss-Jordan elimination on [L | I] (stored in
 // place), then G^{-1} = L^{-T} L^{-1}.  Thread (ty, tx) of a 16 x 16 grid
 // holds entries (ty + 16a, tx + 16b), a, b < 8, of the block in registers;
-// every phase is s rank-1 updates whose vectors travel through LDS, so each
-// step costs two barriers and 64 FMAs per thread, with no dependent chains.
+// every phase is s rank-1 updates whose vectors travel through LDS.  The
+// elimination index j = 16 jb + jj is split so that the register column jb
+// is a compile-time index and a step has a single predicated branch.
 // Entries outside the lower triangle or the block are never read back.
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(kT) void k_factor_small(double* __restrict__ slots, int64_t stride,
@@ -418,47 +419,45 @@ __global__ __launch_bounds__(kT) void k_factor_small(double* __restrict__ slots,
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
       const int i = ty + 16 * a, k = tx + 16 * b;
-      g[a][b] = (i < sb && k < sb && i >= k) ? Lc[static_cast<int64_t>(k) * s + i] : 0.0;
+      const int ic = min(i, sb - 1), kc = min(k, sb - 1);
+      const double v = Lc[static_cast<int64_t>(kc) * s + ic];
+      g[a][b] = (i < sb && k < sb && i >= k) ? v : 0.0;
     }
   int bad = 0;
   // Cholesky, right-looking
-  for (int j = 0; j < sb; ++j) {
-    if (ty == (j & 15) && tx == (j & 15)) {
 #pragma unroll
-      for (int a = 0; a < 8; ++a)
+  for (int jb = 0; jb < 8; ++jb) {
+    for (int jj = 0; jj < 16; ++jj) {
+      const int j = 16 * jb + jj;
+      if (j >= sb) break;
+      if (ty == jj && tx == jj) {
+        const double d = g[jb][jb];
+        bad |= !(d > 0.0);
+        g[jb][jb] = sqrt(d);
+        piv = g[jb][jb];
+      }
+      __syncthreads();
+      const double rinv = 1.0 / piv;
+      if (tx == jj) {
 #pragma unroll
-        for (int b = 0; b < 8; ++b)
-          if (a == b && ty + 16 * a == j) {
-            const double d = g[a][b];
-            if (!(d > 0.0)) bad = 1;
-            g[a][b] = sqrt(d);
-            piv = g[a][b];
-          }
+        for (int a = 0; a < 8; ++a) {
+          const int i = ty + 16 * a;
+          const bool below = i > j && i < sb;
+          const double v = g[a][jb] * rinv;
+          g[a][jb] = below ? v : g[a][jb];
+          colbuf[i] = below ? v : 0.0;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const double ci = colbuf[ty + 16 * a];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) g[a][b] = fma(-ci, colbuf[tx + 16 * b], g[a][b]);
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    const double rinv = 1.0 / piv;
-    if (tx == (j & 15)) {
-#pragma unroll
-      for (int a = 0; a < 8; ++a)
-#pragma unroll
-        for (int b = 0; b < 8; ++b)
-          if (tx + 16 * b == j) {
-            const int i = ty + 16 * a;
-            if (i > j && i < sb) g[a][b] *= rinv;
-            colbuf[i] = (i > j && i < sb) ? g[a][b] : 0.0;
-          }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const double ci = colbuf[ty + 16 * a];
-#pragma unroll
-      for (int b = 0; b < 8; ++b) g[a][b] = fma(-ci, colbuf[tx + 16 * b], g[a][b]);
-    }
-    __syncthreads();
   }
-  // the trailing updates leave column j untouched below the diagonal only if
-  // colbuf[j] == 0, which holds (row j is not > j); write L back
 #pragma unroll
   for (int a = 0; a < 8; ++a)
 #pragma unroll
@@ -470,52 +469,48 @@ __global__ __launch_bounds__(kT) void k_factor_small(double* __restrict__ slots,
   if (!want_inverse) return;
   // L^{-1} in place: at step j, row j is scaled by 1/L_jj and eliminated from
   // the rows below (their left entries in column j are still L's)
-  for (int j = 0; j < sb; ++j) {
-    __syncthreads();
-    if (ty == (j & 15) && tx == (j & 15)) {
 #pragma unroll
-      for (int a = 0; a < 8; ++a)
-#pragma unroll
-        for (int b = 0; b < 8; ++b)
-          if (a == b && ty + 16 * a == j) {
-            g[a][b] = 1.0 / g[a][b];
-            piv = g[a][b];
-          }
-    }
-    __syncthreads();
-    const double pinv = piv;
-    if (ty == (j & 15)) {
-#pragma unroll
-      for (int a = 0; a < 8; ++a)
-        if (ty + 16 * a == j) {
-#pragma unroll
-          for (int b = 0; b < 8; ++b) {
-            const int k = tx + 16 * b;
-            if (k < j) g[a][b] *= pinv;
-            rowbuf[k] = (k < j) ? g[a][b] : (k == j ? pinv : 0.0);
-          }
-        }
-    }
-    if (tx == (j & 15)) {
-#pragma unroll
-      for (int b = 0; b < 8; ++b)
-        if (tx + 16 * b == j) {
-#pragma unroll
-          for (int a = 0; a < 8; ++a) {
-            const int i = ty + 16 * a;
-            colbuf[i] = (i > j && i < sb) ? g[a][b] : 0.0;
-          }
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const double ci = colbuf[ty + 16 * a];
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const int k = tx + 16 * b;
-        g[a][b] = (k == j && ty + 16 * a > j) ? -ci * pinv : fma(-ci, rowbuf[k], g[a][b]);
+  for (int jb = 0; jb < 8; ++jb) {
+    for (int jj = 0; jj < 16; ++jj) {
+      const int j = 16 * jb + jj;
+      if (j >= sb) break;
+      if (ty == jj && tx == jj) {
+        g[jb][jb] = 1.0 / g[jb][jb];
+        piv = g[jb][jb];
       }
+      __syncthreads();
+      const double pinv = piv;
+      if (ty == jj) {
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const int k = tx + 16 * b;
+          const double v = g[jb][b] * pinv;
+          g[jb][b] = (k < j) ? v : g[jb][b];
+          rowbuf[k] = (k < j) ? v : (k == j ? pinv : 0.0);
+        }
+      }
+      if (tx == jj) {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          const int i = ty + 16 * a;
+          colbuf[i] = (i > j && i < sb) ? g[a][jb] : 0.0;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const double ci = colbuf[ty + 16 * a];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) g[a][b] = fma(-ci, rowbuf[tx + 16 * b], g[a][b]);
+      }
+      if (tx == jj) {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          const int i = ty + 16 * a;
+          g[a][jb] = (i > j && i < sb) ? -colbuf[i] * pinv : g[a][jb];
+        }
+      }
+      __syncthreads();
     }
   }
   // G^{-1} = X^T X with X = L^{-1}: rank-1 update per row r of X
@@ -524,25 +519,26 @@ __global__ __launch_bounds__(kT) void k_factor_small(double* __restrict__ slots,
   for (int a = 0; a < 8; ++a)
 #pragma unroll
     for (int b = 0; b < 8; ++b) h[a][b] = 0.0;
-  for (int r = 0; r < sb; ++r) {
-    __syncthreads();
-    if (ty == (r & 15)) {
 #pragma unroll
-      for (int a = 0; a < 8; ++a)
-        if (ty + 16 * a == r) {
+  for (int rb = 0; rb < 8; ++rb) {
+    for (int rr = 0; rr < 16; ++rr) {
+      const int r = 16 * rb + rr;
+      if (r >= sb) break;
+      if (ty == rr) {
 #pragma unroll
-          for (int b = 0; b < 8; ++b) {
-            const int k = tx + 16 * b;
-            rowbuf[k] = (k <= r) ? g[a][b] : 0.0;
-          }
+        for (int b = 0; b < 8; ++b) {
+          const int k = tx + 16 * b;
+          rowbuf[k] = (k <= r) ? g[rb][b] : 0.0;
         }
-    }
-    __syncthreads();
+      }
+      __syncthreads();
 #pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const double xi = rowbuf[ty + 16 * a];
+      for (int a = 0; a < 8; ++a) {
+        const double xi = rowbuf[ty + 16 * a];
 #pragma unroll
-      for (int b = 0; b < 8; ++b) h[a][b] = fma(xi, rowbuf[tx + 16 * b], h[a][b]);
+        for (int b = 0; b < 8; ++b) h[a][b] = fma(xi, rowbuf[tx + 16 * b], h[a][b]);
+      }
+      __syncthreads();
     }
   }
   double* Gi = Lc + static_cast<int64_t>(s) * s;

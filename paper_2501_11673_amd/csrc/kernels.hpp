@@ -110,10 +110,14 @@ struct FusedArgs {
   DevState* ds;
   int32_t* err;              // bit 1: a wait exceeded spin_limit
   int64_t spin_limit;
+  uint64_t* phase_ticks;     // optional (nullptr): wall-clock ticks per step phase, workgroup 0
 };
+
+constexpr int kFusedPhases = 8;
 
 constexpr int kFusedMaxBlock = 256;   // the fused engine gives one thread per block row
 constexpr int kFusedMaxGroups = 256;
+constexpr int kFlagWordsAlloc = 1024 * kFusedMaxGroups;   // up to 4 KB between flags
 
 void launch_fused(int32_t kind, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t st);
 

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -65,7 +66,8 @@ void dev_free(T*& p) {
 
 struct kpp_context {
   int32_t device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;   // borrowed: all results are ordered on it
+  hipStream_t side = nullptr;     // owned: memo-miss factorizations one window ahead
   int32_t cu_count = 0;
 };
 
@@ -101,9 +103,10 @@ struct kpp_system {
   double sig_lambda = 0.0;
   // per-window staging (pinned host mirror + device copy): block rows, lengths,
   // slot ids of the blocks to factor, and the slot of every step
-  int32_t* h_stage = nullptr;
-  int32_t* d_stage = nullptr;
-  size_t stage_cap = 0;
+  int32_t* h_stage[2] = {nullptr, nullptr};
+  int32_t* d_stage[2] = {nullptr, nullptr};
+  size_t stage_cap[2] = {0, 0};
+  hipEvent_t ev_fact[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};  // start, end, ready
   kpp::DevState* h_ds = nullptr;
   int32_t* h_err = nullptr;
   // fused engine
@@ -111,11 +114,12 @@ struct kpp_system {
   uint32_t* flags = nullptr;
   uint32_t epoch = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  uint64_t* phase_ticks = nullptr;   // KPP_PHASE_PROFILE=1: fused-engine phase profile
 };
 
 namespace {
 
-constexpr int kFlagWords = 32 * kpp::kFusedMaxGroups;
+constexpr int kFlagWords = kpp::kFlagWordsAlloc;
 
 void destroy_buffers(kpp_system* s) {
   dev_free(s->mom);
@@ -128,13 +132,22 @@ void destroy_buffers(kpp_system* s) {
   dev_free(s->L);
   dev_free(s->rows);
   dev_free(s->lens);
-  dev_free(s->d_stage);
+  for (int i = 0; i < 2; ++i) {
+    dev_free(s->d_stage[i]);
+    if (s->h_stage[i]) (void)hipHostFree(s->h_stage[i]);
+    s->h_stage[i] = nullptr;
+    s->stage_cap[i] = 0;
+    for (auto& e : s->ev_fact[i])
+      if (e) {
+        (void)hipEventDestroy(e);
+        e = nullptr;
+      }
+  }
   dev_free(s->part);
   dev_free(s->flags);
-  if (s->h_stage) (void)hipHostFree(s->h_stage);
+  dev_free(s->phase_ticks);
   if (s->h_ds) (void)hipHostFree(s->h_ds);
   if (s->h_err) (void)hipHostFree(s->h_err);
-  s->h_stage = nullptr;
   s->h_ds = nullptr;
   s->h_err = nullptr;
   for (auto& e : s->ev)
@@ -143,7 +156,6 @@ void destroy_buffers(kpp_system* s) {
       e = nullptr;
     }
   s->cap_slots = 0;
-  s->stage_cap = 0;
 }
 
 // Grow the slot table to hold `need` slots for block size s (keeps contents).
@@ -162,6 +174,9 @@ kpp_status ensure_slots(kpp_system* sys, int32_t need, int32_t s) {
     sys->memo_valid = false;
   }
   if (need <= sys->cap_slots) return KPP_OK;
+  // kernels in flight on either stream may read the old table
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipStreamSynchronize(sys->ctx->side));
   const int32_t cap = std::max<int32_t>(need, std::max<int32_t>(16, sys->cap_slots * 2));
   double* L = nullptr;
   int32_t *rows = nullptr, *lens = nullptr;
@@ -186,17 +201,18 @@ kpp_status ensure_slots(kpp_system* sys, int32_t need, int32_t s) {
   return KPP_OK;
 }
 
-kpp_status ensure_stage(kpp_system* sys, size_t ints) {
-  if (ints <= sys->stage_cap) return KPP_OK;
-  const size_t cap = std::max<size_t>(ints, std::max<size_t>(4096, sys->stage_cap * 2));
+kpp_status ensure_stage(kpp_system* sys, int idx, size_t ints) {
+  if (ints <= sys->stage_cap[idx]) return KPP_OK;
+  const size_t cap = std::max<size_t>(ints, std::max<size_t>(4096, sys->stage_cap[idx] * 2));
   HIP_TRY(hipStreamSynchronize(sys->ctx->stream));
-  dev_free(sys->d_stage);
-  if (sys->h_stage) (void)hipHostFree(sys->h_stage);
-  sys->h_stage = nullptr;
-  sys->stage_cap = 0;
-  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&sys->h_stage), cap * sizeof(int32_t), hipHostMallocDefault));
-  KPP_TRY(dev_alloc(&sys->d_stage, cap));
-  sys->stage_cap = cap;
+  HIP_TRY(hipStreamSynchronize(sys->ctx->side));
+  dev_free(sys->d_stage[idx]);
+  if (sys->h_stage[idx]) (void)hipHostFree(sys->h_stage[idx]);
+  sys->h_stage[idx] = nullptr;
+  sys->stage_cap[idx] = 0;
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&sys->h_stage[idx]), cap * sizeof(int32_t), hipHostMallocDefault));
+  KPP_TRY(dev_alloc(&sys->d_stage[idx], cap));
+  sys->stage_cap[idx] = cap;
   return KPP_OK;
 }
 
@@ -316,30 +332,49 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
   kpp::launch_state_init(sys->ds, p->rho0, thr, st);
   HIP_TRY(hipGetLastError());
 
+  const char* prof_env = std::getenv("KPP_PHASE_PROFILE");
+  const bool phase_prof = fused && prof_env && prof_env[0] == '1';
+  if (phase_prof) {
+    if (!sys->phase_ticks) KPP_TRY(dev_alloc(&sys->phase_ticks, kpp::kFusedPhases));
+    HIP_TRY(hipMemsetAsync(sys->phase_ticks, 0, kpp::kFusedPhases * sizeof(uint64_t), st));
+  }
   int64_t hits = 0, misses = 0, t = 0;
   bool converged = false;
   double true_rel = NAN;
   double t_factor = 0.0, t_kernel = 0.0;
   int64_t launches = 0;
   kpp::DevState hs{};
-  std::vector<int32_t> step_block, step_slot, pending, pending_slots;
   const int64_t period = 2 * static_cast<int64_t>(zeta);
   const size_t sd = static_cast<size_t>(sys->slot_stride);
-  while (t < p->max_iters && !converged) {
-    const int64_t W = std::min<int64_t>(period - (t % period), p->max_iters - t);
-    step_block.resize(W);
-    step_slot.resize(W);
-    pending.clear();
-    pending_slots.clear();
-    if (mode == kpp::MemoMode::Off) KPP_TRY(ensure_slots(sys, static_cast<int32_t>(W), s));
-    for (int64_t k = 0; k < W; ++k) {
+
+  // A window is the run of steps up to the next checkpoint.  Planning a window
+  // draws its blocks, assigns memo slots and stages (pinned) the rows of its
+  // new blocks plus the slot of every step; its memo misses are then factored
+  // on the side stream while the previous window runs on the main stream.
+  struct Window {
+    int64_t t0 = 0, W = 0;
+    int32_t nb = 0, idx = 0;
+    size_t o_len = 0, o_slot = 0, o_step = 0;
+    std::vector<int32_t> step_block, step_slot;
+  };
+  auto plan = [&](Window& w, int64_t t0, int idx) -> kpp_status {
+    w.t0 = t0;
+    w.idx = idx;
+    w.W = std::min<int64_t>(period - (t0 % period), p->max_iters - t0);
+    w.step_block.resize(w.W);
+    w.step_slot.resize(w.W);
+    std::vector<int32_t> pending, pending_slots;
+    if (mode == kpp::MemoMode::Off) KPP_TRY(ensure_slots(sys, static_cast<int32_t>(2 * period), s));
+    for (int64_t k = 0; k < w.W; ++k) {
       bool is_new = false;
       const int32_t b = sch->next(&is_new);
-      step_block[k] = b;
+      w.step_block[k] = b;
       if (mode == kpp::MemoMode::Off) {
-        step_slot[k] = static_cast<int32_t>(k);
+        // windows alternate between two halves of the slot table
+        const int32_t q = static_cast<int32_t>(idx * period + k);
+        w.step_slot[k] = q;
         pending.push_back(b);
-        pending_slots.push_back(static_cast<int32_t>(k));
+        pending_slots.push_back(q);
         ++misses;
         continue;
       }
@@ -354,43 +389,66 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
       } else {
         ++hits;
       }
-      step_slot[k] = q;
+      w.step_slot[k] = q;
     }
     if (mode != kpp::MemoMode::Off) KPP_TRY(ensure_slots(sys, sys->used_slots, s));
-    // stage: [nb*s rows][nb lens][nb slot ids][W step slots]
-    const int32_t nb = static_cast<int32_t>(pending.size());
-    const size_t o_len = static_cast<size_t>(nb) * s, o_slot = o_len + nb, o_step = o_slot + nb;
-    const size_t need = o_step + static_cast<size_t>(W);
-    KPP_TRY(ensure_stage(sys, need));
-    int32_t* hs_ = sys->h_stage;
-    for (int32_t k = 0; k < nb; ++k) {
+    w.nb = static_cast<int32_t>(pending.size());
+    w.o_len = static_cast<size_t>(w.nb) * s;
+    w.o_slot = w.o_len + w.nb;
+    w.o_step = w.o_slot + w.nb;
+    const size_t need = w.o_step + static_cast<size_t>(w.W);
+    KPP_TRY(ensure_stage(sys, idx, need));
+    int32_t* hs_ = sys->h_stage[idx];
+    for (int32_t k = 0; k < w.nb; ++k) {
       const int32_t b = pending[k];
       const int32_t l = sch->len(b);
       std::copy(sch->rows(b), sch->rows(b) + l, hs_ + static_cast<size_t>(k) * s);
       std::fill(hs_ + static_cast<size_t>(k) * s + l, hs_ + static_cast<size_t>(k + 1) * s, 0);
-      hs_[o_len + k] = l;
-      hs_[o_slot + k] = pending_slots[k];
+      hs_[w.o_len + k] = l;
+      hs_[w.o_slot + k] = pending_slots[k];
     }
-    std::copy(step_slot.begin(), step_slot.end(), hs_ + o_step);
-    HIP_TRY(hipMemcpyAsync(sys->d_stage, hs_, need * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    const int32_t* d_srows = sys->d_stage;
-    const int32_t* d_slens = sys->d_stage + o_len;
-    const int32_t* d_sslot = sys->d_stage + o_slot;
-    const int32_t* d_step = sys->d_stage + o_step;
-    if (nb > 0) {
-      HIP_TRY(hipEventRecord(sys->ev[2], st));
-      kpp::launch_scatter_rows(d_srows, d_slens, d_sslot, nb, s, sys->rows, sys->lens, st);
-      kpp::launch_gram(kind, sys->A, sys->lda, n, d_srows, d_slens, s, nb, p->lambda, sys->L,
-                       sys->slot_stride, d_sslot, st);
+    std::copy(w.step_slot.begin(), w.step_slot.end(), hs_ + w.o_step);
+    return KPP_OK;
+  };
+  // upload the window's staging and factor its memo misses on `fs`
+  auto enqueue_factor = [&](const Window& w, hipStream_t fs) -> kpp_status {
+    const int idx = w.idx;
+    const size_t need = w.o_step + static_cast<size_t>(w.W);
+    HIP_TRY(hipMemcpyAsync(sys->d_stage[idx], sys->h_stage[idx], need * sizeof(int32_t), hipMemcpyHostToDevice, fs));
+    HIP_TRY(hipEventRecord(sys->ev_fact[idx][0], fs));
+    if (w.nb > 0) {
+      const int32_t* d_srows = sys->d_stage[idx];
+      const int32_t* d_slens = sys->d_stage[idx] + w.o_len;
+      const int32_t* d_sslot = sys->d_stage[idx] + w.o_slot;
+      kpp::launch_scatter_rows(d_srows, d_slens, d_sslot, w.nb, s, sys->rows, sys->lens, fs);
+      kpp::launch_gram(kind, sys->A, sys->lda, n, d_srows, d_slens, s, w.nb, p->lambda, sys->L,
+                       sys->slot_stride, d_sslot, fs);
       if (s <= kpp::kFactorSmallMax) {
-        kpp::launch_factor_small(sys->L, sys->slot_stride, s, d_slens, nb, d_sslot, 1, sys->err, st);
+        kpp::launch_factor_small(sys->L, sys->slot_stride, s, d_slens, w.nb, d_sslot, 1, sys->err, fs);
       } else {
-        kpp::launch_cholesky(sys->L, s, sys->slot_stride, d_slens, nb, d_sslot, sys->err, st);
-        kpp::launch_factor_inverse(sys->L, sys->slot_stride, s, d_slens, nb, d_sslot, st);
+        kpp::launch_cholesky(sys->L, s, sys->slot_stride, d_slens, w.nb, d_sslot, sys->err, fs);
+        kpp::launch_factor_inverse(sys->L, sys->slot_stride, s, d_slens, w.nb, d_sslot, fs);
       }
       HIP_TRY(hipGetLastError());
-      HIP_TRY(hipEventRecord(sys->ev[3], st));
     }
+    HIP_TRY(hipEventRecord(sys->ev_fact[idx][1], fs));
+    return KPP_OK;
+  };
+
+  // the side stream's first work must follow this solve's initialisation
+  HIP_TRY(hipEventRecord(sys->ev_fact[1][2], st));
+  HIP_TRY(hipStreamWaitEvent(sys->ctx->side, sys->ev_fact[1][2], 0));
+  Window win[2];
+  bool have_next = false;
+  if (p->max_iters > 0) {
+    KPP_TRY(plan(win[0], 0, 0));
+    KPP_TRY(enqueue_factor(win[0], st));  // nothing to overlap with yet
+  }
+  int cur = 0;
+  while (t < p->max_iters && !converged) {
+    Window& w = win[cur];
+    if (have_next) HIP_TRY(hipStreamWaitEvent(st, sys->ev_fact[cur][1], 0));
+    const int32_t* d_step = sys->d_stage[cur] + w.o_step;
     HIP_TRY(hipEventRecord(sys->ev[0], st));
     if (fused) {
       if (sys->epoch > 0x3fffffffu) {
@@ -407,7 +465,7 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
       a.L = sys->L;
       a.slot_stride = sys->slot_stride;
       a.s = s;
-      a.W = static_cast<int32_t>(W);
+      a.W = static_cast<int32_t>(w.W);
       a.step_slot = d_step;
       a.x = x;
       a.mom = sys->mom;
@@ -420,43 +478,56 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
       a.ds = sys->ds;
       a.err = sys->err;
       a.spin_limit = int64_t{1} << 22;
+      a.phase_ticks = phase_prof ? sys->phase_ticks : nullptr;
       kpp::launch_fused(kind, a, cpl, groups, st);
-      sys->epoch += static_cast<uint32_t>(W);
+      sys->epoch += static_cast<uint32_t>(w.W);
       ++launches;
     } else {
-      for (int64_t k = 0; k < W; ++k) {
-        const int32_t q = step_slot[k];
-        const int32_t sb = sch->len(step_block[k]);
+      for (int64_t k = 0; k < w.W; ++k) {
+        const int32_t q = w.step_slot[k];
+        const int32_t sb = sch->len(w.step_block[k]);
         const int32_t* rows = sys->rows + static_cast<size_t>(q) * s;
         kpp::launch_block_gemv_partial(sys->A, sys->lda, n, rows, sb, x, sys->rpart, P, chunk, st);
-        kpp::launch_block_project(sys->rpart, P, sys->b, rows, sb, sys->L + sd * q + static_cast<size_t>(s) * s, s, sys->y, sys->ds,
-                                  zeta, p->adaptive_rho, st);
+        kpp::launch_block_project(sys->rpart, P, sys->b, rows, sb, sys->L + sd * q + static_cast<size_t>(s) * s,
+                                  s, sys->y, sys->ds, zeta, p->adaptive_rho, st);
         kpp::launch_update(kind, sys->A, sys->lda, n, rows, sb, sys->y, sys->ds, eta, x, sys->mom, st);
       }
-      launches += 3 * W;
+      launches += 3 * w.W;
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(sys->ev[1], st));
     HIP_TRY(hipMemcpyAsync(sys->h_ds, sys->ds, sizeof(kpp::DevState), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(sys->h_err, sys->err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    // plan and factor the next window while this one runs
+    const int64_t t_next = t + w.W;
+    have_next = false;
+    if (t_next < p->max_iters) {
+      KPP_TRY(plan(win[cur ^ 1], t_next, cur ^ 1));
+      KPP_TRY(enqueue_factor(win[cur ^ 1], sys->ctx->side));
+      have_next = true;
+    }
     HIP_TRY(hipStreamSynchronize(st));
     hs = *sys->h_ds;
     float ms = 0.0f;
     HIP_TRY(hipEventElapsedTime(&ms, sys->ev[0], sys->ev[1]));
     t_kernel += 1e-3 * ms;
-    if (nb > 0) {
-      HIP_TRY(hipEventElapsedTime(&ms, sys->ev[2], sys->ev[3]));
+    if (w.nb > 0) {
+      HIP_TRY(hipEventElapsedTime(&ms, sys->ev_fact[cur][0], sys->ev_fact[cur][1]));
       t_factor += 1e-3 * ms;
     }
     const int32_t herr = *sys->h_err;
     if (herr & 2) {
+      HIP_TRY(hipStreamSynchronize(sys->ctx->side));
       HIP_TRY(hipMemsetAsync(sys->flags, 0, kFlagWords * sizeof(uint32_t), st));
       HIP_TRY(hipStreamSynchronize(st));
       sys->epoch = 0;
       return fail(KPP_ERR_DEVICE, "a device-side wait exceeded its bound in the fused engine");
     }
-    if (herr & 1) return fail(KPP_ERR_NOT_SPD, "a regularized block Gram has no Cholesky factor (lambda=%g)", p->lambda);
-    t += W;
+    if (herr & 1) {
+      HIP_TRY(hipStreamSynchronize(sys->ctx->side));
+      return fail(KPP_ERR_NOT_SPD, "a regularized block Gram has no Cholesky factor (lambda=%g)", p->lambda);
+    }
+    t = t_next;
     if ((t % period) == 0 && hs.cand) {
       if (p->confirm_true_residual) {
         double rn = 0.0;
@@ -467,11 +538,32 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
         converged = true;
       }
     }
+    cur ^= 1;
+  }
+  // factorizations planned past the stop are dropped from the counts; the
+  // side stream is drained so that no work of this call is left in flight
+  HIP_TRY(hipStreamSynchronize(sys->ctx->side));
+  if (have_next && converged) {
+    const Window& w = win[cur];
+    misses -= w.nb;
+    hits -= w.W - w.nb;
   }
   if (!converged || std::isnan(true_rel)) {
     double rn = 0.0;
     KPP_TRY(residual_norm(sys, x, &rn));
     true_rel = sys->bnorm > 0 ? rn / sys->bnorm : rn;
+  }
+  if (phase_prof && t > 0) {
+    uint64_t ticks[kpp::kFusedPhases];
+    HIP_TRY(hipMemcpy(ticks, sys->phase_ticks, sizeof ticks, hipMemcpyDeviceToHost));
+    int rate_khz = 0;
+    HIP_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, sys->ctx->device));
+    static const char* names[kpp::kFusedPhases] = {"rows", "tile-dot", "publish", "wait", "reduce-r",
+                                                   "solve+scalars", "update", "-"};
+    std::fprintf(stderr, "[kpp phase profile] %lld steps, workgroup 0, us per step:", static_cast<long long>(t));
+    for (int p = 0; p < kpp::kFusedPhases - 1; ++p)
+      std::fprintf(stderr, " %s=%.3f", names[p], 1e3 * static_cast<double>(ticks[p]) / rate_khz / static_cast<double>(t));
+    std::fprintf(stderr, "\n");
   }
   if (res) {
     res->iters = t;
@@ -544,6 +636,10 @@ KPP_API kpp_status kpp_context_create(int32_t device, void* hip_stream, kpp_cont
   if (!c) return fail(KPP_ERR_OOM, "host allocation failed");
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return fail(KPP_ERR_HIP, "hipStreamCreateWithFlags failed");
+  }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->cu_count = prop.multiProcessorCount;
   *out = c;
@@ -551,6 +647,13 @@ KPP_API kpp_status kpp_context_create(int32_t device, void* hip_stream, kpp_cont
 }
 
 KPP_API kpp_status kpp_context_destroy(kpp_context* ctx) {
+  if (ctx) {
+    (void)hipSetDevice(ctx->device);
+    if (ctx->side) {
+      (void)hipStreamSynchronize(ctx->side);
+      (void)hipStreamDestroy(ctx->side);
+    }
+  }
   delete ctx;
   return KPP_OK;
 }
@@ -596,6 +699,12 @@ KPP_API kpp_status kpp_system_create(kpp_context* ctx, int32_t kind, int64_t m, 
       return fail(KPP_ERR_HIP, "hipEventCreate failed");
     }
   }
+  for (auto& pair : sys->ev_fact)
+    for (auto& e : pair)
+      if (hipEventCreate(&e) != hipSuccess) {
+        destroy_buffers(sys.get());
+        return fail(KPP_ERR_HIP, "hipEventCreate failed");
+      }
   hipStream_t st = ctx->stream;
   HIP_TRY(hipMemsetAsync(sys->flags, 0, kFlagWords * sizeof(uint32_t), st));
   // finiteness of A and b, and ||b||
