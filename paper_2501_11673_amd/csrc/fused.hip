@@ -80,8 +80,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 // the block and columns past the matrix are clamped, not masked: those entries
 // always meet a zero (x is zero beyond n, y is zero beyond the block), and A
 // is finite (checked when the system is created), so they contribute nothing.
-template <int CPL>
-__device__ __forceinline__ void load_tile(double (&tile)[kTileMax], const double* __restrict__ A,
+template <int CPL, typename TA>
+__device__ __forceinline__ void load_tile(TA (&tile)[kTileMax], const TA* __restrict__ A,
                                           int64_t lda, int64_t n, const int32_t* __restrict__ rows,
                                           int sb, int wv, int lane, int64_t col0) {
   constexpr int RMAX = kTileMax / CPL;
@@ -89,14 +89,18 @@ __device__ __forceinline__ void load_tile(double (&tile)[kTileMax], const double
 #pragma unroll
   for (int r = 0; r < RMAX; ++r) {
     const int row = __builtin_amdgcn_readlane(myrow, r);
-    const double* Ai = A + static_cast<int64_t>(row) * lda;
+    const TA* Ai = A + static_cast<int64_t>(row) * lda;
 #pragma unroll
     for (int e = 0; e < CPL; ++e) tile[r * CPL + e] = Ai[min(col0 + e, n - 1)];
   }
 }
 
-template <int KIND, int CPL>
+// TA: storage and product type of A (double; float for the mixed-precision
+// inner solver: the tile, the partial residuals and the direction are formed in
+// FP32 with FP32 accumulation, everything else stays FP64).
+template <int KIND, int CPL, typename TA>
 __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
+  const TA* __restrict__ Amat = static_cast<const TA*>(a.A);
   // optional phase profile (workgroup 0, thread 0): ticks[p] accumulates the
   // wall-clock time from mark p-1 to mark p
   uint64_t tick_last = 0, ticks[kFusedPhases];
@@ -143,11 +147,11 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
     st = *a.ds;
     abort_flag = 0;
   }
-  double tile[kTileMax];
+  TA tile[kTileMax];
   int q = a.step_slot[0];
   int sb = a.lens[q];
   int cur = 0;
-  load_tile<CPL>(tile, a.A, a.lda, n, a.rows + static_cast<int64_t>(q) * s, sb, wv, lane, col0);
+  load_tile<CPL>(tile, Amat, a.lda, n, a.rows + static_cast<int64_t>(q) * s, sb, wv, lane, col0);
   // wave 0 forms r: its lane holds b at block rows lane + 64 u of the current step
   double bval[4] = {0.0, 0.0, 0.0, 0.0};
   if (tid < sb) rsbuf[0][tid] = a.rows[static_cast<int64_t>(q) * s + tid];
@@ -164,18 +168,21 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
   for (int k = 0; k < a.W; ++k) {
     const int32_t* rs = rsbuf[cur];
     if ((KIND == 0 || !KPP_PREFETCH) && k > 0) {
-      load_tile<CPL>(tile, a.A, a.lda, n, a.rows + static_cast<int64_t>(q) * s, sb, wv, lane, col0);
+      load_tile<CPL>(tile, Amat, a.lda, n, a.rows + static_cast<int64_t>(q) * s, sb, wv, lane, col0);
     }
     const double* Ginv = a.L + static_cast<int64_t>(q) * a.slot_stride + static_cast<int64_t>(s) * s;
     KPP_MARK(0)
 
     // 1. partial residuals of this wave's rows, butterfly across the lanes
-    double v[RMAX];
+    TA xt[CPL];
+#pragma unroll
+    for (int e = 0; e < CPL; ++e) xt[e] = static_cast<TA>(xr[e]);
+    TA v[RMAX];
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) {
-      double acc = 0.0;
+      TA acc = 0;
 #pragma unroll
-      for (int e = 0; e < CPL; ++e) acc = fma(tile[r * CPL + e], xr[e], acc);
+      for (int e = 0; e < CPL; ++e) acc = fma(tile[r * CPL + e], xt[e], acc);
       v[r] = acc;
     }
 #pragma unroll
@@ -183,8 +190,8 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
       const bool up = (lane & o) != 0;
 #pragma unroll
       for (int r = 0; r < cnt / 2; ++r) {
-        const double send = up ? v[r] : v[r + cnt / 2];
-        const double keep = up ? v[r + cnt / 2] : v[r];
+        const TA send = up ? v[r] : v[r + cnt / 2];
+        const TA keep = up ? v[r + cnt / 2] : v[r];
         v[r] = keep + __shfl_xor(send, o, 64);
       }
     }
@@ -192,7 +199,7 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
     for (int o = 32 / RMAX; o >= 1; o >>= 1) v[0] += __shfl_xor(v[0], o, 64);
     {
       const int row = wv + 4 * (lane >> RSHIFT);
-      if ((lane & ((1 << RSHIFT) - 1)) == 0 && row < sb) stage[row] = v[0];
+      if ((lane & ((1 << RSHIFT) - 1)) == 0 && row < sb) stage[row] = static_cast<double>(v[0]);
     }
     __syncthreads();
     KPP_MARK(1)
@@ -237,7 +244,7 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
           grow[u] = Ginv[static_cast<int64_t>(my_first) * s + min(kk, sb - 1)];
         }
       }
-      if (KPP_PREFETCH && have_next) load_tile<CPL>(tile, a.A, a.lda, n, Rn, sbn, wv, lane, col0);
+      if (KPP_PREFETCH && have_next) load_tile<CPL>(tile, Amat, a.lda, n, Rn, sbn, wv, lane, col0);
     }
     if (tid < G) {
       int64_t spins = 0;
@@ -301,7 +308,7 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
         }
       }
       // wave 0's share of the next tile, after its partial loads have landed
-      if (KIND == 1 && KPP_PREFETCH && have_next) load_tile<CPL>(tile, a.A, a.lda, n, Rn, sbn, wv, lane, col0);
+      if (KIND == 1 && KPP_PREFETCH && have_next) load_tile<CPL>(tile, Amat, a.lda, n, Rn, sbn, wv, lane, col0);
     }
     __syncthreads();
     KPP_MARK(4)
@@ -384,15 +391,18 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
 #pragma unroll
     for (int e = 0; e < CPL; ++e) w[e] = 0.0;
     if (KIND == 0) {
+      TA wt[CPL];
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) wt[e] = 0;
 #pragma unroll
       for (int r = 0; r < RMAX; ++r) {
         const int i = wv + 4 * r;
-        const double yi = (i < sb) ? yv[i] : 0.0;
+        const TA yi = static_cast<TA>((i < sb) ? yv[i] : 0.0);
 #pragma unroll
-        for (int e = 0; e < CPL; ++e) w[e] = fma(tile[r * CPL + e], yi, w[e]);
+        for (int e = 0; e < CPL; ++e) wt[e] = fma(tile[r * CPL + e], yi, wt[e]);
       }
 #pragma unroll
-      for (int e = 0; e < CPL; ++e) wred[wv * 64 * CPL + lane * CPL + e] = w[e];
+      for (int e = 0; e < CPL; ++e) wred[wv * 64 * CPL + lane * CPL + e] = static_cast<double>(wt[e]);
       __syncthreads();
 #pragma unroll
       for (int e = 0; e < CPL; ++e) {
@@ -448,24 +458,31 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
   if (wg == 0 && tid == 0) *a.ds = st;
 }
 
-template <int KIND>
+template <int KIND, typename TA>
 void launch_kind(const FusedArgs& a, int cpl, int G, hipStream_t st) {
   switch (cpl) {
-    case 1: hipLaunchKernelGGL((k_fused<KIND, 1>), dim3(G), dim3(kT), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_fused<KIND, 2>), dim3(G), dim3(kT), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_fused<KIND, 4>), dim3(G), dim3(kT), 0, st, a); break;
-    case 8: hipLaunchKernelGGL((k_fused<KIND, 8>), dim3(G), dim3(kT), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_fused<KIND, 16>), dim3(G), dim3(kT), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((k_fused<KIND, 1, TA>), dim3(G), dim3(kT), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_fused<KIND, 2, TA>), dim3(G), dim3(kT), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_fused<KIND, 4, TA>), dim3(G), dim3(kT), 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_fused<KIND, 8, TA>), dim3(G), dim3(kT), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_fused<KIND, 16, TA>), dim3(G), dim3(kT), 0, st, a); break;
   }
 }
 
 }  // namespace
 
-void launch_fused(int32_t kind, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t st) {
-  if (kind == 0)
-    launch_kind<0>(a, cpl, groups, st);
-  else
-    launch_kind<1>(a, cpl, groups, st);
+void launch_fused(int32_t kind, bool a_fp32, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t st) {
+  if (kind == 0) {
+    if (a_fp32)
+      launch_kind<0, float>(a, cpl, groups, st);
+    else
+      launch_kind<0, double>(a, cpl, groups, st);
+  } else {
+    if (a_fp32)
+      launch_kind<1, float>(a, cpl, groups, st);
+    else
+      launch_kind<1, double>(a, cpl, groups, st);
+  }
 }
 
 }  // namespace kpp

@@ -10,6 +10,7 @@
 // Every reduction runs in a fixed order so that a run is bitwise repeatable.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "kernels.hpp"
@@ -161,14 +162,17 @@ __global__ __launch_bounds__(kT) void k_update(const double* __restrict__ A, int
 // --------------------------------------------------------------------------
 // memo miss: regularized Grams (lower part, column-major slots)
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(kT) void k_gram_kpp(const double* __restrict__ A, int64_t lda,
+template <typename TA>
+__global__ __launch_bounds__(kT) void k_gram_kpp(const TA* __restrict__ A, int64_t lda,
                                                  int64_t n, const int32_t* __restrict__ rows,
                                                  const int32_t* __restrict__ lens, int32_t s,
                                                  double lambda, double* __restrict__ G, int64_t stride,
-                                                 const int32_t* __restrict__ slot_of) {
-  __shared__ double As[32][33];
-  __shared__ double Bs[32][33];
+                                                 const int32_t* __restrict__ slot_of,
+                                                 const int32_t* __restrict__ only) {
+  __shared__ TA As[32][33];
+  __shared__ TA Bs[32][33];
   const int blk = blockIdx.z;
+  if (only && !only[blk]) return;
   const int sb = lens[blk];
   const int ti = blockIdx.x, tk = blockIdx.y;
   const int i0 = ti * 32, k0 = tk * 32;
@@ -176,12 +180,12 @@ __global__ __launch_bounds__(kT) void k_gram_kpp(const double* __restrict__ A, i
   const int32_t* R = rows + static_cast<int64_t>(blk) * s;
   double* Gb = G + static_cast<int64_t>(slot_of[blk]) * stride;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double a00 = 0, a01 = 0, a10 = 0, a11 = 0;
+  TA a00 = 0, a01 = 0, a10 = 0, a11 = 0;
   for (int64_t j0 = 0; j0 < n; j0 += 32) {
     for (int e = threadIdx.x; e < 1024; e += kT) {
       const int rr = e >> 5, cc = e & 31;
       const int64_t j = j0 + cc;
-      double va = 0.0, vb = 0.0;
+      TA va = 0, vb = 0;
       if (j < n) {
         if (i0 + rr < sb) va = A[static_cast<int64_t>(R[i0 + rr]) * lda + j];
         if (k0 + rr < sb) vb = A[static_cast<int64_t>(R[k0 + rr]) * lda + j];
@@ -192,8 +196,8 @@ __global__ __launch_bounds__(kT) void k_gram_kpp(const double* __restrict__ A, i
     __syncthreads();
 #pragma unroll 8
     for (int cc = 0; cc < 32; ++cc) {
-      const double p0 = As[ty * 2][cc], p1 = As[ty * 2 + 1][cc];
-      const double q0 = Bs[tx * 2][cc], q1 = Bs[tx * 2 + 1][cc];
+      const TA p0 = As[ty * 2][cc], p1 = As[ty * 2 + 1][cc];
+      const TA q0 = Bs[tx * 2][cc], q1 = Bs[tx * 2 + 1][cc];
       a00 = fma(p0, q0, a00);
       a01 = fma(p0, q1, a01);
       a10 = fma(p1, q0, a10);
@@ -201,7 +205,8 @@ __global__ __launch_bounds__(kT) void k_gram_kpp(const double* __restrict__ A, i
     }
     __syncthreads();
   }
-  const double acc[2][2] = {{a00, a01}, {a10, a11}};
+  const double acc[2][2] = {{static_cast<double>(a00), static_cast<double>(a01)},
+                            {static_cast<double>(a10), static_cast<double>(a11)}};
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -211,18 +216,21 @@ __global__ __launch_bounds__(kT) void k_gram_kpp(const double* __restrict__ A, i
     }
 }
 
-__global__ __launch_bounds__(kT) void k_gram_cd(const double* __restrict__ A, int64_t lda,
+template <typename TA>
+__global__ __launch_bounds__(kT) void k_gram_cd(const TA* __restrict__ A, int64_t lda,
                                                 const int32_t* __restrict__ rows,
                                                 const int32_t* __restrict__ lens, int32_t s,
                                                 double lambda, double* __restrict__ G, int64_t stride,
-                                                const int32_t* __restrict__ slot_of) {
+                                                const int32_t* __restrict__ slot_of,
+                                                const int32_t* __restrict__ only) {
   const int blk = blockIdx.x;
+  if (only && !only[blk]) return;
   const int sb = lens[blk];
   const int32_t* R = rows + static_cast<int64_t>(blk) * s;
   double* Gb = G + static_cast<int64_t>(slot_of[blk]) * stride;
   for (int e = threadIdx.x; e < sb * sb; e += kT) {
     const int k = e / sb, i = e - k * sb;
-    if (i >= k) Gb[static_cast<int64_t>(k) * s + i] = A[static_cast<int64_t>(R[i]) * lda + R[k]] + (i == k ? lambda : 0.0);
+    if (i >= k) Gb[static_cast<int64_t>(k) * s + i] = static_cast<double>(A[static_cast<int64_t>(R[i]) * lda + R[k]]) + (i == k ? lambda : 0.0);
   }
 }
 
@@ -233,9 +241,10 @@ template <bool IN_LDS>
 __global__ __launch_bounds__(kT) void k_cholesky(double* __restrict__ G, int32_t s, int64_t stride,
                                                  const int32_t* __restrict__ lens,
                                                  const int32_t* __restrict__ slot_of,
-                                                 int32_t* __restrict__ err) {
+                                                 int32_t* __restrict__ err, FactorCheck chk) {
   extern __shared__ double lds[];
   const int blk = blockIdx.x;
+  if (chk.only && !chk.only[blk]) return;
   const int sb = lens[blk];
   double* Gb = G + static_cast<int64_t>(slot_of[blk]) * stride;
   double* M;
@@ -267,8 +276,28 @@ __global__ __launch_bounds__(kT) void k_cholesky(double* __restrict__ G, int32_t
         M[static_cast<int64_t>(k) * ld + i] = fma(-lij, M[static_cast<int64_t>(j) * ld + k], M[static_cast<int64_t>(k) * ld + i]);
     }
   }
+  __shared__ int bad_any;
+  if (threadIdx.x == 0) bad_any = 0;
   __syncthreads();
-  if (bad && threadIdx.x == 0) atomicOr(err, 1);
+  if (bad) atomicOr(&bad_any, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double lo = 1.0 / 0.0, hi = 0.0;
+    for (int i = 0; i < sb; ++i) {
+      const double d = M[static_cast<int64_t>(i) * ld + i];
+      lo = fmin(lo, d);
+      hi = fmax(hi, d);
+    }
+    const double ratio = hi / lo;
+    const bool ill = !(ratio * ratio <= chk.kappa_max);
+    if (chk.flag) {
+      const int f = (bad_any || ill) ? 1 : 0;
+      chk.flag[blk] = f;
+      if (f) atomicAdd(chk.counter, 1);
+    } else if (bad_any) {
+      atomicOr(err, 1);
+    }
+  }
   // write back L with zero strict upper triangle and zero padding
   for (int e = threadIdx.x; e < s * s; e += kT) {
     const int k = e / s, i = e - k * s;
@@ -321,6 +350,41 @@ __global__ __launch_bounds__(kT) void k_check_finite(const double* __restrict__ 
   (void)m;
 }
 
+__global__ __launch_bounds__(kT) void k_convert_f32(const double* __restrict__ A, int64_t lda, int64_t m,
+                                                    int64_t n, float* __restrict__ out) {
+  const int64_t total = m * n;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x; e < total;
+       e += static_cast<int64_t>(gridDim.x) * kT) {
+    const int64_t i = e / n, j = e - i * n;
+    out[e] = static_cast<float>(A[i * lda + j]);
+  }
+}
+
+// r = b - A x, one wave per row
+__global__ __launch_bounds__(kT) void k_residual_vec(const double* __restrict__ A, int64_t lda, int64_t m,
+                                                     int64_t n, const double* __restrict__ x,
+                                                     const double* __restrict__ b, double* __restrict__ r,
+                                                     double* __restrict__ rowsq) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= m) return;
+  const double* Ai = A + i * lda;
+  double acc = 0.0;
+  for (int64_t j = lane; j < n; j += 64) acc = fma(Ai[j], x[j], acc);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) {
+    const double ri = b[i] - acc;
+    r[i] = ri;
+    rowsq[i] = ri * ri;
+  }
+}
+
+__global__ __launch_bounds__(kT) void k_axpy1(double* __restrict__ x, const double* __restrict__ d, int64_t n) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+  if (j < n) x[j] += d[j];
+}
+
 __global__ void k_state_init(DevState* ds, double rho0, double thr) {
   DevState s{};
   s.rho = rho0;
@@ -344,9 +408,12 @@ __global__ void k_state_init(DevState* ds, double rho0, double thr) {
 template <bool IN_LDS>
 __global__ __launch_bounds__(kT) void k_factor_inverse(double* __restrict__ slots, int64_t stride,
                                                        int32_t s, const int32_t* __restrict__ lens,
-                                                       const int32_t* __restrict__ slot_of) {
+                                                       const int32_t* __restrict__ slot_of,
+                                                       const int32_t* __restrict__ only,
+                                                       const int32_t* __restrict__ skip) {
   extern __shared__ double lds[];
   const int blk = blockIdx.x;
+  if ((only && !only[blk]) || (skip && skip[blk])) return;
   const int sb = lens[blk];
   double* base = slots + static_cast<int64_t>(slot_of[blk]) * stride;
   const double* Lc = base;
@@ -405,11 +472,15 @@ __global__ __launch_bounds__(kT) void k_factor_inverse(double* __restrict__ slot
 __global__ __launch_bounds__(kT) void k_factor_small(double* __restrict__ slots, int64_t stride,
                                                      int32_t s, const int32_t* __restrict__ lens,
                                                      const int32_t* __restrict__ slot_of,
-                                                     int32_t want_inverse, int32_t* __restrict__ err) {
+                                                     int32_t want_inverse, int32_t* __restrict__ err,
+                                                     FactorCheck chk) {
   __shared__ double colbuf[128];
   __shared__ double rowbuf[128];
   __shared__ double piv;
+  __shared__ double dmin[16], dmax[16];
+  __shared__ int flag_blk;
   const int blk = blockIdx.x;
+  if (chk.only && !chk.only[blk]) return;
   const int sb = lens[blk];
   double* Lc = slots + static_cast<int64_t>(slot_of[blk]) * stride;
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
@@ -465,7 +536,44 @@ __global__ __launch_bounds__(kT) void k_factor_small(double* __restrict__ slots,
       const int i = ty + 16 * a, k = tx + 16 * b;
       if (i < s && k < s) Lc[static_cast<int64_t>(k) * s + i] = (i < sb && k < sb && i >= k) ? g[a][b] : 0.0;
     }
-  if (bad) atomicOr(err, 1);
+  // breakdown, and kappa(G) >= (max L_ii / min L_ii)^2 from the factor's diagonal
+  if (tx == ty) {
+    double lo = 1.0 / 0.0, hi = 0.0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int i = ty + 16 * a;
+      if (i < sb) {
+        lo = fmin(lo, g[a][a]);
+        hi = fmax(hi, g[a][a]);
+      }
+    }
+    dmin[ty] = lo;
+    dmax[ty] = hi;
+  }
+  if (threadIdx.x == 0) flag_blk = 0;
+  __syncthreads();
+  if (bad) atomicOr(&flag_blk, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double lo = dmin[0], hi = dmax[0];
+    for (int u = 1; u < 16; ++u) {
+      lo = fmin(lo, dmin[u]);
+      hi = fmax(hi, dmax[u]);
+    }
+    const double ratio = hi / lo;
+    const bool ill = !(ratio * ratio <= chk.kappa_max);
+    if (chk.flag) {
+      // low-precision pass: mark the block for an FP64 redo instead of failing
+      const int f = (flag_blk || ill) ? 1 : 0;
+      chk.flag[blk] = f;
+      if (f) atomicAdd(chk.counter, 1);
+      flag_blk = f;
+    } else if (flag_blk) {
+      atomicOr(err, 1);
+    }
+  }
+  __syncthreads();
+  if (chk.flag && flag_blk) return;  // the FP64 pass recomputes this block
   if (!want_inverse) return;
   // L^{-1} in place: at step j, row j is scaled by 1/L_jj and eliminated from
   // the rows below (their left entries in column j are still L's)
@@ -591,20 +699,20 @@ void launch_update(int32_t kind, const double* A, int64_t lda, int64_t n, const 
 
 void launch_gram(int32_t kind, const double* A, int64_t lda, int64_t n, const int32_t* rows,
                  const int32_t* lens, int32_t s, int32_t nb, double lambda, double* G, int64_t stride,
-                 const int32_t* slot_of, hipStream_t st) {
+                 const int32_t* slot_of, hipStream_t st, const int32_t* only) {
   if (nb <= 0) return;
   if (kind == 0) {
     const int nt = (s + 31) / 32;
-    hipLaunchKernelGGL(k_gram_kpp, dim3(nt, nt, nb), dim3(kT), 0, st, A, lda, n, rows, lens, s,
-                       lambda, G, stride, slot_of);
+    hipLaunchKernelGGL(k_gram_kpp<double>, dim3(nt, nt, nb), dim3(kT), 0, st, A, lda, n, rows, lens, s,
+                       lambda, G, stride, slot_of, only);
   } else {
-    hipLaunchKernelGGL(k_gram_cd, dim3(nb), dim3(kT), 0, st, A, lda, rows, lens, s, lambda, G,
-                       stride, slot_of);
+    hipLaunchKernelGGL(k_gram_cd<double>, dim3(nb), dim3(kT), 0, st, A, lda, rows, lens, s, lambda, G,
+                       stride, slot_of, only);
   }
 }
 
 void launch_cholesky(double* G, int32_t s, int64_t stride, const int32_t* lens, int32_t nb,
-                     const int32_t* slot_of, int32_t* err, hipStream_t st) {
+                     const int32_t* slot_of, int32_t* err, hipStream_t st, FactorCheck chk) {
   if (nb <= 0) return;
   if (s <= kLdsCholMax) {
     const size_t lds = static_cast<size_t>(s) * s * sizeof(double);
@@ -615,9 +723,9 @@ void launch_cholesky(double* G, int32_t s, int64_t stride, const int32_t* lens, 
                                 static_cast<int>(kLdsCholMax * kLdsCholMax * sizeof(double)));
       attr_set = true;
     }
-    hipLaunchKernelGGL(k_cholesky<true>, dim3(nb), dim3(kT), lds, st, G, s, stride, lens, slot_of, err);
+    hipLaunchKernelGGL(k_cholesky<true>, dim3(nb), dim3(kT), lds, st, G, s, stride, lens, slot_of, err, chk);
   } else {
-    hipLaunchKernelGGL(k_cholesky<false>, dim3(nb), dim3(kT), 0, st, G, s, stride, lens, slot_of, err);
+    hipLaunchKernelGGL(k_cholesky<false>, dim3(nb), dim3(kT), 0, st, G, s, stride, lens, slot_of, err, chk);
   }
 }
 
@@ -637,7 +745,7 @@ void launch_check_finite(const double* A, int64_t lda, int64_t m, int64_t n, con
 }
 
 void launch_factor_inverse(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
-                           const int32_t* slot_of, hipStream_t st) {
+                           const int32_t* slot_of, hipStream_t st, const int32_t* only, const int32_t* skip) {
   if (nb <= 0) return;
   if (s <= kLdsCholMax) {
     const size_t lds = (static_cast<size_t>(s) * (s + 1) + s) * sizeof(double);
@@ -648,23 +756,56 @@ void launch_factor_inverse(double* slots, int64_t stride, int32_t s, const int32
                                 static_cast<int>((kLdsCholMax * (kLdsCholMax + 1) + kLdsCholMax) * sizeof(double)));
       attr_set = true;
     }
-    hipLaunchKernelGGL(k_factor_inverse<true>, dim3(nb), dim3(kT), lds, st, slots, stride, s, lens, slot_of);
+    hipLaunchKernelGGL(k_factor_inverse<true>, dim3(nb), dim3(kT), lds, st, slots, stride, s, lens, slot_of, only, skip);
   } else {
-    hipLaunchKernelGGL(k_factor_inverse<false>, dim3(nb), dim3(kT), 0, st, slots, stride, s, lens, slot_of);
+    hipLaunchKernelGGL(k_factor_inverse<false>, dim3(nb), dim3(kT), 0, st, slots, stride, s, lens, slot_of, only, skip);
   }
 }
 
 void launch_factor_small(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
-                         const int32_t* slot_of, int32_t want_inverse, int32_t* err, hipStream_t st) {
+                         const int32_t* slot_of, int32_t want_inverse, int32_t* err, hipStream_t st,
+                         FactorCheck chk) {
   if (nb <= 0) return;
   hipLaunchKernelGGL(k_factor_small, dim3(nb), dim3(kT), 0, st, slots, stride, s, lens, slot_of,
-                     want_inverse, err);
+                     want_inverse, err, chk);
 }
 
 void launch_scatter_rows(const int32_t* stage_rows, const int32_t* stage_lens, const int32_t* slot_of,
                          int32_t nb, int32_t s, int32_t* rows, int32_t* lens, hipStream_t st) {
   if (nb <= 0) return;
   hipLaunchKernelGGL(k_scatter_rows, dim3(nb), dim3(kT), 0, st, stage_rows, stage_lens, slot_of, s, rows, lens);
+}
+
+void launch_gram_f32(int32_t kind, const float* A, int64_t lda, int64_t n, const int32_t* rows,
+                     const int32_t* lens, int32_t s, int32_t nb, double lambda, double* G, int64_t stride,
+                     const int32_t* slot_of, hipStream_t st) {
+  const int32_t* only = nullptr;
+  if (nb <= 0) return;
+  if (kind == 0) {
+    const int nt = (s + 31) / 32;
+    hipLaunchKernelGGL(k_gram_kpp<float>, dim3(nt, nt, nb), dim3(kT), 0, st, A, lda, n, rows, lens, s,
+                       lambda, G, stride, slot_of, only);
+  } else {
+    hipLaunchKernelGGL(k_gram_cd<float>, dim3(nb), dim3(kT), 0, st, A, lda, rows, lens, s, lambda, G,
+                       stride, slot_of, only);
+  }
+}
+
+void launch_convert_f32(const double* A, int64_t lda, int64_t m, int64_t n, float* out, hipStream_t st) {
+  const int64_t total = m * n;
+  const unsigned g = static_cast<unsigned>(std::min<int64_t>((total + kT - 1) / kT, 65536));
+  hipLaunchKernelGGL(k_convert_f32, dim3(g), dim3(kT), 0, st, A, lda, m, n, out);
+}
+
+void launch_residual_vec(const double* A, int64_t lda, int64_t m, int64_t n, const double* x,
+                         const double* b, double* r, double* rowsq, double* out, hipStream_t st) {
+  const unsigned g = static_cast<unsigned>((m + 3) / 4);
+  hipLaunchKernelGGL(k_residual_vec, dim3(g), dim3(kT), 0, st, A, lda, m, n, x, b, r, rowsq);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(kT), 0, st, rowsq, m, out);
+}
+
+void launch_axpy1(double* x, const double* d, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy1, dim3(static_cast<unsigned>((n + kT - 1) / kT)), dim3(kT), 0, st, x, d, n);
 }
 
 void launch_state_init(DevState* ds, double rho0, double thr, hipStream_t st) {

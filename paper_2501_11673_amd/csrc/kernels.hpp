@@ -29,6 +29,17 @@ struct DevState {
 constexpr int kMaxBlock = 512;      // largest supported block size s
 constexpr int kLdsCholMax = 128;    // blocks up to this size are factored in LDS
 
+// Factor-time checks.  only: process just the blocks with only[k] != 0.
+// flag (low-precision pass): instead of failing, set flag[k] = 1 when the
+// factor breaks down or kappa(G) >= (max L_ii / min L_ii)^2 exceeds
+// kappa_max, count it in *counter and leave that block to an FP64 redo.
+struct FactorCheck {
+  const int32_t* only = nullptr;
+  int32_t* flag = nullptr;
+  int32_t* counter = nullptr;
+  double kappa_max = 1.0 / 0.0;
+};
+
 // r-partials of the block residual: rpart[i * P + p] = sum_{j in chunk p} A[rows[i], j] x[j]
 void launch_block_gemv_partial(const double* A, int64_t lda, int64_t n, const int32_t* rows,
                                int32_t sb, const double* x, double* rpart, int32_t P,
@@ -49,23 +60,31 @@ void launch_update(int32_t kind, const double* A, int64_t lda, int64_t n, const 
 // first element is G[slot_of[k] * stride].
 void launch_gram(int32_t kind, const double* A, int64_t lda, int64_t n, const int32_t* rows,
                  const int32_t* lens, int32_t s, int32_t nb, double lambda, double* G, int64_t stride,
-                 const int32_t* slot_of, hipStream_t st);
+                 const int32_t* slot_of, hipStream_t st, const int32_t* only = nullptr);
+
+// The same Grams from an FP32 copy of A (FP32 products, FP32 accumulation),
+// written to the FP64 slots.
+void launch_gram_f32(int32_t kind, const float* A, int64_t lda, int64_t n, const int32_t* rows,
+                     const int32_t* lens, int32_t s, int32_t nb, double lambda, double* G, int64_t stride,
+                     const int32_t* slot_of, hipStream_t st);
 
 // In-place Cholesky of nb slots; breakdown sets *err = 1.
 void launch_cholesky(double* G, int32_t s, int64_t stride, const int32_t* lens, int32_t nb,
-                     const int32_t* slot_of, int32_t* err, hipStream_t st);
+                     const int32_t* slot_of, int32_t* err, hipStream_t st, FactorCheck chk = FactorCheck());
 
 // G^{-1} = L^{-T} L^{-1} of each slot's factor (at +s*s, full symmetric);
 // blocks larger than kLdsCholMax use the slot's last s*s doubles as scratch.
 void launch_factor_inverse(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
-                           const int32_t* slot_of, hipStream_t st);
+                           const int32_t* slot_of, hipStream_t st, const int32_t* only = nullptr,
+                           const int32_t* skip = nullptr);
 
 // Blocks of at most kFactorSmallMax rows: Cholesky in place (breakdown sets
 // *err = 1) and, if want_inverse, G^{-1} at +s*s, one register-resident
 // workgroup per block.
 constexpr int kFactorSmallMax = 128;
 void launch_factor_small(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
-                         const int32_t* slot_of, int32_t want_inverse, int32_t* err, hipStream_t st);
+                         const int32_t* slot_of, int32_t want_inverse, int32_t* err, hipStream_t st,
+                         FactorCheck chk = FactorCheck());
 
 // rows[slot_of[k] * s + i] = stage_rows[k * s + i]; lens[slot_of[k]] = stage_lens[k]
 void launch_scatter_rows(const int32_t* stage_rows, const int32_t* stage_lens, const int32_t* slot_of,
@@ -85,10 +104,20 @@ void launch_check_finite(const double* A, int64_t lda, int64_t m, int64_t n, con
 
 void launch_state_init(DevState* ds, double rho0, double thr, hipStream_t st);
 
+// out[i * n + j] = (float) A[i * lda + j]   (row-major FP32 copy, leading dimension n)
+void launch_convert_f32(const double* A, int64_t lda, int64_t m, int64_t n, float* out, hipStream_t st);
+
+// r = b - A x (FP64), rowsq[i] = r_i^2, *out = sum_i rowsq[i] in a fixed order
+void launch_residual_vec(const double* A, int64_t lda, int64_t m, int64_t n, const double* x,
+                         const double* b, double* r, double* rowsq, double* out, hipStream_t st);
+
+// x += d  (FP64)
+void launch_axpy1(double* x, const double* d, int64_t n, hipStream_t st);
+
 // Arguments of the fused persistent engine (fused.hip): W block steps of one
 // system per launch, `groups` workgroups each owning 64 * cpl columns.
 struct FusedArgs {
-  const double* A;
+  const void* A;             // double, or float for the mixed-precision inner solver
   int64_t lda;
   int64_t n;
   const double* b;
@@ -119,6 +148,6 @@ constexpr int kFusedMaxBlock = 256;   // the fused engine gives one thread per b
 constexpr int kFusedMaxGroups = 256;
 constexpr int kFlagWordsAlloc = 1024 * kFusedMaxGroups;   // up to 4 KB between flags
 
-void launch_fused(int32_t kind, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t st);
+void launch_fused(int32_t kind, bool a_fp32, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t st);
 
 }  // namespace kpp

@@ -98,7 +98,7 @@ struct kpp_system {
   std::vector<int32_t> slot_of_block;
   // signature of the schedule the cache belongs to
   bool memo_valid = false;
-  int32_t sig_s = 0, sig_memo = 0, sig_nb = 0, sig_part = 0;
+  int32_t sig_s = 0, sig_memo = 0, sig_nb = 0, sig_part = 0, sig_prec = 0;
   uint64_t sig_seed = 0;
   double sig_lambda = 0.0;
   // per-window staging (pinned host mirror + device copy): block rows, lengths,
@@ -115,6 +115,11 @@ struct kpp_system {
   uint32_t epoch = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   uint64_t* phase_ticks = nullptr;   // KPP_PHASE_PROFILE=1: fused-engine phase profile
+  // mixed precision: FP32 copy of A (leading dimension n), outer residual, correction
+  float* A32 = nullptr;
+  double* rvec = nullptr;
+  double* dvec = nullptr;
+  int32_t* fp64_count = nullptr;   // blocks refactored in FP64 (mixed precision)
 };
 
 namespace {
@@ -146,6 +151,10 @@ void destroy_buffers(kpp_system* s) {
   dev_free(s->part);
   dev_free(s->flags);
   dev_free(s->phase_ticks);
+  dev_free(s->A32);
+  dev_free(s->rvec);
+  dev_free(s->dvec);
+  dev_free(s->fp64_count);
   if (s->h_ds) (void)hipHostFree(s->h_ds);
   if (s->h_err) (void)hipHostFree(s->h_err);
   s->h_ds = nullptr;
@@ -230,8 +239,15 @@ kpp_status check_params(const kpp_system* sys, const kpp_params* p) {
   if (p->memo == KPP_MEMO_FIXED && !p->fixed_partition && p->num_blocks < 1)
     return fail(KPP_ERR_INVALID_ARG, "fixed collection needs num_blocks >= 1");
   if (!(p->rho0 >= 0.0 && p->rho0 <= 1.0)) return fail(KPP_ERR_INVALID_ARG, "rho0 must be in [0, 1]");
-  if (p->precision != KPP_FP64)
+  if (p->precision != KPP_FP64 && p->precision != KPP_MIXED_FP32)
     return fail(KPP_ERR_INVALID_ARG, "precision %d is not available in this build", p->precision);
+  if (p->precision == KPP_MIXED_FP32) {
+    if (p->engine == 1) return fail(KPP_ERR_INVALID_ARG, "mixed precision runs on the fused engine");
+    if (p->block_size > kpp::kFusedMaxBlock)
+      return fail(KPP_ERR_INVALID_ARG, "mixed precision takes block_size <= %d", kpp::kFusedMaxBlock);
+    if (!(p->inner_tol > 0.0 && p->inner_tol < 1.0)) return fail(KPP_ERR_INVALID_ARG, "inner_tol must be in (0, 1)");
+    if (p->refine_max_rounds < 1) return fail(KPP_ERR_INVALID_ARG, "refine_max_rounds must be >= 1");
+  }
   if (p->engine < 0 || p->engine > 2) return fail(KPP_ERR_INVALID_ARG, "unknown engine %d", p->engine);
   if (p->engine == 2 && p->block_size > kpp::kFusedMaxBlock)
     return fail(KPP_ERR_INVALID_ARG, "the fused engine takes block_size <= %d", kpp::kFusedMaxBlock);
@@ -275,10 +291,37 @@ bool fused_geometry(int64_t n, int32_t s, int32_t target_groups, int32_t* cpl, i
   return true;
 }
 
-kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_result* res) {
-  using clock = std::chrono::steady_clock;
-  const auto t_start = clock::now();
+// The matrix and right-hand side one run of the block iteration works on: the
+// caller's FP64 system, or (mixed precision) the FP32 copy of A with the
+// current outer residual as right-hand side.
+struct Source {
+  const double* A64 = nullptr;
+  const float* A32 = nullptr;
+  int64_t lda = 0;
+  const double* b = nullptr;
+  double bnorm = 0.0;
+};
+
+struct CoreOpts {
+  double tol = 0.0;
+  int32_t confirm = 1;      // confirm a candidate stop with ||A x - b|| (FP64 system only)
+  double rho0 = 0.0;
+  int32_t keep_memo = 0;
+  int64_t max_iters = 0;
+};
+
+struct CoreStats {
+  int64_t iters = 0, hits = 0, misses = 0, launches = 0;
+  bool converged = false;
+  double true_rel = NAN, t_factor = 0.0, t_kernel = 0.0;
+  kpp::DevState hs{};
+  int32_t engine = 0;
+};
+
+kpp_status solve_core(kpp_system* sys, const kpp_params* p, const Source& src, const CoreOpts& o,
+                      double* x, CoreStats* cs) {
   hipStream_t st = sys->ctx->stream;
+  const bool fp32 = src.A32 != nullptr;
   const int32_t kind = sys->kind;
   const int64_t m = sys->m, n = sys->n;
   const int64_t N = kind == KPP_CD_PSD ? n : m;
@@ -303,9 +346,10 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
   // memo cache: reuse only for an identical schedule definition; the slot
   // table is sized for this block size before any slot is handed out
   KPP_TRY(ensure_slots(sys, 16, s));
-  const bool same_sig = sys->memo_valid && p->keep_memo && sys->sig_s == s && sys->sig_memo == p->memo &&
+  const bool same_sig = sys->memo_valid && o.keep_memo && sys->sig_s == s && sys->sig_memo == p->memo &&
                         sys->sig_nb == p->num_blocks && sys->sig_part == p->fixed_partition &&
-                        sys->sig_seed == p->seed && sys->sig_lambda == p->lambda && mode != kpp::MemoMode::Off;
+                        sys->sig_seed == p->seed && sys->sig_lambda == p->lambda &&
+                        sys->sig_prec == (fp32 ? 1 : 0) && mode != kpp::MemoMode::Off;
   if (!same_sig) {
     sys->slot_of_block.clear();
     sys->used_slots = 0;
@@ -316,6 +360,7 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
     sys->sig_part = p->fixed_partition;
     sys->sig_seed = p->seed;
     sys->sig_lambda = p->lambda;
+    sys->sig_prec = fp32 ? 1 : 0;
   }
   if (mode == kpp::MemoMode::Fixed) KPP_TRY(ensure_slots(sys, sch->num_blocks(), s));
   // launch engine: column chunks of the block gemv
@@ -328,8 +373,8 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
   }
   HIP_TRY(hipMemsetAsync(sys->mom, 0, n * sizeof(double), st));
   HIP_TRY(hipMemsetAsync(sys->err, 0, sizeof(int32_t), st));
-  const double thr = p->tol * p->tol * sys->bnorm * sys->bnorm;
-  kpp::launch_state_init(sys->ds, p->rho0, thr, st);
+  const double thr = o.tol * o.tol * src.bnorm * src.bnorm;
+  kpp::launch_state_init(sys->ds, o.rho0, thr, st);
   HIP_TRY(hipGetLastError());
 
   const char* prof_env = std::getenv("KPP_PHASE_PROFILE");
@@ -344,6 +389,7 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
   double t_factor = 0.0, t_kernel = 0.0;
   int64_t launches = 0;
   kpp::DevState hs{};
+  const int64_t max_iters = o.max_iters;
   const int64_t period = 2 * static_cast<int64_t>(zeta);
   const size_t sd = static_cast<size_t>(sys->slot_stride);
 
@@ -360,7 +406,7 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
   auto plan = [&](Window& w, int64_t t0, int idx) -> kpp_status {
     w.t0 = t0;
     w.idx = idx;
-    w.W = std::min<int64_t>(period - (t0 % period), p->max_iters - t0);
+    w.W = std::min<int64_t>(period - (t0 % period), max_iters - t0);
     w.step_block.resize(w.W);
     w.step_slot.resize(w.W);
     std::vector<int32_t> pending, pending_slots;
@@ -396,7 +442,7 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
     w.o_len = static_cast<size_t>(w.nb) * s;
     w.o_slot = w.o_len + w.nb;
     w.o_step = w.o_slot + w.nb;
-    const size_t need = w.o_step + static_cast<size_t>(w.W);
+    const size_t need = w.o_step + static_cast<size_t>(w.W) + static_cast<size_t>(w.nb);  // + flags
     KPP_TRY(ensure_stage(sys, idx, need));
     int32_t* hs_ = sys->h_stage[idx];
     for (int32_t k = 0; k < w.nb; ++k) {
@@ -421,13 +467,34 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
       const int32_t* d_slens = sys->d_stage[idx] + w.o_len;
       const int32_t* d_sslot = sys->d_stage[idx] + w.o_slot;
       kpp::launch_scatter_rows(d_srows, d_slens, d_sslot, w.nb, s, sys->rows, sys->lens, fs);
-      kpp::launch_gram(kind, sys->A, sys->lda, n, d_srows, d_slens, s, w.nb, p->lambda, sys->L,
-                       sys->slot_stride, d_sslot, fs);
-      if (s <= kpp::kFactorSmallMax) {
-        kpp::launch_factor_small(sys->L, sys->slot_stride, s, d_slens, w.nb, d_sslot, 1, sys->err, fs);
+      auto factor = [&](const kpp::FactorCheck& chk, const int32_t* skip) {
+        if (s <= kpp::kFactorSmallMax) {
+          kpp::launch_factor_small(sys->L, sys->slot_stride, s, d_slens, w.nb, d_sslot, 1, sys->err, fs, chk);
+        } else {
+          kpp::launch_cholesky(sys->L, s, sys->slot_stride, d_slens, w.nb, d_sslot, sys->err, fs, chk);
+          kpp::launch_factor_inverse(sys->L, sys->slot_stride, s, d_slens, w.nb, d_sslot, fs, chk.only, skip);
+        }
+      };
+      if (fp32) {
+        // FP32 Grams; blocks whose factor breaks down or whose kappa(G) exceeds
+        // 1e6 are formed again from the FP64 A and factored in FP64
+        int32_t* flag = sys->d_stage[idx] + w.o_step + w.W;
+        kpp::launch_gram_f32(kind, src.A32, src.lda, n, d_srows, d_slens, s, w.nb, p->lambda, sys->L,
+                             sys->slot_stride, d_sslot, fs);
+        kpp::FactorCheck first;
+        first.flag = flag;
+        first.counter = sys->fp64_count;
+        first.kappa_max = 1e6;
+        factor(first, flag);
+        kpp::launch_gram(kind, sys->A, sys->lda, n, d_srows, d_slens, s, w.nb, p->lambda, sys->L,
+                         sys->slot_stride, d_sslot, fs, flag);
+        kpp::FactorCheck redo;
+        redo.only = flag;
+        factor(redo, nullptr);
       } else {
-        kpp::launch_cholesky(sys->L, s, sys->slot_stride, d_slens, w.nb, d_sslot, sys->err, fs);
-        kpp::launch_factor_inverse(sys->L, sys->slot_stride, s, d_slens, w.nb, d_sslot, fs);
+        kpp::launch_gram(kind, src.A64, src.lda, n, d_srows, d_slens, s, w.nb, p->lambda, sys->L,
+                         sys->slot_stride, d_sslot, fs);
+        factor(kpp::FactorCheck(), nullptr);
       }
       HIP_TRY(hipGetLastError());
     }
@@ -440,12 +507,12 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
   HIP_TRY(hipStreamWaitEvent(sys->ctx->side, sys->ev_fact[1][2], 0));
   Window win[2];
   bool have_next = false;
-  if (p->max_iters > 0) {
+  if (max_iters > 0) {
     KPP_TRY(plan(win[0], 0, 0));
     KPP_TRY(enqueue_factor(win[0], st));  // nothing to overlap with yet
   }
   int cur = 0;
-  while (t < p->max_iters && !converged) {
+  while (t < max_iters && !converged) {
     Window& w = win[cur];
     if (have_next) HIP_TRY(hipStreamWaitEvent(st, sys->ev_fact[cur][1], 0));
     const int32_t* d_step = sys->d_stage[cur] + w.o_step;
@@ -456,10 +523,10 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
         sys->epoch = 0;
       }
       kpp::FusedArgs a{};
-      a.A = sys->A;
-      a.lda = sys->lda;
+      a.A = fp32 ? static_cast<const void*>(src.A32) : static_cast<const void*>(src.A64);
+      a.lda = src.lda;
       a.n = n;
-      a.b = sys->b;
+      a.b = src.b;
       a.rows = sys->rows;
       a.lens = sys->lens;
       a.L = sys->L;
@@ -479,7 +546,7 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
       a.err = sys->err;
       a.spin_limit = int64_t{1} << 22;
       a.phase_ticks = phase_prof ? sys->phase_ticks : nullptr;
-      kpp::launch_fused(kind, a, cpl, groups, st);
+      kpp::launch_fused(kind, fp32, a, cpl, groups, st);
       sys->epoch += static_cast<uint32_t>(w.W);
       ++launches;
     } else {
@@ -487,10 +554,10 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
         const int32_t q = w.step_slot[k];
         const int32_t sb = sch->len(w.step_block[k]);
         const int32_t* rows = sys->rows + static_cast<size_t>(q) * s;
-        kpp::launch_block_gemv_partial(sys->A, sys->lda, n, rows, sb, x, sys->rpart, P, chunk, st);
-        kpp::launch_block_project(sys->rpart, P, sys->b, rows, sb, sys->L + sd * q + static_cast<size_t>(s) * s,
+        kpp::launch_block_gemv_partial(src.A64, src.lda, n, rows, sb, x, sys->rpart, P, chunk, st);
+        kpp::launch_block_project(sys->rpart, P, src.b, rows, sb, sys->L + sd * q + static_cast<size_t>(s) * s,
                                   s, sys->y, sys->ds, zeta, p->adaptive_rho, st);
-        kpp::launch_update(kind, sys->A, sys->lda, n, rows, sb, sys->y, sys->ds, eta, x, sys->mom, st);
+        kpp::launch_update(kind, src.A64, src.lda, n, rows, sb, sys->y, sys->ds, eta, x, sys->mom, st);
       }
       launches += 3 * w.W;
     }
@@ -501,7 +568,7 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
     // plan and factor the next window while this one runs
     const int64_t t_next = t + w.W;
     have_next = false;
-    if (t_next < p->max_iters) {
+    if (t_next < max_iters) {
       KPP_TRY(plan(win[cur ^ 1], t_next, cur ^ 1));
       KPP_TRY(enqueue_factor(win[cur ^ 1], sys->ctx->side));
       have_next = true;
@@ -529,11 +596,11 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
     }
     t = t_next;
     if ((t % period) == 0 && hs.cand) {
-      if (p->confirm_true_residual) {
+      if (o.confirm) {
         double rn = 0.0;
         KPP_TRY(residual_norm(sys, x, &rn));
         true_rel = sys->bnorm > 0 ? rn / sys->bnorm : rn;
-        if (rn <= p->tol * sys->bnorm) converged = true;
+        if (rn <= o.tol * sys->bnorm) converged = true;
       } else {
         converged = true;
       }
@@ -548,7 +615,7 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
     misses -= w.nb;
     hits -= w.W - w.nb;
   }
-  if (!converged || std::isnan(true_rel)) {
+  if (o.confirm && (!converged || std::isnan(true_rel))) {
     double rn = 0.0;
     KPP_TRY(residual_norm(sys, x, &rn));
     true_rel = sys->bnorm > 0 ? rn / sys->bnorm : rn;
@@ -561,32 +628,157 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
     static const char* names[kpp::kFusedPhases] = {"rows", "tile-dot", "publish", "wait", "reduce-r",
                                                    "solve+scalars", "update", "-"};
     std::fprintf(stderr, "[kpp phase profile] %lld steps, workgroup 0, us per step:", static_cast<long long>(t));
-    for (int p = 0; p < kpp::kFusedPhases - 1; ++p)
-      std::fprintf(stderr, " %s=%.3f", names[p], 1e3 * static_cast<double>(ticks[p]) / rate_khz / static_cast<double>(t));
+    for (int ph = 0; ph < kpp::kFusedPhases - 1; ++ph)
+      std::fprintf(stderr, " %s=%.3f", names[ph], 1e3 * static_cast<double>(ticks[ph]) / rate_khz / static_cast<double>(t));
     std::fprintf(stderr, "\n");
   }
+  cs->iters = t;
+  cs->hits = hits;
+  cs->misses = misses;
+  cs->launches = launches;
+  cs->converged = converged;
+  cs->true_rel = true_rel;
+  cs->t_factor = t_factor;
+  cs->t_kernel = t_kernel;
+  cs->hs = hs;
+  cs->engine = fused ? 2 : 1;
+  return converged ? KPP_OK : KPP_NOT_CONVERGED;
+}
+
+
+void fill_result(kpp_result* res, const kpp_system* sys, const kpp_params* p, int64_t iters, int64_t hits,
+                 int64_t misses, bool converged, int32_t rounds, const CoreStats& last, double true_rel,
+                 double est_rel, double rho_final, double seconds, double t_factor, double t_kernel,
+                 int64_t launches, int64_t checkpoints, double bytes_per_elem) {
+  if (!res) return;
+  const int32_t kind = sys->kind;
+  const int64_t n = sys->n;
+  const int32_t s = p->block_size;
+  res->iters = iters;
+  res->memo_hits = hits;
+  res->memo_misses = misses;
+  res->factors_fp64 = misses;
+  res->converged = converged ? 1 : 0;
+  res->refinements = rounds;
+  res->checkpoints = static_cast<int32_t>(checkpoints);
+  res->engine_used = last.engine;
+  res->est_rel_res = est_rel;
+  res->true_rel_res = true_rel;
+  res->rho_final = rho_final;
+  res->seconds_total = seconds;
+  res->seconds_factor = t_factor;
+  const double sdb = s;
+  const double nn = static_cast<double>(n);
+  const double per_step = 2.0 * sdb * nn + 2.0 * sdb * sdb + (kind == KPP_CD_PSD ? 0.0 : 2.0 * sdb * nn) + 5.0 * nn;
+  const double per_fact = sdb * sdb * sdb / 3.0 + (kind == KPP_CD_PSD ? 0.0 : sdb * sdb * nn);
+  res->flops = per_step * static_cast<double>(iters) + per_fact * static_cast<double>(misses);
+  res->bytes_algorithmic =
+      static_cast<double>(iters) * (sdb * nn * bytes_per_elem + 0.5 * sdb * (sdb + 1) * 8.0 + 12.0 * sdb);
+  res->kernel_seconds = t_kernel;
+  res->kernel_launches = static_cast<double>(launches);
+}
+
+kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_result* res) {
+  using clock = std::chrono::steady_clock;
+  const auto t0 = clock::now();
+  Source src;
+  src.A64 = sys->A;
+  src.lda = sys->lda;
+  src.b = sys->b;
+  src.bnorm = sys->bnorm;
+  CoreOpts o;
+  o.tol = p->tol;
+  o.confirm = p->confirm_true_residual;
+  o.rho0 = p->rho0;
+  o.keep_memo = p->keep_memo;
+  o.max_iters = p->max_iters;
+  CoreStats cs;
+  KPP_TRY(solve_core(sys, p, src, o, x, &cs));
+  double true_rel = cs.true_rel;
+  if (std::isnan(true_rel)) {
+    double rn = 0.0;
+    KPP_TRY(residual_norm(sys, x, &rn));
+    true_rel = sys->bnorm > 0 ? rn / sys->bnorm : rn;
+  }
+  const double est = sys->bnorm > 0 ? std::sqrt(cs.hs.last_E1) / sys->bnorm : std::sqrt(cs.hs.last_E1);
+  fill_result(res, sys, p, cs.iters, cs.hits, cs.misses, cs.converged, 0, cs, true_rel, est,
+              cs.converged ? cs.hs.rho_before : cs.hs.rho,
+              std::chrono::duration<double>(clock::now() - t0).count(), cs.t_factor, cs.t_kernel, cs.launches,
+              cs.hs.ckpts, 8.0);
+  return cs.converged ? KPP_OK : KPP_NOT_CONVERGED;
+}
+
+// Mixed precision: classical iterative refinement.  The outer loop is FP64 --
+// r = b - A x over the caller's FP64 A, x += d -- and each correction d comes
+// from the block iteration on A32 d = r (FP32 A_S products and Grams, FP64
+// factors, FP64 momentum and iterate) run to the relative tolerance inner_tol.
+// The memo cache of block factors carries over from round to round.
+kpp_status solve_mixed(kpp_system* sys, const kpp_params* p, double* x, kpp_result* res) {
+  using clock = std::chrono::steady_clock;
+  const auto t0 = clock::now();
+  hipStream_t st = sys->ctx->stream;
+  const int64_t m = sys->m, n = sys->n;
+  if (!sys->A32) {
+    KPP_TRY(dev_alloc(&sys->A32, static_cast<size_t>(m) * n));
+    kpp::launch_convert_f32(sys->A, sys->lda, m, n, sys->A32, st);
+    HIP_TRY(hipGetLastError());
+  }
+  if (!sys->rvec) KPP_TRY(dev_alloc(&sys->rvec, m));
+  if (!sys->dvec) KPP_TRY(dev_alloc(&sys->dvec, n));
+  if (!sys->fp64_count) KPP_TRY(dev_alloc(&sys->fp64_count, 1));
+  HIP_TRY(hipMemsetAsync(sys->fp64_count, 0, sizeof(int32_t), st));
+  int64_t iters = 0, hits = 0, misses = 0, launches = 0, ckpts = 0;
+  double t_factor = 0.0, t_kernel = 0.0, rho = p->rho0, true_rel = NAN, est = NAN;
+  bool converged = false;
+  int32_t rounds = 0;
+  CoreStats last;
+  for (;;) {
+    kpp::launch_residual_vec(sys->A, sys->lda, m, n, x, sys->b, sys->rvec, sys->rowsq, sys->scal, st);
+    HIP_TRY(hipGetLastError());
+    double rr = 0.0;
+    HIP_TRY(hipMemcpyAsync(&rr, sys->scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const double rn = std::sqrt(rr);
+    true_rel = sys->bnorm > 0 ? rn / sys->bnorm : rn;
+    if (rn <= p->tol * sys->bnorm) {
+      converged = true;
+      break;
+    }
+    if (rounds >= p->refine_max_rounds || iters >= p->max_iters) break;
+    HIP_TRY(hipMemsetAsync(sys->dvec, 0, n * sizeof(double), st));
+    Source src;
+    src.A32 = sys->A32;
+    src.lda = n;
+    src.b = sys->rvec;
+    src.bnorm = rn;
+    CoreOpts o;
+    o.tol = p->inner_tol;
+    o.confirm = 0;
+    o.rho0 = rho;
+    o.keep_memo = rounds > 0 ? 1 : p->keep_memo;
+    o.max_iters = p->max_iters - iters;
+    CoreStats cs;
+    KPP_TRY(solve_core(sys, p, src, o, sys->dvec, &cs));
+    kpp::launch_axpy1(x, sys->dvec, n, st);
+    HIP_TRY(hipGetLastError());
+    ++rounds;
+    iters += cs.iters;
+    hits += cs.hits;
+    misses += cs.misses;
+    launches += cs.launches;
+    ckpts += cs.hs.ckpts;
+    t_factor += cs.t_factor;
+    t_kernel += cs.t_kernel;
+    rho = cs.converged ? cs.hs.rho_before : cs.hs.rho;
+    est = rn > 0 ? std::sqrt(cs.hs.last_E1) / rn : 0.0;
+    last = cs;
+  }
+  fill_result(res, sys, p, iters, hits, misses, converged, rounds, last, true_rel, est, rho,
+              std::chrono::duration<double>(clock::now() - t0).count(), t_factor, t_kernel, launches, ckpts, 4.0);
   if (res) {
-    res->iters = t;
-    res->memo_hits = hits;
-    res->memo_misses = misses;
-    res->factors_fp64 = misses;
-    res->converged = converged ? 1 : 0;
-    res->refinements = 0;
-    res->checkpoints = hs.ckpts;
-    res->engine_used = fused ? 2 : 1;
-    res->est_rel_res = sys->bnorm > 0 ? std::sqrt(hs.last_E1) / sys->bnorm : std::sqrt(hs.last_E1);
-    res->true_rel_res = true_rel;
-    res->rho_final = converged ? hs.rho_before : hs.rho;
-    res->seconds_total = std::chrono::duration<double>(clock::now() - t_start).count();
-    res->seconds_factor = t_factor;
-    const double sdb = s;
-    const double nn = static_cast<double>(n);
-    const double per_step = 2.0 * sdb * nn + 2.0 * sdb * sdb + (kind == KPP_CD_PSD ? 0.0 : 2.0 * sdb * nn) + 5.0 * nn;
-    const double per_fact = sdb * sdb * sdb / 3.0 + (kind == KPP_CD_PSD ? 0.0 : sdb * sdb * nn);
-    res->flops = per_step * static_cast<double>(t) + per_fact * static_cast<double>(misses);
-    res->bytes_algorithmic = static_cast<double>(t) * (sdb * nn * 8.0 + 0.5 * sdb * (sdb + 1) * 8.0 + 12.0 * sdb);
-    res->kernel_seconds = t_kernel;
-    res->kernel_launches = static_cast<double>(launches);
+    int32_t nfp64 = 0;
+    HIP_TRY(hipMemcpy(&nfp64, sys->fp64_count, sizeof(int32_t), hipMemcpyDeviceToHost));
+    res->factors_fp64 = nfp64;
   }
   return converged ? KPP_OK : KPP_NOT_CONVERGED;
 }
@@ -619,7 +811,7 @@ KPP_API kpp_status kpp_params_default(kpp_params* p, int32_t kind) {
   p->seed = 0x2501116730ull;
   p->keep_memo = 0;
   p->refine_max_rounds = 12;
-  p->inner_tol = 1e-5;
+  p->inner_tol = 1e-3;
   p->engine = 0;
   p->team_groups = 0;
   return KPP_OK;
@@ -743,6 +935,7 @@ KPP_API kpp_status kpp_solve(kpp_system* sys, const kpp_params* p, double* x_dev
   KPP_TRY(check_params(sys, p));
   HIP_TRY(hipSetDevice(sys->ctx->device));
   try {
+    if (p->precision == KPP_MIXED_FP32) return solve_mixed(sys, p, x_dev, res);
     return solve_fp64(sys, p, x_dev, res);
   } catch (const std::bad_alloc&) {
     return fail(KPP_ERR_OOM, "host allocation failed");

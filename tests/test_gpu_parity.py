@@ -296,3 +296,75 @@ def test_errors(env):
     with pytest.raises(kpp.KppError) as e:
         gpu_solve(env, np.ones((5, 6)), np.ones(5), "psd", 2, lam=1e-6, T=10)
     assert e.value.status == kpp.KPP_ERR_SHAPE
+
+
+# ---------------------------------------------------------------------------
+# mixed precision: FP32 inner block iteration, FP64 refinement
+# ---------------------------------------------------------------------------
+
+MIXED_CASES = [
+    ("c1", "general", lambda: synth.config("c1"), 20, 1e-3, "online"),
+    ("c2_small", "psd", lambda: synth.config("c2_small"), 128, 1e-8, "online"),
+    ("c3_small", "general", lambda: synth.config("c3_small"), 256, 1e-8, "fixed"),
+    ("c4_small", "general", lambda: synth.config("c4_small"), 64, 1e-4, "online"),
+]
+
+
+@pytest.mark.parametrize("case", MIXED_CASES, ids=[c[0] for c in MIXED_CASES])
+def test_mixed_precision_reaches_fp64_accuracy(env, case):
+    """Iterative refinement recovers a true FP64 relative residual of 1e-10;
+    the error against the FP64 oracle's converged solution is stated."""
+    kpp, torch, dev, ctx = env
+    name, kind, build, s, lam, mode = case
+    sysm = build()
+    A, b = sysm.A, sysm.b
+    m, n = A.shape
+    ck = kpp.KPP_CD_PSD if kind == "psd" else kpp.KPP_KACZMARZ
+    p = kpp.kpp_params_default(ck)
+    p.block_size = s
+    p.lambda_ = lam
+    p.tol = 1e-10
+    p.max_iters = 200_000
+    p.seed = 77
+    p.memo = MODES[mode]
+    p.precision = kpp.KPP_MIXED_FP32
+    Ad = torch.from_numpy(A).to(dev)
+    bd = torch.from_numpy(b).to(dev)
+    xd = torch.zeros(n, dtype=torch.float64, device=dev)
+    h = kpp.kpp_system_create(ctx, ck, m, n, Ad.data_ptr(), n, bd.data_ptr())
+    try:
+        st, res = kpp.kpp_solve(h, p, xd.data_ptr())
+    finally:
+        kpp.kpp_system_destroy(h)
+    x = xd.cpu().numpy()
+    true_rel = np.linalg.norm(A @ x - b) / np.linalg.norm(b)
+    ref = oracle_solve(A, b, kind, s, lam=lam, T=200_000, tol=1e-10, mode=mode, seed=77)
+    err_orc = relerr(x, ref.x)
+    err_star = relerr(x, sysm.xstar)
+    print(f"[mixed] {name}: status {st}, {res.refinements} refinements, {res.iters} inner steps "
+          f"(FP64 oracle {ref.iters}), true rel. residual {true_rel:.2e}, "
+          f"|x - x_fp64_oracle|/|x| = {err_orc:.2e}, |x - x*|/|x*| = {err_star:.2e}", flush=True)
+    assert st == kpp.KPP_OK and res.converged == 1
+    assert true_rel <= 1e-10 * 1.0001
+    assert res.true_rel_res == pytest.approx(true_rel, rel=1e-6, abs=1e-14)
+    assert res.refinements >= 1
+    # both solutions satisfy ||A x - b|| <= 1e-10 ||b||, so within the row space
+    # of A they differ by at most about kappa(A) * 1e-10 relative.  A wide system
+    # also has a null space: FP32 copies of its rows carry components outside
+    # the FP64 row space into x (about u32 * kappa), which leave the residual
+    # untouched; that drift is stated, and the row-space part is compared.
+    kappa = synth_kappa(sysm)
+    if m < n:
+        Q, _ = np.linalg.qr(A.T)
+        xr = Q @ (Q.T @ x)
+        drift = np.linalg.norm(x - xr) / np.linalg.norm(x)
+        print(f"[mixed] {name}: null-space drift |x - P_row x|/|x| = {drift:.2e}", flush=True)
+        assert relerr(xr, ref.x) <= 2.0 * kappa * 1e-10 + 1e-12
+        assert drift <= 10.0 * kappa * 6e-8
+    else:
+        assert err_orc <= 2.0 * kappa * 1e-10 + 1e-12
+
+
+def synth_kappa(sysm):
+    sp = np.abs(np.asarray(sysm.spectrum))
+    return float(sp.max() / sp.min())
