@@ -10,6 +10,8 @@ resident in HBM before the timed region.
 One "step" is one full solve from x0 = 0 with an empty memo cache (every
 factorization is paid inside the timed region).  value = block steps per
 second over the timed solves; ms_per_step = time to tolerance per solve.
+The same solves are then timed with mixed precision (FP32 block products,
+FP64 factors and iterative refinement) and reported under "mixed".
 
 Also printed: the roofline of the dominant kernel (the step kernel, timed with
 HIP events inside the library on the stream it runs on) and the CPU oracle
@@ -160,6 +162,43 @@ def main():
         "factor_ms_per_solve": 1e3 * last.seconds_factor,
         "kernel_ms_per_solve": 1e3 * ktime / args.steps,
         "roofline": roofline,
+    }
+    # the same workload with mixed precision (FP32 block products, FP64 refinement)
+    x_fp64 = x.clone()
+    pm = kpp.kpp_params_default(kpp.KPP_CD_PSD)
+    for f, _ in kpp.kpp_params._fields_:
+        setattr(pm, f, getattr(p, f))
+    pm.precision = kpp.KPP_MIXED_FP32
+    pm.engine = 0
+
+    def one_mixed():
+        x.zero_()
+        return kpp.kpp_solve(h, pm, x.data_ptr())
+
+    for _ in range(args.warmup):
+        one_mixed()
+    torch.cuda.synchronize()
+    mres = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        mres.append(one_mixed())
+    torch.cuda.synchronize()
+    melapsed = time.perf_counter() - t0
+    miters = sum(r.iters for _, r in mres)
+    mlast = mres[-1][1]
+    line["mixed"] = {
+        "time_to_tol_ms": 1e3 * melapsed / args.steps,
+        "block_iters_per_s": miters / melapsed,
+        "iters_per_solve": miters / args.steps,
+        "refinements": mlast.refinements,
+        "converged": all(st == kpp.KPP_OK and r.converged for st, r in mres),
+        "true_rel_res": mlast.true_rel_res,
+        "rel_diff_vs_fp64_solution": float(torch.linalg.norm(x - x_fp64) / torch.linalg.norm(x_fp64)),
+        "rel_err_vs_planted": float(torch.linalg.norm(x - sysm.xstar) / torch.linalg.norm(sysm.xstar)),
+        "factorizations_per_solve": mlast.memo_misses,
+        "factors_redone_fp64": mlast.factors_fp64,
+        "kernel_ms_per_solve": 1e3 * sum(r.kernel_seconds for _, r in mres) / args.steps,
+        "speedup_vs_fp64": (1e3 * elapsed / args.steps) / (1e3 * melapsed / args.steps),
     }
     kpp.kpp_system_destroy(h)
     kpp.kpp_context_destroy(ctx)

@@ -177,21 +177,27 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
     TA xt[CPL];
 #pragma unroll
     for (int e = 0; e < CPL; ++e) xt[e] = static_cast<TA>(xr[e]);
-    TA v[RMAX];
+    // the lane's products are summed in TA, the sums across lanes in FP64.
+    // The pair (v[r], v[r + cnt/2]) passes through an empty asm statement:
+    // otherwise the compiler may fold the two selects into one indexed read of
+    // v, which it lowers to a chain of compares over the whole array.
+    double v[RMAX];
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) {
       TA acc = 0;
 #pragma unroll
       for (int e = 0; e < CPL; ++e) acc = fma(tile[r * CPL + e], xt[e], acc);
-      v[r] = acc;
+      v[r] = static_cast<double>(acc);
     }
 #pragma unroll
     for (int cnt = RMAX, o = 32; cnt > 1; cnt >>= 1, o >>= 1) {
       const bool up = (lane & o) != 0;
 #pragma unroll
       for (int r = 0; r < cnt / 2; ++r) {
-        const TA send = up ? v[r] : v[r + cnt / 2];
-        const TA keep = up ? v[r + cnt / 2] : v[r];
+        double lo = v[r], hi = v[r + cnt / 2];
+        asm("" : "+v"(lo), "+v"(hi));
+        const double send = up ? lo : hi;
+        const double keep = up ? hi : lo;
         v[r] = keep + __shfl_xor(send, o, 64);
       }
     }
@@ -199,7 +205,7 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
     for (int o = 32 / RMAX; o >= 1; o >>= 1) v[0] += __shfl_xor(v[0], o, 64);
     {
       const int row = wv + 4 * (lane >> RSHIFT);
-      if ((lane & ((1 << RSHIFT) - 1)) == 0 && row < sb) stage[row] = static_cast<double>(v[0]);
+      if ((lane & ((1 << RSHIFT) - 1)) == 0 && row < sb) stage[row] = v[0];
     }
     __syncthreads();
     KPP_MARK(1)
