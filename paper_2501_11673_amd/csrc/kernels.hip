@@ -163,60 +163,6 @@ __global__ __launch_bounds__(kT) void k_update(const double* __restrict__ A, int
 // memo miss: regularized Grams (lower part, column-major slots)
 // --------------------------------------------------------------------------
 template <typename TA>
-__global__ __launch_bounds__(kT) void k_gram_kpp(const TA* __restrict__ A, int64_t lda,
-                                                 int64_t n, const int32_t* __restrict__ rows,
-                                                 const int32_t* __restrict__ lens, int32_t s,
-                                                 double lambda, double* __restrict__ G, int64_t stride,
-                                                 const int32_t* __restrict__ slot_of,
-                                                 const int32_t* __restrict__ only) {
-  __shared__ TA As[32][33];
-  __shared__ TA Bs[32][33];
-  const int blk = blockIdx.z;
-  if (only && !only[blk]) return;
-  const int sb = lens[blk];
-  const int ti = blockIdx.x, tk = blockIdx.y;
-  const int i0 = ti * 32, k0 = tk * 32;
-  if (ti < tk || i0 >= sb || k0 >= sb) return;  // uniform over the workgroup
-  const int32_t* R = rows + static_cast<int64_t>(blk) * s;
-  double* Gb = G + static_cast<int64_t>(slot_of[blk]) * stride;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  TA a00 = 0, a01 = 0, a10 = 0, a11 = 0;
-  for (int64_t j0 = 0; j0 < n; j0 += 32) {
-    for (int e = threadIdx.x; e < 1024; e += kT) {
-      const int rr = e >> 5, cc = e & 31;
-      const int64_t j = j0 + cc;
-      TA va = 0, vb = 0;
-      if (j < n) {
-        if (i0 + rr < sb) va = A[static_cast<int64_t>(R[i0 + rr]) * lda + j];
-        if (k0 + rr < sb) vb = A[static_cast<int64_t>(R[k0 + rr]) * lda + j];
-      }
-      As[rr][cc] = va;
-      Bs[rr][cc] = vb;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int cc = 0; cc < 32; ++cc) {
-      const TA p0 = As[ty * 2][cc], p1 = As[ty * 2 + 1][cc];
-      const TA q0 = Bs[tx * 2][cc], q1 = Bs[tx * 2 + 1][cc];
-      a00 = fma(p0, q0, a00);
-      a01 = fma(p0, q1, a01);
-      a10 = fma(p1, q0, a10);
-      a11 = fma(p1, q1, a11);
-    }
-    __syncthreads();
-  }
-  const double acc[2][2] = {{static_cast<double>(a00), static_cast<double>(a01)},
-                            {static_cast<double>(a10), static_cast<double>(a11)}};
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const int i = i0 + ty * 2 + a, k = k0 + tx * 2 + c;
-      if (i < sb && k < sb && i >= k) Gb[static_cast<int64_t>(k) * s + i] = acc[a][c] + (i == k ? lambda : 0.0);
-    }
-}
-
-template <typename TA>
 __global__ __launch_bounds__(kT) void k_gram_cd(const TA* __restrict__ A, int64_t lda,
                                                 const int32_t* __restrict__ rows,
                                                 const int32_t* __restrict__ lens, int32_t s,
@@ -237,6 +183,18 @@ __global__ __launch_bounds__(kT) void k_gram_cd(const TA* __restrict__ A, int64_
 // --------------------------------------------------------------------------
 // memo miss: Cholesky, one workgroup per block (right-looking, column by column)
 // --------------------------------------------------------------------------
+// Low-precision pass: a block whose Frobenius condition number
+// ||G||_F ||G^{-1}||_F (at least kappa_2(G), at most s kappa_2(G)) exceeds
+// chk.kappa_max is marked for the FP64 Gram and factor.
+__device__ __forceinline__ void flag_ill_conditioned(const FactorCheck& chk, int blk, double norm_g2,
+                                                     double norm_gi2) {
+  const double kf = sqrt(norm_g2 * norm_gi2);
+  if (!(kf <= chk.kappa_max)) {
+    chk.flag[blk] = 1;
+    atomicAdd(chk.counter, 1);
+  }
+}
+
 template <bool IN_LDS>
 __global__ __launch_bounds__(kT) void k_cholesky(double* __restrict__ G, int32_t s, int64_t stride,
                                                  const int32_t* __restrict__ lens,
@@ -259,6 +217,22 @@ __global__ __launch_bounds__(kT) void k_cholesky(double* __restrict__ G, int32_t
   } else {
     M = Gb;
     ld = s;
+  }
+  if (chk.flag) {
+    // ||G||_F^2 of the symmetric Gram, kept for the condition test made once
+    // G^{-1} exists: in the last entry of the inverse's region, which is
+    // neither read nor written before the inverse is stored
+    __shared__ double red4[4];
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < sb * sb; e += kT) {
+      const int k = e / sb, i = e - k * sb;
+      if (i >= k) {
+        const double v = Gb[static_cast<int64_t>(k) * s + i];
+        acc += (i == k ? 1.0 : 2.0) * v * v;
+      }
+    }
+    acc = block_sum(acc, red4);
+    if (threadIdx.x == 0) Gb[2 * static_cast<int64_t>(s) * s - 1] = acc;
   }
   int bad = 0;
   for (int j = 0; j < sb; ++j) {
@@ -409,15 +383,18 @@ template <bool IN_LDS>
 __global__ __launch_bounds__(kT) void k_factor_inverse(double* __restrict__ slots, int64_t stride,
                                                        int32_t s, const int32_t* __restrict__ lens,
                                                        const int32_t* __restrict__ slot_of,
-                                                       const int32_t* __restrict__ only,
+                                                       FactorCheck chk,
                                                        const int32_t* __restrict__ skip) {
   extern __shared__ double lds[];
+  __shared__ double red4[4];
+  __shared__ double norm_g2;
   const int blk = blockIdx.x;
-  if ((only && !only[blk]) || (skip && skip[blk])) return;
+  if ((chk.only && !chk.only[blk]) || (skip && skip[blk])) return;
   const int sb = lens[blk];
   double* base = slots + static_cast<int64_t>(slot_of[blk]) * stride;
   const double* Lc = base;
   double* Gi = base + static_cast<int64_t>(s) * s;
+  if (chk.flag && threadIdx.x == 0) norm_g2 = Gi[static_cast<int64_t>(s) * s - 1];  // left by k_cholesky
   double* M;
   double* tmp;
   int64_t ld;
@@ -457,6 +434,17 @@ __global__ __launch_bounds__(kT) void k_factor_inverse(double* __restrict__ slot
       Gi[static_cast<int64_t>(k) * s + i] = acc;
     }
   }
+  if (chk.flag) {
+    __syncthreads();
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < sb * sb; e += kT) {
+      const int k = e / sb, i = e - k * sb;
+      const double v = Gi[static_cast<int64_t>(k) * s + i];
+      acc = fma(v, v, acc);
+    }
+    acc = block_sum(acc, red4);
+    if (threadIdx.x == 0) flag_ill_conditioned(chk, blk, norm_g2, acc);
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -494,6 +482,18 @@ __global__ __launch_bounds__(kT) void k_factor_small(double* __restrict__ slots,
       const double v = Lc[static_cast<int64_t>(kc) * s + ic];
       g[a][b] = (i < sb && k < sb && i >= k) ? v : 0.0;
     }
+  __shared__ double red4[4];
+  __shared__ double norm_g2;
+  if (chk.flag) {
+    // ||G||_F^2 of the symmetric Gram (only the lower triangle is held)
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int b = 0; b < 8; ++b) acc += ((ty + 16 * a) == (tx + 16 * b) ? 1.0 : 2.0) * g[a][b] * g[a][b];
+    acc = block_sum(acc, red4);
+    if (threadIdx.x == 0) norm_g2 = acc;
+  }
   int bad = 0;
   // Cholesky, right-looking
 #pragma unroll
@@ -657,6 +657,17 @@ __global__ __launch_bounds__(kT) void k_factor_small(double* __restrict__ slots,
       const int i = ty + 16 * a, k = tx + 16 * b;
       if (i < sb && k < sb) Gi[static_cast<int64_t>(k) * s + i] = h[a][b];
     }
+  if (chk.flag) {
+    // entries outside the block are zero in h
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int b = 0; b < 8; ++b) acc = fma(h[a][b], h[a][b], acc);
+    __syncthreads();
+    acc = block_sum(acc, red4);
+    if (threadIdx.x == 0) flag_ill_conditioned(chk, blk, norm_g2, acc);
+  }
 }
 
 // Block rows and lengths from a staging area into their slots.
@@ -699,12 +710,10 @@ void launch_update(int32_t kind, const double* A, int64_t lda, int64_t n, const 
 
 void launch_gram(int32_t kind, const double* A, int64_t lda, int64_t n, const int32_t* rows,
                  const int32_t* lens, int32_t s, int32_t nb, double lambda, double* G, int64_t stride,
-                 const int32_t* slot_of, hipStream_t st, const int32_t* only) {
+                 const int32_t* slot_of, double* ws, hipStream_t st, const int32_t* only) {
   if (nb <= 0) return;
   if (kind == 0) {
-    const int nt = (s + 31) / 32;
-    hipLaunchKernelGGL(k_gram_kpp<double>, dim3(nt, nt, nb), dim3(kT), 0, st, A, lda, n, rows, lens, s,
-                       lambda, G, stride, slot_of, only);
+    launch_gram_syrk(A, lda, n, rows, lens, s, nb, lambda, G, stride, slot_of, only, ws, st);
   } else {
     hipLaunchKernelGGL(k_gram_cd<double>, dim3(nb), dim3(kT), 0, st, A, lda, rows, lens, s, lambda, G,
                        stride, slot_of, only);
@@ -745,7 +754,7 @@ void launch_check_finite(const double* A, int64_t lda, int64_t m, int64_t n, con
 }
 
 void launch_factor_inverse(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
-                           const int32_t* slot_of, hipStream_t st, const int32_t* only, const int32_t* skip) {
+                           const int32_t* slot_of, hipStream_t st, FactorCheck chk, const int32_t* skip) {
   if (nb <= 0) return;
   if (s <= kLdsCholMax) {
     const size_t lds = (static_cast<size_t>(s) * (s + 1) + s) * sizeof(double);
@@ -756,9 +765,9 @@ void launch_factor_inverse(double* slots, int64_t stride, int32_t s, const int32
                                 static_cast<int>((kLdsCholMax * (kLdsCholMax + 1) + kLdsCholMax) * sizeof(double)));
       attr_set = true;
     }
-    hipLaunchKernelGGL(k_factor_inverse<true>, dim3(nb), dim3(kT), lds, st, slots, stride, s, lens, slot_of, only, skip);
+    hipLaunchKernelGGL(k_factor_inverse<true>, dim3(nb), dim3(kT), lds, st, slots, stride, s, lens, slot_of, chk, skip);
   } else {
-    hipLaunchKernelGGL(k_factor_inverse<false>, dim3(nb), dim3(kT), 0, st, slots, stride, s, lens, slot_of, only, skip);
+    hipLaunchKernelGGL(k_factor_inverse<false>, dim3(nb), dim3(kT), 0, st, slots, stride, s, lens, slot_of, chk, skip);
   }
 }
 
@@ -778,14 +787,12 @@ void launch_scatter_rows(const int32_t* stage_rows, const int32_t* stage_lens, c
 
 void launch_gram_f32(int32_t kind, const float* A, int64_t lda, int64_t n, const int32_t* rows,
                      const int32_t* lens, int32_t s, int32_t nb, double lambda, double* G, int64_t stride,
-                     const int32_t* slot_of, hipStream_t st) {
-  const int32_t* only = nullptr;
+                     const int32_t* slot_of, double* ws, hipStream_t st) {
   if (nb <= 0) return;
   if (kind == 0) {
-    const int nt = (s + 31) / 32;
-    hipLaunchKernelGGL(k_gram_kpp<float>, dim3(nt, nt, nb), dim3(kT), 0, st, A, lda, n, rows, lens, s,
-                       lambda, G, stride, slot_of, only);
+    launch_gram_syrk_f32(A, lda, n, rows, lens, s, nb, lambda, G, stride, slot_of, ws, st);
   } else {
+    const int32_t* only = nullptr;
     hipLaunchKernelGGL(k_gram_cd<float>, dim3(nb), dim3(kT), 0, st, A, lda, rows, lens, s, lambda, G,
                        stride, slot_of, only);
   }

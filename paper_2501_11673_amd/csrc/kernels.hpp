@@ -57,16 +57,29 @@ void launch_update(int32_t kind, const double* A, int64_t lda, int64_t n, const 
 
 // Regularized Grams of nb blocks into column-major s x s slots (lower part);
 // block k is staged at rows[k * s], lens[k] and goes to slot slot_of[k], whose
-// first element is G[slot_of[k] * stride].
+// first element is G[slot_of[k] * stride].  Kaczmarz++ Grams use the MFMA
+// SYRK below and need gram_syrk_work(s, n, nb) doubles of workspace in ws.
 void launch_gram(int32_t kind, const double* A, int64_t lda, int64_t n, const int32_t* rows,
                  const int32_t* lens, int32_t s, int32_t nb, double lambda, double* G, int64_t stride,
-                 const int32_t* slot_of, hipStream_t st, const int32_t* only = nullptr);
+                 const int32_t* slot_of, double* ws, hipStream_t st, const int32_t* only = nullptr);
 
 // The same Grams from an FP32 copy of A (FP32 products, FP32 accumulation),
 // written to the FP64 slots.
 void launch_gram_f32(int32_t kind, const float* A, int64_t lda, int64_t n, const int32_t* rows,
                      const int32_t* lens, int32_t s, int32_t nb, double lambda, double* G, int64_t stride,
-                     const int32_t* slot_of, hipStream_t st);
+                     const int32_t* slot_of, double* ws, hipStream_t st);
+
+// Kaczmarz++ Grams A_S A_S^T + lambda I on the matrix cores: 64 x 64 lower
+// tiles x column chunks, 16x16x4 MFMA (FP64, or FP32 in / FP32 accumulate),
+// FP64 partial tiles summed in chunk order.  gram_syrk_plan gives the split.
+void gram_syrk_plan(int32_t s, int64_t n, int32_t nb, int32_t* nchunks, int64_t* chunk, int32_t* ntiles);
+size_t gram_syrk_work(int32_t s, int64_t n, int32_t nb);
+void launch_gram_syrk(const double* A, int64_t lda, int64_t n, const int32_t* rows, const int32_t* lens, int32_t s,
+                      int32_t nb, double lambda, double* G, int64_t stride, const int32_t* slot_of,
+                      const int32_t* only, double* ws, hipStream_t st);
+void launch_gram_syrk_f32(const float* A, int64_t lda, int64_t n, const int32_t* rows, const int32_t* lens, int32_t s,
+                          int32_t nb, double lambda, double* G, int64_t stride, const int32_t* slot_of,
+                          double* ws, hipStream_t st);
 
 // In-place Cholesky of nb slots; breakdown sets *err = 1.
 void launch_cholesky(double* G, int32_t s, int64_t stride, const int32_t* lens, int32_t nb,
@@ -74,8 +87,11 @@ void launch_cholesky(double* G, int32_t s, int64_t stride, const int32_t* lens, 
 
 // G^{-1} = L^{-T} L^{-1} of each slot's factor (at +s*s, full symmetric);
 // blocks larger than kLdsCholMax use the slot's last s*s doubles as scratch.
+// With chk.flag set (low-precision pass), blocks whose Frobenius condition
+// number exceeds chk.kappa_max are flagged; launch_cholesky with the same
+// check must have run first (it leaves ||G||_F^2 in the slot).
 void launch_factor_inverse(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
-                           const int32_t* slot_of, hipStream_t st, const int32_t* only = nullptr,
+                           const int32_t* slot_of, hipStream_t st, FactorCheck chk = FactorCheck(),
                            const int32_t* skip = nullptr);
 
 // Blocks of at most kFactorSmallMax rows: Cholesky in place (breakdown sets

@@ -117,6 +117,8 @@ struct kpp_system {
   uint64_t* phase_ticks = nullptr;   // KPP_PHASE_PROFILE=1: fused-engine phase profile
   // mixed precision: FP32 copy of A (leading dimension n), outer residual, correction
   float* A32 = nullptr;
+  double* gram_ws[2] = {nullptr, nullptr};   // split-Gram partial tiles, one per staging buffer
+  size_t gram_ws_cap[2] = {0, 0};
   double* rvec = nullptr;
   double* dvec = nullptr;
   int32_t* fp64_count = nullptr;   // blocks refactored in FP64 (mixed precision)
@@ -152,6 +154,10 @@ void destroy_buffers(kpp_system* s) {
   dev_free(s->flags);
   dev_free(s->phase_ticks);
   dev_free(s->A32);
+  for (int i = 0; i < 2; ++i) {
+    dev_free(s->gram_ws[i]);
+    s->gram_ws_cap[i] = 0;
+  }
   dev_free(s->rvec);
   dev_free(s->dvec);
   dev_free(s->fp64_count);
@@ -222,6 +228,19 @@ kpp_status ensure_stage(kpp_system* sys, int idx, size_t ints) {
   HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&sys->h_stage[idx]), cap * sizeof(int32_t), hipHostMallocDefault));
   KPP_TRY(dev_alloc(&sys->d_stage[idx], cap));
   sys->stage_cap[idx] = cap;
+  return KPP_OK;
+}
+
+// Workspace of the split Kaczmarz++ Gram for staging buffer idx.
+kpp_status ensure_gram_ws(kpp_system* sys, int idx, size_t doubles) {
+  if (doubles <= sys->gram_ws_cap[idx]) return KPP_OK;
+  const size_t cap = std::max<size_t>(doubles, sys->gram_ws_cap[idx] * 2);
+  HIP_TRY(hipStreamSynchronize(sys->ctx->stream));
+  HIP_TRY(hipStreamSynchronize(sys->ctx->side));
+  dev_free(sys->gram_ws[idx]);
+  sys->gram_ws_cap[idx] = 0;
+  KPP_TRY(dev_alloc(&sys->gram_ws[idx], cap));
+  sys->gram_ws_cap[idx] = cap;
   return KPP_OK;
 }
 
@@ -467,12 +486,14 @@ kpp_status solve_core(kpp_system* sys, const kpp_params* p, const Source& src, c
       const int32_t* d_slens = sys->d_stage[idx] + w.o_len;
       const int32_t* d_sslot = sys->d_stage[idx] + w.o_slot;
       kpp::launch_scatter_rows(d_srows, d_slens, d_sslot, w.nb, s, sys->rows, sys->lens, fs);
+      if (kind == KPP_KACZMARZ) KPP_TRY(ensure_gram_ws(sys, idx, kpp::gram_syrk_work(s, n, w.nb)));
+      double* gws = sys->gram_ws[idx];
       auto factor = [&](const kpp::FactorCheck& chk, const int32_t* skip) {
         if (s <= kpp::kFactorSmallMax) {
           kpp::launch_factor_small(sys->L, sys->slot_stride, s, d_slens, w.nb, d_sslot, 1, sys->err, fs, chk);
         } else {
           kpp::launch_cholesky(sys->L, s, sys->slot_stride, d_slens, w.nb, d_sslot, sys->err, fs, chk);
-          kpp::launch_factor_inverse(sys->L, sys->slot_stride, s, d_slens, w.nb, d_sslot, fs, chk.only, skip);
+          kpp::launch_factor_inverse(sys->L, sys->slot_stride, s, d_slens, w.nb, d_sslot, fs, chk, skip);
         }
       };
       if (fp32) {
@@ -480,20 +501,20 @@ kpp_status solve_core(kpp_system* sys, const kpp_params* p, const Source& src, c
         // 1e6 are formed again from the FP64 A and factored in FP64
         int32_t* flag = sys->d_stage[idx] + w.o_step + w.W;
         kpp::launch_gram_f32(kind, src.A32, src.lda, n, d_srows, d_slens, s, w.nb, p->lambda, sys->L,
-                             sys->slot_stride, d_sslot, fs);
+                             sys->slot_stride, d_sslot, gws, fs);
         kpp::FactorCheck first;
         first.flag = flag;
         first.counter = sys->fp64_count;
         first.kappa_max = 1e6;
         factor(first, flag);
         kpp::launch_gram(kind, sys->A, sys->lda, n, d_srows, d_slens, s, w.nb, p->lambda, sys->L,
-                         sys->slot_stride, d_sslot, fs, flag);
+                         sys->slot_stride, d_sslot, gws, fs, flag);
         kpp::FactorCheck redo;
         redo.only = flag;
         factor(redo, nullptr);
       } else {
         kpp::launch_gram(kind, src.A64, src.lda, n, d_srows, d_slens, s, w.nb, p->lambda, sys->L,
-                         sys->slot_stride, d_sslot, fs);
+                         sys->slot_stride, d_sslot, gws, fs);
         factor(kpp::FactorCheck(), nullptr);
       }
       HIP_TRY(hipGetLastError());
@@ -998,8 +1019,9 @@ KPP_API kpp_status kpp_block_factor(kpp_system* sys, int32_t s, double lambda, i
   HIP_TRY(hipMemcpyAsync(d_ids, ids.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemsetAsync(sys->err, 0, sizeof(int32_t), st));
   HIP_TRY(hipMemsetAsync(L_dev, 0, static_cast<size_t>(nb) * s * s * sizeof(double), st));
+  if (sys->kind == KPP_KACZMARZ) KPP_TRY(ensure_gram_ws(sys, 0, kpp::gram_syrk_work(s, sys->n, nb)));
   kpp::launch_gram(sys->kind, sys->A, sys->lda, sys->n, d_rows, d_lens, s, nb, lambda, L_dev,
-                   static_cast<int64_t>(s) * s, d_ids, st);
+                   static_cast<int64_t>(s) * s, d_ids, sys->gram_ws[0], st);
   HIP_TRY(hipGetLastError());
   if (s <= kpp::kFactorSmallMax)
     kpp::launch_factor_small(L_dev, static_cast<int64_t>(s) * s, s, d_lens, nb, d_ids, 0, sys->err, st);

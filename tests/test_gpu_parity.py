@@ -107,6 +107,7 @@ def parity_bound(A, b, kind, s, ref, **kw):
     ("general", 300, 150, 20, 1e-3),
     ("general", 700, 300, 37, 1e-2),     # ragged tiles
     ("general", 1200, 400, 256, 1e-1),   # factor in global memory (s > 128)
+    ("general", 400, 3000, 100, 1e-2),   # wide: Gram split over 47 column chunks, ragged tile
     ("psd", 500, 500, 128, 1e-8),
     ("psd", 300, 300, 1, 1e-8),
 ])
