@@ -125,8 +125,24 @@ typedef struct kpp_result {
   double bytes_algorithmic;   /* per step: s n b_A (A_S) + s(s+1)/2 * 8 (factor) + 12 s (b_S, rows) */
   double kernel_seconds;      /* device time of the step kernels (HIP events), all launches */
   double kernel_launches;     /* number of step-kernel launches (fused: one per window)  */
-  double reserved[2];
+  double seconds_queued;      /* serving: time from submission to admission             */
+  double reserved[1];
 } kpp_result;
+
+/* Serving statistics (kpp_server_stats). */
+typedef struct kpp_server_info {
+  int64_t submitted;          /* accepted by kpp_server_submit                           */
+  int64_t completed;          /* finished (any status), including not yet polled         */
+  int64_t rejected;           /* refused by kpp_server_submit with KPP_ERR_REJECTED      */
+  int64_t rounds;             /* shared step launches issued                             */
+  int32_t queued;             /* waiting for admission now                               */
+  int32_t active;             /* admitted and not finished now                           */
+  int32_t peak_active;        /* largest number of requests on the device at once        */
+  int32_t cu_budget;          /* workgroups (one per compute unit) shared by active runs */
+  uint64_t bytes_active;      /* admitted device-memory footprint now                    */
+  uint64_t peak_bytes;        /* largest admitted footprint                              */
+  double busy_seconds;        /* device time of the shared step launches                 */
+} kpp_server_info;
 
 typedef struct kpp_context kpp_context;
 typedef struct kpp_system kpp_system;
@@ -184,6 +200,52 @@ KPP_API kpp_status kpp_block_factor(kpp_system* sys, int32_t s, double lambda, i
 
 /* ||A x - b||_2 in FP64 (eq. (residual-error)); x_dev device, result on host. */
 KPP_API kpp_status kpp_residual_norm(kpp_system* sys, const double* x_dev, double* out_host);
+
+/*
+ * Serving: continuous batching of solves (each one the solve kpp_solve runs).
+ * A worker thread owned by the server runs every admitted request on the
+ * context's streams; from kpp_server_create until kpp_server_destroy returns,
+ * the context and the systems with submitted requests are used by that thread,
+ * and the caller uses them only through kpp_server_* calls (creating further
+ * systems on the context is allowed).  Requests wait in arrival order and are
+ * admitted while (a) the sum of their device-memory footprints (memo cache,
+ * FP32 copy of A, state and staging; the caller's A, b, x not counted) stays
+ * within hbm_budget_bytes, (b) their workgroups (one per compute unit, ceil(n /
+ * 128) for block size <= 128, else ceil(n / 64)) fit on the device, (c) at most
+ * max_active are active, and (d) no other request on the same system is active;
+ * a request held back only by (d) does not hold back later ones.  Every round
+ * advances each active request by a window of its own length, all of them in
+ * one persistent launch, so that requests of different sizes overlap on the
+ * device; a request's iterates do not depend on what else is being served.
+ */
+
+/* Device-memory footprint admission charges for a request (bytes). */
+KPP_API kpp_status kpp_request_footprint(kpp_system* sys, const kpp_params* p, uint64_t* bytes_out);
+
+/* Start a server on ctx (the worker thread starts at once). */
+KPP_API kpp_status kpp_server_create(kpp_context* ctx, uint64_t hbm_budget_bytes, int32_t max_active,
+                                     kpp_server** out);
+
+/* Queue a solve of sys from x_dev (in: x0, out: final iterate), with the
+ * parameters of kpp_solve (engine 1 is not available here).  Returns at once
+ * with the request id; KPP_ERR_REJECTED if the request alone exceeds the
+ * memory budget or the device.  sys, x_dev and *p's values are captured; x_dev
+ * must stay valid until the request has been polled. */
+KPP_API kpp_status kpp_server_submit(kpp_server* srv, kpp_system* sys, const kpp_params* p, double* x_dev,
+                                     uint64_t* id_out);
+
+/* Collect up to cap finished requests (waiting up to wait_seconds for the
+ * first one): ids[i], status[i] (what kpp_solve would return) and, if res is
+ * not NULL, res[i] with seconds_total = submission to completion and
+ * seconds_queued = submission to admission. */
+KPP_API kpp_status kpp_server_poll(kpp_server* srv, int32_t cap, double wait_seconds, uint64_t* ids,
+                                   int32_t* status, kpp_result* res, int32_t* n_out);
+
+KPP_API kpp_status kpp_server_stats(kpp_server* srv, kpp_server_info* out);
+
+/* Finish every submitted request, stop the worker and free the server;
+ * results not polled are dropped. */
+KPP_API kpp_status kpp_server_destroy(kpp_server* srv);
 
 #ifdef __cplusplus
 }

@@ -87,7 +87,8 @@ class kpp_result(ctypes.Structure):
         ("bytes_algorithmic", ctypes.c_double),
         ("kernel_seconds", ctypes.c_double),
         ("kernel_launches", ctypes.c_double),
-        ("reserved", ctypes.c_double * 2),
+        ("seconds_queued", ctypes.c_double),
+        ("reserved", ctypes.c_double * 1),
     ]
 
     def as_dict(self):
@@ -99,6 +100,25 @@ class KppError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
         self.status = status
+
+
+class kpp_server_info(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64),
+        ("completed", ctypes.c_int64),
+        ("rejected", ctypes.c_int64),
+        ("rounds", ctypes.c_int64),
+        ("queued", ctypes.c_int32),
+        ("active", ctypes.c_int32),
+        ("peak_active", ctypes.c_int32),
+        ("cu_budget", ctypes.c_int32),
+        ("bytes_active", ctypes.c_uint64),
+        ("peak_bytes", ctypes.c_uint64),
+        ("busy_seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 def _load():
@@ -131,6 +151,12 @@ def _load():
                                         i32, P(i32)]),
         "kpp_block_factor": (i32, [vp, i32, f64, i32, P(i32), P(i32), vp]),
         "kpp_residual_norm": (i32, [vp, vp, P(f64)]),
+        "kpp_request_footprint": (i32, [vp, P(kpp_params), P(ctypes.c_uint64)]),
+        "kpp_server_create": (i32, [vp, ctypes.c_uint64, i32, P(vp)]),
+        "kpp_server_submit": (i32, [vp, vp, P(kpp_params), vp, P(ctypes.c_uint64)]),
+        "kpp_server_poll": (i32, [vp, i32, f64, P(ctypes.c_uint64), P(i32), P(kpp_result), P(i32)]),
+        "kpp_server_stats": (i32, [vp, P(kpp_server_info)]),
+        "kpp_server_destroy": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -142,7 +168,8 @@ def _load():
 _lib = _load()
 EXPORTED = ("kpp_abi_version", "kpp_last_error", "kpp_params_default", "kpp_context_create",
             "kpp_context_destroy", "kpp_system_create", "kpp_system_destroy", "kpp_solve",
-            "kpp_schedule_generate", "kpp_block_factor", "kpp_residual_norm")
+            "kpp_schedule_generate", "kpp_block_factor", "kpp_residual_norm", "kpp_request_footprint", "kpp_server_create",
+            "kpp_server_submit", "kpp_server_poll", "kpp_server_stats", "kpp_server_destroy")
 
 
 def _check(status):
@@ -218,3 +245,43 @@ def kpp_residual_norm(sys_: int, x_dev: int) -> float:
     out = ctypes.c_double()
     _check(_lib.kpp_residual_norm(ctypes.c_void_p(sys_), ctypes.c_void_p(x_dev), ctypes.byref(out)))
     return out.value
+
+
+def kpp_request_footprint(sys_: int, params: kpp_params) -> int:
+    out = ctypes.c_uint64()
+    _check(_lib.kpp_request_footprint(ctypes.c_void_p(sys_), ctypes.byref(params), ctypes.byref(out)))
+    return out.value
+
+
+def kpp_server_create(ctx: int, hbm_budget_bytes: int, max_active: int) -> int:
+    out = ctypes.c_void_p()
+    _check(_lib.kpp_server_create(ctypes.c_void_p(ctx), int(hbm_budget_bytes), max_active, ctypes.byref(out)))
+    return out.value
+
+
+def kpp_server_submit(srv: int, sys_: int, params: kpp_params, x_dev: int) -> int:
+    """Returns the request id; raises KppError (KPP_ERR_REJECTED, ...) if refused."""
+    rid = ctypes.c_uint64()
+    _check(_lib.kpp_server_submit(ctypes.c_void_p(srv), ctypes.c_void_p(sys_), ctypes.byref(params),
+                                  ctypes.c_void_p(x_dev), ctypes.byref(rid)))
+    return rid.value
+
+
+def kpp_server_poll(srv: int, cap: int = 64, wait_seconds: float = 0.0):
+    """Returns [(id, status, kpp_result), ...] of finished requests."""
+    ids = (ctypes.c_uint64 * max(cap, 1))()
+    sts = (ctypes.c_int32 * max(cap, 1))()
+    res = (kpp_result * max(cap, 1))()
+    n = ctypes.c_int32()
+    _check(_lib.kpp_server_poll(ctypes.c_void_p(srv), cap, float(wait_seconds), ids, sts, res, ctypes.byref(n)))
+    return [(ids[i], sts[i], res[i]) for i in range(n.value)]
+
+
+def kpp_server_stats(srv: int) -> kpp_server_info:
+    out = kpp_server_info()
+    _check(_lib.kpp_server_stats(ctypes.c_void_p(srv), ctypes.byref(out)))
+    return out
+
+
+def kpp_server_destroy(srv: int) -> None:
+    _check(_lib.kpp_server_destroy(ctypes.c_void_p(srv)))

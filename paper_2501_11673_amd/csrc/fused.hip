@@ -98,13 +98,15 @@ __device__ __forceinline__ void load_tile(TA (&tile)[kTileMax], const TA* __rest
 // TA: storage and product type of A (double; float for the mixed-precision
 // inner solver: the tile, the partial residuals and the direction are formed in
 // FP32 with FP32 accumulation, everything else stays FP64).
+// The team of G workgroups runs a.W steps (fewer when a.stop_on_cand ends it
+// at a checkpoint); wg is this workgroup's index in the team.
 template <int KIND, int CPL, typename TA>
-__global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
+__device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, const int wg) {
   const TA* __restrict__ Amat = static_cast<const TA*>(a.A);
   // optional phase profile (workgroup 0, thread 0): ticks[p] accumulates the
   // wall-clock time from mark p-1 to mark p
   uint64_t tick_last = 0, ticks[kFusedPhases];
-  const bool prof = a.phase_ticks != nullptr && blockIdx.x == 0 && threadIdx.x == 0;
+  const bool prof = a.phase_ticks != nullptr && wg == 0 && threadIdx.x == 0;
 #pragma unroll
   for (int p = 0; p < kFusedPhases; ++p) ticks[p] = 0;
 #define KPP_MARK(p)                                   \
@@ -122,10 +124,9 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
   __shared__ double wred[KIND == 0 ? 4 * 64 * CPL : 1];
   __shared__ double red[1];
   __shared__ double bc_c;
+  __shared__ int bc_stop;
   __shared__ int abort_flag;
 
-  const int G = gridDim.x;
-  const int wg = blockIdx.x;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
@@ -364,11 +365,13 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
         st.E0 += rr;
       else
         st.E1 += rr;
+      bc_stop = 0;
       if (ph == period - 1) {
         st.ckpts += 1;
         st.last_E1 = st.E1;
         st.rho_before = rho;
         st.cand = (st.E1 <= st.thr) ? 1 : 0;
+        bc_stop = a.stop_on_cand && st.cand;
         if (a.adaptive && st.E0 > 0.0) {
           const double qr = st.E1 / st.E0;
           if (!st.have_rhat) {
@@ -391,6 +394,7 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
     __syncthreads();
     KPP_MARK(5)
     const double c = bc_c;
+    const bool stop_now = bc_stop != 0;   // the same in every workgroup of the team
 
     // 4. direction on the slice and the momentum update
     double w[CPL];
@@ -443,6 +447,7 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
     cur ^= 1;
     __syncthreads();
     KPP_MARK(6)
+    if (stop_now) break;
   }
 #undef KPP_MARK
   if (prof) {
@@ -464,6 +469,33 @@ __global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
   if (wg == 0 && tid == 0) *a.ds = st;
 }
 
+template <int KIND, int CPL, typename TA>
+__global__ __launch_bounds__(kT) void k_fused(FusedArgs a) {
+  fused_body<KIND, CPL, TA>(a, static_cast<int>(gridDim.x), static_cast<int>(blockIdx.x));
+}
+
+template <int KIND, int CPL, typename TA>
+__global__ __launch_bounds__(kT) void k_fused_multi(const FusedArgs* __restrict__ args,
+                                                    const int32_t* __restrict__ team_start, int32_t nteams) {
+  const int g = static_cast<int>(blockIdx.x);
+  int t = 0;
+  while (t + 1 < nteams && team_start[t + 1] <= g) ++t;
+  const FusedArgs a = args[t];
+  fused_body<KIND, CPL, TA>(a, team_start[t + 1] - team_start[t], g - team_start[t]);
+}
+
+template <int KIND, typename TA>
+void launch_multi_kind(const FusedArgs* args, const int32_t* team_start, int32_t nteams, int total, int cpl,
+                       hipStream_t st) {
+  switch (cpl) {
+    case 1: hipLaunchKernelGGL((k_fused_multi<KIND, 1, TA>), dim3(total), dim3(kT), 0, st, args, team_start, nteams); break;
+    case 2: hipLaunchKernelGGL((k_fused_multi<KIND, 2, TA>), dim3(total), dim3(kT), 0, st, args, team_start, nteams); break;
+    case 4: hipLaunchKernelGGL((k_fused_multi<KIND, 4, TA>), dim3(total), dim3(kT), 0, st, args, team_start, nteams); break;
+    case 8: hipLaunchKernelGGL((k_fused_multi<KIND, 8, TA>), dim3(total), dim3(kT), 0, st, args, team_start, nteams); break;
+    default: hipLaunchKernelGGL((k_fused_multi<KIND, 16, TA>), dim3(total), dim3(kT), 0, st, args, team_start, nteams); break;
+  }
+}
+
 template <int KIND, typename TA>
 void launch_kind(const FusedArgs& a, int cpl, int G, hipStream_t st) {
   switch (cpl) {
@@ -476,6 +508,22 @@ void launch_kind(const FusedArgs& a, int cpl, int G, hipStream_t st) {
 }
 
 }  // namespace
+
+void launch_fused_multi(int32_t kind, bool a_fp32, const FusedArgs* args, const int32_t* team_start,
+                        int32_t nteams, int32_t total_groups, int32_t cpl, hipStream_t st) {
+  if (nteams <= 0 || total_groups <= 0) return;
+  if (kind == 0) {
+    if (a_fp32)
+      launch_multi_kind<0, float>(args, team_start, nteams, total_groups, cpl, st);
+    else
+      launch_multi_kind<0, double>(args, team_start, nteams, total_groups, cpl, st);
+  } else {
+    if (a_fp32)
+      launch_multi_kind<1, float>(args, team_start, nteams, total_groups, cpl, st);
+    else
+      launch_multi_kind<1, double>(args, team_start, nteams, total_groups, cpl, st);
+  }
+}
 
 void launch_fused(int32_t kind, bool a_fp32, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t st) {
   if (kind == 0) {

@@ -156,6 +156,8 @@ struct FusedArgs {
   int32_t* err;              // bit 1: a wait exceeded spin_limit
   int64_t spin_limit;
   uint64_t* phase_ticks;     // optional (nullptr): wall-clock ticks per step phase, workgroup 0
+  int32_t stop_on_cand;      // 1: end the launch after a checkpoint whose stop test passes
+  int32_t pad0;
 };
 
 constexpr int kFusedPhases = 8;
@@ -165,5 +167,13 @@ constexpr int kFusedMaxGroups = 256;
 constexpr int kFlagWordsAlloc = 1024 * kFusedMaxGroups;   // up to 4 KB between flags
 
 void launch_fused(int32_t kind, bool a_fp32, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t st);
+
+// Several independent runs in one launch: team t has the workgroups
+// [team_start[t], team_start[t + 1]) and the arguments args[t] (device
+// memory); every team has the same kind, precision and cpl.  The caller keeps
+// team_start[nteams] <= the number of compute units (one workgroup each) so
+// that every team is resident at once.
+void launch_fused_multi(int32_t kind, bool a_fp32, const FusedArgs* args, const int32_t* team_start,
+                        int32_t nteams, int32_t total_groups, int32_t cpl, hipStream_t st);
 
 }  // namespace kpp

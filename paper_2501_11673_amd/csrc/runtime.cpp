@@ -5,15 +5,19 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kernels.hpp"
@@ -34,18 +38,20 @@ kpp_status fail(kpp_status st, const char* fmt, ...) {
   return st;
 }
 
-#define HIP_TRY(expr)                                                                   \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return fail(e_ == hipErrorOutOfMemory ? KPP_ERR_OOM : KPP_ERR_HIP, "%s: %s (%s:%d)", \
-                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                    \
+// The locals of these macros have names no caller uses (a caller's variable
+// of the same name inside `expr` would otherwise be the macro's own local).
+#define HIP_TRY(expr)                                                                             \
+  do {                                                                                            \
+    hipError_t hip_try_err_ = (expr);                                                             \
+    if (hip_try_err_ != hipSuccess)                                                               \
+      return fail(hip_try_err_ == hipErrorOutOfMemory ? KPP_ERR_OOM : KPP_ERR_HIP, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(hip_try_err_), __FILE__, __LINE__);                    \
   } while (0)
 
-#define KPP_TRY(expr)                   \
-  do {                                  \
-    kpp_status s_ = (expr);             \
-    if (s_ < 0) return s_;              \
+#define KPP_TRY(expr)                          \
+  do {                                         \
+    kpp_status kpp_try_status_ = (expr);       \
+    if (kpp_try_status_ < 0) return kpp_try_status_; \
   } while (0)
 
 template <class T>
@@ -337,110 +343,337 @@ struct CoreStats {
   int32_t engine = 0;
 };
 
-kpp_status solve_core(kpp_system* sys, const kpp_params* p, const Source& src, const CoreOpts& o,
-                      double* x, CoreStats* cs) {
-  hipStream_t st = sys->ctx->stream;
-  const bool fp32 = src.A32 != nullptr;
-  const int32_t kind = sys->kind;
-  const int64_t m = sys->m, n = sys->n;
-  const int64_t N = kind == KPP_CD_PSD ? n : m;
-  const int32_t s = p->block_size;
-  const int32_t zeta = static_cast<int32_t>((N + s - 1) / s);
-  double eta = p->eta < 0.0 ? default_eta(kind, m, n, s) : p->eta;
-  if (!p->accel) eta = 0.0;
-  const kpp::MemoMode mode = static_cast<kpp::MemoMode>(p->memo);
-  const double B0 = kpp::online_rate(kind, m, n, s);
-  std::unique_ptr<kpp::BlockSchedule> sch;
-  try {
-    sch.reset(new kpp::BlockSchedule(mode, N, s, p->seed, B0, p->num_blocks, p->fixed_partition != 0));
-  } catch (const std::exception& e) {
-    return fail(KPP_ERR_INVALID_ARG, "%s", e.what());
-  }
-  // engine
-  int32_t cpl = 0, groups = 0;
-  bool fused = false;
-  if (p->engine != 1) fused = fused_geometry(n, s, p->team_groups, &cpl, &groups);
-  if (p->engine == 2 && !fused) return fail(KPP_ERR_INVALID_ARG, "n=%lld is too wide for the fused engine", (long long)n);
+// One run of the block iteration (Algorithm 2 / Algorithm 5 with the exact
+// memoized projection), advanced launch by launch: kpp_solve drives a run to
+// its end on its own, the server advances many runs in shared launches.
+//
+// A window is the run of steps up to the `periods`-th next checkpoint.
+// Planning a window draws its blocks, assigns memo slots and stages (pinned)
+// the rows of its new blocks plus the slot of every step; its memo misses are
+// then factored on the side stream while the previous window runs on the main
+// stream.  With stop_on_cand a launch ends at a checkpoint whose stop test
+// passes, and the rest of the window follows if the true residual does not
+// confirm the stop; the iterates are the same as with one checkpoint per
+// window.
+class CoreRun {
+ public:
+  ~CoreRun() { drain(); }
 
-  // memo cache: reuse only for an identical schedule definition; the slot
-  // table is sized for this block size before any slot is handed out
-  KPP_TRY(ensure_slots(sys, 16, s));
-  const bool same_sig = sys->memo_valid && o.keep_memo && sys->sig_s == s && sys->sig_memo == p->memo &&
-                        sys->sig_nb == p->num_blocks && sys->sig_part == p->fixed_partition &&
-                        sys->sig_seed == p->seed && sys->sig_lambda == p->lambda &&
-                        sys->sig_prec == (fp32 ? 1 : 0) && mode != kpp::MemoMode::Off;
-  if (!same_sig) {
-    sys->slot_of_block.clear();
-    sys->used_slots = 0;
-    sys->memo_valid = mode != kpp::MemoMode::Off;
-    sys->sig_s = s;
-    sys->sig_memo = p->memo;
-    sys->sig_nb = p->num_blocks;
-    sys->sig_part = p->fixed_partition;
-    sys->sig_seed = p->seed;
-    sys->sig_lambda = p->lambda;
-    sys->sig_prec = fp32 ? 1 : 0;
+  kpp_status begin(kpp_system* sys, const kpp_params* p, const Source& src, const CoreOpts& o, double* x,
+                   int32_t periods, int32_t force_cpl) {
+    sys_ = sys;
+    prm_ = *p;
+    src_ = src;
+    o_ = o;
+    x_ = x;
+    st_ = sys->ctx->stream;
+    side_ = sys->ctx->side;
+    fp32_ = src.A32 != nullptr;
+    kind_ = sys->kind;
+    m_ = sys->m;
+    n_ = sys->n;
+    N_ = kind_ == KPP_CD_PSD ? n_ : m_;
+    s_ = p->block_size;
+    zeta_ = static_cast<int32_t>((N_ + s_ - 1) / s_);
+    period_ = 2 * static_cast<int64_t>(zeta_);
+    periods_ = std::max<int32_t>(1, periods);
+    eta_ = p->eta < 0.0 ? default_eta(kind_, m_, n_, s_) : p->eta;
+    if (!p->accel) eta_ = 0.0;
+    mode_ = static_cast<kpp::MemoMode>(p->memo);
+    max_iters_ = o.max_iters;
+    const double B0 = kpp::online_rate(kind_, m_, n_, s_);
+    try {
+      sch_.reset(new kpp::BlockSchedule(mode_, N_, s_, p->seed, B0, p->num_blocks, p->fixed_partition != 0));
+    } catch (const std::exception& e) {
+      return fail(KPP_ERR_INVALID_ARG, "%s", e.what());
+    }
+    if (force_cpl > 0) {
+      fused_ = s_ * force_cpl <= 256 && s_ <= kpp::kFusedMaxBlock;
+      cpl_ = force_cpl;
+      groups_ = static_cast<int32_t>((n_ + 64 * cpl_ - 1) / (64 * cpl_));
+      if (groups_ > kpp::kFusedMaxGroups) fused_ = false;
+      if (!fused_) return fail(KPP_ERR_INVALID_ARG, "no fused geometry with %d columns per lane", force_cpl);
+    } else {
+      if (p->engine != 1) fused_ = fused_geometry(n_, s_, p->team_groups, &cpl_, &groups_);
+      if (p->engine == 2 && !fused_)
+        return fail(KPP_ERR_INVALID_ARG, "n=%lld is too wide for the fused engine", (long long)n_);
+    }
+    // memo cache: reuse only for an identical schedule definition; the slot
+    // table is sized for this block size before any slot is handed out
+    KPP_TRY(ensure_slots(sys, 16, s_));
+    const bool same_sig = sys->memo_valid && o.keep_memo && sys->sig_s == s_ && sys->sig_memo == p->memo &&
+                          sys->sig_nb == p->num_blocks && sys->sig_part == p->fixed_partition &&
+                          sys->sig_seed == p->seed && sys->sig_lambda == p->lambda &&
+                          sys->sig_prec == (fp32_ ? 1 : 0) && mode_ != kpp::MemoMode::Off;
+    if (!same_sig) {
+      sys->slot_of_block.clear();
+      sys->used_slots = 0;
+      sys->memo_valid = mode_ != kpp::MemoMode::Off;
+      sys->sig_s = s_;
+      sys->sig_memo = p->memo;
+      sys->sig_nb = p->num_blocks;
+      sys->sig_part = p->fixed_partition;
+      sys->sig_seed = p->seed;
+      sys->sig_lambda = p->lambda;
+      sys->sig_prec = fp32_ ? 1 : 0;
+    }
+    if (mode_ == kpp::MemoMode::Fixed) KPP_TRY(ensure_slots(sys, sch_->num_blocks(), s_));
+    // launch engine: column chunks of the block gemv
+    P_ = static_cast<int32_t>((n_ + kChunk - 1) / kChunk);
+    if (!fused_ && static_cast<int64_t>(s_) * P_ > sys->rpart_cap) {
+      dev_free(sys->rpart);
+      KPP_TRY(dev_alloc(&sys->rpart, static_cast<size_t>(s_) * P_));
+      sys->rpart_cap = static_cast<int64_t>(s_) * P_;
+    }
+    HIP_TRY(hipMemsetAsync(sys->mom, 0, n_ * sizeof(double), st_));
+    HIP_TRY(hipMemsetAsync(sys->err, 0, sizeof(int32_t), st_));
+    const double thr = o.tol * o.tol * src.bnorm * src.bnorm;
+    kpp::launch_state_init(sys->ds, o.rho0, thr, st_);
+    HIP_TRY(hipGetLastError());
+    const char* prof_env = std::getenv("KPP_PHASE_PROFILE");
+    phase_prof_ = fused_ && prof_env && prof_env[0] == '1';
+    if (phase_prof_) {
+      if (!sys->phase_ticks) KPP_TRY(dev_alloc(&sys->phase_ticks, kpp::kFusedPhases));
+      HIP_TRY(hipMemsetAsync(sys->phase_ticks, 0, kpp::kFusedPhases * sizeof(uint64_t), st_));
+    }
+    // the side stream's first work must follow this run's initialisation
+    HIP_TRY(hipEventRecord(sys->ev_fact[1][2], st_));
+    HIP_TRY(hipStreamWaitEvent(side_, sys->ev_fact[1][2], 0));
+    begun_ = true;
+    if (max_iters_ <= 0) {
+      finished_ = true;
+      return KPP_OK;
+    }
+    KPP_TRY(plan(win_[0], 0, 0));
+    KPP_TRY(enqueue_factor(win_[0], st_));  // nothing to overlap with yet
+    win_[0].on_side = false;
+    return KPP_OK;
   }
-  if (mode == kpp::MemoMode::Fixed) KPP_TRY(ensure_slots(sys, sch->num_blocks(), s));
-  // launch engine: column chunks of the block gemv
-  const int64_t chunk = 2048;
-  const int32_t P = static_cast<int32_t>((n + chunk - 1) / chunk);
-  if (!fused && static_cast<int64_t>(s) * P > sys->rpart_cap) {
-    dev_free(sys->rpart);
-    KPP_TRY(dev_alloc(&sys->rpart, static_cast<size_t>(s) * P));
-    sys->rpart_cap = static_cast<int64_t>(s) * P;
-  }
-  HIP_TRY(hipMemsetAsync(sys->mom, 0, n * sizeof(double), st));
-  HIP_TRY(hipMemsetAsync(sys->err, 0, sizeof(int32_t), st));
-  const double thr = o.tol * o.tol * src.bnorm * src.bnorm;
-  kpp::launch_state_init(sys->ds, o.rho0, thr, st);
-  HIP_TRY(hipGetLastError());
 
-  const char* prof_env = std::getenv("KPP_PHASE_PROFILE");
-  const bool phase_prof = fused && prof_env && prof_env[0] == '1';
-  if (phase_prof) {
-    if (!sys->phase_ticks) KPP_TRY(dev_alloc(&sys->phase_ticks, kpp::kFusedPhases));
-    HIP_TRY(hipMemsetAsync(sys->phase_ticks, 0, kpp::kFusedPhases * sizeof(uint64_t), st));
-  }
-  int64_t hits = 0, misses = 0, t = 0;
-  bool converged = false;
-  double true_rel = NAN;
-  double t_factor = 0.0, t_kernel = 0.0;
-  int64_t launches = 0;
-  kpp::DevState hs{};
-  const int64_t max_iters = o.max_iters;
-  const int64_t period = 2 * static_cast<int64_t>(zeta);
-  const size_t sd = static_cast<size_t>(sys->slot_stride);
+  bool finished() const { return finished_; }
+  bool fused() const { return fused_; }
+  bool fp32() const { return fp32_; }
+  int32_t kind() const { return kind_; }
+  int32_t cpl() const { return cpl_; }
+  int32_t groups() const { return groups_; }
+  int64_t steps() const { return t_; }
+  bool converged() const { return converged_; }
+  const kpp::DevState& state() const { return hs_; }
+  void add_kernel_seconds(double sec) { t_kernel_ += sec; }
+  void set_stop_on_cand(bool v) { stop_on_cand_ = v; }
 
-  // A window is the run of steps up to the next checkpoint.  Planning a window
-  // draws its blocks, assigns memo slots and stages (pinned) the rows of its
-  // new blocks plus the slot of every step; its memo misses are then factored
-  // on the side stream while the previous window runs on the main stream.
+  // Order the main stream after the current window's factors and, for the
+  // fused engine, fill the step-kernel arguments for the rest of the window.
+  kpp_status prepare(kpp::FusedArgs* a) {
+    Window& w = win_[cur_];
+    if (w.on_side && !w.waited) {
+      HIP_TRY(hipStreamWaitEvent(st_, sys_->ev_fact[cur_][1], 0));
+      w.waited = true;
+    }
+    if (!fused_) return KPP_OK;
+    if (sys_->epoch > 0x3fffffffu) {
+      HIP_TRY(hipMemsetAsync(sys_->flags, 0, kFlagWords * sizeof(uint32_t), st_));
+      sys_->epoch = 0;
+    }
+    *a = kpp::FusedArgs{};
+    a->A = fp32_ ? static_cast<const void*>(src_.A32) : static_cast<const void*>(src_.A64);
+    a->lda = src_.lda;
+    a->n = n_;
+    a->b = src_.b;
+    a->rows = sys_->rows;
+    a->lens = sys_->lens;
+    a->L = sys_->L;
+    a->slot_stride = sys_->slot_stride;
+    a->s = s_;
+    a->W = static_cast<int32_t>(w.W - w.done);
+    a->step_slot = sys_->d_stage[cur_] + w.o_step + w.done;
+    a->x = x_;
+    a->mom = sys_->mom;
+    a->part = sys_->part;
+    a->flags = sys_->flags;
+    a->epoch = sys_->epoch;
+    a->zeta = zeta_;
+    a->adaptive = prm_.adaptive_rho;
+    a->eta = eta_;
+    a->ds = sys_->ds;
+    a->err = sys_->err;
+    a->spin_limit = int64_t{1} << 22;
+    a->phase_ticks = phase_prof_ ? sys_->phase_ticks : nullptr;
+    a->stop_on_cand = stop_on_cand_ ? 1 : 0;
+    return KPP_OK;
+  }
+
+  // One launch per phase for the rest of the window (engine 1).
+  kpp_status launch_unfused() {
+    Window& w = win_[cur_];
+    const size_t sd = static_cast<size_t>(sys_->slot_stride);
+    for (int64_t k = w.done; k < w.W; ++k) {
+      const int32_t q = w.step_slot[k];
+      const int32_t sb = sch_->len(w.step_block[k]);
+      const int32_t* rows = sys_->rows + static_cast<size_t>(q) * s_;
+      kpp::launch_block_gemv_partial(src_.A64, src_.lda, n_, rows, sb, x_, sys_->rpart, P_, kChunk, st_);
+      kpp::launch_block_project(sys_->rpart, P_, src_.b, rows, sb, sys_->L + sd * q + static_cast<size_t>(s_) * s_,
+                                s_, sys_->y, sys_->ds, zeta_, prm_.adaptive_rho, st_);
+      kpp::launch_update(kind_, src_.A64, src_.lda, n_, rows, sb, sys_->y, sys_->ds, eta_, x_, sys_->mom, st_);
+    }
+    launches_ += 3 * (w.W - w.done);
+    HIP_TRY(hipGetLastError());
+    return KPP_OK;
+  }
+
+  void count_fused_launch() { ++launches_; }
+
+  // After the launch is enqueued: state copy-back, and the next window planned
+  // and factored on the side stream while this one runs.
+  kpp_status after_launch() {
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(sys_->h_ds, sys_->ds, sizeof(kpp::DevState), hipMemcpyDeviceToHost, st_));
+    HIP_TRY(hipMemcpyAsync(sys_->h_err, sys_->err, sizeof(int32_t), hipMemcpyDeviceToHost, st_));
+    const Window& w = win_[cur_];
+    const int64_t t_next = w.t0 + w.W;
+    if (!have_next_ && t_next < max_iters_) {
+      KPP_TRY(plan(win_[cur_ ^ 1], t_next, cur_ ^ 1));
+      KPP_TRY(enqueue_factor(win_[cur_ ^ 1], side_));
+      win_[cur_ ^ 1].on_side = true;
+      have_next_ = true;
+    }
+    return KPP_OK;
+  }
+
+  // After the main stream has drained: progress, errors, checkpoint, stop.
+  kpp_status finish() {
+    hs_ = *sys_->h_ds;
+    const int32_t herr = *sys_->h_err;
+    if (herr & 2) {
+      drain();
+      HIP_TRY(hipMemsetAsync(sys_->flags, 0, kFlagWords * sizeof(uint32_t), st_));
+      HIP_TRY(hipStreamSynchronize(st_));
+      sys_->epoch = 0;
+      finished_ = true;
+      return fail(KPP_ERR_DEVICE, "a device-side wait exceeded its bound in the fused engine");
+    }
+    if (herr & 1) {
+      drain();
+      finished_ = true;
+      return fail(KPP_ERR_NOT_SPD, "a regularized block Gram has no Cholesky factor (lambda=%g)", prm_.lambda);
+    }
+    Window& w = win_[cur_];
+    const int64_t ran = hs_.t - t_;
+    if (ran < 0 || ran > w.W - w.done) {
+      finished_ = true;
+      return fail(KPP_ERR_DEVICE, "step count out of range after a launch");
+    }
+    for (int64_t k = w.done; k < w.done + ran; ++k) {
+      if (w.step_new[k])
+        ++misses_;
+      else
+        ++hits_;
+    }
+    if (fused_) sys_->epoch += static_cast<uint32_t>(ran);
+    w.done += ran;
+    t_ = hs_.t;
+    if (w.done == w.W && w.nb > 0) {
+      float ms = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&ms, sys_->ev_fact[cur_][0], sys_->ev_fact[cur_][1]));
+      t_factor_ += 1e-3 * ms;
+    }
+    if (ran > 0 && (t_ % period_) == 0 && hs_.cand) {
+      if (o_.confirm) {
+        double rn = 0.0;
+        KPP_TRY(residual_norm(sys_, x_, &rn));
+        true_rel_ = sys_->bnorm > 0 ? rn / sys_->bnorm : rn;
+        if (rn <= o_.tol * sys_->bnorm) converged_ = true;
+      } else {
+        converged_ = true;
+      }
+    }
+    if (converged_ || t_ >= max_iters_) {
+      finished_ = true;
+    } else if (w.done == w.W) {
+      cur_ ^= 1;
+      have_next_ = false;
+    }
+    return KPP_OK;
+  }
+
+  // Drain the side stream (factorizations planned past the stop included) and
+  // report the run.
+  kpp_status end(CoreStats* cs) {
+    HIP_TRY(hipStreamSynchronize(side_));
+    if (o_.confirm && (!converged_ || std::isnan(true_rel_))) {
+      double rn = 0.0;
+      KPP_TRY(residual_norm(sys_, x_, &rn));
+      true_rel_ = sys_->bnorm > 0 ? rn / sys_->bnorm : rn;
+    }
+    if (phase_prof_ && t_ > 0) {
+      uint64_t ticks[kpp::kFusedPhases];
+      HIP_TRY(hipMemcpy(ticks, sys_->phase_ticks, sizeof ticks, hipMemcpyDeviceToHost));
+      int rate_khz = 0;
+      HIP_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, sys_->ctx->device));
+      static const char* names[kpp::kFusedPhases] = {"rows", "tile-dot", "publish", "wait", "reduce-r",
+                                                     "solve+scalars", "update", "-"};
+      std::fprintf(stderr, "[kpp phase profile] %lld steps, workgroup 0, us per step:", static_cast<long long>(t_));
+      for (int ph = 0; ph < kpp::kFusedPhases - 1; ++ph)
+        std::fprintf(stderr, " %s=%.3f", names[ph],
+                     1e3 * static_cast<double>(ticks[ph]) / rate_khz / static_cast<double>(t_));
+      std::fprintf(stderr, "\n");
+    }
+    cs->iters = t_;
+    cs->hits = hits_;
+    cs->misses = misses_;
+    cs->launches = launches_;
+    cs->converged = converged_;
+    cs->true_rel = true_rel_;
+    cs->t_factor = t_factor_;
+    cs->t_kernel = t_kernel_;
+    cs->hs = hs_;
+    cs->engine = fused_ ? 2 : 1;
+    return converged_ ? KPP_OK : KPP_NOT_CONVERGED;
+  }
+
+  // Wait for this run's side-stream work (used on every exit path).
+  void drain() {
+    if (begun_ && side_) (void)hipStreamSynchronize(side_);
+  }
+
+ private:
+  static constexpr int64_t kChunk = 2048;
+
   struct Window {
-    int64_t t0 = 0, W = 0;
+    int64_t t0 = 0, W = 0, done = 0;
     int32_t nb = 0, idx = 0;
+    bool on_side = false, waited = false;
     size_t o_len = 0, o_slot = 0, o_step = 0;
     std::vector<int32_t> step_block, step_slot;
+    std::vector<char> step_new;
   };
-  auto plan = [&](Window& w, int64_t t0, int idx) -> kpp_status {
+
+  kpp_status plan(Window& w, int64_t t0, int idx) {
+    kpp_system* sys = sys_;
+    const int32_t s = s_;
     w.t0 = t0;
     w.idx = idx;
-    w.W = std::min<int64_t>(period - (t0 % period), max_iters - t0);
+    w.done = 0;
+    w.on_side = false;
+    w.waited = false;
+    const int64_t span = periods_ * period_;
+    w.W = std::min<int64_t>(span - (t0 % period_), max_iters_ - t0);
     w.step_block.resize(w.W);
     w.step_slot.resize(w.W);
+    w.step_new.assign(w.W, 0);
     std::vector<int32_t> pending, pending_slots;
-    if (mode == kpp::MemoMode::Off) KPP_TRY(ensure_slots(sys, static_cast<int32_t>(2 * period), s));
+    if (mode_ == kpp::MemoMode::Off) KPP_TRY(ensure_slots(sys, static_cast<int32_t>(2 * span), s));
     for (int64_t k = 0; k < w.W; ++k) {
       bool is_new = false;
-      const int32_t b = sch->next(&is_new);
+      const int32_t b = sch_->next(&is_new);
       w.step_block[k] = b;
-      if (mode == kpp::MemoMode::Off) {
+      if (mode_ == kpp::MemoMode::Off) {
         // windows alternate between two halves of the slot table
-        const int32_t q = static_cast<int32_t>(idx * period + k);
+        const int32_t q = static_cast<int32_t>(idx * span + k);
         w.step_slot[k] = q;
+        w.step_new[k] = 1;
         pending.push_back(b);
         pending_slots.push_back(q);
-        ++misses;
         continue;
       }
       if (static_cast<int32_t>(sys->slot_of_block.size()) <= b) sys->slot_of_block.resize(b + 1, -1);
@@ -450,33 +683,34 @@ kpp_status solve_core(kpp_system* sys, const kpp_params* p, const Source& src, c
         sys->slot_of_block[b] = q;
         pending.push_back(b);
         pending_slots.push_back(q);
-        ++misses;
-      } else {
-        ++hits;
+        w.step_new[k] = 1;
       }
       w.step_slot[k] = q;
     }
-    if (mode != kpp::MemoMode::Off) KPP_TRY(ensure_slots(sys, sys->used_slots, s));
+    if (mode_ != kpp::MemoMode::Off) KPP_TRY(ensure_slots(sys, sys->used_slots, s));
     w.nb = static_cast<int32_t>(pending.size());
     w.o_len = static_cast<size_t>(w.nb) * s;
     w.o_slot = w.o_len + w.nb;
     w.o_step = w.o_slot + w.nb;
     const size_t need = w.o_step + static_cast<size_t>(w.W) + static_cast<size_t>(w.nb);  // + flags
     KPP_TRY(ensure_stage(sys, idx, need));
-    int32_t* hs_ = sys->h_stage[idx];
+    int32_t* stage = sys->h_stage[idx];
     for (int32_t k = 0; k < w.nb; ++k) {
       const int32_t b = pending[k];
-      const int32_t l = sch->len(b);
-      std::copy(sch->rows(b), sch->rows(b) + l, hs_ + static_cast<size_t>(k) * s);
-      std::fill(hs_ + static_cast<size_t>(k) * s + l, hs_ + static_cast<size_t>(k + 1) * s, 0);
-      hs_[w.o_len + k] = l;
-      hs_[w.o_slot + k] = pending_slots[k];
+      const int32_t l = sch_->len(b);
+      std::copy(sch_->rows(b), sch_->rows(b) + l, stage + static_cast<size_t>(k) * s);
+      std::fill(stage + static_cast<size_t>(k) * s + l, stage + static_cast<size_t>(k + 1) * s, 0);
+      stage[w.o_len + k] = l;
+      stage[w.o_slot + k] = pending_slots[k];
     }
-    std::copy(w.step_slot.begin(), w.step_slot.end(), hs_ + w.o_step);
+    std::copy(w.step_slot.begin(), w.step_slot.end(), stage + w.o_step);
     return KPP_OK;
-  };
+  }
+
   // upload the window's staging and factor its memo misses on `fs`
-  auto enqueue_factor = [&](const Window& w, hipStream_t fs) -> kpp_status {
+  kpp_status enqueue_factor(const Window& w, hipStream_t fs) {
+    kpp_system* sys = sys_;
+    const int32_t s = s_;
     const int idx = w.idx;
     const size_t need = w.o_step + static_cast<size_t>(w.W);
     HIP_TRY(hipMemcpyAsync(sys->d_stage[idx], sys->h_stage[idx], need * sizeof(int32_t), hipMemcpyHostToDevice, fs));
@@ -486,7 +720,7 @@ kpp_status solve_core(kpp_system* sys, const kpp_params* p, const Source& src, c
       const int32_t* d_slens = sys->d_stage[idx] + w.o_len;
       const int32_t* d_sslot = sys->d_stage[idx] + w.o_slot;
       kpp::launch_scatter_rows(d_srows, d_slens, d_sslot, w.nb, s, sys->rows, sys->lens, fs);
-      if (kind == KPP_KACZMARZ) KPP_TRY(ensure_gram_ws(sys, idx, kpp::gram_syrk_work(s, n, w.nb)));
+      if (kind_ == KPP_KACZMARZ) KPP_TRY(ensure_gram_ws(sys, idx, kpp::gram_syrk_work(s, n_, w.nb)));
       double* gws = sys->gram_ws[idx];
       auto factor = [&](const kpp::FactorCheck& chk, const int32_t* skip) {
         if (s <= kpp::kFactorSmallMax) {
@@ -496,24 +730,24 @@ kpp_status solve_core(kpp_system* sys, const kpp_params* p, const Source& src, c
           kpp::launch_factor_inverse(sys->L, sys->slot_stride, s, d_slens, w.nb, d_sslot, fs, chk, skip);
         }
       };
-      if (fp32) {
+      if (fp32_) {
         // FP32 Grams; blocks whose factor breaks down or whose kappa(G) exceeds
         // 1e6 are formed again from the FP64 A and factored in FP64
         int32_t* flag = sys->d_stage[idx] + w.o_step + w.W;
-        kpp::launch_gram_f32(kind, src.A32, src.lda, n, d_srows, d_slens, s, w.nb, p->lambda, sys->L,
+        kpp::launch_gram_f32(kind_, src_.A32, src_.lda, n_, d_srows, d_slens, s, w.nb, prm_.lambda, sys->L,
                              sys->slot_stride, d_sslot, gws, fs);
         kpp::FactorCheck first;
         first.flag = flag;
         first.counter = sys->fp64_count;
         first.kappa_max = 1e6;
         factor(first, flag);
-        kpp::launch_gram(kind, sys->A, sys->lda, n, d_srows, d_slens, s, w.nb, p->lambda, sys->L,
+        kpp::launch_gram(kind_, sys->A, sys->lda, n_, d_srows, d_slens, s, w.nb, prm_.lambda, sys->L,
                          sys->slot_stride, d_sslot, gws, fs, flag);
         kpp::FactorCheck redo;
         redo.only = flag;
         factor(redo, nullptr);
       } else {
-        kpp::launch_gram(kind, src.A64, src.lda, n, d_srows, d_slens, s, w.nb, p->lambda, sys->L,
+        kpp::launch_gram(kind_, src_.A64, src_.lda, n_, d_srows, d_slens, s, w.nb, prm_.lambda, sys->L,
                          sys->slot_stride, d_sslot, gws, fs);
         factor(kpp::FactorCheck(), nullptr);
       }
@@ -521,149 +755,55 @@ kpp_status solve_core(kpp_system* sys, const kpp_params* p, const Source& src, c
     }
     HIP_TRY(hipEventRecord(sys->ev_fact[idx][1], fs));
     return KPP_OK;
-  };
-
-  // the side stream's first work must follow this solve's initialisation
-  HIP_TRY(hipEventRecord(sys->ev_fact[1][2], st));
-  HIP_TRY(hipStreamWaitEvent(sys->ctx->side, sys->ev_fact[1][2], 0));
-  Window win[2];
-  bool have_next = false;
-  if (max_iters > 0) {
-    KPP_TRY(plan(win[0], 0, 0));
-    KPP_TRY(enqueue_factor(win[0], st));  // nothing to overlap with yet
   }
-  int cur = 0;
-  while (t < max_iters && !converged) {
-    Window& w = win[cur];
-    if (have_next) HIP_TRY(hipStreamWaitEvent(st, sys->ev_fact[cur][1], 0));
-    const int32_t* d_step = sys->d_stage[cur] + w.o_step;
+
+  kpp_system* sys_ = nullptr;
+  kpp_params prm_{};
+  Source src_{};
+  CoreOpts o_{};
+  double* x_ = nullptr;
+  hipStream_t st_ = nullptr, side_ = nullptr;
+  bool fp32_ = false, fused_ = false, phase_prof_ = false, stop_on_cand_ = false, begun_ = false;
+  int32_t kind_ = 0, s_ = 0, zeta_ = 0, periods_ = 1, cpl_ = 0, groups_ = 0, P_ = 0;
+  int64_t m_ = 0, n_ = 0, N_ = 0, period_ = 0, max_iters_ = 0;
+  double eta_ = 0.0;
+  kpp::MemoMode mode_ = kpp::MemoMode::Online;
+  std::unique_ptr<kpp::BlockSchedule> sch_;
+  Window win_[2];
+  int cur_ = 0;
+  bool have_next_ = false;
+  int64_t t_ = 0, hits_ = 0, misses_ = 0, launches_ = 0;
+  bool converged_ = false, finished_ = false;
+  double true_rel_ = NAN, t_factor_ = 0.0, t_kernel_ = 0.0;
+  kpp::DevState hs_{};
+};
+
+// A run driven on its own: one launch per window.
+kpp_status solve_core(kpp_system* sys, const kpp_params* p, const Source& src, const CoreOpts& o,
+                      double* x, CoreStats* cs) {
+  hipStream_t st = sys->ctx->stream;
+  CoreRun run;
+  KPP_TRY(run.begin(sys, p, src, o, x, 1, 0));
+  while (!run.finished()) {
+    kpp::FusedArgs a;
+    KPP_TRY(run.prepare(&a));
     HIP_TRY(hipEventRecord(sys->ev[0], st));
-    if (fused) {
-      if (sys->epoch > 0x3fffffffu) {
-        HIP_TRY(hipMemsetAsync(sys->flags, 0, kFlagWords * sizeof(uint32_t), st));
-        sys->epoch = 0;
-      }
-      kpp::FusedArgs a{};
-      a.A = fp32 ? static_cast<const void*>(src.A32) : static_cast<const void*>(src.A64);
-      a.lda = src.lda;
-      a.n = n;
-      a.b = src.b;
-      a.rows = sys->rows;
-      a.lens = sys->lens;
-      a.L = sys->L;
-      a.slot_stride = sys->slot_stride;
-      a.s = s;
-      a.W = static_cast<int32_t>(w.W);
-      a.step_slot = d_step;
-      a.x = x;
-      a.mom = sys->mom;
-      a.part = sys->part;
-      a.flags = sys->flags;
-      a.epoch = sys->epoch;
-      a.zeta = zeta;
-      a.adaptive = p->adaptive_rho;
-      a.eta = eta;
-      a.ds = sys->ds;
-      a.err = sys->err;
-      a.spin_limit = int64_t{1} << 22;
-      a.phase_ticks = phase_prof ? sys->phase_ticks : nullptr;
-      kpp::launch_fused(kind, fp32, a, cpl, groups, st);
-      sys->epoch += static_cast<uint32_t>(w.W);
-      ++launches;
+    if (run.fused()) {
+      kpp::launch_fused(run.kind(), run.fp32(), a, run.cpl(), run.groups(), st);
+      run.count_fused_launch();
     } else {
-      for (int64_t k = 0; k < w.W; ++k) {
-        const int32_t q = w.step_slot[k];
-        const int32_t sb = sch->len(w.step_block[k]);
-        const int32_t* rows = sys->rows + static_cast<size_t>(q) * s;
-        kpp::launch_block_gemv_partial(src.A64, src.lda, n, rows, sb, x, sys->rpart, P, chunk, st);
-        kpp::launch_block_project(sys->rpart, P, src.b, rows, sb, sys->L + sd * q + static_cast<size_t>(s) * s,
-                                  s, sys->y, sys->ds, zeta, p->adaptive_rho, st);
-        kpp::launch_update(kind, src.A64, src.lda, n, rows, sb, sys->y, sys->ds, eta, x, sys->mom, st);
-      }
-      launches += 3 * w.W;
+      KPP_TRY(run.launch_unfused());
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(sys->ev[1], st));
-    HIP_TRY(hipMemcpyAsync(sys->h_ds, sys->ds, sizeof(kpp::DevState), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(sys->h_err, sys->err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    // plan and factor the next window while this one runs
-    const int64_t t_next = t + w.W;
-    have_next = false;
-    if (t_next < max_iters) {
-      KPP_TRY(plan(win[cur ^ 1], t_next, cur ^ 1));
-      KPP_TRY(enqueue_factor(win[cur ^ 1], sys->ctx->side));
-      have_next = true;
-    }
+    KPP_TRY(run.after_launch());
     HIP_TRY(hipStreamSynchronize(st));
-    hs = *sys->h_ds;
     float ms = 0.0f;
     HIP_TRY(hipEventElapsedTime(&ms, sys->ev[0], sys->ev[1]));
-    t_kernel += 1e-3 * ms;
-    if (w.nb > 0) {
-      HIP_TRY(hipEventElapsedTime(&ms, sys->ev_fact[cur][0], sys->ev_fact[cur][1]));
-      t_factor += 1e-3 * ms;
-    }
-    const int32_t herr = *sys->h_err;
-    if (herr & 2) {
-      HIP_TRY(hipStreamSynchronize(sys->ctx->side));
-      HIP_TRY(hipMemsetAsync(sys->flags, 0, kFlagWords * sizeof(uint32_t), st));
-      HIP_TRY(hipStreamSynchronize(st));
-      sys->epoch = 0;
-      return fail(KPP_ERR_DEVICE, "a device-side wait exceeded its bound in the fused engine");
-    }
-    if (herr & 1) {
-      HIP_TRY(hipStreamSynchronize(sys->ctx->side));
-      return fail(KPP_ERR_NOT_SPD, "a regularized block Gram has no Cholesky factor (lambda=%g)", p->lambda);
-    }
-    t = t_next;
-    if ((t % period) == 0 && hs.cand) {
-      if (o.confirm) {
-        double rn = 0.0;
-        KPP_TRY(residual_norm(sys, x, &rn));
-        true_rel = sys->bnorm > 0 ? rn / sys->bnorm : rn;
-        if (rn <= o.tol * sys->bnorm) converged = true;
-      } else {
-        converged = true;
-      }
-    }
-    cur ^= 1;
+    run.add_kernel_seconds(1e-3 * ms);
+    KPP_TRY(run.finish());
   }
-  // factorizations planned past the stop are dropped from the counts; the
-  // side stream is drained so that no work of this call is left in flight
-  HIP_TRY(hipStreamSynchronize(sys->ctx->side));
-  if (have_next && converged) {
-    const Window& w = win[cur];
-    misses -= w.nb;
-    hits -= w.W - w.nb;
-  }
-  if (o.confirm && (!converged || std::isnan(true_rel))) {
-    double rn = 0.0;
-    KPP_TRY(residual_norm(sys, x, &rn));
-    true_rel = sys->bnorm > 0 ? rn / sys->bnorm : rn;
-  }
-  if (phase_prof && t > 0) {
-    uint64_t ticks[kpp::kFusedPhases];
-    HIP_TRY(hipMemcpy(ticks, sys->phase_ticks, sizeof ticks, hipMemcpyDeviceToHost));
-    int rate_khz = 0;
-    HIP_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, sys->ctx->device));
-    static const char* names[kpp::kFusedPhases] = {"rows", "tile-dot", "publish", "wait", "reduce-r",
-                                                   "solve+scalars", "update", "-"};
-    std::fprintf(stderr, "[kpp phase profile] %lld steps, workgroup 0, us per step:", static_cast<long long>(t));
-    for (int ph = 0; ph < kpp::kFusedPhases - 1; ++ph)
-      std::fprintf(stderr, " %s=%.3f", names[ph], 1e3 * static_cast<double>(ticks[ph]) / rate_khz / static_cast<double>(t));
-    std::fprintf(stderr, "\n");
-  }
-  cs->iters = t;
-  cs->hits = hits;
-  cs->misses = misses;
-  cs->launches = launches;
-  cs->converged = converged;
-  cs->true_rel = true_rel;
-  cs->t_factor = t_factor;
-  cs->t_kernel = t_kernel;
-  cs->hs = hs;
-  cs->engine = fused ? 2 : 1;
-  return converged ? KPP_OK : KPP_NOT_CONVERGED;
+  return run.end(cs);
 }
 
 
@@ -802,6 +942,425 @@ kpp_status solve_mixed(kpp_system* sys, const kpp_params* p, double* x, kpp_resu
     res->factors_fp64 = nfp64;
   }
   return converged ? KPP_OK : KPP_NOT_CONVERGED;
+}
+
+
+// --------------------------------------------------------------------------
+// Serving: continuous batching of solves.  A worker thread owns the context's
+// streams.  Every round it admits queued requests that fit (device-memory
+// budget, compute units, active-request cap, one active request per system),
+// then advances every active run by one window of its own length in a single
+// persistent launch per (kind, precision, columns-per-lane) group: team t of
+// the launch is run t's workgroups, so requests of different sizes and step
+// counts share the device.  A window spans k_r checkpoint periods, k_r chosen
+// per request so that windows are about kServeRoundSteps steps; a team stops
+// early at a checkpoint whose stop test passes.  Each run's iterates are those
+// of the same request served alone.
+// --------------------------------------------------------------------------
+
+constexpr int64_t kServeRoundSteps = 128;
+
+double now_seconds() {
+  using clock = std::chrono::steady_clock;
+  return std::chrono::duration<double>(clock::now().time_since_epoch()).count();
+}
+
+struct ServeReq {
+  uint64_t id = 0;
+  kpp_system* sys = nullptr;
+  kpp_params p{};
+  double* x = nullptr;
+  bool mixed = false;
+  size_t footprint = 0;
+  int32_t groups = 0, cpl = 0, periods = 1;
+  double t_submit = 0.0, t_admit = 0.0, t_start = 0.0;
+  kpp_status status = KPP_OK;
+  kpp_result res{};
+  std::unique_ptr<CoreRun> run;
+  // refinement bookkeeping (mixed precision) and totals over runs
+  int32_t rounds = 0;
+  int64_t iters = 0, hits = 0, misses = 0, launches = 0, ckpts = 0;
+  double t_factor = 0.0, t_kernel = 0.0, rho = 0.0, true_rel = NAN, est = NAN, last_rn = 0.0;
+  CoreStats last;
+  bool complete = false;
+};
+
+// Checkpoint periods per window of a served request: about kServeRoundSteps
+// steps, so that requests of different sizes take similar time per round.
+int32_t serve_periods(const kpp_system* sys, const kpp_params* p) {
+  const int64_t N = sys->kind == KPP_CD_PSD ? sys->n : sys->m;
+  const int64_t period = 2 * ((N + p->block_size - 1) / p->block_size);
+  return static_cast<int32_t>(std::max<int64_t>(1, kServeRoundSteps / period));
+}
+
+// Device memory a request needs while it runs, beyond the caller's A, b and x:
+// memo slots, the FP32 copy of A (mixed precision), state vectors, staging.
+size_t serve_footprint(const kpp_system* sys, const kpp_params* p, int32_t periods) {
+  const int64_t N = sys->kind == KPP_CD_PSD ? sys->n : sys->m;
+  const int32_t s = p->block_size;
+  const int64_t zeta = (N + s - 1) / s;
+  int64_t blocks = 0;
+  if (p->memo == KPP_MEMO_FIXED)
+    blocks = p->fixed_partition ? zeta : p->num_blocks;
+  else if (p->memo == KPP_MEMO_OFF)
+    blocks = 4 * periods * zeta;
+  else
+    blocks = static_cast<int64_t>(4.0 * kpp::online_rate(sys->kind, sys->m, sys->n, s)) + 16;
+  size_t bytes = static_cast<size_t>(blocks) * (static_cast<size_t>(kpp::slot_doubles(s)) * 8 + 4 * (s + 1));
+  if (p->precision == KPP_MIXED_FP32) bytes += static_cast<size_t>(sys->m) * sys->n * 4 + 8 * (sys->m + sys->n);
+  bytes += 8 * static_cast<size_t>(sys->n) * 2 + 2 * 4 * static_cast<size_t>(s) * (4 * periods * zeta + 2 * s);
+  return bytes;
+}
+
+}  // namespace
+
+struct kpp_server {
+  kpp_context* ctx = nullptr;
+  uint64_t budget = 0;
+  int32_t max_active = 0;
+  int32_t cu_budget = 0;
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  bool stopping = false;
+  uint64_t next_id = 1;
+  std::deque<ServeReq*> queue;           // guarded by mu
+  std::vector<ServeReq*> active;         // worker thread only
+  std::deque<ServeReq*> done;            // guarded by mu
+  std::vector<kpp_system*> busy;         // systems with an active request (worker thread only)
+  // device and pinned host copies of one launch's team table
+  kpp::FusedArgs* d_args = nullptr;
+  int32_t* d_team = nullptr;
+  kpp::FusedArgs* h_args = nullptr;
+  int32_t* h_team = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  // statistics (guarded by mu)
+  int64_t submitted = 0, completed = 0, rejected = 0, rounds = 0;
+  int32_t n_active = 0, peak_active = 0;
+  uint64_t bytes_active = 0, peak_bytes = 0;
+  double busy_seconds = 0.0;
+  int32_t groups_active = 0;
+};
+
+namespace {
+
+// Final numbers of a finished request (worker thread).  The request is handed
+// to the caller later, by serve_handoff, after the worker's last use of it.
+void serve_complete(kpp_server* srv, ServeReq* r) {
+  (void)srv;
+  if (r->run) {
+    r->run->drain();
+    r->run.reset();
+  }
+  kpp_result* res = &r->res;
+  std::memset(res, 0, sizeof(*res));
+  if (r->status >= 0) {
+    fill_result(res, r->sys, &r->p, r->iters, r->hits, r->misses, r->status == KPP_OK, r->rounds, r->last,
+                r->true_rel, r->est, r->rho, now_seconds() - r->t_submit, r->t_factor, r->t_kernel, r->launches,
+                r->ckpts, r->mixed ? 4.0 : 8.0);
+    if (r->mixed && r->sys->fp64_count) {
+      int32_t nfp64 = 0;
+      if (hipMemcpy(&nfp64, r->sys->fp64_count, sizeof(int32_t), hipMemcpyDeviceToHost) == hipSuccess)
+        res->factors_fp64 = nfp64;
+    }
+  }
+  res->seconds_total = now_seconds() - r->t_submit;
+  res->seconds_queued = r->t_admit - r->t_submit;
+  r->complete = true;
+}
+
+// Move the worker's completed requests to the done queue; once there, a
+// request belongs to kpp_server_poll (which deletes it) and the worker does
+// not touch it again.
+void serve_handoff(kpp_server* srv) {
+  std::vector<ServeReq*> finished, keep;
+  for (ServeReq* r : srv->active) {
+    if (r->complete) {
+      srv->busy.erase(std::find(srv->busy.begin(), srv->busy.end(), r->sys));
+      finished.push_back(r);
+    } else {
+      keep.push_back(r);
+    }
+  }
+  srv->active.swap(keep);
+  if (finished.empty()) return;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  for (ServeReq* r : finished) {
+    srv->bytes_active -= r->footprint;
+    srv->groups_active -= r->groups;
+    srv->n_active -= 1;
+    srv->completed += 1;
+    srv->done.push_back(r);
+  }
+  srv->cv_done.notify_all();
+}
+
+// Start the next run of request r: the FP64 solve, or the next refinement
+// round (mixed precision).  Sets r->status and returns false when r is over.
+bool serve_next_run(kpp_server* srv, ServeReq* r) {
+  kpp_system* sys = r->sys;
+  hipStream_t st = sys->ctx->stream;
+  auto failed = [&](kpp_status s) {
+    r->status = s;
+    return false;
+  };
+  if (!r->mixed) {
+    Source src;
+    src.A64 = sys->A;
+    src.lda = sys->lda;
+    src.b = sys->b;
+    src.bnorm = sys->bnorm;
+    CoreOpts o;
+    o.tol = r->p.tol;
+    o.confirm = r->p.confirm_true_residual;
+    o.rho0 = r->p.rho0;
+    o.keep_memo = r->p.keep_memo;
+    o.max_iters = r->p.max_iters;
+    r->run.reset(new CoreRun);
+    r->run->set_stop_on_cand(true);
+    const kpp_status s = r->run->begin(sys, &r->p, src, o, r->x, r->periods, r->cpl);
+    if (s < 0) return failed(s);
+    return true;
+  }
+  // mixed precision: r = b - A x in FP64; stop, or solve A32 d = r approximately
+  kpp::launch_residual_vec(sys->A, sys->lda, sys->m, sys->n, r->x, sys->b, sys->rvec, sys->rowsq, sys->scal, st);
+  if (hipGetLastError() != hipSuccess) return failed(fail(KPP_ERR_HIP, "residual launch failed"));
+  double rr = 0.0;
+  if (hipMemcpyAsync(&rr, sys->scal, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return failed(fail(KPP_ERR_HIP, "residual copy failed"));
+  const double rn = std::sqrt(rr);
+  r->true_rel = sys->bnorm > 0 ? rn / sys->bnorm : rn;
+  if (rn <= r->p.tol * sys->bnorm) {
+    r->status = KPP_OK;
+    return false;
+  }
+  if (r->rounds >= r->p.refine_max_rounds || r->iters >= r->p.max_iters) {
+    r->status = KPP_NOT_CONVERGED;
+    return false;
+  }
+  if (hipMemsetAsync(sys->dvec, 0, sys->n * sizeof(double), st) != hipSuccess)
+    return failed(fail(KPP_ERR_HIP, "memset failed"));
+  Source src;
+  src.A32 = sys->A32;
+  src.lda = sys->n;
+  src.b = sys->rvec;
+  src.bnorm = rn;
+  CoreOpts o;
+  o.tol = r->p.inner_tol;
+  o.confirm = 0;
+  o.rho0 = r->rho;
+  o.keep_memo = r->rounds > 0 ? 1 : r->p.keep_memo;
+  o.max_iters = r->p.max_iters - r->iters;
+  r->run.reset(new CoreRun);
+  r->run->set_stop_on_cand(true);
+  const kpp_status s = r->run->begin(sys, &r->p, src, o, sys->dvec, r->periods, r->cpl);
+  if (s < 0) return failed(s);
+  r->est = NAN;
+  r->last_rn = rn;
+  return true;
+}
+
+// A run of request r has ended: fold its numbers in, apply the correction
+// (mixed precision) and start the next run if there is one.
+bool serve_run_ended(kpp_server* srv, ServeReq* r) {
+  CoreStats cs;
+  const kpp_status s = r->run->end(&cs);
+  if (s < 0) {
+    r->status = s;
+    return false;
+  }
+  r->iters += cs.iters;
+  r->hits += cs.hits;
+  r->misses += cs.misses;
+  r->launches += cs.launches;
+  r->ckpts += cs.hs.ckpts;
+  r->t_factor += cs.t_factor;
+  r->t_kernel += cs.t_kernel;
+  r->last = cs;
+  if (!r->mixed) {
+    r->true_rel = cs.true_rel;
+    r->rho = cs.converged ? cs.hs.rho_before : cs.hs.rho;
+    r->est = r->sys->bnorm > 0 ? std::sqrt(cs.hs.last_E1) / r->sys->bnorm : std::sqrt(cs.hs.last_E1);
+    r->status = cs.converged ? KPP_OK : KPP_NOT_CONVERGED;
+    r->run.reset();
+    return false;
+  }
+  kpp::launch_axpy1(r->x, r->sys->dvec, r->sys->n, r->sys->ctx->stream);
+  if (hipGetLastError() != hipSuccess) {
+    r->status = fail(KPP_ERR_HIP, "axpy launch failed");
+    return false;
+  }
+  r->rounds += 1;
+  r->rho = cs.converged ? cs.hs.rho_before : cs.hs.rho;
+  r->est = r->last_rn > 0 ? std::sqrt(cs.hs.last_E1) / r->last_rn : 0.0;
+  r->run.reset();
+  return serve_next_run(srv, r);
+}
+
+// First work of an admitted request (worker thread).
+bool serve_start(kpp_server* srv, ServeReq* r) {
+  kpp_system* sys = r->sys;
+  hipStream_t st = sys->ctx->stream;
+  r->t_start = now_seconds();
+  if (r->mixed) {
+    auto failed = [&](kpp_status s) {
+      r->status = s;
+      return false;
+    };
+    if (!sys->A32) {
+      if (dev_alloc(&sys->A32, static_cast<size_t>(sys->m) * sys->n) < 0) return failed(KPP_ERR_OOM);
+      kpp::launch_convert_f32(sys->A, sys->lda, sys->m, sys->n, sys->A32, st);
+    }
+    if (!sys->rvec && dev_alloc(&sys->rvec, sys->m) < 0) return failed(KPP_ERR_OOM);
+    if (!sys->dvec && dev_alloc(&sys->dvec, sys->n) < 0) return failed(KPP_ERR_OOM);
+    if (!sys->fp64_count && dev_alloc(&sys->fp64_count, 1) < 0) return failed(KPP_ERR_OOM);
+    if (hipMemsetAsync(sys->fp64_count, 0, sizeof(int32_t), st) != hipSuccess) return failed(KPP_ERR_HIP);
+    r->rho = r->p.rho0;
+  }
+  return serve_next_run(srv, r);
+}
+
+// One round: a window of every active run, one launch per group.
+void serve_round(kpp_server* srv) {
+  hipStream_t st = srv->ctx->stream;
+  std::vector<ServeReq*> live;
+  for (ServeReq* r : srv->active)
+    if (!r->complete && r->run && !r->run->finished()) live.push_back(r);
+  if (live.empty()) return;
+  // groups of runs that can share one launch
+  std::vector<std::vector<ServeReq*>> groups;
+  for (ServeReq* r : live) {
+    bool placed = false;
+    for (auto& g : groups) {
+      ServeReq* h = g.front();
+      if (h->run->kind() == r->run->kind() && h->run->fp32() == r->run->fp32() && h->run->cpl() == r->run->cpl()) {
+        g.push_back(r);
+        placed = true;
+        break;
+      }
+    }
+    if (!placed) groups.push_back({r});
+  }
+  std::vector<ServeReq*> launched;
+  (void)hipEventRecord(srv->ev[0], st);
+  int32_t off_args = 0, off_team = 0;
+  for (auto& g : groups) {
+    std::vector<ServeReq*> team;
+    for (ServeReq* r : g) {
+      const kpp_status s = r->run->prepare(&srv->h_args[off_args + static_cast<int32_t>(team.size())]);
+      if (s < 0) {
+        r->status = s;
+        continue;
+      }
+      team.push_back(r);
+    }
+    if (team.empty()) continue;
+    const int32_t n_t = static_cast<int32_t>(team.size());
+    int32_t* ht = srv->h_team + off_team;
+    int32_t total = 0;
+    ht[0] = 0;
+    for (int32_t i = 0; i < n_t; ++i) {
+      total += team[i]->run->groups();
+      ht[i + 1] = total;
+    }
+    if (hipMemcpyAsync(srv->d_args + off_args, srv->h_args + off_args, n_t * sizeof(kpp::FusedArgs),
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(srv->d_team + off_team, ht, (n_t + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st) !=
+            hipSuccess) {
+      for (ServeReq* r : team) r->status = fail(KPP_ERR_HIP, "team table upload failed");
+      continue;
+    }
+    ServeReq* h = team.front();
+    kpp::launch_fused_multi(h->run->kind(), h->run->fp32(), srv->d_args + off_args, srv->d_team + off_team, n_t,
+                            total, h->run->cpl(), st);
+    if (hipGetLastError() != hipSuccess) {
+      for (ServeReq* r : team) r->status = fail(KPP_ERR_HIP, "step launch failed");
+      continue;
+    }
+    for (ServeReq* r : team) {
+      r->run->count_fused_launch();
+      launched.push_back(r);
+    }
+    off_args += n_t;
+    off_team += n_t + 1;
+  }
+  (void)hipEventRecord(srv->ev[1], st);
+  for (ServeReq* r : launched) {
+    const kpp_status s = r->run->after_launch();
+    if (s < 0) r->status = s;
+  }
+  (void)hipStreamSynchronize(st);
+  float ms = 0.0f;
+  (void)hipEventElapsedTime(&ms, srv->ev[0], srv->ev[1]);
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->rounds += 1;
+    srv->busy_seconds += 1e-3 * ms;
+  }
+  for (ServeReq* r : launched) {
+    if (r->status < 0) continue;
+    r->run->add_kernel_seconds(1e-3 * ms);
+    const kpp_status s = r->run->finish();
+    if (s < 0) r->status = s;
+  }
+}
+
+void serve_loop(kpp_server* srv) {
+  (void)hipSetDevice(srv->ctx->device);
+  for (;;) {
+    std::vector<ServeReq*> admitted;
+    {
+      std::unique_lock<std::mutex> lk(srv->mu);
+      // admission in arrival order; a request whose system is busy waits
+      // without holding back later ones, one that does not fit stops the scan
+      for (auto it = srv->queue.begin(); it != srv->queue.end();) {
+        ServeReq* r = *it;
+        if (std::find(srv->busy.begin(), srv->busy.end(), r->sys) != srv->busy.end()) {
+          ++it;
+          continue;
+        }
+        if (srv->n_active >= srv->max_active || srv->bytes_active + r->footprint > srv->budget ||
+            srv->groups_active + r->groups > srv->cu_budget)
+          break;
+        srv->bytes_active += r->footprint;
+        srv->groups_active += r->groups;
+        srv->n_active += 1;
+        srv->peak_active = std::max(srv->peak_active, srv->n_active);
+        srv->peak_bytes = std::max<uint64_t>(srv->peak_bytes, srv->bytes_active);
+        r->t_admit = now_seconds();
+        srv->busy.push_back(r->sys);
+        admitted.push_back(r);
+        it = srv->queue.erase(it);
+      }
+      if (admitted.empty() && srv->active.empty()) {
+        if (srv->stopping && srv->queue.empty()) return;
+        srv->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+        continue;
+      }
+    }
+    for (ServeReq* r : admitted) {
+      srv->active.push_back(r);
+      if (!serve_start(srv, r)) {
+        serve_complete(srv, r);
+      }
+    }
+    serve_round(srv);
+    // runs that ended start their next refinement round or complete
+    for (ServeReq* r : srv->active) {
+      if (r->complete) continue;
+      if (r->status < 0) {
+        serve_complete(srv, r);
+        continue;
+      }
+      if (r->run && r->run->finished()) {
+        if (!serve_run_ended(srv, r)) serve_complete(srv, r);
+      } else if (!r->run) {
+        serve_complete(srv, r);
+      }
+    }
+    serve_handoff(srv);
+  }
 }
 
 }  // namespace
@@ -1042,6 +1601,161 @@ KPP_API kpp_status kpp_residual_norm(kpp_system* sys, const double* x_dev, doubl
   if (!sys || !x_dev || !out_host) return fail(KPP_ERR_INVALID_ARG, "bad arguments");
   HIP_TRY(hipSetDevice(sys->ctx->device));
   return residual_norm(sys, x_dev, out_host);
+}
+
+
+KPP_API kpp_status kpp_server_create(kpp_context* ctx, uint64_t hbm_budget_bytes, int32_t max_active,
+                                     kpp_server** out) {
+  if (!out) return fail(KPP_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!ctx) return fail(KPP_ERR_INVALID_ARG, "context is NULL");
+  if (max_active < 1 || max_active > kpp::kFusedMaxGroups)
+    return fail(KPP_ERR_INVALID_ARG, "max_active must be in [1, %d]", kpp::kFusedMaxGroups);
+  if (hbm_budget_bytes == 0) return fail(KPP_ERR_INVALID_ARG, "hbm_budget_bytes must be > 0");
+  HIP_TRY(hipSetDevice(ctx->device));
+  auto* srv = new (std::nothrow) kpp_server;
+  if (!srv) return fail(KPP_ERR_OOM, "host allocation failed");
+  srv->ctx = ctx;
+  srv->budget = hbm_budget_bytes;
+  srv->max_active = max_active;
+  srv->cu_budget = ctx->cu_count > 0 ? std::min<int32_t>(ctx->cu_count, kpp::kFusedMaxGroups) : 64;
+  const size_t n_args = static_cast<size_t>(max_active);
+  const size_t n_team = 2 * static_cast<size_t>(max_active) + 2;
+  kpp_status st = KPP_OK;
+  if ((st = dev_alloc(&srv->d_args, n_args)) < 0 || (st = dev_alloc(&srv->d_team, n_team)) < 0 ||
+      hipHostMalloc(reinterpret_cast<void**>(&srv->h_args), n_args * sizeof(kpp::FusedArgs), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&srv->h_team), n_team * sizeof(int32_t), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipEventCreate(&srv->ev[0]) != hipSuccess || hipEventCreate(&srv->ev[1]) != hipSuccess) {
+    dev_free(srv->d_args);
+    dev_free(srv->d_team);
+    if (srv->h_args) (void)hipHostFree(srv->h_args);
+    if (srv->h_team) (void)hipHostFree(srv->h_team);
+    for (auto& e : srv->ev)
+      if (e) (void)hipEventDestroy(e);
+    delete srv;
+    return fail(st < 0 ? st : KPP_ERR_HIP, "server buffers could not be allocated");
+  }
+  try {
+    srv->worker = std::thread(serve_loop, srv);
+  } catch (const std::exception&) {
+    dev_free(srv->d_args);
+    dev_free(srv->d_team);
+    (void)hipHostFree(srv->h_args);
+    (void)hipHostFree(srv->h_team);
+    for (auto& e : srv->ev) (void)hipEventDestroy(e);
+    delete srv;
+    return fail(KPP_ERR_HIP, "the worker thread could not be started");
+  }
+  *out = srv;
+  return KPP_OK;
+}
+
+KPP_API kpp_status kpp_request_footprint(kpp_system* sys, const kpp_params* p, uint64_t* bytes_out) {
+  if (!sys || !bytes_out) return fail(KPP_ERR_INVALID_ARG, "NULL argument");
+  KPP_TRY(check_params(sys, p));
+  *bytes_out = serve_footprint(sys, p, serve_periods(sys, p));
+  return KPP_OK;
+}
+
+KPP_API kpp_status kpp_server_submit(kpp_server* srv, kpp_system* sys, const kpp_params* p, double* x_dev,
+                                     uint64_t* id_out) {
+  if (!srv || !sys || !x_dev || !id_out) return fail(KPP_ERR_INVALID_ARG, "NULL argument");
+  *id_out = 0;
+  if (sys->ctx != srv->ctx) return fail(KPP_ERR_INVALID_ARG, "the system belongs to another context");
+  KPP_TRY(check_params(sys, p));
+  if (p->engine == 1) return fail(KPP_ERR_INVALID_ARG, "the server runs the fused engine only");
+  auto* r = new (std::nothrow) ServeReq;
+  if (!r) return fail(KPP_ERR_OOM, "host allocation failed");
+  r->sys = sys;
+  r->p = *p;
+  r->x = x_dev;
+  r->mixed = p->precision == KPP_MIXED_FP32;
+  r->periods = serve_periods(sys, p);
+  r->cpl = p->block_size <= 128 ? 2 : 1;
+  r->groups = static_cast<int32_t>((sys->n + 64 * r->cpl - 1) / (64 * r->cpl));
+  r->footprint = serve_footprint(sys, p, r->periods);
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (p->block_size > kpp::kFusedMaxBlock || r->groups > srv->cu_budget || r->footprint > srv->budget) {
+    srv->rejected += 1;
+    const size_t need = r->footprint;
+    const int32_t g = r->groups;
+    delete r;
+    return fail(KPP_ERR_REJECTED, "request needs %zu bytes and %d compute units (budget %llu bytes, %d units)", need,
+                g, static_cast<unsigned long long>(srv->budget), srv->cu_budget);
+  }
+  if (srv->stopping) {
+    delete r;
+    return fail(KPP_ERR_INVALID_ARG, "the server is shutting down");
+  }
+  r->id = srv->next_id++;
+  r->t_submit = now_seconds();
+  srv->queue.push_back(r);
+  srv->submitted += 1;
+  *id_out = r->id;
+  srv->cv_work.notify_one();
+  return KPP_OK;
+}
+
+KPP_API kpp_status kpp_server_poll(kpp_server* srv, int32_t cap, double wait_seconds, uint64_t* ids,
+                                   int32_t* status, kpp_result* res, int32_t* n_out) {
+  if (!srv || !n_out || cap < 0 || (cap > 0 && (!ids || !status))) return fail(KPP_ERR_INVALID_ARG, "bad arguments");
+  *n_out = 0;
+  std::unique_lock<std::mutex> lk(srv->mu);
+  if (srv->done.empty() && wait_seconds > 0.0)
+    srv->cv_done.wait_for(lk, std::chrono::duration<double>(wait_seconds), [&] { return !srv->done.empty(); });
+  int32_t n = 0;
+  while (n < cap && !srv->done.empty()) {
+    ServeReq* r = srv->done.front();
+    srv->done.pop_front();
+    ids[n] = r->id;
+    status[n] = r->status;
+    if (res) res[n] = r->res;
+    delete r;
+    ++n;
+  }
+  *n_out = n;
+  return KPP_OK;
+}
+
+KPP_API kpp_status kpp_server_stats(kpp_server* srv, kpp_server_info* out) {
+  if (!srv || !out) return fail(KPP_ERR_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  std::memset(out, 0, sizeof(*out));
+  out->submitted = srv->submitted;
+  out->completed = srv->completed;
+  out->rejected = srv->rejected;
+  out->rounds = srv->rounds;
+  out->queued = static_cast<int32_t>(srv->queue.size());
+  out->active = srv->n_active;
+  out->peak_active = srv->peak_active;
+  out->cu_budget = srv->cu_budget;
+  out->bytes_active = srv->bytes_active;
+  out->peak_bytes = srv->peak_bytes;
+  out->busy_seconds = srv->busy_seconds;
+  return KPP_OK;
+}
+
+KPP_API kpp_status kpp_server_destroy(kpp_server* srv) {
+  if (!srv) return KPP_OK;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stopping = true;
+  }
+  srv->cv_work.notify_all();
+  if (srv->worker.joinable()) srv->worker.join();
+  for (ServeReq* r : srv->done) delete r;
+  srv->done.clear();
+  (void)hipSetDevice(srv->ctx->device);
+  dev_free(srv->d_args);
+  dev_free(srv->d_team);
+  if (srv->h_args) (void)hipHostFree(srv->h_args);
+  if (srv->h_team) (void)hipHostFree(srv->h_team);
+  for (auto& e : srv->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete srv;
+  return KPP_OK;
 }
 
 }  // extern "C"
