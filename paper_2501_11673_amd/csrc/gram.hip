@@ -17,10 +17,9 @@
 namespace kpp {
 namespace {
 
-constexpr int kGT = 64;   // output tile edge
-constexpr int kKc = 32;   // columns per LDS panel
+constexpr int kGT = kGramTile;    // output tile edge
+constexpr int kKc = kGramPanel;   // columns per LDS panel
 constexpr int kGThreads = 256;
-constexpr int kTargetGroups = 1024;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -183,26 +182,6 @@ __global__ __launch_bounds__(kGThreads) void k_gram_reduce(const double* __restr
 }
 
 }  // namespace
-
-void gram_syrk_plan(int32_t s, int64_t n, int32_t nb, int32_t* nchunks, int64_t* chunk, int32_t* ntiles) {
-  const int32_t nt = (s + kGT - 1) / kGT;
-  const int32_t tiles = nt * (nt + 1) / 2;
-  const int64_t panels = std::max<int64_t>(1, (n + kKc - 1) / kKc);
-  const int64_t base = std::max<int64_t>(1, static_cast<int64_t>(nb) * tiles);
-  int64_t c = std::min<int64_t>(panels, std::max<int64_t>(1, kTargetGroups / base));
-  const int64_t per = ((panels + c - 1) / c) * kKc;  // whole panels per chunk
-  c = std::max<int64_t>(1, (n + per - 1) / per);
-  *nchunks = static_cast<int32_t>(c);
-  *chunk = per;
-  *ntiles = tiles;
-}
-
-size_t gram_syrk_work(int32_t s, int64_t n, int32_t nb) {
-  int32_t nc, nt;
-  int64_t chunk;
-  gram_syrk_plan(s, n, nb, &nc, &chunk, &nt);
-  return static_cast<size_t>(nb) * nt * nc * kGT * kGT;
-}
 
 template <typename TA>
 static void launch_syrk(const TA* A, int64_t lda, int64_t n, const int32_t* rows, const int32_t* lens, int32_t s,

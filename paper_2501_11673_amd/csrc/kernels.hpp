@@ -72,6 +72,9 @@ void launch_gram_f32(int32_t kind, const float* A, int64_t lda, int64_t n, const
 // Kaczmarz++ Grams A_S A_S^T + lambda I on the matrix cores: 64 x 64 lower
 // tiles x column chunks, 16x16x4 MFMA (FP64, or FP32 in / FP32 accumulate),
 // FP64 partial tiles summed in chunk order.  gram_syrk_plan gives the split.
+constexpr int kGramTile = 64;
+constexpr int kGramPanel = 32;
+constexpr int kGramTargetGroups = 1024;
 void gram_syrk_plan(int32_t s, int64_t n, int32_t nb, int32_t* nchunks, int64_t* chunk, int32_t* ntiles);
 size_t gram_syrk_work(int32_t s, int64_t n, int32_t nb);
 void launch_gram_syrk(const double* A, int64_t lda, int64_t n, const int32_t* rows, const int32_t* lens, int32_t s,

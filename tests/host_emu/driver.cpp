@@ -1,0 +1,94 @@
+// Solver and server scenarios through the C ABI on the CPU stand-ins: every
+// kernel argument range is checked, and the sanitizers the test builds with
+// check the host code (heap, undefined behaviour, data races).
+#include <hip/hip_runtime.h>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+#include <thread>
+#include <chrono>
+#include "kpp.h"
+
+static double* dev_vec(size_t n, double v) {
+  void* p; hipMalloc(&p, n * 8); double* d = (double*)p; for (size_t i = 0; i < n; ++i) d[i] = v; return d;
+}
+#define CHECK(x) do { kpp_status s_ = (x); if (s_ < 0) { std::printf("FAIL %s -> %d: %s\n", #x, s_, kpp_last_error()); std::exit(1);} } while (0)
+
+static void solve_case(const char* name, int kind, int64_t m, int64_t n, int s, int memo, int part, int nblocks,
+                       int engine, int prec, int64_t T, double tol) {
+  kpp_context* ctx; CHECK(kpp_context_create(0, nullptr, &ctx));
+  double* A = dev_vec(m * n, 0.5); double* b = dev_vec(m, 1.0); double* x = dev_vec(n, 0.0);
+  kpp_system* sys; CHECK(kpp_system_create(ctx, kind, m, n, A, n, b, &sys));
+  for (int rep = 0; rep < 2; ++rep) {
+    kpp_params p; CHECK(kpp_params_default(&p, kind));
+    p.block_size = s; p.memo = memo; p.fixed_partition = part; p.num_blocks = nblocks; p.engine = engine;
+    p.precision = prec; p.max_iters = T * (rep + 1) / 2; p.tol = tol; p.seed = 31; p.lambda = 1e-3;
+    kpp_result r; kpp_status st = kpp_solve(sys, &p, x, &r);
+    if (st < 0) { std::printf("FAIL %s: %d %s\n", name, st, kpp_last_error()); std::exit(1); }
+    std::printf("%-22s T=%-6lld st=%d iters=%lld misses=%lld hits=%lld rounds=%d\n", name, (long long)p.max_iters, st,
+                (long long)r.iters, (long long)r.memo_misses, (long long)r.memo_hits, r.refinements);
+  }
+  CHECK(kpp_system_destroy(sys)); CHECK(kpp_context_destroy(ctx));
+  hipFree(A); hipFree(b); hipFree(x);
+}
+
+static void serve_case() {
+  kpp_context* ctx; CHECK(kpp_context_create(0, nullptr, &ctx));
+  struct J { int kind; int64_t m, n; int s; int prec; double tol; };
+  std::vector<J> jobs = {{1, 500, 500, 64, 0, 1e-10}, {1, 1100, 1100, 128, 1, 1e-6}, {1, 300, 300, 32, 1, 1e-10},
+                         {0, 900, 350, 50, 0, 1e-10}, {1, 1500, 1500, 128, 0, 1e-10}, {0, 400, 1200, 64, 1, 1e-8}};
+  std::vector<kpp_system*> syss; std::vector<double*> xs; std::vector<double*> bufs;
+  kpp_server* srv; CHECK(kpp_server_create(ctx, 64ull << 30, 16, &srv));
+  std::vector<uint64_t> ids;
+  for (auto& j : jobs) {
+    double* A = dev_vec(j.m * j.n, 0.5); double* b = dev_vec(j.m, 1.0); double* x = dev_vec(j.n, 0.0);
+    bufs.push_back(A); bufs.push_back(b); xs.push_back(x);
+    kpp_system* sys; CHECK(kpp_system_create(ctx, j.kind, j.m, j.n, A, j.n, b, &sys)); syss.push_back(sys);
+    kpp_params p; CHECK(kpp_params_default(&p, j.kind));
+    p.block_size = j.s; p.precision = j.prec; p.tol = j.tol; p.max_iters = 200000; p.seed = 7;
+    p.memo = KPP_MEMO_ONLINE;
+    uint64_t id; CHECK(kpp_server_submit(srv, sys, &p, x, &id)); ids.push_back(id);
+  }
+  // a second request on system 3
+  { kpp_params p; CHECK(kpp_params_default(&p, 0)); p.block_size = 50; p.tol = 1e-10; p.seed = 7;
+    uint64_t id; CHECK(kpp_server_submit(srv, syss[3], &p, xs[3], &id)); ids.push_back(id); }
+  size_t got = 0;
+  for (long it = 0; it < 200000000L && got < ids.size(); ++it) {
+    uint64_t rid[16]; int32_t st[16]; kpp_result res[16]; int32_t n = 0;
+    CHECK(kpp_server_poll(srv, 16, 0.0, rid, st, res, &n));
+    for (int i = 0; i < n; ++i)
+      std::printf("served id=%llu st=%d iters=%lld rounds=%d queued=%.4f total=%.4f\n", (unsigned long long)rid[i], st[i],
+                  (long long)res[i].iters, res[i].refinements, res[i].seconds_queued, res[i].seconds_total);
+    got += n;
+  }
+  kpp_server_info info; CHECK(kpp_server_stats(srv, &info));
+  std::printf("server: completed=%lld rounds=%lld peak_active=%d peak_bytes=%llu\n", (long long)info.completed,
+              (long long)info.rounds, info.peak_active, (unsigned long long)info.peak_bytes);
+  CHECK(kpp_server_destroy(srv));
+  for (auto* s : syss) CHECK(kpp_system_destroy(s));
+  for (auto* p : bufs) hipFree(p);
+  for (auto* p : xs) hipFree(p);
+  CHECK(kpp_context_destroy(ctx));
+  if (got != ids.size()) { std::printf("FAIL: %zu of %zu served\n", got, ids.size()); std::exit(1); }
+}
+
+int main(int argc, char** argv) {
+  const char* only = argc > 1 ? argv[1] : "";
+  if (!*only || !std::strcmp(only, "solve")) {
+    for (int eng : {1, 2}) {
+      solve_case("c1", 0, 1000, 200, 20, 1, 1, 0, eng, 0, 600, 0.0);
+      solve_case("c2_small", 1, 1000, 1000, 128, 1, 1, 0, eng, 0, 320, 0.0);
+      solve_case("c2_small_partition", 1, 1000, 1000, 128, 2, 1, 0, eng, 0, 160, 0.0);
+      solve_case("c3_small", 0, 6000, 700, 256, 2, 1, 0, eng, 0, 200, 0.0);
+      solve_case("c4_small", 0, 300, 5000, 64, 1, 1, 0, eng, 0, 200, 0.0);
+      solve_case("tiny_under_off", 0, 30, 90, 7, 0, 1, 0, eng, 0, 150, 0.0);
+      solve_case("tiny_fixed_subsets", 0, 80, 30, 9, 2, 0, 11, eng, 0, 200, 0.0);
+    }
+    solve_case("mixed_c3_small", 0, 6000, 700, 256, 2, 1, 0, 0, 1, 20000, 1e-10);
+    solve_case("mixed_psd", 1, 1000, 1000, 128, 1, 1, 0, 0, 1, 20000, 1e-10);
+  }
+  if (!*only || !std::strcmp(only, "serve")) serve_case();
+  std::printf("EMU OK\n");
+  return 0;
+}

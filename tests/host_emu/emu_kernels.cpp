@@ -1,0 +1,215 @@
+// CPU stand-ins for the library's kernel launchers (host-logic test): every
+// device range a kernel would touch is checked against the live allocations
+// of the stand-in runtime, and the solver state evolves with a modelled block
+// residual so that checkpoints, stops and refinement rounds occur.  Nothing
+// here computes the method; parity of the numbers is tested on the GPU.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+
+#include "kernels.hpp"
+
+namespace kpp {
+namespace {
+double model_rr(int64_t t) { return std::pow(0.985, static_cast<double>(t)); }
+void emu_step(DevState* ds, int32_t zeta, bool* stop) {
+  emu_check(ds, sizeof(DevState), "DevState");
+  DevState& s = *ds;
+  const double rr = model_rr(s.t);
+  const int64_t period = 2 * static_cast<int64_t>(zeta);
+  const int64_t ph = s.t % period;
+  if (ph < zeta) s.E0 += rr; else s.E1 += rr;
+  if (stop) *stop = false;
+  if (ph == period - 1) {
+    s.ckpts += 1;
+    s.last_E1 = s.E1;
+    s.cand = s.E1 <= s.thr;
+    if (stop) *stop = s.cand;
+    s.E0 = s.E1 = 0.0;
+  }
+  s.t += 1;
+}
+void check_rows(const int32_t* rows, int32_t sb, const char* what) {
+  emu_check(rows, sizeof(int32_t) * sb, what);
+}
+void check_A(const void* A, size_t esz, int64_t lda, const int32_t* rows, int32_t sb, int64_t n, const char* what) {
+  for (int32_t i = 0; i < sb; ++i) {
+    const int64_t r = rows[i];
+    if (r < 0) { std::fprintf(stderr, "EMU: negative row %lld in %s\n", (long long)r, what); std::abort(); }
+    emu_check(static_cast<const char*>(A) + esz * (r * lda), esz * n, what);
+  }
+}
+}  // namespace
+
+void launch_block_gemv_partial(const double* A, int64_t lda, int64_t n, const int32_t* rows, int32_t sb,
+                               const double* x, double* rpart, int32_t P, int64_t, hipStream_t) {
+  check_rows(rows, sb, "gemv rows");
+  check_A(A, 8, lda, rows, sb, n, "gemv A");
+  emu_check(x, 8 * n, "gemv x");
+  emu_check(rpart, 8 * sb * P, "gemv rpart");
+}
+void launch_block_project(const double* rpart, int32_t P, const double* b, const int32_t* rows, int32_t sb,
+                          const double* Ginv, int32_t ldl, double* y, DevState* ds, int32_t zeta, int32_t,
+                          hipStream_t) {
+  emu_check(rpart, 8 * sb * P, "project rpart");
+  check_rows(rows, sb, "project rows");
+  for (int i = 0; i < sb; ++i) emu_check(b + rows[i], 8, "project b");
+  emu_check(Ginv, 8 * (static_cast<size_t>(sb - 1) * ldl + sb), "project Ginv");
+  emu_check(y, 8 * sb, "project y");
+  emu_step(ds, zeta, nullptr);
+}
+void launch_update(int32_t kind, const double* A, int64_t lda, int64_t n, const int32_t* rows, int32_t sb,
+                   const double* y, const DevState* ds, double, double* x, double* mom, hipStream_t) {
+  check_rows(rows, sb, "update rows");
+  if (kind == 0) check_A(A, 8, lda, rows, sb, n, "update A");
+  emu_check(y, 8 * sb, "update y");
+  emu_check(ds, sizeof(DevState), "update ds");
+  emu_check(x, 8 * n, "update x");
+  emu_check(mom, 8 * n, "update mom");
+}
+static void check_slots(const double* G, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
+                        const int32_t* slot_of, int64_t span, const char* what) {
+  emu_check(lens, 4 * nb, what);
+  emu_check(slot_of, 4 * nb, what);
+  for (int k = 0; k < nb; ++k) {
+    if (lens[k] < 1 || lens[k] > s) { std::fprintf(stderr, "EMU: %s len %d\n", what, lens[k]); std::abort(); }
+    emu_check(G + slot_of[k] * stride, 8 * span, what);
+  }
+}
+void launch_gram(int32_t kind, const double* A, int64_t lda, int64_t n, const int32_t* rows, const int32_t* lens,
+                 int32_t s, int32_t nb, double, double* G, int64_t stride, const int32_t* slot_of, double* ws,
+                 hipStream_t, const int32_t* only) {
+  if (nb <= 0) return;
+  check_slots(G, stride, s, lens, nb, slot_of, static_cast<int64_t>(s) * s, "gram slots");
+  for (int k = 0; k < nb; ++k) {
+    if (only && !only[k]) continue;
+    check_rows(rows + static_cast<int64_t>(k) * s, lens[k], "gram rows");
+    check_A(A, 8, lda, rows + static_cast<int64_t>(k) * s, lens[k], n, "gram A");
+  }
+  if (kind == 0) emu_check(ws, 8 * gram_syrk_work(s, n, nb), "gram ws");
+}
+void launch_gram_f32(int32_t kind, const float* A, int64_t lda, int64_t n, const int32_t* rows, const int32_t* lens,
+                     int32_t s, int32_t nb, double, double* G, int64_t stride, const int32_t* slot_of, double* ws,
+                     hipStream_t) {
+  if (nb <= 0) return;
+  check_slots(G, stride, s, lens, nb, slot_of, static_cast<int64_t>(s) * s, "gram32 slots");
+  for (int k = 0; k < nb; ++k) check_A(A, 4, lda, rows + static_cast<int64_t>(k) * s, lens[k], n, "gram32 A");
+  if (kind == 0) emu_check(ws, 8 * gram_syrk_work(s, n, nb), "gram32 ws");
+}
+void launch_gram_syrk(const double*, int64_t, int64_t, const int32_t*, const int32_t*, int32_t, int32_t, double,
+                      double*, int64_t, const int32_t*, const int32_t*, double*, hipStream_t) {}
+void launch_gram_syrk_f32(const float*, int64_t, int64_t, const int32_t*, const int32_t*, int32_t, int32_t, double,
+                          double*, int64_t, const int32_t*, double*, hipStream_t) {}
+void launch_cholesky(double* G, int32_t s, int64_t stride, const int32_t* lens, int32_t nb, const int32_t* slot_of,
+                     int32_t* err, hipStream_t, FactorCheck chk) {
+  if (nb <= 0) return;
+  check_slots(G, stride, s, lens, nb, slot_of, 3 * static_cast<int64_t>(s) * s, "cholesky slots");
+  emu_check(err, 4, "cholesky err");
+  if (chk.flag) { emu_check(chk.flag, 4 * nb, "cholesky flag"); for (int k = 0; k < nb; ++k) chk.flag[k] = 0; }
+}
+void launch_factor_inverse(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
+                           const int32_t* slot_of, hipStream_t, FactorCheck, const int32_t*) {
+  if (nb <= 0) return;
+  check_slots(slots, stride, s, lens, nb, slot_of, 3 * static_cast<int64_t>(s) * s, "inverse slots");
+}
+void launch_factor_small(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
+                         const int32_t* slot_of, int32_t want_inverse, int32_t* err, hipStream_t, FactorCheck chk) {
+  if (nb <= 0) return;
+  check_slots(slots, stride, s, lens, nb, slot_of, (want_inverse ? 2 : 1) * static_cast<int64_t>(s) * s,
+              "factor_small slots");
+  emu_check(err, 4, "factor_small err");
+  if (chk.flag) { emu_check(chk.flag, 4 * nb, "factor_small flag"); for (int k = 0; k < nb; ++k) chk.flag[k] = (k % 3 == 0); }
+  if (chk.counter) emu_check(chk.counter, 4, "factor_small counter");
+}
+void launch_scatter_rows(const int32_t* stage_rows, const int32_t* stage_lens, const int32_t* slot_of, int32_t nb,
+                         int32_t s, int32_t* rows, int32_t* lens, hipStream_t) {
+  if (nb <= 0) return;
+  emu_check(stage_rows, 4 * static_cast<size_t>(nb) * s, "scatter stage rows");
+  emu_check(stage_lens, 4 * nb, "scatter stage lens");
+  emu_check(slot_of, 4 * nb, "scatter slot_of");
+  for (int k = 0; k < nb; ++k) {
+    emu_check(rows + static_cast<int64_t>(slot_of[k]) * s, 4 * s, "scatter rows");
+    emu_check(lens + slot_of[k], 4, "scatter lens");
+    for (int i = 0; i < s; ++i) rows[slot_of[k] * s + i] = stage_rows[k * s + i];
+    lens[slot_of[k]] = stage_lens[k];
+  }
+}
+void launch_residual_sq(const double* A, int64_t lda, int64_t m, int64_t n, const double* x, const double* b,
+                        double* part, int32_t, double* out, hipStream_t) {
+  emu_check(A, 8 * (static_cast<size_t>(m - 1) * lda + n), "residual A");
+  emu_check(x, 8 * n, "residual x");
+  emu_check(b, 8 * m, "residual b");
+  emu_check(part, 8 * m, "residual rowsq");
+  emu_check(out, 8, "residual out");
+  *out = 0.0;
+}
+void launch_check_finite(const double* A, int64_t lda, int64_t m, int64_t n, const double* b, int32_t* flag,
+                         hipStream_t) {
+  emu_check(A, 8 * (static_cast<size_t>(m - 1) * lda + n), "finite A");
+  emu_check(b, 8 * m, "finite b");
+  emu_check(flag, 4, "finite flag");
+}
+void launch_state_init(DevState* ds, double rho0, double thr, hipStream_t) {
+  emu_check(ds, sizeof(DevState), "state init");
+  DevState s{};
+  s.rho = rho0; s.c = (1 - rho0) / (1 + rho0); s.thr = thr; s.rho_before = rho0;
+  *ds = s;
+}
+void launch_convert_f32(const double* A, int64_t lda, int64_t m, int64_t n, float* out, hipStream_t) {
+  emu_check(A, 8 * (static_cast<size_t>(m - 1) * lda + n), "convert A");
+  emu_check(out, 4 * static_cast<size_t>(m) * n, "convert out");
+}
+static std::map<const double*, int> g_rounds;
+void launch_residual_vec(const double* A, int64_t lda, int64_t m, int64_t n, const double* x, const double* b,
+                         double* r, double* rowsq, double* out, hipStream_t) {
+  emu_check(A, 8 * (static_cast<size_t>(m - 1) * lda + n), "rvec A");
+  emu_check(x, 8 * n, "rvec x");
+  emu_check(b, 8 * m, "rvec b");
+  emu_check(r, 8 * m, "rvec r");
+  emu_check(rowsq, 8 * m, "rvec rowsq");
+  emu_check(out, 8, "rvec out");
+  const int k = g_rounds[x]++;
+  double bb = 0.0;
+  for (int64_t i = 0; i < m; ++i) bb += b[i] * b[i];
+  *out = bb * std::pow(1e-4, 2.0 * k);
+  if (*out < bb * 1e-30) g_rounds[x] = 0;
+}
+void launch_axpy1(double* x, const double* d, int64_t n, hipStream_t) {
+  emu_check(x, 8 * n, "axpy x");
+  emu_check(d, 8 * n, "axpy d");
+}
+static void emu_fused(const FusedArgs& a, int32_t cpl, int32_t G, bool fp32) {
+  const int64_t s = a.s;
+  emu_check(a.step_slot, 4 * static_cast<size_t>(a.W), "fused step_slot");
+  emu_check(a.x, 8 * a.n, "fused x");
+  emu_check(a.mom, 8 * a.n, "fused mom");
+  emu_check(a.part, 8 * 2 * static_cast<size_t>(G) * s, "fused part");
+  emu_check(a.flags, 4 * static_cast<size_t>(G) * 32, "fused flags");
+  emu_check(a.err, 4, "fused err");
+  if (G * 64 * cpl < a.n) { std::fprintf(stderr, "EMU: fused team too small\n"); std::abort(); }
+  for (int k = 0; k < a.W; ++k) {
+    const int q = a.step_slot[k];
+    emu_check(a.lens + q, 4, "fused lens");
+    const int sb = a.lens[q];
+    if (sb < 1 || sb > s) { std::fprintf(stderr, "EMU: fused sb %d (slot %d, step %d)\n", sb, q, k); std::abort(); }
+    emu_check(a.rows + q * s, 4 * sb, "fused rows");
+    check_A(a.A, fp32 ? 4 : 8, a.lda, a.rows + q * s, sb, a.n, "fused A");
+    for (int i = 0; i < sb; ++i) emu_check(a.b + a.rows[q * s + i], 8, "fused b");
+    emu_check(a.L + q * a.slot_stride + s * s, 8 * static_cast<size_t>(s) * s, "fused Ginv");
+    bool stop = false;
+    emu_step(a.ds, a.zeta, &stop);
+    if (a.stop_on_cand && stop) break;
+  }
+}
+void launch_fused(int32_t, bool a_fp32, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t) {
+  emu_fused(a, cpl, groups, a_fp32);
+}
+void launch_fused_multi(int32_t, bool a_fp32, const FusedArgs* args, const int32_t* team_start, int32_t nteams,
+                        int32_t total, int32_t cpl, hipStream_t) {
+  emu_check(args, sizeof(FusedArgs) * nteams, "multi args");
+  emu_check(team_start, 4 * (nteams + 1), "multi team_start");
+  if (team_start[0] != 0 || team_start[nteams] != total || total > 256) { std::fprintf(stderr, "EMU: team table\n"); std::abort(); }
+  for (int t = 0; t < nteams; ++t) emu_fused(args[t], cpl, team_start[t + 1] - team_start[t], a_fp32);
+}
+}  // namespace kpp
