@@ -11,7 +11,9 @@ One "step" is one full solve from x0 = 0 with an empty memo cache (every
 factorization is paid inside the timed region).  value = block steps per
 second over the timed solves; ms_per_step = time to tolerance per solve.
 The same solves are then timed with mixed precision (FP32 block products,
-FP64 factors and iterative refinement) and reported under "mixed".
+FP64 factors and iterative refinement) and reported under "mixed", and the
+serving workload (continuous batching of 512 solves arriving at 200/s) is
+replayed in real time and reported under "serving" (p50/p99 latency).
 
 Also printed: the roofline of the dominant kernel (the step kernel, timed with
 HIP events inside the library on the stream it runs on) and the CPU oracle
@@ -39,6 +41,11 @@ def parse():
     ap.add_argument("--team-groups", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=202)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB three times (HBM counter calibration)")
+    ap.add_argument("--serve-requests", type=int, default=512)
     return ap.parse_args()
 
 
@@ -68,6 +75,89 @@ def cpu_baseline(A, b, s, lam, tol, seed):
             "sample": f"one full CD++ solve of the n=4096 system to {tol:g} "
                       f"({res.iters} block steps, {dt:.2f} s, converged={res.converged})",
             "time_to_tol_s": dt}
+
+
+def serving(kpp, torch, dev, num_requests, seed=5):
+    """Serving workload: Poisson arrivals (200/s) of CD++ solves, n uniform over
+    {512, ..., 8192} (each a seeded matrix from a pool of 8 per size, outlier
+    spectrum as the n = 4096 workload), own right-hand side b = A x*, tolerance
+    1e-6 or 1e-10, mixed precision.  Arrivals are replayed in real time against
+    the server; latency = completion - scheduled arrival."""
+    import numpy as np
+
+    import synth
+
+    reqs = synth.serving_workload(num_requests=num_requests, rate_per_s=200.0, seed=seed)
+    pool = {}
+    for r in reqs:
+        key = (r["n"], r["pool_index"])
+        if key not in pool:
+            pool[key] = synth.serving_matrix(r["n"], r["pool_index"], device="cuda").A
+    stream = torch.cuda.Stream(device=dev)
+    ctx = kpp.kpp_context_create(0, stream.cuda_stream)
+    systems, xs, bs, params = [], [], [], []
+    for r in reqs:
+        A = pool[(r["n"], r["pool_index"])]
+        g = torch.Generator(device=dev)
+        g.manual_seed(r["x_seed"])
+        xstar = torch.randn(r["n"], dtype=torch.float64, device=dev, generator=g)
+        b = A @ xstar
+        bs.append(b)
+        xs.append(torch.zeros(r["n"], dtype=torch.float64, device=dev))
+        torch.cuda.synchronize()
+        systems.append(kpp.kpp_system_create(ctx, kpp.KPP_CD_PSD, r["n"], r["n"], A.data_ptr(), r["n"], b.data_ptr()))
+        p = kpp.kpp_params_default(kpp.KPP_CD_PSD)
+        p.block_size = 128
+        p.lambda_ = 1e-8
+        p.tol = r["tol"]
+        p.memo = kpp.KPP_MEMO_ONLINE
+        p.precision = kpp.KPP_MIXED_FP32
+        p.seed = r["x_seed"]
+        p.max_iters = 400_000
+        params.append(p)
+    torch.cuda.synchronize()
+    srv = kpp.kpp_server_create(ctx, 96 << 30, 64)
+    arrivals = [r["arrival_s"] for r in reqs]
+    done = {}
+    rid_of = {}
+    i = 0
+    t0 = time.perf_counter()
+    while len(done) < len(reqs):
+        now = time.perf_counter() - t0
+        while i < len(reqs) and arrivals[i] <= now:
+            rid_of[kpp.kpp_server_submit(srv, systems[i], params[i], xs[i].data_ptr())] = i
+            i += 1
+        wait = min(0.002, max(0.0, arrivals[i] - now)) if i < len(reqs) else 0.02
+        for rid, st, res in kpp.kpp_server_poll(srv, 64, wait):
+            done[rid_of[rid]] = (st, res, time.perf_counter() - t0)
+        if now > 600:
+            break
+    wall = time.perf_counter() - t0
+    info = kpp.kpp_server_stats(srv).as_dict()
+    kpp.kpp_server_destroy(srv)
+    for h in systems:
+        kpp.kpp_system_destroy(h)
+    kpp.kpp_context_destroy(ctx)
+    lat = np.array([done[k][2] - arrivals[k] for k in sorted(done)])
+    ok = [done[k][0] == kpp.KPP_OK and done[k][1].true_rel_res <= reqs[k]["tol"] for k in sorted(done)]
+    iters = sum(done[k][1].iters for k in done)
+    by_n = {}
+    for k in sorted(done):
+        by_n.setdefault(reqs[k]["n"], []).append(done[k][2] - arrivals[k])
+    last = max(v[2] for v in done.values()) if done else wall
+    return {
+        "workload": f"{len(reqs)} CD++ solves, Poisson 200/s, n in {{512..8192}}, tol 1e-6/1e-10, mixed precision",
+        "completed": len(done), "all_reached_tol": bool(all(ok)) and len(done) == len(reqs),
+        "p50_latency_ms": float(1e3 * np.percentile(lat, 50)), "p99_latency_ms": float(1e3 * np.percentile(lat, 99)),
+        "mean_latency_ms": float(1e3 * lat.mean()),
+        "latency_ms_by_n": {str(n): {"p50": float(1e3 * np.percentile(v, 50)), "p99": float(1e3 * np.percentile(v, 99)),
+                                     "count": len(v)} for n, v in sorted(by_n.items())},
+        "requests_per_s": len(done) / last, "block_iters_per_s": iters / last,
+        "makespan_s": last, "arrival_span_s": arrivals[-1],
+        "peak_active": info["peak_active"], "rounds": info["rounds"],
+        "device_busy_fraction": info["busy_seconds"] / last,
+        "max_true_rel_res_over_tol": float(max(done[k][1].true_rel_res / reqs[k]["tol"] for k in done)),
+    }
 
 
 def main():
@@ -163,6 +253,15 @@ def main():
         "kernel_ms_per_solve": 1e3 * ktime / args.steps,
         "roofline": roofline,
     }
+    if args.calibrate_copy > 0:
+        src = torch.empty(args.calibrate_copy << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = args.calibrate_copy << 20
+        del src, dst
     # the same workload with mixed precision (FP32 block products, FP64 refinement)
     x_fp64 = x.clone()
     pm = kpp.kpp_params_default(kpp.KPP_CD_PSD)
@@ -175,18 +274,18 @@ def main():
         x.zero_()
         return kpp.kpp_solve(h, pm, x.data_ptr())
 
-    for _ in range(args.warmup):
+    for _ in range(args.warmup if not args.no_mixed else 0):
         one_mixed()
     torch.cuda.synchronize()
     mres = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(args.steps if not args.no_mixed else 0):
         mres.append(one_mixed())
     torch.cuda.synchronize()
     melapsed = time.perf_counter() - t0
     miters = sum(r.iters for _, r in mres)
-    mlast = mres[-1][1]
-    line["mixed"] = {
+    mlast = mres[-1][1] if mres else None
+    line["mixed"] = None if not mres else {
         "time_to_tol_ms": 1e3 * melapsed / args.steps,
         "block_iters_per_s": miters / melapsed,
         "iters_per_solve": miters / args.steps,
@@ -202,6 +301,8 @@ def main():
     }
     kpp.kpp_system_destroy(h)
     kpp.kpp_context_destroy(ctx)
+    if not args.no_serving:
+        line["serving"] = serving(kpp, torch, dev, args.serve_requests)
     if not args.no_cpu_baseline:
         Ah = A.cpu().numpy()
         bh = b.cpu().numpy()

@@ -100,7 +100,9 @@ typedef struct kpp_params {
   int32_t keep_memo;          /* 1: keep factors from an earlier solve with the same
                                  schedule settings; 0: start with an empty cache          */
   int32_t refine_max_rounds;  /* mixed precision: outer refinement rounds (default 12)   */
-  double inner_tol;           /* mixed precision: inner relative tolerance (default 1e-5) */
+  double inner_tol;           /* mixed precision: relative tolerance of each inner solve
+                                 (default 1e-2); an inner solve also ends when its
+                                 residual estimate stalls (FP32 precision floor)    */
   int32_t engine;             /* 0: auto, 1: one launch per phase, 2: fused persistent  */
   int32_t team_groups;        /* fused engine: workgroups sharing one step (0: auto)    */
   double reserved1[4];
@@ -210,8 +212,10 @@ KPP_API kpp_status kpp_residual_norm(kpp_system* sys, const double* x_dev, doubl
  * systems on the context is allowed).  Requests wait in arrival order and are
  * admitted while (a) the sum of their device-memory footprints (memo cache,
  * FP32 copy of A, state and staging; the caller's A, b, x not counted) stays
- * within hbm_budget_bytes, (b) their workgroups (one per compute unit, ceil(n /
- * 128) for block size <= 128, else ceil(n / 64)) fit on the device, (c) at most
+ * within hbm_budget_bytes, (b) their workgroups (one per compute unit:
+ * ceil(n / (64 c)), c = columns per lane, the most the block size s allows --
+ * FP64: 2 for s <= 128, else 1; mixed precision: 4 for s <= 128, else 1) fit on
+ * the device, (c) at most
  * max_active are active, and (d) no other request on the same system is active;
  * a request held back only by (d) does not hold back later ones.  Every round
  * advances each active request by a window of its own length, all of them in

@@ -46,7 +46,12 @@ namespace {
 
 constexpr int kT = 256;
 constexpr int kFlagStride = KPP_FLAG_STRIDE;  // uint32 words between flags
-constexpr int kTileMax = 64;                  // tile doubles per lane
+// Tile entries per lane: 64 doubles, or 128 floats (the same registers) when a
+// lane holds at least four columns; a wave then still holds 32 rows or fewer.
+template <typename TA, int CPL>
+struct TileElems {
+  static constexpr int value = (sizeof(TA) == 4 && CPL >= 4) ? 128 : 64;
+};
 static_assert(kFlagStride * kFusedMaxGroups <= kFlagWordsAlloc, "flag area too small");
 
 __device__ __forceinline__ double ld_coherent(const double* p) {
@@ -80,11 +85,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 // the block and columns past the matrix are clamped, not masked: those entries
 // always meet a zero (x is zero beyond n, y is zero beyond the block), and A
 // is finite (checked when the system is created), so they contribute nothing.
-template <int CPL, typename TA>
-__device__ __forceinline__ void load_tile(TA (&tile)[kTileMax], const TA* __restrict__ A,
+template <int CPL, typename TA, int TE>
+__device__ __forceinline__ void load_tile(TA (&tile)[TE], const TA* __restrict__ A,
                                           int64_t lda, int64_t n, const int32_t* __restrict__ rows,
                                           int sb, int wv, int lane, int64_t col0) {
-  constexpr int RMAX = kTileMax / CPL;
+  constexpr int RMAX = TE / CPL;
   const int myrow = rows[min(wv + 4 * (lane & (RMAX - 1)), sb - 1)];
 #pragma unroll
   for (int r = 0; r < RMAX; ++r) {
@@ -115,8 +120,10 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     ticks[p] += now_ - tick_last;                     \
     tick_last = now_;                                 \
   }
-  constexpr int RMAX = kTileMax / CPL;   // rows per wave held in registers (power of two)
+  constexpr int TE = TileElems<TA, CPL>::value;
+  constexpr int RMAX = TE / CPL;   // rows per wave held in registers (power of two, <= 64)
   constexpr int RSHIFT = (RMAX == 64) ? 0 : (RMAX == 32) ? 1 : (RMAX == 16) ? 2 : (RMAX == 8) ? 3 : 4;
+  static_assert(RMAX >= 4 && RMAX <= 64, "rows per wave");
   __shared__ int32_t rsbuf[2][256];
   __shared__ double rv[256];
   __shared__ double yv[256];
@@ -148,7 +155,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     st = *a.ds;
     abort_flag = 0;
   }
-  TA tile[kTileMax];
+  TA tile[TE];
   int q = a.step_slot[0];
   int sb = a.lens[q];
   int cur = 0;

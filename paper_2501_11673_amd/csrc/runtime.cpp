@@ -298,15 +298,27 @@ kpp_status residual_norm(kpp_system* sys, const double* x, double* out) {
 }
 
 // Fused-engine geometry: columns per lane (cpl) and workgroups per step.  A
-// wave holds ceil(s/4) block rows of cpl columns in registers (at most 64
-// doubles per lane), so cpl <= 256/s; the smallest cpl that brings the team
-// down to the target size is taken.
-bool fused_geometry(int64_t n, int32_t s, int32_t target_groups, int32_t* cpl, int32_t* groups) {
+// lane holds 64 FP64 tile entries, or 128 FP32 ones when cpl >= 4; the four
+// waves of a workgroup hold 4 * entries / cpl block rows, which must cover s.
+int32_t fused_tile_elems(bool fp32, int32_t cpl) { return (fp32 && cpl >= 4) ? 128 : 64; }
+
+bool fused_cpl_fits(int32_t s, bool fp32, int32_t cpl) {
+  return s <= kpp::kFusedMaxBlock && 4 * fused_tile_elems(fp32, cpl) / cpl >= s;
+}
+
+int32_t fused_cpl_max(int32_t s, bool fp32) {
+  int32_t c = 1;
+  while (c < 16 && fused_cpl_fits(s, fp32, 2 * c)) c *= 2;
+  return c;
+}
+
+// The smallest cpl that brings the team down to the target size (default 32
+// workgroups: a step is bound by the load rate of each compute unit as much as
+// by the exchange between workgroups, and 32 was the fastest at n = 4096).
+bool fused_geometry(int64_t n, int32_t s, int32_t target_groups, bool fp32, int32_t* cpl, int32_t* groups) {
   if (s > kpp::kFusedMaxBlock) return false;
   const int32_t gmax = target_groups > 0 ? target_groups : 32;
-  const int32_t rows_per_wave = (s + 3) / 4;
-  int32_t cmax = 1;
-  while (cmax < 16 && 2 * cmax * rows_per_wave <= 64) cmax *= 2;
+  const int32_t cmax = fused_cpl_max(s, fp32);
   int32_t c = 1;
   while (c < cmax && (n + 64 * c - 1) / (64 * c) > gmax) c *= 2;
   const int64_t g = (n + 64 * c - 1) / (64 * c);
@@ -333,7 +345,14 @@ struct CoreOpts {
   double rho0 = 0.0;
   int32_t keep_memo = 0;
   int64_t max_iters = 0;
+  // end the run when the window residual estimate E1 has not fallen below
+  // kStallRatio times its value kStallWindows window ends earlier (an inner
+  // low-precision solve at its precision floor); 0 = never
+  int32_t stop_on_stall = 0;
 };
+
+constexpr int kStallWindows = 8;
+constexpr double kStallRatio = 0.9;
 
 struct CoreStats {
   int64_t iters = 0, hits = 0, misses = 0, launches = 0;
@@ -388,13 +407,13 @@ class CoreRun {
       return fail(KPP_ERR_INVALID_ARG, "%s", e.what());
     }
     if (force_cpl > 0) {
-      fused_ = s_ * force_cpl <= 256 && s_ <= kpp::kFusedMaxBlock;
+      fused_ = fused_cpl_fits(s_, fp32_, force_cpl);
       cpl_ = force_cpl;
       groups_ = static_cast<int32_t>((n_ + 64 * cpl_ - 1) / (64 * cpl_));
       if (groups_ > kpp::kFusedMaxGroups) fused_ = false;
       if (!fused_) return fail(KPP_ERR_INVALID_ARG, "no fused geometry with %d columns per lane", force_cpl);
     } else {
-      if (p->engine != 1) fused_ = fused_geometry(n_, s_, p->team_groups, &cpl_, &groups_);
+      if (p->engine != 1) fused_ = fused_geometry(n_, s_, p->team_groups, fp32_, &cpl_, &groups_);
       if (p->engine == 2 && !fused_)
         return fail(KPP_ERR_INVALID_ARG, "n=%lld is too wide for the fused engine", (long long)n_);
     }
@@ -587,7 +606,14 @@ class CoreRun {
         converged_ = true;
       }
     }
-    if (converged_ || t_ >= max_iters_) {
+    if (o_.stop_on_stall && ran > 0 && (t_ % period_) == 0 && !converged_) {
+      e1_hist_.push_back(hs_.last_E1);
+      const size_t k = e1_hist_.size();
+      if (k > static_cast<size_t>(kStallWindows) &&
+          !(e1_hist_[k - 1] < kStallRatio * e1_hist_[k - 1 - kStallWindows]))
+        stalled_ = true;
+    }
+    if (converged_ || stalled_ || t_ >= max_iters_) {
       finished_ = true;
     } else if (w.done == w.W) {
       cur_ ^= 1;
@@ -773,9 +799,10 @@ class CoreRun {
   int cur_ = 0;
   bool have_next_ = false;
   int64_t t_ = 0, hits_ = 0, misses_ = 0, launches_ = 0;
-  bool converged_ = false, finished_ = false;
+  bool converged_ = false, finished_ = false, stalled_ = false;
   double true_rel_ = NAN, t_factor_ = 0.0, t_kernel_ = 0.0;
   kpp::DevState hs_{};
+  std::vector<double> e1_hist_;
 };
 
 // A run driven on its own: one launch per window.
@@ -915,6 +942,7 @@ kpp_status solve_mixed(kpp_system* sys, const kpp_params* p, double* x, kpp_resu
     CoreOpts o;
     o.tol = p->inner_tol;
     o.confirm = 0;
+    o.stop_on_stall = 1;
     o.rho0 = rho;
     o.keep_memo = rounds > 0 ? 1 : p->keep_memo;
     o.max_iters = p->max_iters - iters;
@@ -1149,6 +1177,7 @@ bool serve_next_run(kpp_server* srv, ServeReq* r) {
   CoreOpts o;
   o.tol = r->p.inner_tol;
   o.confirm = 0;
+  o.stop_on_stall = 1;
   o.rho0 = r->rho;
   o.keep_memo = r->rounds > 0 ? 1 : r->p.keep_memo;
   o.max_iters = r->p.max_iters - r->iters;
@@ -1391,7 +1420,7 @@ KPP_API kpp_status kpp_params_default(kpp_params* p, int32_t kind) {
   p->seed = 0x2501116730ull;
   p->keep_memo = 0;
   p->refine_max_rounds = 12;
-  p->inner_tol = 1e-3;
+  p->inner_tol = 1e-2;
   p->engine = 0;
   p->team_groups = 0;
   return KPP_OK;
@@ -1673,7 +1702,8 @@ KPP_API kpp_status kpp_server_submit(kpp_server* srv, kpp_system* sys, const kpp
   r->x = x_dev;
   r->mixed = p->precision == KPP_MIXED_FP32;
   r->periods = serve_periods(sys, p);
-  r->cpl = p->block_size <= 128 ? 2 : 1;
+  // the most columns per lane: the fewest compute units per request
+  r->cpl = fused_cpl_max(p->block_size, r->mixed);
   r->groups = static_cast<int32_t>((sys->n + 64 * r->cpl - 1) / (64 * r->cpl));
   r->footprint = serve_footprint(sys, p, r->periods);
   std::lock_guard<std::mutex> lk(srv->mu);

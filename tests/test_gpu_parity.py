@@ -304,10 +304,15 @@ def test_errors(env):
 # ---------------------------------------------------------------------------
 
 MIXED_CASES = [
-    ("c1", "general", lambda: synth.config("c1"), 20, 1e-3, "online"),
-    ("c2_small", "psd", lambda: synth.config("c2_small"), 128, 1e-8, "online"),
-    ("c3_small", "general", lambda: synth.config("c3_small"), 256, 1e-8, "fixed"),
-    ("c4_small", "general", lambda: synth.config("c4_small"), 64, 1e-4, "online"),
+    # name, kind, builder, s, lam, mode, team_groups (0: default team)
+    ("c1", "general", lambda: synth.config("c1"), 20, 1e-3, "online", 0),
+    ("c2_small", "psd", lambda: synth.config("c2_small"), 128, 1e-8, "online", 0),
+    # 4 workgroups: 4 columns per lane, FP32 tile of 128 entries per lane
+    ("c2_small_cpl4", "psd", lambda: synth.config("c2_small"), 128, 1e-8, "online", 4),
+    ("c3_small", "general", lambda: synth.config("c3_small"), 256, 1e-8, "fixed", 0),
+    # s = 256 in a team of 11 workgroups (one column per lane)
+    ("c3_small_team11", "general", lambda: synth.config("c3_small"), 256, 1e-8, "fixed", 6),
+    ("c4_small", "general", lambda: synth.config("c4_small"), 64, 1e-4, "online", 0),
 ]
 
 
@@ -316,7 +321,7 @@ def test_mixed_precision_reaches_fp64_accuracy(env, case):
     """Iterative refinement recovers a true FP64 relative residual of 1e-10;
     the error against the FP64 oracle's converged solution is stated."""
     kpp, torch, dev, ctx = env
-    name, kind, build, s, lam, mode = case
+    name, kind, build, s, lam, mode, team_groups = case
     sysm = build()
     A, b = sysm.A, sysm.b
     m, n = A.shape
@@ -329,6 +334,7 @@ def test_mixed_precision_reaches_fp64_accuracy(env, case):
     p.seed = 77
     p.memo = MODES[mode]
     p.precision = kpp.KPP_MIXED_FP32
+    p.team_groups = team_groups
     Ad = torch.from_numpy(A).to(dev)
     bd = torch.from_numpy(b).to(dev)
     xd = torch.zeros(n, dtype=torch.float64, device=dev)
@@ -369,3 +375,33 @@ def test_mixed_precision_reaches_fp64_accuracy(env, case):
 def synth_kappa(sysm):
     sp = np.abs(np.asarray(sysm.spectrum))
     return float(sp.max() / sp.min())
+
+
+def test_mixed_inner_round_ends_at_precision_floor(env):
+    """An inner tolerance below what FP32 products can reach (1e-7 relative on
+    a kappa = 1e5 system) does not trap the inner solve: a round ends once its
+    residual estimate stalls and refinement still reaches 1e-10."""
+    kpp, torch, dev, ctx = env
+    sysm = synth.config("c2_small")
+    A, b = sysm.A, sysm.b
+    n = A.shape[0]
+    p = kpp.kpp_params_default(kpp.KPP_CD_PSD)
+    p.block_size = 128
+    p.lambda_ = 1e-8
+    p.tol = 1e-10
+    p.max_iters = 200_000
+    p.seed = 77
+    p.precision = kpp.KPP_MIXED_FP32
+    p.inner_tol = 1e-7
+    Ad = torch.from_numpy(A).to(dev)
+    bd = torch.from_numpy(b).to(dev)
+    xd = torch.zeros(n, dtype=torch.float64, device=dev)
+    h = kpp.kpp_system_create(ctx, kpp.KPP_CD_PSD, n, n, Ad.data_ptr(), n, bd.data_ptr())
+    try:
+        st, res = kpp.kpp_solve(h, p, xd.data_ptr())
+    finally:
+        kpp.kpp_system_destroy(h)
+    print(f"[mixed floor] status {st}, {res.refinements} rounds, {res.iters} steps, true {res.true_rel_res:.2e}",
+          flush=True)
+    assert st == kpp.KPP_OK and res.true_rel_res <= 1e-10
+    assert res.iters < 50_000
