@@ -99,7 +99,7 @@ typedef struct kpp_params {
   uint64_t seed;              /* schedule seed (SplitMix64 draws; see kpp_schedule_generate) */
   int32_t keep_memo;          /* 1: keep factors from an earlier solve with the same
                                  schedule settings; 0: start with an empty cache          */
-  int32_t refine_max_rounds;  /* mixed precision: outer refinement rounds (default 12)   */
+  int32_t refine_max_rounds;  /* mixed precision: outer refinement rounds (default 40)   */
   double inner_tol;           /* mixed precision: relative tolerance of each inner solve
                                  (default 1e-2); an inner solve also ends when its
                                  residual estimate stalls (FP32 precision floor)    */

@@ -129,7 +129,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
   __shared__ double yv[256];
   __shared__ double stage[256];
   __shared__ double wred[KIND == 0 ? 4 * 64 * CPL : 1];
-  __shared__ double red[1];
+  __shared__ double red[4];
   __shared__ double bc_c;
   __shared__ int bc_stop;
   __shared__ int abort_flag;
@@ -160,15 +160,12 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
   int sb = a.lens[q];
   int cur = 0;
   load_tile<CPL>(tile, Amat, a.lda, n, a.rows + static_cast<int64_t>(q) * s, sb, wv, lane, col0);
-  // wave 0 forms r: its lane holds b at block rows lane + 64 u of the current step
-  double bval[4] = {0.0, 0.0, 0.0, 0.0};
-  if (tid < sb) rsbuf[0][tid] = a.rows[static_cast<int64_t>(q) * s + tid];
-  if (wv == 0) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = lane + 64 * u;
-      if (i < sb) bval[u] = a.b[a.rows[static_cast<int64_t>(q) * s + i]];
-    }
+  // thread tid forms r at block row tid: it holds b there for the current step
+  double bval = 0.0;
+  if (tid < sb) {
+    const int32_t row = a.rows[static_cast<int64_t>(q) * s + tid];
+    rsbuf[0][tid] = row;
+    bval = a.b[row];
   }
   __syncthreads();
 
@@ -274,56 +271,49 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     __syncthreads();
     KPP_MARK(3)
     if (abort_flag) break;
-    // r = sum_g p_g - b_S by wave 0 (it has no loads in flight), the
-    // next step's rows and b values right after (used after this step)
-    double bnext[4] = {0.0, 0.0, 0.0, 0.0};
-    if (wv == 0) {
-      double rr_lane = 0.0;
+    // r = sum_g p_g - b_S: wave w sums block rows 64 w .. 64 w + 63, one row
+    // per lane, so that every wave's partial loads are a single batch; then
+    // the next step's rows and b values (used after this step)
+    double bnext = 0.0;
+    const int nu = (sb + 63) >> 6;
+    if (wv < nu) {
+      const int c = min(tid, sb - 1);   // rows past the block: clamped, sum dropped
+      double acc = 0.0;
+      int g = 0;
+      for (; g + 32 <= G; g += 32) {
+        double t32[32];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int i = lane + 64 * u;
-        if (i < sb) {
-          double acc = 0.0;
-          int g = 0;
-          for (; g + 32 <= G; g += 32) {
-            double t32[32];
+        for (int uu = 0; uu < 32; ++uu) t32[uu] = ld_coherent(&Pb[static_cast<size_t>(g + uu) * s + c]);
 #pragma unroll
-            for (int uu = 0; uu < 32; ++uu) t32[uu] = ld_coherent(&Pb[static_cast<size_t>(g + uu) * s + i]);
+        for (int uu = 0; uu < 32; ++uu) acc += t32[uu];
+      }
+      for (; g + 8 <= G; g += 8) {
+        double t8[8];
 #pragma unroll
-            for (int uu = 0; uu < 32; ++uu) acc += t32[uu];
-          }
-          for (; g + 8 <= G; g += 8) {
-            double t8[8];
+        for (int uu = 0; uu < 8; ++uu) t8[uu] = ld_coherent(&Pb[static_cast<size_t>(g + uu) * s + c]);
 #pragma unroll
-            for (int uu = 0; uu < 8; ++uu) t8[uu] = ld_coherent(&Pb[static_cast<size_t>(g + uu) * s + i]);
-#pragma unroll
-            for (int uu = 0; uu < 8; ++uu) acc += t8[uu];
-          }
-          for (; g < G; ++g) acc += ld_coherent(&Pb[static_cast<size_t>(g) * s + i]);
-          const double ri = acc - bval[u];
-          rv[i] = ri;
-          rr_lane = fma(ri, ri, rr_lane);
-        }
+        for (int uu = 0; uu < 8; ++uu) acc += t8[uu];
+      }
+      for (; g < G; ++g) acc += ld_coherent(&Pb[static_cast<size_t>(g) * s + c]);
+      double rr_w = 0.0;
+      if (tid < sb) {
+        const double ri = acc - bval;
+        rv[tid] = ri;
+        rr_w = ri * ri;
       }
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) rr_lane += __shfl_down(rr_lane, off, 64);
-      if (lane == 0) red[0] = rr_lane;
-      // next step's rows and b (a dependent pair: issued before the tile loads
-      // so that waiting for the row indices does not wait for the tile)
-      if (have_next) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int i = lane + 64 * u;
-          if (i < sbn) {
-            const int32_t row = Rn[i];
-            rsbuf[cur ^ 1][i] = row;
-            bnext[u] = a.b[row];
-          }
-        }
-      }
-      // wave 0's share of the next tile, after its partial loads have landed
-      if (KIND == 1 && KPP_PREFETCH && have_next) load_tile<CPL>(tile, Amat, a.lda, n, Rn, sbn, wv, lane, col0);
+      for (int off = 32; off > 0; off >>= 1) rr_w += __shfl_down(rr_w, off, 64);
+      if (lane == 0) red[wv] = rr_w;
     }
+    // next step's rows and b (a dependent pair: issued before wave 0's tile
+    // loads so that waiting for the row indices does not wait for the tile)
+    if (have_next && tid < sbn) {
+      const int32_t row = Rn[tid];
+      rsbuf[cur ^ 1][tid] = row;
+      bnext = a.b[row];
+    }
+    // wave 0's share of the next tile, after its partial loads have landed
+    if (wv == 0 && KIND == 1 && KPP_PREFETCH && have_next) load_tile<CPL>(tile, Amat, a.lda, n, Rn, sbn, wv, lane, col0);
     __syncthreads();
     KPP_MARK(4)
 
@@ -362,7 +352,8 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
 
     // 5. scalars: c for this step, window sums, checkpoint
     if (tid == 0) {
-      const double rr = red[0];
+      double rr = red[0];
+      for (int w = 1; w < ((sb + 63) >> 6); ++w) rr += red[w];
       const double rho = st.rho;
       st.c = (1.0 - rho) / (1.0 + rho);
       bc_c = st.c;
@@ -449,8 +440,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     }
     q = qn;
     sb = sbn;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) bval[u] = bnext[u];
+    bval = bnext;
     cur ^= 1;
     __syncthreads();
     KPP_MARK(6)

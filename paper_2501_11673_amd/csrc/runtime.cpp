@@ -351,7 +351,7 @@ struct CoreOpts {
   int32_t stop_on_stall = 0;
 };
 
-constexpr int kStallWindows = 8;
+constexpr int kStallWindows = 12;
 constexpr double kStallRatio = 0.9;
 
 struct CoreStats {
@@ -1419,7 +1419,7 @@ KPP_API kpp_status kpp_params_default(kpp_params* p, int32_t kind) {
   p->max_iters = 1000000;
   p->seed = 0x2501116730ull;
   p->keep_memo = 0;
-  p->refine_max_rounds = 12;
+  p->refine_max_rounds = 40;
   p->inner_tol = 1e-2;
   p->engine = 0;
   p->team_groups = 0;
