@@ -7,6 +7,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <functional>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -179,6 +180,16 @@ void destroy_buffers(kpp_system* s) {
   s->cap_slots = 0;
 }
 
+// Wait for this system's work on the side stream (memo-miss factorizations):
+// the stream runs in order, so the last event recorded for each staging
+// buffer covers everything the system enqueued there.  Other systems' work on
+// the shared side stream is not waited for.
+kpp_status wait_side_work(kpp_system* sys) {
+  HIP_TRY(hipEventSynchronize(sys->ev_fact[0][1]));
+  HIP_TRY(hipEventSynchronize(sys->ev_fact[1][1]));
+  return KPP_OK;
+}
+
 // Grow the slot table to hold `need` slots for block size s (keeps contents).
 kpp_status ensure_slots(kpp_system* sys, int32_t need, int32_t s) {
   hipStream_t st = sys->ctx->stream;
@@ -196,8 +207,10 @@ kpp_status ensure_slots(kpp_system* sys, int32_t need, int32_t s) {
   }
   if (need <= sys->cap_slots) return KPP_OK;
   // kernels in flight on either stream may read the old table
-  HIP_TRY(hipStreamSynchronize(st));
-  HIP_TRY(hipStreamSynchronize(sys->ctx->side));
+  if (sys->cap_slots > 0) {
+    HIP_TRY(hipStreamSynchronize(st));
+    KPP_TRY(wait_side_work(sys));
+  }
   const int32_t cap = std::max<int32_t>(need, std::max<int32_t>(16, sys->cap_slots * 2));
   double* L = nullptr;
   int32_t *rows = nullptr, *lens = nullptr;
@@ -225,8 +238,10 @@ kpp_status ensure_slots(kpp_system* sys, int32_t need, int32_t s) {
 kpp_status ensure_stage(kpp_system* sys, int idx, size_t ints) {
   if (ints <= sys->stage_cap[idx]) return KPP_OK;
   const size_t cap = std::max<size_t>(ints, std::max<size_t>(4096, sys->stage_cap[idx] * 2));
-  HIP_TRY(hipStreamSynchronize(sys->ctx->stream));
-  HIP_TRY(hipStreamSynchronize(sys->ctx->side));
+  if (sys->stage_cap[idx] > 0) {
+    HIP_TRY(hipStreamSynchronize(sys->ctx->stream));
+    KPP_TRY(wait_side_work(sys));
+  }
   dev_free(sys->d_stage[idx]);
   if (sys->h_stage[idx]) (void)hipHostFree(sys->h_stage[idx]);
   sys->h_stage[idx] = nullptr;
@@ -241,8 +256,10 @@ kpp_status ensure_stage(kpp_system* sys, int idx, size_t ints) {
 kpp_status ensure_gram_ws(kpp_system* sys, int idx, size_t doubles) {
   if (doubles <= sys->gram_ws_cap[idx]) return KPP_OK;
   const size_t cap = std::max<size_t>(doubles, sys->gram_ws_cap[idx] * 2);
-  HIP_TRY(hipStreamSynchronize(sys->ctx->stream));
-  HIP_TRY(hipStreamSynchronize(sys->ctx->side));
+  if (sys->gram_ws_cap[idx] > 0) {
+    HIP_TRY(hipStreamSynchronize(sys->ctx->stream));
+    KPP_TRY(wait_side_work(sys));
+  }
   dev_free(sys->gram_ws[idx]);
   sys->gram_ws_cap[idx] = 0;
   KPP_TRY(dev_alloc(&sys->gram_ws[idx], cap));
@@ -351,6 +368,16 @@ struct CoreOpts {
   int32_t stop_on_stall = 0;
 };
 
+// host seconds spent in window planning, split for the serving profile
+// (KPP_SERVE_PROFILE): buffer growth, schedule and slots, factor enqueue
+thread_local double t_prof_grow = 0.0, t_prof_sched = 0.0, t_prof_enqueue = 0.0, t_prof_slots = 0.0;
+thread_local int64_t n_prof_slot_growth = 0;
+
+double wall_now() {
+  using clock = std::chrono::steady_clock;
+  return std::chrono::duration<double>(clock::now().time_since_epoch()).count();
+}
+
 constexpr int kStallWindows = 12;
 constexpr double kStallRatio = 0.9;
 
@@ -417,9 +444,23 @@ class CoreRun {
       if (p->engine == 2 && !fused_)
         return fail(KPP_ERR_INVALID_ARG, "n=%lld is too wide for the fused engine", (long long)n_);
     }
-    // memo cache: reuse only for an identical schedule definition; the slot
-    // table is sized for this block size before any slot is handed out
-    KPP_TRY(ensure_slots(sys, 16, s_));
+    // memo cache: reuse only for an identical schedule definition.  The slot
+    // table and the staging buffers are sized for the whole run before any
+    // slot is handed out: growing them later waits for the device (a freed
+    // buffer may still be read).  An online collection holds about
+    // B0 (1 + ln(T / B0)) blocks after T steps (Section 5.2); 4 B0 covers
+    // T up to ~20 B0, and the table still grows past that if needed.
+    int64_t est_blocks = 16;
+    if (mode_ == kpp::MemoMode::Fixed) est_blocks = sch_->num_blocks();
+    if (mode_ == kpp::MemoMode::Online)
+      est_blocks = std::min<int64_t>(static_cast<int64_t>(4.0 * B0) + 16, std::max<int64_t>(16, max_iters_ + 1));
+    if (mode_ == kpp::MemoMode::Off) est_blocks = 2 * periods_ * period_;
+    KPP_TRY(ensure_slots(sys, static_cast<int32_t>(std::min<int64_t>(est_blocks, 1 << 24)), s_));
+    {
+      const size_t stage = static_cast<size_t>(periods_ * period_) * (s_ + 4) + 16;
+      KPP_TRY(ensure_stage(sys, 0, stage));
+      KPP_TRY(ensure_stage(sys, 1, stage));
+    }
     const bool same_sig = sys->memo_valid && o.keep_memo && sys->sig_s == s_ && sys->sig_memo == p->memo &&
                           sys->sig_nb == p->num_blocks && sys->sig_part == p->fixed_partition &&
                           sys->sig_seed == p->seed && sys->sig_lambda == p->lambda &&
@@ -436,7 +477,6 @@ class CoreRun {
       sys->sig_lambda = p->lambda;
       sys->sig_prec = fp32_ ? 1 : 0;
     }
-    if (mode_ == kpp::MemoMode::Fixed) KPP_TRY(ensure_slots(sys, sch_->num_blocks(), s_));
     // launch engine: column chunks of the block gemv
     P_ = static_cast<int32_t>((n_ + kChunk - 1) / kChunk);
     if (!fused_ && static_cast<int64_t>(s_) * P_ > sys->rpart_cap) {
@@ -464,8 +504,8 @@ class CoreRun {
       return KPP_OK;
     }
     KPP_TRY(plan(win_[0], 0, 0));
-    KPP_TRY(enqueue_factor(win_[0], st_));  // nothing to overlap with yet
-    win_[0].on_side = false;
+    KPP_TRY(enqueue_factor(win_[0], side_));
+    win_[0].on_side = true;
     return KPP_OK;
   }
 
@@ -545,17 +585,38 @@ class CoreRun {
   // After the launch is enqueued: state copy-back, and the next window planned
   // and factored on the side stream while this one runs.
   kpp_status after_launch() {
+    KPP_TRY(copy_back());
+    KPP_TRY(plan_ahead());
+    return enqueue_ahead();
+  }
+
+  // The three parts of after_launch, for callers that plan several runs at
+  // once: the state copy-back (HIP calls on the main stream), the next
+  // window's host planning (touches only this run and its system: runs of
+  // different systems may plan concurrently), and its factorization on the
+  // side stream (HIP calls).
+  kpp_status copy_back() {
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(sys_->h_ds, sys_->ds, sizeof(kpp::DevState), hipMemcpyDeviceToHost, st_));
     HIP_TRY(hipMemcpyAsync(sys_->h_err, sys_->err, sizeof(int32_t), hipMemcpyDeviceToHost, st_));
+    return KPP_OK;
+  }
+  kpp_status plan_ahead() {
     const Window& w = win_[cur_];
     const int64_t t_next = w.t0 + w.W;
+    planned_ = false;
     if (!have_next_ && t_next < max_iters_) {
       KPP_TRY(plan(win_[cur_ ^ 1], t_next, cur_ ^ 1));
-      KPP_TRY(enqueue_factor(win_[cur_ ^ 1], side_));
-      win_[cur_ ^ 1].on_side = true;
-      have_next_ = true;
+      planned_ = true;
     }
+    return KPP_OK;
+  }
+  kpp_status enqueue_ahead() {
+    if (!planned_) return KPP_OK;
+    planned_ = false;
+    KPP_TRY(enqueue_factor(win_[cur_ ^ 1], side_));
+    win_[cur_ ^ 1].on_side = true;
+    have_next_ = true;
     return KPP_OK;
   }
 
@@ -622,10 +683,10 @@ class CoreRun {
     return KPP_OK;
   }
 
-  // Drain the side stream (factorizations planned past the stop included) and
-  // report the run.
+  // Wait for the system's side-stream work (factorizations planned past the
+  // stop included) and report the run.
   kpp_status end(CoreStats* cs) {
-    HIP_TRY(hipStreamSynchronize(side_));
+    KPP_TRY(wait_side_work(sys_));
     if (o_.confirm && (!converged_ || std::isnan(true_rel_))) {
       double rn = 0.0;
       KPP_TRY(residual_norm(sys_, x_, &rn));
@@ -657,9 +718,9 @@ class CoreRun {
     return converged_ ? KPP_OK : KPP_NOT_CONVERGED;
   }
 
-  // Wait for this run's side-stream work (used on every exit path).
+  // Wait for this system's side-stream work (used on every exit path).
   void drain() {
-    if (begun_ && side_) (void)hipStreamSynchronize(side_);
+    if (begun_) (void)wait_side_work(sys_);
   }
 
  private:
@@ -675,6 +736,12 @@ class CoreRun {
   };
 
   kpp_status plan(Window& w, int64_t t0, int idx) {
+    const double tp0 = wall_now();
+    const double grow0 = t_prof_grow;
+    struct Done {
+      double t0, g0;
+      ~Done() { t_prof_sched += (wall_now() - t0) - (t_prof_grow - g0); }
+    } done{tp0, grow0};
     kpp_system* sys = sys_;
     const int32_t s = s_;
     w.t0 = t0;
@@ -713,13 +780,20 @@ class CoreRun {
       }
       w.step_slot[k] = q;
     }
-    if (mode_ != kpp::MemoMode::Off) KPP_TRY(ensure_slots(sys, sys->used_slots, s));
+    if (mode_ != kpp::MemoMode::Off) {
+      const double ts = wall_now();
+      if (sys->used_slots > sys->cap_slots) ++n_prof_slot_growth;
+      KPP_TRY(ensure_slots(sys, sys->used_slots, s));
+      t_prof_slots += wall_now() - ts;
+    }
     w.nb = static_cast<int32_t>(pending.size());
     w.o_len = static_cast<size_t>(w.nb) * s;
     w.o_slot = w.o_len + w.nb;
     w.o_step = w.o_slot + w.nb;
     const size_t need = w.o_step + static_cast<size_t>(w.W) + static_cast<size_t>(w.nb);  // + flags
+    const double tg = wall_now();
     KPP_TRY(ensure_stage(sys, idx, need));
+    t_prof_grow += wall_now() - tg;
     int32_t* stage = sys->h_stage[idx];
     for (int32_t k = 0; k < w.nb; ++k) {
       const int32_t b = pending[k];
@@ -735,6 +809,10 @@ class CoreRun {
 
   // upload the window's staging and factor its memo misses on `fs`
   kpp_status enqueue_factor(const Window& w, hipStream_t fs) {
+    struct Done {
+      double t0;
+      ~Done() { t_prof_enqueue += wall_now() - t0; }
+    } done{wall_now()};
     kpp_system* sys = sys_;
     const int32_t s = s_;
     const int idx = w.idx;
@@ -799,7 +877,7 @@ class CoreRun {
   int cur_ = 0;
   bool have_next_ = false;
   int64_t t_ = 0, hits_ = 0, misses_ = 0, launches_ = 0;
-  bool converged_ = false, finished_ = false, stalled_ = false;
+  bool converged_ = false, finished_ = false, stalled_ = false, planned_ = false;
   double true_rel_ = NAN, t_factor_ = 0.0, t_kernel_ = 0.0;
   kpp::DevState hs_{};
   std::vector<double> e1_hist_;
@@ -1042,8 +1120,84 @@ size_t serve_footprint(const kpp_system* sys, const kpp_params* p, int32_t perio
 
 }  // namespace
 
+// A small pool of host threads that run one indexed job at a time (the
+// calling thread takes part); used to plan the next windows of many runs.
+// Indices are handed out under the mutex and tagged with the job's
+// generation, so an index runs exactly once and a thread that is late for one
+// job cannot take indices of the next.
+class HostPool {
+ public:
+  explicit HostPool(int nthreads) {
+    for (int i = 0; i < nthreads; ++i) threads_.emplace_back([this] { work(); });
+  }
+  ~HostPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      quit_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : threads_) t.join();
+  }
+  // fn(i) for i in [0, n), returns when all are done
+  void run(int n, const std::function<void(int)>& fn) {
+    if (n <= 0) return;
+    uint64_t gen;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      fn_ = &fn;
+      n_ = n;
+      next_ = 0;
+      done_ = 0;
+      gen = ++gen_;
+    }
+    cv_.notify_all();
+    drain(gen);
+    std::unique_lock<std::mutex> lk(mu_);
+    cv_done_.wait(lk, [&] { return done_ == n_; });
+    fn_ = nullptr;
+  }
+
+ private:
+  bool grab(uint64_t gen, int* i, const std::function<void(int)>** fn) {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (gen != gen_ || next_ >= n_) return false;
+    *i = next_++;
+    *fn = fn_;
+    return true;
+  }
+  void drain(uint64_t gen) {
+    int i;
+    const std::function<void(int)>* fn;
+    while (grab(gen, &i, &fn)) {
+      (*fn)(i);
+      std::lock_guard<std::mutex> lk(mu_);
+      if (++done_ == n_) cv_done_.notify_all();
+    }
+  }
+  void work() {
+    uint64_t seen = 0;
+    for (;;) {
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return quit_ || gen_ != seen; });
+        if (quit_) return;
+        seen = gen_;
+      }
+      drain(seen);
+    }
+  }
+  std::vector<std::thread> threads_;
+  std::mutex mu_;
+  std::condition_variable cv_, cv_done_;
+  const std::function<void(int)>* fn_ = nullptr;
+  int n_ = 0, next_ = 0, done_ = 0;
+  uint64_t gen_ = 0;
+  bool quit_ = false;
+};
+
 struct kpp_server {
   kpp_context* ctx = nullptr;
+  std::unique_ptr<HostPool> pool;
   uint64_t budget = 0;
   int32_t max_active = 0;
   int32_t cu_budget = 0;
@@ -1068,6 +1222,11 @@ struct kpp_server {
   uint64_t bytes_active = 0, peak_bytes = 0;
   double busy_seconds = 0.0;
   int32_t groups_active = 0;
+  // KPP_SERVE_PROFILE=1: host seconds per worker-loop section, printed at destroy
+  bool prof = false;
+  double prof_s[6] = {0, 0, 0, 0, 0, 0};
+  double prof_grow = 0.0, prof_sched = 0.0, prof_enqueue = 0.0, prof_slots = 0.0;   // from the worker thread
+  int64_t prof_slot_growth = 0;
 };
 
 namespace {
@@ -1272,6 +1431,7 @@ void serve_round(kpp_server* srv) {
     if (!placed) groups.push_back({r});
   }
   std::vector<ServeReq*> launched;
+  double tp = now_seconds();
   (void)hipEventRecord(srv->ev[0], st);
   int32_t off_args = 0, off_team = 0;
   for (auto& g : groups) {
@@ -1315,11 +1475,38 @@ void serve_round(kpp_server* srv) {
     off_team += n_t + 1;
   }
   (void)hipEventRecord(srv->ev[1], st);
+  if (srv->prof) {
+    const double t = now_seconds();
+    srv->prof_s[1] += t - tp;
+    tp = t;
+  }
+  // next windows: copy-back and factor enqueue in order, host planning in parallel
   for (ServeReq* r : launched) {
-    const kpp_status s = r->run->after_launch();
+    const kpp_status s = r->run->copy_back();
     if (s < 0) r->status = s;
   }
+  srv->pool->run(static_cast<int>(launched.size()), [&](int i) {
+    ServeReq* r = launched[i];
+    if (r->status < 0) return;
+    const kpp_status s = r->run->plan_ahead();
+    if (s < 0) r->status = s;
+  });
+  for (ServeReq* r : launched) {
+    if (r->status < 0) continue;
+    const kpp_status s = r->run->enqueue_ahead();
+    if (s < 0) r->status = s;
+  }
+  if (srv->prof) {
+    const double t = now_seconds();
+    srv->prof_s[2] += t - tp;
+    tp = t;
+  }
   (void)hipStreamSynchronize(st);
+  if (srv->prof) {
+    const double t = now_seconds();
+    srv->prof_s[3] += t - tp;
+    tp = t;
+  }
   float ms = 0.0f;
   (void)hipEventElapsedTime(&ms, srv->ev[0], srv->ev[1]);
   {
@@ -1333,6 +1520,7 @@ void serve_round(kpp_server* srv) {
     const kpp_status s = r->run->finish();
     if (s < 0) r->status = s;
   }
+  if (srv->prof) srv->prof_s[4] += now_seconds() - tp;
 }
 
 void serve_loop(kpp_server* srv) {
@@ -1368,13 +1556,16 @@ void serve_loop(kpp_server* srv) {
         continue;
       }
     }
+    double t0 = now_seconds();
     for (ServeReq* r : admitted) {
       srv->active.push_back(r);
       if (!serve_start(srv, r)) {
         serve_complete(srv, r);
       }
     }
+    if (srv->prof) srv->prof_s[0] += now_seconds() - t0;
     serve_round(srv);
+    t0 = now_seconds();
     // runs that ended start their next refinement round or complete
     for (ServeReq* r : srv->active) {
       if (r->complete) continue;
@@ -1389,6 +1580,14 @@ void serve_loop(kpp_server* srv) {
       }
     }
     serve_handoff(srv);
+    if (srv->prof) {
+      srv->prof_s[5] += now_seconds() - t0;
+      srv->prof_grow = t_prof_grow;
+      srv->prof_sched = t_prof_sched;
+      srv->prof_enqueue = t_prof_enqueue;
+      srv->prof_slots = t_prof_slots;
+      srv->prof_slot_growth = n_prof_slot_growth;
+    }
   }
 }
 
@@ -1648,6 +1847,8 @@ KPP_API kpp_status kpp_server_create(kpp_context* ctx, uint64_t hbm_budget_bytes
   srv->budget = hbm_budget_bytes;
   srv->max_active = max_active;
   srv->cu_budget = ctx->cu_count > 0 ? std::min<int32_t>(ctx->cu_count, kpp::kFusedMaxGroups) : 64;
+  const char* prof_env = std::getenv("KPP_SERVE_PROFILE");
+  srv->prof = prof_env && prof_env[0] == '1';
   const size_t n_args = static_cast<size_t>(max_active);
   const size_t n_team = 2 * static_cast<size_t>(max_active) + 2;
   kpp_status st = KPP_OK;
@@ -1667,6 +1868,7 @@ KPP_API kpp_status kpp_server_create(kpp_context* ctx, uint64_t hbm_budget_bytes
     return fail(st < 0 ? st : KPP_ERR_HIP, "server buffers could not be allocated");
   }
   try {
+    srv->pool.reset(new HostPool(7));
     srv->worker = std::thread(serve_loop, srv);
   } catch (const std::exception&) {
     dev_free(srv->d_args);
@@ -1775,6 +1977,14 @@ KPP_API kpp_status kpp_server_destroy(kpp_server* srv) {
   }
   srv->cv_work.notify_all();
   if (srv->worker.joinable()) srv->worker.join();
+  if (srv->prof)
+    std::fprintf(stderr,
+                 "[kpp serve profile] %lld rounds, host s: start %.3f, prepare+launch %.3f, plan+factor %.3f, "
+                 "wait %.3f, finish %.3f, transitions %.3f (all planning: buffer growth %.3f, schedule %.3f "
+                 "of which slot table %.3f in %lld growths, factor enqueue %.3f); device busy %.3f\n",
+                 static_cast<long long>(srv->rounds), srv->prof_s[0], srv->prof_s[1], srv->prof_s[2], srv->prof_s[3],
+                 srv->prof_s[4], srv->prof_s[5], srv->prof_grow, srv->prof_sched, srv->prof_slots,
+                 static_cast<long long>(srv->prof_slot_growth), srv->prof_enqueue, srv->busy_seconds);
   for (ServeReq* r : srv->done) delete r;
   srv->done.clear();
   (void)hipSetDevice(srv->ctx->device);

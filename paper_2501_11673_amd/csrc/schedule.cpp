@@ -36,23 +36,32 @@ BlockSchedule::BlockSchedule(MemoMode mode, int64_t N, int32_t s, uint64_t seed,
       }
     } else {
       if (num_blocks < 1) throw std::invalid_argument("fixed collection needs num_blocks >= 1");
+      std::iota(perm_.begin(), perm_.end(), 0);
       for (int32_t b = 0; b < num_blocks; ++b) add_subset();
     }
     used_.assign(len_.size(), 0);
+  } else {
+    std::iota(perm_.begin(), perm_.end(), 0);
   }
 }
 
+// Partial Fisher-Yates on the identity permutation (perm_ is the identity on
+// entry and on exit: only the positions the draws touched are put back, so a
+// subset costs O(s log s), not O(N)).
 void BlockSchedule::add_subset() {
-  std::iota(perm_.begin(), perm_.end(), 0);
+  touched_.clear();
   for (int32_t j = 0; j < s_; ++j) {
     int64_t k = j + static_cast<int64_t>(g_.bounded(static_cast<uint64_t>(N_ - j)));
     std::swap(perm_[j], perm_[k]);
+    touched_.push_back(k);
   }
   size_t base = rows_.size();
   rows_.resize(base + s_);
   std::copy(perm_.begin(), perm_.begin() + s_, rows_.begin() + base);
   std::sort(rows_.begin() + base, rows_.end());
   len_.push_back(s_);
+  for (int32_t j = 0; j < s_; ++j) perm_[j] = static_cast<int32_t>(j);
+  for (int64_t k : touched_) perm_[k] = static_cast<int32_t>(k);
 }
 
 int32_t BlockSchedule::next(bool* is_new) {

@@ -79,6 +79,7 @@ class BlockSchedule {
   std::vector<int32_t> len_;
   std::vector<uint8_t> used_;
   std::vector<int32_t> perm_;
+  std::vector<int64_t> touched_;
 };
 
 // B0 of the Bernoulli(min(1, B0 / t)) rule.
