@@ -150,6 +150,22 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     xr[e] = j < n ? a.x[j] : 0.0;
     mr[e] = j < n ? a.mom[j] : 0.0;
   }
+  // dual slice (Kaczmarz++ with m < n): rows d0 + tid + 256 u of [d0, d1)
+  constexpr int DU = 4;
+  double zxr[DU], zmr[DU];
+  const bool dual = KIND == 0 && a.zx != nullptr;
+  int64_t d0 = 0, d1 = 0;
+  if (dual) {
+    const int64_t per = (a.mrows + G - 1) / G;   // at most 256 DU (checked by the host)
+    d0 = min(a.mrows, static_cast<int64_t>(wg) * per);
+    d1 = min(a.mrows, d0 + per);
+  }
+#pragma unroll
+  for (int u = 0; u < DU; ++u) {
+    const int64_t i = d0 + tid + 256 * u;
+    zxr[u] = (dual && i < d1) ? a.zx[i] : 0.0;
+    zmr[u] = (dual && i < d1) ? a.zm[i] : 0.0;
+  }
   DevState st{};
   if (tid == 0) {
     st = *a.ds;
@@ -438,6 +454,25 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
       mr[e] = mn;
       xr[e] = __dadd_rn(__dsub_rn(xr[e], w[e]), __dmul_rn(a.eta, mn));
     }
+    // the same recursion on the dual: w = A_S^T y is A^T applied to y placed
+    // at the block's rows
+    if (dual) {
+#pragma unroll
+      for (int u = 0; u < DU; ++u) {
+        const int64_t i = d0 + tid + 256 * u;
+        if (i < d1) {
+          int l = 0, h = sb;
+          while (l < h) {
+            const int mid = (l + h) >> 1;
+            if (rs[mid] < i) l = mid + 1; else h = mid;
+          }
+          const double yi = (l < sb && rs[l] == i) ? yv[l] : 0.0;
+          const double mn = __dmul_rn(c, __dsub_rn(zmr[u], yi));
+          zmr[u] = mn;
+          zxr[u] = __dadd_rn(__dsub_rn(zxr[u], yi), __dmul_rn(a.eta, mn));
+        }
+      }
+    }
     q = qn;
     sb = sbn;
     bval = bnext;
@@ -460,6 +495,16 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
       if (j < n) {
         a.x[j] = xr[e];
         a.mom[j] = mr[e];
+      }
+    }
+  }
+  if (dual) {
+#pragma unroll
+    for (int u = 0; u < DU; ++u) {
+      const int64_t i = d0 + tid + 256 * u;
+      if (i < d1) {
+        a.zx[i] = zxr[u];
+        a.zm[i] = zmr[u];
       }
     }
   }

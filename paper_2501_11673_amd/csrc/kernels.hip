@@ -670,6 +670,17 @@ __global__ __launch_bounds__(kT) void k_factor_small(double* __restrict__ slots,
   }
 }
 
+// d_j = sum_i A_ij z_i: a workgroup owns 256 consecutive columns and walks
+// the rows in order (coalesced row segments, deterministic sums).
+__global__ __launch_bounds__(kT) void k_gemv_t(const double* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                               const double* __restrict__ z, double* __restrict__ d) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+  if (j >= n) return;
+  double acc = 0.0;
+  for (int64_t i = 0; i < m; ++i) acc = fma(A[i * lda + j], z[i], acc);
+  d[j] = acc;
+}
+
 // Block rows and lengths from a staging area into their slots.
 __global__ __launch_bounds__(kT) void k_scatter_rows(const int32_t* __restrict__ stage_rows,
                                                      const int32_t* __restrict__ stage_lens,
@@ -809,6 +820,11 @@ void launch_residual_vec(const double* A, int64_t lda, int64_t m, int64_t n, con
   const unsigned g = static_cast<unsigned>((m + 3) / 4);
   hipLaunchKernelGGL(k_residual_vec, dim3(g), dim3(kT), 0, st, A, lda, m, n, x, b, r, rowsq);
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(kT), 0, st, rowsq, m, out);
+}
+
+void launch_gemv_t(const double* A, int64_t lda, int64_t m, int64_t n, const double* z, double* d, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_gemv_t, dim3(static_cast<unsigned>((n + kT - 1) / kT)), dim3(kT), 0, st, A, lda, m, n, z, d);
 }
 
 void launch_axpy1(double* x, const double* d, int64_t n, hipStream_t st) {

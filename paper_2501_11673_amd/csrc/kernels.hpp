@@ -133,6 +133,9 @@ void launch_residual_vec(const double* A, int64_t lda, int64_t m, int64_t n, con
 // x += d  (FP64)
 void launch_axpy1(double* x, const double* d, int64_t n, hipStream_t st);
 
+// d = A^T z (m x n row-major A, FP64, fixed summation order over the rows)
+void launch_gemv_t(const double* A, int64_t lda, int64_t m, int64_t n, const double* z, double* d, hipStream_t st);
+
 // Arguments of the fused persistent engine (fused.hip): W block steps of one
 // system per launch, `groups` workgroups each owning 64 * cpl columns.
 struct FusedArgs {
@@ -161,6 +164,12 @@ struct FusedArgs {
   uint64_t* phase_ticks;     // optional (nullptr): wall-clock ticks per step phase, workgroup 0
   int32_t stop_on_cand;      // 1: end the launch after a checkpoint whose stop test passes
   int32_t pad0;
+  // Kaczmarz++ with m < n only (optional, nullptr = off): the dual of the
+  // iterate and of the momentum, x = A^T zx and m = A^T zm in exact
+  // arithmetic (m FP64 entries each, in and out like x and mom)
+  double* zx;
+  double* zm;
+  int64_t mrows;
 };
 
 constexpr int kFusedPhases = 8;

@@ -128,6 +128,8 @@ struct kpp_system {
   size_t gram_ws_cap[2] = {0, 0};
   double* rvec = nullptr;
   double* dvec = nullptr;
+  double* zx = nullptr;    // mixed precision, wide Kaczmarz++: duals of the inner iterate and momentum
+  double* zm = nullptr;
   int32_t* fp64_count = nullptr;   // blocks refactored in FP64 (mixed precision)
 };
 
@@ -167,6 +169,8 @@ void destroy_buffers(kpp_system* s) {
   }
   dev_free(s->rvec);
   dev_free(s->dvec);
+  dev_free(s->zx);
+  dev_free(s->zm);
   dev_free(s->fp64_count);
   if (s->h_ds) (void)hipHostFree(s->h_ds);
   if (s->h_err) (void)hipHostFree(s->h_err);
@@ -366,6 +370,11 @@ struct CoreOpts {
   // kStallRatio times its value kStallWindows window ends earlier (an inner
   // low-precision solve at its precision floor); 0 = never
   int32_t stop_on_stall = 0;
+  // duals of the iterate and momentum (m entries each, zero on entry), kept
+  // by the fused engine for Kaczmarz++ when every workgroup's share of the m
+  // rows fits its registers; CoreStats::dual says whether they were
+  double* zx = nullptr;
+  double* zm = nullptr;
 };
 
 // host seconds spent in window planning, split for the serving profile
@@ -379,6 +388,7 @@ double wall_now() {
 }
 
 constexpr int kStallWindows = 12;
+constexpr int64_t kDualRowsPerGroup = 1024;   // 4 rows per thread in the step kernel
 constexpr double kStallRatio = 0.9;
 
 struct CoreStats {
@@ -387,6 +397,7 @@ struct CoreStats {
   double true_rel = NAN, t_factor = 0.0, t_kernel = 0.0;
   kpp::DevState hs{};
   int32_t engine = 0;
+  bool dual = false;
 };
 
 // One run of the block iteration (Algorithm 2 / Algorithm 5 with the exact
@@ -444,6 +455,8 @@ class CoreRun {
       if (p->engine == 2 && !fused_)
         return fail(KPP_ERR_INVALID_ARG, "n=%lld is too wide for the fused engine", (long long)n_);
     }
+    dual_ = o.zx != nullptr && o.zm != nullptr && kind_ == KPP_KACZMARZ && fused_ && groups_ > 0 &&
+            (m_ + groups_ - 1) / groups_ <= kDualRowsPerGroup;
     // memo cache: reuse only for an identical schedule definition.  The slot
     // table and the staging buffers are sized for the whole run before any
     // slot is handed out: growing them later waits for the device (a freed
@@ -510,6 +523,7 @@ class CoreRun {
   }
 
   bool finished() const { return finished_; }
+  bool dual() const { return dual_; }
   bool fused() const { return fused_; }
   bool fp32() const { return fp32_; }
   int32_t kind() const { return kind_; }
@@ -559,6 +573,9 @@ class CoreRun {
     a->spin_limit = int64_t{1} << 22;
     a->phase_ticks = phase_prof_ ? sys_->phase_ticks : nullptr;
     a->stop_on_cand = stop_on_cand_ ? 1 : 0;
+    a->zx = dual_ ? o_.zx : nullptr;
+    a->zm = dual_ ? o_.zm : nullptr;
+    a->mrows = m_;
     return KPP_OK;
   }
 
@@ -715,6 +732,7 @@ class CoreRun {
     cs->t_kernel = t_kernel_;
     cs->hs = hs_;
     cs->engine = fused_ ? 2 : 1;
+    cs->dual = dual_;
     return converged_ ? KPP_OK : KPP_NOT_CONVERGED;
   }
 
@@ -877,7 +895,7 @@ class CoreRun {
   int cur_ = 0;
   bool have_next_ = false;
   int64_t t_ = 0, hits_ = 0, misses_ = 0, launches_ = 0;
-  bool converged_ = false, finished_ = false, stalled_ = false, planned_ = false;
+  bool converged_ = false, finished_ = false, stalled_ = false, planned_ = false, dual_ = false;
   double true_rel_ = NAN, t_factor_ = 0.0, t_kernel_ = 0.0;
   kpp::DevState hs_{};
   std::vector<double> e1_hist_;
@@ -991,6 +1009,9 @@ kpp_status solve_mixed(kpp_system* sys, const kpp_params* p, double* x, kpp_resu
   }
   if (!sys->rvec) KPP_TRY(dev_alloc(&sys->rvec, m));
   if (!sys->dvec) KPP_TRY(dev_alloc(&sys->dvec, n));
+  const bool wide = sys->kind == KPP_KACZMARZ && m < n;
+  if (wide && !sys->zx) KPP_TRY(dev_alloc(&sys->zx, m));
+  if (wide && !sys->zm) KPP_TRY(dev_alloc(&sys->zm, m));
   if (!sys->fp64_count) KPP_TRY(dev_alloc(&sys->fp64_count, 1));
   HIP_TRY(hipMemsetAsync(sys->fp64_count, 0, sizeof(int32_t), st));
   int64_t iters = 0, hits = 0, misses = 0, launches = 0, ckpts = 0;
@@ -1012,12 +1033,18 @@ kpp_status solve_mixed(kpp_system* sys, const kpp_params* p, double* x, kpp_resu
     }
     if (rounds >= p->refine_max_rounds || iters >= p->max_iters) break;
     HIP_TRY(hipMemsetAsync(sys->dvec, 0, n * sizeof(double), st));
+    if (wide) {
+      HIP_TRY(hipMemsetAsync(sys->zx, 0, m * sizeof(double), st));
+      HIP_TRY(hipMemsetAsync(sys->zm, 0, m * sizeof(double), st));
+    }
     Source src;
     src.A32 = sys->A32;
     src.lda = n;
     src.b = sys->rvec;
     src.bnorm = rn;
     CoreOpts o;
+    o.zx = wide ? sys->zx : nullptr;
+    o.zm = wide ? sys->zm : nullptr;
     o.tol = p->inner_tol;
     o.confirm = 0;
     o.stop_on_stall = 1;
@@ -1026,6 +1053,9 @@ kpp_status solve_mixed(kpp_system* sys, const kpp_params* p, double* x, kpp_resu
     o.max_iters = p->max_iters - iters;
     CoreStats cs;
     KPP_TRY(solve_core(sys, p, src, o, sys->dvec, &cs));
+    // a wide system's correction is A^T zx with the FP64 A: in the row space
+    // of A, so the refined x converges to the minimum-norm solution
+    if (cs.dual) kpp::launch_gemv_t(sys->A, sys->lda, m, n, sys->zx, sys->dvec, st);
     kpp::launch_axpy1(x, sys->dvec, n, st);
     HIP_TRY(hipGetLastError());
     ++rounds;
@@ -1328,12 +1358,18 @@ bool serve_next_run(kpp_server* srv, ServeReq* r) {
   }
   if (hipMemsetAsync(sys->dvec, 0, sys->n * sizeof(double), st) != hipSuccess)
     return failed(fail(KPP_ERR_HIP, "memset failed"));
+  const bool wide = sys->kind == KPP_KACZMARZ && sys->m < sys->n;
+  if (wide && (hipMemsetAsync(sys->zx, 0, sys->m * sizeof(double), st) != hipSuccess ||
+               hipMemsetAsync(sys->zm, 0, sys->m * sizeof(double), st) != hipSuccess))
+    return failed(fail(KPP_ERR_HIP, "memset failed"));
   Source src;
   src.A32 = sys->A32;
   src.lda = sys->n;
   src.b = sys->rvec;
   src.bnorm = rn;
   CoreOpts o;
+  o.zx = wide ? sys->zx : nullptr;
+  o.zm = wide ? sys->zm : nullptr;
   o.tol = r->p.inner_tol;
   o.confirm = 0;
   o.stop_on_stall = 1;
@@ -1374,6 +1410,9 @@ bool serve_run_ended(kpp_server* srv, ServeReq* r) {
     r->run.reset();
     return false;
   }
+  if (cs.dual)
+    kpp::launch_gemv_t(r->sys->A, r->sys->lda, r->sys->m, r->sys->n, r->sys->zx, r->sys->dvec,
+                       r->sys->ctx->stream);
   kpp::launch_axpy1(r->x, r->sys->dvec, r->sys->n, r->sys->ctx->stream);
   if (hipGetLastError() != hipSuccess) {
     r->status = fail(KPP_ERR_HIP, "axpy launch failed");
@@ -1402,6 +1441,10 @@ bool serve_start(kpp_server* srv, ServeReq* r) {
     }
     if (!sys->rvec && dev_alloc(&sys->rvec, sys->m) < 0) return failed(KPP_ERR_OOM);
     if (!sys->dvec && dev_alloc(&sys->dvec, sys->n) < 0) return failed(KPP_ERR_OOM);
+    if (sys->kind == KPP_KACZMARZ && sys->m < sys->n) {
+      if (!sys->zx && dev_alloc(&sys->zx, sys->m) < 0) return failed(KPP_ERR_OOM);
+      if (!sys->zm && dev_alloc(&sys->zm, sys->m) < 0) return failed(KPP_ERR_OOM);
+    }
     if (!sys->fp64_count && dev_alloc(&sys->fp64_count, 1) < 0) return failed(KPP_ERR_OOM);
     if (hipMemsetAsync(sys->fp64_count, 0, sizeof(int32_t), st) != hipSuccess) return failed(KPP_ERR_HIP);
     r->rho = r->p.rho0;

@@ -175,6 +175,11 @@ void launch_residual_vec(const double* A, int64_t lda, int64_t m, int64_t n, con
   *out = bb * std::pow(1e-4, 2.0 * k);
   if (*out < bb * 1e-30) g_rounds[x] = 0;
 }
+void launch_gemv_t(const double* A, int64_t lda, int64_t m, int64_t n, const double* z, double* d, hipStream_t) {
+  emu_check(A, 8 * (static_cast<size_t>(m - 1) * lda + n), "gemv_t A");
+  emu_check(z, 8 * m, "gemv_t z");
+  emu_check(d, 8 * n, "gemv_t d");
+}
 void launch_axpy1(double* x, const double* d, int64_t n, hipStream_t) {
   emu_check(x, 8 * n, "axpy x");
   emu_check(d, 8 * n, "axpy d");
@@ -188,6 +193,11 @@ static void emu_fused(const FusedArgs& a, int32_t cpl, int32_t G, bool fp32) {
   emu_check(a.flags, 4 * static_cast<size_t>(G) * 32, "fused flags");
   emu_check(a.err, 4, "fused err");
   if (G * 64 * cpl < a.n) { std::fprintf(stderr, "EMU: fused team too small\n"); std::abort(); }
+  if (a.zx) {
+    emu_check(a.zx, 8 * a.mrows, "fused zx");
+    emu_check(a.zm, 8 * a.mrows, "fused zm");
+    if ((a.mrows + G - 1) / G > 1024) { std::fprintf(stderr, "EMU: dual slice too long\n"); std::abort(); }
+  }
   for (int k = 0; k < a.W; ++k) {
     const int q = a.step_slot[k];
     emu_check(a.lens + q, 4, "fused lens");

@@ -357,19 +357,17 @@ def test_mixed_precision_reaches_fp64_accuracy(env, case):
     assert res.refinements >= 1
     # both solutions satisfy ||A x - b|| <= 1e-10 ||b||, so within the row space
     # of A they differ by at most about kappa(A) * 1e-10 relative.  A wide system
-    # also has a null space: FP32 copies of its rows carry components outside
-    # the FP64 row space into x (about u32 * kappa), which leave the residual
-    # untouched; that drift is stated, and the row-space part is compared.
+    # also has a null space; its corrections are formed as A^T z with the FP64 A
+    # (z the dual of the inner iterate), so x stays in the row space and the
+    # minimum-norm solution is reached, not just some solution.
     kappa = synth_kappa(sysm)
     if m < n:
         Q, _ = np.linalg.qr(A.T)
         xr = Q @ (Q.T @ x)
         drift = np.linalg.norm(x - xr) / np.linalg.norm(x)
-        print(f"[mixed] {name}: null-space drift |x - P_row x|/|x| = {drift:.2e}", flush=True)
-        assert relerr(xr, ref.x) <= 2.0 * kappa * 1e-10 + 1e-12
-        assert drift <= 10.0 * kappa * 6e-8
-    else:
-        assert err_orc <= 2.0 * kappa * 1e-10 + 1e-12
+        print(f"[mixed] {name}: null-space component |x - P_row x|/|x| = {drift:.2e}", flush=True)
+        assert drift <= 1e-10
+    assert err_orc <= 2.0 * kappa * 1e-10 + 1e-12
 
 
 def synth_kappa(sysm):

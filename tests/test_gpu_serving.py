@@ -118,8 +118,6 @@ def test_mix_equals_alone(senv):
             assert res.true_rel_res <= p.tol, (case, res.true_rel_res)
             err = float(torch.linalg.norm(x - sysm.xstar) / torch.linalg.norm(sysm.xstar))
             bound = 1e-2 if p.tol > 1e-8 else 1e-5
-            if case[6] == "mixed" and case[1] < case[2]:
-                bound = 1e-3   # FP32 products leave a null-space component (wide systems)
             assert err < bound, (case, err)
         for (case, (sysm, h, p), x_m, (st_m, res_m)) in zip(MIX, built, xs_mix, mix):
             x_a = torch.zeros_like(x_m)
