@@ -12,10 +12,9 @@
 //      all-gather through per-workgroup flags: the step's only cross-CU
 //      sync); r = sum_g p_g - b_S, summed in the same order in every
 //      workgroup.  CD++ loads the next step's tile, rows and b values while
-//      it waits (the block sequence never depends on x): waves 1-3 issue
-//      their loads before the wait, wave 0 polls the flags (a wave's loads
-//      complete in order, so a polling wave must not have loads in flight)
-//      and issues its share right after;
+//      it waits (the block sequence never depends on x): every wave issues
+//      its loads before the wait, so the partial-residual loads after it do
+//      not queue behind a tile (a wave's loads complete in order);
 //   3. y = (A_S A_S^T + lam I)^{-1} r through the memoized inverse
 //      G^{-1} = L^{-T} L^{-1} of the block's Cholesky factor: CD++ needs only
 //      the rows of y whose coordinates fall into J_g (w = I_S^T y), Kaczmarz++
@@ -63,8 +62,14 @@ __device__ __forceinline__ void st_coherent(double* p, double v) {
 __device__ __forceinline__ uint32_t ld_flag(uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_flag_release(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+// Publish a flag after this wave's partial-residual stores.  Those stores are
+// agent-scope atomics (they complete at the device's coherence point), so
+// waiting for their completion orders them before the flag; a release store
+// would in addition write back every dirty line of this die's L2 (buffer_wbl2),
+// on every step, for data this kernel never publishes through plain stores.
+__device__ __forceinline__ void st_flag_after_stores(uint32_t* p, uint32_t v) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ double rho_from_rate(double rhat, int zeta) {
@@ -73,24 +78,91 @@ __device__ __forceinline__ double rho_from_rate(double rhat, int zeta) {
   return fmin(1.0, fmax(0.0, r));
 }
 
+// Cross-lane exchange without the LDS crossbar.  Lanes are paired across bit
+// o of the lane index: o = 32 and 16 by the permlane swaps, o = 8, 2, 1 by DPP
+// moves (xor o), o = 4 by the DPP half-row mirror (xor 7: it flips bit 2 and
+// keeps the bits above it, which is all a butterfly stage needs).
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ double dpp_partner(double v, int o) {
+  const int l = __double2loint(v), h = __double2hiint(v);
+  switch (o) {
+    case 8: return __hiloint2double(dpp_mov<0x128>(h), dpp_mov<0x128>(l));   // row_ror:8
+    case 4: return __hiloint2double(dpp_mov<0x141>(h), dpp_mov<0x141>(l));   // row_half_mirror
+    case 2: return __hiloint2double(dpp_mov<0x4E>(h), dpp_mov<0x4E>(l));     // quad_perm [2,3,0,1]
+    default: return __hiloint2double(dpp_mov<0xB1>(h), dpp_mov<0xB1>(l));    // quad_perm [1,0,3,2]
+  }
+}
+// One butterfly stage over a pair of row sums: a lane with bit o clear returns
+// its lo plus its partner's lo, a lane with bit o set its hi plus the
+// partner's hi.  For o = 32 (16) the swap leaves x = [lo of the lower lanes,
+// hi of the lower lanes] and y = [lo of the upper lanes, hi of the upper
+// lanes] per 64 (32) lanes, so x + y is that sum in every lane.
+__device__ __forceinline__ double fold(double lo, double hi, int o, bool up) {
+  if (o >= 16) {
+    const unsigned xl = __double2loint(lo), xh = __double2hiint(lo);
+    const unsigned yl = __double2loint(hi), yh = __double2hiint(hi);
+    const auto sl = o == 32 ? __builtin_amdgcn_permlane32_swap(xl, yl, false, false)
+                            : __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+    const auto sh = o == 32 ? __builtin_amdgcn_permlane32_swap(xh, yh, false, false)
+                            : __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+    return __hiloint2double(static_cast<int>(sh[0]), static_cast<int>(sl[0])) +
+           __hiloint2double(static_cast<int>(sh[1]), static_cast<int>(sl[1]));
+  }
+  // the pair passes through an empty asm statement: otherwise the compiler may
+  // fold the two selects into one indexed read of the row array, which it
+  // lowers to a chain of compares over the whole array
+  asm("" : "+v"(lo), "+v"(hi));
+  const double send = up ? lo : hi;
+  const double keep = up ? hi : lo;
+  return keep + dpp_partner(send, o);
+}
+
+// sum over the wave, in every lane
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  for (int o = 32; o > 0; o >>= 1) v = fold(v, v, o, false);
   return v;
 }
 
 // Load this wave's rows of the block tile: tile[r * CPL + e] = A[rows[wv + 4r], col0 + e].
 // One vector load fetches the wave's row indices (lane r holds row wv + 4r),
-// read back lane by lane, so every tile load issues at once.  Row indices past
-// the block and columns past the matrix are clamped, not masked: those entries
-// always meet a zero (x is zero beyond n, y is zero beyond the block), and A
-// is finite (checked when the system is created), so they contribute nothing.
+// read back lane by lane, so every tile load issues at once.  When rows start
+// 16-byte aligned and the whole slice lies inside the matrix (vec, the same
+// for every lane of the workgroup) a lane fetches its CPL columns in loads of
+// up to 16 bytes.  The choice must not differ between lanes: readlane takes
+// the row index from lanes that a divergent branch would leave inactive, and
+// the compiler may reuse those lanes' registers in the other branch.  The
+// element path clamps row indices past the block and columns past the matrix
+// instead of masking them: those entries always meet a zero (x is zero beyond
+// n, y is zero beyond the block), and A is finite (checked when the system is
+// created), so they contribute nothing.
 template <int CPL, typename TA, int TE>
 __device__ __forceinline__ void load_tile(TA (&tile)[TE], const TA* __restrict__ A,
                                           int64_t lda, int64_t n, const int32_t* __restrict__ rows,
-                                          int sb, int wv, int lane, int64_t col0) {
+                                          int sb, int wv, int lane, int64_t col0, bool vec) {
   constexpr int RMAX = TE / CPL;
+  constexpr int V = (CPL < 16 / static_cast<int>(sizeof(TA))) ? CPL : 16 / static_cast<int>(sizeof(TA));
   const int myrow = rows[min(wv + 4 * (lane & (RMAX - 1)), sb - 1)];
+  if constexpr (V > 1) {
+    if (vec) {
+      typedef TA vec_t __attribute__((ext_vector_type(V)));
+#pragma unroll
+      for (int r = 0; r < RMAX; ++r) {
+        const int row = __builtin_amdgcn_readlane(myrow, r);
+        const vec_t* Ai = reinterpret_cast<const vec_t*>(A + static_cast<int64_t>(row) * lda + col0);
+#pragma unroll
+        for (int e = 0; e < CPL / V; ++e) {
+          const vec_t t = Ai[e];
+#pragma unroll
+          for (int j = 0; j < V; ++j) tile[r * CPL + e * V + j] = t[j];
+        }
+      }
+      return;
+    }
+  }
 #pragma unroll
   for (int r = 0; r < RMAX; ++r) {
     const int row = __builtin_amdgcn_readlane(myrow, r);
@@ -142,6 +214,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
   const int64_t slice0 = static_cast<int64_t>(wg) * 64 * CPL;
   const int64_t slice1 = min(n, slice0 + 64 * CPL);
   const int64_t col0 = slice0 + static_cast<int64_t>(lane) * CPL;
+  const bool vec = a.vec_rows != 0 && slice1 == slice0 + 64 * CPL;   // uniform over the workgroup
 
   double xr[CPL], mr[CPL];
 #pragma unroll
@@ -175,7 +248,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
   int q = a.step_slot[0];
   int sb = a.lens[q];
   int cur = 0;
-  load_tile<CPL>(tile, Amat, a.lda, n, a.rows + static_cast<int64_t>(q) * s, sb, wv, lane, col0);
+  load_tile<CPL>(tile, Amat, a.lda, n, a.rows + static_cast<int64_t>(q) * s, sb, wv, lane, col0, vec);
   // thread tid forms r at block row tid: it holds b there for the current step
   double bval = 0.0;
   if (tid < sb) {
@@ -189,7 +262,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
   for (int k = 0; k < a.W; ++k) {
     const int32_t* rs = rsbuf[cur];
     if ((KIND == 0 || !KPP_PREFETCH) && k > 0) {
-      load_tile<CPL>(tile, Amat, a.lda, n, a.rows + static_cast<int64_t>(q) * s, sb, wv, lane, col0);
+      load_tile<CPL>(tile, Amat, a.lda, n, a.rows + static_cast<int64_t>(q) * s, sb, wv, lane, col0, vec);
     }
     const double* Ginv = a.L + static_cast<int64_t>(q) * a.slot_stride + static_cast<int64_t>(s) * s;
     KPP_MARK(0)
@@ -198,10 +271,9 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     TA xt[CPL];
 #pragma unroll
     for (int e = 0; e < CPL; ++e) xt[e] = static_cast<TA>(xr[e]);
-    // the lane's products are summed in TA, the sums across lanes in FP64.
-    // The pair (v[r], v[r + cnt/2]) passes through an empty asm statement:
-    // otherwise the compiler may fold the two selects into one indexed read of
-    // v, which it lowers to a chain of compares over the whole array.
+    // the lane's products are summed in TA, the sums across lanes in FP64:
+    // each butterfly stage halves the rows a lane holds, until lane l holds
+    // row l >> RSHIFT of the wave (summed over lanes with the same row)
     double v[RMAX];
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) {
@@ -214,16 +286,10 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     for (int cnt = RMAX, o = 32; cnt > 1; cnt >>= 1, o >>= 1) {
       const bool up = (lane & o) != 0;
 #pragma unroll
-      for (int r = 0; r < cnt / 2; ++r) {
-        double lo = v[r], hi = v[r + cnt / 2];
-        asm("" : "+v"(lo), "+v"(hi));
-        const double send = up ? lo : hi;
-        const double keep = up ? hi : lo;
-        v[r] = keep + __shfl_xor(send, o, 64);
-      }
+      for (int r = 0; r < cnt / 2; ++r) v[r] = fold(v[r], v[r + cnt / 2], o, up);
     }
 #pragma unroll
-    for (int o = 32 / RMAX; o >= 1; o >>= 1) v[0] += __shfl_xor(v[0], o, 64);
+    for (int o = 32 / RMAX; o >= 1; o >>= 1) v[0] = fold(v[0], v[0], o, false);
     {
       const int row = wv + 4 * (lane >> RSHIFT);
       if ((lane & ((1 << RSHIFT) - 1)) == 0 && row < sb) stage[row] = v[0];
@@ -236,7 +302,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     double* Pb = a.part + static_cast<size_t>(ep & 1u) * G * s;
     if (wv == 0) {
       for (int i = lane; i < sb; i += 64) st_coherent(&Pb[static_cast<size_t>(wg) * s + i], stage[i]);
-      if (lane == 0) st_flag_release(&a.flags[wg * kFlagStride], ep);
+      if (lane == 0) st_flag_after_stores(&a.flags[wg * kFlagStride], ep);
     }
     KPP_MARK(2)
     // block rows whose coordinates fall into this slice (rows are sorted)
@@ -259,19 +325,30 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     const int qn = have_next ? a.step_slot[k + 1] : q;
     const int sbn = a.lens[qn];
     const int32_t* Rn = a.rows + static_cast<int64_t>(qn) * s;
-    // CD++: the memoized inverse's rows for this slice; slice row lo + t
-    // belongs to wave 1 + t % 3 (wave 0 polls), lanes hold entries k = lane + 64 u
-    double grow[4] = {0.0, 0.0, 0.0, 0.0};
-    const int my_first = (KIND == 1 && wv > 0) ? lo + (wv - 1) : hi;
-    if (KIND == 1 && wv > 0) {
-      if (my_first < hi) {
+    // Loads that do not depend on r go out before the wait, in this order: the
+    // next block's row indices, the memoized inverse's rows for this slice
+    // (CD++), the next tile (CD++, every wave), the next b values.  A wave's
+    // loads complete in order, so the wave that polls the flags sees its first
+    // flag only once these have landed, and the partial-residual loads after
+    // the wait no longer queue behind a tile.
+    int32_t rown = 0;
+    if (have_next && tid < sbn) rown = Rn[tid];
+    // CD++: slice rows lo + wv and lo + wv + 4 (lanes hold entries kk = lane + 64 u)
+    double grow0[4] = {0.0, 0.0, 0.0, 0.0}, grow1[4] = {0.0, 0.0, 0.0, 0.0};
+    if (KIND == 1) {
+      const int i0 = lo + wv, i1 = lo + wv + 4;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int kk = lane + 64 * u;
-          grow[u] = Ginv[static_cast<int64_t>(my_first) * s + min(kk, sb - 1)];
-        }
+      for (int u = 0; u < 4; ++u) {
+        const int kk = min(lane + 64 * u, sb - 1);
+        if (i0 < hi && 64 * u < sb) grow0[u] = Ginv[static_cast<int64_t>(i0) * s + kk];
+        if (i1 < hi && 64 * u < sb) grow1[u] = Ginv[static_cast<int64_t>(i1) * s + kk];
       }
-      if (KPP_PREFETCH && have_next) load_tile<CPL>(tile, Amat, a.lda, n, Rn, sbn, wv, lane, col0);
+      if (KPP_PREFETCH && have_next) load_tile<CPL>(tile, Amat, a.lda, n, Rn, sbn, wv, lane, col0, vec);
+    }
+    double bnext = 0.0;
+    if (have_next && tid < sbn) {
+      rsbuf[cur ^ 1][tid] = rown;
+      bnext = a.b[rown];
     }
     if (tid < G) {
       int64_t spins = 0;
@@ -290,7 +367,6 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     // r = sum_g p_g - b_S: wave w sums block rows 64 w .. 64 w + 63, one row
     // per lane, so that every wave's partial loads are a single batch; then
     // the next step's rows and b values (used after this step)
-    double bnext = 0.0;
     const int nu = (sb + 63) >> 6;
     if (wv < nu) {
       const int c = min(tid, sb - 1);   // rows past the block: clamped, sum dropped
@@ -317,40 +393,30 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
         rv[tid] = ri;
         rr_w = ri * ri;
       }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) rr_w += __shfl_down(rr_w, off, 64);
+      rr_w = wave_sum(rr_w);
       if (lane == 0) red[wv] = rr_w;
     }
-    // next step's rows and b (a dependent pair: issued before wave 0's tile
-    // loads so that waiting for the row indices does not wait for the tile)
-    if (have_next && tid < sbn) {
-      const int32_t row = Rn[tid];
-      rsbuf[cur ^ 1][tid] = row;
-      bnext = a.b[row];
-    }
-    // wave 0's share of the next tile, after its partial loads have landed
-    if (wv == 0 && KIND == 1 && KPP_PREFETCH && have_next) load_tile<CPL>(tile, Amat, a.lda, n, Rn, sbn, wv, lane, col0);
     __syncthreads();
     KPP_MARK(4)
 
     // 3. y through the memoized inverse
     if (KIND == 1) {
-      if (wv > 0) {
-        for (int i = my_first; i < hi; i += 3) {
-          double acc = 0.0;
-          if (i == my_first) {
+      // slice row lo + t belongs to wave t % 4; the first two rows of a wave
+      // were loaded before the wait
+      for (int i = lo + wv, j = 0; i < hi; i += 4, ++j) {
+        double acc = 0.0;
+        if (j < 2) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const int kk = lane + 64 * u;
-              if (kk < sb) acc = fma(grow[u], rv[kk], acc);
-            }
-          } else {
-            const double* Gi = Ginv + static_cast<int64_t>(i) * s;
-            for (int kk = lane; kk < sb; kk += 64) acc = fma(Gi[kk], rv[kk], acc);
+          for (int u = 0; u < 4; ++u) {
+            const int kk = lane + 64 * u;
+            if (kk < sb) acc = fma(j == 0 ? grow0[u] : grow1[u], rv[kk], acc);
           }
-          acc = wave_sum(acc);
-          if (lane == 0) yv[i] = acc;
+        } else {
+          const double* Gi = Ginv + static_cast<int64_t>(i) * s;
+          for (int kk = lane; kk < sb; kk += 64) acc = fma(Gi[kk], rv[kk], acc);
         }
+        acc = wave_sum(acc);
+        if (lane == 0) yv[i] = acc;
       }
     } else if (tid < sb) {
       double acc = 0.0;

@@ -163,7 +163,7 @@ struct FusedArgs {
   int64_t spin_limit;
   uint64_t* phase_ticks;     // optional (nullptr): wall-clock ticks per step phase, workgroup 0
   int32_t stop_on_cand;      // 1: end the launch after a checkpoint whose stop test passes
-  int32_t pad0;
+  int32_t vec_rows;          // 1: A and lda keep every row 16-byte aligned (vector tile loads)
   // Kaczmarz++ with m < n only (optional, nullptr = off): the dual of the
   // iterate and of the momentum, x = A^T zx and m = A^T zm in exact
   // arithmetic (m FP64 entries each, in and out like x and mom)

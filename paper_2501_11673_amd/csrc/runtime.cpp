@@ -576,6 +576,10 @@ class CoreRun {
     a->zx = dual_ ? o_.zx : nullptr;
     a->zm = dual_ ? o_.zm : nullptr;
     a->mrows = m_;
+    {
+      const size_t esz = fp32_ ? sizeof(float) : sizeof(double);
+      a->vec_rows = (reinterpret_cast<uintptr_t>(a->A) % 16 == 0 && (static_cast<size_t>(a->lda) * esz) % 16 == 0) ? 1 : 0;
+    }
     return KPP_OK;
   }
 

@@ -193,6 +193,10 @@ static void emu_fused(const FusedArgs& a, int32_t cpl, int32_t G, bool fp32) {
   emu_check(a.flags, 4 * static_cast<size_t>(G) * 32, "fused flags");
   emu_check(a.err, 4, "fused err");
   if (G * 64 * cpl < a.n) { std::fprintf(stderr, "EMU: fused team too small\n"); std::abort(); }
+  if (a.vec_rows && (reinterpret_cast<uintptr_t>(a.A) % 16 != 0 || (a.lda * (fp32 ? 4 : 8)) % 16 != 0)) {
+    std::fprintf(stderr, "EMU: vector tile loads on unaligned rows\n");
+    std::abort();
+  }
   if (a.zx) {
     emu_check(a.zx, 8 * a.mrows, "fused zx");
     emu_check(a.zm, 8 * a.mrows, "fused zm");
