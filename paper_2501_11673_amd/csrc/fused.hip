@@ -127,9 +127,18 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Row index that lane r of wave wv contributes to a tile: block row wv + 4r
+// (clamped to the block).  It is loaded a step ahead of the tile, so that the
+// tile's loads wait for no dependent round trip.
+template <int CPL, typename TA, int TE>
+__device__ __forceinline__ int32_t tile_row_index(const int32_t* __restrict__ rows, int sb, int wv, int lane) {
+  constexpr int RMAX = TE / CPL;
+  return rows[min(wv + 4 * (lane & (RMAX - 1)), sb - 1)];
+}
+
 // Load this wave's rows of the block tile: tile[r * CPL + e] = A[rows[wv + 4r], col0 + e].
-// One vector load fetches the wave's row indices (lane r holds row wv + 4r),
-// read back lane by lane, so every tile load issues at once.  When rows start
+// Lane r holds the row index of row wv + 4r (tile_row_index), read back lane
+// by lane, so every tile load issues at once.  When rows start
 // 16-byte aligned and the whole slice lies inside the matrix (vec, the same
 // for every lane of the workgroup) a lane fetches its CPL columns in loads of
 // up to 16 bytes.  The choice must not differ between lanes: readlane takes
@@ -140,12 +149,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 // n, y is zero beyond the block), and A is finite (checked when the system is
 // created), so they contribute nothing.
 template <int CPL, typename TA, int TE>
-__device__ __forceinline__ void load_tile(TA (&tile)[TE], const TA* __restrict__ A,
-                                          int64_t lda, int64_t n, const int32_t* __restrict__ rows,
-                                          int sb, int wv, int lane, int64_t col0, bool vec) {
+__device__ __forceinline__ void load_tile(TA (&tile)[TE], const TA* __restrict__ A, int64_t lda, int64_t n,
+                                          int32_t myrow, int64_t col0, bool vec) {
   constexpr int RMAX = TE / CPL;
   constexpr int V = (CPL < 16 / static_cast<int>(sizeof(TA))) ? CPL : 16 / static_cast<int>(sizeof(TA));
-  const int myrow = rows[min(wv + 4 * (lane & (RMAX - 1)), sb - 1)];
   if constexpr (V > 1) {
     if (vec) {
       typedef TA vec_t __attribute__((ext_vector_type(V)));
@@ -248,7 +255,18 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
   int q = a.step_slot[0];
   int sb = a.lens[q];
   int cur = 0;
-  load_tile<CPL>(tile, Amat, a.lda, n, a.rows + static_cast<int64_t>(q) * s, sb, wv, lane, col0, vec);
+  // row indices run ahead of their use: myrow_c / myrow_n are this lane's
+  // tile row index for the current and the next step, rown_n thread tid's
+  // block row of the next step
+  int32_t myrow_c = tile_row_index<CPL, TA, TE>(a.rows + static_cast<int64_t>(q) * s, sb, wv, lane);
+  int32_t myrow_n = 0, rown_n = 0;
+  if (a.W > 1) {
+    const int q1 = a.step_slot[1];
+    const int sb1 = a.lens[q1];
+    myrow_n = tile_row_index<CPL, TA, TE>(a.rows + static_cast<int64_t>(q1) * s, sb1, wv, lane);
+    if (tid < sb1) rown_n = a.rows[static_cast<int64_t>(q1) * s + tid];
+  }
+  load_tile<CPL>(tile, Amat, a.lda, n, myrow_c, col0, vec);
   // thread tid forms r at block row tid: it holds b there for the current step
   double bval = 0.0;
   if (tid < sb) {
@@ -261,9 +279,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
   if (prof) tick_last = wall_clock64();
   for (int k = 0; k < a.W; ++k) {
     const int32_t* rs = rsbuf[cur];
-    if ((KIND == 0 || !KPP_PREFETCH) && k > 0) {
-      load_tile<CPL>(tile, Amat, a.lda, n, a.rows + static_cast<int64_t>(q) * s, sb, wv, lane, col0, vec);
-    }
+    if ((KIND == 0 || !KPP_PREFETCH) && k > 0) load_tile<CPL>(tile, Amat, a.lda, n, myrow_c, col0, vec);
     const double* Ginv = a.L + static_cast<int64_t>(q) * a.slot_stride + static_cast<int64_t>(s) * s;
     KPP_MARK(0)
 
@@ -324,15 +340,13 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     const bool have_next = k + 1 < a.W;
     const int qn = have_next ? a.step_slot[k + 1] : q;
     const int sbn = a.lens[qn];
-    const int32_t* Rn = a.rows + static_cast<int64_t>(qn) * s;
     // Loads that do not depend on r go out before the wait, in this order: the
-    // next block's row indices, the memoized inverse's rows for this slice
-    // (CD++), the next tile (CD++, every wave), the next b values.  A wave's
+    // memoized inverse's rows for this slice (CD++), the next tile (CD++,
+    // every wave), the next b values, the row indices of step k + 2 (last: their
+    // addresses come from a chain of dependent scalar loads).  A wave's
     // loads complete in order, so the wave that polls the flags sees its first
     // flag only once these have landed, and the partial-residual loads after
-    // the wait no longer queue behind a tile.
-    int32_t rown = 0;
-    if (have_next && tid < sbn) rown = Rn[tid];
+    // the wait do not queue behind a tile.
     // CD++: slice rows lo + wv and lo + wv + 4 (lanes hold entries kk = lane + 64 u)
     double grow0[4] = {0.0, 0.0, 0.0, 0.0}, grow1[4] = {0.0, 0.0, 0.0, 0.0};
     if (KIND == 1) {
@@ -343,12 +357,20 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
         if (i0 < hi && 64 * u < sb) grow0[u] = Ginv[static_cast<int64_t>(i0) * s + kk];
         if (i1 < hi && 64 * u < sb) grow1[u] = Ginv[static_cast<int64_t>(i1) * s + kk];
       }
-      if (KPP_PREFETCH && have_next) load_tile<CPL>(tile, Amat, a.lda, n, Rn, sbn, wv, lane, col0, vec);
+      if (KPP_PREFETCH && have_next) load_tile<CPL>(tile, Amat, a.lda, n, myrow_n, col0, vec);
     }
     double bnext = 0.0;
     if (have_next && tid < sbn) {
-      rsbuf[cur ^ 1][tid] = rown;
-      bnext = a.b[rown];
+      rsbuf[cur ^ 1][tid] = rown_n;
+      bnext = a.b[rown_n];
+    }
+    int32_t myrow_nn = 0, rown_nn = 0;
+    if (k + 2 < a.W) {
+      const int q2 = a.step_slot[k + 2];
+      const int sb2 = a.lens[q2];
+      const int32_t* R2 = a.rows + static_cast<int64_t>(q2) * s;
+      myrow_nn = tile_row_index<CPL, TA, TE>(R2, sb2, wv, lane);
+      if (tid < sb2) rown_nn = R2[tid];
     }
     if (tid < G) {
       int64_t spins = 0;
@@ -543,6 +565,9 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     sb = sbn;
     bval = bnext;
     cur ^= 1;
+    myrow_c = myrow_n;
+    myrow_n = myrow_nn;
+    rown_n = rown_nn;
     __syncthreads();
     KPP_MARK(6)
     if (stop_now) break;
