@@ -49,6 +49,35 @@ def parse():
     return ap.parse_args()
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_fused_cdpp_n4096_s128_fp64.md")
+
+
+def measured_traffic(kernel_name):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes, each scaled by what the counter read for a
+    device copy of known size.  None when the kernel's sources have changed
+    since the counters were taken, or for another kernel."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"```json kpp-traffic\n(.*?)```", text, re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec["kernel"] != kernel_name:
+        return None
+    for rel, digest in rec["sources"].items():
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    fetch = rec["fetch_kib_per_dispatch"] * rec["copy_bytes"] / rec["copy_fetch_kib"]
+    write = rec["write_kib_per_dispatch"] * rec["copy_bytes"] / rec["copy_write_kib"]
+    return round(fetch + write, 1)
+
+
 def blas_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -222,7 +251,9 @@ def main():
     per_launch_s = ktime / max(klaunch, 1)
     achieved = per_launch_bytes / per_launch_s / 1e9 if per_launch_s > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": measured_traffic("k_fused<1, 2, double>") if last.engine_used == 2 else None,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "kernel": engine_name, "launches": int(klaunch),
                 "avg_launch_us": round(per_launch_s * 1e6, 3),
                 "bytes_per_launch": round(per_launch_bytes, 1)}
