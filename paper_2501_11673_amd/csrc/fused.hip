@@ -51,7 +51,8 @@ template <typename TA, int CPL>
 struct TileElems {
   static constexpr int value = (sizeof(TA) == 4 && CPL >= 4) ? 128 : 64;
 };
-static_assert(kFlagStride * kFusedMaxGroups <= kFlagWordsAlloc, "flag area too small");
+static_assert(kFlagStride * kFusedMaxGroups <= kYFlagOffset, "flag area too small");
+static_assert(kYFlagOffset + kFlagStride * kFusedMaxGroups <= kFlagWordsAlloc, "flag area too small");
 
 __device__ __forceinline__ double ld_coherent(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -337,6 +338,13 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
       }
       hi = l;
     }
+    // Kaczmarz++ with y split across the team: this workgroup's rows of y
+    const bool ysplit = KIND == 0 && a.ysplit != 0;
+    const int yper = (sb + G - 1) / G;
+    if (ysplit) {
+      lo = min(sb, wg * yper);
+      hi = min(sb, lo + yper);
+    }
     const bool have_next = k + 1 < a.W;
     const int qn = have_next ? a.step_slot[k + 1] : q;
     const int sbn = a.lens[qn];
@@ -349,7 +357,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     // the wait do not queue behind a tile.
     // CD++: slice rows lo + wv and lo + wv + 4 (lanes hold entries kk = lane + 64 u)
     double grow0[4] = {0.0, 0.0, 0.0, 0.0}, grow1[4] = {0.0, 0.0, 0.0, 0.0};
-    if (KIND == 1) {
+    if (KIND == 1 || ysplit) {
       const int i0 = lo + wv, i1 = lo + wv + 4;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -357,8 +365,8 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
         if (i0 < hi && 64 * u < sb) grow0[u] = Ginv[static_cast<int64_t>(i0) * s + kk];
         if (i1 < hi && 64 * u < sb) grow1[u] = Ginv[static_cast<int64_t>(i1) * s + kk];
       }
-      if (KPP_PREFETCH && have_next) load_tile<CPL>(tile, Amat, a.lda, n, myrow_n, col0, vec);
     }
+    if (KIND == 1 && KPP_PREFETCH && have_next) load_tile<CPL>(tile, Amat, a.lda, n, myrow_n, col0, vec);
     double bnext = 0.0;
     if (have_next && tid < sbn) {
       rsbuf[cur ^ 1][tid] = rown_n;
@@ -422,9 +430,10 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     KPP_MARK(4)
 
     // 3. y through the memoized inverse
-    if (KIND == 1) {
-      // slice row lo + t belongs to wave t % 4; the first two rows of a wave
-      // were loaded before the wait
+    if (KIND == 1 || ysplit) {
+      // CD++: the rows of y whose coordinates fall into the slice; split
+      // Kaczmarz++: this workgroup's share of y.  Row lo + t belongs to wave
+      // t % 4; the first two rows of a wave were loaded before the wait
       for (int i = lo + wv, j = 0; i < hi; i += 4, ++j) {
         double acc = 0.0;
         if (j < 2) {
@@ -439,6 +448,31 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
         }
         acc = wave_sum(acc);
         if (lane == 0) yv[i] = acc;
+      }
+      if (ysplit) {
+        // all-gather of y: publish this workgroup's rows, wait for every
+        // workgroup that owns rows, read all of y (the same values everywhere)
+        __syncthreads();
+        double* Yb = a.ypart + static_cast<size_t>(ep & 1u) * s;
+        uint32_t* yflags = a.flags + kYFlagOffset;
+        if (wv == 0) {
+          for (int i = lo + lane; i < hi; i += 64) st_coherent(&Yb[i], yv[i]);
+          if (lane == 0) st_flag_after_stores(&yflags[wg * kFlagStride], ep);
+        }
+        const int nown = (sb + yper - 1) / yper;
+        if (tid < nown) {
+          int64_t spins = 0;
+          while (static_cast<int32_t>(ld_flag(&yflags[tid * kFlagStride]) - ep) < 0) {
+            if (++spins > a.spin_limit) {
+              atomicOr(a.err, 2);
+              abort_flag = 1;
+              break;
+            }
+          }
+        }
+        __syncthreads();
+        if (abort_flag) break;
+        if (tid < sb) yv[tid] = ld_coherent(&Yb[tid]);
       }
     } else if (tid < sb) {
       double acc = 0.0;

@@ -170,6 +170,12 @@ struct FusedArgs {
   double* zx;
   double* zm;
   int64_t mrows;
+  // Kaczmarz++ only: 1 = y = G^{-1} r is split across the team (each
+  // workgroup forms ceil(s/G) rows, then one all-gather of y through ypart,
+  // 2 x s doubles, and a second set of flags); 0 = every workgroup forms all of y
+  double* ypart;
+  int32_t ysplit;
+  int32_t pad1;
 };
 
 constexpr int kFusedPhases = 8;
@@ -177,6 +183,10 @@ constexpr int kFusedPhases = 8;
 constexpr int kFusedMaxBlock = 256;   // the fused engine gives one thread per block row
 constexpr int kFusedMaxGroups = 256;
 constexpr int kFlagWordsAlloc = 1024 * kFusedMaxGroups;   // up to 4 KB between flags
+// the y all-gather's flags start this many words into the flag area
+constexpr int kYFlagOffset = kFlagWordsAlloc / 2;
+// exchange buffer per system: partial residuals, then the y all-gather
+constexpr size_t kPartDoubles = 2 * static_cast<size_t>(kFusedMaxGroups) * kFusedMaxBlock + 2 * kFusedMaxBlock;
 
 void launch_fused(int32_t kind, bool a_fp32, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t st);
 

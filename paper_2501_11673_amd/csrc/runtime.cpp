@@ -390,6 +390,10 @@ double wall_now() {
 constexpr int kStallWindows = 12;
 constexpr int64_t kDualRowsPerGroup = 1024;   // 4 rows per thread in the step kernel
 constexpr double kStallRatio = 0.9;
+// Kaczmarz++ blocks of at least this many rows split y = G^{-1} r across the
+// team: forming all of y reads the whole s x s inverse in every workgroup
+// (512 KB per workgroup per step at s = 256), one more exchange costs less
+constexpr int32_t kYSplitMinBlock = 128;
 
 struct CoreStats {
   int64_t iters = 0, hits = 0, misses = 0, launches = 0;
@@ -576,6 +580,8 @@ class CoreRun {
     a->zx = dual_ ? o_.zx : nullptr;
     a->zm = dual_ ? o_.zm : nullptr;
     a->mrows = m_;
+    a->ypart = sys_->part + 2 * static_cast<size_t>(kpp::kFusedMaxGroups) * kpp::kFusedMaxBlock;
+    a->ysplit = (kind_ == KPP_KACZMARZ && s_ >= kYSplitMinBlock && groups_ >= 4) ? 1 : 0;
     {
       const size_t esz = fp32_ ? sizeof(float) : sizeof(double);
       a->vec_rows = (reinterpret_cast<uintptr_t>(a->A) % 16 == 0 && (static_cast<size_t>(a->lda) * esz) % 16 == 0) ? 1 : 0;
@@ -1730,7 +1736,7 @@ KPP_API kpp_status kpp_system_create(kpp_context* ctx, int32_t kind, int64_t m, 
   if ((stt = dev_alloc(&sys->mom, n)) < 0 || (stt = dev_alloc(&sys->ds, 1)) < 0 ||
       (stt = dev_alloc(&sys->y, kpp::kMaxBlock)) < 0 || (stt = dev_alloc(&sys->rowsq, m)) < 0 ||
       (stt = dev_alloc(&sys->scal, 4)) < 0 || (stt = dev_alloc(&sys->err, 4)) < 0 ||
-      (stt = dev_alloc(&sys->part, 2 * static_cast<size_t>(kpp::kFusedMaxGroups) * kpp::kFusedMaxBlock)) < 0 ||
+      (stt = dev_alloc(&sys->part, kpp::kPartDoubles)) < 0 ||
       (stt = dev_alloc(&sys->flags, kFlagWords)) < 0) {
     destroy_buffers(sys.get());
     return stt;

@@ -188,6 +188,8 @@ ITER_CASES = [
     ("c2_small_partition", "psd", lambda: synth.config("c2_small"), 128, 1e-8, "fixed", 160, {}),
     ("c3_small", "general", lambda: synth.config("c3_small"), 256, 1e-8, "fixed", 200, {}),
     ("c4_small", "general", lambda: synth.config("c4_small"), 64, 1e-4, "online", 200, {}),
+    # Kaczmarz++ blocks of 128+ rows on 4+ workgroups split y across the team
+    ("c4_small_s128", "general", lambda: synth.config("c4_small"), 128, 1e-4, "online", 120, {}),
     ("tiny_over_s1", "general", lambda: synth.tiny_system("general", 50, 9, seed=5), 1, 1e-6, "online", 300, {}),
     ("tiny_psd_sN", "psd", lambda: synth.tiny_system("psd", 24, 24, seed=6), 24, 1e-6, "online", 40, {}),
     ("tiny_under_off", "general", lambda: synth.tiny_system("general", 30, 90, seed=8), 7, 1e-5, "off", 150, {}),
@@ -248,6 +250,21 @@ def test_fused_team_sizes_agree_with_oracle(env, groups):
     A, b = sysm.A, sysm.b
     x, st, res = gpu_solve(env, A, b, "general", 32, lam=1e-6, T=150, seed=5, engine=2, team_groups=groups)
     ref = oracle_solve(A, b, "general", 32, lam=1e-6, T=150, seed=5)
+    assert relerr(x, ref.x) <= 1e-10
+
+
+@pytest.mark.parametrize("n", [150, 250, 700, 4000])
+def test_split_y_team_sizes_agree_with_oracle(env, n):
+    """Kaczmarz++ with 130-row blocks (one column per lane, so ceil(n/64)
+    workgroups: 3, 4, 11, 63): y is formed whole in every workgroup (3) or by
+    the workgroup owning each row and all-gathered (4+).  The partition of 1000
+    rows ends in a ragged 90-row block, and ceil(s/G) rows per workgroup do not
+    divide the block."""
+    sysm = synth.tiny_system("general", 1000, n, seed=15, cond=30.0)
+    A, b = sysm.A, sysm.b
+    x, st, res = gpu_solve(env, A, b, "general", 130, lam=1e-6, T=120, mode="fixed", seed=5, engine=2)
+    ref = oracle_solve(A, b, "general", 130, lam=1e-6, T=120, mode="fixed", seed=5)
+    assert res.iters == 120
     assert relerr(x, ref.x) <= 1e-10
 
 
