@@ -448,6 +448,247 @@ __global__ __launch_bounds__(kT) void k_factor_inverse(double* __restrict__ slot
 }
 
 // --------------------------------------------------------------------------
+// memo miss for blocks of kLdsCholMax+1 .. kFusedMaxBlock rows, blocked in LDS.
+//
+// k_cholesky_panel: left-looking Cholesky in panels of kPanel columns.  The
+// panel (rows p0 .. sb-1 of columns p0 .. p0+pw-1) and the rows of L it
+// depends on (L(p0 + c, k), k < p0) sit in LDS; thread i brings panel row i
+// up to date with the finished columns of L (read from the slot, coalesced
+// over i, against LDS broadcasts), then the panel is factored column by
+// column in LDS and written back.  With chk.flag it leaves ||G||_F^2 in the
+// first entry of the slot's last third.
+// --------------------------------------------------------------------------
+constexpr int kPanel = 32;
+constexpr int kPanelLd = kPanel + 1;
+constexpr size_t kCholPanelLds =
+    (static_cast<size_t>(kFusedMaxBlock) * kPanelLd + static_cast<size_t>(kFusedMaxBlock) * kPanel) * sizeof(double);
+constexpr size_t kInverseBlockedLds =
+    (static_cast<size_t>(kPanel) * kFusedMaxBlock + static_cast<size_t>(kPanel) * kPanelLd) * sizeof(double);
+
+__global__ __launch_bounds__(kT) void k_cholesky_panel(double* __restrict__ G, int32_t s, int64_t stride,
+                                                       const int32_t* __restrict__ lens,
+                                                       const int32_t* __restrict__ slot_of,
+                                                       int32_t* __restrict__ err, FactorCheck chk) {
+  extern __shared__ double lds[];
+  double* P = lds;                                  // P[i * kPanelLd + c] = G(p0 + i, p0 + c)
+  double* Lt = lds + kFusedMaxBlock * kPanelLd;     // Lt[k * kPanel + c] = L(p0 + c, k), k < p0
+  __shared__ double red4[4];
+  __shared__ int bad_any;
+  const int blk = blockIdx.x;
+  if (chk.only && !chk.only[blk]) return;
+  const int sb = lens[blk];
+  const int tid = threadIdx.x;
+  const int64_t ss = static_cast<int64_t>(s) * s;
+  double* Gb = G + static_cast<int64_t>(slot_of[blk]) * stride;
+  if (chk.flag) {
+    double acc = 0.0;
+    for (int e = tid; e < sb * sb; e += kT) {
+      const int k = e / sb, i = e - k * sb;
+      if (i >= k) {
+        const double v = Gb[static_cast<int64_t>(k) * s + i];
+        acc += (i == k ? 1.0 : 2.0) * v * v;
+      }
+    }
+    acc = block_sum(acc, red4);
+    if (tid == 0) Gb[2 * ss] = acc;
+  }
+  if (tid == 0) bad_any = 0;
+  __syncthreads();
+  int bad = 0;
+  for (int p0 = 0; p0 < sb; p0 += kPanel) {
+    const int pw = min(kPanel, sb - p0), R = sb - p0;
+    for (int e = tid; e < R * pw; e += kT) {
+      const int c = e / R, i = e - c * R;
+      P[i * kPanelLd + c] = Gb[static_cast<int64_t>(p0 + c) * s + p0 + i];
+    }
+    for (int e = tid; e < p0 * pw; e += kT) {
+      const int k = e / pw, c = e - k * pw;
+      Lt[k * kPanel + c] = Gb[static_cast<int64_t>(k) * s + p0 + c];
+    }
+    __syncthreads();
+    if (p0 > 0 && tid < R) {
+      double acc[kPanel];
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c) acc[c] = c < pw ? P[tid * kPanelLd + c] : 0.0;
+      const double* Lrow = Gb + p0 + tid;
+      for (int k = 0; k < p0; ++k) {
+        const double l = Lrow[static_cast<int64_t>(k) * s];
+        const double* lt = Lt + k * kPanel;
+#pragma unroll
+        for (int c = 0; c < kPanel; ++c) acc[c] = fma(-l, lt[c], acc[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c)
+        if (c < pw) P[tid * kPanelLd + c] = acc[c];
+    }
+    __syncthreads();
+    for (int c = 0; c < pw; ++c) {
+      const double d2 = P[c * kPanelLd + c];
+      if (!(d2 > 0.0)) bad = 1;
+      const double d = sqrt(d2);
+      __syncthreads();
+      if (tid > c && tid < R) P[tid * kPanelLd + c] /= d;
+      if (tid == 0) P[c * kPanelLd + c] = d;
+      __syncthreads();
+      if (tid > c && tid < R) {
+        const double lic = P[tid * kPanelLd + c];
+        for (int c2 = c + 1; c2 < pw && c2 <= tid; ++c2)
+          P[tid * kPanelLd + c2] = fma(-lic, P[c2 * kPanelLd + c], P[tid * kPanelLd + c2]);
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < R * pw; e += kT) {
+      const int c = e / R, i = e - c * R;
+      if (i >= c) Gb[static_cast<int64_t>(p0 + c) * s + p0 + i] = P[i * kPanelLd + c];
+    }
+    __syncthreads();
+  }
+  if (bad) atomicOr(&bad_any, 1);
+  __syncthreads();
+  if (tid == 0) {
+    double lo = 1.0 / 0.0, hi = 0.0;
+    for (int i = 0; i < sb; ++i) {
+      const double d = Gb[static_cast<int64_t>(i) * s + i];
+      lo = fmin(lo, d);
+      hi = fmax(hi, d);
+    }
+    const double ratio = hi / lo;
+    const bool ill = !(ratio * ratio <= chk.kappa_max);
+    if (chk.flag) {
+      const int f = (bad_any || ill) ? 1 : 0;
+      chk.flag[blk] = f;
+      if (f) atomicAdd(chk.counter, 1);
+    } else if (bad_any) {
+      atomicOr(err, 1);
+    }
+  }
+  // zero strict upper triangle and padding
+  for (int e = tid; e < s * s; e += kT) {
+    const int k = e / s, i = e - k * s;
+    if (!(i < sb && k < sb && i >= k)) Gb[static_cast<int64_t>(k) * s + i] = 0.0;
+  }
+}
+
+// --------------------------------------------------------------------------
+// G^{-1} = L^{-T} L^{-1} of a block of kLdsCholMax+1 .. kFusedMaxBlock rows,
+// blocked in LDS.  X = L^{-1} is formed one block row of kPanel rows at a time
+// (X_rr = L_rr^{-1} by substitution in LDS; X_rq = -X_rr sum_k L_rk X_kq for
+// the columns to the left: thread j owns column j, reads it from the slot's
+// last third, where X is kept row-major, and the block row of L from LDS);
+// then G^{-1}(i, j) = sum_{k >= max(i, j)} X(k, i) X(k, j) with the columns of
+// X for 32 rows i at a time staged in LDS.  Entries (i, j) and (j, i) are summed
+// in the same order, so the stored inverse is exactly symmetric.  With chk.flag
+// the Frobenius condition number is tested as in k_factor_inverse.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(kT) void k_inverse_blocked(double* __restrict__ slots, int64_t stride, int32_t s,
+                                                        const int32_t* __restrict__ lens,
+                                                        const int32_t* __restrict__ slot_of, FactorCheck chk,
+                                                        const int32_t* __restrict__ skip) {
+  extern __shared__ double lds[];
+  double* Lr = lds;                                 // Lr[a * kFusedMaxBlock + k] = L(r0 + a, k); later Xt
+  double* Xd = lds + kPanel * kFusedMaxBlock;       // Xd[a * kPanelLd + c] = X(r0 + a, r0 + c)
+  __shared__ double red4[4];
+  const int blk = blockIdx.x;
+  if ((chk.only && !chk.only[blk]) || (skip && skip[blk])) return;
+  const int sb = lens[blk];
+  const int tid = threadIdx.x;
+  const int64_t ss = static_cast<int64_t>(s) * s;
+  double* base = slots + static_cast<int64_t>(slot_of[blk]) * stride;
+  const double* Lc = base;                          // L(i, k) at Lc[k * s + i]
+  double* Gi = base + ss;
+  double* X = base + 2 * ss;                        // X(i, j) at X[i * s + j]
+  const double norm_g2 = chk.flag ? X[0] : 0.0;     // left by the Cholesky, overwritten below
+  __syncthreads();
+  const int j = tid;
+  for (int r0 = 0; r0 < sb; r0 += kPanel) {
+    const int w = min(kPanel, sb - r0);
+    for (int e = tid; e < w * r0; e += kT) {
+      const int k = e / w, a = e - k * w;
+      Lr[a * kFusedMaxBlock + k] = Lc[static_cast<int64_t>(k) * s + r0 + a];
+    }
+    // X_rr = L_rr^{-1}: thread c < w substitutes down column c
+    for (int e = tid; e < w * w; e += kT) {
+      const int a = e / w, c = e - a * w;
+      Xd[a * kPanelLd + c] = 0.0;
+    }
+    __syncthreads();
+    if (tid < w) {
+      const int c = tid;
+      Xd[c * kPanelLd + c] = 1.0 / Lc[static_cast<int64_t>(r0 + c) * s + r0 + c];
+      for (int i = c + 1; i < w; ++i) {
+        double acc = 0.0;
+        for (int k = c; k < i; ++k) acc = fma(Lc[static_cast<int64_t>(r0 + k) * s + r0 + i], Xd[k * kPanelLd + c], acc);
+        Xd[i * kPanelLd + c] = -acc / Lc[static_cast<int64_t>(r0 + i) * s + r0 + i];
+      }
+    }
+    __syncthreads();
+    if (j < r0) {
+      // T(a) = sum_{k = j}^{r0 - 1} L(r0 + a, k) X(k, j), then X(r0 + a, j) = -sum_b X_rr(a, b) T(b)
+      double t[kPanel];
+#pragma unroll
+      for (int a = 0; a < kPanel; ++a) t[a] = 0.0;
+#pragma unroll 4
+      for (int k = j; k < r0; ++k) {
+        const double xkj = X[static_cast<int64_t>(k) * s + j];
+#pragma unroll
+        for (int a = 0; a < kPanel; ++a) t[a] = fma(Lr[a * kFusedMaxBlock + k], xkj, t[a]);
+      }
+      for (int a = 0; a < w; ++a) {
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 0; b < kPanel; ++b)
+          if (b <= a) acc = fma(Xd[a * kPanelLd + b], t[b], acc);
+        X[static_cast<int64_t>(r0 + a) * s + j] = -acc;
+      }
+    } else if (j < r0 + w) {
+      for (int a = 0; a < w; ++a) X[static_cast<int64_t>(r0 + a) * s + j] = Xd[a * kPanelLd + (j - r0)];
+    }
+    __syncthreads();
+  }
+  // G^{-1}(i, j) for rows i0 .. i0 + 31, thread j; Xt[k * kPanel + a] = X(k, i0 + a)
+  double* Xt = lds;
+  for (int i0 = 0; i0 < sb; i0 += kPanel) {
+    const int w = min(kPanel, sb - i0);
+    for (int e = tid; e < (sb - i0) * kPanel; e += kT) {
+      const int k = i0 + e / kPanel, a = e % kPanel;
+      Xt[k * kPanel + a] = (a < w && k >= i0 + a) ? X[static_cast<int64_t>(k) * s + i0 + a] : 0.0;
+    }
+    __syncthreads();
+    if (j < sb) {
+      double acc[kPanel];
+#pragma unroll
+      for (int a = 0; a < kPanel; ++a) acc[a] = 0.0;
+#pragma unroll 4
+      for (int k = max(i0, j); k < sb; ++k) {
+        const double xkj = X[static_cast<int64_t>(k) * s + j];
+        const double* xt = Xt + k * kPanel;
+#pragma unroll
+        for (int a = 0; a < kPanel; ++a) acc[a] = fma(xt[a], xkj, acc[a]);
+      }
+#pragma unroll
+      for (int a = 0; a < kPanel; ++a)
+        if (a < w) Gi[static_cast<int64_t>(i0 + a) * s + j] = acc[a];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < s * s; e += kT) {
+    const int i = e / s, jj = e - i * s;
+    if (i >= sb || jj >= sb) Gi[e] = 0.0;
+  }
+  if (chk.flag) {
+    __syncthreads();
+    double acc = 0.0;
+    for (int e = tid; e < sb * sb; e += kT) {
+      const int i = e / sb, jj = e - i * sb;
+      const double v = Gi[static_cast<int64_t>(i) * s + jj];
+      acc = fma(v, v, acc);
+    }
+    acc = block_sum(acc, red4);
+    if (tid == 0) flag_ill_conditioned(chk, blk, norm_g2, acc);
+  }
+}
+
+// --------------------------------------------------------------------------
 // memo miss for blocks of up to 128 rows, register resident: Cholesky
 // L L^T = G, then L^{-1} by Gauss-Jordan elimination on [L | I] (stored in
 // place), then G^{-1} = L^{-T} L^{-1}.  Thread (ty, tx) of a 16 x 16 grid
@@ -734,6 +975,17 @@ void launch_gram(int32_t kind, const double* A, int64_t lda, int64_t n, const in
 void launch_cholesky(double* G, int32_t s, int64_t stride, const int32_t* lens, int32_t nb,
                      const int32_t* slot_of, int32_t* err, hipStream_t st, FactorCheck chk) {
   if (nb <= 0) return;
+  if (s > kLdsCholMax && s <= kFusedMaxBlock) {
+    static bool attr_set = false;
+    if (!attr_set) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cholesky_panel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kCholPanelLds));
+      attr_set = true;
+    }
+    hipLaunchKernelGGL(k_cholesky_panel, dim3(nb), dim3(kT), kCholPanelLds, st, G, s, stride, lens, slot_of, err,
+                       chk);
+    return;
+  }
   if (s <= kLdsCholMax) {
     const size_t lds = static_cast<size_t>(s) * s * sizeof(double);
     static bool attr_set = false;
@@ -767,6 +1019,17 @@ void launch_check_finite(const double* A, int64_t lda, int64_t m, int64_t n, con
 void launch_factor_inverse(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
                            const int32_t* slot_of, hipStream_t st, FactorCheck chk, const int32_t* skip) {
   if (nb <= 0) return;
+  if (s > kLdsCholMax && s <= kFusedMaxBlock) {
+    static bool attr_set = false;
+    if (!attr_set) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_inverse_blocked),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kInverseBlockedLds));
+      attr_set = true;
+    }
+    hipLaunchKernelGGL(k_inverse_blocked, dim3(nb), dim3(kT), kInverseBlockedLds, st, slots, stride, s, lens,
+                       slot_of, chk, skip);
+    return;
+  }
   if (s <= kLdsCholMax) {
     const size_t lds = (static_cast<size_t>(s) * (s + 1) + s) * sizeof(double);
     static bool attr_set = false;

@@ -84,15 +84,17 @@ void launch_gram_syrk_f32(const float* A, int64_t lda, int64_t n, const int32_t*
                           int32_t nb, double lambda, double* G, int64_t stride, const int32_t* slot_of,
                           double* ws, hipStream_t st);
 
-// In-place Cholesky of nb slots; breakdown sets *err = 1.
+// In-place Cholesky of nb slots; breakdown sets *err = 1.  Blocks of
+// kLdsCholMax+1 .. kFusedMaxBlock rows are factored in LDS panels.
 void launch_cholesky(double* G, int32_t s, int64_t stride, const int32_t* lens, int32_t nb,
                      const int32_t* slot_of, int32_t* err, hipStream_t st, FactorCheck chk = FactorCheck());
 
 // G^{-1} = L^{-T} L^{-1} of each slot's factor (at +s*s, full symmetric);
-// blocks larger than kLdsCholMax use the slot's last s*s doubles as scratch.
-// With chk.flag set (low-precision pass), blocks whose Frobenius condition
-// number exceeds chk.kappa_max are flagged; launch_cholesky with the same
-// check must have run first (it leaves ||G||_F^2 in the slot).
+// blocks larger than kLdsCholMax use the slot's last s*s doubles as scratch
+// (blocked in LDS up to kFusedMaxBlock rows).  With chk.flag set
+// (low-precision pass), blocks whose Frobenius condition number exceeds
+// chk.kappa_max are flagged; launch_cholesky with the same check must have run
+// first (it leaves ||G||_F^2 in the slot).
 void launch_factor_inverse(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
                            const int32_t* slot_of, hipStream_t st, FactorCheck chk = FactorCheck(),
                            const int32_t* skip = nullptr);

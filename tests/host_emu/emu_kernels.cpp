@@ -104,7 +104,8 @@ void launch_gram_syrk_f32(const float*, int64_t, int64_t, const int32_t*, const 
 void launch_cholesky(double* G, int32_t s, int64_t stride, const int32_t* lens, int32_t nb, const int32_t* slot_of,
                      int32_t* err, hipStream_t, FactorCheck chk) {
   if (nb <= 0) return;
-  check_slots(G, stride, s, lens, nb, slot_of, 3 * static_cast<int64_t>(s) * s, "cholesky slots");
+  const int64_t ss = static_cast<int64_t>(s) * s;
+  check_slots(G, stride, s, lens, nb, slot_of, chk.flag ? 3 * ss : ss, "cholesky slots");
   emu_check(err, 4, "cholesky err");
   if (chk.flag) { emu_check(chk.flag, 4 * nb, "cholesky flag"); for (int k = 0; k < nb; ++k) chk.flag[k] = 0; }
 }
