@@ -460,6 +460,20 @@ __global__ __launch_bounds__(kT) void k_factor_inverse(double* __restrict__ slot
 // --------------------------------------------------------------------------
 constexpr int kPanel = 32;
 constexpr int kPanelLd = kPanel + 1;
+
+// acc[c] += f * row[c], c < 32, with the LDS row read in 16-byte loads issued
+// together (row 16-byte aligned)
+__device__ __forceinline__ void axpy_row32(double (&acc)[32], double f, const double* row) {
+  const double2* r2 = reinterpret_cast<const double2*>(row);
+  double2 v[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) v[c] = r2[c];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    acc[2 * c] = fma(f, v[c].x, acc[2 * c]);
+    acc[2 * c + 1] = fma(f, v[c].y, acc[2 * c + 1]);
+  }
+}
 constexpr size_t kCholPanelLds =
     (static_cast<size_t>(kFusedMaxBlock) * kPanelLd + static_cast<size_t>(kFusedMaxBlock) * kPanel) * sizeof(double);
 constexpr size_t kInverseBlockedLds =
@@ -473,6 +487,8 @@ __global__ __launch_bounds__(kT) void k_cholesky_panel(double* __restrict__ G, i
   double* P = lds;                                  // P[i * kPanelLd + c] = G(p0 + i, p0 + c)
   double* Lt = lds + kFusedMaxBlock * kPanelLd;     // Lt[k * kPanel + c] = L(p0 + c, k), k < p0
   __shared__ double red4[4];
+  __shared__ double colbuf[kPanel];
+  __shared__ double piv;
   __shared__ int bad_any;
   const int blk = blockIdx.x;
   if (chk.only && !chk.only[blk]) return;
@@ -511,36 +527,46 @@ __global__ __launch_bounds__(kT) void k_cholesky_panel(double* __restrict__ G, i
 #pragma unroll
       for (int c = 0; c < kPanel; ++c) acc[c] = c < pw ? P[tid * kPanelLd + c] : 0.0;
       const double* Lrow = Gb + p0 + tid;
-      for (int k = 0; k < p0; ++k) {
-        const double l = Lrow[static_cast<int64_t>(k) * s];
-        const double* lt = Lt + k * kPanel;
+      // p0 is a multiple of kPanel: eight entries of this row of L in flight
+      for (int k0 = 0; k0 < p0; k0 += 8) {
+        double l8[8];
 #pragma unroll
-        for (int c = 0; c < kPanel; ++c) acc[c] = fma(-l, lt[c], acc[c]);
+        for (int q = 0; q < 8; ++q) l8[q] = Lrow[static_cast<int64_t>(k0 + q) * s];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) axpy_row32(acc, -l8[q], Lt + (k0 + q) * kPanel);
       }
 #pragma unroll
       for (int c = 0; c < kPanel; ++c)
         if (c < pw) P[tid * kPanelLd + c] = acc[c];
     }
     __syncthreads();
-    for (int c = 0; c < pw; ++c) {
-      const double d2 = P[c * kPanelLd + c];
-      if (!(d2 > 0.0)) bad = 1;
-      const double d = sqrt(d2);
-      __syncthreads();
-      if (tid > c && tid < R) P[tid * kPanelLd + c] /= d;
-      if (tid == 0) P[c * kPanelLd + c] = d;
-      __syncthreads();
-      if (tid > c && tid < R) {
-        const double lic = P[tid * kPanelLd + c];
-        for (int c2 = c + 1; c2 < pw && c2 <= tid; ++c2)
-          P[tid * kPanelLd + c2] = fma(-lic, P[c2 * kPanelLd + c], P[tid * kPanelLd + c2]);
+    // factor the panel with row tid in registers: per column, the pivot and
+    // the column's entries in the panel's first rows go through LDS
+    double prow[kPanel];
+#pragma unroll
+    for (int c = 0; c < kPanel; ++c) prow[c] = (tid < R && c < pw) ? P[tid * kPanelLd + c] : 0.0;
+#pragma unroll
+    for (int c = 0; c < kPanel; ++c) {
+      if (c < pw) {
+        if (tid == c) piv = prow[c];
+        __syncthreads();
+        const double d2 = piv;
+        if (!(d2 > 0.0)) bad = 1;
+        const double d = sqrt(d2);
+        if (tid == c) prow[c] = d;
+        if (tid > c) prow[c] /= d;
+        if (tid < pw) colbuf[tid] = prow[c];
+        __syncthreads();
+        if (tid > c && tid < R) {
+#pragma unroll
+          for (int c2 = c + 1; c2 < kPanel; ++c2)
+            if (c2 < pw && c2 <= tid) prow[c2] = fma(-prow[c], colbuf[c2], prow[c2]);
+        }
       }
-      __syncthreads();
     }
-    for (int e = tid; e < R * pw; e += kT) {
-      const int c = e / R, i = e - c * R;
-      if (i >= c) Gb[static_cast<int64_t>(p0 + c) * s + p0 + i] = P[i * kPanelLd + c];
-    }
+#pragma unroll
+    for (int c = 0; c < kPanel; ++c)
+      if (c < pw && tid < R && tid >= c) Gb[static_cast<int64_t>(p0 + c) * s + p0 + tid] = prow[c];
     __syncthreads();
   }
   if (bad) atomicOr(&bad_any, 1);
@@ -585,7 +611,7 @@ __global__ __launch_bounds__(kT) void k_inverse_blocked(double* __restrict__ slo
                                                         const int32_t* __restrict__ slot_of, FactorCheck chk,
                                                         const int32_t* __restrict__ skip) {
   extern __shared__ double lds[];
-  double* Lr = lds;                                 // Lr[a * kFusedMaxBlock + k] = L(r0 + a, k); later Xt
+  double* Lr = lds;                                 // Lr[k * kPanel + a] = L(r0 + a, k), k < r0 + w; later Xt
   double* Xd = lds + kPanel * kFusedMaxBlock;       // Xd[a * kPanelLd + c] = X(r0 + a, r0 + c)
   __shared__ double red4[4];
   const int blk = blockIdx.x;
@@ -602,9 +628,9 @@ __global__ __launch_bounds__(kT) void k_inverse_blocked(double* __restrict__ slo
   const int j = tid;
   for (int r0 = 0; r0 < sb; r0 += kPanel) {
     const int w = min(kPanel, sb - r0);
-    for (int e = tid; e < w * r0; e += kT) {
-      const int k = e / w, a = e - k * w;
-      Lr[a * kFusedMaxBlock + k] = Lc[static_cast<int64_t>(k) * s + r0 + a];
+    for (int e = tid; e < kPanel * (r0 + w); e += kT) {
+      const int k = e / kPanel, a = e - k * kPanel;
+      Lr[k * kPanel + a] = a < w ? Lc[static_cast<int64_t>(k) * s + r0 + a] : 0.0;
     }
     // X_rr = L_rr^{-1}: thread c < w substitutes down column c
     for (int e = tid; e < w * w; e += kT) {
@@ -613,13 +639,26 @@ __global__ __launch_bounds__(kT) void k_inverse_blocked(double* __restrict__ slo
     }
     __syncthreads();
     if (tid < w) {
+      // column c of X_rr in registers, rows i > c by substitution
       const int c = tid;
-      Xd[c * kPanelLd + c] = 1.0 / Lc[static_cast<int64_t>(r0 + c) * s + r0 + c];
-      for (int i = c + 1; i < w; ++i) {
-        double acc = 0.0;
-        for (int k = c; k < i; ++k) acc = fma(Lc[static_cast<int64_t>(r0 + k) * s + r0 + i], Xd[k * kPanelLd + c], acc);
-        Xd[i * kPanelLd + c] = -acc / Lc[static_cast<int64_t>(r0 + i) * s + r0 + i];
+      double xc[kPanel];
+#pragma unroll
+      for (int i = 0; i < kPanel; ++i) {
+        double v = 0.0;
+        if (i == c) {
+          v = 1.0 / Lr[(r0 + i) * kPanel + i];
+        } else if (i > c && i < w) {
+          double acc = 0.0;
+#pragma unroll
+          for (int k = 0; k < i; ++k)
+            if (k >= c) acc = fma(Lr[(r0 + k) * kPanel + i], xc[k], acc);
+          v = -acc / Lr[(r0 + i) * kPanel + i];
+        }
+        xc[i] = v;
       }
+#pragma unroll
+      for (int i = 0; i < kPanel; ++i)
+        if (i < w) Xd[i * kPanelLd + c] = xc[i];
     }
     __syncthreads();
     if (j < r0) {
@@ -627,11 +666,13 @@ __global__ __launch_bounds__(kT) void k_inverse_blocked(double* __restrict__ slo
       double t[kPanel];
 #pragma unroll
       for (int a = 0; a < kPanel; ++a) t[a] = 0.0;
-#pragma unroll 4
-      for (int k = j; k < r0; ++k) {
-        const double xkj = X[static_cast<int64_t>(k) * s + j];
+      for (int k0 = j; k0 < r0; k0 += 8) {
+        double x8[8];
 #pragma unroll
-        for (int a = 0; a < kPanel; ++a) t[a] = fma(Lr[a * kFusedMaxBlock + k], xkj, t[a]);
+        for (int q = 0; q < 8; ++q) x8[q] = k0 + q < r0 ? X[static_cast<int64_t>(k0 + q) * s + j] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (k0 + q < r0) axpy_row32(t, x8[q], Lr + (k0 + q) * kPanel);
       }
       for (int a = 0; a < w; ++a) {
         double acc = 0.0;
@@ -658,12 +699,13 @@ __global__ __launch_bounds__(kT) void k_inverse_blocked(double* __restrict__ slo
       double acc[kPanel];
 #pragma unroll
       for (int a = 0; a < kPanel; ++a) acc[a] = 0.0;
-#pragma unroll 4
-      for (int k = max(i0, j); k < sb; ++k) {
-        const double xkj = X[static_cast<int64_t>(k) * s + j];
-        const double* xt = Xt + k * kPanel;
+      for (int k0 = max(i0, j); k0 < sb; k0 += 8) {
+        double x8[8];
 #pragma unroll
-        for (int a = 0; a < kPanel; ++a) acc[a] = fma(xt[a], xkj, acc[a]);
+        for (int q = 0; q < 8; ++q) x8[q] = k0 + q < sb ? X[static_cast<int64_t>(k0 + q) * s + j] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (k0 + q < sb) axpy_row32(acc, x8[q], Xt + (k0 + q) * kPanel);
       }
 #pragma unroll
       for (int a = 0; a < kPanel; ++a)
