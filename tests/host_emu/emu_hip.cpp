@@ -50,7 +50,15 @@ hipError_t hipMemcpyAsync(void* d, const void* s, size_t bytes, hipMemcpyKind k,
   if (k != hipMemcpyHostToDevice) emu_check(s, bytes, "memcpy src");
   std::memmove(d, s, bytes); return hipSuccess; }
 hipError_t hipMemcpy(void* d, const void* s, size_t bytes, hipMemcpyKind k) { return hipMemcpyAsync(d, s, bytes, k, nullptr); }
-hipError_t hipMemsetAsync(void* d, int v, size_t bytes, hipStream_t) { emu_check(d, bytes, "memset"); std::memset(d, v, bytes); return hipSuccess; }
+namespace kpp {
+void emu_note_memset(const void* d);
+}
+hipError_t hipMemsetAsync(void* d, int v, size_t bytes, hipStream_t) {
+  emu_check(d, bytes, "memset");
+  std::memset(d, v, bytes);
+  kpp::emu_note_memset(d);
+  return hipSuccess;
+}
 hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 hipError_t hipStreamCreateWithFlags(hipStream_t* st, unsigned) { *st = reinterpret_cast<hipStream_t>(new char[8]); return hipSuccess; }
 hipError_t hipStreamDestroy(hipStream_t st) { delete[] reinterpret_cast<char*>(st); return hipSuccess; }

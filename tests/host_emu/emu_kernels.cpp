@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <map>
+#include <mutex>
 
 #include "kernels.hpp"
 
@@ -185,6 +186,26 @@ void launch_axpy1(double* x, const double* d, int64_t n, hipStream_t) {
   emu_check(x, 8 * n, "axpy x");
   emu_check(d, 8 * n, "axpy d");
 }
+// The step kernel's flags hold the step (epoch) each workgroup last
+// published: a run continues exactly where the last one on the same flags
+// stopped, or starts at 0 after the flags were cleared.
+static std::map<const void*, uint32_t> g_next_epoch;
+static std::mutex g_epoch_mu;
+void emu_note_memset(const void* d) {
+  std::lock_guard<std::mutex> lk(g_epoch_mu);
+  g_next_epoch.erase(d);
+}
+static void check_epoch(const FusedArgs& a, int64_t steps_run) {
+  std::lock_guard<std::mutex> lk(g_epoch_mu);
+  auto it = g_next_epoch.find(a.flags);
+  const uint32_t expect = it == g_next_epoch.end() ? 0u : it->second;
+  if (a.epoch != expect) {
+    std::fprintf(stderr, "EMU: step kernel epoch %u on flags that stopped at %u\n", a.epoch, expect);
+    std::abort();
+  }
+  g_next_epoch[a.flags] = a.epoch + static_cast<uint32_t>(steps_run);
+}
+
 static void emu_fused(const FusedArgs& a, int32_t cpl, int32_t G, bool fp32) {
   const int64_t s = a.s;
   emu_check(a.step_slot, 4 * static_cast<size_t>(a.W), "fused step_slot");
@@ -207,6 +228,7 @@ static void emu_fused(const FusedArgs& a, int32_t cpl, int32_t G, bool fp32) {
     emu_check(a.zm, 8 * a.mrows, "fused zm");
     if ((a.mrows + G - 1) / G > 1024) { std::fprintf(stderr, "EMU: dual slice too long\n"); std::abort(); }
   }
+  int64_t ran = 0;
   for (int k = 0; k < a.W; ++k) {
     const int q = a.step_slot[k];
     emu_check(a.lens + q, 4, "fused lens");
@@ -218,8 +240,10 @@ static void emu_fused(const FusedArgs& a, int32_t cpl, int32_t G, bool fp32) {
     emu_check(a.L + q * a.slot_stride + s * s, 8 * static_cast<size_t>(s) * s, "fused Ginv");
     bool stop = false;
     emu_step(a.ds, a.zeta, &stop);
+    ++ran;
     if (a.stop_on_cand && stop) break;
   }
+  check_epoch(a, ran);
 }
 void launch_fused(int32_t, bool a_fp32, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t) {
   emu_fused(a, cpl, groups, a_fp32);
