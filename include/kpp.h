@@ -105,7 +105,21 @@ typedef struct kpp_params {
                                  residual estimate stalls (FP32 precision floor)    */
   int32_t engine;             /* 0: auto, 1: one launch per phase, 2: fused persistent  */
   int32_t team_groups;        /* fused engine: workgroups sharing one step (0: auto)    */
-  double reserved1[4];
+  /* Optional caller-given block schedule (host memory, read during kpp_solve;
+   * the caller keeps ownership).  When schedule is not NULL it replaces the
+   * memo/seed/num_blocks/fixed_partition settings: step t uses block
+   * schedule[t] of the table block_rows (block_rows_count x block_size row
+   * indices, ascending, a shorter block padded with -1), each block is
+   * factored on first use and kept for the rest of the solve (Algorithm 1's
+   * fixed collection with the paper's "if no factor is cached for S" rule),
+   * and a solve runs at most min(max_iters, schedule_len) steps.  FP64 and
+   * kpp_solve only: mixed precision and kpp_server_submit reject it with
+   * KPP_ERR_INVALID_ARG, as does a malformed table or an id out of range. */
+  const int32_t* schedule;
+  int64_t schedule_len;
+  const int32_t* block_rows;
+  int32_t block_rows_count;
+  int32_t reserved2;
 } kpp_params;
 
 /* Per-solve report. */

@@ -64,7 +64,11 @@ class kpp_params(ctypes.Structure):
         ("inner_tol", ctypes.c_double),
         ("engine", ctypes.c_int32),
         ("team_groups", ctypes.c_int32),
-        ("reserved1", ctypes.c_double * 4),
+        ("schedule", ctypes.c_void_p),
+        ("schedule_len", ctypes.c_int64),
+        ("block_rows", ctypes.c_void_p),
+        ("block_rows_count", ctypes.c_int32),
+        ("reserved2", ctypes.c_int32),
     ]
 
 
@@ -232,6 +236,21 @@ def kpp_schedule_generate(kind: int, m: int, n: int, params: kpp_params, T: int,
                                       blocks_cap, ctypes.byref(nb)))
     k = nb.value
     return (list(steps[:T]), [list(rows[b * s:(b + 1) * s]) for b in range(k)], list(lens[:k]))
+
+
+def kpp_set_schedule(params: kpp_params, step_block, block_rows):
+    """Point params at a caller-given schedule: step_block[t] is the block of
+    step t, block_rows a (blocks x block_size) table of row indices (ascending,
+    -1 after the last row of a shorter block).  Returns the int32 arrays the
+    pointers refer to; keep them alive until kpp_solve returns."""
+    steps = (ctypes.c_int32 * max(len(step_block), 1))(*[int(v) for v in step_block])
+    flat = [int(v) for row in block_rows for v in row]
+    table = (ctypes.c_int32 * max(len(flat), 1))(*flat)
+    params.schedule = ctypes.cast(steps, ctypes.c_void_p).value
+    params.schedule_len = len(step_block)
+    params.block_rows = ctypes.cast(table, ctypes.c_void_p).value
+    params.block_rows_count = len(block_rows)
+    return steps, table
 
 
 def kpp_block_factor(sys_: int, s: int, lam: float, rows, lens, L_dev: int) -> None:

@@ -106,6 +106,7 @@ struct kpp_system {
   // signature of the schedule the cache belongs to
   bool memo_valid = false;
   int32_t sig_s = 0, sig_memo = 0, sig_nb = 0, sig_part = 0, sig_prec = 0;
+  bool sig_explicit = false;
   uint64_t sig_seed = 0;
   double sig_lambda = 0.0;
   // per-window staging (pinned host mirror + device copy): block rows, lengths,
@@ -299,6 +300,12 @@ kpp_status check_params(const kpp_system* sys, const kpp_params* p) {
     return fail(KPP_ERR_INVALID_ARG, "the fused engine takes block_size <= %d", kpp::kFusedMaxBlock);
   if (p->team_groups < 0 || p->team_groups > kpp::kFusedMaxGroups)
     return fail(KPP_ERR_INVALID_ARG, "team_groups must be in [0, %d]", kpp::kFusedMaxGroups);
+  if (p->schedule) {
+    if (p->schedule_len < 0) return fail(KPP_ERR_INVALID_ARG, "schedule_len must be >= 0");
+    if (!p->block_rows || p->block_rows_count < 1)
+      return fail(KPP_ERR_INVALID_ARG, "an explicit schedule needs block_rows and block_rows_count >= 1");
+    if (p->precision != KPP_FP64) return fail(KPP_ERR_INVALID_ARG, "an explicit schedule runs in FP64 only");
+  }
   return KPP_OK;
 }
 
@@ -444,7 +451,13 @@ class CoreRun {
     max_iters_ = o.max_iters;
     const double B0 = kpp::online_rate(kind_, m_, n_, s_);
     try {
-      sch_.reset(new kpp::BlockSchedule(mode_, N_, s_, p->seed, B0, p->num_blocks, p->fixed_partition != 0));
+      if (p->schedule) {
+        sch_.reset(new kpp::BlockSchedule(N_, s_, p->block_rows, p->block_rows_count, p->schedule, p->schedule_len));
+        mode_ = kpp::MemoMode::Fixed;
+        max_iters_ = std::min(max_iters_, p->schedule_len);
+      } else {
+        sch_.reset(new kpp::BlockSchedule(mode_, N_, s_, p->seed, B0, p->num_blocks, p->fixed_partition != 0));
+      }
     } catch (const std::exception& e) {
       return fail(KPP_ERR_INVALID_ARG, "%s", e.what());
     }
@@ -481,7 +494,8 @@ class CoreRun {
     const bool same_sig = sys->memo_valid && o.keep_memo && sys->sig_s == s_ && sys->sig_memo == p->memo &&
                           sys->sig_nb == p->num_blocks && sys->sig_part == p->fixed_partition &&
                           sys->sig_seed == p->seed && sys->sig_lambda == p->lambda &&
-                          sys->sig_prec == (fp32_ ? 1 : 0) && mode_ != kpp::MemoMode::Off;
+                          sys->sig_prec == (fp32_ ? 1 : 0) && mode_ != kpp::MemoMode::Off &&
+                          !sch_->is_explicit() && !sys->sig_explicit;
     if (!same_sig) {
       sys->slot_of_block.clear();
       sys->used_slots = 0;
@@ -493,6 +507,7 @@ class CoreRun {
       sys->sig_seed = p->seed;
       sys->sig_lambda = p->lambda;
       sys->sig_prec = fp32_ ? 1 : 0;
+      sys->sig_explicit = sch_->is_explicit();
     }
     // launch engine: column chunks of the block gemv
     P_ = static_cast<int32_t>((n_ + kChunk - 1) / kChunk);
@@ -1815,8 +1830,12 @@ KPP_API kpp_status kpp_schedule_generate(int32_t kind, int64_t m, int64_t n, con
   const int64_t N = kind == KPP_CD_PSD ? n : m;
   const int32_t s = p->block_size;
   try {
-    kpp::BlockSchedule sch(static_cast<kpp::MemoMode>(p->memo), N, s, p->seed,
-                           kpp::online_rate(kind, m, n, s), p->num_blocks, p->fixed_partition != 0);
+    if (p->schedule && T > p->schedule_len)
+      return fail(KPP_ERR_INVALID_ARG, "T = %lld exceeds schedule_len", static_cast<long long>(T));
+    kpp::BlockSchedule sch = p->schedule
+        ? kpp::BlockSchedule(N, s, p->block_rows, p->block_rows_count, p->schedule, p->schedule_len)
+        : kpp::BlockSchedule(static_cast<kpp::MemoMode>(p->memo), N, s, p->seed, kpp::online_rate(kind, m, n, s),
+                             p->num_blocks, p->fixed_partition != 0);
     for (int64_t t = 0; t < T; ++t) step_block_host[t] = sch.next(nullptr);
     const int32_t nb = sch.num_blocks();
     *num_blocks_out = nb;
@@ -1950,6 +1969,7 @@ KPP_API kpp_status kpp_server_submit(kpp_server* srv, kpp_system* sys, const kpp
   if (sys->ctx != srv->ctx) return fail(KPP_ERR_INVALID_ARG, "the system belongs to another context");
   KPP_TRY(check_params(sys, p));
   if (p->engine == 1) return fail(KPP_ERR_INVALID_ARG, "the server runs the fused engine only");
+  if (p->schedule) return fail(KPP_ERR_INVALID_ARG, "explicit schedules are for kpp_solve");
   auto* r = new (std::nothrow) ServeReq;
   if (!r) return fail(KPP_ERR_OOM, "host allocation failed");
   r->sys = sys;

@@ -64,9 +64,43 @@ void BlockSchedule::add_subset() {
   for (int64_t k : touched_) perm_[k] = static_cast<int32_t>(k);
 }
 
+BlockSchedule::BlockSchedule(int64_t N, int32_t s, const int32_t* table, int32_t B, const int32_t* seq, int64_t L)
+    : mode_(MemoMode::Fixed), N_(N), s_(s), B0_(0.0), g_(0), explicit_(true) {
+  if (s < 1 || N < s) throw std::invalid_argument("block size must satisfy 1 <= s <= rows");
+  if (B < 1 || table == nullptr) throw std::invalid_argument("an explicit schedule needs a table of at least one block");
+  if (L < 0 || (L > 0 && seq == nullptr)) throw std::invalid_argument("explicit schedule: bad step sequence");
+  rows_.assign(table, table + static_cast<size_t>(B) * s);
+  for (int32_t b = 0; b < B; ++b) {
+    const int32_t* r = table + static_cast<size_t>(b) * s;
+    int32_t l = 0;
+    while (l < s && r[l] >= 0) ++l;
+    if (l == 0) throw std::invalid_argument("explicit schedule: empty block");
+    for (int32_t j = l; j < s; ++j)
+      if (r[j] != -1) throw std::invalid_argument("explicit schedule: rows after the padding of a block");
+    for (int32_t j = 0; j < l; ++j) {
+      if (r[j] >= N) throw std::invalid_argument("explicit schedule: row index out of range");
+      if (j > 0 && r[j] <= r[j - 1]) throw std::invalid_argument("explicit schedule: rows of a block must ascend");
+    }
+    len_.push_back(l);
+  }
+  seq_.assign(seq, seq + L);
+  for (int32_t b : seq_)
+    if (b < 0 || b >= B) throw std::invalid_argument("explicit schedule: block id out of range");
+  used_.assign(len_.size(), 0);
+}
+
 int32_t BlockSchedule::next(bool* is_new) {
   int32_t b;
   bool fresh = false;
+  if (explicit_) {
+    if (t_ >= static_cast<int64_t>(seq_.size())) throw std::out_of_range("explicit schedule exhausted");
+    b = seq_[static_cast<size_t>(t_)];
+    fresh = !used_[b];
+    used_[b] = 1;
+    ++t_;
+    if (is_new) *is_new = fresh;
+    return b;
+  }
   switch (mode_) {
     case MemoMode::Fixed: {
       b = static_cast<int32_t>(g_.bounded(len_.size()));

@@ -20,6 +20,9 @@
 //           last chunk possibly shorter) or num_blocks subsets -- and each
 //           step uses block bounded(B).
 //   OFF:    a new subset at every step; its factor is not kept.
+//   Explicit (caller-given): a table of blocks (rows ascending, -1 after the
+//           last row of a shorter block) and the block id of every step; each
+//           block is factored on first use and kept, as in FIXED.
 #pragma once
 
 #include <cstdint>
@@ -54,6 +57,9 @@ class BlockSchedule {
  public:
   BlockSchedule(MemoMode mode, int64_t N, int32_t s, uint64_t seed, double B0,
                 int32_t num_blocks, bool partition);
+  // Explicit schedule: table holds B x s row indices, seq the block of each of
+  // L steps.  Throws std::invalid_argument on a malformed table or sequence.
+  BlockSchedule(int64_t N, int32_t s, const int32_t* table, int32_t B, const int32_t* seq, int64_t L);
 
   // Block id of the next step; *is_new is set when that block is used for the
   // first time (its factor has to be computed).
@@ -66,6 +72,8 @@ class BlockSchedule {
   int32_t len(int32_t b) const { return len_[b]; }
   // For OFF mode the table only needs the latest block: callers may drop old ones.
   MemoMode mode() const { return mode_; }
+  bool is_explicit() const { return explicit_; }
+  int64_t length() const { return static_cast<int64_t>(seq_.size()); }
 
  private:
   void add_subset();
@@ -80,6 +88,8 @@ class BlockSchedule {
   std::vector<uint8_t> used_;
   std::vector<int32_t> perm_;
   std::vector<int64_t> touched_;
+  bool explicit_ = false;
+  std::vector<int32_t> seq_;
 };
 
 // B0 of the Bernoulli(min(1, B0 / t)) rule.

@@ -98,3 +98,35 @@ def test_schedule_rejects_small_capacity(kpp):
     p.memo = kpp.KPP_MEMO_FIXED
     with pytest.raises(kpp.KppError):
         kpp.kpp_schedule_generate(kpp.KPP_CD_PSD, 100, 100, p, 5, 3)
+
+
+def test_explicit_schedule_is_used_as_given(kpp):
+    """A caller-given schedule replaces the generator: the steps come back as
+    given and the table as given (padding -1)."""
+    p = kpp.kpp_params_default(kpp.KPP_KACZMARZ)
+    p.block_size = 4
+    table = [[0, 3, 7, 9], [1, 2, -1, -1], [4, 5, 6, 8]]
+    steps = [2, 0, 0, 1, 2, 1, 0]
+    keep = kpp.kpp_set_schedule(p, steps, table)
+    got_steps, rows, lens = kpp.kpp_schedule_generate(kpp.KPP_KACZMARZ, 10, 6, p, len(steps), 3)
+    assert got_steps == steps
+    assert rows == table and lens == [4, 2, 4]
+    with pytest.raises(kpp.KppError):
+        kpp.kpp_schedule_generate(kpp.KPP_KACZMARZ, 10, 6, p, len(steps) + 1, 3)
+    del keep
+
+
+@pytest.mark.parametrize("table,steps", [
+    ([[0, 3, 2, 9]], [0]),            # rows not ascending
+    ([[0, 3, 7, 10]], [0]),           # row out of range (10 rows)
+    ([[0, -1, 7, 9]], [0]),           # a row after the padding
+    ([[-1, -1, -1, -1]], [0]),        # empty block
+    ([[0, 1, 2, 3]], [0, 1]),         # block id out of range
+])
+def test_explicit_schedule_rejects_malformed_input(kpp, table, steps):
+    p = kpp.kpp_params_default(kpp.KPP_KACZMARZ)
+    p.block_size = 4
+    keep = kpp.kpp_set_schedule(p, steps, table)
+    with pytest.raises(kpp.KppError):
+        kpp.kpp_schedule_generate(kpp.KPP_KACZMARZ, 10, 6, p, len(steps), 4)
+    del keep

@@ -268,6 +268,51 @@ def test_split_y_team_sizes_agree_with_oracle(env, n):
     assert relerr(x, ref.x) <= 1e-10
 
 
+@pytest.mark.parametrize("engine", [1, 2], ids=["launch", "fused"])
+def test_explicit_schedule_matches_oracle(env, engine):
+    """A caller-given schedule (overlapping blocks, one of them ragged, steps
+    drawn by numpy) gives the oracle's iterates on the same schedule; a step
+    budget past the schedule's end stops at its end."""
+    kpp, torch, dev, ctx = env
+    sysm = synth.tiny_system("general", 300, 120, seed=21, cond=20.0)
+    A, b = sysm.A, sysm.b
+    m, n = A.shape
+    s, T = 16, 150
+    rng = np.random.default_rng(4)
+    blocks = [np.sort(rng.choice(m, size=s, replace=False)) for _ in range(6)]
+    blocks.append(np.sort(rng.choice(m, size=10, replace=False)))
+    steps = rng.integers(0, len(blocks), size=T)
+    table = [list(map(int, blk)) + [-1] * (s - len(blk)) for blk in blocks]
+    p = kpp.kpp_params_default(kpp.KPP_KACZMARZ)
+    p.block_size = s
+    p.lambda_ = 1e-4
+    p.tol = 0.0
+    p.max_iters = T + 40
+    p.engine = engine
+    keep = kpp.kpp_set_schedule(p, steps.tolist(), table)
+    Ad = torch.from_numpy(np.ascontiguousarray(A)).to(dev)
+    bd = torch.from_numpy(np.ascontiguousarray(b)).to(dev)
+    xd = torch.zeros(n, dtype=torch.float64, device=dev)
+    h = kpp.kpp_system_create(ctx, kpp.KPP_KACZMARZ, m, n, Ad.data_ptr(), n, bd.data_ptr())
+    try:
+        st, res = kpp.kpp_solve(h, p, xd.data_ptr())
+    finally:
+        kpp.kpp_system_destroy(h)
+    del keep
+    x = xd.cpu().numpy()
+    first = np.zeros(T, dtype=bool)
+    seen = set()
+    for t, blk_id in enumerate(steps.tolist()):
+        first[t] = blk_id not in seen
+        seen.add(blk_id)
+    schd = osch.Schedule(blocks=[blk.astype(np.int64) for blk in blocks], step_block=steps.astype(np.int64),
+                         new_block=first)
+    ref = okpp.solve(A, b, "general", okpp.Params(s=s, lam=1e-4, tol=0.0, max_iters=T), schd)
+    assert st == kpp.KPP_NOT_CONVERGED and res.iters == T
+    assert res.memo_misses == len(set(steps.tolist())) == ref.factorizations
+    assert relerr(x, ref.x) <= 1e-10
+
+
 # ---------------------------------------------------------------------------
 # edge cases and error paths
 # ---------------------------------------------------------------------------
