@@ -119,7 +119,11 @@ typedef struct kpp_params {
   int64_t schedule_len;
   const int32_t* block_rows;
   int32_t block_rows_count;
-  int32_t reserved2;
+  /* 1: continue the saved state of this system (the last FP64 kpp_solve on
+   * it, or kpp_state_import) instead of starting with zero momentum, rho0 and
+   * a fresh schedule: x_dev must hold the iterate that solve returned, and
+   * max_iters counts the further steps.  FP64 and kpp_solve only. */
+  int32_t resume;
 } kpp_params;
 
 /* Per-solve report. */
@@ -193,6 +197,23 @@ KPP_API kpp_status kpp_system_destroy(kpp_system* sys);
  * when max_iters steps ran first.  `res` may be NULL. */
 KPP_API kpp_status kpp_solve(kpp_system* sys, const kpp_params* p, double* x_dev,
                              kpp_result* res);
+
+/* Resume support.  After an FP64 kpp_solve a system holds what is needed to
+ * continue that solve: the momentum vector, the step counter and checkpoint
+ * statistics (rho, r_hat, E0, E1: Section 5.4) and the block schedule's
+ * generator (Section 5.2).  kpp_state_export writes it to host memory owned by
+ * the caller (host_buf NULL: only *bytes is set to the size needed; otherwise
+ * *bytes is the buffer's size on entry and the size written on return;
+ * KPP_ERR_INVALID_ARG when it is too small or the system holds no state).
+ * kpp_state_import loads such a buffer into a system of the same kind and
+ * shape (KPP_ERR_SHAPE otherwise); a kpp_solve with params.resume = 1 then
+ * continues from it.  The memo cache is not part of the state: factors are
+ * formed again on first use.  Continuing a CD++ solve this way gives the same
+ * iterates, bit for bit, as one uninterrupted solve; Kaczmarz++ agrees up to
+ * the rounding of Grams formed in a different batch.  The state holds no x:
+ * the caller keeps the iterate it passed to kpp_solve. */
+KPP_API kpp_status kpp_state_export(const kpp_system* sys, void* host_buf, size_t* bytes);
+KPP_API kpp_status kpp_state_import(kpp_system* sys, const void* host_buf, size_t bytes);
 
 /* The block schedule kpp_solve uses for these settings, on the host (Section
  * 5.2; Algorithms 1, 2, 5).  rows = m (Kaczmarz++) or n (CD++).  Writes the

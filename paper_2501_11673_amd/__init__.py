@@ -68,7 +68,7 @@ class kpp_params(ctypes.Structure):
         ("schedule_len", ctypes.c_int64),
         ("block_rows", ctypes.c_void_p),
         ("block_rows_count", ctypes.c_int32),
-        ("reserved2", ctypes.c_int32),
+        ("resume", ctypes.c_int32),
     ]
 
 
@@ -161,6 +161,8 @@ def _load():
         "kpp_server_poll": (i32, [vp, i32, f64, P(ctypes.c_uint64), P(i32), P(kpp_result), P(i32)]),
         "kpp_server_stats": (i32, [vp, P(kpp_server_info)]),
         "kpp_server_destroy": (i32, [vp]),
+        "kpp_state_export": (i32, [vp, vp, P(ctypes.c_size_t)]),
+        "kpp_state_import": (i32, [vp, vp, ctypes.c_size_t]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -173,7 +175,8 @@ _lib = _load()
 EXPORTED = ("kpp_abi_version", "kpp_last_error", "kpp_params_default", "kpp_context_create",
             "kpp_context_destroy", "kpp_system_create", "kpp_system_destroy", "kpp_solve",
             "kpp_schedule_generate", "kpp_block_factor", "kpp_residual_norm", "kpp_request_footprint", "kpp_server_create",
-            "kpp_server_submit", "kpp_server_poll", "kpp_server_stats", "kpp_server_destroy")
+            "kpp_server_submit", "kpp_server_poll", "kpp_server_stats", "kpp_server_destroy",
+            "kpp_state_export", "kpp_state_import")
 
 
 def _check(status):
@@ -251,6 +254,20 @@ def kpp_set_schedule(params: kpp_params, step_block, block_rows):
     params.block_rows = ctypes.cast(table, ctypes.c_void_p).value
     params.block_rows_count = len(block_rows)
     return steps, table
+
+
+def kpp_state_export(sys_: int) -> bytes:
+    """The system's resumable solver state (see kpp.h) as bytes."""
+    size = ctypes.c_size_t(0)
+    _check(_lib.kpp_state_export(ctypes.c_void_p(sys_), None, ctypes.byref(size)))
+    buf = (ctypes.c_uint8 * max(size.value, 1))()
+    _check(_lib.kpp_state_export(ctypes.c_void_p(sys_), ctypes.cast(buf, ctypes.c_void_p), ctypes.byref(size)))
+    return bytes(buf[:size.value])
+
+
+def kpp_state_import(sys_: int, state: bytes) -> None:
+    buf = (ctypes.c_uint8 * max(len(state), 1)).from_buffer_copy(state if state else b"\0")
+    _check(_lib.kpp_state_import(ctypes.c_void_p(sys_), ctypes.cast(buf, ctypes.c_void_p), len(state)))
 
 
 def kpp_block_factor(sys_: int, s: int, lam: float, rows, lens, L_dev: int) -> None:

@@ -107,6 +107,14 @@ struct kpp_system {
   bool memo_valid = false;
   int32_t sig_s = 0, sig_memo = 0, sig_nb = 0, sig_part = 0, sig_prec = 0;
   bool sig_explicit = false;
+  // resumable state of the last FP64 kpp_solve, or of kpp_state_import: step
+  // counter and checkpoint statistics, the schedule generator, and (on the
+  // device, in mom) the momentum
+  bool res_valid = false;
+  int32_t res_s = 0;
+  int64_t res_t = 0;
+  kpp::DevState res_ds{};
+  std::unique_ptr<kpp::BlockSchedule> res_sch;
   uint64_t sig_seed = 0;
   double sig_lambda = 0.0;
   // per-window staging (pinned host mirror + device copy): block rows, lengths,
@@ -300,6 +308,7 @@ kpp_status check_params(const kpp_system* sys, const kpp_params* p) {
     return fail(KPP_ERR_INVALID_ARG, "the fused engine takes block_size <= %d", kpp::kFusedMaxBlock);
   if (p->team_groups < 0 || p->team_groups > kpp::kFusedMaxGroups)
     return fail(KPP_ERR_INVALID_ARG, "team_groups must be in [0, %d]", kpp::kFusedMaxGroups);
+  if (p->resume && p->precision != KPP_FP64) return fail(KPP_ERR_INVALID_ARG, "resume runs in FP64 only");
   if (p->schedule) {
     if (p->schedule_len < 0) return fail(KPP_ERR_INVALID_ARG, "schedule_len must be >= 0");
     if (!p->block_rows || p->block_rows_count < 1)
@@ -372,7 +381,9 @@ struct CoreOpts {
   int32_t confirm = 1;      // confirm a candidate stop with ||A x - b|| (FP64 system only)
   double rho0 = 0.0;
   int32_t keep_memo = 0;
-  int64_t max_iters = 0;
+  int64_t max_iters = 0;       // steps in this run (after the resumed ones)
+  bool resume = false;         // continue the system's saved state
+  bool keep_state = false;     // save this run's state on the system at its end
   // end the run when the window residual estimate E1 has not fallen below
   // kStallRatio times its value kStallWindows window ends earlier (an inner
   // low-precision solve at its precision floor); 0 = never
@@ -461,6 +472,17 @@ class CoreRun {
     } catch (const std::exception& e) {
       return fail(KPP_ERR_INVALID_ARG, "%s", e.what());
     }
+    if (o.resume) {
+      if (!sys->res_valid || !sys->res_sch || sys->res_s != s_)
+        return fail(KPP_ERR_INVALID_ARG, "no saved state of a solve with block size %d to resume", s_);
+      sch_ = std::move(sys->res_sch);
+      sys->res_valid = false;
+      mode_ = sch_->mode();
+      t_ = t_start_ = sys->res_t;
+      max_iters_ = t_ + o.max_iters;
+      if (sch_->is_explicit()) max_iters_ = std::min(max_iters_, sch_->length());
+      hs_ = sys->res_ds;
+    }
     if (force_cpl > 0) {
       fused_ = fused_cpl_fits(s_, fp32_, force_cpl);
       cpl_ = force_cpl;
@@ -491,7 +513,7 @@ class CoreRun {
       KPP_TRY(ensure_stage(sys, 0, stage));
       KPP_TRY(ensure_stage(sys, 1, stage));
     }
-    const bool same_sig = sys->memo_valid && o.keep_memo && sys->sig_s == s_ && sys->sig_memo == p->memo &&
+    const bool same_sig = sys->memo_valid && (o.keep_memo || o.resume) && sys->sig_s == s_ && sys->sig_memo == p->memo &&
                           sys->sig_nb == p->num_blocks && sys->sig_part == p->fixed_partition &&
                           sys->sig_seed == p->seed && sys->sig_lambda == p->lambda &&
                           sys->sig_prec == (fp32_ ? 1 : 0) && mode_ != kpp::MemoMode::Off &&
@@ -516,10 +538,19 @@ class CoreRun {
       KPP_TRY(dev_alloc(&sys->rpart, static_cast<size_t>(s_) * P_));
       sys->rpart_cap = static_cast<int64_t>(s_) * P_;
     }
-    HIP_TRY(hipMemsetAsync(sys->mom, 0, n_ * sizeof(double), st_));
     HIP_TRY(hipMemsetAsync(sys->err, 0, sizeof(int32_t), st_));
     const double thr = o.tol * o.tol * src.bnorm * src.bnorm;
-    kpp::launch_state_init(sys->ds, o.rho0, thr, st_);
+    if (o.resume) {
+      // the momentum is still (or was imported) on the device
+      kpp::DevState d = hs_;
+      d.thr = thr;
+      *sys->h_ds = d;
+      HIP_TRY(hipMemcpyAsync(sys->ds, sys->h_ds, sizeof(kpp::DevState), hipMemcpyHostToDevice, st_));
+      HIP_TRY(hipStreamSynchronize(st_));
+    } else {
+      HIP_TRY(hipMemsetAsync(sys->mom, 0, n_ * sizeof(double), st_));
+      kpp::launch_state_init(sys->ds, o.rho0, thr, st_);
+    }
     HIP_TRY(hipGetLastError());
     const char* prof_env = std::getenv("KPP_PHASE_PROFILE");
     phase_prof_ = fused_ && prof_env && prof_env[0] == '1';
@@ -531,14 +562,24 @@ class CoreRun {
     HIP_TRY(hipEventRecord(sys->ev_fact[1][2], st_));
     HIP_TRY(hipStreamWaitEvent(side_, sys->ev_fact[1][2], 0));
     begun_ = true;
-    if (max_iters_ <= 0) {
+    if (max_iters_ <= t_) {
       finished_ = true;
       return KPP_OK;
     }
-    KPP_TRY(plan(win_[0], 0, 0));
+    KPP_TRY(plan(win_[0], t_, 0));
     KPP_TRY(enqueue_factor(win_[0], side_));
     win_[0].on_side = true;
     return KPP_OK;
+  }
+
+  // Leave this run's state on the system for a later resume (after end()).
+  void keep_state() {
+    if (!sch_) return;
+    sys_->res_valid = true;
+    sys_->res_s = s_;
+    sys_->res_t = t_;
+    sys_->res_ds = hs_;
+    sys_->res_sch = std::move(sch_);
   }
 
   bool finished() const { return finished_; }
@@ -747,7 +788,7 @@ class CoreRun {
                      1e3 * static_cast<double>(ticks[ph]) / rate_khz / static_cast<double>(t_));
       std::fprintf(stderr, "\n");
     }
-    cs->iters = t_;
+    cs->iters = t_ - t_start_;
     cs->hits = hits_;
     cs->misses = misses_;
     cs->launches = launches_;
@@ -919,7 +960,7 @@ class CoreRun {
   Window win_[2];
   int cur_ = 0;
   bool have_next_ = false;
-  int64_t t_ = 0, hits_ = 0, misses_ = 0, launches_ = 0;
+  int64_t t_ = 0, t_start_ = 0, hits_ = 0, misses_ = 0, launches_ = 0;
   bool converged_ = false, finished_ = false, stalled_ = false, planned_ = false, dual_ = false;
   double true_rel_ = NAN, t_factor_ = 0.0, t_kernel_ = 0.0;
   kpp::DevState hs_{};
@@ -951,7 +992,9 @@ kpp_status solve_core(kpp_system* sys, const kpp_params* p, const Source& src, c
     run.add_kernel_seconds(1e-3 * ms);
     KPP_TRY(run.finish());
   }
-  return run.end(cs);
+  KPP_TRY(run.end(cs));
+  if (o.keep_state) run.keep_state();
+  return KPP_OK;
 }
 
 
@@ -1001,6 +1044,9 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
   o.rho0 = p->rho0;
   o.keep_memo = p->keep_memo;
   o.max_iters = p->max_iters;
+  o.resume = p->resume != 0;
+  o.keep_state = true;
+  if (!o.resume) sys->res_valid = false;
   CoreStats cs;
   KPP_TRY(solve_core(sys, p, src, o, x, &cs));
   double true_rel = cs.true_rel;
@@ -1023,6 +1069,7 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
 // factors, FP64 momentum and iterate) run to the relative tolerance inner_tol.
 // The memo cache of block factors carries over from round to round.
 kpp_status solve_mixed(kpp_system* sys, const kpp_params* p, double* x, kpp_result* res) {
+  sys->res_valid = false;   // the inner runs reuse the momentum buffer
   using clock = std::chrono::steady_clock;
   const auto t0 = clock::now();
   hipStream_t st = sys->ctx->stream;
@@ -1820,6 +1867,86 @@ KPP_API kpp_status kpp_solve(kpp_system* sys, const kpp_params* p, double* x_dev
   }
 }
 
+namespace {
+constexpr uint32_t kStateMagic = 0x4b505358u;   // "KPSX"
+constexpr uint32_t kStateVersion = 1;
+struct StateHeader {
+  uint32_t magic, version;
+  int32_t kind, s;
+  int64_t m, n, t;
+  uint64_t sched_bytes;
+};
+}  // namespace
+
+KPP_API kpp_status kpp_state_export(const kpp_system* sys, void* host_buf, size_t* bytes) {
+  if (!sys || !bytes) return fail(KPP_ERR_INVALID_ARG, "NULL argument");
+  if (!sys->res_valid || !sys->res_sch) return fail(KPP_ERR_INVALID_ARG, "the system holds no solver state");
+  std::vector<uint8_t> sched;
+  try {
+    sys->res_sch->save(&sched);
+  } catch (const std::bad_alloc&) {
+    return fail(KPP_ERR_OOM, "host allocation failed");
+  }
+  const size_t need = sizeof(StateHeader) + sizeof(kpp::DevState) + static_cast<size_t>(sys->n) * sizeof(double) +
+                      sched.size();
+  if (!host_buf) {
+    *bytes = need;
+    return KPP_OK;
+  }
+  if (*bytes < need) return fail(KPP_ERR_INVALID_ARG, "buffer of %zu bytes, %zu needed", *bytes, need);
+  HIP_TRY(hipSetDevice(sys->ctx->device));
+  StateHeader h{kStateMagic, kStateVersion, sys->kind, sys->res_s, sys->m, sys->n, sys->res_t, sched.size()};
+  uint8_t* out = static_cast<uint8_t*>(host_buf);
+  std::memcpy(out, &h, sizeof h);
+  std::memcpy(out + sizeof h, &sys->res_ds, sizeof(kpp::DevState));
+  double* mom = reinterpret_cast<double*>(out + sizeof h + sizeof(kpp::DevState));
+  HIP_TRY(hipStreamSynchronize(sys->ctx->stream));
+  HIP_TRY(hipMemcpy(mom, sys->mom, static_cast<size_t>(sys->n) * sizeof(double), hipMemcpyDeviceToHost));
+  std::memcpy(out + sizeof h + sizeof(kpp::DevState) + static_cast<size_t>(sys->n) * sizeof(double), sched.data(),
+              sched.size());
+  *bytes = need;
+  return KPP_OK;
+}
+
+KPP_API kpp_status kpp_state_import(kpp_system* sys, const void* host_buf, size_t bytes) {
+  if (!sys || !host_buf) return fail(KPP_ERR_INVALID_ARG, "NULL argument");
+  StateHeader h;
+  if (bytes < sizeof h) return fail(KPP_ERR_INVALID_ARG, "state buffer too short");
+  const uint8_t* in = static_cast<const uint8_t*>(host_buf);
+  std::memcpy(&h, in, sizeof h);
+  if (h.magic != kStateMagic || h.version != kStateVersion) return fail(KPP_ERR_INVALID_ARG, "not a solver state");
+  if (h.kind != sys->kind || h.m != sys->m || h.n != sys->n)
+    return fail(KPP_ERR_SHAPE, "the state belongs to a %lld x %lld system of kind %d", static_cast<long long>(h.m),
+                static_cast<long long>(h.n), h.kind);
+  const size_t need = sizeof h + sizeof(kpp::DevState) + static_cast<size_t>(sys->n) * sizeof(double) + h.sched_bytes;
+  if (bytes != need) return fail(KPP_ERR_INVALID_ARG, "state buffer of %zu bytes, %zu expected", bytes, need);
+  kpp::DevState ds;
+  std::memcpy(&ds, in + sizeof h, sizeof ds);
+  std::unique_ptr<kpp::BlockSchedule> sch;
+  try {
+    sch.reset(new kpp::BlockSchedule(kpp::BlockSchedule::load(
+        in + sizeof h + sizeof(kpp::DevState) + static_cast<size_t>(sys->n) * sizeof(double), h.sched_bytes)));
+  } catch (const std::exception& e) {
+    return fail(KPP_ERR_INVALID_ARG, "%s", e.what());
+  }
+  const int64_t rows = sys->kind == KPP_CD_PSD ? sys->n : sys->m;
+  if (sch->block_size() != h.s || h.t < 0 || ds.t != h.t)
+    return fail(KPP_ERR_INVALID_ARG, "inconsistent solver state");
+  for (int32_t b = 0; b < sch->num_blocks(); ++b)
+    if (sch->rows(b)[sch->len(b) - 1] >= rows) return fail(KPP_ERR_INVALID_ARG, "inconsistent solver state");
+  HIP_TRY(hipSetDevice(sys->ctx->device));
+  HIP_TRY(hipStreamSynchronize(sys->ctx->stream));
+  HIP_TRY(hipMemcpy(sys->mom, in + sizeof h + sizeof(kpp::DevState), static_cast<size_t>(sys->n) * sizeof(double),
+                    hipMemcpyHostToDevice));
+  sys->res_ds = ds;
+  sys->res_t = h.t;
+  sys->res_s = h.s;
+  sys->res_sch = std::move(sch);
+  sys->res_valid = true;
+  sys->memo_valid = false;   // factors are formed again on first use
+  return KPP_OK;
+}
+
 KPP_API kpp_status kpp_schedule_generate(int32_t kind, int64_t m, int64_t n, const kpp_params* p,
                                          int64_t T, int32_t* step_block_host,
                                          int32_t* block_rows_host, int32_t* block_len_host,
@@ -1970,6 +2097,8 @@ KPP_API kpp_status kpp_server_submit(kpp_server* srv, kpp_system* sys, const kpp
   KPP_TRY(check_params(sys, p));
   if (p->engine == 1) return fail(KPP_ERR_INVALID_ARG, "the server runs the fused engine only");
   if (p->schedule) return fail(KPP_ERR_INVALID_ARG, "explicit schedules are for kpp_solve");
+  if (p->resume) return fail(KPP_ERR_INVALID_ARG, "resume is for kpp_solve");
+  sys->res_valid = false;
   auto* r = new (std::nothrow) ServeReq;
   if (!r) return fail(KPP_ERR_OOM, "host allocation failed");
   r->sys = sys;

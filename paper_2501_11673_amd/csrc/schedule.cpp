@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <numeric>
 #include <stdexcept>
 
@@ -130,6 +131,101 @@ int32_t BlockSchedule::next(bool* is_new) {
   ++t_;
   if (is_new) *is_new = fresh;
   return b;
+}
+
+namespace {
+template <typename T>
+void put(std::vector<uint8_t>* out, const T& v) {
+  const uint8_t* p = reinterpret_cast<const uint8_t*>(&v);
+  out->insert(out->end(), p, p + sizeof(T));
+}
+template <typename T>
+void put_vec(std::vector<uint8_t>* out, const std::vector<T>& v) {
+  put<uint64_t>(out, v.size());
+  if (v.empty()) return;
+  const uint8_t* p = reinterpret_cast<const uint8_t*>(v.data());
+  out->insert(out->end(), p, p + v.size() * sizeof(T));
+}
+struct Reader {
+  const uint8_t* p;
+  size_t left;
+  template <typename T>
+  T get() {
+    if (left < sizeof(T)) throw std::invalid_argument("schedule state is truncated");
+    T v;
+    std::memcpy(&v, p, sizeof(T));
+    p += sizeof(T);
+    left -= sizeof(T);
+    return v;
+  }
+  template <typename T>
+  std::vector<T> get_vec(uint64_t max_len) {
+    const uint64_t len = get<uint64_t>();
+    if (len > max_len || len * sizeof(T) > left) throw std::invalid_argument("schedule state is malformed");
+    std::vector<T> v(len);
+    if (len > 0) std::memcpy(v.data(), p, len * sizeof(T));
+    p += len * sizeof(T);
+    left -= len * sizeof(T);
+    return v;
+  }
+};
+constexpr uint32_t kScheduleStateTag = 0x4b505353u;   // "KPSS"
+}  // namespace
+
+void BlockSchedule::save(std::vector<uint8_t>* out) const {
+  put<uint32_t>(out, kScheduleStateTag);
+  put<int32_t>(out, static_cast<int32_t>(mode_));
+  put<int64_t>(out, N_);
+  put<int32_t>(out, s_);
+  put<double>(out, B0_);
+  put<uint64_t>(out, g_.state());
+  put<int64_t>(out, t_);
+  put<uint8_t>(out, explicit_ ? 1 : 0);
+  put_vec(out, rows_);
+  put_vec(out, len_);
+  put_vec(out, used_);
+  put_vec(out, seq_);
+}
+
+BlockSchedule BlockSchedule::load(const uint8_t* data, size_t bytes) {
+  Reader r{data, bytes};
+  if (r.get<uint32_t>() != kScheduleStateTag) throw std::invalid_argument("not a schedule state");
+  const int32_t mode = r.get<int32_t>();
+  const int64_t N = r.get<int64_t>();
+  const int32_t s = r.get<int32_t>();
+  const double B0 = r.get<double>();
+  const uint64_t state = r.get<uint64_t>();
+  const int64_t t = r.get<int64_t>();
+  const bool expl = r.get<uint8_t>() != 0;
+  if (mode < 0 || mode > 2 || s < 1 || N < s || t < 0) throw std::invalid_argument("schedule state is malformed");
+  const uint64_t cap = uint64_t{1} << 40;
+  std::vector<int32_t> rows = r.get_vec<int32_t>(cap);
+  std::vector<int32_t> len = r.get_vec<int32_t>(cap);
+  std::vector<uint8_t> used = r.get_vec<uint8_t>(cap);
+  std::vector<int32_t> seq = r.get_vec<int32_t>(cap);
+  if (rows.size() != len.size() * static_cast<size_t>(s) || (!used.empty() && used.size() != len.size()))
+    throw std::invalid_argument("schedule state is malformed");
+  for (size_t b = 0; b < len.size(); ++b) {
+    if (len[b] < 1 || len[b] > s) throw std::invalid_argument("schedule state is malformed");
+    for (int32_t j = 0; j < len[b]; ++j) {
+      const int32_t v = rows[b * s + j];
+      if (v < 0 || v >= N) throw std::invalid_argument("schedule state is malformed");
+    }
+  }
+  for (int32_t b : seq)
+    if (b < 0 || static_cast<size_t>(b) >= len.size()) throw std::invalid_argument("schedule state is malformed");
+  if (expl && t > static_cast<int64_t>(seq.size())) throw std::invalid_argument("schedule state is malformed");
+  // a generator of the right shape, then the saved state in place of its draws
+  BlockSchedule out(MemoMode::Online, N, s, 0, B0, 0, true);
+  out.mode_ = static_cast<MemoMode>(mode);
+  out.g_ = SplitMix64(state);
+  out.t_ = t;
+  out.explicit_ = expl;
+  out.rows_ = std::move(rows);
+  out.len_ = std::move(len);
+  out.used_ = std::move(used);
+  out.seq_ = std::move(seq);
+  return out;
 }
 
 }  // namespace kpp

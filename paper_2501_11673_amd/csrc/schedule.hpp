@@ -25,6 +25,7 @@
 //           block is factored on first use and kept, as in FIXED.
 #pragma once
 
+#include <cstddef>
 #include <cstdint>
 #include <vector>
 
@@ -33,6 +34,7 @@ namespace kpp {
 class SplitMix64 {
  public:
   explicit SplitMix64(uint64_t seed) : state_(seed) {}
+  uint64_t state() const { return state_; }
   uint64_t next() {
     state_ += 0x9E3779B97F4A7C15ull;
     uint64_t z = state_;
@@ -74,6 +76,11 @@ class BlockSchedule {
   MemoMode mode() const { return mode_; }
   bool is_explicit() const { return explicit_; }
   int64_t length() const { return static_cast<int64_t>(seq_.size()); }
+
+  // The generator's whole state (draws made, collection, step count) as
+  // bytes, and a generator that continues exactly where the saved one stopped.
+  void save(std::vector<uint8_t>* out) const;
+  static BlockSchedule load(const uint8_t* data, size_t bytes);  // throws std::invalid_argument
 
  private:
   void add_subset();

@@ -33,6 +33,35 @@ static void solve_case(const char* name, int kind, int64_t m, int64_t n, int s, 
   hipFree(A); hipFree(b); hipFree(x);
 }
 
+// A solve cut in two: the state of the first part moves to a fresh system
+// through export/import and the second part resumes there.
+static void resume_case(int kind, int64_t m, int64_t n, int s) {
+  kpp_context* ctx; CHECK(kpp_context_create(0, nullptr, &ctx));
+  double* A = dev_vec(m * n, 0.5); double* b = dev_vec(m, 1.0); double* x = dev_vec(n, 0.0);
+  kpp_system* sys; CHECK(kpp_system_create(ctx, kind, m, n, A, n, b, &sys));
+  size_t bytes = 0;
+  if (kpp_state_export(sys, nullptr, &bytes) >= 0) { std::printf("FAIL: export without state\n"); std::exit(1); }
+  kpp_params p; CHECK(kpp_params_default(&p, kind));
+  p.block_size = s; p.max_iters = 70; p.tol = 0.0; p.seed = 5;
+  kpp_result r; CHECK(kpp_solve(sys, &p, x, &r));
+  CHECK(kpp_state_export(sys, nullptr, &bytes));
+  std::vector<unsigned char> buf(bytes);
+  CHECK(kpp_state_export(sys, buf.data(), &bytes));
+  kpp_system* sys2; CHECK(kpp_system_create(ctx, kind, m, n, A, n, b, &sys2));
+  CHECK(kpp_state_import(sys2, buf.data(), bytes));
+  p.resume = 1; p.max_iters = 45;
+  CHECK(kpp_solve(sys2, &p, x, &r));
+  if (r.iters != 45) { std::printf("FAIL: resumed %lld steps\n", (long long)r.iters); std::exit(1); }
+  // wrong shape and truncated buffers are refused
+  kpp_system* sys3; CHECK(kpp_system_create(ctx, kind, m - 1, n - 1, A, n, b, &sys3));
+  if (kpp_state_import(sys3, buf.data(), bytes) >= 0) { std::printf("FAIL: import into another shape\n"); std::exit(1); }
+  if (kpp_state_import(sys2, buf.data(), bytes - 1) >= 0) { std::printf("FAIL: truncated import\n"); std::exit(1); }
+  std::printf("resume kind=%d: 70 + %lld steps\n", kind, (long long)r.iters);
+  CHECK(kpp_system_destroy(sys3)); CHECK(kpp_system_destroy(sys2)); CHECK(kpp_system_destroy(sys));
+  CHECK(kpp_context_destroy(ctx));
+  hipFree(A); hipFree(b); hipFree(x);
+}
+
 static void serve_case() {
   kpp_context* ctx; CHECK(kpp_context_create(0, nullptr, &ctx));
   struct J { int kind; int64_t m, n; int s; int prec; double tol; };
@@ -87,6 +116,8 @@ int main(int argc, char** argv) {
     }
     solve_case("mixed_c3_small", 0, 6000, 700, 256, 2, 1, 0, 0, 1, 20000, 1e-10);
     solve_case("mixed_psd", 1, 1000, 1000, 128, 1, 1, 0, 0, 1, 20000, 1e-10);
+    resume_case(1, 600, 600, 64);
+    resume_case(0, 900, 300, 40);
   }
   if (!*only || !std::strcmp(only, "serve")) serve_case();
   std::printf("EMU OK\n");

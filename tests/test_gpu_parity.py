@@ -313,6 +313,91 @@ def test_explicit_schedule_matches_oracle(env, engine):
     assert relerr(x, ref.x) <= 1e-10
 
 
+def _resume_params(kpp, kind, s, lam, steps, resume):
+    p = kpp.kpp_params_default(kind)
+    p.block_size = s
+    p.lambda_ = lam
+    p.tol = 0.0
+    p.seed = 77
+    p.max_iters = steps
+    p.memo = MODES["online"]
+    p.num_blocks = 0
+    p.fixed_partition = 1
+    p.accel = 1
+    p.adaptive_rho = 1
+    p.resume = 1 if resume else 0
+    return p
+
+
+@pytest.mark.parametrize("via", ["export_import", "same_system"])
+def test_resumed_cdpp_solve_equals_uninterrupted(env, via):
+    """A CD++ solve cut after 170 steps (mid-window) and continued for 230 --
+    on the same system, or on a fresh one through kpp_state_export/import --
+    gives the iterate of one 400-step solve bit for bit."""
+    kpp, torch, dev, ctx = env
+    sysm = synth.config("c2_small")
+    A = torch.from_numpy(np.ascontiguousarray(sysm.A)).to(dev)
+    b = torch.from_numpy(np.ascontiguousarray(sysm.b)).to(dev)
+    n = A.shape[0]
+    ck = kpp.KPP_CD_PSD
+
+    def new_system():
+        return kpp.kpp_system_create(ctx, ck, n, n, A.data_ptr(), n, b.data_ptr())
+
+    h = new_system()
+    x_full = torch.zeros(n, dtype=torch.float64, device=dev)
+    st, full = kpp.kpp_solve(h, _resume_params(kpp, ck, 128, 1e-8, 400, False), x_full.data_ptr())
+    kpp.kpp_system_destroy(h)
+    h = new_system()
+    h2 = None
+    try:
+        x = torch.zeros(n, dtype=torch.float64, device=dev)
+        kpp.kpp_solve(h, _resume_params(kpp, ck, 128, 1e-8, 170, False), x.data_ptr())
+        target = h
+        if via == "export_import":
+            state = kpp.kpp_state_export(h)
+            h2 = new_system()
+            kpp.kpp_state_import(h2, state)
+            target = h2
+        st, part = kpp.kpp_solve(target, _resume_params(kpp, ck, 128, 1e-8, 230, True), x.data_ptr())
+        assert part.iters == 230 and full.iters == 400
+        assert torch.equal(x, x_full), float(torch.max(torch.abs(x - x_full)))
+        assert part.rho_final == full.rho_final
+        with pytest.raises(kpp.KppError):   # the saved state is of a solve with blocks of 128
+            kpp.kpp_solve(target, _resume_params(kpp, ck, 64, 1e-8, 10, True), x.data_ptr())
+    finally:
+        kpp.kpp_system_destroy(h)
+        if h2 is not None:
+            kpp.kpp_system_destroy(h2)
+
+
+def test_resumed_kaczmarz_solve_matches_oracle(env):
+    """Kaczmarz++ (1000 x 200, blocks of 20): 250 steps, export, import into a
+    fresh system, 350 more; the oracle runs 600 steps in one go (the resumed
+    run forms its Grams again in other batches: equal up to rounding)."""
+    kpp, torch, dev, ctx = env
+    sysm = synth.config("c1")
+    m, n = sysm.A.shape
+    A = torch.from_numpy(np.ascontiguousarray(sysm.A)).to(dev)
+    b = torch.from_numpy(np.ascontiguousarray(sysm.b)).to(dev)
+    ck = kpp.KPP_KACZMARZ
+    h = kpp.kpp_system_create(ctx, ck, m, n, A.data_ptr(), n, b.data_ptr())
+    h2 = kpp.kpp_system_create(ctx, ck, m, n, A.data_ptr(), n, b.data_ptr())
+    try:
+        x = torch.zeros(n, dtype=torch.float64, device=dev)
+        kpp.kpp_solve(h, _resume_params(kpp, ck, 20, 1e-3, 250, False), x.data_ptr())
+        kpp.kpp_state_import(h2, kpp.kpp_state_export(h))
+        st, res = kpp.kpp_solve(h2, _resume_params(kpp, ck, 20, 1e-3, 350, True), x.data_ptr())
+    finally:
+        kpp.kpp_system_destroy(h)
+        kpp.kpp_system_destroy(h2)
+    kw = dict(lam=1e-3, T=600, seed=77)
+    ref = oracle_solve(sysm.A, sysm.b, "general", 20, **kw)
+    bound, nf, _ = parity_bound(sysm.A, sysm.b, "general", 20, ref, **kw)
+    assert res.iters == 350
+    assert relerr(x.cpu().numpy(), ref.x) <= bound, (relerr(x.cpu().numpy(), ref.x), nf)
+
+
 # ---------------------------------------------------------------------------
 # edge cases and error paths
 # ---------------------------------------------------------------------------
