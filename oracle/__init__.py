@@ -10,7 +10,9 @@ Contents
   schedule : block schedule (SplitMix64 draws; Section 5.2, Algorithms 1, 2, 5)
   kpp      : block residual, regularized Gram, Cholesky projection, momentum
              update, adaptive rho, the solver loop, FP64 iterative refinement
+  rht      : randomized Hadamard preprocessing (Definition d:rht; FHT,
+             Algorithm 4; SymFHT, Algorithm 3) and the solvers with it
 """
-from . import schedule, kpp  # noqa: F401
+from . import schedule, kpp, rht  # noqa: F401
 from .kpp import Params, Result, solve  # noqa: F401
 from .schedule import Schedule, SplitMix64, make_schedule, online_rate  # noqa: F401
