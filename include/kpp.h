@@ -45,7 +45,7 @@ extern "C" {
 #endif
 
 #define KPP_API __attribute__((visibility("default")))
-#define KPP_ABI_VERSION 1
+#define KPP_ABI_VERSION 2
 
 typedef enum kpp_status {
   KPP_OK = 0,
@@ -124,6 +124,19 @@ typedef struct kpp_params {
    * a fresh schedule: x_dev must hold the iterate that solve returned, and
    * max_iters counts the further steps.  FP64 and kpp_solve only. */
   int32_t resume;
+  /* 1: randomized Hadamard preprocessing (Definition d:rht; the RHT lines of
+   * Algorithms 2 and 5).  Signs d_i from SplitMix64(rht_seed) (kpp_rht_signs),
+   * rows padded with zeros to R = the next power of two of the row count.
+   * Kaczmarz++ runs on (H D A) x = H D b, CD++ on (H D A D H) xbar = H D b with
+   * xbar0 = H D x0 and x = D H xbar.  The transformed system is formed on the
+   * device on the first such solve and kept with the system (an R x n or
+   * R x R FP64 copy) until a solve asks for another rht_seed; memo, resume
+   * state and an explicit schedule (rows 0..R-1) then belong to it.
+   * true_rel_res is recomputed on the original system.  R <= 2^24.  resume
+   * and kpp_server_submit reject rht = 1 (KPP_ERR_INVALID_ARG). */
+  int32_t rht;
+  int32_t reserved2;
+  uint64_t rht_seed;
 } kpp_params;
 
 /* Per-solve report. */
@@ -214,6 +227,44 @@ KPP_API kpp_status kpp_solve(kpp_system* sys, const kpp_params* p, double* x_dev
  * the caller keeps the iterate it passed to kpp_solve. */
 KPP_API kpp_status kpp_state_export(const kpp_system* sys, void* host_buf, size_t* bytes);
 KPP_API kpp_status kpp_state_import(kpp_system* sys, const void* host_buf, size_t bytes);
+
+/* Randomized Hadamard preprocessing (Definition d:rht; Algorithm 4, FHT;
+ * Algorithm 3 and Section 5.3, the symmetric transform).  H is the Sylvester
+ * Hadamard matrix (H_1 = 1, H_2k = [[H_k, H_k], [H_k, -H_k]]); R is a power of
+ * two; D = diag(signs) / sqrt(R).  Inputs are zero-padded to R.  All matrix and
+ * vector pointers are device memory owned by the caller, row-major FP64;
+ * signs is a device array of R int8 values +1 / -1.  The calls enqueue on the
+ * context's stream and return without waiting.  Outputs must not overlap
+ * inputs.  KPP_ERR_SHAPE: R not a power of two, R below the row count, or
+ * R > 2^24; KPP_ERR_INVALID_ARG: a NULL pointer or a leading dimension too
+ * small. */
+
+/* N signs: signs_host[i] = +1 when the top bit of the i-th SplitMix64(seed)
+ * output is 0, else -1 (host memory, caller-owned).  These are the signs
+ * kpp_solve uses with params.rht = 1 and params.rht_seed = seed. */
+KPP_API kpp_status kpp_rht_signs(uint64_t seed, int64_t N, int8_t* signs_host);
+
+/* Kaczmarz++ (Algorithm 5): At (R x n, leading dimension ldt >= n) = H D A
+ * and bt (R) = H D b, with A (m x n, lda >= n) and b (m) padded to R >= m rows. */
+KPP_API kpp_status kpp_rht_general(kpp_context* ctx, int64_t m, int64_t n, const double* A, int64_t lda,
+                                   const double* b, const int8_t* signs, int64_t R, double* At,
+                                   int64_t ldt, double* bt);
+
+/* CD++ (Algorithm 2): At (R x R, ldt >= R) = H D A D H and bt (R) = H D b, with
+ * A (n x n symmetric, lda >= n) padded to R x R and b to R entries.  The
+ * transform runs as H (H D A D)^T, two passes over At.  work: R x R doubles of
+ * scratch when R > 4096 (may be NULL otherwise). */
+KPP_API kpp_status kpp_rht_psd(kpp_context* ctx, int64_t n, const double* A, int64_t lda, const double* b,
+                               const int8_t* signs, int64_t R, double* At, int64_t ldt, double* bt,
+                               double* work);
+
+/* Vector transforms of Algorithm 2.  direction 0: y (R entries) = H D [x; 0]
+ * for x of nx <= R entries (the transformed start xbar0).  direction 1:
+ * y (nx entries) = the first nx entries of D H x for x of R entries (the
+ * returned x = D FHT(xbar)).  work: R doubles of scratch when R > 4096 and
+ * direction 1 with nx < R (may be NULL otherwise). */
+KPP_API kpp_status kpp_rht_vector(kpp_context* ctx, int64_t R, const int8_t* signs, const double* x,
+                                  int64_t nx, double* y, int32_t direction, double* work);
 
 /* The block schedule kpp_solve uses for these settings, on the host (Section
  * 5.2; Algorithms 1, 2, 5).  rows = m (Kaczmarz++) or n (CD++).  Writes the

@@ -69,6 +69,9 @@ class kpp_params(ctypes.Structure):
         ("block_rows", ctypes.c_void_p),
         ("block_rows_count", ctypes.c_int32),
         ("resume", ctypes.c_int32),
+        ("rht", ctypes.c_int32),
+        ("reserved2", ctypes.c_int32),
+        ("rht_seed", ctypes.c_uint64),
     ]
 
 
@@ -163,6 +166,10 @@ def _load():
         "kpp_server_destroy": (i32, [vp]),
         "kpp_state_export": (i32, [vp, vp, P(ctypes.c_size_t)]),
         "kpp_state_import": (i32, [vp, vp, ctypes.c_size_t]),
+        "kpp_rht_signs": (i32, [ctypes.c_uint64, i64, P(ctypes.c_int8)]),
+        "kpp_rht_general": (i32, [vp, i64, i64, vp, i64, vp, vp, i64, vp, i64, vp]),
+        "kpp_rht_psd": (i32, [vp, i64, vp, i64, vp, vp, i64, vp, i64, vp, vp]),
+        "kpp_rht_vector": (i32, [vp, i64, vp, vp, i64, vp, i32, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -176,7 +183,8 @@ EXPORTED = ("kpp_abi_version", "kpp_last_error", "kpp_params_default", "kpp_cont
             "kpp_context_destroy", "kpp_system_create", "kpp_system_destroy", "kpp_solve",
             "kpp_schedule_generate", "kpp_block_factor", "kpp_residual_norm", "kpp_request_footprint", "kpp_server_create",
             "kpp_server_submit", "kpp_server_poll", "kpp_server_stats", "kpp_server_destroy",
-            "kpp_state_export", "kpp_state_import")
+            "kpp_state_export", "kpp_state_import", "kpp_rht_signs", "kpp_rht_general", "kpp_rht_psd",
+            "kpp_rht_vector")
 
 
 def _check(status):
@@ -268,6 +276,34 @@ def kpp_state_export(sys_: int) -> bytes:
 def kpp_state_import(sys_: int, state: bytes) -> None:
     buf = (ctypes.c_uint8 * max(len(state), 1)).from_buffer_copy(state if state else b"\0")
     _check(_lib.kpp_state_import(ctypes.c_void_p(sys_), ctypes.cast(buf, ctypes.c_void_p), len(state)))
+
+
+def kpp_rht_signs(seed: int, N: int):
+    """N signs (+1 / -1, a list of ints) drawn as kpp_solve draws them for rht_seed = seed."""
+    out = (ctypes.c_int8 * max(N, 1))()
+    _check(_lib.kpp_rht_signs(ctypes.c_uint64(seed), N, out))
+    return list(out[:N])
+
+
+def kpp_rht_general(ctx: int, m: int, n: int, A_dev: int, lda: int, b_dev: int, signs_dev: int, R: int,
+                    At_dev: int, ldt: int, bt_dev: int) -> None:
+    vp = ctypes.c_void_p
+    _check(_lib.kpp_rht_general(vp(ctx), m, n, vp(A_dev), lda, vp(b_dev), vp(signs_dev), R, vp(At_dev), ldt,
+                                vp(bt_dev)))
+
+
+def kpp_rht_psd(ctx: int, n: int, A_dev: int, lda: int, b_dev: int, signs_dev: int, R: int, At_dev: int,
+                ldt: int, bt_dev: int, work_dev: int = 0) -> None:
+    vp = ctypes.c_void_p
+    _check(_lib.kpp_rht_psd(vp(ctx), n, vp(A_dev), lda, vp(b_dev), vp(signs_dev), R, vp(At_dev), ldt, vp(bt_dev),
+                            vp(work_dev or None)))
+
+
+def kpp_rht_vector(ctx: int, R: int, signs_dev: int, x_dev: int, nx: int, y_dev: int, direction: int,
+                   work_dev: int = 0) -> None:
+    vp = ctypes.c_void_p
+    _check(_lib.kpp_rht_vector(vp(ctx), R, vp(signs_dev), vp(x_dev), nx, vp(y_dev), direction,
+                               vp(work_dev or None)))
 
 
 def kpp_block_factor(sys_: int, s: int, lam: float, rows, lens, L_dev: int) -> None:

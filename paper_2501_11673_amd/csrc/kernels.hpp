@@ -200,4 +200,34 @@ void launch_fused(int32_t kind, bool a_fp32, const FusedArgs& a, int32_t cpl, in
 void launch_fused_multi(int32_t kind, bool a_fp32, const FusedArgs* args, const int32_t* team_start,
                         int32_t nteams, int32_t total_groups, int32_t cpl, hipStream_t st);
 
+// Randomized Hadamard transform (rht.hip): out = Do H_M Di X Dc along the row
+// index of a row-major X, where Di, Dc, Do are optional diagonals of signs
+// times a scale, X is zero-padded to M rows (rows >= rows_valid) and ncols
+// columns (columns >= cols_valid), and output rows >= rows_out are dropped.
+// transpose_out stores out[col * ld_out + row].  M is a power of two up to
+// kFhtMaxRows; M > 4096 takes two passes, whose intermediate lives in out when
+// the last pass can run in place there, otherwise in work (M x ncols).  in
+// must not overlap out unless the transform is a single in-place pass without
+// transpose.
+constexpr int kFhtMaxDigitLog = 12;
+constexpr int64_t kFhtMaxRows = int64_t{1} << (2 * kFhtMaxDigitLog);
+struct FhtSpec {
+  const double* in = nullptr;
+  int64_t ld_in = 0;
+  int64_t rows_valid = 0, cols_valid = 0;
+  const int8_t* isign = nullptr;
+  const int8_t* csign = nullptr;
+  double iscale = 1.0, cscale = 1.0;
+  double* out = nullptr;
+  int64_t ld_out = 0;
+  int64_t rows_out = 0;
+  const int8_t* osign = nullptr;
+  double oscale = 1.0;
+  int32_t transpose_out = 0;
+  int64_t M = 0, ncols = 0;
+  double* work = nullptr;
+};
+inline int fht_passes(int64_t M) { return M > (int64_t{1} << kFhtMaxDigitLog) ? 2 : 1; }
+void launch_fht(const FhtSpec& s, hipStream_t st);
+
 }  // namespace kpp

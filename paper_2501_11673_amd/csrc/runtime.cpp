@@ -140,13 +140,36 @@ struct kpp_system {
   double* zx = nullptr;    // mixed precision, wide Kaczmarz++: duals of the inner iterate and momentum
   double* zm = nullptr;
   int32_t* fp64_count = nullptr;   // blocks refactored in FP64 (mixed precision)
+  // randomized Hadamard preprocessing (params.rht): the transformed padded
+  // system (its own memo and resume state), the signs and the seed they came
+  // from; formed on the first such solve
+  kpp_system* rht_inner = nullptr;
+  int8_t* rht_signs = nullptr;
+  double* rht_A = nullptr;
+  double* rht_b = nullptr;
+  double* rht_x = nullptr;      // CD++: the transformed iterate
+  double* rht_work = nullptr;   // two-pass transforms (R > 4096)
+  int64_t rht_R = 0;
+  uint64_t rht_seed = 0;
 };
 
 namespace {
 
 constexpr int kFlagWords = kpp::kFlagWordsAlloc;
 
+void drop_rht(kpp_system* s) {
+  if (s->rht_inner) (void)kpp_system_destroy(s->rht_inner);
+  s->rht_inner = nullptr;
+  dev_free(s->rht_signs);
+  dev_free(s->rht_A);
+  dev_free(s->rht_b);
+  dev_free(s->rht_x);
+  dev_free(s->rht_work);
+  s->rht_R = 0;
+}
+
 void destroy_buffers(kpp_system* s) {
+  drop_rht(s);
   dev_free(s->mom);
   dev_free(s->ds);
   dev_free(s->rpart);
@@ -309,6 +332,8 @@ kpp_status check_params(const kpp_system* sys, const kpp_params* p) {
   if (p->team_groups < 0 || p->team_groups > kpp::kFusedMaxGroups)
     return fail(KPP_ERR_INVALID_ARG, "team_groups must be in [0, %d]", kpp::kFusedMaxGroups);
   if (p->resume && p->precision != KPP_FP64) return fail(KPP_ERR_INVALID_ARG, "resume runs in FP64 only");
+  if (p->rht != 0 && p->rht != 1) return fail(KPP_ERR_INVALID_ARG, "rht must be 0 or 1");
+  if (p->rht && p->resume) return fail(KPP_ERR_INVALID_ARG, "resume does not combine with rht");
   if (p->schedule) {
     if (p->schedule_len < 0) return fail(KPP_ERR_INVALID_ARG, "schedule_len must be >= 0");
     if (!p->block_rows || p->block_rows_count < 1)
@@ -1710,6 +1735,221 @@ void serve_loop(kpp_server* srv) {
 
 extern "C" {
 
+// ---------------------------------------------------------------------------
+// randomized Hadamard preprocessing (Definition d:rht; Algorithms 2 to 5)
+// ---------------------------------------------------------------------------
+namespace {
+
+bool is_pow2(int64_t v) { return v >= 1 && (v & (v - 1)) == 0; }
+int64_t next_pow2(int64_t v) {
+  int64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+kpp_status check_rht_size(int64_t rows, int64_t R) {
+  if (!is_pow2(R) || R < rows || R > kpp::kFhtMaxRows)
+    return fail(KPP_ERR_SHAPE, "R=%lld must be a power of two in [%lld, %lld]", static_cast<long long>(R),
+                static_cast<long long>(rows), static_cast<long long>(kpp::kFhtMaxRows));
+  return KPP_OK;
+}
+
+// H D [x; 0] (forward) or the first nx entries of D H x (back), D = diag(d)/sqrt(R)
+kpp_status rht_vector(hipStream_t st, int64_t R, const int8_t* signs, const double* x, int64_t nx, double* y,
+                      bool back, double* work) {
+  kpp::FhtSpec f;
+  f.in = x;
+  f.ld_in = 1;
+  f.rows_valid = back ? R : nx;
+  f.cols_valid = 1;
+  f.out = y;
+  f.ld_out = 1;
+  f.rows_out = back ? nx : R;
+  f.M = R;
+  f.ncols = 1;
+  f.work = work;
+  const double scale = 1.0 / std::sqrt(static_cast<double>(R));
+  if (back) {
+    f.osign = signs;
+    f.oscale = scale;
+  } else {
+    f.isign = signs;
+    f.iscale = scale;
+  }
+  kpp::launch_fht(f, st);
+  HIP_TRY(hipGetLastError());
+  return KPP_OK;
+}
+
+kpp_status rht_general(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t lda, const double* b,
+                       const int8_t* signs, int64_t R, double* At, int64_t ldt, double* bt) {
+  kpp::FhtSpec f;
+  f.in = A;
+  f.ld_in = lda;
+  f.rows_valid = m;
+  f.cols_valid = n;
+  f.isign = signs;
+  f.iscale = 1.0 / std::sqrt(static_cast<double>(R));
+  f.out = At;
+  f.ld_out = ldt;
+  f.rows_out = R;
+  f.M = R;
+  f.ncols = n;
+  kpp::launch_fht(f, st);   // two passes run in place on At
+  HIP_TRY(hipGetLastError());
+  return rht_vector(st, R, signs, b, m, bt, false, nullptr);
+}
+
+kpp_status rht_psd(hipStream_t st, int64_t n, const double* A, int64_t lda, const double* b, const int8_t* signs,
+                   int64_t R, double* At, int64_t ldt, double* bt, double* work) {
+  const double scale = 1.0 / std::sqrt(static_cast<double>(R));
+  // (H D A D)^T into At, then H applied to it in place: H (H D A D)^T = H D A D H
+  kpp::FhtSpec f;
+  f.in = A;
+  f.ld_in = lda;
+  f.rows_valid = n;
+  f.cols_valid = n;
+  f.isign = signs;
+  f.iscale = scale;
+  f.csign = signs;
+  f.cscale = scale;
+  f.out = At;
+  f.ld_out = ldt;
+  f.rows_out = R;
+  f.transpose_out = 1;
+  f.M = R;
+  f.ncols = R;
+  f.work = work;
+  kpp::launch_fht(f, st);
+  HIP_TRY(hipGetLastError());
+  kpp::FhtSpec g;
+  g.in = At;
+  g.ld_in = ldt;
+  g.rows_valid = R;
+  g.cols_valid = R;
+  g.out = At;
+  g.ld_out = ldt;
+  g.rows_out = R;
+  g.M = R;
+  g.ncols = R;
+  kpp::launch_fht(g, st);
+  HIP_TRY(hipGetLastError());
+  return rht_vector(st, R, signs, b, n, bt, false, nullptr);
+}
+
+void draw_signs(uint64_t seed, int64_t N, int8_t* out) {
+  kpp::SplitMix64 g(seed);
+  for (int64_t i = 0; i < N; ++i) out[i] = (g.next() >> 63) ? int8_t{-1} : int8_t{1};
+}
+
+// Form (or reuse) the transformed system of sys for this seed.
+kpp_status prepare_rht(kpp_system* sys, uint64_t seed) {
+  const bool psd = sys->kind == KPP_CD_PSD;
+  const int64_t rows = psd ? sys->n : sys->m;
+  const int64_t R = next_pow2(rows);
+  KPP_TRY(check_rht_size(rows, R));
+  if (sys->rht_inner && sys->rht_seed == seed) return KPP_OK;
+  hipStream_t st = sys->ctx->stream;
+  HIP_TRY(hipStreamSynchronize(st));
+  drop_rht(sys);
+  const int64_t cols = psd ? R : sys->n;
+  kpp_status stt;
+  if ((stt = dev_alloc(&sys->rht_signs, R)) < 0 || (stt = dev_alloc(&sys->rht_A, R * cols)) < 0 ||
+      (stt = dev_alloc(&sys->rht_b, R)) < 0 || (psd && (stt = dev_alloc(&sys->rht_x, R)) < 0) ||
+      (kpp::fht_passes(R) > 1 && (stt = dev_alloc(&sys->rht_work, psd ? R * R : R)) < 0)) {
+    drop_rht(sys);
+    return stt;
+  }
+  std::vector<int8_t> h(static_cast<size_t>(R));
+  draw_signs(seed, R, h.data());
+  HIP_TRY(hipMemcpyAsync(sys->rht_signs, h.data(), static_cast<size_t>(R), hipMemcpyHostToDevice, st));
+  kpp_status r = psd ? rht_psd(st, sys->n, sys->A, sys->lda, sys->b, sys->rht_signs, R, sys->rht_A, R, sys->rht_b,
+                               sys->rht_work)
+                     : rht_general(st, sys->m, sys->n, sys->A, sys->lda, sys->b, sys->rht_signs, R, sys->rht_A,
+                                   sys->n, sys->rht_b);
+  if (r < 0) {
+    drop_rht(sys);
+    return r;
+  }
+  HIP_TRY(hipStreamSynchronize(st));   // the signs' host copy goes out of scope
+  r = kpp_system_create(sys->ctx, sys->kind, R, cols, sys->rht_A, cols, sys->rht_b, &sys->rht_inner);
+  if (r < 0) {
+    drop_rht(sys);
+    return r;
+  }
+  sys->rht_R = R;
+  sys->rht_seed = seed;
+  return KPP_OK;
+}
+
+kpp_status solve_rht(kpp_system* sys, const kpp_params* p, double* x, kpp_result* res) {
+  KPP_TRY(prepare_rht(sys, p->rht_seed));
+  sys->res_valid = false;
+  hipStream_t st = sys->ctx->stream;
+  kpp_params q = *p;
+  q.rht = 0;
+  kpp_result r{};
+  kpp_status out;
+  if (sys->kind == KPP_CD_PSD) {
+    const int64_t R = sys->rht_R;
+    KPP_TRY(rht_vector(st, R, sys->rht_signs, x, sys->n, sys->rht_x, false, nullptr));
+    out = kpp_solve(sys->rht_inner, &q, sys->rht_x, &r);
+    if (out < 0) return out;
+    KPP_TRY(rht_vector(st, R, sys->rht_signs, sys->rht_x, sys->n, x, true, sys->rht_work));
+  } else {
+    out = kpp_solve(sys->rht_inner, &q, x, &r);
+    if (out < 0) return out;
+  }
+  double rn = 0.0;
+  KPP_TRY(residual_norm(sys, x, &rn));
+  r.true_rel_res = rn / (sys->bnorm > 0.0 ? sys->bnorm : 1.0);
+  if (res) *res = r;
+  return out;
+}
+
+}  // namespace
+
+KPP_API kpp_status kpp_rht_signs(uint64_t seed, int64_t N, int8_t* signs_host) {
+  if (N < 0 || (N > 0 && !signs_host)) return fail(KPP_ERR_INVALID_ARG, "N < 0 or NULL output");
+  draw_signs(seed, N, signs_host);
+  return KPP_OK;
+}
+
+KPP_API kpp_status kpp_rht_general(kpp_context* ctx, int64_t m, int64_t n, const double* A, int64_t lda,
+                                   const double* b, const int8_t* signs, int64_t R, double* At, int64_t ldt,
+                                   double* bt) {
+  if (!ctx || !A || !b || !signs || !At || !bt) return fail(KPP_ERR_INVALID_ARG, "NULL argument");
+  if (m < 1 || n < 1) return fail(KPP_ERR_SHAPE, "empty matrix");
+  if (lda < n || ldt < n) return fail(KPP_ERR_INVALID_ARG, "leading dimension below n");
+  KPP_TRY(check_rht_size(m, R));
+  HIP_TRY(hipSetDevice(ctx->device));
+  return rht_general(ctx->stream, m, n, A, lda, b, signs, R, At, ldt, bt);
+}
+
+KPP_API kpp_status kpp_rht_psd(kpp_context* ctx, int64_t n, const double* A, int64_t lda, const double* b,
+                               const int8_t* signs, int64_t R, double* At, int64_t ldt, double* bt,
+                               double* work) {
+  if (!ctx || !A || !b || !signs || !At || !bt) return fail(KPP_ERR_INVALID_ARG, "NULL argument");
+  if (n < 1) return fail(KPP_ERR_SHAPE, "empty matrix");
+  if (lda < n || ldt < R) return fail(KPP_ERR_INVALID_ARG, "leading dimension too small");
+  KPP_TRY(check_rht_size(n, R));
+  if (kpp::fht_passes(R) > 1 && !work) return fail(KPP_ERR_INVALID_ARG, "R > 4096 needs R x R doubles of work");
+  HIP_TRY(hipSetDevice(ctx->device));
+  return rht_psd(ctx->stream, n, A, lda, b, signs, R, At, ldt, bt, work);
+}
+
+KPP_API kpp_status kpp_rht_vector(kpp_context* ctx, int64_t R, const int8_t* signs, const double* x, int64_t nx,
+                                  double* y, int32_t direction, double* work) {
+  if (!ctx || !signs || !x || !y) return fail(KPP_ERR_INVALID_ARG, "NULL argument");
+  if (direction != 0 && direction != 1) return fail(KPP_ERR_INVALID_ARG, "direction must be 0 or 1");
+  if (nx < 1) return fail(KPP_ERR_SHAPE, "empty vector");
+  KPP_TRY(check_rht_size(nx, R));
+  if (direction == 1 && nx < R && kpp::fht_passes(R) > 1 && !work)
+    return fail(KPP_ERR_INVALID_ARG, "R > 4096 with nx < R needs R doubles of work");
+  HIP_TRY(hipSetDevice(ctx->device));
+  return rht_vector(ctx->stream, R, signs, x, nx, y, direction == 1, work);
+}
+
 KPP_API int32_t kpp_abi_version(void) { return KPP_ABI_VERSION; }
 
 KPP_API const char* kpp_last_error(void) { return g_last_error.c_str(); }
@@ -1858,6 +2098,7 @@ KPP_API kpp_status kpp_solve(kpp_system* sys, const kpp_params* p, double* x_dev
   KPP_TRY(check_params(sys, p));
   HIP_TRY(hipSetDevice(sys->ctx->device));
   try {
+    if (p->rht) return solve_rht(sys, p, x_dev, res);
     if (p->precision == KPP_MIXED_FP32) return solve_mixed(sys, p, x_dev, res);
     return solve_fp64(sys, p, x_dev, res);
   } catch (const std::bad_alloc&) {
@@ -2098,6 +2339,7 @@ KPP_API kpp_status kpp_server_submit(kpp_server* srv, kpp_system* sys, const kpp
   if (p->engine == 1) return fail(KPP_ERR_INVALID_ARG, "the server runs the fused engine only");
   if (p->schedule) return fail(KPP_ERR_INVALID_ARG, "explicit schedules are for kpp_solve");
   if (p->resume) return fail(KPP_ERR_INVALID_ARG, "resume is for kpp_solve");
+  if (p->rht) return fail(KPP_ERR_INVALID_ARG, "rht is for kpp_solve (submit a system transformed by kpp_rht_psd)");
   sys->res_valid = false;
   auto* r = new (std::nothrow) ServeReq;
   if (!r) return fail(KPP_ERR_OOM, "host allocation failed");

@@ -62,6 +62,28 @@ static void resume_case(int kind, int64_t m, int64_t n, int s) {
   hipFree(A); hipFree(b); hipFree(x);
 }
 
+// Solves with randomized Hadamard preprocessing: a Kaczmarz++ system whose
+// padded row count takes two transform passes, and a CD++ one; a second solve
+// with the same seed reuses the transformed system, another seed rebuilds it.
+static void rht_case(int kind, int64_t m, int64_t n, int s) {
+  kpp_context* ctx; CHECK(kpp_context_create(0, nullptr, &ctx));
+  double* A = dev_vec(m * n, 0.5); double* b = dev_vec(m, 1.0); double* x = dev_vec(n, 0.0);
+  kpp_system* sys; CHECK(kpp_system_create(ctx, kind, m, n, A, n, b, &sys));
+  for (uint64_t seed : {3ull, 3ull, 4ull}) {
+    kpp_params p; CHECK(kpp_params_default(&p, kind));
+    p.block_size = s; p.max_iters = 90; p.tol = 0.0; p.rht = 1; p.rht_seed = seed;
+    kpp_result r; CHECK(kpp_solve(sys, &p, x, &r));
+    std::printf("rht kind=%d m=%lld seed=%llu iters=%lld\n", kind, (long long)m, (unsigned long long)seed,
+                (long long)r.iters);
+  }
+  kpp_params p; CHECK(kpp_params_default(&p, kind));
+  p.block_size = s; p.rht = 1; p.resume = 1;
+  kpp_result r;
+  if (kpp_solve(sys, &p, x, &r) >= 0) { std::printf("FAIL: rht with resume\n"); std::exit(1); }
+  CHECK(kpp_system_destroy(sys)); CHECK(kpp_context_destroy(ctx));
+  hipFree(A); hipFree(b); hipFree(x);
+}
+
 static void serve_case() {
   kpp_context* ctx; CHECK(kpp_context_create(0, nullptr, &ctx));
   struct J { int kind; int64_t m, n; int s; int prec; double tol; };
@@ -118,6 +140,8 @@ int main(int argc, char** argv) {
     solve_case("mixed_psd", 1, 1000, 1000, 128, 1, 1, 0, 0, 1, 20000, 1e-10);
     resume_case(1, 600, 600, 64);
     resume_case(0, 900, 300, 40);
+    rht_case(0, 5000, 12, 16);
+    rht_case(1, 100, 100, 16);
   }
   if (!*only || !std::strcmp(only, "serve")) serve_case();
   std::printf("EMU OK\n");

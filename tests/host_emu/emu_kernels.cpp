@@ -152,6 +152,39 @@ void launch_check_finite(const double* A, int64_t lda, int64_t m, int64_t n, con
   emu_check(b, 8 * m, "finite b");
   emu_check(flag, 4, "finite flag");
 }
+// The device routine's pass chain: the first pass reads in (rows < rows_valid,
+// columns < min(cols_valid, ncols)), the last one writes out (rows < rows_out,
+// transposed or not), and with two passes the intermediate lives in out when
+// the last pass runs in place there, otherwise in work (M x ncols).
+void launch_fht(const FhtSpec& s, hipStream_t) {
+  if (s.M < 1 || (s.M & (s.M - 1)) || s.M > kFhtMaxRows || s.ncols < 1 || s.rows_valid < 1 ||
+      s.rows_valid > s.M || s.cols_valid < 1 || s.rows_out < 1 || s.rows_out > s.M) {
+    std::fprintf(stderr, "EMU: bad fht shape M=%lld ncols=%lld\n", (long long)s.M, (long long)s.ncols);
+    std::abort();
+  }
+  const int64_t cin = std::min(s.cols_valid, s.ncols);
+  emu_check(s.in, 8 * (static_cast<size_t>(s.rows_valid - 1) * s.ld_in + cin), "fht in");
+  if (s.isign) emu_check(s.isign, static_cast<size_t>(s.rows_valid), "fht row signs");
+  if (s.csign) emu_check(s.csign, static_cast<size_t>(cin), "fht column signs");
+  if (s.osign) emu_check(s.osign, static_cast<size_t>(s.rows_out), "fht output signs");
+  if (s.transpose_out)
+    emu_check(s.out, 8 * (static_cast<size_t>(s.ncols - 1) * s.ld_out + s.rows_out), "fht out (transposed)");
+  else
+    emu_check(s.out, 8 * (static_cast<size_t>(s.rows_out - 1) * s.ld_out + s.ncols), "fht out");
+  if (fht_passes(s.M) > 1) {
+    const bool mid_is_out = !s.transpose_out && s.rows_out >= s.M && s.ld_out >= s.ncols;
+    if (mid_is_out)
+      emu_check(s.out, 8 * (static_cast<size_t>(s.M - 1) * s.ld_out + s.ncols), "fht intermediate in out");
+    else
+      emu_check(s.work, 8 * static_cast<size_t>(s.M) * s.ncols, "fht work");
+  }
+  // a single transposed pass cannot run in place (other workgroups still read what it writes)
+  if (s.in == s.out && s.transpose_out && fht_passes(s.M) == 1) {
+    std::fprintf(stderr, "EMU: transposed fht in place\n");
+    std::abort();
+  }
+}
+
 void launch_state_init(DevState* ds, double rho0, double thr, hipStream_t) {
   emu_check(ds, sizeof(DevState), "state init");
   DevState s{};

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(kpp):
     for name in syms:
         assert hasattr(raw, name), name
     assert set(syms) == set(kpp.EXPORTED)
-    assert kpp.kpp_abi_version() == 1
+    assert kpp.kpp_abi_version() == 2
 
 
 def test_params_default_and_validation(kpp):
@@ -52,6 +52,27 @@ def test_params_default_and_validation(kpp):
     p.block_size = 11
     with pytest.raises(kpp.KppError):
         kpp.kpp_schedule_generate(kpp.KPP_CD_PSD, 10, 10, p, 5, 100)
+
+
+@pytest.mark.parametrize("seed,N", [(0, 1), (9, 4096), (0x2501116730, 1000), (2 ** 64 - 1, 77)])
+def test_rht_signs_match_oracle(kpp, seed, N):
+    from oracle import rht as orht
+
+    assert kpp.kpp_rht_signs(seed, N) == [int(v) for v in orht.rademacher(seed, N)]
+
+
+def test_rht_argument_checks(kpp):
+    with pytest.raises(kpp.KppError) as e:
+        kpp.kpp_rht_general(0, 4, 4, 0, 4, 0, 0, 4, 0, 4, 0)
+    assert e.value.status == kpp.KPP_ERR_INVALID_ARG
+    with pytest.raises(kpp.KppError):
+        kpp.kpp_rht_psd(0, 4, 0, 4, 0, 0, 4, 0, 4, 0)
+    with pytest.raises(kpp.KppError):
+        kpp.kpp_rht_vector(0, 4, 0, 0, 4, 0, 0)
+    with pytest.raises(kpp.KppError):
+        kpp.kpp_rht_signs(1, -1)
+    p = kpp.kpp_params_default(kpp.KPP_KACZMARZ)
+    assert p.rht == 0 and p.rht_seed == 0
 
 
 def oracle_schedule(kind, m, n, mode, s, T, seed, num_blocks=0, partition=True):
