@@ -13,7 +13,9 @@ second over the timed solves; ms_per_step = time to tolerance per solve.
 The same solves are then timed with mixed precision (FP32 block products,
 FP64 factors and iterative refinement) and reported under "mixed", and the
 serving workload (continuous batching of 512 solves arriving at 200/s) is
-replayed in real time and reported under "serving" (p50/p99 latency).
+replayed in real time and reported under "serving" (p50/p99 latency).  Under
+"rht": the randomized Hadamard preprocessing (Definition d:rht) timed at the
+workloads' shapes, and the same CD++ solve with it.
 
 Also printed: the roofline of the dominant kernel (the step kernel, timed with
 HIP events inside the library on the stream it runs on) and the CPU oracle
@@ -46,6 +48,9 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB three times (HBM counter calibration)")
     ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--no-rht", action="store_true")
+    ap.add_argument("--rht-only", action="store_true",
+                    help="only the randomized Hadamard transforms (for profiling them)")
     return ap.parse_args()
 
 
@@ -189,6 +194,81 @@ def serving(kpp, torch, dev, num_requests, seed=5):
     }
 
 
+def rht_transforms(kpp, torch, dev, ctx, A, b, reps=5):
+    """Randomized Hadamard preprocessing at the workloads' shapes, timed with
+    events on the library's stream: the two-sided CD++ transform of the n = 4096
+    system (two passes), and the Kaczmarz++ row transform of a 2048 x 32768
+    (one pass) and a 65536 x 2048 (two passes) seeded normal matrix.
+    Algorithmic bytes: read the input once, write the output once."""
+    out = {}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / 1e3 / reps
+
+    n = A.shape[0]
+    R = n
+    sg = torch.tensor(kpp.kpp_rht_signs(11, R), dtype=torch.int8, device=dev)
+    At = torch.empty((R, R), dtype=torch.float64, device=dev)
+    bt = torch.empty((R,), dtype=torch.float64, device=dev)
+    t = timed(lambda: kpp.kpp_rht_psd(ctx, n, A.data_ptr(), n, b.data_ptr(), sg.data_ptr(), R, At.data_ptr(), R,
+                                      bt.data_ptr()))
+    alg = 8.0 * (n * n + R * R + n + R)
+    out["psd_n4096"] = {"us": round(t * 1e6, 2), "passes_over_A": 2, "bytes_algorithmic": alg,
+                        "achieved_GBs": round(alg / t / 1e9, 1), "frac": round(alg / t / 1e9 / HBM_PEAK_GBS, 4)}
+    del At, bt
+    g = torch.Generator(device=dev)
+    g.manual_seed(404)
+    for name, m, nn in (("general_2048x32768", 2048, 32768), ("general_65536x2048", 65536, 2048)):
+        M = 1
+        while M < m:
+            M *= 2
+        X = torch.randn((m, nn), generator=g, dtype=torch.float64, device=dev)
+        y = torch.randn((m,), generator=g, dtype=torch.float64, device=dev)
+        sg = torch.tensor(kpp.kpp_rht_signs(12, M), dtype=torch.int8, device=dev)
+        Xt = torch.empty((M, nn), dtype=torch.float64, device=dev)
+        yt = torch.empty((M,), dtype=torch.float64, device=dev)
+        t = timed(lambda: kpp.kpp_rht_general(ctx, m, nn, X.data_ptr(), nn, y.data_ptr(), sg.data_ptr(), M,
+                                              Xt.data_ptr(), nn, yt.data_ptr()))
+        alg = 8.0 * (m * nn + M * nn + m + M)
+        out[name] = {"us": round(t * 1e6, 2), "passes_over_A": 1 if M <= 4096 else 2, "bytes_algorithmic": alg,
+                     "achieved_GBs": round(alg / t / 1e9, 1), "frac": round(alg / t / 1e9 / HBM_PEAK_GBS, 4)}
+        del X, Xt
+    return out
+
+
+def rht_solves(kpp, torch, dev, h, p, x, reps):
+    """CD++ on the same system with params.rht = 1: the first solve forms the
+    transformed system, later ones reuse it."""
+    q = kpp.kpp_params_default(kpp.KPP_CD_PSD)
+    for f, _ in kpp.kpp_params._fields_:
+        setattr(q, f, getattr(p, f))
+    q.rht = 1
+    q.rht_seed = 2
+    times, res = [], []
+    for _ in range(1 + reps):
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, r = kpp.kpp_solve(h, q, x.data_ptr())
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        res.append((st, r))
+    cached = times[1:]
+    return {"first_solve_ms": round(1e3 * times[0], 3),
+            "time_to_tol_ms": round(1e3 * sum(cached) / max(len(cached), 1), 3),
+            "iters_per_solve": sum(r.iters for _, r in res[1:]) / max(len(cached), 1),
+            "converged": all(st == kpp.KPP_OK and r.converged for st, r in res),
+            "true_rel_res": res[-1][1].true_rel_res}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -222,6 +302,19 @@ def main():
     p.engine = args.engine
     p.team_groups = args.team_groups
     x = torch.zeros(n, dtype=torch.float64, device=dev)
+    if args.rht_only:
+        rec = {"rht": rht_transforms(kpp, torch, dev, ctx, A, b, reps=args.steps)}
+        if args.calibrate_copy > 0:
+            src = torch.empty(args.calibrate_copy << 20, dtype=torch.uint8, device=dev).fill_(1)
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            rec["copy_calibration_bytes"] = args.calibrate_copy << 20
+        print(json.dumps(rec), flush=True)
+        kpp.kpp_system_destroy(h)
+        kpp.kpp_context_destroy(ctx)
+        return
 
     def one():
         x.zero_()
@@ -330,6 +423,10 @@ def main():
         "kernel_ms_per_solve": 1e3 * sum(r.kernel_seconds for _, r in mres) / args.steps,
         "speedup_vs_fp64": (1e3 * elapsed / args.steps) / (1e3 * melapsed / args.steps),
     }
+    if not args.no_rht:
+        rh = rht_transforms(kpp, torch, dev, ctx, A, b)
+        rh["cdpp_n4096_with_rht"] = rht_solves(kpp, torch, dev, h, p, x, args.steps)
+        line["rht"] = rh
     kpp.kpp_system_destroy(h)
     kpp.kpp_context_destroy(ctx)
     if not args.no_serving:

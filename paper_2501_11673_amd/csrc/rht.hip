@@ -32,9 +32,16 @@ constexpr int kStripCols = 8;
 constexpr int kStripWaves = 16;
 constexpr int kStripThreads = 64 * kStripWaves;
 constexpr int kStripLow = 8 * kStripWaves;       // rows of a digit spanned by lanes and waves
-constexpr int kLdsRoundJ = 16;                   // register values exchanged per LDS round
-constexpr size_t kStripLds = sizeof(double) * kLdsRoundJ * kStripWaves * 64;
 constexpr int kSmallThreads = 256;
+constexpr int kVecThreads = 1024;
+constexpr int kVecMax = 4096;                    // one-pass vector transforms in LDS
+
+// Register values exchanged per LDS round (up to 16: 128 KB of LDS).  Rounds
+// of 8 with two workgroups per compute unit measured slower for J = 16.
+template <int J>
+constexpr int lds_round() { return J < 16 ? J : 16; }
+template <int J>
+constexpr size_t strip_lds_bytes() { return sizeof(double) * lds_round<J>() * kStripWaves * 64; }
 
 struct FhtPass {
   const double* in;
@@ -177,7 +184,7 @@ __global__ __launch_bounds__(kStripThreads) void k_fht_strip(FhtPass a) {
   }
   // r bits 3..6 : waves, through LDS in rounds of up to 16 register values.
   // Layout [q][wave][lane]: every access below is 64 consecutive doubles.
-  constexpr int JC = J < kLdsRoundJ ? J : kLdsRoundJ;
+  constexpr int JC = lds_round<J>();
 #pragma unroll
   for (int j0 = 0; j0 < J; j0 += JC) {
 #pragma unroll
@@ -204,6 +211,25 @@ __global__ __launch_bounds__(kStripThreads) void k_fht_strip(FhtPass a) {
   }
 }
 
+// One column of up to 4096 rows in one pass (the vectors b, x0, x): the
+// column sits in LDS and the log2 R butterfly stages run there.
+__global__ __launch_bounds__(kVecThreads) void k_fht_vec(FhtPass a) {
+  __shared__ double buf[kVecMax];
+  const int R = static_cast<int>(a.rsig);
+  for (int i = threadIdx.x; i < R; i += kVecThreads) buf[i] = load_in(a, i, 0);
+  __syncthreads();
+  for (int h = 1; h < R; h <<= 1) {
+    for (int k = threadIdx.x; k < R / 2; k += kVecThreads) {
+      const int i = (k / h) * 2 * h + (k % h);
+      const double x = buf[i], y = buf[i + h];
+      buf[i] = x + y;
+      buf[i + h] = x - y;
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < R; i += kVecThreads) store_out(a, i, 0, buf[i]);
+}
+
 // Digits with R < 128: lane = column, R registers per lane.
 template <int R>
 __global__ __launch_bounds__(kSmallThreads) void k_fht_small(FhtPass a) {
@@ -225,14 +251,14 @@ __global__ __launch_bounds__(kSmallThreads) void k_fht_small(FhtPass a) {
 
 template <int J>
 void launch_strip(const FhtPass& a, hipStream_t st) {
+  constexpr size_t lds = strip_lds_bytes<J>();
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fht_strip<J>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kStripLds));
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     attr_set = true;
   }
   const int64_t blocks = (a.tiles + 15) / 16 * 16;
-  const size_t lds = sizeof(double) * (J < kLdsRoundJ ? J : kLdsRoundJ) * kStripWaves * 64;
   hipLaunchKernelGGL(k_fht_strip<J>, dim3(static_cast<unsigned>(blocks)), dim3(kStripThreads), lds, st, a);
 }
 
@@ -246,6 +272,10 @@ void launch_small(const FhtPass& a, hipStream_t st) {
 void launch_pass(FhtPass a, int log_r, hipStream_t st) {
   const int64_t R = int64_t{1} << log_r;
   a.rsig = R * a.sigma;
+  if (a.ncols == 1 && a.sigma == 1 && a.tiles == 1 && R >= kSmallThreads && R <= kVecMax) {
+    hipLaunchKernelGGL(k_fht_vec, dim3(1), dim3(kVecThreads), 0, st, a);
+    return;
+  }
   if (log_r >= 7) {
     a.nstrips = (a.ncols + kStripCols - 1) / kStripCols;
     const int64_t n_hi = a.tiles;   // caller passes M / (R sigma) here
