@@ -15,7 +15,8 @@ FP64 factors and iterative refinement) and reported under "mixed", and the
 serving workload (continuous batching of 512 solves arriving at 200/s) is
 replayed in real time and reported under "serving" (p50/p99 latency).  Under
 "rht": the randomized Hadamard preprocessing (Definition d:rht) timed at the
-workloads' shapes, and the same CD++ solve with it.
+workloads' shapes, and the same CD++ solve with it.  Under "flops_to_tol": the
+paper's FLOP comparison (Section 6.3) re-run on synthetic kernel matrices.
 
 Also printed: the roofline of the dominant kernel (the step kernel, timed with
 HIP events inside the library on the stream it runs on) and the CPU oracle
@@ -49,6 +50,7 @@ def parse():
                     help="also run a plain device copy of MIB MiB three times (HBM counter calibration)")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--no-rht", action="store_true")
+    ap.add_argument("--no-flops", action="store_true")
     ap.add_argument("--rht-only", action="store_true",
                     help="only the randomized Hadamard transforms (for profiling them)")
     return ap.parse_args()
@@ -269,6 +271,57 @@ def rht_solves(kpp, torch, dev, h, p, x, reps):
             "true_rel_res": res[-1][1].true_rel_res}
 
 
+PAPER_TAB_FLOPS = {
+    # Table tab:flops (Section 6.3 and its appendix), over its 20 matrices: min and max
+    "full_cdpp": {"1e-04": [2.23e8, 5.71e9], "1e-08": [1.80e9, 3.64e10]},
+    "cdpp_wo_rht": {"1e-04": [4.39e6, 3.63e9], "1e-08": [1.79e9, 3.11e10]},
+    "gmres": {"1e-04": [3.37e8, 4.87e9], "1e-08": [1.33e9, 1.70e10]},
+    "cg": {"1e-04": [3.70e8, 1.65e10], "1e-08": [3.26e9, 5.55e10]},
+}
+
+
+def flops_to_tol(kpp, torch, dev, ctx, seed):
+    """The paper's FLOP comparison (Section 6.3, Table tab:flops) on synthetic
+    data: CD++ with and without RHT on Gaussian and Laplacian kernel matrices
+    (gamma 0.1 and 0.01) of n = 4096 seeded points plus 1e-3 I, b ~ N(0, I),
+    s = 200, lambda = 1e-8, online memo; FLOPs counted as the paper counts them
+    (kpp_result.flops, RHT included), next to the range of the paper's own
+    numbers over its 20 matrices (other data, no hardware stated)."""
+    import synth
+
+    rows = []
+    n, s = 4096, 200
+    for kern in ("gaussian", "laplacian"):
+        for gamma in (0.1, 0.01):
+            sysm = synth.kernel_system(kern, n, gamma, seed=seed, device="cuda")
+            for rht in (1, 0):
+                for tol in (1e-4, 1e-8):
+                    h = kpp.kpp_system_create(ctx, kpp.KPP_CD_PSD, n, n, sysm.A.data_ptr(), n, sysm.b.data_ptr())
+                    p = kpp.kpp_params_default(kpp.KPP_CD_PSD)
+                    p.block_size = s
+                    p.lambda_ = 1e-8
+                    p.tol = tol
+                    p.max_iters = 400_000
+                    p.seed = seed
+                    p.rht = rht
+                    p.rht_seed = seed + 1
+                    x = torch.zeros(n, dtype=torch.float64, device=dev)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    st, r = kpp.kpp_solve(h, p, x.data_ptr())
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t0
+                    kpp.kpp_system_destroy(h)
+                    rows.append({"matrix": f"{kern} gamma={gamma:g}", "method": "full_cdpp" if rht else "cdpp_wo_rht",
+                                 "tol": tol, "flops": r.flops, "iters": r.iters, "ms": round(1e3 * dt, 3),
+                                 "converged": bool(st == kpp.KPP_OK and r.converged),
+                                 "true_rel_res": r.true_rel_res})
+            del sysm
+    return {"workload": "CD++ on n=4096 kernel matrices + 1e-3 I (seeded Gaussian points, d=8), s=200, "
+                        "lambda=1e-8, online memo; b ~ N(0, I)",
+            "runs": rows, "paper_tab_flops_range": PAPER_TAB_FLOPS}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -427,6 +480,8 @@ def main():
         rh = rht_transforms(kpp, torch, dev, ctx, A, b)
         rh["cdpp_n4096_with_rht"] = rht_solves(kpp, torch, dev, h, p, x, args.steps)
         line["rht"] = rh
+    if not args.no_flops:
+        line["flops_to_tol"] = flops_to_tol(kpp, torch, dev, ctx, args.seed)
     kpp.kpp_system_destroy(h)
     kpp.kpp_context_destroy(ctx)
     if not args.no_serving:

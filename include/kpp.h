@@ -154,7 +154,10 @@ typedef struct kpp_result {
   double rho_final;
   double seconds_total;
   double seconds_factor;      /* time in Gram + Cholesky                                 */
-  double flops;               /* 2sn (+2sn K++) + 2s^2 + 5n per step; s^3/3 (+s^2 n) per factor */
+  double flops;               /* 2sn (+2sn K++) + 2s^2 + 5n per step; s^3/3 (+s^2 n) per factor;
+                                 with rht: the transform's additions as the paper counts
+                                 them (SymFHT or FHT of A and FHT of b when the solve
+                                 formed them; CD++ also FHTs of the iterate in and out) */
   double bytes_algorithmic;   /* per step: s n b_A (A_S) + s(s+1)/2 * 8 (factor) + 12 s (b_S, rows) */
   double kernel_seconds;      /* device time of the step kernels (HIP events), all launches */
   double kernel_launches;     /* number of step-kernel launches (fused: one per window)  */

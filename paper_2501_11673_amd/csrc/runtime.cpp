@@ -1837,13 +1837,26 @@ kpp_status rht_psd(hipStream_t st, int64_t n, const double* A, int64_t lda, cons
   return rht_vector(st, R, signs, b, n, bt, false, nullptr);
 }
 
+// Additions of the transforms as the paper counts them (Appendix on SymFHT):
+// FHT of an n x d matrix n d log2 n, SymFHT by its recursion (two half-size
+// SymFHTs, two FHTs of the off-diagonal block, 7 (n/2)^2 block sums).
+double fht_adds(double n, double d) { return n > 1.0 ? n * d * std::log2(n) : 0.0; }
+double symfht_adds(int64_t n) {
+  if (n <= 1) return 0.0;
+  const int64_t h = n / 2;
+  const double hd = static_cast<double>(h);
+  return 2.0 * symfht_adds(h) + 2.0 * fht_adds(hd, hd) + 7.0 * hd * hd;
+}
+
 void draw_signs(uint64_t seed, int64_t N, int8_t* out) {
   kpp::SplitMix64 g(seed);
   for (int64_t i = 0; i < N; ++i) out[i] = (g.next() >> 63) ? int8_t{-1} : int8_t{1};
 }
 
-// Form (or reuse) the transformed system of sys for this seed.
-kpp_status prepare_rht(kpp_system* sys, uint64_t seed) {
+// Form (or reuse) the transformed system of sys for this seed; *built tells
+// whether this call formed it.
+kpp_status prepare_rht(kpp_system* sys, uint64_t seed, bool* built) {
+  *built = false;
   const bool psd = sys->kind == KPP_CD_PSD;
   const int64_t rows = psd ? sys->n : sys->m;
   const int64_t R = next_pow2(rows);
@@ -1879,11 +1892,13 @@ kpp_status prepare_rht(kpp_system* sys, uint64_t seed) {
   }
   sys->rht_R = R;
   sys->rht_seed = seed;
+  *built = true;
   return KPP_OK;
 }
 
 kpp_status solve_rht(kpp_system* sys, const kpp_params* p, double* x, kpp_result* res) {
-  KPP_TRY(prepare_rht(sys, p->rht_seed));
+  bool built = false;
+  KPP_TRY(prepare_rht(sys, p->rht_seed, &built));
   sys->res_valid = false;
   hipStream_t st = sys->ctx->stream;
   kpp_params q = *p;
@@ -1903,6 +1918,15 @@ kpp_status solve_rht(kpp_system* sys, const kpp_params* p, double* x, kpp_result
   double rn = 0.0;
   KPP_TRY(residual_norm(sys, x, &rn));
   r.true_rel_res = rn / (sys->bnorm > 0.0 ? sys->bnorm : 1.0);
+  // the transforms' additions: A and b when this solve formed them, and for
+  // CD++ the iterate in and out
+  const double Rd = static_cast<double>(sys->rht_R);
+  if (sys->kind == KPP_CD_PSD) {
+    if (built) r.flops += symfht_adds(sys->rht_R) + fht_adds(Rd, 1.0);
+    r.flops += 2.0 * fht_adds(Rd, 1.0);
+  } else if (built) {
+    r.flops += fht_adds(Rd, static_cast<double>(sys->n)) + fht_adds(Rd, 1.0);
+  }
   if (res) *res = r;
   return out;
 }

@@ -18,6 +18,12 @@ Recipes (all seeded; numpy ``default_rng(seed)`` on the CPU, a seeded
 * PSD systems (CD++): A = Q diag(lambda) Q^T, symmetrised as (A + A^T)/2,
   x* ~ N(0, I), b = A x*.
 
+* Kernel systems (the setting of the paper's FLOP comparison, Section 6.3):
+  n points phi_i ~ N(0, I_d), A = K + phi I with K_ij = exp(-gamma ||phi_i -
+  phi_j||^2) (Gaussian) or exp(-gamma ||phi_i - phi_j||) (Laplacian),
+  b ~ N(0, I).  A is positive definite, so the system is consistent, but x* is
+  not planted (xstar is None).
+
 The spectra follow the paper's experimental premise (Section 6): a few large
 outliers over a flat or decaying bulk.  The paper's own matrices (the
 scikit-learn low-rank generator and four ML data sets, Section 6.1) are not
@@ -46,6 +52,7 @@ __all__ = [
     "CONFIGS",
     "tiny_system",
     "serving_workload",
+    "kernel_system",
 ]
 
 
@@ -183,6 +190,40 @@ def psd_system(n: int, eig_fn, seed: int, *, device: Optional[str] = None,
         b = A @ xstar
     return System(A=A, b=b, xstar=xstar, kind="psd", name=name, spectrum=lam,
                   params=dict(n=n, seed=seed))
+
+
+def kernel_system(kernel: str, n: int, gamma: float, *, d: int = 8, phi: float = 1e-3, seed: int = 0,
+                  device: Optional[str] = None) -> System:
+    """Kernel matrix plus phi I on n seeded Gaussian points in d dimensions
+    (Section 6.1, "Kernel Matrices from Machine Learning", with synthetic
+    features in place of the data sets); b ~ N(0, I)."""
+    if kernel not in ("gaussian", "laplacian"):
+        raise ValueError("kernel must be gaussian or laplacian")
+    if device is None:
+        rng = np.random.default_rng(seed)
+        F = rng.standard_normal((n, d))
+        sq = np.maximum((F * F).sum(1)[:, None] + (F * F).sum(1)[None, :] - 2.0 * F @ F.T, 0.0)
+        np.fill_diagonal(sq, 0.0)
+        K = np.exp(-gamma * sq) if kernel == "gaussian" else np.exp(-gamma * np.sqrt(sq))
+        A = 0.5 * (K + K.T) + phi * np.eye(n)
+        b = rng.standard_normal(n)
+    else:
+        import torch
+
+        gen = torch.Generator(device=device)
+        gen.manual_seed(int(seed))
+        F = torch.randn((n, d), dtype=torch.float64, device=device, generator=gen)
+        nrm = (F * F).sum(1)
+        sq = torch.clamp(nrm[:, None] + nrm[None, :] - 2.0 * (F @ F.T), min=0.0)
+        sq.fill_diagonal_(0.0)
+        K = torch.exp(-gamma * sq) if kernel == "gaussian" else torch.exp(-gamma * torch.sqrt(sq))
+        del sq
+        A = (0.5 * (K + K.T)).contiguous()
+        del K
+        A.diagonal().add_(phi)
+        b = torch.randn(n, dtype=torch.float64, device=device, generator=gen)
+    return System(A=A, b=b, xstar=None, kind="psd", name=f"{kernel}_g{gamma:g}_n{n}", spectrum=np.zeros(0),
+                  params=dict(n=n, d=d, gamma=gamma, phi=phi, seed=seed))
 
 
 # ----------------------------------------------------------------------------

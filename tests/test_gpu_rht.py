@@ -332,3 +332,33 @@ def test_rht_solve_rejects_resume_and_server(env):
     finally:
         kpp.kpp_server_destroy(srv)
         kpp.kpp_system_destroy(h)
+
+
+def test_rht_flops_follow_the_paper_count(env):
+    """kpp_result.flops with rht = 1: the per-step and per-factor counts of
+    the transformed system plus the transform's additions as the paper counts
+    them -- SymFHT of A (the oracle's counted additions) and FHT of b when the
+    solve forms the transformed system, FHTs of the iterate in and out always."""
+    kpp, torch, dev, ctx = env
+    n, s, T = 100, 16, 50
+    R = 128
+    sysm = synth.tiny_system("psd", n, n, seed=4)
+    Ad = torch.from_numpy(sysm.A).to(dev)
+    bd = torch.from_numpy(sysm.b).to(dev)
+    ck, p = _params(kpp, "psd", s, 1e-8, T, "online", 5, 6)
+    h = kpp.kpp_system_create(ctx, ck, n, n, Ad.data_ptr(), n, bd.data_ptr())
+    try:
+        xd = torch.zeros(n, dtype=torch.float64, device=dev)
+        _, r1 = kpp.kpp_solve(h, p, xd.data_ptr())
+        xd.zero_()
+        _, r2 = kpp.kpp_solve(h, p, xd.data_ptr())
+    finally:
+        kpp.kpp_system_destroy(h)
+    ops = orht.OpCount()
+    orht.symfht(np.zeros((R, R)), ops)
+    vec = R * math.log2(R)
+    per_step = 2.0 * s * R + 2.0 * s * s + 5.0 * R
+    for r, first in ((r1, True), (r2, False)):
+        base = r.iters * per_step + r.memo_misses * s ** 3 / 3.0 + 2.0 * vec
+        want = base + (ops.adds + vec if first else 0.0)
+        assert r.flops == pytest.approx(want, rel=1e-12)
