@@ -12,7 +12,9 @@ Contents
              update, adaptive rho, the solver loop, FP64 iterative refinement
   rht      : randomized Hadamard preprocessing (Definition d:rht; FHT,
              Algorithm 4; SymFHT, Algorithm 3) and the solvers with it
+  lsqr     : the sketch-preconditioned LSQR projection of Kaczmarz++
+             (Section 4.1; Proj of Algorithm 5)
 """
-from . import schedule, kpp, rht  # noqa: F401
+from . import schedule, kpp, rht, lsqr  # noqa: F401
 from .kpp import Params, Result, solve  # noqa: F401
 from .schedule import Schedule, SplitMix64, make_schedule, online_rate  # noqa: F401

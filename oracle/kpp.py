@@ -178,11 +178,15 @@ class Result:
 
 
 def solve(A: np.ndarray, b: np.ndarray, kind: str, params: Params, schedule: Schedule,
-          x0: Optional[np.ndarray] = None, snapshot_steps=(), record_checkpoint_x=False) -> Result:
+          x0: Optional[np.ndarray] = None, snapshot_steps=(), record_checkpoint_x=False,
+          proj=None) -> Result:
     """Kaczmarz++ (Algorithm 5, exact projection) or CD++ (Algorithm 2, no RHT).
 
     `snapshot_steps`: step counts t at which x_t (the iterate after t steps)
-    is stored in Result.snapshots.
+    is stored in Result.snapshots.  `proj`: another projection for
+    Kaczmarz++ (an object with factor(A, S), direction(A, S, F, r),
+    factor_flops(sb, n) and step_flops(sb, n); the inexact Proj of Algorithm 5
+    in oracle/lsqr.py); None is the exact memoized Cholesky projection.
     """
     A = np.asarray(A, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
@@ -224,15 +228,23 @@ def solve(A: np.ndarray, b: np.ndarray, kind: str, params: Params, schedule: Sch
             L = factors[bid]
             hits += 1
         else:
-            L = cholesky_lower(regularized_gram(A, S, params.lam, kind, reverse=rev))
+            if proj is not None:
+                L = proj.factor(A, S)
+                flops += proj.factor_flops(sb, n)
+            else:
+                L = cholesky_lower(regularized_gram(A, S, params.lam, kind, reverse=rev))
+                flops += sb ** 3 / 3.0 + (sb * sb * n if kind != "psd" else 0.0)
             nfact += 1
-            flops += sb ** 3 / 3.0 + (sb * sb * n if kind != "psd" else 0.0)
             if params.memo:
                 factors[bid] = L
-        y = projection_solve(L, r)
-        w = direction(A, S, y, kind, reverse=rev)
+        if proj is not None:
+            w = proj.direction(A, S, L, r)
+            flops += proj.step_flops(sb, n)
+        else:
+            y = projection_solve(L, r)
+            w = direction(A, S, y, kind, reverse=rev)
+            flops += 2.0 * sb * n + 2.0 * sb * sb + (2.0 * sb * n if kind != "psd" else 0.0) + 5.0 * n
         x, mom = momentum_update(x, mom, w, rho, eta)
-        flops += 2.0 * sb * n + 2.0 * sb * sb + (2.0 * sb * n if kind != "psd" else 0.0) + 5.0 * n
         if t + 1 in snap_set:
             snaps[t + 1] = x.copy()
         rr = float(r @ r)
