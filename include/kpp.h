@@ -45,7 +45,7 @@ extern "C" {
 #endif
 
 #define KPP_API __attribute__((visibility("default")))
-#define KPP_ABI_VERSION 2
+#define KPP_ABI_VERSION 3
 
 typedef enum kpp_status {
   KPP_OK = 0,
@@ -137,6 +137,23 @@ typedef struct kpp_params {
   int32_t rht;
   int32_t reserved2;
   uint64_t rht_seed;
+  /* Kaczmarz++ projection (Section 4.1).  0: exact, w = A_S^T (A_S A_S^T +
+   * lambda I)^{-1} r through the memoized Cholesky factor.  1: the inexact
+   * Proj of Algorithm 5: on a new block the SRHT sketch A_hat = A_S Pi^T with
+   * tau rows (Lemma l:inner; n padded to a power of two N) and
+   * L = chol(A_hat A_hat^T + lambda I) are formed and L^{-1} memoized; each
+   * step runs lsqr_iters LSQR iterations from zero on
+   * min || L^{-1} [A_S, sqrt(lambda) I] z - L^{-1} r || and takes w = z[0:n].
+   * The sketch draws come from SplitMix64(sketch_seed): N signs, then tau
+   * sketch rows per new block in step order.  Kaczmarz++, FP64, kpp_solve,
+   * launch-per-phase engine (engine 0 or 1) only; resume and an explicit
+   * engine 2 are rejected (KPP_ERR_INVALID_ARG), and the factors are not kept
+   * for a later solve. */
+  int32_t projection;
+  int32_t lsqr_iters;         /* t_max, 1..256 (default 8, Appendix F.1)              */
+  int32_t sketch_size;        /* tau; 0: 2 s (Section 6.2), capped at N               */
+  int32_t reserved3;
+  uint64_t sketch_seed;
 } kpp_params;
 
 /* Per-solve report. */
@@ -157,7 +174,9 @@ typedef struct kpp_result {
   double flops;               /* 2sn (+2sn K++) + 2s^2 + 5n per step; s^3/3 (+s^2 n) per factor;
                                  with rht: the transform's additions as the paper counts
                                  them (SymFHT or FHT of A and FHT of b when the solve
-                                 formed them; CD++ also FHTs of the iterate in and out) */
+                                 formed them; CD++ also FHTs of the iterate in and out);
+                                 projection 1: per step 4sn + 5n + s^2 + t_max (4sn + 2n
+                                 + 4s^2), per factor s N log2 N + s^2 tau + 2 s^3 / 3 */
   double bytes_algorithmic;   /* per step: s n b_A (A_S) + s(s+1)/2 * 8 (factor) + 12 s (b_S, rows) */
   double kernel_seconds;      /* device time of the step kernels (HIP events), all launches */
   double kernel_launches;     /* number of step-kernel launches (fused: one per window)  */

@@ -40,6 +40,9 @@ KPP_ENGINE_AUTO = 0
 KPP_ENGINE_LAUNCH = 1
 KPP_ENGINE_FUSED = 2
 
+KPP_PROJ_EXACT = 0
+KPP_PROJ_LSQR = 1
+
 _STATUS_NAMES = {v: k for k, v in globals().items() if k.startswith(("KPP_OK", "KPP_NOT", "KPP_ERR"))}
 
 
@@ -72,6 +75,11 @@ class kpp_params(ctypes.Structure):
         ("rht", ctypes.c_int32),
         ("reserved2", ctypes.c_int32),
         ("rht_seed", ctypes.c_uint64),
+        ("projection", ctypes.c_int32),
+        ("lsqr_iters", ctypes.c_int32),
+        ("sketch_size", ctypes.c_int32),
+        ("reserved3", ctypes.c_int32),
+        ("sketch_seed", ctypes.c_uint64),
     ]
 
 

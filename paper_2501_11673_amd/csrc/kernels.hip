@@ -14,6 +14,7 @@
 #include <cmath>
 
 #include "kernels.hpp"
+#include "lsqr.hpp"
 
 namespace kpp {
 namespace {
@@ -379,7 +380,7 @@ __global__ void k_state_init(DevState* ds, double rho0, double thr) {
 // (leading dimension sb + 1 against bank conflicts), larger ones in the
 // slot's scratch third.  One workgroup per slot.
 // --------------------------------------------------------------------------
-template <bool IN_LDS>
+template <bool IN_LDS, bool LINV = false>
 __global__ __launch_bounds__(kT) void k_factor_inverse(double* __restrict__ slots, int64_t stride,
                                                        int32_t s, const int32_t* __restrict__ lens,
                                                        const int32_t* __restrict__ slot_of,
@@ -425,6 +426,14 @@ __global__ __launch_bounds__(kT) void k_factor_inverse(double* __restrict__ slot
     if (threadIdx.x == 0) M[static_cast<int64_t>(j) * ld + j] = d;
   }
   __syncthreads();
+  if constexpr (LINV) {
+    // keep L^{-1} itself, column-major (entry (i, k) at k * s + i), zero above the diagonal
+    for (int e = threadIdx.x; e < sb * sb; e += kT) {
+      const int k = e / sb, i = e - k * sb;
+      Gi[static_cast<int64_t>(k) * s + i] = (i >= k) ? M[static_cast<int64_t>(k) * ld + i] : 0.0;
+    }
+    return;
+  }
   // G^{-1} = M^T M; thread owns column k, entries i >= k, mirrored to (k, i)
   for (int k = threadIdx.x; k < sb; k += kT) {
     for (int i = k; i < sb; ++i) {
@@ -1084,6 +1093,26 @@ void launch_factor_inverse(double* slots, int64_t stride, int32_t s, const int32
     hipLaunchKernelGGL(k_factor_inverse<true>, dim3(nb), dim3(kT), lds, st, slots, stride, s, lens, slot_of, chk, skip);
   } else {
     hipLaunchKernelGGL(k_factor_inverse<false>, dim3(nb), dim3(kT), 0, st, slots, stride, s, lens, slot_of, chk, skip);
+  }
+}
+
+void launch_factor_linv(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
+                        const int32_t* slot_of, hipStream_t st) {
+  if (nb <= 0) return;
+  if (s <= kLdsCholMax) {
+    const size_t lds = (static_cast<size_t>(s) * (s + 1) + s) * sizeof(double);
+    static bool attr_set = false;
+    if (!attr_set) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_factor_inverse<true, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                static_cast<int>((kLdsCholMax * (kLdsCholMax + 1) + kLdsCholMax) * sizeof(double)));
+      attr_set = true;
+    }
+    hipLaunchKernelGGL((k_factor_inverse<true, true>), dim3(nb), dim3(kT), lds, st, slots, stride, s, lens, slot_of,
+                       FactorCheck(), nullptr);
+  } else {
+    hipLaunchKernelGGL((k_factor_inverse<false, true>), dim3(nb), dim3(kT), 0, st, slots, stride, s, lens, slot_of,
+                       FactorCheck(), nullptr);
   }
 }
 

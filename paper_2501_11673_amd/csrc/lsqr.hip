@@ -1,0 +1,226 @@
+// Sketch-preconditioned LSQR projection of Kaczmarz++ (Section 4.1; the Proj
+// routine of Algorithm 5), carried in the s coordinates described in
+// lsqr.hpp.  LSQR is Paige and Saunders' algorithm (Golub-Kahan
+// bidiagonalization with one plane rotation per iteration).  The s-sized work
+// runs in one workgroup; the two products with A_S per iteration run across
+// the device (k_lsqr_at here, the block gemv of the exact path for A_S p).
+#include "lsqr.hpp"
+
+namespace kpp {
+namespace {
+
+constexpr int kL = 256;   // threads per workgroup
+
+// sum over the workgroup, in every thread (fixed order: deterministic)
+__device__ double wg_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < kL / 64; ++i) t += red[i];
+  return t;
+}
+
+__global__ __launch_bounds__(kL) void k_sketch_gather(const double* __restrict__ A, int64_t lda, int64_t n,
+                                                      const int32_t* __restrict__ rows, int32_t sb, int32_t s,
+                                                      double* __restrict__ Xt) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kL + threadIdx.x;
+  if (j >= n) return;
+  for (int i = 0; i < s; ++i) Xt[j * s + i] = i < sb ? A[static_cast<int64_t>(rows[i]) * lda + j] : 0.0;
+}
+
+__global__ __launch_bounds__(kL) void k_sketch_select(const double* __restrict__ Y, int32_t s,
+                                                      const int32_t* __restrict__ T, int32_t tau, int32_t sb,
+                                                      double scale, double* __restrict__ Ahat) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kL + threadIdx.x;
+  if (e >= static_cast<int64_t>(s) * tau) return;
+  const int i = static_cast<int>(e / tau), k = static_cast<int>(e % tau);
+  Ahat[e] = i < sb ? scale * Y[static_cast<int64_t>(T[k]) * s + i] : 0.0;
+}
+
+__global__ __launch_bounds__(kL) void k_lsqr_start(const double* __restrict__ y, const double* __restrict__ Li,
+                                                   int32_t s, int32_t sb, LsqrState* __restrict__ L) {
+  __shared__ double red[kL / 64];
+  __shared__ double u[kMaxBlock];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < sb; i += kL) acc = fma(y[i], y[i], acc);
+  const double beta = sqrt(wg_sum(acc, red));
+  for (int i = threadIdx.x; i < sb; i += kL) {
+    L->zx[i] = 0.0;
+    u[i] = beta > 0.0 ? y[i] / beta : 0.0;
+    L->u[i] = u[i];
+  }
+  __syncthreads();
+  // z~ = L^{-T} u: entry i is sum_k L^{-1}(k, i) u_k, L^{-1}(k, i) at i s + k
+  for (int i = threadIdx.x; i < sb; i += kL) {
+    double a = 0.0;
+    for (int k = i; k < sb; ++k) a = fma(Li[static_cast<int64_t>(i) * s + k], u[k], a);
+    L->zt[i] = a;
+  }
+  if (threadIdx.x == 0) {
+    L->beta = beta;
+    L->phibar = beta;
+    L->live = beta > 0.0 ? 1 : 0;
+  }
+}
+
+__global__ __launch_bounds__(kL) void k_lsqr_at(const double* __restrict__ A, int64_t lda, int64_t n,
+                                                const int32_t* __restrict__ rows, int32_t sb,
+                                                const LsqrState* __restrict__ L, double* __restrict__ p,
+                                                double* __restrict__ partsq) {
+  __shared__ double red[kL / 64];
+  __shared__ double z[kMaxBlock];
+  __shared__ int32_t rw[kMaxBlock];
+  if (!L->live) return;   // uniform over the grid
+  for (int i = threadIdx.x; i < sb; i += kL) {
+    z[i] = L->zt[i];
+    rw[i] = rows[i];
+  }
+  __syncthreads();
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kL + threadIdx.x;
+  double acc = 0.0;
+  if (j < n) {
+    for (int i = 0; i < sb; ++i) acc = fma(A[static_cast<int64_t>(rw[i]) * lda + j], z[i], acc);
+    p[j] = acc;
+  }
+  const double sq = wg_sum(acc * acc, red);
+  if (threadIdx.x == 0) partsq[blockIdx.x] = sq;
+}
+
+__global__ __launch_bounds__(kL) void k_lsqr_post(const double* __restrict__ partsq, int32_t ngroups, int32_t sb,
+                                                  double lambda, int32_t first, LsqrState* __restrict__ L) {
+  __shared__ double red[kL / 64];
+  __shared__ double sh[4];
+  if (!L->live) return;
+  double zz = 0.0;
+  for (int i = threadIdx.x; i < sb; i += kL) zz = fma(L->zt[i], L->zt[i], zz);
+  zz = wg_sum(zz, red);
+  if (threadIdx.x == 0) {
+    double pp = 0.0;
+    for (int g = 0; g < ngroups; ++g) pp += partsq[g];
+    const double alpha = sqrt(pp + lambda * zz);
+    double coef_x = 0.0, coef_w = 0.0;
+    int live = 1;
+    if (first) {
+      if (!(alpha > 0.0)) live = 0;
+      L->rhobar = alpha;
+    } else {
+      const double rho = hypot(L->rhobar, L->beta);
+      if (rho == 0.0) {
+        live = 0;
+      } else {
+        const double c = L->rhobar / rho, sn = L->beta / rho;
+        const double theta = sn * alpha;
+        L->rhobar = -c * alpha;
+        const double phi = c * L->phibar;
+        L->phibar = sn * L->phibar;
+        coef_x = phi / rho;
+        coef_w = theta / rho;
+      }
+    }
+    L->alpha = alpha;
+    L->pscale = alpha > 0.0 ? 1.0 / alpha : 0.0;
+    sh[0] = alpha;
+    sh[1] = coef_x;
+    sh[2] = coef_w;
+    sh[3] = live;
+  }
+  __syncthreads();
+  const double alpha = sh[0], coef_x = sh[1], coef_w = sh[2];
+  const bool live = sh[3] != 0.0;
+  if (!live) {
+    if (threadIdx.x == 0) L->live = 0;
+    return;
+  }
+  for (int i = threadIdx.x; i < sb; i += kL) {
+    const double v = alpha > 0.0 ? L->zt[i] / alpha : L->zt[i];
+    if (first) {
+      L->zw[i] = v;
+    } else {
+      // x <- x + (phi / rho) w with the old w, then w <- v - (theta / rho) w
+      const double w = L->zw[i];
+      L->zx[i] = fma(coef_x, w, L->zx[i]);
+      L->zw[i] = v - coef_w * w;
+    }
+    L->zv[i] = v;
+  }
+}
+
+__global__ __launch_bounds__(kL) void k_lsqr_mid(const double* __restrict__ rpart, int32_t P,
+                                                 const double* __restrict__ Li, int32_t s, int32_t sb, double lambda,
+                                                 LsqrState* __restrict__ L) {
+  __shared__ double red[kL / 64];
+  __shared__ double t[kMaxBlock];
+  __shared__ double u[kMaxBlock];
+  if (!L->live) return;
+  const double pscale = L->pscale, alpha = L->alpha;
+  for (int i = threadIdx.x; i < sb; i += kL) {
+    double q = 0.0;
+    for (int k = 0; k < P; ++k) q += rpart[static_cast<int64_t>(i) * P + k];
+    t[i] = fma(lambda, L->zv[i], q * pscale);
+  }
+  __syncthreads();
+  // u~ = L^{-1} t - alpha u
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < sb; i += kL) {
+    double a = 0.0;
+    for (int k = 0; k <= i; ++k) a = fma(Li[static_cast<int64_t>(k) * s + i], t[k], a);
+    const double ui = a - alpha * L->u[i];
+    u[i] = ui;
+    acc = fma(ui, ui, acc);
+  }
+  const double beta = sqrt(wg_sum(acc, red));
+  for (int i = threadIdx.x; i < sb; i += kL) {
+    if (beta > 0.0) u[i] /= beta;
+    L->u[i] = u[i];
+  }
+  __syncthreads();
+  // z~ = L^{-T} u - beta v
+  for (int i = threadIdx.x; i < sb; i += kL) {
+    double a = 0.0;
+    for (int k = i; k < sb; ++k) a = fma(Li[static_cast<int64_t>(i) * s + k], u[k], a);
+    L->zt[i] = a - beta * L->zv[i];
+  }
+  if (threadIdx.x == 0) L->beta = beta;
+}
+
+}  // namespace
+
+void launch_sketch_gather(const double* A, int64_t lda, int64_t n, const int32_t* rows, int32_t sb, int32_t s,
+                          double* Xt, hipStream_t st) {
+  hipLaunchKernelGGL(k_sketch_gather, dim3(static_cast<unsigned>((n + kL - 1) / kL)), dim3(kL), 0, st, A, lda, n,
+                     rows, sb, s, Xt);
+}
+
+void launch_sketch_select(const double* Y, int32_t s, const int32_t* T, int32_t tau, int32_t sb, double scale,
+                          double* Ahat, hipStream_t st) {
+  const int64_t total = static_cast<int64_t>(s) * tau;
+  hipLaunchKernelGGL(k_sketch_select, dim3(static_cast<unsigned>((total + kL - 1) / kL)), dim3(kL), 0, st, Y, s, T,
+                     tau, sb, scale, Ahat);
+}
+
+void launch_lsqr_start(const double* y, const double* Linv, int32_t s, int32_t sb, LsqrState* L, hipStream_t st) {
+  hipLaunchKernelGGL(k_lsqr_start, dim3(1), dim3(kL), 0, st, y, Linv, s, sb, L);
+}
+
+int32_t lsqr_at_groups(int64_t n) { return static_cast<int32_t>((n + kL - 1) / kL); }
+
+void launch_lsqr_at(const double* A, int64_t lda, int64_t n, const int32_t* rows, int32_t sb, const LsqrState* L,
+                    double* p, double* partsq, hipStream_t st) {
+  hipLaunchKernelGGL(k_lsqr_at, dim3(static_cast<unsigned>(lsqr_at_groups(n))), dim3(kL), 0, st, A, lda, n, rows,
+                     sb, L, p, partsq);
+}
+
+void launch_lsqr_post(const double* partsq, int32_t ngroups, int32_t sb, double lambda, int32_t first, LsqrState* L,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_lsqr_post, dim3(1), dim3(kL), 0, st, partsq, ngroups, sb, lambda, first, L);
+}
+
+void launch_lsqr_mid(const double* rpart, int32_t P, const double* Linv, int32_t s, int32_t sb, double lambda,
+                     LsqrState* L, hipStream_t st) {
+  hipLaunchKernelGGL(k_lsqr_mid, dim3(1), dim3(kL), 0, st, rpart, P, Linv, s, sb, lambda, L);
+}
+
+}  // namespace kpp

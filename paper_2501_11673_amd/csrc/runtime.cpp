@@ -10,18 +10,22 @@
 #include <functional>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
 #include <new>
+#include <numeric>
 #include <stdexcept>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "kernels.hpp"
+#include "lsqr.hpp"
 #include "kpp.h"
 #include "schedule.hpp"
 
@@ -151,6 +155,22 @@ struct kpp_system {
   double* rht_work = nullptr;   // two-pass transforms (R > 4096)
   int64_t rht_R = 0;
   uint64_t rht_seed = 0;
+  // LSQR projection (params.projection = 1): per-step state, p = A_S^T z, the
+  // partial norms, the sketch's staging and signs, and the sketch rows of the
+  // new blocks of each staging buffer
+  kpp::LsqrState* lsqr_state = nullptr;
+  double* lsqr_p = nullptr;
+  double* lsqr_part = nullptr;
+  double* lsqr_Xt = nullptr;
+  double* lsqr_Y = nullptr;
+  double* lsqr_Ahat = nullptr;
+  int32_t* lsqr_iota = nullptr;
+  int8_t* lsqr_signs = nullptr;
+  int32_t* lsqr_T[2] = {nullptr, nullptr};
+  size_t lsqr_T_cap[2] = {0, 0};
+  int64_t lsqr_cap_n = 0, lsqr_cap_N = 0;
+  int32_t lsqr_cap_s = 0, lsqr_cap_tau = 0;
+  int32_t sig_proj = 0;
 };
 
 namespace {
@@ -168,8 +188,26 @@ void drop_rht(kpp_system* s) {
   s->rht_R = 0;
 }
 
+void drop_lsqr(kpp_system* s) {
+  dev_free(s->lsqr_state);
+  dev_free(s->lsqr_p);
+  dev_free(s->lsqr_part);
+  dev_free(s->lsqr_Xt);
+  dev_free(s->lsqr_Y);
+  dev_free(s->lsqr_Ahat);
+  dev_free(s->lsqr_iota);
+  dev_free(s->lsqr_signs);
+  for (int i = 0; i < 2; ++i) {
+    dev_free(s->lsqr_T[i]);
+    s->lsqr_T_cap[i] = 0;
+  }
+  s->lsqr_cap_n = s->lsqr_cap_N = 0;
+  s->lsqr_cap_s = s->lsqr_cap_tau = 0;
+}
+
 void destroy_buffers(kpp_system* s) {
   drop_rht(s);
+  drop_lsqr(s);
   dev_free(s->mom);
   dev_free(s->ds);
   dev_free(s->rpart);
@@ -333,6 +371,18 @@ kpp_status check_params(const kpp_system* sys, const kpp_params* p) {
     return fail(KPP_ERR_INVALID_ARG, "team_groups must be in [0, %d]", kpp::kFusedMaxGroups);
   if (p->resume && p->precision != KPP_FP64) return fail(KPP_ERR_INVALID_ARG, "resume runs in FP64 only");
   if (p->rht != 0 && p->rht != 1) return fail(KPP_ERR_INVALID_ARG, "rht must be 0 or 1");
+  if (p->projection != 0 && p->projection != 1) return fail(KPP_ERR_INVALID_ARG, "projection must be 0 or 1");
+  if (p->projection == 1) {
+    if (sys->kind != KPP_KACZMARZ) return fail(KPP_ERR_INVALID_ARG, "the LSQR projection is for Kaczmarz++");
+    if (p->precision != KPP_FP64) return fail(KPP_ERR_INVALID_ARG, "the LSQR projection runs in FP64 only");
+    if (p->engine == 2) return fail(KPP_ERR_INVALID_ARG, "the LSQR projection runs on the launch-per-phase engine");
+    if (p->resume) return fail(KPP_ERR_INVALID_ARG, "resume does not combine with the LSQR projection");
+    if (p->lsqr_iters < 1 || p->lsqr_iters > 256) return fail(KPP_ERR_INVALID_ARG, "lsqr_iters must be in [1, 256]");
+    if (p->sketch_size < 0) return fail(KPP_ERR_INVALID_ARG, "sketch_size must be >= 0");
+    int64_t N = 1;
+    while (N < sys->n) N <<= 1;
+    if (N > kpp::kFhtMaxRows) return fail(KPP_ERR_SHAPE, "n is too large for the sketch's Hadamard transform");
+  }
   if (p->rht && p->resume) return fail(KPP_ERR_INVALID_ARG, "resume does not combine with rht");
   if (p->schedule) {
     if (p->schedule_len < 0) return fail(KPP_ERR_INVALID_ARG, "schedule_len must be >= 0");
@@ -519,6 +569,11 @@ class CoreRun {
       if (p->engine == 2 && !fused_)
         return fail(KPP_ERR_INVALID_ARG, "n=%lld is too wide for the fused engine", (long long)n_);
     }
+    lsqr_ = p->projection == 1;
+    if (lsqr_) {
+      fused_ = false;
+      KPP_TRY(setup_lsqr(p));
+    }
     dual_ = o.zx != nullptr && o.zm != nullptr && kind_ == KPP_KACZMARZ && fused_ && groups_ > 0 &&
             (m_ + groups_ - 1) / groups_ <= kDualRowsPerGroup;
     // memo cache: reuse only for an identical schedule definition.  The slot
@@ -542,7 +597,7 @@ class CoreRun {
                           sys->sig_nb == p->num_blocks && sys->sig_part == p->fixed_partition &&
                           sys->sig_seed == p->seed && sys->sig_lambda == p->lambda &&
                           sys->sig_prec == (fp32_ ? 1 : 0) && mode_ != kpp::MemoMode::Off &&
-                          !sch_->is_explicit() && !sys->sig_explicit;
+                          !sch_->is_explicit() && !sys->sig_explicit && !lsqr_ && sys->sig_proj == 0;
     if (!same_sig) {
       sys->slot_of_block.clear();
       sys->used_slots = 0;
@@ -555,6 +610,7 @@ class CoreRun {
       sys->sig_lambda = p->lambda;
       sys->sig_prec = fp32_ ? 1 : 0;
       sys->sig_explicit = sch_->is_explicit();
+      sys->sig_proj = lsqr_ ? 1 : 0;
     }
     // launch engine: column chunks of the block gemv
     P_ = static_cast<int32_t>((n_ + kChunk - 1) / kChunk);
@@ -674,6 +730,7 @@ class CoreRun {
   kpp_status launch_unfused() {
     Window& w = win_[cur_];
     const size_t sd = static_cast<size_t>(sys_->slot_stride);
+    if (lsqr_) return launch_lsqr_steps();
     for (int64_t k = w.done; k < w.W; ++k) {
       const int32_t q = w.step_slot[k];
       const int32_t sb = sch_->len(w.step_block[k]);
@@ -684,6 +741,40 @@ class CoreRun {
       kpp::launch_update(kind_, src_.A64, src_.lda, n_, rows, sb, sys_->y, sys_->ds, eta_, x_, sys_->mom, st_);
     }
     launches_ += 3 * (w.W - w.done);
+    HIP_TRY(hipGetLastError());
+    return KPP_OK;
+  }
+
+  // Steps with the LSQR projection: r and y = L^{-1} r (the projection kernel
+  // with L^{-1} in place of G^{-1}: it also keeps the window sums), LSQR in the
+  // block's coordinates, then the update with w = A_S^T z_x.
+  kpp_status launch_lsqr_steps() {
+    Window& w = win_[cur_];
+    kpp_system* sys = sys_;
+    const size_t sd = static_cast<size_t>(sys->slot_stride);
+    const int32_t G = kpp::lsqr_at_groups(n_);
+    kpp::LsqrState* L = sys->lsqr_state;
+    const double* zx = reinterpret_cast<const double*>(reinterpret_cast<const char*>(L) + offsetof(kpp::LsqrState, zx));
+    for (int64_t k = w.done; k < w.W; ++k) {
+      const int32_t q = w.step_slot[k];
+      const int32_t sb = sch_->len(w.step_block[k]);
+      const int32_t* rows = sys->rows + static_cast<size_t>(q) * s_;
+      const double* Li = sys->L + sd * q + static_cast<size_t>(s_) * s_;
+      kpp::launch_block_gemv_partial(src_.A64, src_.lda, n_, rows, sb, x_, sys->rpart, P_, kChunk, st_);
+      kpp::launch_block_project(sys->rpart, P_, src_.b, rows, sb, Li, s_, sys->y, sys->ds, zeta_, prm_.adaptive_rho,
+                                st_);
+      kpp::launch_lsqr_start(sys->y, Li, s_, sb, L, st_);
+      kpp::launch_lsqr_at(src_.A64, src_.lda, n_, rows, sb, L, sys->lsqr_p, sys->lsqr_part, st_);
+      kpp::launch_lsqr_post(sys->lsqr_part, G, sb, prm_.lambda, 1, L, st_);
+      for (int32_t it = 0; it < lsqr_iters_; ++it) {
+        kpp::launch_block_gemv_partial(src_.A64, src_.lda, n_, rows, sb, sys->lsqr_p, sys->rpart, P_, kChunk, st_);
+        kpp::launch_lsqr_mid(sys->rpart, P_, Li, s_, sb, prm_.lambda, L, st_);
+        kpp::launch_lsqr_at(src_.A64, src_.lda, n_, rows, sb, L, sys->lsqr_p, sys->lsqr_part, st_);
+        kpp::launch_lsqr_post(sys->lsqr_part, G, sb, prm_.lambda, 0, L, st_);
+      }
+      kpp::launch_update(kind_, src_.A64, src_.lda, n_, rows, sb, zx, sys->ds, eta_, x_, sys->mom, st_);
+    }
+    launches_ += (6 + 4 * lsqr_iters_) * (w.W - w.done);
     HIP_TRY(hipGetLastError());
     return KPP_OK;
   }
@@ -913,6 +1004,65 @@ class CoreRun {
       stage[w.o_slot + k] = pending_slots[k];
     }
     std::copy(w.step_slot.begin(), w.step_slot.end(), stage + w.o_step);
+    if (lsqr_) {
+      // the sketch rows of the new blocks, in step order
+      auto& T = lsqr_T_host_[idx];
+      T.resize(static_cast<size_t>(w.nb) * tau_);
+      for (int32_t k = 0; k < w.nb; ++k) draw_sketch_rows(T.data() + static_cast<size_t>(k) * tau_);
+    }
+    return KPP_OK;
+  }
+
+  // tau of the Nsk padded columns: the sorted first tau entries of a partial
+  // Fisher-Yates shuffle of 0..Nsk-1 (the schedule's subset draw)
+  void draw_sketch_rows(int32_t* out) {
+    std::unordered_map<int64_t, int64_t> moved;
+    auto at = [&](int64_t i) {
+      auto it = moved.find(i);
+      return it == moved.end() ? i : it->second;
+    };
+    for (int32_t j = 0; j < tau_; ++j) {
+      const int64_t k = j + static_cast<int64_t>(sk_gen_.bounded(static_cast<uint64_t>(Nsk_ - j)));
+      const int64_t vj = at(j), vk = at(k);
+      moved[j] = vk;
+      moved[k] = vj;
+      out[j] = static_cast<int32_t>(vk);
+    }
+    std::sort(out, out + tau_);
+  }
+
+  kpp_status setup_lsqr(const kpp_params* p) {
+    kpp_system* sys = sys_;
+    Nsk_ = 1;
+    while (Nsk_ < n_) Nsk_ <<= 1;
+    tau_ = static_cast<int32_t>(std::min<int64_t>(p->sketch_size > 0 ? p->sketch_size : 2 * static_cast<int64_t>(s_), Nsk_));
+    lsqr_iters_ = p->lsqr_iters;
+    sk_gen_ = kpp::SplitMix64(p->sketch_seed);
+    if (sys->lsqr_cap_n < n_ || sys->lsqr_cap_N < Nsk_ || sys->lsqr_cap_s < s_ || sys->lsqr_cap_tau < tau_) {
+      HIP_TRY(hipStreamSynchronize(st_));
+      HIP_TRY(hipStreamSynchronize(side_));
+      drop_lsqr(sys);
+      kpp_status stt;
+      const int32_t groups = kpp::lsqr_at_groups(n_);
+      if ((stt = dev_alloc(&sys->lsqr_state, 1)) < 0 || (stt = dev_alloc(&sys->lsqr_p, n_)) < 0 ||
+          (stt = dev_alloc(&sys->lsqr_part, groups)) < 0 || (stt = dev_alloc(&sys->lsqr_Xt, n_ * s_)) < 0 ||
+          (stt = dev_alloc(&sys->lsqr_Y, Nsk_ * s_)) < 0 ||
+          (stt = dev_alloc(&sys->lsqr_Ahat, static_cast<int64_t>(s_) * tau_)) < 0 ||
+          (stt = dev_alloc(&sys->lsqr_iota, s_)) < 0 || (stt = dev_alloc(&sys->lsqr_signs, Nsk_)) < 0) {
+        drop_lsqr(sys);
+        return stt;
+      }
+      sys->lsqr_cap_n = n_;
+      sys->lsqr_cap_N = Nsk_;
+      sys->lsqr_cap_s = s_;
+      sys->lsqr_cap_tau = tau_;
+    }
+    std::vector<int32_t> iota(static_cast<size_t>(s_));
+    std::iota(iota.begin(), iota.end(), 0);
+    std::vector<int8_t> sg(static_cast<size_t>(Nsk_));
+    for (auto& v : sg) v = (sk_gen_.next() >> 63) ? int8_t{-1} : int8_t{1};
+    HIP_TRY(hipMemcpy(sys->lsqr_iota, iota.data(), iota.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(sys->lsqr_signs, sg.data(), sg.size(), hipMemcpyHostToDevice));
     return KPP_OK;
   }
 
@@ -933,6 +1083,11 @@ class CoreRun {
       const int32_t* d_slens = sys->d_stage[idx] + w.o_len;
       const int32_t* d_sslot = sys->d_stage[idx] + w.o_slot;
       kpp::launch_scatter_rows(d_srows, d_slens, d_sslot, w.nb, s, sys->rows, sys->lens, fs);
+      if (lsqr_) {
+        KPP_TRY(enqueue_sketch_factor(w, fs));
+        HIP_TRY(hipEventRecord(sys->ev_fact[idx][1], fs));
+        return KPP_OK;
+      }
       if (kind_ == KPP_KACZMARZ) KPP_TRY(ensure_gram_ws(sys, idx, kpp::gram_syrk_work(s, n_, w.nb)));
       double* gws = sys->gram_ws[idx];
       auto factor = [&](const kpp::FactorCheck& chk, const int32_t* skip) {
@@ -970,6 +1125,55 @@ class CoreRun {
     return KPP_OK;
   }
 
+  // New blocks of the LSQR projection: the sketch A_hat = A_S Pi^T of each,
+  // then the Gram of A_hat, its Cholesky factor and L^{-1} in the block's slot.
+  kpp_status enqueue_sketch_factor(const Window& w, hipStream_t fs) {
+    kpp_system* sys = sys_;
+    const int idx = w.idx;
+    const auto& Th = lsqr_T_host_[idx];
+    const size_t nT = Th.size();
+    if (sys->lsqr_T_cap[idx] < nT) {
+      HIP_TRY(hipStreamSynchronize(fs));
+      dev_free(sys->lsqr_T[idx]);
+      sys->lsqr_T_cap[idx] = 0;
+      KPP_TRY(dev_alloc(&sys->lsqr_T[idx], nT));
+      sys->lsqr_T_cap[idx] = nT;
+    }
+    HIP_TRY(hipMemcpyAsync(sys->lsqr_T[idx], Th.data(), nT * sizeof(int32_t), hipMemcpyHostToDevice, fs));
+    KPP_TRY(ensure_gram_ws(sys, idx, kpp::gram_syrk_work(s_, tau_, 1)));
+    const int32_t* d_slens = sys->d_stage[idx] + w.o_len;
+    const int32_t* d_sslot = sys->d_stage[idx] + w.o_slot;
+    const double iscale = 1.0 / std::sqrt(static_cast<double>(Nsk_));
+    const double scale = std::sqrt(static_cast<double>(Nsk_) / static_cast<double>(tau_));
+    for (int32_t k = 0; k < w.nb; ++k) {
+      const int32_t q = sys->h_stage[idx][w.o_slot + k];
+      const int32_t sb = sys->h_stage[idx][w.o_len + k];
+      const int32_t* rows = sys->rows + static_cast<size_t>(q) * s_;
+      kpp::launch_sketch_gather(src_.A64, src_.lda, n_, rows, sb, s_, sys->lsqr_Xt, fs);
+      kpp::FhtSpec f;
+      f.in = sys->lsqr_Xt;
+      f.ld_in = s_;
+      f.rows_valid = n_;
+      f.cols_valid = s_;
+      f.isign = sys->lsqr_signs;
+      f.iscale = iscale;
+      f.out = sys->lsqr_Y;
+      f.ld_out = s_;
+      f.rows_out = Nsk_;
+      f.M = Nsk_;
+      f.ncols = s_;
+      kpp::launch_fht(f, fs);
+      kpp::launch_sketch_select(sys->lsqr_Y, s_, sys->lsqr_T[idx] + static_cast<size_t>(k) * tau_, tau_, sb, scale,
+                                sys->lsqr_Ahat, fs);
+      kpp::launch_gram(KPP_KACZMARZ, sys->lsqr_Ahat, tau_, tau_, sys->lsqr_iota, d_slens + k, s_, 1, prm_.lambda,
+                       sys->L, sys->slot_stride, d_sslot + k, sys->gram_ws[idx], fs);
+      kpp::launch_cholesky(sys->L, s_, sys->slot_stride, d_slens + k, 1, d_sslot + k, sys->err, fs);
+      kpp::launch_factor_linv(sys->L, sys->slot_stride, s_, d_slens + k, 1, d_sslot + k, fs);
+    }
+    HIP_TRY(hipGetLastError());
+    return KPP_OK;
+  }
+
   kpp_system* sys_ = nullptr;
   kpp_params prm_{};
   Source src_{};
@@ -990,6 +1194,12 @@ class CoreRun {
   double true_rel_ = NAN, t_factor_ = 0.0, t_kernel_ = 0.0;
   kpp::DevState hs_{};
   std::vector<double> e1_hist_;
+  // LSQR projection
+  bool lsqr_ = false;
+  int64_t Nsk_ = 0;
+  int32_t tau_ = 0, lsqr_iters_ = 0;
+  kpp::SplitMix64 sk_gen_{0};
+  std::vector<int32_t> lsqr_T_host_[2];
 };
 
 // A run driven on its own: one launch per window.
@@ -1049,6 +1259,15 @@ void fill_result(kpp_result* res, const kpp_system* sys, const kpp_params* p, in
   const double per_step = 2.0 * sdb * nn + 2.0 * sdb * sdb + (kind == KPP_CD_PSD ? 0.0 : 2.0 * sdb * nn) + 5.0 * nn;
   const double per_fact = sdb * sdb * sdb / 3.0 + (kind == KPP_CD_PSD ? 0.0 : sdb * sdb * nn);
   res->flops = per_step * static_cast<double>(iters) + per_fact * static_cast<double>(misses);
+  if (p->projection == 1) {
+    double Nsk = 1.0;
+    while (Nsk < nn) Nsk *= 2.0;
+    const double tau = std::min(p->sketch_size > 0 ? static_cast<double>(p->sketch_size) : 2.0 * sdb, Nsk);
+    const double t = p->lsqr_iters;
+    const double step = 4.0 * sdb * nn + 5.0 * nn + sdb * sdb + t * (4.0 * sdb * nn + 2.0 * nn + 4.0 * sdb * sdb);
+    const double fact = sdb * Nsk * std::log2(Nsk) + sdb * sdb * tau + 2.0 * sdb * sdb * sdb / 3.0;
+    res->flops = step * static_cast<double>(iters) + fact * static_cast<double>(misses);
+  }
   res->bytes_algorithmic =
       static_cast<double>(iters) * (sdb * nn * bytes_per_elem + 0.5 * sdb * (sdb + 1) * 8.0 + 12.0 * sdb);
   res->kernel_seconds = t_kernel;
@@ -2001,6 +2220,8 @@ KPP_API kpp_status kpp_params_default(kpp_params* p, int32_t kind) {
   p->inner_tol = 1e-2;
   p->engine = 0;
   p->team_groups = 0;
+  p->lsqr_iters = 8;
+  p->sketch_seed = 0x5ca7c4ull;
   return KPP_OK;
 }
 
@@ -2364,6 +2585,7 @@ KPP_API kpp_status kpp_server_submit(kpp_server* srv, kpp_system* sys, const kpp
   if (p->schedule) return fail(KPP_ERR_INVALID_ARG, "explicit schedules are for kpp_solve");
   if (p->resume) return fail(KPP_ERR_INVALID_ARG, "resume is for kpp_solve");
   if (p->rht) return fail(KPP_ERR_INVALID_ARG, "rht is for kpp_solve (submit a system transformed by kpp_rht_psd)");
+  if (p->projection) return fail(KPP_ERR_INVALID_ARG, "the LSQR projection is for kpp_solve");
   sys->res_valid = false;
   auto* r = new (std::nothrow) ServeReq;
   if (!r) return fail(KPP_ERR_OOM, "host allocation failed");

@@ -84,6 +84,23 @@ static void rht_case(int kind, int64_t m, int64_t n, int s) {
   hipFree(A); hipFree(b); hipFree(x);
 }
 
+// Kaczmarz++ with the LSQR projection (online, fixed partition, and a
+// block size above the in-LDS factor limit), and the combinations it rejects.
+static void lsqr_case(int64_t m, int64_t n, int s, int memo) {
+  kpp_context* ctx; CHECK(kpp_context_create(0, nullptr, &ctx));
+  double* A = dev_vec(m * n, 0.5); double* b = dev_vec(m, 1.0); double* x = dev_vec(n, 0.0);
+  kpp_system* sys; CHECK(kpp_system_create(ctx, KPP_KACZMARZ, m, n, A, n, b, &sys));
+  kpp_params p; CHECK(kpp_params_default(&p, KPP_KACZMARZ));
+  p.block_size = s; p.memo = memo; p.max_iters = 150; p.tol = 0.0; p.projection = 1; p.lsqr_iters = 3;
+  kpp_result r; CHECK(kpp_solve(sys, &p, x, &r));
+  std::printf("lsqr m=%lld n=%lld s=%d memo=%d iters=%lld misses=%lld\n", (long long)m, (long long)n, s, memo,
+              (long long)r.iters, (long long)r.memo_misses);
+  p.engine = 2;
+  if (kpp_solve(sys, &p, x, &r) >= 0) { std::printf("FAIL: lsqr on the fused engine\n"); std::exit(1); }
+  CHECK(kpp_system_destroy(sys)); CHECK(kpp_context_destroy(ctx));
+  hipFree(A); hipFree(b); hipFree(x);
+}
+
 static void serve_case() {
   kpp_context* ctx; CHECK(kpp_context_create(0, nullptr, &ctx));
   struct J { int kind; int64_t m, n; int s; int prec; double tol; };
@@ -142,6 +159,9 @@ int main(int argc, char** argv) {
     resume_case(0, 900, 300, 40);
     rht_case(0, 5000, 12, 16);
     rht_case(1, 100, 100, 16);
+    lsqr_case(1000, 200, 20, 1);
+    lsqr_case(700, 300, 160, 2);
+    lsqr_case(400, 5000, 64, 0);
   }
   if (!*only || !std::strcmp(only, "serve")) serve_case();
   std::printf("EMU OK\n");

@@ -10,6 +10,7 @@
 #include <mutex>
 
 #include "kernels.hpp"
+#include "lsqr.hpp"
 
 namespace kpp {
 namespace {
@@ -183,6 +184,58 @@ void launch_fht(const FhtSpec& s, hipStream_t) {
     std::fprintf(stderr, "EMU: transposed fht in place\n");
     std::abort();
   }
+}
+
+// LSQR projection: the ranges each launcher's kernels touch
+void launch_factor_linv(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
+                        const int32_t* slot_of, hipStream_t) {
+  emu_check(lens, 4 * static_cast<size_t>(nb), "linv lens");
+  emu_check(slot_of, 4 * static_cast<size_t>(nb), "linv slots");
+  for (int32_t k = 0; k < nb; ++k) {
+    if (lens[k] < 1 || lens[k] > s) { std::fprintf(stderr, "EMU: linv block length %d\n", lens[k]); std::abort(); }
+    emu_check(slots + static_cast<int64_t>(slot_of[k]) * stride, 8 * (s > 128 ? 3 : 2) * static_cast<size_t>(s) * s,
+              "linv slot");
+  }
+}
+void launch_sketch_gather(const double* A, int64_t lda, int64_t n, const int32_t* rows, int32_t sb, int32_t s,
+                          double* Xt, hipStream_t) {
+  check_rows(rows, sb, "sketch rows");
+  check_A(A, 8, lda, rows, sb, n, "sketch A");
+  emu_check(Xt, 8 * static_cast<size_t>(n) * s, "sketch Xt");
+}
+void launch_sketch_select(const double* Y, int32_t s, const int32_t* T, int32_t tau, int32_t sb, double,
+                          double* Ahat, hipStream_t) {
+  emu_check(T, 4 * static_cast<size_t>(tau), "sketch T");
+  int32_t tmax = 0;
+  for (int32_t k = 0; k < tau; ++k) tmax = std::max(tmax, T[k]);
+  emu_check(Y, 8 * (static_cast<size_t>(tmax) * s + sb), "sketch Y");
+  emu_check(Ahat, 8 * static_cast<size_t>(s) * tau, "sketch Ahat");
+}
+void launch_lsqr_start(const double* y, const double* Linv, int32_t s, int32_t sb, LsqrState* L, hipStream_t) {
+  emu_check(y, 8 * static_cast<size_t>(sb), "lsqr y");
+  emu_check(Linv, 8 * static_cast<size_t>(s) * s, "lsqr Linv");
+  emu_check(L, sizeof(LsqrState), "lsqr state");
+  L->live = 0;   // the stand-in solves nothing: later LSQR kernels are no-ops
+  for (int32_t i = 0; i < sb; ++i) L->zx[i] = 0.0;
+}
+int32_t lsqr_at_groups(int64_t n) { return static_cast<int32_t>((n + 255) / 256); }
+void launch_lsqr_at(const double* A, int64_t lda, int64_t n, const int32_t* rows, int32_t sb, const LsqrState* L,
+                    double* p, double* partsq, hipStream_t) {
+  check_rows(rows, sb, "lsqr rows");
+  check_A(A, 8, lda, rows, sb, n, "lsqr A");
+  emu_check(L, sizeof(LsqrState), "lsqr state");
+  emu_check(p, 8 * static_cast<size_t>(n), "lsqr p");
+  emu_check(partsq, 8 * static_cast<size_t>(lsqr_at_groups(n)), "lsqr partials");
+}
+void launch_lsqr_post(const double* partsq, int32_t ngroups, int32_t, double, int32_t, LsqrState* L, hipStream_t) {
+  emu_check(partsq, 8 * static_cast<size_t>(ngroups), "lsqr partials");
+  emu_check(L, sizeof(LsqrState), "lsqr state");
+}
+void launch_lsqr_mid(const double* rpart, int32_t P, const double* Linv, int32_t s, int32_t sb, double, LsqrState* L,
+                     hipStream_t) {
+  emu_check(rpart, 8 * static_cast<size_t>(sb) * P, "lsqr rpart");
+  emu_check(Linv, 8 * static_cast<size_t>(s) * s, "lsqr Linv");
+  emu_check(L, sizeof(LsqrState), "lsqr state");
 }
 
 void launch_state_init(DevState* ds, double rho0, double thr, hipStream_t) {

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(kpp):
     for name in syms:
         assert hasattr(raw, name), name
     assert set(syms) == set(kpp.EXPORTED)
-    assert kpp.kpp_abi_version() == 2
+    assert kpp.kpp_abi_version() == 3
 
 
 def test_params_default_and_validation(kpp):
@@ -73,6 +73,7 @@ def test_rht_argument_checks(kpp):
         kpp.kpp_rht_signs(1, -1)
     p = kpp.kpp_params_default(kpp.KPP_KACZMARZ)
     assert p.rht == 0 and p.rht_seed == 0
+    assert p.projection == kpp.KPP_PROJ_EXACT and p.lsqr_iters == 8 and p.sketch_size == 0
 
 
 def oracle_schedule(kind, m, n, mode, s, T, seed, num_blocks=0, partition=True):

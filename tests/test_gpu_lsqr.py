@@ -1,0 +1,143 @@
+"""GPU parity of Kaczmarz++ with the sketch-preconditioned LSQR projection
+(params.projection = 1; Section 4.1, the Proj routine of Algorithm 5) against
+the oracle (oracle/lsqr.py run inside oracle/kpp.py's solver loop) on the same
+seeded inputs, the same block schedule and the same sketch draws.
+
+The GPU carries LSQR in the block's s coordinates (every LSQR direction is
+[A_S^T z; sqrt(lambda) z]); the oracle forms M = L^{-1} [A_S, sqrt(lambda) I]
+explicitly and runs textbook LSQR on it.  Iterates after a fixed number of
+steps are compared with the FP64 noise-floor bound of the exact path,
+max(1e-10, 10 nf), nf the oracle's distance to itself with every sum of the
+solver loop reversed.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import kpp as okpp
+from oracle import lsqr as ol
+from oracle import schedule as osch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import paper_2501_11673_amd as kpp
+
+    assert torch.cuda.is_available()
+    dev = torch.device("cuda:0")
+    ctx = kpp.kpp_context_create(0, torch.cuda.current_stream(dev).cuda_stream)
+    yield kpp, torch, dev, ctx
+    kpp.kpp_context_destroy(ctx)
+
+
+def gpu_lsqr(env, A, b, s, lam, T, mode, seed, sketch_seed, iters, tau=0, tol=0.0, x0=None):
+    kpp, torch, dev, ctx = env
+    m, n = A.shape
+    p = kpp.kpp_params_default(kpp.KPP_KACZMARZ)
+    p.block_size = s
+    p.lambda_ = lam
+    p.tol = tol
+    p.max_iters = T
+    p.seed = seed
+    p.memo = {"off": 0, "online": 1, "fixed": 2}[mode]
+    p.fixed_partition = 1
+    p.projection = kpp.KPP_PROJ_LSQR
+    p.lsqr_iters = iters
+    p.sketch_size = tau
+    p.sketch_seed = sketch_seed
+    Ad = torch.from_numpy(np.ascontiguousarray(A)).to(dev)
+    bd = torch.from_numpy(np.ascontiguousarray(b)).to(dev)
+    xd = torch.zeros(n, dtype=torch.float64, device=dev) if x0 is None else torch.from_numpy(x0.copy()).to(dev)
+    h = kpp.kpp_system_create(ctx, kpp.KPP_KACZMARZ, m, n, Ad.data_ptr(), n, bd.data_ptr())
+    try:
+        st, res = kpp.kpp_solve(h, p, xd.data_ptr())
+    finally:
+        kpp.kpp_system_destroy(h)
+    return xd.cpu().numpy(), st, res
+
+
+def oracle_lsqr(A, b, s, lam, T, mode, seed, sketch_seed, iters, tau=None, tol=0.0, reverse=False, x0=None):
+    m, n = A.shape
+    schd = osch.make_schedule(mode, m, s, T, seed, B0=osch.online_rate("general", m, n, s))
+    P = ol.LsqrProj(n, s, lam, sketch_seed, tau=tau, iters=iters)
+    prm = okpp.Params(s=s, lam=lam, tol=tol, max_iters=T, memo=mode != "off", reverse_sums=reverse)
+    return okpp.solve(A, b, "general", prm, schd, proj=P, x0=x0)
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("case,m,n,s,lam,T,mode,iters,tau", [
+    ("c1_shape", 1000, 200, 20, 1e-3, 300, "online", 8, 0),        # N = 256, tau = 40
+    ("ragged_fixed", 700, 300, 64, 1e-4, 200, "fixed", 8, 0),      # 11 blocks, last of 60 rows
+    ("wide", 120, 1500, 24, 1e-4, 150, "online", 8, 0),            # N = 2048
+    ("big_block", 900, 350, 160, 1e-6, 60, "fixed", 4, 0),         # factor kernels for s > 128
+    ("one_iter_tau", 500, 100, 16, 1e-3, 200, "online", 1, 100),   # t_max = 1, tau given
+    ("memo_off", 400, 90, 12, 1e-3, 120, "off", 8, 0),
+])
+def test_lsqr_iterates_match_oracle(env, case, m, n, s, lam, T, mode, iters, tau):
+    print(f"lsqr parity {case}", flush=True)
+    sysm = synth.tiny_system("general", m, n, seed=m + n, cond=30.0)
+    x, st, res = gpu_lsqr(env, sysm.A, sysm.b, s, lam, T, mode, 7, 99, iters, tau)
+    ref = oracle_lsqr(sysm.A, sysm.b, s, lam, T, mode, 7, 99, iters, tau=tau or None)
+    alt = oracle_lsqr(sysm.A, sysm.b, s, lam, T, mode, 7, 99, iters, tau=tau or None, reverse=True)
+    nf = relerr(alt.x, ref.x)
+    assert res.iters == T
+    assert res.memo_misses == ref.factorizations
+    assert relerr(x, ref.x) <= max(1e-10, 10.0 * nf), (relerr(x, ref.x), nf)
+    rho_nf = abs(alt.rho_final - ref.rho_final)
+    assert abs(res.rho_final - ref.rho_final) <= max(1e-9 * abs(ref.rho_final), 1e-12, 10.0 * rho_nf)
+
+
+def test_lsqr_on_c1_converges(env):
+    """The 1000 x 200 workload with the inexact projection (t_max = 8, tau = 2s)
+    reaches 1e-10 and the planted x*, in step counts close to the exact
+    projection's (Appendix F.1: 8 iterations nearly match it)."""
+    kpp, torch, dev, ctx = env
+    sysm = synth.config("c1")
+    x, st, res = gpu_lsqr(env, sysm.A, sysm.b, 20, 1e-3, 200000, "online", 101, 5, 8, tol=1e-10)
+    assert st == kpp.KPP_OK and res.converged
+    assert np.linalg.norm(sysm.A @ x - sysm.b) <= 1e-10 * np.linalg.norm(sysm.b)
+    assert relerr(x, sysm.xstar) <= 1e-7
+    ref = oracle_lsqr(sysm.A, sysm.b, 20, 1e-3, 200000, "online", 101, 5, 8, tol=1e-10)
+    assert ref.converged and abs(res.iters - ref.iters) <= 2 * 2 * 50   # within two windows (2 zeta = 100)
+
+
+def test_lsqr_flop_count(env):
+    kpp, torch, dev, ctx = env
+    sysm = synth.tiny_system("general", 300, 100, seed=3, cond=10.0)
+    s, T, it = 10, 40, 5
+    x, st, res = gpu_lsqr(env, sysm.A, sysm.b, s, 1e-3, T, "online", 3, 4, it)
+    n, N, tau = 100, 128, 20
+    step = 4 * s * n + 5 * n + s * s + it * (4 * s * n + 2 * n + 4 * s * s)
+    fact = s * N * math.log2(N) + s * s * tau + 2 * s ** 3 / 3
+    assert res.flops == pytest.approx(step * res.iters + fact * res.memo_misses, rel=1e-12)
+
+
+def test_lsqr_rejections(env):
+    kpp, torch, dev, ctx = env
+    sysm = synth.tiny_system("psd", 32, 32, seed=1)
+    Ad = torch.from_numpy(sysm.A).to(dev)
+    bd = torch.from_numpy(sysm.b).to(dev)
+    xd = torch.zeros(32, dtype=torch.float64, device=dev)
+    for kind, field, value in ((kpp.KPP_CD_PSD, None, None), (kpp.KPP_KACZMARZ, "engine", 2),
+                               (kpp.KPP_KACZMARZ, "resume", 1), (kpp.KPP_KACZMARZ, "precision", kpp.KPP_MIXED_FP32),
+                               (kpp.KPP_KACZMARZ, "lsqr_iters", 0)):
+        h = kpp.kpp_system_create(ctx, kind, 32, 32, Ad.data_ptr(), 32, bd.data_ptr())
+        p = kpp.kpp_params_default(kind)
+        p.block_size = 8
+        p.projection = kpp.KPP_PROJ_LSQR
+        if field:
+            setattr(p, field, value)
+        try:
+            with pytest.raises(kpp.KppError):
+                kpp.kpp_solve(h, p, xd.data_ptr())
+        finally:
+            kpp.kpp_system_destroy(h)
