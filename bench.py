@@ -17,6 +17,7 @@ replayed in real time and reported under "serving" (p50/p99 latency).  Under
 "rht": the randomized Hadamard preprocessing (Definition d:rht) timed at the
 workloads' shapes, and the same CD++ solve with it.  Under "flops_to_tol": the
 paper's FLOP comparison (Section 6.3) re-run on synthetic kernel matrices.
+Under "lsqr": Kaczmarz++ with the exact and with the LSQR projection.
 
 Also printed: the roofline of the dominant kernel (the step kernel, timed with
 HIP events inside the library on the stream it runs on) and the CPU oracle
@@ -51,6 +52,7 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--no-rht", action="store_true")
     ap.add_argument("--no-flops", action="store_true")
+    ap.add_argument("--no-lsqr", action="store_true")
     ap.add_argument("--rht-only", action="store_true",
                     help="only the randomized Hadamard transforms (for profiling them)")
     return ap.parse_args()
@@ -322,6 +324,46 @@ def flops_to_tol(kpp, torch, dev, ctx, seed):
             "runs": rows, "paper_tab_flops_range": PAPER_TAB_FLOPS}
 
 
+def lsqr_solves(kpp, torch, dev, ctx):
+    """Kaczmarz++ to 1e-10 with the exact projection (the memoized Cholesky
+    factor) and with the sketch-preconditioned LSQR projection (t_max = 8,
+    tau = 2s; Section 4.1) on the 1000 x 200 and 65536 x 2048 workloads."""
+    import synth
+
+    out = {}
+    for name, cfg, s, lam, memo in (("k_1000x200_s20", "c1", 20, 1e-3, 1), ("k_65536x2048_s256", "c3", 256, 1e-8, 2)):
+        sysm = synth.config(cfg, device="cuda")
+        A, b = sysm.A, sysm.b
+        m, n = A.shape
+        h = kpp.kpp_system_create(ctx, kpp.KPP_KACZMARZ, m, n, A.data_ptr(), n, b.data_ptr())
+        rec = {}
+        for proj in (kpp.KPP_PROJ_EXACT, kpp.KPP_PROJ_LSQR):
+            p = kpp.kpp_params_default(kpp.KPP_KACZMARZ)
+            p.block_size = s
+            p.lambda_ = lam
+            p.tol = 1e-10
+            p.memo = memo
+            p.fixed_partition = 1
+            p.max_iters = 200_000
+            p.seed = sysm.params["schedule_seed"]
+            p.projection = proj
+            x = torch.zeros(n, dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, r = kpp.kpp_solve(h, p, x.data_ptr())
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rec["exact" if proj == 0 else "lsqr_t8"] = {
+                "time_to_tol_ms": round(1e3 * dt, 3), "iters": r.iters, "us_per_step": round(1e6 * dt / max(r.iters, 1), 2),
+                "flops": r.flops, "converged": bool(st == kpp.KPP_OK and r.converged), "true_rel_res": r.true_rel_res,
+                "engine": r.engine_used,
+                "rel_err_vs_planted": float(torch.linalg.norm(x - sysm.xstar) / torch.linalg.norm(sysm.xstar))}
+        kpp.kpp_system_destroy(h)
+        out[name] = rec
+        del sysm, A, b
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -482,6 +524,8 @@ def main():
         line["rht"] = rh
     if not args.no_flops:
         line["flops_to_tol"] = flops_to_tol(kpp, torch, dev, ctx, args.seed)
+    if not args.no_lsqr:
+        line["lsqr"] = lsqr_solves(kpp, torch, dev, ctx)
     kpp.kpp_system_destroy(h)
     kpp.kpp_context_destroy(ctx)
     if not args.no_serving:

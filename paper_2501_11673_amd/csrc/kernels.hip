@@ -380,6 +380,18 @@ __global__ void k_state_init(DevState* ds, double rho0, double thr) {
 // (leading dimension sb + 1 against bank conflicts), larger ones in the
 // slot's scratch third.  One workgroup per slot.
 // --------------------------------------------------------------------------
+// L^{-T} column-major (entry (i, k) = L^{-1}(k, i) at k * s + i) in the slot's
+// last third, from L^{-1} column-major in its second third
+__device__ void write_linv_transpose(double* base, int32_t s, int32_t sb) {
+  const int64_t ss = static_cast<int64_t>(s) * s;
+  const double* Li = base + ss;
+  double* Lt = base + 2 * ss;
+  for (int e = threadIdx.x; e < sb * sb; e += kT) {
+    const int k = e / sb, i = e - k * sb;
+    Lt[static_cast<int64_t>(k) * s + i] = (k >= i) ? Li[static_cast<int64_t>(i) * s + k] : 0.0;
+  }
+}
+
 template <bool IN_LDS, bool LINV = false>
 __global__ __launch_bounds__(kT) void k_factor_inverse(double* __restrict__ slots, int64_t stride,
                                                        int32_t s, const int32_t* __restrict__ lens,
@@ -427,11 +439,14 @@ __global__ __launch_bounds__(kT) void k_factor_inverse(double* __restrict__ slot
   }
   __syncthreads();
   if constexpr (LINV) {
-    // keep L^{-1} itself, column-major (entry (i, k) at k * s + i), zero above the diagonal
+    // keep L^{-1} itself, column-major (entry (i, k) at k * s + i), zero above
+    // the diagonal, and L^{-T} the same way in the slot's last third
     for (int e = threadIdx.x; e < sb * sb; e += kT) {
       const int k = e / sb, i = e - k * sb;
       Gi[static_cast<int64_t>(k) * s + i] = (i >= k) ? M[static_cast<int64_t>(k) * ld + i] : 0.0;
     }
+    __syncthreads();
+    write_linv_transpose(base, s, sb);
     return;
   }
   // G^{-1} = M^T M; thread owns column k, entries i >= k, mirrored to (k, i)
@@ -615,6 +630,7 @@ __global__ __launch_bounds__(kT) void k_cholesky_panel(double* __restrict__ G, i
 // in the same order, so the stored inverse is exactly symmetric.  With chk.flag
 // the Frobenius condition number is tested as in k_factor_inverse.
 // --------------------------------------------------------------------------
+template <bool LINV = false>
 __global__ __launch_bounds__(kT) void k_inverse_blocked(double* __restrict__ slots, int64_t stride, int32_t s,
                                                         const int32_t* __restrict__ lens,
                                                         const int32_t* __restrict__ slot_of, FactorCheck chk,
@@ -694,6 +710,20 @@ __global__ __launch_bounds__(kT) void k_inverse_blocked(double* __restrict__ slo
       for (int a = 0; a < w; ++a) X[static_cast<int64_t>(r0 + a) * s + j] = Xd[a * kPanelLd + (j - r0)];
     }
     __syncthreads();
+  }
+  if constexpr (LINV) {
+    // X = L^{-1} row-major is L^{-T} column-major already: copy L^{-1}
+    // column-major into the second third, then clear X above the diagonal
+    for (int e = tid; e < sb * sb; e += kT) {
+      const int k = e / sb, i = e - k * sb;
+      Gi[static_cast<int64_t>(k) * s + i] = (i >= k) ? X[static_cast<int64_t>(i) * s + k] : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < sb * sb; e += kT) {
+      const int k = e / sb, i = e - k * sb;
+      if (i > k) X[static_cast<int64_t>(k) * s + i] = 0.0;
+    }
+    return;
   }
   // G^{-1}(i, j) for rows i0 .. i0 + 31, thread j; Xt[k * kPanel + a] = X(k, i0 + a)
   double* Xt = lds;
@@ -1073,11 +1103,11 @@ void launch_factor_inverse(double* slots, int64_t stride, int32_t s, const int32
   if (s > kLdsCholMax && s <= kFusedMaxBlock) {
     static bool attr_set = false;
     if (!attr_set) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_inverse_blocked),
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_inverse_blocked<false>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kInverseBlockedLds));
       attr_set = true;
     }
-    hipLaunchKernelGGL(k_inverse_blocked, dim3(nb), dim3(kT), kInverseBlockedLds, st, slots, stride, s, lens,
+    hipLaunchKernelGGL(k_inverse_blocked<false>, dim3(nb), dim3(kT), kInverseBlockedLds, st, slots, stride, s, lens,
                        slot_of, chk, skip);
     return;
   }
@@ -1099,6 +1129,17 @@ void launch_factor_inverse(double* slots, int64_t stride, int32_t s, const int32
 void launch_factor_linv(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
                         const int32_t* slot_of, hipStream_t st) {
   if (nb <= 0) return;
+  if (s > kLdsCholMax && s <= kFusedMaxBlock) {
+    static bool attr_set = false;
+    if (!attr_set) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_inverse_blocked<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kInverseBlockedLds));
+      attr_set = true;
+    }
+    hipLaunchKernelGGL(k_inverse_blocked<true>, dim3(nb), dim3(kT), kInverseBlockedLds, st, slots, stride, s, lens,
+                       slot_of, FactorCheck(), nullptr);
+    return;
+  }
   if (s <= kLdsCholMax) {
     const size_t lds = (static_cast<size_t>(s) * (s + 1) + s) * sizeof(double);
     static bool attr_set = false;

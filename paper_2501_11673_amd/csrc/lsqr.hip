@@ -9,9 +9,13 @@
 namespace kpp {
 namespace {
 
-constexpr int kL = 256;   // threads per workgroup
+constexpr int kL = 256;        // threads per workgroup of the column kernels
+constexpr int kS = 1024;       // threads of the one-workgroup kernels on s-vectors
+constexpr int kSRows = 256;    // output rows per pass of those kernels (4 threads each)
+constexpr int kAtRows = 16;    // block rows per workgroup of the A_S^T z pass
 
-// sum over the workgroup, in every thread (fixed order: deterministic)
+// sum over the workgroup of NT threads, in every thread (fixed order)
+template <int NT>
 __device__ double wg_sum(double v, double* red) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   const int w = threadIdx.x >> 6;
@@ -19,8 +23,33 @@ __device__ double wg_sum(double v, double* red) {
   if ((threadIdx.x & 63) == 0) red[w] = v;
   __syncthreads();
   double t = 0.0;
-  for (int i = 0; i < kL / 64; ++i) t += red[i];
+  for (int i = 0; i < NT / 64; ++i) t += red[i];
   return t;
+}
+
+// out_i = sum_k B[k s + i] v_k for i < sb (B column-major, s x s): thread
+// (i mod 256, part) sums k = part, part + 4, ..., the four parts are added in
+// a fixed order.  v and out in LDS; ends with a barrier.
+__device__ void mv_colmajor(const double* __restrict__ B, int32_t s, int32_t sb, const double* v, double* out,
+                            double* part4) {
+  const int i0 = threadIdx.x & (kSRows - 1), pt = threadIdx.x / kSRows;
+  for (int ib = 0; ib < sb; ib += kSRows) {
+    const int i = ib + i0;
+    double a0 = 0.0, a1 = 0.0;
+    if (i < sb) {
+      int k = pt;
+      for (; k + 4 < sb; k += 8) {
+        a0 = fma(B[static_cast<int64_t>(k) * s + i], v[k], a0);
+        a1 = fma(B[static_cast<int64_t>(k + 4) * s + i], v[k + 4], a1);
+      }
+      if (k < sb) a0 = fma(B[static_cast<int64_t>(k) * s + i], v[k], a0);
+    }
+    part4[pt * kSRows + i0] = a0 + a1;
+    __syncthreads();
+    if (pt == 0 && i < sb)
+      out[i] = (part4[i0] + part4[kSRows + i0]) + (part4[2 * kSRows + i0] + part4[3 * kSRows + i0]);
+    __syncthreads();
+  }
 }
 
 __global__ __launch_bounds__(kL) void k_sketch_gather(const double* __restrict__ A, int64_t lda, int64_t n,
@@ -40,25 +69,23 @@ __global__ __launch_bounds__(kL) void k_sketch_select(const double* __restrict__
   Ahat[e] = i < sb ? scale * Y[static_cast<int64_t>(T[k]) * s + i] : 0.0;
 }
 
-__global__ __launch_bounds__(kL) void k_lsqr_start(const double* __restrict__ y, const double* __restrict__ Li,
+__global__ __launch_bounds__(kS) void k_lsqr_start(const double* __restrict__ y, const double* __restrict__ Lt,
                                                    int32_t s, int32_t sb, LsqrState* __restrict__ L) {
-  __shared__ double red[kL / 64];
+  __shared__ double red[kS / 64];
   __shared__ double u[kMaxBlock];
+  __shared__ double zt[kMaxBlock];
+  __shared__ double part4[4 * kSRows];
   double acc = 0.0;
-  for (int i = threadIdx.x; i < sb; i += kL) acc = fma(y[i], y[i], acc);
-  const double beta = sqrt(wg_sum(acc, red));
-  for (int i = threadIdx.x; i < sb; i += kL) {
+  for (int i = threadIdx.x; i < sb; i += kS) acc = fma(y[i], y[i], acc);
+  const double beta = sqrt(wg_sum<kS>(acc, red));
+  for (int i = threadIdx.x; i < sb; i += kS) {
     L->zx[i] = 0.0;
     u[i] = beta > 0.0 ? y[i] / beta : 0.0;
     L->u[i] = u[i];
   }
   __syncthreads();
-  // z~ = L^{-T} u: entry i is sum_k L^{-1}(k, i) u_k, L^{-1}(k, i) at i s + k
-  for (int i = threadIdx.x; i < sb; i += kL) {
-    double a = 0.0;
-    for (int k = i; k < sb; ++k) a = fma(Li[static_cast<int64_t>(i) * s + k], u[k], a);
-    L->zt[i] = a;
-  }
+  mv_colmajor(Lt, s, sb, u, zt, part4);   // z~ = L^{-T} u
+  for (int i = threadIdx.x; i < sb; i += kS) L->zt[i] = zt[i];
   if (threadIdx.x == 0) {
     L->beta = beta;
     L->phibar = beta;
@@ -66,26 +93,34 @@ __global__ __launch_bounds__(kL) void k_lsqr_start(const double* __restrict__ y,
   }
 }
 
+// p_part[c n + j] = sum over block rows 16 c .. 16 c + 15 of A[rows[i], j] z~_i
 __global__ __launch_bounds__(kL) void k_lsqr_at(const double* __restrict__ A, int64_t lda, int64_t n,
                                                 const int32_t* __restrict__ rows, int32_t sb,
-                                                const LsqrState* __restrict__ L, double* __restrict__ p,
-                                                double* __restrict__ partsq) {
-  __shared__ double red[kL / 64];
-  __shared__ double z[kMaxBlock];
-  __shared__ int32_t rw[kMaxBlock];
+                                                const LsqrState* __restrict__ L, double* __restrict__ ppart) {
   if (!L->live) return;   // uniform over the grid
-  for (int i = threadIdx.x; i < sb; i += kL) {
-    z[i] = L->zt[i];
-    rw[i] = rows[i];
-  }
-  __syncthreads();
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kL + threadIdx.x;
+  const int i0 = blockIdx.y * kAtRows;
+  const int i1 = min(sb, i0 + kAtRows);
+  if (j >= n) return;
+  double acc = 0.0;
+  for (int i = i0; i < i1; ++i) acc = fma(A[static_cast<int64_t>(rows[i]) * lda + j], L->zt[i], acc);
+  ppart[static_cast<int64_t>(blockIdx.y) * n + j] = acc;
+}
+
+// p = the sum of the row-chunk parts (fixed order), and the workgroup partial
+// sums of ||p||^2
+__global__ __launch_bounds__(kL) void k_lsqr_at_sum(const double* __restrict__ ppart, int32_t nchunks, int64_t n,
+                                                    const LsqrState* __restrict__ L, double* __restrict__ p,
+                                                    double* __restrict__ partsq) {
+  __shared__ double red[kL / 64];
+  if (!L->live) return;
   const int64_t j = static_cast<int64_t>(blockIdx.x) * kL + threadIdx.x;
   double acc = 0.0;
   if (j < n) {
-    for (int i = 0; i < sb; ++i) acc = fma(A[static_cast<int64_t>(rw[i]) * lda + j], z[i], acc);
+    for (int c = 0; c < nchunks; ++c) acc += ppart[static_cast<int64_t>(c) * n + j];
     p[j] = acc;
   }
-  const double sq = wg_sum(acc * acc, red);
+  const double sq = wg_sum<kL>(acc * acc, red);
   if (threadIdx.x == 0) partsq[blockIdx.x] = sq;
 }
 
@@ -96,7 +131,7 @@ __global__ __launch_bounds__(kL) void k_lsqr_post(const double* __restrict__ par
   if (!L->live) return;
   double zz = 0.0;
   for (int i = threadIdx.x; i < sb; i += kL) zz = fma(L->zt[i], L->zt[i], zz);
-  zz = wg_sum(zz, red);
+  zz = wg_sum<kL>(zz, red);
   if (threadIdx.x == 0) {
     double pp = 0.0;
     for (int g = 0; g < ngroups; ++g) pp += partsq[g];
@@ -148,41 +183,36 @@ __global__ __launch_bounds__(kL) void k_lsqr_post(const double* __restrict__ par
   }
 }
 
-__global__ __launch_bounds__(kL) void k_lsqr_mid(const double* __restrict__ rpart, int32_t P,
-                                                 const double* __restrict__ Li, int32_t s, int32_t sb, double lambda,
-                                                 LsqrState* __restrict__ L) {
-  __shared__ double red[kL / 64];
+__global__ __launch_bounds__(kS) void k_lsqr_mid(const double* __restrict__ rpart, int32_t P,
+                                                 const double* __restrict__ Li, const double* __restrict__ Lt,
+                                                 int32_t s, int32_t sb, double lambda, LsqrState* __restrict__ L) {
+  __shared__ double red[kS / 64];
   __shared__ double t[kMaxBlock];
   __shared__ double u[kMaxBlock];
+  __shared__ double part4[4 * kSRows];
   if (!L->live) return;
   const double pscale = L->pscale, alpha = L->alpha;
-  for (int i = threadIdx.x; i < sb; i += kL) {
+  for (int i = threadIdx.x; i < sb; i += kS) {
     double q = 0.0;
     for (int k = 0; k < P; ++k) q += rpart[static_cast<int64_t>(i) * P + k];
     t[i] = fma(lambda, L->zv[i], q * pscale);
   }
   __syncthreads();
-  // u~ = L^{-1} t - alpha u
+  mv_colmajor(Li, s, sb, t, u, part4);   // L^{-1} t
   double acc = 0.0;
-  for (int i = threadIdx.x; i < sb; i += kL) {
-    double a = 0.0;
-    for (int k = 0; k <= i; ++k) a = fma(Li[static_cast<int64_t>(k) * s + i], t[k], a);
-    const double ui = a - alpha * L->u[i];
+  for (int i = threadIdx.x; i < sb; i += kS) {
+    const double ui = u[i] - alpha * L->u[i];   // u~ = M v - alpha u
     u[i] = ui;
     acc = fma(ui, ui, acc);
   }
-  const double beta = sqrt(wg_sum(acc, red));
-  for (int i = threadIdx.x; i < sb; i += kL) {
+  const double beta = sqrt(wg_sum<kS>(acc, red));
+  for (int i = threadIdx.x; i < sb; i += kS) {
     if (beta > 0.0) u[i] /= beta;
     L->u[i] = u[i];
   }
   __syncthreads();
-  // z~ = L^{-T} u - beta v
-  for (int i = threadIdx.x; i < sb; i += kL) {
-    double a = 0.0;
-    for (int k = i; k < sb; ++k) a = fma(Li[static_cast<int64_t>(i) * s + k], u[k], a);
-    L->zt[i] = a - beta * L->zv[i];
-  }
+  mv_colmajor(Lt, s, sb, u, t, part4);   // L^{-T} u
+  for (int i = threadIdx.x; i < sb; i += kS) L->zt[i] = t[i] - beta * L->zv[i];
   if (threadIdx.x == 0) L->beta = beta;
 }
 
@@ -202,15 +232,20 @@ void launch_sketch_select(const double* Y, int32_t s, const int32_t* T, int32_t 
 }
 
 void launch_lsqr_start(const double* y, const double* Linv, int32_t s, int32_t sb, LsqrState* L, hipStream_t st) {
-  hipLaunchKernelGGL(k_lsqr_start, dim3(1), dim3(kL), 0, st, y, Linv, s, sb, L);
+  const double* Lt = Linv + static_cast<int64_t>(s) * s;
+  hipLaunchKernelGGL(k_lsqr_start, dim3(1), dim3(kS), 0, st, y, Lt, s, sb, L);
 }
 
 int32_t lsqr_at_groups(int64_t n) { return static_cast<int32_t>((n + kL - 1) / kL); }
 
+int32_t lsqr_at_chunks(int32_t s) { return (s + kAtRows - 1) / kAtRows; }
+
 void launch_lsqr_at(const double* A, int64_t lda, int64_t n, const int32_t* rows, int32_t sb, const LsqrState* L,
-                    double* p, double* partsq, hipStream_t st) {
-  hipLaunchKernelGGL(k_lsqr_at, dim3(static_cast<unsigned>(lsqr_at_groups(n))), dim3(kL), 0, st, A, lda, n, rows,
-                     sb, L, p, partsq);
+                    double* ppart, double* p, double* partsq, hipStream_t st) {
+  const int32_t nch = lsqr_at_chunks(sb);
+  const unsigned gx = static_cast<unsigned>(lsqr_at_groups(n));
+  hipLaunchKernelGGL(k_lsqr_at, dim3(gx, static_cast<unsigned>(nch)), dim3(kL), 0, st, A, lda, n, rows, sb, L, ppart);
+  hipLaunchKernelGGL(k_lsqr_at_sum, dim3(gx), dim3(kL), 0, st, ppart, nch, n, L, p, partsq);
 }
 
 void launch_lsqr_post(const double* partsq, int32_t ngroups, int32_t sb, double lambda, int32_t first, LsqrState* L,
@@ -220,7 +255,8 @@ void launch_lsqr_post(const double* partsq, int32_t ngroups, int32_t sb, double 
 
 void launch_lsqr_mid(const double* rpart, int32_t P, const double* Linv, int32_t s, int32_t sb, double lambda,
                      LsqrState* L, hipStream_t st) {
-  hipLaunchKernelGGL(k_lsqr_mid, dim3(1), dim3(kL), 0, st, rpart, P, Linv, s, sb, lambda, L);
+  const double* Lt = Linv + static_cast<int64_t>(s) * s;
+  hipLaunchKernelGGL(k_lsqr_mid, dim3(1), dim3(kS), 0, st, rpart, P, Linv, Lt, s, sb, lambda, L);
 }
 
 }  // namespace kpp

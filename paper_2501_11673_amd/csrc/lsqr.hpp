@@ -34,7 +34,8 @@ struct LsqrState {
 };
 
 // L^{-1} of each slot's factor at +s*s, column-major (entry (i, k) at k s + i),
-// zero above the diagonal; so y_i = sum_k slot[s s + k s + i] r_k is L^{-1} r.
+// zero above the diagonal, so y_i = sum_k slot[s s + k s + i] r_k is L^{-1} r;
+// and L^{-T} the same way at +2 s*s.
 void launch_factor_linv(double* slots, int64_t stride, int32_t s, const int32_t* lens, int32_t nb,
                         const int32_t* slot_of, hipStream_t st);
 
@@ -47,12 +48,15 @@ void launch_sketch_select(const double* Y, int32_t s, const int32_t* T, int32_t 
                           double* Ahat, hipStream_t st);
 
 // LSQR from z = 0 on M z = y, y = L^{-1} r (left in y by the projection
-// kernel): beta_1, u_1, and z~ = L^{-T} u_1.
+// kernel): beta_1, u_1, and z~ = L^{-T} u_1.  Linv points at the slot's
+// L^{-1}; L^{-T} follows it.
 void launch_lsqr_start(const double* y, const double* Linv, int32_t s, int32_t sb, LsqrState* L, hipStream_t st);
-// p = A_S^T z~ (n entries) and the workgroup partial sums of ||p||^2.
+// p = A_S^T z~ (n entries) and the lsqr_at_groups(n) workgroup partial sums
+// of ||p||^2; ppart holds lsqr_at_chunks(sb) x n partial products.
 int32_t lsqr_at_groups(int64_t n);
+int32_t lsqr_at_chunks(int32_t s);
 void launch_lsqr_at(const double* A, int64_t lda, int64_t n, const int32_t* rows, int32_t sb, const LsqrState* L,
-                    double* p, double* partsq, hipStream_t st);
+                    double* ppart, double* p, double* partsq, hipStream_t st);
 // alpha = sqrt(||p||^2 + lambda ||z~||^2), v = z~ / alpha; first: set up the
 // recurrences, else: one plane rotation and the updates of x and w.
 void launch_lsqr_post(const double* partsq, int32_t ngroups, int32_t sb, double lambda, int32_t first, LsqrState* L,

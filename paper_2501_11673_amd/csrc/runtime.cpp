@@ -160,6 +160,7 @@ struct kpp_system {
   // new blocks of each staging buffer
   kpp::LsqrState* lsqr_state = nullptr;
   double* lsqr_p = nullptr;
+  double* lsqr_ppart = nullptr;
   double* lsqr_part = nullptr;
   double* lsqr_Xt = nullptr;
   double* lsqr_Y = nullptr;
@@ -191,6 +192,7 @@ void drop_rht(kpp_system* s) {
 void drop_lsqr(kpp_system* s) {
   dev_free(s->lsqr_state);
   dev_free(s->lsqr_p);
+  dev_free(s->lsqr_ppart);
   dev_free(s->lsqr_part);
   dev_free(s->lsqr_Xt);
   dev_free(s->lsqr_Y);
@@ -764,17 +766,17 @@ class CoreRun {
       kpp::launch_block_project(sys->rpart, P_, src_.b, rows, sb, Li, s_, sys->y, sys->ds, zeta_, prm_.adaptive_rho,
                                 st_);
       kpp::launch_lsqr_start(sys->y, Li, s_, sb, L, st_);
-      kpp::launch_lsqr_at(src_.A64, src_.lda, n_, rows, sb, L, sys->lsqr_p, sys->lsqr_part, st_);
+      kpp::launch_lsqr_at(src_.A64, src_.lda, n_, rows, sb, L, sys->lsqr_ppart, sys->lsqr_p, sys->lsqr_part, st_);
       kpp::launch_lsqr_post(sys->lsqr_part, G, sb, prm_.lambda, 1, L, st_);
       for (int32_t it = 0; it < lsqr_iters_; ++it) {
         kpp::launch_block_gemv_partial(src_.A64, src_.lda, n_, rows, sb, sys->lsqr_p, sys->rpart, P_, kChunk, st_);
         kpp::launch_lsqr_mid(sys->rpart, P_, Li, s_, sb, prm_.lambda, L, st_);
-        kpp::launch_lsqr_at(src_.A64, src_.lda, n_, rows, sb, L, sys->lsqr_p, sys->lsqr_part, st_);
+        kpp::launch_lsqr_at(src_.A64, src_.lda, n_, rows, sb, L, sys->lsqr_ppart, sys->lsqr_p, sys->lsqr_part, st_);
         kpp::launch_lsqr_post(sys->lsqr_part, G, sb, prm_.lambda, 0, L, st_);
       }
       kpp::launch_update(kind_, src_.A64, src_.lda, n_, rows, sb, zx, sys->ds, eta_, x_, sys->mom, st_);
     }
-    launches_ += (6 + 4 * lsqr_iters_) * (w.W - w.done);
+    launches_ += (7 + 5 * lsqr_iters_) * (w.W - w.done);
     HIP_TRY(hipGetLastError());
     return KPP_OK;
   }
@@ -1045,6 +1047,7 @@ class CoreRun {
       kpp_status stt;
       const int32_t groups = kpp::lsqr_at_groups(n_);
       if ((stt = dev_alloc(&sys->lsqr_state, 1)) < 0 || (stt = dev_alloc(&sys->lsqr_p, n_)) < 0 ||
+          (stt = dev_alloc(&sys->lsqr_ppart, static_cast<int64_t>(kpp::lsqr_at_chunks(s_)) * n_)) < 0 ||
           (stt = dev_alloc(&sys->lsqr_part, groups)) < 0 || (stt = dev_alloc(&sys->lsqr_Xt, n_ * s_)) < 0 ||
           (stt = dev_alloc(&sys->lsqr_Y, Nsk_ * s_)) < 0 ||
           (stt = dev_alloc(&sys->lsqr_Ahat, static_cast<int64_t>(s_) * tau_)) < 0 ||

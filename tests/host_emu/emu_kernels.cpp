@@ -193,8 +193,7 @@ void launch_factor_linv(double* slots, int64_t stride, int32_t s, const int32_t*
   emu_check(slot_of, 4 * static_cast<size_t>(nb), "linv slots");
   for (int32_t k = 0; k < nb; ++k) {
     if (lens[k] < 1 || lens[k] > s) { std::fprintf(stderr, "EMU: linv block length %d\n", lens[k]); std::abort(); }
-    emu_check(slots + static_cast<int64_t>(slot_of[k]) * stride, 8 * (s > 128 ? 3 : 2) * static_cast<size_t>(s) * s,
-              "linv slot");
+    emu_check(slots + static_cast<int64_t>(slot_of[k]) * stride, 8 * 3 * static_cast<size_t>(s) * s, "linv slot");
   }
 }
 void launch_sketch_gather(const double* A, int64_t lda, int64_t n, const int32_t* rows, int32_t sb, int32_t s,
@@ -213,17 +212,19 @@ void launch_sketch_select(const double* Y, int32_t s, const int32_t* T, int32_t 
 }
 void launch_lsqr_start(const double* y, const double* Linv, int32_t s, int32_t sb, LsqrState* L, hipStream_t) {
   emu_check(y, 8 * static_cast<size_t>(sb), "lsqr y");
-  emu_check(Linv, 8 * static_cast<size_t>(s) * s, "lsqr Linv");
+  emu_check(Linv, 8 * 2 * static_cast<size_t>(s) * s, "lsqr Linv and its transpose");
   emu_check(L, sizeof(LsqrState), "lsqr state");
   L->live = 0;   // the stand-in solves nothing: later LSQR kernels are no-ops
   for (int32_t i = 0; i < sb; ++i) L->zx[i] = 0.0;
 }
 int32_t lsqr_at_groups(int64_t n) { return static_cast<int32_t>((n + 255) / 256); }
+int32_t lsqr_at_chunks(int32_t s) { return (s + 15) / 16; }
 void launch_lsqr_at(const double* A, int64_t lda, int64_t n, const int32_t* rows, int32_t sb, const LsqrState* L,
-                    double* p, double* partsq, hipStream_t) {
+                    double* ppart, double* p, double* partsq, hipStream_t) {
   check_rows(rows, sb, "lsqr rows");
   check_A(A, 8, lda, rows, sb, n, "lsqr A");
   emu_check(L, sizeof(LsqrState), "lsqr state");
+  emu_check(ppart, 8 * static_cast<size_t>(lsqr_at_chunks(sb)) * n, "lsqr row-chunk parts");
   emu_check(p, 8 * static_cast<size_t>(n), "lsqr p");
   emu_check(partsq, 8 * static_cast<size_t>(lsqr_at_groups(n)), "lsqr partials");
 }
@@ -234,7 +235,7 @@ void launch_lsqr_post(const double* partsq, int32_t ngroups, int32_t, double, in
 void launch_lsqr_mid(const double* rpart, int32_t P, const double* Linv, int32_t s, int32_t sb, double, LsqrState* L,
                      hipStream_t) {
   emu_check(rpart, 8 * static_cast<size_t>(sb) * P, "lsqr rpart");
-  emu_check(Linv, 8 * static_cast<size_t>(s) * s, "lsqr Linv");
+  emu_check(Linv, 8 * 2 * static_cast<size_t>(s) * s, "lsqr Linv and its transpose");
   emu_check(L, sizeof(LsqrState), "lsqr state");
 }
 
