@@ -17,7 +17,8 @@ replayed in real time and reported under "serving" (p50/p99 latency).  Under
 "rht": the randomized Hadamard preprocessing (Definition d:rht) timed at the
 workloads' shapes, and the same CD++ solve with it.  Under "flops_to_tol": the
 paper's FLOP comparison (Section 6.3) re-run on synthetic kernel matrices.
-Under "lsqr": Kaczmarz++ with the exact and with the LSQR projection.
+Under "lsqr": Kaczmarz++ with the exact and with the LSQR projection.  Under
+"ablation": the four Kaczmarz++ variants of the paper's ablation table.
 
 Also printed: the roofline of the dominant kernel (the step kernel, timed with
 HIP events inside the library on the stream it runs on) and the CPU oracle
@@ -324,6 +325,43 @@ def flops_to_tol(kpp, torch, dev, ctx, seed):
             "runs": rows, "paper_tab_flops_range": PAPER_TAB_FLOPS}
 
 
+def ablation(kpp, torch, dev, ctx):
+    """The four Kaczmarz++ variants of Table tab:kacz-variants (Appendix F.1)
+    on the 1000 x 200 workload to 1e-10, with its block size 20 and with 5
+    (fewer rows than the 10 outlying singular values): Full K++ (acceleration
+    and online memo), w/o Accel (eta = 0), w/o Memo (a new block, and its
+    factor, every step) and plain randomized block Kaczmarz (neither)."""
+    import synth
+
+    sysm = synth.config("c1", device="cuda")
+    A, b = sysm.A, sysm.b
+    m, n = A.shape
+    h = kpp.kpp_system_create(ctx, kpp.KPP_KACZMARZ, m, n, A.data_ptr(), n, b.data_ptr())
+    out = {}
+    for s, name, accel, memo in [(s, nm, a, mm) for s in (20, 5)
+                                 for nm, a, mm in (("full_kpp", 1, 1), ("wo_accel", 0, 1), ("wo_memo", 1, 0),
+                                                   ("kaczmarz", 0, 0))]:
+        p = kpp.kpp_params_default(kpp.KPP_KACZMARZ)
+        p.block_size = s
+        p.lambda_ = 1e-3
+        p.tol = 1e-10
+        p.memo = memo
+        p.accel = accel
+        p.max_iters = 200_000
+        p.seed = sysm.params["schedule_seed"]
+        x = torch.zeros(n, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, r = kpp.kpp_solve(h, p, x.data_ptr())
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out.setdefault(f"s{s}", {})[name] = {"iters": r.iters, "time_to_tol_ms": round(1e3 * dt, 3), "flops": r.flops,
+                     "factorizations": r.memo_misses, "converged": bool(st == kpp.KPP_OK and r.converged),
+                     "true_rel_res": r.true_rel_res}
+    kpp.kpp_system_destroy(h)
+    return out
+
+
 def lsqr_solves(kpp, torch, dev, ctx):
     """Kaczmarz++ to 1e-10 with the exact projection (the memoized Cholesky
     factor) and with the sketch-preconditioned LSQR projection (t_max = 8,
@@ -526,6 +564,8 @@ def main():
         line["flops_to_tol"] = flops_to_tol(kpp, torch, dev, ctx, args.seed)
     if not args.no_lsqr:
         line["lsqr"] = lsqr_solves(kpp, torch, dev, ctx)
+    if not args.no_flops:
+        line["ablation"] = ablation(kpp, torch, dev, ctx)
     kpp.kpp_system_destroy(h)
     kpp.kpp_context_destroy(ctx)
     if not args.no_serving:
