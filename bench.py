@@ -18,7 +18,8 @@ replayed in real time and reported under "serving" (p50/p99 latency).  Under
 workloads' shapes, and the same CD++ solve with it.  Under "flops_to_tol": the
 paper's FLOP comparison (Section 6.3) re-run on synthetic kernel matrices.
 Under "lsqr": Kaczmarz++ with the exact and with the LSQR projection.  Under
-"ablation": the four Kaczmarz++ variants of the paper's ablation table.
+"ablation": the four Kaczmarz++ variants of the paper's ablation table.  Under
+"multi_rhs": 16 right-hand sides on the n = 4096 system solved together.
 
 Also printed: the roofline of the dominant kernel (the step kernel, timed with
 HIP events inside the library on the stream it runs on) and the CPU oracle
@@ -54,6 +55,7 @@ def parse():
     ap.add_argument("--no-rht", action="store_true")
     ap.add_argument("--no-flops", action="store_true")
     ap.add_argument("--no-lsqr", action="store_true")
+    ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--rht-only", action="store_true",
                     help="only the randomized Hadamard transforms (for profiling them)")
     return ap.parse_args()
@@ -362,6 +364,34 @@ def ablation(kpp, torch, dev, ctx):
     return out
 
 
+def multi_rhs(kpp, torch, dev, ctx, h, A, n, p, k=16):
+    """k right-hand sides b_c = A x*_c (seeded x*_c ~ N(0, I)) on the n = 4096
+    system, solved together to 1e-10 (kpp_solve_multi: one pass over A_S per
+    step for all k): aggregate block steps per second."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(77)
+    Xs = torch.randn((n, k), generator=g, dtype=torch.float64, device=dev)
+    B = (A @ Xs).contiguous()
+    X = torch.zeros((n, k), dtype=torch.float64, device=dev)
+    q = kpp.kpp_params_default(kpp.KPP_CD_PSD)
+    for f, _ in kpp.kpp_params._fields_:
+        setattr(q, f, getattr(p, f))
+    q.engine = 0
+    kpp.kpp_solve_multi(h, q, k, B.data_ptr(), k, X.data_ptr(), k)   # warm-up
+    X.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, res = kpp.kpp_solve_multi(h, q, k, B.data_ptr(), k, X.data_ptr(), k)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = [r.iters for r in res]
+    err = float(torch.max(torch.linalg.norm(X - Xs, dim=0) / torch.linalg.norm(Xs, dim=0)))
+    return {"k": k, "time_ms": round(1e3 * dt, 3), "iters_min": min(iters), "iters_max": max(iters),
+            "block_iters_per_s_aggregate": sum(iters) / dt, "steps_per_s": max(iters) / dt,
+            "all_converged": bool(st == kpp.KPP_OK and all(r.converged for r in res)),
+            "max_true_rel_res": max(r.true_rel_res for r in res), "max_rel_err_vs_planted": err}
+
+
 def lsqr_solves(kpp, torch, dev, ctx):
     """Kaczmarz++ to 1e-10 with the exact projection (the memoized Cholesky
     factor) and with the sketch-preconditioned LSQR projection (t_max = 8,
@@ -556,6 +586,8 @@ def main():
         "kernel_ms_per_solve": 1e3 * sum(r.kernel_seconds for _, r in mres) / args.steps,
         "speedup_vs_fp64": (1e3 * elapsed / args.steps) / (1e3 * melapsed / args.steps),
     }
+    if not args.no_multi:
+        line["multi_rhs"] = multi_rhs(kpp, torch, dev, ctx, h, A, n, p)
     if not args.no_rht:
         rh = rht_transforms(kpp, torch, dev, ctx, A, b)
         rh["cdpp_n4096_with_rht"] = rht_solves(kpp, torch, dev, h, p, x, args.steps)

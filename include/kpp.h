@@ -250,6 +250,22 @@ KPP_API kpp_status kpp_solve(kpp_system* sys, const kpp_params* p, double* x_dev
 KPP_API kpp_status kpp_state_export(const kpp_system* sys, void* host_buf, size_t* bytes);
 KPP_API kpp_status kpp_state_import(kpp_system* sys, const void* host_buf, size_t bytes);
 
+/* Several right-hand sides on one system (A x_c = b_c, c < k <= 32): the k
+ * solves share the block schedule, the memoized factors and every pass over
+ * A_S (each A_S element is read once per step for all of them); each keeps
+ * its own momentum, window sums and adaptive rho (Algorithms 2 and 5), is
+ * confirmed against its own true residual and stops at its own step, exactly
+ * where a kpp_solve of that right-hand side with the same parameters would.
+ * B_dev: m x k row-major (leading dimension ldb >= k); X_dev: n x k row-major
+ * (ldx >= k), in: the k starting iterates, out: the results; both device
+ * memory owned by the caller; the system's own b is not used.  res: k results
+ * (host) or NULL; the memo counts are the shared ones.  FP64, the seeded
+ * schedule and the launch-per-phase kernels only: rht, projection, resume, an
+ * explicit schedule or another precision give KPP_ERR_INVALID_ARG.  Returns
+ * KPP_OK when every right-hand side converged, else KPP_NOT_CONVERGED. */
+KPP_API kpp_status kpp_solve_multi(kpp_system* sys, const kpp_params* p, int32_t k, const double* B_dev,
+                                   int64_t ldb, double* X_dev, int64_t ldx, kpp_result* res);
+
 /* Randomized Hadamard preprocessing (Definition d:rht; Algorithm 4, FHT;
  * Algorithm 3 and Section 5.3, the symmetric transform).  H is the Sylvester
  * Hadamard matrix (H_1 = 1, H_2k = [[H_k, H_k], [H_k, -H_k]]); R is a power of

@@ -174,6 +174,7 @@ def _load():
         "kpp_server_destroy": (i32, [vp]),
         "kpp_state_export": (i32, [vp, vp, P(ctypes.c_size_t)]),
         "kpp_state_import": (i32, [vp, vp, ctypes.c_size_t]),
+        "kpp_solve_multi": (i32, [vp, P(kpp_params), i32, vp, i64, vp, i64, P(kpp_result)]),
         "kpp_rht_signs": (i32, [ctypes.c_uint64, i64, P(ctypes.c_int8)]),
         "kpp_rht_general": (i32, [vp, i64, i64, vp, i64, vp, vp, i64, vp, i64, vp]),
         "kpp_rht_psd": (i32, [vp, i64, vp, i64, vp, vp, i64, vp, i64, vp, vp]),
@@ -191,7 +192,7 @@ EXPORTED = ("kpp_abi_version", "kpp_last_error", "kpp_params_default", "kpp_cont
             "kpp_context_destroy", "kpp_system_create", "kpp_system_destroy", "kpp_solve",
             "kpp_schedule_generate", "kpp_block_factor", "kpp_residual_norm", "kpp_request_footprint", "kpp_server_create",
             "kpp_server_submit", "kpp_server_poll", "kpp_server_stats", "kpp_server_destroy",
-            "kpp_state_export", "kpp_state_import", "kpp_rht_signs", "kpp_rht_general", "kpp_rht_psd",
+            "kpp_state_export", "kpp_state_import", "kpp_solve_multi", "kpp_rht_signs", "kpp_rht_general", "kpp_rht_psd",
             "kpp_rht_vector")
 
 
@@ -284,6 +285,15 @@ def kpp_state_export(sys_: int) -> bytes:
 def kpp_state_import(sys_: int, state: bytes) -> None:
     buf = (ctypes.c_uint8 * max(len(state), 1)).from_buffer_copy(state if state else b"\0")
     _check(_lib.kpp_state_import(ctypes.c_void_p(sys_), ctypes.cast(buf, ctypes.c_void_p), len(state)))
+
+
+def kpp_solve_multi(sys_: int, params: kpp_params, k: int, B_dev: int, ldb: int, X_dev: int, ldx: int):
+    """k right-hand sides (B m x k, X n x k, row-major device arrays).
+    Returns (status, [kpp_result] * k)."""
+    res = (kpp_result * max(k, 1))()
+    st = _check(_lib.kpp_solve_multi(ctypes.c_void_p(sys_), ctypes.byref(params), k, ctypes.c_void_p(B_dev), ldb,
+                                     ctypes.c_void_p(X_dev), ldx, res))
+    return st, [res[c] for c in range(k)]
 
 
 def kpp_rht_signs(seed: int, N: int):

@@ -15,6 +15,7 @@
 
 #include "kernels.hpp"
 #include "lsqr.hpp"
+#include "multi.hpp"
 
 namespace kpp {
 namespace {
@@ -61,6 +62,45 @@ __global__ __launch_bounds__(kT) void k_block_gemv_partial(
 // --------------------------------------------------------------------------
 // projection through the memoized inverse and checkpoint bookkeeping: one workgroup
 // --------------------------------------------------------------------------
+// One step's scalar bookkeeping (Algorithms 2 and 5): c for this step's
+// momentum, ||r||^2 into the window sums, and at a checkpoint the stop
+// candidate and the revision of rho (eq. (weighted)).
+__device__ void step_state(DevState* ds, double rr, int32_t zeta, int32_t adaptive) {
+  DevState s = *ds;
+  const double rho = s.rho;
+  s.c = (1.0 - rho) / (1.0 + rho);
+  const int64_t period = 2 * static_cast<int64_t>(zeta);
+  const int64_t ph = s.t % period;
+  if (ph < zeta)
+    s.E0 += rr;
+  else
+    s.E1 += rr;
+  if (ph == period - 1) {
+    s.ckpts += 1;
+    s.last_E1 = s.E1;
+    s.rho_before = rho;
+    s.cand = (s.E1 <= s.thr) ? 1 : 0;
+    if (adaptive && s.E0 > 0.0) {
+      const double q = s.E1 / s.E0;
+      if (!s.have_rhat) {
+        s.rhat = q;
+        s.have_rhat = 1;
+      } else {
+        const double li = log(static_cast<double>(s.ckpt));
+        const double li1 = log(static_cast<double>(s.ckpt) + 1.0);
+        const double w = exp(li * li - li1 * li1);
+        s.rhat = w * s.rhat + (1.0 - w) * q;
+      }
+      s.ckpt += 1;
+      s.rho = rho_from_rate(s.rhat, zeta);
+    }
+    s.E0 = 0.0;
+    s.E1 = 0.0;
+  }
+  s.t += 1;
+  *ds = s;
+}
+
 __global__ __launch_bounds__(kT) void k_block_project(
     const double* __restrict__ rpart, int32_t P, const double* __restrict__ b,
     const int32_t* __restrict__ rows, int32_t sb, const double* __restrict__ Ginv, int32_t ldl,
@@ -85,41 +125,7 @@ __global__ __launch_bounds__(kT) void k_block_project(
     for (int k = 0; k < sb; ++k) acc = fma(Ginv[static_cast<int64_t>(k) * ldl + i], r[k], acc);
     y[i] = acc;
   }
-  if (tid == 0) {
-    DevState s = *ds;
-    const double rho = s.rho;
-    s.c = (1.0 - rho) / (1.0 + rho);
-    const int64_t period = 2 * static_cast<int64_t>(zeta);
-    const int64_t ph = s.t % period;
-    if (ph < zeta)
-      s.E0 += rr;
-    else
-      s.E1 += rr;
-    if (ph == period - 1) {
-      s.ckpts += 1;
-      s.last_E1 = s.E1;
-      s.rho_before = rho;
-      s.cand = (s.E1 <= s.thr) ? 1 : 0;
-      if (adaptive && s.E0 > 0.0) {
-        const double q = s.E1 / s.E0;
-        if (!s.have_rhat) {
-          s.rhat = q;
-          s.have_rhat = 1;
-        } else {
-          const double li = log(static_cast<double>(s.ckpt));
-          const double li1 = log(static_cast<double>(s.ckpt) + 1.0);
-          const double w = exp(li * li - li1 * li1);
-          s.rhat = w * s.rhat + (1.0 - w) * q;
-        }
-        s.ckpt += 1;
-        s.rho = rho_from_rate(s.rhat, zeta);
-      }
-      s.E0 = 0.0;
-      s.E1 = 0.0;
-    }
-    s.t += 1;
-    *ds = s;
-  }
+  if (tid == 0) step_state(ds, rr, zeta, adaptive);
 }
 
 // --------------------------------------------------------------------------
@@ -158,6 +164,134 @@ __global__ __launch_bounds__(kT) void k_update(const double* __restrict__ A, int
   const double mn = __dmul_rn(c, __dsub_rn(mom[j], w));
   mom[j] = mn;
   x[j] = __dadd_rn(__dsub_rn(x[j], w), __dmul_rn(eta, mn));
+}
+
+// --------------------------------------------------------------------------
+// several right-hand sides: the same three phases, every A_S element used for
+// all k columns (registers hold k sums per thread)
+// --------------------------------------------------------------------------
+template <int KM>
+__global__ __launch_bounds__(kT) void k_block_gemm_partial(const double* __restrict__ A, int64_t lda, int64_t n,
+                                                           const int32_t* __restrict__ rows,
+                                                           const double* __restrict__ X, int64_t ldx, int32_t k,
+                                                           double* __restrict__ rpart, int32_t P, int64_t chunk) {
+  __shared__ double red[4][kMaxRhs];
+  const int i = blockIdx.y;
+  const int p = blockIdx.x;
+  const double* Ai = A + static_cast<int64_t>(rows[i]) * lda;
+  const int64_t j0 = static_cast<int64_t>(p) * chunk;
+  const int64_t j1 = min(n, j0 + chunk);
+  double acc[KM];
+#pragma unroll
+  for (int c = 0; c < KM; ++c) acc[c] = 0.0;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += kT) {
+    const double a = Ai[j];
+    const double* xr = X + j * ldx;
+#pragma unroll
+    for (int c = 0; c < KM; ++c)
+      if (c < k) acc[c] = fma(a, xr[c], acc[c]);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < KM; ++c) {
+    double v = acc[c];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0 && c < k) red[w][c] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < k) {
+    const int c = threadIdx.x;
+    rpart[(static_cast<int64_t>(i) * P + p) * k + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+  }
+}
+
+__global__ __launch_bounds__(kT) void k_block_project_multi(
+    const double* __restrict__ rpart, int32_t P, int32_t k, const double* __restrict__ B, int64_t ldb,
+    const int32_t* __restrict__ rows, int32_t sb, const double* __restrict__ Ginv, int32_t ldl,
+    double* __restrict__ Y, DevState* __restrict__ ds, const int32_t* __restrict__ frozen, int32_t zeta,
+    int32_t adaptive) {
+  __shared__ double r[kMaxBlock];
+  __shared__ double red[4];
+  const int c = blockIdx.x;
+  if (frozen[c]) return;   // uniform over the workgroup
+  const int tid = threadIdx.x;
+  double part = 0.0;
+  for (int i = tid; i < sb; i += kT) {
+    double acc = 0.0;
+    for (int p = 0; p < P; ++p) acc += rpart[(static_cast<int64_t>(i) * P + p) * k + c];
+    const double ri = acc - B[static_cast<int64_t>(rows[i]) * ldb + c];
+    r[i] = ri;
+    part = fma(ri, ri, part);
+  }
+  const double rr = block_sum(part, red);
+  __syncthreads();
+  for (int i = tid; i < sb; i += kT) {
+    double acc = 0.0;
+    for (int q = 0; q < sb; ++q) acc = fma(Ginv[static_cast<int64_t>(q) * ldl + i], r[q], acc);
+    Y[static_cast<int64_t>(c) * ldl + i] = acc;
+  }
+  if (tid == 0) step_state(ds + c, rr, zeta, adaptive);
+}
+
+template <int KIND, int KM>
+__global__ __launch_bounds__(kT) void k_update_multi(const double* __restrict__ A, int64_t lda, int64_t n,
+                                                     const int32_t* __restrict__ rows, int32_t sb,
+                                                     const double* __restrict__ Y, int32_t s, int32_t k,
+                                                     const DevState* __restrict__ ds,
+                                                     const int32_t* __restrict__ frozen, double eta,
+                                                     double* __restrict__ X, int64_t ldx, double* __restrict__ M) {
+  __shared__ int32_t rs[kMaxBlock];
+  __shared__ double cc[kMaxRhs];
+  __shared__ int32_t fz[kMaxRhs];
+  for (int i = threadIdx.x; i < sb; i += kT) rs[i] = rows[i];
+  if (threadIdx.x < k) {
+    cc[threadIdx.x] = ds[threadIdx.x].c;
+    fz[threadIdx.x] = frozen[threadIdx.x];
+  }
+  __syncthreads();
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+  if (j >= n) return;
+  double w[KM];
+#pragma unroll
+  for (int c = 0; c < KM; ++c) w[c] = 0.0;
+  if (KIND == 0) {
+    for (int i = 0; i < sb; ++i) {
+      const double a = A[static_cast<int64_t>(rs[i]) * lda + j];
+#pragma unroll
+      for (int c = 0; c < KM; ++c)
+        if (c < k) w[c] = fma(a, Y[static_cast<int64_t>(c) * s + i], w[c]);
+    }
+  } else {
+    int lo = 0, hi = sb;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (rs[mid] < j)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    if (lo < sb && rs[lo] == j) {
+#pragma unroll
+      for (int c = 0; c < KM; ++c)
+        if (c < k) w[c] = Y[static_cast<int64_t>(c) * s + lo];
+    }
+  }
+  double* xr = X + j * ldx;
+  double* mr = M + j * k;
+#pragma unroll
+  for (int c = 0; c < KM; ++c) {
+    if (c < k && !fz[c]) {
+      const double mn = __dmul_rn(cc[c], __dsub_rn(mr[c], w[c]));
+      mr[c] = mn;
+      xr[c] = __dadd_rn(__dsub_rn(xr[c], w[c]), __dmul_rn(eta, mn));
+    }
+  }
+}
+
+__global__ __launch_bounds__(kT) void k_column(const double* __restrict__ X, int64_t ldx, int64_t n, int32_t c,
+                                               double* __restrict__ out) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+  if (j < n) out[j] = X[j * ldx + c];
 }
 
 // --------------------------------------------------------------------------
@@ -1039,6 +1173,52 @@ void launch_update(int32_t kind, const double* A, int64_t lda, int64_t n, const 
     hipLaunchKernelGGL(k_update<0>, grid, dim3(kT), 0, st, A, lda, n, rows, sb, y, ds, eta, x, mom);
   else
     hipLaunchKernelGGL(k_update<1>, grid, dim3(kT), 0, st, A, lda, n, rows, sb, y, ds, eta, x, mom);
+}
+
+void launch_block_gemm_partial(const double* A, int64_t lda, int64_t n, const int32_t* rows, int32_t sb,
+                               const double* X, int64_t ldx, int32_t k, double* rpart, int32_t P, int64_t chunk,
+                               hipStream_t st) {
+  const dim3 grid(P, sb);
+  if (k <= 4)
+    hipLaunchKernelGGL(k_block_gemm_partial<4>, grid, dim3(kT), 0, st, A, lda, n, rows, X, ldx, k, rpart, P, chunk);
+  else if (k <= 8)
+    hipLaunchKernelGGL(k_block_gemm_partial<8>, grid, dim3(kT), 0, st, A, lda, n, rows, X, ldx, k, rpart, P, chunk);
+  else if (k <= 16)
+    hipLaunchKernelGGL(k_block_gemm_partial<16>, grid, dim3(kT), 0, st, A, lda, n, rows, X, ldx, k, rpart, P, chunk);
+  else
+    hipLaunchKernelGGL(k_block_gemm_partial<32>, grid, dim3(kT), 0, st, A, lda, n, rows, X, ldx, k, rpart, P, chunk);
+}
+
+void launch_block_project_multi(const double* rpart, int32_t P, int32_t k, const double* B, int64_t ldb,
+                                const int32_t* rows, int32_t sb, const double* Ginv, int32_t s, double* Y,
+                                DevState* ds, const int32_t* frozen, int32_t zeta, int32_t adaptive, hipStream_t st) {
+  hipLaunchKernelGGL(k_block_project_multi, dim3(k), dim3(kT), 0, st, rpart, P, k, B, ldb, rows, sb, Ginv, s, Y, ds,
+                     frozen, zeta, adaptive);
+}
+
+void launch_update_multi(int32_t kind, const double* A, int64_t lda, int64_t n, const int32_t* rows, int32_t sb,
+                         const double* Y, int32_t s, int32_t k, const DevState* ds, const int32_t* frozen, double eta,
+                         double* X, int64_t ldx, double* M, hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>((n + kT - 1) / kT));
+#define KPP_UPDATE_MULTI(KIND, KM)                                                                               \
+  hipLaunchKernelGGL((k_update_multi<KIND, KM>), grid, dim3(kT), 0, st, A, lda, n, rows, sb, Y, s, k, ds, frozen, \
+                     eta, X, ldx, M)
+  if (kind == 0) {
+    if (k <= 4) KPP_UPDATE_MULTI(0, 4);
+    else if (k <= 8) KPP_UPDATE_MULTI(0, 8);
+    else if (k <= 16) KPP_UPDATE_MULTI(0, 16);
+    else KPP_UPDATE_MULTI(0, 32);
+  } else {
+    if (k <= 4) KPP_UPDATE_MULTI(1, 4);
+    else if (k <= 8) KPP_UPDATE_MULTI(1, 8);
+    else if (k <= 16) KPP_UPDATE_MULTI(1, 16);
+    else KPP_UPDATE_MULTI(1, 32);
+  }
+#undef KPP_UPDATE_MULTI
+}
+
+void launch_column(const double* X, int64_t ldx, int64_t n, int32_t c, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_column, dim3(static_cast<unsigned>((n + kT - 1) / kT)), dim3(kT), 0, st, X, ldx, n, c, out);
 }
 
 void launch_gram(int32_t kind, const double* A, int64_t lda, int64_t n, const int32_t* rows,

@@ -26,6 +26,7 @@
 
 #include "kernels.hpp"
 #include "lsqr.hpp"
+#include "multi.hpp"
 #include "kpp.h"
 #include "schedule.hpp"
 
@@ -2194,6 +2195,243 @@ KPP_API kpp_status kpp_rht_vector(kpp_context* ctx, int64_t R, const int8_t* sig
     return fail(KPP_ERR_INVALID_ARG, "R > 4096 with nx < R needs R doubles of work");
   HIP_TRY(hipSetDevice(ctx->device));
   return rht_vector(ctx->stream, R, signs, x, nx, y, direction == 1, work);
+}
+
+// ---------------------------------------------------------------------------
+// several right-hand sides on one system (the multi-RHS form): one schedule,
+// one memo, one pass over A_S per step for all of them
+// ---------------------------------------------------------------------------
+namespace {
+
+extern "C++" {
+// a device array freed when it goes out of scope
+template <class T>
+struct DevVec {
+  T* p = nullptr;
+  ~DevVec() { dev_free(p); }
+  kpp_status alloc(size_t count) {
+    dev_free(p);
+    return dev_alloc(&p, count);
+  }
+};
+}
+
+kpp_status solve_multi(kpp_system* sys, const kpp_params* p, int32_t k, const double* B, int64_t ldb, double* X,
+                       int64_t ldx, kpp_result* res) {
+  using clock = std::chrono::steady_clock;
+  const auto t_begin = clock::now();
+  hipStream_t st = sys->ctx->stream;
+  const int32_t kind = sys->kind;
+  const int64_t m = sys->m, n = sys->n, N = kind == KPP_CD_PSD ? n : m;
+  const int32_t s = p->block_size;
+  const int32_t zeta = static_cast<int32_t>((N + s - 1) / s);
+  const int64_t period = 2 * static_cast<int64_t>(zeta);
+  double eta = p->eta < 0.0 ? default_eta(kind, m, n, s) : p->eta;
+  if (!p->accel) eta = 0.0;
+  const auto mode = static_cast<kpp::MemoMode>(p->memo);
+  kpp::BlockSchedule sch(mode, N, s, p->seed, kpp::online_rate(kind, m, n, s), p->num_blocks,
+                         p->fixed_partition != 0);
+  constexpr int64_t kChunk = 2048;
+  const int32_t P = static_cast<int32_t>((n + kChunk - 1) / kChunk);
+  const int64_t stride = kpp::slot_doubles(s);
+  // ||b_c|| on the host
+  std::vector<double> hb(static_cast<size_t>(m) * ldb);
+  HIP_TRY(hipMemcpy(hb.data(), B, hb.size() * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<double> bn(k, 0.0);
+  for (int64_t i = 0; i < m; ++i)
+    for (int32_t c = 0; c < k; ++c) bn[c] += hb[static_cast<size_t>(i) * ldb + c] * hb[static_cast<size_t>(i) * ldb + c];
+  for (auto& v : bn) v = std::sqrt(v);
+  DevVec<double> mom, rpart, Y, xcol, bcol, rowsq, scal, ws, L;
+  DevVec<kpp::DevState> ds;
+  DevVec<int32_t> frozen, err, rows, lens, ids;
+  KPP_TRY(mom.alloc(static_cast<size_t>(n) * k));
+  KPP_TRY(rpart.alloc(static_cast<size_t>(s) * P * k));
+  KPP_TRY(Y.alloc(static_cast<size_t>(k) * s));
+  KPP_TRY(xcol.alloc(n));
+  KPP_TRY(bcol.alloc(m));
+  KPP_TRY(rowsq.alloc(m));
+  KPP_TRY(scal.alloc(4));
+  KPP_TRY(ds.alloc(k));
+  KPP_TRY(frozen.alloc(k));
+  KPP_TRY(err.alloc(1));
+  if (kind == KPP_KACZMARZ) KPP_TRY(ws.alloc(kpp::gram_syrk_work(s, n, 1)));
+  HIP_TRY(hipMemsetAsync(mom.p, 0, static_cast<size_t>(n) * k * sizeof(double), st));
+  HIP_TRY(hipMemsetAsync(frozen.p, 0, k * sizeof(int32_t), st));
+  HIP_TRY(hipMemsetAsync(err.p, 0, sizeof(int32_t), st));
+  std::vector<kpp::DevState> hds(k);
+  for (int32_t c = 0; c < k; ++c) {
+    kpp::DevState d{};
+    d.rho = p->rho0;
+    d.c = (1.0 - p->rho0) / (1.0 + p->rho0);
+    d.rho_before = p->rho0;
+    d.thr = p->tol * p->tol * bn[c] * bn[c];
+    hds[c] = d;
+  }
+  HIP_TRY(hipMemcpy(ds.p, hds.data(), k * sizeof(kpp::DevState), hipMemcpyHostToDevice));
+  // memo slots (one for every block in OFF mode: factored at every step)
+  int64_t cap = 1;
+  if (mode == kpp::MemoMode::Fixed) cap = sch.num_blocks();
+  if (mode == kpp::MemoMode::Online) cap = std::min<int64_t>(static_cast<int64_t>(4.0 * kpp::online_rate(kind, m, n, s)) + 16,
+                                                            std::max<int64_t>(16, p->max_iters + 1));
+  cap = std::max<int64_t>(cap, 1);
+  auto grow = [&](int64_t want) -> kpp_status {
+    if (want <= cap && L.p) return KPP_OK;
+    const int64_t nc = std::max(want, L.p ? 2 * cap : cap);
+    HIP_TRY(hipStreamSynchronize(st));
+    DevVec<double> L2;
+    DevVec<int32_t> r2, l2, i2;
+    KPP_TRY(L2.alloc(static_cast<size_t>(nc) * stride));
+    KPP_TRY(r2.alloc(static_cast<size_t>(nc) * s));
+    KPP_TRY(l2.alloc(nc));
+    KPP_TRY(i2.alloc(nc));
+    if (L.p) {
+      HIP_TRY(hipMemcpy(L2.p, L.p, static_cast<size_t>(cap) * stride * sizeof(double), hipMemcpyDeviceToDevice));
+      HIP_TRY(hipMemcpy(r2.p, rows.p, static_cast<size_t>(cap) * s * sizeof(int32_t), hipMemcpyDeviceToDevice));
+      HIP_TRY(hipMemcpy(l2.p, lens.p, static_cast<size_t>(cap) * sizeof(int32_t), hipMemcpyDeviceToDevice));
+    }
+    std::vector<int32_t> iota(static_cast<size_t>(nc));
+    std::iota(iota.begin(), iota.end(), 0);
+    HIP_TRY(hipMemcpy(i2.p, iota.data(), iota.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    std::swap(L.p, L2.p);
+    std::swap(rows.p, r2.p);
+    std::swap(lens.p, l2.p);
+    std::swap(ids.p, i2.p);
+    cap = nc;
+    return KPP_OK;
+  };
+  KPP_TRY(grow(cap));
+  std::vector<int32_t> slot_of;
+  std::vector<int32_t> stage(static_cast<size_t>(s) + 1);
+  std::vector<int32_t> hfrozen(k, 0);
+  std::vector<int64_t> iters(k, -1);
+  std::vector<double> true_rel(k, NAN);
+  int64_t t = 0, hits = 0, misses = 0;
+  int32_t used = 0;
+  auto confirm = [&](int32_t c, double* out) -> kpp_status {
+    kpp::launch_column(X, ldx, n, c, xcol.p, st);
+    kpp::launch_column(B, ldb, m, c, bcol.p, st);
+    kpp::launch_residual_sq(sys->A, sys->lda, m, n, xcol.p, bcol.p, rowsq.p, 0, scal.p, st);
+    HIP_TRY(hipGetLastError());
+    double v = 0.0;
+    HIP_TRY(hipMemcpyAsync(&v, scal.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *out = std::sqrt(v);
+    return KPP_OK;
+  };
+  int32_t active = k;
+  while (t < p->max_iters && active > 0) {
+    bool is_new = false;
+    const int32_t b = sch.next(&is_new);
+    int32_t q = 0;
+    bool factor = true;
+    if (mode != kpp::MemoMode::Off) {
+      if (static_cast<int32_t>(slot_of.size()) <= b) slot_of.resize(b + 1, -1);
+      if (slot_of[b] < 0) {
+        KPP_TRY(grow(used + 1));
+        slot_of[b] = used++;
+      } else {
+        factor = false;
+      }
+      q = slot_of[b];
+    }
+    const int32_t sb = sch.len(b);
+    if (factor) {
+      std::copy(sch.rows(b), sch.rows(b) + sb, stage.begin());
+      std::fill(stage.begin() + sb, stage.begin() + s, 0);
+      stage[s] = sb;
+      HIP_TRY(hipMemcpy(rows.p + static_cast<size_t>(q) * s, stage.data(), s * sizeof(int32_t), hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy(lens.p + q, &stage[s], sizeof(int32_t), hipMemcpyHostToDevice));
+      kpp::launch_gram(kind, sys->A, sys->lda, n, rows.p + static_cast<size_t>(q) * s, lens.p + q, s, 1, p->lambda,
+                       L.p, stride, ids.p + q, ws.p, st);
+      if (s <= kpp::kFactorSmallMax) {
+        kpp::launch_factor_small(L.p, stride, s, lens.p + q, 1, ids.p + q, 1, err.p, st);
+      } else {
+        kpp::launch_cholesky(L.p, s, stride, lens.p + q, 1, ids.p + q, err.p, st);
+        kpp::launch_factor_inverse(L.p, stride, s, lens.p + q, 1, ids.p + q, st);
+      }
+      ++misses;
+    } else {
+      ++hits;
+    }
+    const int32_t* r = rows.p + static_cast<size_t>(q) * s;
+    const double* Gi = L.p + static_cast<size_t>(q) * stride + static_cast<size_t>(s) * s;
+    kpp::launch_block_gemm_partial(sys->A, sys->lda, n, r, sb, X, ldx, k, rpart.p, P, kChunk, st);
+    kpp::launch_block_project_multi(rpart.p, P, k, B, ldb, r, sb, Gi, s, Y.p, ds.p, frozen.p, zeta,
+                                    p->adaptive_rho, st);
+    kpp::launch_update_multi(kind, sys->A, sys->lda, n, r, sb, Y.p, s, k, ds.p, frozen.p, eta, X, ldx, mom.p, st);
+    HIP_TRY(hipGetLastError());
+    ++t;
+    if (t % period == 0 || t == p->max_iters) {
+      int32_t herr = 0;
+      HIP_TRY(hipMemcpyAsync(hds.data(), ds.p, k * sizeof(kpp::DevState), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(&herr, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (herr) return fail(KPP_ERR_NOT_SPD, "a regularized block Gram has no Cholesky factor (lambda=%g)", p->lambda);
+      bool changed = false;
+      for (int32_t c = 0; c < k; ++c) {
+        if (hfrozen[c] || !(t % period == 0 && hds[c].cand)) continue;
+        double rn = 0.0;
+        if (p->confirm_true_residual) KPP_TRY(confirm(c, &rn));
+        if (!p->confirm_true_residual || rn <= p->tol * bn[c]) {
+          hfrozen[c] = 1;
+          iters[c] = t;
+          true_rel[c] = p->confirm_true_residual ? rn / (bn[c] > 0.0 ? bn[c] : 1.0) : NAN;
+          --active;
+          changed = true;
+        }
+      }
+      if (changed && active > 0)
+        HIP_TRY(hipMemcpy(frozen.p, hfrozen.data(), k * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipMemcpy(hds.data(), ds.p, k * sizeof(kpp::DevState), hipMemcpyDeviceToHost));
+  bool all = true;
+  for (int32_t c = 0; c < k; ++c) {
+    if (!hfrozen[c]) {
+      iters[c] = t;
+      all = false;
+    }
+    if (std::isnan(true_rel[c])) {
+      double rn = 0.0;
+      KPP_TRY(confirm(c, &rn));
+      true_rel[c] = rn / (bn[c] > 0.0 ? bn[c] : 1.0);
+    }
+  }
+  const double seconds = std::chrono::duration<double>(clock::now() - t_begin).count();
+  if (res) {
+    for (int32_t c = 0; c < k; ++c) {
+      kpp_result& r = res[c];
+      std::memset(&r, 0, sizeof(r));
+      CoreStats cs{};
+      cs.engine = 1;
+      fill_result(&r, sys, p, iters[c], hits, misses, hfrozen[c] != 0, 0, cs, true_rel[c],
+                  std::sqrt(hds[c].last_E1) / (bn[c] > 0.0 ? bn[c] : 1.0), hds[c].rho, seconds, 0.0, 0.0,
+                  3 * t, hds[c].ckpts, 8.0);
+    }
+  }
+  return all ? KPP_OK : KPP_NOT_CONVERGED;
+}
+
+}  // namespace
+
+KPP_API kpp_status kpp_solve_multi(kpp_system* sys, const kpp_params* p, int32_t k, const double* B_dev, int64_t ldb,
+                                   double* X_dev, int64_t ldx, kpp_result* res) {
+  if (!sys || !B_dev || !X_dev) return fail(KPP_ERR_INVALID_ARG, "NULL system, B or X");
+  if (k < 1 || k > kpp::kMaxRhs) return fail(KPP_ERR_INVALID_ARG, "k must be in [1, %d]", kpp::kMaxRhs);
+  if (ldb < k || ldx < k) return fail(KPP_ERR_INVALID_ARG, "leading dimensions must be >= k");
+  KPP_TRY(check_params(sys, p));
+  if (p->precision != KPP_FP64 || p->rht || p->projection || p->resume || p->schedule)
+    return fail(KPP_ERR_INVALID_ARG, "several right-hand sides: FP64 with the seeded schedule only");
+  HIP_TRY(hipSetDevice(sys->ctx->device));
+  sys->res_valid = false;
+  try {
+    return solve_multi(sys, p, k, B_dev, ldb, X_dev, ldx, res);
+  } catch (const std::bad_alloc&) {
+    return fail(KPP_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(KPP_ERR_INVALID_ARG, "%s", e.what());
+  }
 }
 
 KPP_API int32_t kpp_abi_version(void) { return KPP_ABI_VERSION; }

@@ -101,6 +101,23 @@ static void lsqr_case(int64_t m, int64_t n, int s, int memo) {
   hipFree(A); hipFree(b); hipFree(x);
 }
 
+// Several right-hand sides (both kinds, memo modes, k not a power of two).
+static void multi_case(int kind, int64_t m, int64_t n, int s, int memo, int k) {
+  kpp_context* ctx; CHECK(kpp_context_create(0, nullptr, &ctx));
+  double* A = dev_vec(m * n, 0.5); double* b = dev_vec(m, 1.0);
+  double* B = dev_vec(m * (k + 1), 1.0); double* X = dev_vec(n * (k + 2), 0.0);
+  kpp_system* sys; CHECK(kpp_system_create(ctx, kind, m, n, A, n, b, &sys));
+  kpp_params p; CHECK(kpp_params_default(&p, kind));
+  p.block_size = s; p.memo = memo; p.max_iters = 300; p.tol = 1e-10;
+  std::vector<kpp_result> r(k);
+  kpp_status st = kpp_solve_multi(sys, &p, k, B, k + 1, X, k + 2, r.data());
+  if (st < 0) { std::printf("FAIL multi: %d %s\n", st, kpp_last_error()); std::exit(1); }
+  std::printf("multi kind=%d k=%d st=%d iters[0]=%lld iters[k-1]=%lld misses=%lld\n", kind, k, st,
+              (long long)r[0].iters, (long long)r[k - 1].iters, (long long)r[0].memo_misses);
+  CHECK(kpp_system_destroy(sys)); CHECK(kpp_context_destroy(ctx));
+  hipFree(A); hipFree(b); hipFree(B); hipFree(X);
+}
+
 static void serve_case() {
   kpp_context* ctx; CHECK(kpp_context_create(0, nullptr, &ctx));
   struct J { int kind; int64_t m, n; int s; int prec; double tol; };
@@ -162,6 +179,9 @@ int main(int argc, char** argv) {
     lsqr_case(1000, 200, 20, 1);
     lsqr_case(700, 300, 160, 2);
     lsqr_case(400, 5000, 64, 0);
+    multi_case(0, 1000, 200, 20, 1, 5);
+    multi_case(1, 600, 600, 64, 2, 32);
+    multi_case(0, 300, 2500, 150, 0, 3);
   }
   if (!*only || !std::strcmp(only, "serve")) serve_case();
   std::printf("EMU OK\n");

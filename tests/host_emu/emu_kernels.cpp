@@ -11,6 +11,7 @@
 
 #include "kernels.hpp"
 #include "lsqr.hpp"
+#include "multi.hpp"
 
 namespace kpp {
 namespace {
@@ -237,6 +238,44 @@ void launch_lsqr_mid(const double* rpart, int32_t P, const double* Linv, int32_t
   emu_check(rpart, 8 * static_cast<size_t>(sb) * P, "lsqr rpart");
   emu_check(Linv, 8 * 2 * static_cast<size_t>(s) * s, "lsqr Linv and its transpose");
   emu_check(L, sizeof(LsqrState), "lsqr state");
+}
+
+// several right-hand sides
+void launch_block_gemm_partial(const double* A, int64_t lda, int64_t n, const int32_t* rows, int32_t sb,
+                               const double* X, int64_t ldx, int32_t k, double* rpart, int32_t P, int64_t,
+                               hipStream_t) {
+  check_rows(rows, sb, "multi rows");
+  check_A(A, 8, lda, rows, sb, n, "multi A");
+  emu_check(X, 8 * (static_cast<size_t>(n - 1) * ldx + k), "multi X");
+  emu_check(rpart, 8 * static_cast<size_t>(sb) * P * k, "multi rpart");
+}
+void launch_block_project_multi(const double* rpart, int32_t P, int32_t k, const double* B, int64_t ldb,
+                                const int32_t* rows, int32_t sb, const double* Ginv, int32_t s, double* Y,
+                                DevState* ds, const int32_t* frozen, int32_t zeta, int32_t, hipStream_t) {
+  emu_check(rpart, 8 * static_cast<size_t>(sb) * P * k, "multi rpart");
+  check_rows(rows, sb, "multi rows");
+  for (int32_t i = 0; i < sb; ++i) emu_check(B + static_cast<int64_t>(rows[i]) * ldb, 8 * static_cast<size_t>(k), "multi B");
+  emu_check(Ginv, 8 * static_cast<size_t>(s) * s, "multi Ginv");
+  emu_check(Y, 8 * static_cast<size_t>(k) * s, "multi Y");
+  emu_check(ds, sizeof(DevState) * k, "multi states");
+  emu_check(frozen, 4 * static_cast<size_t>(k), "multi frozen");
+  for (int32_t c = 0; c < k; ++c)
+    if (!frozen[c]) emu_step(ds + c, zeta, nullptr);
+}
+void launch_update_multi(int32_t, const double* A, int64_t lda, int64_t n, const int32_t* rows, int32_t sb,
+                         const double* Y, int32_t s, int32_t k, const DevState* ds, const int32_t* frozen, double,
+                         double* X, int64_t ldx, double* M, hipStream_t) {
+  check_rows(rows, sb, "multi rows");
+  check_A(A, 8, lda, rows, sb, n, "multi A");
+  emu_check(Y, 8 * static_cast<size_t>(k) * s, "multi Y");
+  emu_check(ds, sizeof(DevState) * k, "multi states");
+  emu_check(frozen, 4 * static_cast<size_t>(k), "multi frozen");
+  emu_check(X, 8 * (static_cast<size_t>(n - 1) * ldx + k), "multi X");
+  emu_check(M, 8 * static_cast<size_t>(n) * k, "multi momentum");
+}
+void launch_column(const double* X, int64_t ldx, int64_t n, int32_t c, double* out, hipStream_t) {
+  emu_check(X, 8 * (static_cast<size_t>(n - 1) * ldx + c + 1), "column source");
+  emu_check(out, 8 * static_cast<size_t>(n), "column out");
 }
 
 void launch_state_init(DevState* ds, double rho0, double thr, hipStream_t) {

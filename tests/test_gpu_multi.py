@@ -1,0 +1,176 @@
+"""GPU parity of kpp_solve_multi (several right-hand sides on one system)
+against the oracle run once per right-hand side with the same schedule and
+parameters, and against single kpp_solve calls on the GPU.
+
+Each right-hand side must follow its own single solve: the same iterates
+(FP64 noise-floor bound, as the single-solve parity cases), the same stop step
+at a tolerance, the same rho.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import kpp as okpp
+from oracle import schedule as osch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import paper_2501_11673_amd as kpp
+
+    assert torch.cuda.is_available()
+    dev = torch.device("cuda:0")
+    ctx = kpp.kpp_context_create(0, torch.cuda.current_stream(dev).cuda_stream)
+    yield kpp, torch, dev, ctx
+    kpp.kpp_context_destroy(ctx)
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def make_rhs(A, k, seed, x0_scale=0.0):
+    m, n = A.shape
+    rng = np.random.default_rng(seed)
+    Xs = rng.standard_normal((n, k))
+    B = A @ Xs
+    X0 = x0_scale * rng.standard_normal((n, k))
+    return B, X0
+
+
+def params(kpp, kind, s, lam, T, mode, seed, tol=0.0):
+    ck = kpp.KPP_CD_PSD if kind == "psd" else kpp.KPP_KACZMARZ
+    p = kpp.kpp_params_default(ck)
+    p.block_size = s
+    p.lambda_ = lam
+    p.tol = tol
+    p.max_iters = T
+    p.seed = seed
+    p.memo = {"off": 0, "online": 1, "fixed": 2}[mode]
+    p.fixed_partition = 1
+    return ck, p
+
+
+def run_multi(env, A, B, X0, kind, s, lam, T, mode, seed, tol=0.0, pad=0):
+    kpp, torch, dev, ctx = env
+    m, n = A.shape
+    k = B.shape[1]
+    ck, p = params(kpp, kind, s, lam, T, mode, seed, tol)
+    Bp = np.zeros((m, k + pad))
+    Bp[:, :k] = B
+    Xp = np.zeros((n, k + pad))
+    Xp[:, :k] = X0
+    Ad = torch.from_numpy(np.ascontiguousarray(A)).to(dev)
+    Bd = torch.from_numpy(Bp).to(dev)
+    Xd = torch.from_numpy(Xp).to(dev)
+    bd = torch.zeros(m, dtype=torch.float64, device=dev)
+    h = kpp.kpp_system_create(ctx, ck, m, n, Ad.data_ptr(), n, bd.data_ptr())
+    try:
+        st, res = kpp.kpp_solve_multi(h, p, k, Bd.data_ptr(), k + pad, Xd.data_ptr(), k + pad)
+    finally:
+        kpp.kpp_system_destroy(h)
+    X = Xd.cpu().numpy()
+    assert np.array_equal(X[:, k:], Xp[:, k:])   # padding columns untouched
+    return X[:, :k], st, res
+
+
+def oracle_one(A, b, x0, kind, s, lam, T, mode, seed, tol=0.0, reverse=False):
+    m, n = A.shape
+    N = n if kind == "psd" else m
+    schd = osch.make_schedule(mode, N, s, T, seed, B0=osch.online_rate(kind, m, n, s))
+    prm = okpp.Params(s=s, lam=lam, tol=tol, max_iters=T, memo=mode != "off", reverse_sums=reverse)
+    return okpp.solve(A, b, kind, prm, schd, x0=x0)
+
+
+@pytest.mark.parametrize("case,kind,cfg,s,lam,T,mode,k", [
+    ("c1_k5", "general", "c1", 20, 1e-3, 300, "online", 5),
+    ("c2_small_k7", "psd", "c2_small", 128, 1e-8, 160, "fixed", 7),
+    ("c4_small_k3", "general", "c4_small", 64, 1e-4, 120, "online", 3),
+    ("c1_k32_off", "general", "c1", 20, 1e-3, 80, "off", 32),
+    ("c3_small_k17", "general", "c3_small", 256, 1e-8, 60, "fixed", 17),
+])
+def test_multi_matches_oracle_per_column(env, case, kind, cfg, s, lam, T, mode, k):
+    print(f"multi parity {case}", flush=True)
+    sysm = synth.config(cfg)
+    A = sysm.A
+    B, X0 = make_rhs(A, k, 11, x0_scale=0.1)
+    X, st, res = run_multi(env, A, B, X0, kind, s, lam, T, mode, 7, pad=1)
+    for c in range(k):
+        ref = oracle_one(A, B[:, c], X0[:, c], kind, s, lam, T, mode, 7)
+        alt = oracle_one(A, B[:, c], X0[:, c], kind, s, lam, T, mode, 7, reverse=True)
+        nf = relerr(alt.x, ref.x)
+        assert res[c].iters == T
+        assert relerr(X[:, c], ref.x) <= max(1e-10, 10.0 * nf), (c, relerr(X[:, c], ref.x), nf)
+        rho_nf = abs(alt.rho_final - ref.rho_final)
+        assert abs(res[c].rho_final - ref.rho_final) <= max(1e-9 * abs(ref.rho_final), 1e-12, 10.0 * rho_nf)
+    assert res[0].memo_misses == ref.factorizations
+
+
+def test_multi_stops_each_rhs_where_a_single_solve_stops(env):
+    """Right-hand sides of different difficulty stop at their own checkpoint:
+    the step counts equal the oracle's and the GPU single solve's."""
+    kpp, torch, dev, ctx = env
+    sysm = synth.config("c1")
+    A = sysm.A
+    m, n = A.shape
+    rng = np.random.default_rng(2)
+    B = np.stack([A @ rng.standard_normal(n), sysm.b, A @ (1e3 * rng.standard_normal(n)),
+                  A @ rng.standard_normal(n)], axis=1)
+    X0 = np.zeros((n, 4))
+    X0[:, 3] = np.linalg.lstsq(A, B[:, 3], rcond=None)[0] + 1e-6 * rng.standard_normal(n)   # starts close
+    X, st, res = run_multi(env, A, B, X0, "general", 20, 1e-3, 50000, "online", 101, tol=1e-10)
+    assert st == kpp.KPP_OK
+    ck, p = params(kpp, "general", 20, 1e-3, 50000, "online", 101, tol=1e-10)
+    Ad = torch.from_numpy(A).to(dev)
+    iters = []
+    for c in range(4):
+        ref = oracle_one(A, B[:, c], X0[:, c], "general", 20, 1e-3, 50000, "online", 101, tol=1e-10)
+        bd = torch.from_numpy(np.ascontiguousarray(B[:, c])).to(dev)
+        xd = torch.from_numpy(np.ascontiguousarray(X0[:, c])).to(dev)
+        h = kpp.kpp_system_create(ctx, ck, m, n, Ad.data_ptr(), n, bd.data_ptr())
+        try:
+            st1, r1 = kpp.kpp_solve(h, p, xd.data_ptr())
+        finally:
+            kpp.kpp_system_destroy(h)
+        assert res[c].converged and ref.converged and r1.converged
+        assert res[c].iters == ref.iters == r1.iters, (c, res[c].iters, ref.iters, r1.iters)
+        assert np.linalg.norm(A @ X[:, c] - B[:, c]) <= 1e-10 * np.linalg.norm(B[:, c])
+        assert relerr(X[:, c], xd.cpu().numpy()) <= 1e-8
+        iters.append(res[c].iters)
+    assert len(set(iters)) > 1      # the right-hand sides stopped at different steps
+
+
+def test_multi_one_rhs_equals_single_solve(env):
+    kpp, torch, dev, ctx = env
+    sysm = synth.config("c2_small")
+    A = sysm.A
+    B = sysm.b[:, None].copy()
+    X, st, res = run_multi(env, A, B, np.zeros((A.shape[1], 1)), "psd", 128, 1e-8, 200, "online", 9)
+    ref = oracle_one(A, sysm.b, None, "psd", 128, 1e-8, 200, "online", 9)
+    alt = oracle_one(A, sysm.b, None, "psd", 128, 1e-8, 200, "online", 9, reverse=True)
+    assert relerr(X[:, 0], ref.x) <= max(1e-10, 10.0 * relerr(alt.x, ref.x))
+
+
+def test_multi_rejections(env):
+    kpp, torch, dev, ctx = env
+    sysm = synth.tiny_system("general", 40, 20, seed=1)
+    Ad = torch.from_numpy(sysm.A).to(dev)
+    bd = torch.from_numpy(sysm.b).to(dev)
+    Bd = torch.zeros((40, 40), dtype=torch.float64, device=dev)
+    Xd = torch.zeros((20, 40), dtype=torch.float64, device=dev)
+    h = kpp.kpp_system_create(ctx, kpp.KPP_KACZMARZ, 40, 20, Ad.data_ptr(), 20, bd.data_ptr())
+    try:
+        p = kpp.kpp_params_default(kpp.KPP_KACZMARZ)
+        p.block_size = 4
+        for k, ldb, ldx in ((0, 1, 1), (33, 33, 33), (4, 3, 4), (4, 4, 2)):
+            with pytest.raises(kpp.KppError):
+                kpp.kpp_solve_multi(h, p, k, Bd.data_ptr(), ldb, Xd.data_ptr(), ldx)
+        p.rht = 1
+        with pytest.raises(kpp.KppError):
+            kpp.kpp_solve_multi(h, p, 2, Bd.data_ptr(), 2, Xd.data_ptr(), 2)
+    finally:
+        kpp.kpp_system_destroy(h)
