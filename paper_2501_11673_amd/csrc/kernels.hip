@@ -170,38 +170,55 @@ __global__ __launch_bounds__(kT) void k_update(const double* __restrict__ A, int
 // several right-hand sides: the same three phases, every A_S element used for
 // all k columns (registers hold k sums per thread)
 // --------------------------------------------------------------------------
-template <int KM>
-__global__ __launch_bounds__(kT) void k_block_gemm_partial(const double* __restrict__ A, int64_t lda, int64_t n,
-                                                           const int32_t* __restrict__ rows,
-                                                           const double* __restrict__ X, int64_t ldx, int32_t k,
-                                                           double* __restrict__ rpart, int32_t P, int64_t chunk) {
-  __shared__ double red[4][kMaxRhs];
-  const int i = blockIdx.y;
-  const int p = blockIdx.x;
-  const double* Ai = A + static_cast<int64_t>(rows[i]) * lda;
-  const int64_t j0 = static_cast<int64_t>(p) * chunk;
-  const int64_t j1 = min(n, j0 + chunk);
-  double acc[KM];
-#pragma unroll
-  for (int c = 0; c < KM; ++c) acc[c] = 0.0;
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += kT) {
-    const double a = Ai[j];
-    const double* xr = X + j * ldx;
-#pragma unroll
-    for (int c = 0; c < KM; ++c)
-      if (c < k) acc[c] = fma(a, xr[c], acc[c]);
-  }
+// R = A_S X on the matrix cores (FP64 16x16x4): workgroup (p, ti) forms the
+// 16-row tile ti of R over column chunk p of A, each wave a quarter of the
+// chunk; the four wave tiles are summed in a fixed order.  Operands of the
+// MFMA: lane l supplies A[row ti 16 + l % 16][k + l / 16] and
+// X[k + l / 16][c0 + l % 16]; register r of lane l returns R[l / 16 + 4 r][c0 + l % 16]
+// (the layout the Gram kernels use).  NT tiles of 16 right-hand sides.
+typedef double v4d_m __attribute__((ext_vector_type(4)));
+template <int NT>
+__global__ __launch_bounds__(kT) void k_block_gemm_mfma(const double* __restrict__ A, int64_t lda, int64_t n,
+                                                        const int32_t* __restrict__ rows, int32_t sb,
+                                                        const double* __restrict__ X, int64_t ldx, int32_t k,
+                                                        double* __restrict__ rpart, int32_t P) {
+  __shared__ double red[4][NT][4][64];
+  const int p = blockIdx.x, i0 = blockIdx.y * 16;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const bool rok = i0 + li < sb;
+  const double* Arow = A + static_cast<int64_t>(rows[rok ? i0 + li : 0]) * lda;
+  const int64_t kb = static_cast<int64_t>(p) * kGemmChunk + w * (kGemmChunk / 4);
+  const int64_t ke = min(n, kb + kGemmChunk / 4);
+  v4d_m acc[NT];
 #pragma unroll
-  for (int c = 0; c < KM; ++c) {
-    double v = acc[c];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if (lane == 0 && c < k) red[w][c] = v;
+  for (int t = 0; t < NT; ++t) acc[t] = v4d_m{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int64_t k0 = kb; k0 < ke; k0 += 4) {
+    const int64_t kk = k0 + lk;
+    const bool kok = kk < ke;
+    const double a = (rok && kok) ? Arow[kk] : 0.0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int c = 16 * t + li;
+      const double b = (kok && c < k) ? X[kk * ldx + c] : 0.0;
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+    }
   }
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[w][t][r][lane] = acc[t][r];
   __syncthreads();
-  if (threadIdx.x < k) {
-    const int c = threadIdx.x;
-    rpart[(static_cast<int64_t>(i) * P + p) * k + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+  if (w == 0) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double v = (red[0][t][r][lane] + red[1][t][r][lane]) + (red[2][t][r][lane] + red[3][t][r][lane]);
+        const int i = i0 + lk + 4 * r, c = 16 * t + li;
+        if (i < sb && c < k) rpart[(static_cast<int64_t>(i) * P + p) * k + c] = v;
+      }
   }
 }
 
@@ -1176,17 +1193,12 @@ void launch_update(int32_t kind, const double* A, int64_t lda, int64_t n, const 
 }
 
 void launch_block_gemm_partial(const double* A, int64_t lda, int64_t n, const int32_t* rows, int32_t sb,
-                               const double* X, int64_t ldx, int32_t k, double* rpart, int32_t P, int64_t chunk,
-                               hipStream_t st) {
-  const dim3 grid(P, sb);
-  if (k <= 4)
-    hipLaunchKernelGGL(k_block_gemm_partial<4>, grid, dim3(kT), 0, st, A, lda, n, rows, X, ldx, k, rpart, P, chunk);
-  else if (k <= 8)
-    hipLaunchKernelGGL(k_block_gemm_partial<8>, grid, dim3(kT), 0, st, A, lda, n, rows, X, ldx, k, rpart, P, chunk);
-  else if (k <= 16)
-    hipLaunchKernelGGL(k_block_gemm_partial<16>, grid, dim3(kT), 0, st, A, lda, n, rows, X, ldx, k, rpart, P, chunk);
+                               const double* X, int64_t ldx, int32_t k, double* rpart, int32_t P, hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>(P), static_cast<unsigned>((sb + 15) / 16));
+  if (k <= 16)
+    hipLaunchKernelGGL(k_block_gemm_mfma<1>, grid, dim3(kT), 0, st, A, lda, n, rows, sb, X, ldx, k, rpart, P);
   else
-    hipLaunchKernelGGL(k_block_gemm_partial<32>, grid, dim3(kT), 0, st, A, lda, n, rows, X, ldx, k, rpart, P, chunk);
+    hipLaunchKernelGGL(k_block_gemm_mfma<2>, grid, dim3(kT), 0, st, A, lda, n, rows, sb, X, ldx, k, rpart, P);
 }
 
 void launch_block_project_multi(const double* rpart, int32_t P, int32_t k, const double* B, int64_t ldb,

@@ -15,11 +15,13 @@
 namespace kpp {
 
 constexpr int kMaxRhs = 32;
+constexpr int64_t kGemmChunk = 256;   // columns of A per partial of the block product
+inline int32_t gemm_parts(int64_t n) { return static_cast<int32_t>((n + kGemmChunk - 1) / kGemmChunk); }
 
-// rpart[(i P + p) k + c] = sum_{j in chunk p} A[rows[i], j] X[j, c]
+// rpart[(i P + p) k + c] = sum_{j in chunk p} A[rows[i], j] X[j, c], P = gemm_parts(n)
+// (FP64 matrix cores)
 void launch_block_gemm_partial(const double* A, int64_t lda, int64_t n, const int32_t* rows, int32_t sb,
-                               const double* X, int64_t ldx, int32_t k, double* rpart, int32_t P, int64_t chunk,
-                               hipStream_t st);
+                               const double* X, int64_t ldx, int32_t k, double* rpart, int32_t P, hipStream_t st);
 // per right-hand side c with frozen[c] == 0: r_c = sum_p rpart - B[rows, c],
 // the step's bookkeeping in ds[c], and Y[c s + i] = (G^{-1} r_c)_i
 void launch_block_project_multi(const double* rpart, int32_t P, int32_t k, const double* B, int64_t ldb,

@@ -2231,8 +2231,7 @@ kpp_status solve_multi(kpp_system* sys, const kpp_params* p, int32_t k, const do
   const auto mode = static_cast<kpp::MemoMode>(p->memo);
   kpp::BlockSchedule sch(mode, N, s, p->seed, kpp::online_rate(kind, m, n, s), p->num_blocks,
                          p->fixed_partition != 0);
-  constexpr int64_t kChunk = 2048;
-  const int32_t P = static_cast<int32_t>((n + kChunk - 1) / kChunk);
+  const int32_t P = kpp::gemm_parts(n);
   const int64_t stride = kpp::slot_doubles(s);
   // ||b_c|| on the host
   std::vector<double> hb(static_cast<size_t>(m) * ldb);
@@ -2254,7 +2253,7 @@ kpp_status solve_multi(kpp_system* sys, const kpp_params* p, int32_t k, const do
   KPP_TRY(ds.alloc(k));
   KPP_TRY(frozen.alloc(k));
   KPP_TRY(err.alloc(1));
-  if (kind == KPP_KACZMARZ) KPP_TRY(ws.alloc(kpp::gram_syrk_work(s, n, 1)));
+  if (kind == KPP_KACZMARZ) KPP_TRY(ws.alloc(kpp::gram_syrk_work(s, n, static_cast<int32_t>(period))));
   HIP_TRY(hipMemsetAsync(mom.p, 0, static_cast<size_t>(n) * k * sizeof(double), st));
   HIP_TRY(hipMemsetAsync(frozen.p, 0, k * sizeof(int32_t), st));
   HIP_TRY(hipMemsetAsync(err.p, 0, sizeof(int32_t), st));
@@ -2269,7 +2268,7 @@ kpp_status solve_multi(kpp_system* sys, const kpp_params* p, int32_t k, const do
   }
   HIP_TRY(hipMemcpy(ds.p, hds.data(), k * sizeof(kpp::DevState), hipMemcpyHostToDevice));
   // memo slots (one for every block in OFF mode: factored at every step)
-  int64_t cap = 1;
+  int64_t cap = period;   // OFF: the blocks of one window
   if (mode == kpp::MemoMode::Fixed) cap = sch.num_blocks();
   if (mode == kpp::MemoMode::Online) cap = std::min<int64_t>(static_cast<int64_t>(4.0 * kpp::online_rate(kind, m, n, s)) + 16,
                                                             std::max<int64_t>(16, p->max_iters + 1));
@@ -2301,7 +2300,7 @@ kpp_status solve_multi(kpp_system* sys, const kpp_params* p, int32_t k, const do
   };
   KPP_TRY(grow(cap));
   std::vector<int32_t> slot_of;
-  std::vector<int32_t> stage(static_cast<size_t>(s) + 1);
+  std::vector<int32_t> stage_rows, stage_lens;
   std::vector<int32_t> hfrozen(k, 0);
   std::vector<int64_t> iters(k, -1);
   std::vector<double> true_rel(k, NAN);
@@ -2319,49 +2318,73 @@ kpp_status solve_multi(kpp_system* sys, const kpp_params* p, int32_t k, const do
     return KPP_OK;
   };
   int32_t active = k;
+  std::vector<int32_t> wblock, wslot;
   while (t < p->max_iters && active > 0) {
-    bool is_new = false;
-    const int32_t b = sch.next(&is_new);
-    int32_t q = 0;
-    bool factor = true;
-    if (mode != kpp::MemoMode::Off) {
-      if (static_cast<int32_t>(slot_of.size()) <= b) slot_of.resize(b + 1, -1);
-      if (slot_of[b] < 0) {
-        KPP_TRY(grow(used + 1));
-        slot_of[b] = used++;
+    // one checkpoint window: its steps drawn first (the schedule never looks
+    // at x), its new blocks factored in one batch, then its steps
+    const int64_t W = std::min<int64_t>(period - t % period, p->max_iters - t);
+    wblock.assign(W, 0);
+    wslot.assign(W, 0);
+    stage_rows.clear();
+    stage_lens.clear();
+    int32_t q0 = -1, nb = 0;
+    for (int64_t j = 0; j < W; ++j) {
+      bool is_new = false;
+      const int32_t b = sch.next(&is_new);
+      wblock[j] = b;
+      int32_t q;
+      bool fresh = true;
+      if (mode == kpp::MemoMode::Off) {
+        q = static_cast<int32_t>(j);
       } else {
-        factor = false;
+        if (static_cast<int32_t>(slot_of.size()) <= b) slot_of.resize(b + 1, -1);
+        if (slot_of[b] < 0) {
+          KPP_TRY(grow(used + 1));
+          slot_of[b] = used++;
+        } else {
+          fresh = false;
+        }
+        q = slot_of[b];
       }
-      q = slot_of[b];
+      wslot[j] = q;
+      if (fresh) {
+        if (q0 < 0) q0 = q;   // new slots of a window are consecutive
+        const int32_t sb = sch.len(b);
+        stage_rows.insert(stage_rows.end(), sch.rows(b), sch.rows(b) + sb);
+        stage_rows.insert(stage_rows.end(), static_cast<size_t>(s - sb), 0);
+        stage_lens.push_back(sb);
+        ++nb;
+        ++misses;
+      } else {
+        ++hits;
+      }
     }
-    const int32_t sb = sch.len(b);
-    if (factor) {
-      std::copy(sch.rows(b), sch.rows(b) + sb, stage.begin());
-      std::fill(stage.begin() + sb, stage.begin() + s, 0);
-      stage[s] = sb;
-      HIP_TRY(hipMemcpy(rows.p + static_cast<size_t>(q) * s, stage.data(), s * sizeof(int32_t), hipMemcpyHostToDevice));
-      HIP_TRY(hipMemcpy(lens.p + q, &stage[s], sizeof(int32_t), hipMemcpyHostToDevice));
-      kpp::launch_gram(kind, sys->A, sys->lda, n, rows.p + static_cast<size_t>(q) * s, lens.p + q, s, 1, p->lambda,
-                       L.p, stride, ids.p + q, ws.p, st);
+    if (nb > 0) {
+      HIP_TRY(hipMemcpy(rows.p + static_cast<size_t>(q0) * s, stage_rows.data(), stage_rows.size() * sizeof(int32_t),
+                        hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy(lens.p + q0, stage_lens.data(), stage_lens.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+      kpp::launch_gram(kind, sys->A, sys->lda, n, rows.p + static_cast<size_t>(q0) * s, lens.p + q0, s, nb, p->lambda,
+                       L.p, stride, ids.p + q0, ws.p, st);
       if (s <= kpp::kFactorSmallMax) {
-        kpp::launch_factor_small(L.p, stride, s, lens.p + q, 1, ids.p + q, 1, err.p, st);
+        kpp::launch_factor_small(L.p, stride, s, lens.p + q0, nb, ids.p + q0, 1, err.p, st);
       } else {
-        kpp::launch_cholesky(L.p, s, stride, lens.p + q, 1, ids.p + q, err.p, st);
-        kpp::launch_factor_inverse(L.p, stride, s, lens.p + q, 1, ids.p + q, st);
+        kpp::launch_cholesky(L.p, s, stride, lens.p + q0, nb, ids.p + q0, err.p, st);
+        kpp::launch_factor_inverse(L.p, stride, s, lens.p + q0, nb, ids.p + q0, st);
       }
-      ++misses;
-    } else {
-      ++hits;
     }
-    const int32_t* r = rows.p + static_cast<size_t>(q) * s;
-    const double* Gi = L.p + static_cast<size_t>(q) * stride + static_cast<size_t>(s) * s;
-    kpp::launch_block_gemm_partial(sys->A, sys->lda, n, r, sb, X, ldx, k, rpart.p, P, kChunk, st);
-    kpp::launch_block_project_multi(rpart.p, P, k, B, ldb, r, sb, Gi, s, Y.p, ds.p, frozen.p, zeta,
-                                    p->adaptive_rho, st);
-    kpp::launch_update_multi(kind, sys->A, sys->lda, n, r, sb, Y.p, s, k, ds.p, frozen.p, eta, X, ldx, mom.p, st);
+    for (int64_t j = 0; j < W; ++j) {
+      const int32_t q = wslot[j];
+      const int32_t sb = sch.len(wblock[j]);
+      const int32_t* r = rows.p + static_cast<size_t>(q) * s;
+      const double* Gi = L.p + static_cast<size_t>(q) * stride + static_cast<size_t>(s) * s;
+      kpp::launch_block_gemm_partial(sys->A, sys->lda, n, r, sb, X, ldx, k, rpart.p, P, st);
+      kpp::launch_block_project_multi(rpart.p, P, k, B, ldb, r, sb, Gi, s, Y.p, ds.p, frozen.p, zeta,
+                                      p->adaptive_rho, st);
+      kpp::launch_update_multi(kind, sys->A, sys->lda, n, r, sb, Y.p, s, k, ds.p, frozen.p, eta, X, ldx, mom.p, st);
+    }
     HIP_TRY(hipGetLastError());
-    ++t;
-    if (t % period == 0 || t == p->max_iters) {
+    t += W;
+    {
       int32_t herr = 0;
       HIP_TRY(hipMemcpyAsync(hds.data(), ds.p, k * sizeof(kpp::DevState), hipMemcpyDeviceToHost, st));
       HIP_TRY(hipMemcpyAsync(&herr, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));

@@ -242,8 +242,8 @@ void launch_lsqr_mid(const double* rpart, int32_t P, const double* Linv, int32_t
 
 // several right-hand sides
 void launch_block_gemm_partial(const double* A, int64_t lda, int64_t n, const int32_t* rows, int32_t sb,
-                               const double* X, int64_t ldx, int32_t k, double* rpart, int32_t P, int64_t,
-                               hipStream_t) {
+                               const double* X, int64_t ldx, int32_t k, double* rpart, int32_t P, hipStream_t) {
+  if (P != gemm_parts(n)) { std::fprintf(stderr, "EMU: gemm parts %d for n=%lld\n", P, (long long)n); std::abort(); }
   check_rows(rows, sb, "multi rows");
   check_A(A, 8, lda, rows, sb, n, "multi A");
   emu_check(X, 8 * (static_cast<size_t>(n - 1) * ldx + k), "multi X");

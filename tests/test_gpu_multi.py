@@ -103,10 +103,16 @@ def test_multi_matches_oracle_per_column(env, case, kind, cfg, s, lam, T, mode, 
         ref = oracle_one(A, B[:, c], X0[:, c], kind, s, lam, T, mode, 7)
         alt = oracle_one(A, B[:, c], X0[:, c], kind, s, lam, T, mode, 7, reverse=True)
         nf = relerr(alt.x, ref.x)
+        bound = max(1e-10, 10.0 * nf)
         assert res[c].iters == T
-        assert relerr(X[:, c], ref.x) <= max(1e-10, 10.0 * nf), (c, relerr(X[:, c], ref.x), nf)
+        assert relerr(X[:, c], ref.x) <= bound, (c, relerr(X[:, c], ref.x), nf)
+        # rho = 1 - (E1/E0)^(1/zeta) is formed from window sums of residuals that
+        # are small beside their terms, so it carries the iterate's rounding
+        # noise amplified: held to ten times the iterate's bound (relative),
+        # which is the 1e-9 of the well-conditioned cases
         rho_nf = abs(alt.rho_final - ref.rho_final)
-        assert abs(res[c].rho_final - ref.rho_final) <= max(1e-9 * abs(ref.rho_final), 1e-12, 10.0 * rho_nf)
+        rho_tol = max(10.0 * bound * abs(ref.rho_final), 1e-12, 10.0 * rho_nf)
+        assert abs(res[c].rho_final - ref.rho_final) <= rho_tol, (c, res[c].rho_final, ref.rho_final, nf)
     assert res[0].memo_misses == ref.factorizations
 
 
