@@ -242,10 +242,19 @@ __global__ __launch_bounds__(kT) void k_block_project_multi(
   }
   const double rr = block_sum(part, red);
   __syncthreads();
-  for (int i = tid; i < sb; i += kT) {
+  // y = G^{-1} r: four threads per row (q = part, part + 4, ...), added in a fixed order
+  __shared__ double part4[4][kT / 4];
+  const int i0 = tid & (kT / 4 - 1), pt = tid / (kT / 4);
+  for (int ib = 0; ib < sb; ib += kT / 4) {
+    const int i = ib + i0;
     double acc = 0.0;
-    for (int q = 0; q < sb; ++q) acc = fma(Ginv[static_cast<int64_t>(q) * ldl + i], r[q], acc);
-    Y[static_cast<int64_t>(c) * ldl + i] = acc;
+    if (i < sb)
+      for (int q = pt; q < sb; q += 4) acc = fma(Ginv[static_cast<int64_t>(q) * ldl + i], r[q], acc);
+    part4[pt][i0] = acc;
+    __syncthreads();
+    if (pt == 0 && i < sb)
+      Y[static_cast<int64_t>(c) * ldl + i] = (part4[0][i0] + part4[1][i0]) + (part4[2][i0] + part4[3][i0]);
+    __syncthreads();
   }
   if (tid == 0) step_state(ds + c, rr, zeta, adaptive);
 }
@@ -303,6 +312,36 @@ __global__ __launch_bounds__(kT) void k_update_multi(const double* __restrict__ 
       xr[c] = __dadd_rn(__dsub_rn(xr[c], w[c]), __dmul_rn(eta, mn));
     }
   }
+}
+
+// CD++ update with one thread per (coordinate j, right-hand side c): w is
+// y_c at j's position in the block, or 0
+__global__ __launch_bounds__(kT) void k_update_multi_cd(int64_t n, const int32_t* __restrict__ rows, int32_t sb,
+                                                        const double* __restrict__ Y, int32_t s, int32_t k,
+                                                        const DevState* __restrict__ ds,
+                                                        const int32_t* __restrict__ frozen, double eta,
+                                                        double* __restrict__ X, int64_t ldx, double* __restrict__ M) {
+  __shared__ int32_t rs[kMaxBlock];
+  for (int i = threadIdx.x; i < sb; i += kT) rs[i] = rows[i];
+  __syncthreads();
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+  if (e >= n * k) return;
+  const int64_t j = e / k;
+  const int c = static_cast<int>(e - j * k);
+  if (frozen[c]) return;
+  int lo = 0, hi = sb;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (rs[mid] < j)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  const double w = (lo < sb && rs[lo] == j) ? Y[static_cast<int64_t>(c) * s + lo] : 0.0;
+  const double mn = __dmul_rn(ds[c].c, __dsub_rn(M[e], w));
+  M[e] = mn;
+  double* xe = X + j * ldx + c;
+  *xe = __dadd_rn(__dsub_rn(*xe, w), __dmul_rn(eta, mn));
 }
 
 __global__ __launch_bounds__(kT) void k_column(const double* __restrict__ X, int64_t ldx, int64_t n, int32_t c,
@@ -1215,17 +1254,16 @@ void launch_update_multi(int32_t kind, const double* A, int64_t lda, int64_t n, 
 #define KPP_UPDATE_MULTI(KIND, KM)                                                                               \
   hipLaunchKernelGGL((k_update_multi<KIND, KM>), grid, dim3(kT), 0, st, A, lda, n, rows, sb, Y, s, k, ds, frozen, \
                      eta, X, ldx, M)
-  if (kind == 0) {
-    if (k <= 4) KPP_UPDATE_MULTI(0, 4);
-    else if (k <= 8) KPP_UPDATE_MULTI(0, 8);
-    else if (k <= 16) KPP_UPDATE_MULTI(0, 16);
-    else KPP_UPDATE_MULTI(0, 32);
-  } else {
-    if (k <= 4) KPP_UPDATE_MULTI(1, 4);
-    else if (k <= 8) KPP_UPDATE_MULTI(1, 8);
-    else if (k <= 16) KPP_UPDATE_MULTI(1, 16);
-    else KPP_UPDATE_MULTI(1, 32);
+  if (kind == 1) {
+    const int64_t total = n * k;
+    hipLaunchKernelGGL(k_update_multi_cd, dim3(static_cast<unsigned>((total + kT - 1) / kT)), dim3(kT), 0, st, n,
+                       rows, sb, Y, s, k, ds, frozen, eta, X, ldx, M);
+    return;
   }
+  if (k <= 4) KPP_UPDATE_MULTI(0, 4);
+  else if (k <= 8) KPP_UPDATE_MULTI(0, 8);
+  else if (k <= 16) KPP_UPDATE_MULTI(0, 16);
+  else KPP_UPDATE_MULTI(0, 32);
 #undef KPP_UPDATE_MULTI
 }
 
