@@ -242,19 +242,10 @@ __global__ __launch_bounds__(kT) void k_block_project_multi(
   }
   const double rr = block_sum(part, red);
   __syncthreads();
-  // y = G^{-1} r: four threads per row (q = part, part + 4, ...), added in a fixed order
-  __shared__ double part4[4][kT / 4];
-  const int i0 = tid & (kT / 4 - 1), pt = tid / (kT / 4);
-  for (int ib = 0; ib < sb; ib += kT / 4) {
-    const int i = ib + i0;
+  for (int i = tid; i < sb; i += kT) {
     double acc = 0.0;
-    if (i < sb)
-      for (int q = pt; q < sb; q += 4) acc = fma(Ginv[static_cast<int64_t>(q) * ldl + i], r[q], acc);
-    part4[pt][i0] = acc;
-    __syncthreads();
-    if (pt == 0 && i < sb)
-      Y[static_cast<int64_t>(c) * ldl + i] = (part4[0][i0] + part4[1][i0]) + (part4[2][i0] + part4[3][i0]);
-    __syncthreads();
+    for (int q = 0; q < sb; ++q) acc = fma(Ginv[static_cast<int64_t>(q) * ldl + i], r[q], acc);
+    Y[static_cast<int64_t>(c) * ldl + i] = acc;
   }
   if (tid == 0) step_state(ds + c, rr, zeta, adaptive);
 }
