@@ -72,6 +72,11 @@ def test_rht_argument_checks(kpp):
     with pytest.raises(kpp.KppError):
         kpp.kpp_rht_signs(1, -1)
     p = kpp.kpp_params_default(kpp.KPP_KACZMARZ)
+    # several right-hand sides: a NULL system (or B, X) is refused before any device work
+    for sys_, B, X in ((0, 8, 8), (8, 0, 8), (8, 8, 0)):
+        with pytest.raises(kpp.KppError) as e:
+            kpp.kpp_solve_multi(sys_, p, 2, B, 2, X, 2)
+        assert e.value.status == kpp.KPP_ERR_INVALID_ARG
     assert p.rht == 0 and p.rht_seed == 0
     assert p.projection == kpp.KPP_PROJ_EXACT and p.lsqr_iters == 8 and p.sketch_size == 0
 
