@@ -165,13 +165,13 @@ struct kpp_system {
   double* lsqr_part = nullptr;
   double* lsqr_Xt = nullptr;
   double* lsqr_Y = nullptr;
-  double* lsqr_Ahat = nullptr;
-  int32_t* lsqr_iota = nullptr;
+  double* lsqr_Ahat = nullptr;   // the sketches of up to lsqr_cap_chunk blocks, s x tau each
+  int32_t* lsqr_iota = nullptr;   // their row indices in that stack: k s + i
   int8_t* lsqr_signs = nullptr;
   int32_t* lsqr_T[2] = {nullptr, nullptr};
   size_t lsqr_T_cap[2] = {0, 0};
   int64_t lsqr_cap_n = 0, lsqr_cap_N = 0;
-  int32_t lsqr_cap_s = 0, lsqr_cap_tau = 0;
+  int32_t lsqr_cap_s = 0, lsqr_cap_tau = 0, lsqr_cap_chunk = 0;
   int32_t sig_proj = 0;
 };
 
@@ -205,7 +205,7 @@ void drop_lsqr(kpp_system* s) {
     s->lsqr_T_cap[i] = 0;
   }
   s->lsqr_cap_n = s->lsqr_cap_N = 0;
-  s->lsqr_cap_s = s->lsqr_cap_tau = 0;
+  s->lsqr_cap_s = s->lsqr_cap_tau = s->lsqr_cap_chunk = 0;
 }
 
 void destroy_buffers(kpp_system* s) {
@@ -490,6 +490,8 @@ constexpr double kStallRatio = 0.9;
 // team: forming all of y reads the whole s x s inverse in every workgroup
 // (512 KB per workgroup per step at s = 256), one more exchange costs less
 constexpr int32_t kYSplitMinBlock = 128;
+// most sketches of the LSQR projection stacked for one batched factoring
+constexpr int64_t kSketchBatch = 256;
 
 struct CoreStats {
   int64_t iters = 0, hits = 0, misses = 0, launches = 0;
@@ -1041,7 +1043,13 @@ class CoreRun {
     tau_ = static_cast<int32_t>(std::min<int64_t>(p->sketch_size > 0 ? p->sketch_size : 2 * static_cast<int64_t>(s_), Nsk_));
     lsqr_iters_ = p->lsqr_iters;
     sk_gen_ = kpp::SplitMix64(p->sketch_seed);
-    if (sys->lsqr_cap_n < n_ || sys->lsqr_cap_N < Nsk_ || sys->lsqr_cap_s < s_ || sys->lsqr_cap_tau < tau_) {
+    // a window's new blocks are factored in batches of up to this many
+    // sketches (at most 2^25 doubles, 256 MB, of stacked sketches)
+    const int64_t per = static_cast<int64_t>(s_) * tau_;
+    chunk_ = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(kSketchBatch, (int64_t{1} << 25) / per)));
+    if (sys->lsqr_cap_n < n_ || sys->lsqr_cap_N < Nsk_ || sys->lsqr_cap_s < s_ || sys->lsqr_cap_tau < tau_ ||
+        static_cast<int64_t>(sys->lsqr_cap_chunk) * sys->lsqr_cap_s * sys->lsqr_cap_tau < chunk_ * per ||
+        static_cast<int64_t>(sys->lsqr_cap_chunk) * sys->lsqr_cap_s < static_cast<int64_t>(chunk_) * s_) {
       HIP_TRY(hipStreamSynchronize(st_));
       HIP_TRY(hipStreamSynchronize(side_));
       drop_lsqr(sys);
@@ -1051,8 +1059,9 @@ class CoreRun {
           (stt = dev_alloc(&sys->lsqr_ppart, static_cast<int64_t>(kpp::lsqr_at_chunks(s_)) * n_)) < 0 ||
           (stt = dev_alloc(&sys->lsqr_part, groups)) < 0 || (stt = dev_alloc(&sys->lsqr_Xt, n_ * s_)) < 0 ||
           (stt = dev_alloc(&sys->lsqr_Y, Nsk_ * s_)) < 0 ||
-          (stt = dev_alloc(&sys->lsqr_Ahat, static_cast<int64_t>(s_) * tau_)) < 0 ||
-          (stt = dev_alloc(&sys->lsqr_iota, s_)) < 0 || (stt = dev_alloc(&sys->lsqr_signs, Nsk_)) < 0) {
+          (stt = dev_alloc(&sys->lsqr_Ahat, chunk_ * per)) < 0 ||
+          (stt = dev_alloc(&sys->lsqr_iota, static_cast<int64_t>(chunk_) * s_)) < 0 ||
+          (stt = dev_alloc(&sys->lsqr_signs, Nsk_)) < 0) {
         drop_lsqr(sys);
         return stt;
       }
@@ -1060,8 +1069,9 @@ class CoreRun {
       sys->lsqr_cap_N = Nsk_;
       sys->lsqr_cap_s = s_;
       sys->lsqr_cap_tau = tau_;
+      sys->lsqr_cap_chunk = chunk_;
     }
-    std::vector<int32_t> iota(static_cast<size_t>(s_));
+    std::vector<int32_t> iota(static_cast<size_t>(chunk_) * s_);
     std::iota(iota.begin(), iota.end(), 0);
     std::vector<int8_t> sg(static_cast<size_t>(Nsk_));
     for (auto& v : sg) v = (sk_gen_.next() >> 63) ? int8_t{-1} : int8_t{1};
@@ -1144,35 +1154,46 @@ class CoreRun {
       sys->lsqr_T_cap[idx] = nT;
     }
     HIP_TRY(hipMemcpyAsync(sys->lsqr_T[idx], Th.data(), nT * sizeof(int32_t), hipMemcpyHostToDevice, fs));
-    KPP_TRY(ensure_gram_ws(sys, idx, kpp::gram_syrk_work(s_, tau_, 1)));
+    // split-Gram workspace for a full batch and for the last, shorter one
+    const int32_t tail = w.nb % chunk_;
+    KPP_TRY(ensure_gram_ws(sys, idx, std::max(kpp::gram_syrk_work(s_, tau_, std::min(chunk_, w.nb)),
+                                              tail ? kpp::gram_syrk_work(s_, tau_, tail) : size_t{0})));
     const int32_t* d_slens = sys->d_stage[idx] + w.o_len;
     const int32_t* d_sslot = sys->d_stage[idx] + w.o_slot;
     const double iscale = 1.0 / std::sqrt(static_cast<double>(Nsk_));
     const double scale = std::sqrt(static_cast<double>(Nsk_) / static_cast<double>(tau_));
-    for (int32_t k = 0; k < w.nb; ++k) {
-      const int32_t q = sys->h_stage[idx][w.o_slot + k];
-      const int32_t sb = sys->h_stage[idx][w.o_len + k];
-      const int32_t* rows = sys->rows + static_cast<size_t>(q) * s_;
-      kpp::launch_sketch_gather(src_.A64, src_.lda, n_, rows, sb, s_, sys->lsqr_Xt, fs);
-      kpp::FhtSpec f;
-      f.in = sys->lsqr_Xt;
-      f.ld_in = s_;
-      f.rows_valid = n_;
-      f.cols_valid = s_;
-      f.isign = sys->lsqr_signs;
-      f.iscale = iscale;
-      f.out = sys->lsqr_Y;
-      f.ld_out = s_;
-      f.rows_out = Nsk_;
-      f.M = Nsk_;
-      f.ncols = s_;
-      kpp::launch_fht(f, fs);
-      kpp::launch_sketch_select(sys->lsqr_Y, s_, sys->lsqr_T[idx] + static_cast<size_t>(k) * tau_, tau_, sb, scale,
-                                sys->lsqr_Ahat, fs);
-      kpp::launch_gram(KPP_KACZMARZ, sys->lsqr_Ahat, tau_, tau_, sys->lsqr_iota, d_slens + k, s_, 1, prm_.lambda,
-                       sys->L, sys->slot_stride, d_sslot + k, sys->gram_ws[idx], fs);
-      kpp::launch_cholesky(sys->L, s_, sys->slot_stride, d_slens + k, 1, d_sslot + k, sys->err, fs);
-      kpp::launch_factor_linv(sys->L, sys->slot_stride, s_, d_slens + k, 1, d_sslot + k, fs);
+    const size_t per = static_cast<size_t>(s_) * tau_;
+    for (int32_t k0 = 0; k0 < w.nb; k0 += chunk_) {
+      // the sketches of up to chunk_ new blocks, stacked s x tau each ...
+      const int32_t nk = std::min(chunk_, w.nb - k0);
+      for (int32_t j = 0; j < nk; ++j) {
+        const int32_t k = k0 + j;
+        const int32_t q = sys->h_stage[idx][w.o_slot + k];
+        const int32_t sb = sys->h_stage[idx][w.o_len + k];
+        const int32_t* rows = sys->rows + static_cast<size_t>(q) * s_;
+        kpp::launch_sketch_gather(src_.A64, src_.lda, n_, rows, sb, s_, sys->lsqr_Xt, fs);
+        kpp::FhtSpec f;
+        f.in = sys->lsqr_Xt;
+        f.ld_in = s_;
+        f.rows_valid = n_;
+        f.cols_valid = s_;
+        f.isign = sys->lsqr_signs;
+        f.iscale = iscale;
+        f.out = sys->lsqr_Y;
+        f.ld_out = s_;
+        f.rows_out = Nsk_;
+        f.M = Nsk_;
+        f.ncols = s_;
+        kpp::launch_fht(f, fs);
+        kpp::launch_sketch_select(sys->lsqr_Y, s_, sys->lsqr_T[idx] + static_cast<size_t>(k) * tau_, tau_, sb, scale,
+                                  sys->lsqr_Ahat + j * per, fs);
+      }
+      // ... then their Grams A_hat A_hat^T + lambda I, Cholesky factors and
+      // inverses in one launch each (rows k s + i of the stack)
+      kpp::launch_gram(KPP_KACZMARZ, sys->lsqr_Ahat, tau_, tau_, sys->lsqr_iota, d_slens + k0, s_, nk, prm_.lambda,
+                       sys->L, sys->slot_stride, d_sslot + k0, sys->gram_ws[idx], fs);
+      kpp::launch_cholesky(sys->L, s_, sys->slot_stride, d_slens + k0, nk, d_sslot + k0, sys->err, fs);
+      kpp::launch_factor_linv(sys->L, sys->slot_stride, s_, d_slens + k0, nk, d_sslot + k0, fs);
     }
     HIP_TRY(hipGetLastError());
     return KPP_OK;
@@ -1185,6 +1206,7 @@ class CoreRun {
   double* x_ = nullptr;
   hipStream_t st_ = nullptr, side_ = nullptr;
   bool fp32_ = false, fused_ = false, phase_prof_ = false, stop_on_cand_ = false, begun_ = false;
+  int32_t chunk_ = 1;   // sketches per batched factoring (LSQR projection)
   int32_t kind_ = 0, s_ = 0, zeta_ = 0, periods_ = 1, cpl_ = 0, groups_ = 0, P_ = 0;
   int64_t m_ = 0, n_ = 0, N_ = 0, period_ = 0, max_iters_ = 0;
   double eta_ = 0.0;

@@ -85,13 +85,14 @@ static void rht_case(int kind, int64_t m, int64_t n, int s) {
 }
 
 // Kaczmarz++ with the LSQR projection (online, fixed partition, and a
-// block size above the in-LDS factor limit), and the combinations it rejects.
-static void lsqr_case(int64_t m, int64_t n, int s, int memo) {
+// block size above the in-LDS factor limit, more new blocks in a window than
+// one batched sketch factoring takes), and the combinations it rejects.
+static void lsqr_case(int64_t m, int64_t n, int s, int memo, int64_t iters = 150) {
   kpp_context* ctx; CHECK(kpp_context_create(0, nullptr, &ctx));
   double* A = dev_vec(m * n, 0.5); double* b = dev_vec(m, 1.0); double* x = dev_vec(n, 0.0);
   kpp_system* sys; CHECK(kpp_system_create(ctx, KPP_KACZMARZ, m, n, A, n, b, &sys));
   kpp_params p; CHECK(kpp_params_default(&p, KPP_KACZMARZ));
-  p.block_size = s; p.memo = memo; p.max_iters = 150; p.tol = 0.0; p.projection = 1; p.lsqr_iters = 3;
+  p.block_size = s; p.memo = memo; p.max_iters = iters; p.tol = 0.0; p.projection = 1; p.lsqr_iters = 3;
   kpp_result r; CHECK(kpp_solve(sys, &p, x, &r));
   std::printf("lsqr m=%lld n=%lld s=%d memo=%d iters=%lld misses=%lld\n", (long long)m, (long long)n, s, memo,
               (long long)r.iters, (long long)r.memo_misses);
@@ -179,6 +180,7 @@ int main(int argc, char** argv) {
     lsqr_case(1000, 200, 20, 1);
     lsqr_case(700, 300, 160, 2);
     lsqr_case(400, 5000, 64, 0);
+    lsqr_case(20000, 100, 16, 2, 600);   // 1250 blocks: about 480 new ones in the first window
     multi_case(0, 1000, 200, 20, 1, 5);
     multi_case(1, 600, 600, 64, 2, 32);
     multi_case(0, 300, 2500, 150, 0, 3);
