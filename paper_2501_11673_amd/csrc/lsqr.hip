@@ -1,9 +1,12 @@
 // Sketch-preconditioned LSQR projection of Kaczmarz++ (Section 4.1; the Proj
 // routine of Algorithm 5), carried in the s coordinates described in
 // lsqr.hpp.  LSQR is Paige and Saunders' algorithm (Golub-Kahan
-// bidiagonalization with one plane rotation per iteration).  The s-sized work
-// runs in one workgroup; the two products with A_S per iteration run across
-// the device (k_lsqr_at here, the block gemv of the exact path for A_S p).
+// bidiagonalization with one plane rotation per iteration).  For s above 128
+// the products with L^{-1} and L^{-T} split the s rows over workgroups of 16
+// rows each (below, one workgroup does them); the rotation runs in one
+// workgroup; the two products with A_S per
+// iteration run across the device (k_lsqr_at here, the block gemv of the
+// exact path for A_S p).
 #include "lsqr.hpp"
 
 namespace kpp {
@@ -13,6 +16,8 @@ constexpr int kL = 256;        // threads per workgroup of the column kernels
 constexpr int kS = 1024;       // threads of the one-workgroup kernels on s-vectors
 constexpr int kSRows = 256;    // output rows per pass of those kernels (4 threads each)
 constexpr int kAtRows = 16;    // block rows per workgroup of the A_S^T z pass
+constexpr int kMidRows = 16;   // rows per workgroup of the L^{-1} and L^{-T} products (16 k-lanes each)
+constexpr int kMidOneGroup = 128;   // largest s whose products stay in one workgroup
 
 // sum over the workgroup of NT threads, in every thread (fixed order)
 template <int NT>
@@ -183,6 +188,10 @@ __global__ __launch_bounds__(kL) void k_lsqr_post(const double* __restrict__ par
   }
 }
 
+// M v = L^{-1} (A_S p pscale + lambda v) from the partial sums of A_S p,
+// u = (M v - alpha u) / beta, z~ = L^{-T} u - beta v, in one workgroup (the
+// form for s <= kMidOneGroup, where a second launch costs more than the
+// products save when split)
 __global__ __launch_bounds__(kS) void k_lsqr_mid(const double* __restrict__ rpart, int32_t P,
                                                  const double* __restrict__ Li, const double* __restrict__ Lt,
                                                  int32_t s, int32_t sb, double lambda, LsqrState* __restrict__ L) {
@@ -214,6 +223,70 @@ __global__ __launch_bounds__(kS) void k_lsqr_mid(const double* __restrict__ rpar
   mv_colmajor(Lt, s, sb, u, t, part4);   // L^{-T} u
   for (int i = threadIdx.x; i < sb; i += kS) L->zt[i] = t[i] - beta * L->zv[i];
   if (threadIdx.x == 0) L->beta = beta;
+}
+
+
+// Rows 16 b .. 16 b + 15 of B v (B column-major, s x s; v in LDS): thread
+// (r, kk) = (tid mod 16, tid / 16) sums k = kk, kk + 16, ..., and the 16
+// partial sums of a row are added in a fixed order by thread r.  Returns the
+// row's value in threads 0..15 (0 elsewhere); ends with a barrier.
+__device__ double mv_rows16(const double* __restrict__ B, int32_t s, int32_t sb, const double* v,
+                            double (*part)[kMidRows + 1]) {
+  const int r = threadIdx.x & (kMidRows - 1), kk = threadIdx.x / kMidRows;
+  const int i = blockIdx.x * kMidRows + r;
+  double acc = 0.0;
+  if (i < sb)
+    for (int k = kk; k < sb; k += kL / kMidRows) acc = fma(B[static_cast<int64_t>(k) * s + i], v[k], acc);
+  part[kk][r] = acc;
+  __syncthreads();
+  double y = 0.0;
+  if (threadIdx.x < kMidRows)
+    for (int q = 0; q < kL / kMidRows; ++q) y += part[q][threadIdx.x];
+  __syncthreads();
+  return y;
+}
+
+// u~ = M v - alpha u = L^{-1} (A_S p pscale + lambda v) - alpha u, its rows
+// of this workgroup, from the partial sums of A_S p (every workgroup forms
+// the whole s-vector it multiplies)
+__global__ __launch_bounds__(kL) void k_lsqr_mid_a(const double* __restrict__ rpart, int32_t P,
+                                                   const double* __restrict__ Li, int32_t s, int32_t sb,
+                                                   double lambda, LsqrState* __restrict__ L) {
+  __shared__ double t[kMaxBlock];
+  __shared__ double part[kL / kMidRows][kMidRows + 1];
+  if (!L->live) return;   // uniform over the grid
+  const double pscale = L->pscale, alpha = L->alpha;
+  for (int k = threadIdx.x; k < sb; k += kL) {
+    double q = 0.0;
+    for (int c = 0; c < P; ++c) q += rpart[static_cast<int64_t>(k) * P + c];
+    t[k] = fma(lambda, L->zv[k], q * pscale);
+  }
+  __syncthreads();
+  const double y = mv_rows16(Li, s, sb, t, part);
+  const int i = blockIdx.x * kMidRows + threadIdx.x;
+  if (threadIdx.x < kMidRows && i < sb) L->ut[i] = y - alpha * L->u[i];
+}
+
+// beta = ||u~||, u = u~ / beta, and this workgroup's rows of
+// z~ = L^{-T} u - beta v (every workgroup forms beta and u the same way)
+__global__ __launch_bounds__(kL) void k_lsqr_mid_b(const double* __restrict__ Lt, int32_t s, int32_t sb,
+                                                   LsqrState* __restrict__ L) {
+  __shared__ double red[kL / 64];
+  __shared__ double u[kMaxBlock];
+  __shared__ double part[kL / kMidRows][kMidRows + 1];
+  if (!L->live) return;
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < sb; k += kL) acc = fma(L->ut[k], L->ut[k], acc);
+  const double beta = sqrt(wg_sum<kL>(acc, red));
+  for (int k = threadIdx.x; k < sb; k += kL) u[k] = beta > 0.0 ? L->ut[k] / beta : L->ut[k];
+  __syncthreads();
+  const double y = mv_rows16(Lt, s, sb, u, part);
+  const int i = blockIdx.x * kMidRows + threadIdx.x;
+  if (threadIdx.x < kMidRows && i < sb) {
+    L->u[i] = u[i];
+    L->zt[i] = y - beta * L->zv[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) L->beta = beta;
 }
 
 }  // namespace
@@ -256,7 +329,13 @@ void launch_lsqr_post(const double* partsq, int32_t ngroups, int32_t sb, double 
 void launch_lsqr_mid(const double* rpart, int32_t P, const double* Linv, int32_t s, int32_t sb, double lambda,
                      LsqrState* L, hipStream_t st) {
   const double* Lt = Linv + static_cast<int64_t>(s) * s;
-  hipLaunchKernelGGL(k_lsqr_mid, dim3(1), dim3(kS), 0, st, rpart, P, Linv, Lt, s, sb, lambda, L);
+  if (s <= kMidOneGroup) {
+    hipLaunchKernelGGL(k_lsqr_mid, dim3(1), dim3(kS), 0, st, rpart, P, Linv, Lt, s, sb, lambda, L);
+    return;
+  }
+  const unsigned g = static_cast<unsigned>((sb + kMidRows - 1) / kMidRows);
+  hipLaunchKernelGGL(k_lsqr_mid_a, dim3(g), dim3(kL), 0, st, rpart, P, Linv, s, sb, lambda, L);
+  hipLaunchKernelGGL(k_lsqr_mid_b, dim3(g), dim3(kL), 0, st, Lt, s, sb, L);
 }
 
 }  // namespace kpp

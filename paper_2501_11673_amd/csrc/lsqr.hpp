@@ -31,6 +31,7 @@ struct LsqrState {
   double zw[kMaxBlock];   // LSQR's search direction w
   double zx[kMaxBlock];   // the iterate x (its first n entries are A_S^T zx)
   double zt[kMaxBlock];   // M^T u - beta v before normalisation
+  double ut[kMaxBlock];   // M v - alpha u before normalisation
 };
 
 // L^{-1} of each slot's factor at +s*s, column-major (entry (i, k) at k s + i),
