@@ -57,12 +57,28 @@ __device__ void mv_colmajor(const double* __restrict__ B, int32_t s, int32_t sb,
   }
 }
 
+// Xt[j s + i] = A[rows[i], j] (0 for i >= sb): a 64 x 64 tile (columns j0..,
+// block rows i0..) is read along A's rows and written along Xt's rows through
+// LDS, so both sides are coalesced
+constexpr int kGatherTile = 64;
 __global__ __launch_bounds__(kL) void k_sketch_gather(const double* __restrict__ A, int64_t lda, int64_t n,
                                                       const int32_t* __restrict__ rows, int32_t sb, int32_t s,
                                                       double* __restrict__ Xt) {
-  const int64_t j = static_cast<int64_t>(blockIdx.x) * kL + threadIdx.x;
-  if (j >= n) return;
-  for (int i = 0; i < s; ++i) Xt[j * s + i] = i < sb ? A[static_cast<int64_t>(rows[i]) * lda + j] : 0.0;
+  __shared__ double tile[kGatherTile][kGatherTile + 1];
+  const int64_t j0 = static_cast<int64_t>(blockIdx.x) * kGatherTile;
+  const int i0 = blockIdx.y * kGatherTile;
+  const int tx = threadIdx.x & (kGatherTile - 1), ty = threadIdx.x / kGatherTile;
+  for (int r = ty; r < kGatherTile; r += kL / kGatherTile) {
+    const int i = i0 + r;
+    const int64_t j = j0 + tx;
+    tile[r][tx] = (i < sb && j < n) ? A[static_cast<int64_t>(rows[i]) * lda + j] : 0.0;
+  }
+  __syncthreads();
+  for (int c = ty; c < kGatherTile; c += kL / kGatherTile) {
+    const int64_t j = j0 + c;
+    const int i = i0 + tx;
+    if (j < n && i < s) Xt[j * s + i] = tile[tx][c];
+  }
 }
 
 __global__ __launch_bounds__(kL) void k_sketch_select(const double* __restrict__ Y, int32_t s,
@@ -293,8 +309,9 @@ __global__ __launch_bounds__(kL) void k_lsqr_mid_b(const double* __restrict__ Lt
 
 void launch_sketch_gather(const double* A, int64_t lda, int64_t n, const int32_t* rows, int32_t sb, int32_t s,
                           double* Xt, hipStream_t st) {
-  hipLaunchKernelGGL(k_sketch_gather, dim3(static_cast<unsigned>((n + kL - 1) / kL)), dim3(kL), 0, st, A, lda, n,
-                     rows, sb, s, Xt);
+  const dim3 grid(static_cast<unsigned>((n + kGatherTile - 1) / kGatherTile),
+                  static_cast<unsigned>((s + kGatherTile - 1) / kGatherTile));
+  hipLaunchKernelGGL(k_sketch_gather, grid, dim3(kL), 0, st, A, lda, n, rows, sb, s, Xt);
 }
 
 void launch_sketch_select(const double* Y, int32_t s, const int32_t* T, int32_t tau, int32_t sb, double scale,
