@@ -7,6 +7,8 @@
 // workgroup; the two products with A_S per
 // iteration run across the device (k_lsqr_at here, the block gemv of the
 // exact path for A_S p).
+#include <cstddef>
+
 #include "lsqr.hpp"
 
 namespace kpp {
@@ -284,25 +286,39 @@ __global__ __launch_bounds__(kL) void k_lsqr_mid_a(const double* __restrict__ rp
 }
 
 // beta = ||u~||, u = u~ / beta, and this workgroup's rows of
-// z~ = L^{-T} u - beta v (every workgroup forms beta and u the same way)
-__global__ __launch_bounds__(kL) void k_lsqr_mid_b(const double* __restrict__ Lt, int32_t s, int32_t sb,
-                                                   LsqrState* __restrict__ L) {
+// z~ = L^{-T} u - beta v (every workgroup forms beta and u the same way).
+// START: the first LSQR iteration from z = 0 with u~ = src = L^{-1} r, so
+// z~ = L^{-T} u, x = 0, and the recurrences start (as k_lsqr_start).
+template <bool START>
+__global__ __launch_bounds__(kL) void k_lsqr_mid_b(const double* __restrict__ src, const double* __restrict__ Lt,
+                                                   int32_t s, int32_t sb, LsqrState* __restrict__ L) {
   __shared__ double red[kL / 64];
   __shared__ double u[kMaxBlock];
   __shared__ double part[kL / kMidRows][kMidRows + 1];
-  if (!L->live) return;
+  if (!START && !L->live) return;
   double acc = 0.0;
-  for (int k = threadIdx.x; k < sb; k += kL) acc = fma(L->ut[k], L->ut[k], acc);
+  for (int k = threadIdx.x; k < sb; k += kL) acc = fma(src[k], src[k], acc);
   const double beta = sqrt(wg_sum<kL>(acc, red));
-  for (int k = threadIdx.x; k < sb; k += kL) u[k] = beta > 0.0 ? L->ut[k] / beta : L->ut[k];
+  for (int k = threadIdx.x; k < sb; k += kL) u[k] = beta > 0.0 ? src[k] / beta : (START ? 0.0 : src[k]);
   __syncthreads();
   const double y = mv_rows16(Lt, s, sb, u, part);
   const int i = blockIdx.x * kMidRows + threadIdx.x;
   if (threadIdx.x < kMidRows && i < sb) {
     L->u[i] = u[i];
-    L->zt[i] = y - beta * L->zv[i];
+    if (START) {
+      L->zt[i] = y;
+      L->zx[i] = 0.0;
+    } else {
+      L->zt[i] = y - beta * L->zv[i];
+    }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) L->beta = beta;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    L->beta = beta;
+    if (START) {
+      L->phibar = beta;
+      L->live = beta > 0.0 ? 1 : 0;
+    }
+  }
 }
 
 }  // namespace
@@ -323,7 +339,12 @@ void launch_sketch_select(const double* Y, int32_t s, const int32_t* T, int32_t 
 
 void launch_lsqr_start(const double* y, const double* Linv, int32_t s, int32_t sb, LsqrState* L, hipStream_t st) {
   const double* Lt = Linv + static_cast<int64_t>(s) * s;
-  hipLaunchKernelGGL(k_lsqr_start, dim3(1), dim3(kS), 0, st, y, Lt, s, sb, L);
+  if (s <= kMidOneGroup) {
+    hipLaunchKernelGGL(k_lsqr_start, dim3(1), dim3(kS), 0, st, y, Lt, s, sb, L);
+    return;
+  }
+  const unsigned g = static_cast<unsigned>((sb + kMidRows - 1) / kMidRows);
+  hipLaunchKernelGGL(k_lsqr_mid_b<true>, dim3(g), dim3(kL), 0, st, y, Lt, s, sb, L);
 }
 
 int32_t lsqr_at_groups(int64_t n) { return static_cast<int32_t>((n + kL - 1) / kL); }
@@ -352,7 +373,8 @@ void launch_lsqr_mid(const double* rpart, int32_t P, const double* Linv, int32_t
   }
   const unsigned g = static_cast<unsigned>((sb + kMidRows - 1) / kMidRows);
   hipLaunchKernelGGL(k_lsqr_mid_a, dim3(g), dim3(kL), 0, st, rpart, P, Linv, s, sb, lambda, L);
-  hipLaunchKernelGGL(k_lsqr_mid_b, dim3(g), dim3(kL), 0, st, Lt, s, sb, L);
+  const double* ut = reinterpret_cast<const double*>(reinterpret_cast<const char*>(L) + offsetof(LsqrState, ut));
+  hipLaunchKernelGGL(k_lsqr_mid_b<false>, dim3(g), dim3(kL), 0, st, ut, Lt, s, sb, L);
 }
 
 }  // namespace kpp
