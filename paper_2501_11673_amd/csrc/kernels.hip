@@ -128,6 +128,45 @@ __global__ __launch_bounds__(kT) void k_block_project(
   if (tid == 0) step_state(ds, rr, zeta, adaptive);
 }
 
+// The same for large blocks: y's rows split over workgroups of 16 (thread
+// (i mod 16, kk) sums k = kk, kk + 16, ...; the 16 partial sums of a row are
+// added in a fixed order).  Every workgroup forms r the same way; workgroup 0
+// alone does the step's bookkeeping.
+constexpr int kProjRows = 16;
+__global__ __launch_bounds__(kT) void k_block_project_rows(
+    const double* __restrict__ rpart, int32_t P, const double* __restrict__ b,
+    const int32_t* __restrict__ rows, int32_t sb, const double* __restrict__ Ginv, int32_t ldl,
+    double* __restrict__ y, DevState* __restrict__ ds, int32_t zeta, int32_t adaptive) {
+  __shared__ double r[kMaxBlock];
+  __shared__ double red[4];
+  __shared__ double pr[kT / kProjRows][kProjRows + 1];
+  const int tid = threadIdx.x;
+  double part = 0.0;
+  for (int i = tid; i < sb; i += kT) {
+    const double* rp = rpart + static_cast<int64_t>(i) * P;
+    double acc = 0.0;
+    for (int p = 0; p < P; ++p) acc += rp[p];
+    const double ri = acc - b[rows[i]];
+    r[i] = ri;
+    part = fma(ri, ri, part);
+  }
+  const double rr = block_sum(part, red);
+  __syncthreads();
+  const int ri = tid & (kProjRows - 1), kk = tid / kProjRows;
+  const int i = blockIdx.x * kProjRows + ri;
+  double acc = 0.0;
+  if (i < sb)
+    for (int k = kk; k < sb; k += kT / kProjRows) acc = fma(Ginv[static_cast<int64_t>(k) * ldl + i], r[k], acc);
+  pr[kk][ri] = acc;
+  __syncthreads();
+  if (tid < kProjRows && i < sb) {
+    double v = 0.0;
+    for (int q = 0; q < kT / kProjRows; ++q) v += pr[q][tid];
+    y[i] = v;
+  }
+  if (blockIdx.x == 0 && tid == 0) step_state(ds, rr, zeta, adaptive);
+}
+
 // --------------------------------------------------------------------------
 // momentum + iterate update over all n coordinates
 // --------------------------------------------------------------------------
@@ -1208,6 +1247,12 @@ void launch_block_gemv_partial(const double* A, int64_t lda, int64_t n, const in
 void launch_block_project(const double* rpart, int32_t P, const double* b, const int32_t* rows,
                           int32_t sb, const double* L, int32_t ldl, double* y, DevState* ds,
                           int32_t zeta, int32_t adaptive, hipStream_t st) {
+  if (ldl > 128) {   // large blocks: rows of y over workgroups
+    const unsigned g = static_cast<unsigned>((sb + kProjRows - 1) / kProjRows);
+    hipLaunchKernelGGL(k_block_project_rows, dim3(g), dim3(kT), 0, st, rpart, P, b, rows, sb, L, ldl, y, ds, zeta,
+                       adaptive);
+    return;
+  }
   hipLaunchKernelGGL(k_block_project, dim3(1), dim3(kT), 0, st, rpart, P, b, rows, sb, L, ldl, y,
                      ds, zeta, adaptive);
 }
