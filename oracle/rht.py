@@ -11,10 +11,16 @@ What is computed
     a_1 + a_2 and of a_1 - a_2.  The printed recursion forms the second half
     from a_2 - a_1, which contradicts the definition of H_n; this follows the
     definition.
-  * SymFHT(A) = H_n A H_n for symmetric A, by the recursion of Algorithm 3:
-    SymFHT of the two diagonal blocks, two FHTs of the off-diagonal block, and
-    the block combination of Algorithm 3 (its correctness is Theorem
-    t:symFHT; its cost is at most n^2 (2.5 + log2 n) additions).
+  * SymFHT(A) = H_n A H_n for symmetric A (Algorithm 3, Theorem t:symFHT),
+    derived here from the Sylvester definition: with h = n/2, H = H_h and A
+    split into h x h blocks [[A11, A12], [A12^T, A22]],
+        H_n A H_n = [[P + Q + (R + R^T),  (P - Q) - (R - R^T)],
+                     [(P - Q) + (R - R^T), P + Q - (R + R^T)]]
+    where P = H A11 H and Q = H A22 H (the same transform, recursively, on the
+    symmetric diagonal blocks) and R = H A12 H (two FHTs); H A12^T H = R^T.
+    The lower-left block is the transpose of the upper-right one.  The
+    additions this takes are counted; Theorem t:symFHT bounds them by
+    n^2 (2.5 + log2 n).
   * The RHT Q = H D (Definition d:rht), D = diag(d_1, ..., d_N) / sqrt(N) with
     Rademacher signs d_i.  Kaczmarz++ (Algorithm 5) solves (Q A) x = Q b, the
     same x.  CD++ (Algorithm 2; Section 5.3, symmetric RHT) solves
@@ -80,7 +86,8 @@ def fht(X: np.ndarray, ops: Optional[OpCount] = None) -> np.ndarray:
 
 
 def symfht(A: np.ndarray, ops: Optional[OpCount] = None) -> np.ndarray:
-    """H_n A H_n for symmetric A (Algorithm 3).  The 1 x 1 case returns A."""
+    """H_n A H_n for symmetric A (Theorem t:symFHT), from the block form of
+    H_n = [[H, H], [H, -H]] given in the module docstring.  1 x 1: A itself."""
     A = np.asarray(A, dtype=np.float64)
     n = A.shape[0]
     if A.shape != (n, n) or n & (n - 1) or n == 0:
@@ -88,20 +95,21 @@ def symfht(A: np.ndarray, ops: Optional[OpCount] = None) -> np.ndarray:
     if n == 1:
         return A.copy()
     h = n // 2
-    A11, A12, A22 = A[:h, :h], A[:h, h:], A[h:, h:]
-    B11 = symfht(A11, ops)
-    B22 = symfht(A22, ops)
-    B12 = fht(fht(A12.T, ops).T, ops)
-    C11 = B11 + B12.T
-    C12 = B11 - B12
-    C21 = B12 + B22
-    C22 = B12.T - B22
-    upper_right = C12 + C22            # the lower-left block is its transpose
-    top = np.concatenate([C11 + C21, upper_right], axis=1)
-    bottom = np.concatenate([upper_right.T, C12 - C22], axis=1)
+    P = symfht(A[:h, :h], ops)              # H A11 H
+    Q = symfht(A[h:, h:], ops)              # H A22 H
+    R = fht(fht(A[:h, h:], ops).T, ops).T   # H A12 H (H is symmetric)
+    diag_sum = P + Q
+    diag_diff = P - Q
+    cross_sym = R + R.T
+    cross_skew = R - R.T
+    out = np.empty((n, n))
+    out[:h, :h] = diag_sum + cross_sym
+    out[h:, h:] = diag_sum - cross_sym
+    out[:h, h:] = diag_diff - cross_skew
+    out[h:, :h] = out[:h, h:].T
     if ops is not None:
-        ops.adds += 7 * h * h   # four combinations, then three block sums
-    return np.concatenate([top, bottom], axis=0)
+        ops.adds += 7 * h * h   # four block sums/differences, then three output blocks
+    return out
 
 
 def rademacher(seed: int, N: int) -> np.ndarray:

@@ -90,6 +90,98 @@ def test_online_schedule_rate_matches_bernoulli_expectation():
     assert all(s_.step_block[t] < len(s_.blocks) for t in range(T))
 
 
+def test_online_rate_values_from_section_5_2():
+    """B0 of the new-block rule, evaluated by hand at the workloads' shapes.
+    Section 5.2 and Algorithm 2: min(1, (1/t) (n/s) log n) for CD++;
+    Algorithm 5: min(1, (1/t) (m/s) log m, (1/t) (n/s) log m) for Kaczmarz++,
+    i.e. (min(m, n)/s) log m.  Natural log (the paper states no base).
+      n = 4096, s = 128 (CD++):          32 ln 4096  = 266.1685...
+      1000 x 200, s = 20:                10 ln 1000  = 69.0776...
+      65536 x 2048, s = 256 (tall):       8 ln 65536 = 88.7228...
+      2048 x 32768, s = 128 (wide):      16 ln 2048  = 121.9939...
+    A swapped n and s, a base-2 log, m in place of min(m, n) or log n in
+    place of log m each move at least one of these."""
+    assert sch.online_rate("psd", 4096, 4096, 128) == pytest.approx(266.168517335019, rel=1e-12)
+    assert sch.online_rate("general", 1000, 200, 20) == pytest.approx(69.07755278982137, rel=1e-12)
+    assert sch.online_rate("general", 65536, 2048, 256) == pytest.approx(88.722839111673, rel=1e-12)
+    assert sch.online_rate("general", 2048, 32768, 128) == pytest.approx(121.99390377855038, rel=1e-12)
+
+
+def test_online_block_count_follows_section_5_2():
+    """Section 5.2: the first B = (n/s) log n steps all draw new blocks, and T
+    steps collect about B + sum_{t=B}^{T} B/t = B (1 + log(T/B)) blocks.  B is
+    the hand value for 1000 x 200 with s = 20 (not taken from online_rate)."""
+    B = 69.07755278982137
+    T = 2000
+    expect = 1.0 + sum(min(1.0, B / t) for t in range(1, T))   # 302.05 (Bernoulli means)
+    assert abs(expect - B * (1.0 + math.log(T / B))) < 1.0
+    var = sum(min(1.0, B / t) * (1.0 - min(1.0, B / t)) for t in range(1, T))
+    rate = sch.online_rate("general", 1000, 200, 20)
+    counts = []
+    for sd in range(16):
+        s_ = sch.make_schedule("online", 1000, 20, T, seed=sd, B0=rate)
+        assert s_.new_block[:69].all()
+        counts.append(len(s_.blocks))
+    assert abs(np.mean(counts) - expect) < 4.0 * math.sqrt(var / 16.0)
+
+
+def test_default_eta_values():
+    """eta = s/(2n) (Section 5.4; Algorithm 2; Algorithm 5 for tall systems),
+    evaluated by hand: 1000 x 200, s = 20 -> 0.05; n = 4096 CD++, s = 128 ->
+    0.015625; 65536 x 2048, s = 256 -> 0.0625.  Wide Kaczmarz++ takes the rank
+    min(m, n) in place of n (the variance parameter nu scales with the rank,
+    Section 5.4): 2048 x 32768, s = 128 -> 0.03125 (the literal s/(2n) would be
+    0.001953125)."""
+    assert kpp.default_eta("general", 1000, 200, 20) == 0.05
+    assert kpp.default_eta("psd", 4096, 4096, 128) == 0.015625
+    assert kpp.default_eta("general", 65536, 2048, 256) == 0.0625
+    assert kpp.default_eta("general", 2048, 32768, 128) == 0.03125
+
+
+def test_refinement_with_half_exact_inner_solve():
+    """Classical iterative refinement, closed form: an inner solve returning
+    exactly half of the correction leaves r_k = 2^-k r_0, so the relative
+    residual history is 1, 1/2, 1/4, ... and 1e-6 is reached after
+    ceil(log2(1e6)) = 20 corrections; x_k = (1 - 2^-k) x*."""
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((12, 12)) + 6.0 * np.eye(12)
+    xs = rng.standard_normal(12)
+    b = A @ xs
+    x, hist, ok = kpp.refine(A, b, "general", lambda r: 0.5 * np.linalg.solve(A, r), tol=1e-6,
+                             max_rounds=20)
+    assert ok and len(hist) == 21
+    for k, h in enumerate(hist):
+        assert h == pytest.approx(2.0 ** -k, rel=1e-9)
+    assert relerr(x, (1.0 - 2.0 ** -20) * xs) < 1e-12
+    # one round fewer does not reach the tolerance
+    _, hist19, ok19 = kpp.refine(A, b, "general", lambda r: 0.5 * np.linalg.solve(A, r), tol=1e-6,
+                                 max_rounds=19)
+    assert not ok19 and hist19[-1] == pytest.approx(2.0 ** -19, rel=1e-9)
+
+
+def test_refinement_with_perturbed_inner_solve_contracts():
+    """An inner solve with a relative error e (here the exact solve of a
+    perturbed matrix) contracts the residual by about e per round: reaching
+    1e-10 from 1 takes about log(1e-10)/log(e) rounds (Section 2: inexact
+    projections within a bound proportional to the error still converge)."""
+    rng = np.random.default_rng(8)
+    n = 30
+    A = rng.standard_normal((n, n)) + 8.0 * np.eye(n)
+    xs = rng.standard_normal(n)
+    b = A @ xs
+    E = rng.standard_normal((n, n))
+    E *= 1e-2 * np.linalg.norm(A, 2) / np.linalg.norm(E, 2)
+    Ap = A + E
+    x, hist, ok = kpp.refine(A, b, "general", lambda r: np.linalg.solve(Ap, r), tol=1e-10, max_rounds=40)
+    assert ok
+    e = np.linalg.norm(np.eye(n) - A @ np.linalg.inv(Ap), 2)   # residual contraction bound
+    assert e < 0.2
+    assert len(hist) - 1 <= math.ceil(math.log(1e-10) / math.log(e)) + 1
+    for k in range(1, len(hist)):
+        assert hist[k] <= e * hist[k - 1] * (1 + 1e-6) + 1e-15
+    assert relerr(x, xs) < 1e-8
+
+
 # ---------------------------------------------------------------------------
 # the regularized projection (eq. (bk), eq. (cd-update), Theorem 5.1 proof)
 # ---------------------------------------------------------------------------
@@ -388,19 +480,73 @@ def _bad_direction_transposed(A, S, y, kind, reverse=False):
     return A[S, :].T @ y[::-1]
 
 
+def _bad_rate_n_s_swapped(kind, m, n, s):
+    if kind == "psd":
+        return (float(s) / float(n)) * math.log(float(n))
+    return (float(s) / float(min(m, n))) * math.log(float(m))
+
+
+def _bad_rate_log2(kind, m, n, s):
+    if kind == "psd":
+        return (float(n) / float(s)) * math.log2(float(n))
+    return (float(min(m, n)) / float(s)) * math.log2(float(m))
+
+
+def _bad_rate_m_not_min(kind, m, n, s):
+    if kind == "psd":
+        return (float(n) / float(s)) * math.log(float(n))
+    return (float(m) / float(s)) * math.log(float(m))
+
+
+def _bad_eta_no_half(kind, m, n, s):
+    return s / float(n if kind == "psd" else min(m, n))
+
+
+def _bad_eta_max(kind, m, n, s):
+    return s / (2.0 * (n if kind == "psd" else max(m, n)))
+
+
+def _bad_refine_sign(A, b, kind, inner_solve, tol=1e-10, max_rounds=20, x0=None):
+    A = np.asarray(A, dtype=np.float64)
+    x = np.zeros(A.shape[1]) if x0 is None else np.array(x0, dtype=np.float64)
+    nb = float(np.linalg.norm(b))
+    hist = []
+    for _ in range(max_rounds):
+        res = b - A @ x
+        rel = float(np.linalg.norm(res)) / nb
+        hist.append(rel)
+        if rel <= tol:
+            return x, hist, True
+        x = x - inner_solve(res)
+    hist.append(float(np.linalg.norm(b - A @ x)) / nb)
+    return x, hist, hist[-1] <= tol
+
+
 @pytest.mark.parametrize("mutant,target", [
     (_bad_momentum_sign, "momentum_update"),
     (_bad_momentum_c, "momentum_update"),
     (_bad_gram_no_lambda, "regularized_gram"),
     (_bad_direction_transposed, "direction"),
+    (_bad_rate_n_s_swapped, "schedule.online_rate"),
+    (_bad_rate_log2, "schedule.online_rate"),
+    (_bad_rate_m_not_min, "schedule.online_rate"),
+    (_bad_eta_no_half, "default_eta"),
+    (_bad_eta_max, "default_eta"),
+    (_bad_refine_sign, "refine"),
 ])
 def test_planted_mistakes_are_caught(monkeypatch, mutant, target):
-    monkeypatch.setattr(kpp, target, mutant)
+    if target.startswith("schedule."):
+        monkeypatch.setattr(sch, target.split(".", 1)[1], mutant)
+    else:
+        monkeypatch.setattr(kpp, target, mutant)
     caught = []
     for fn in (lambda: test_momentum_equals_three_sequence_form(0.3, 0.2),
                lambda: test_projection_is_regularized_least_squares(12, 7, 5, 0.3),
                lambda: test_cdpp_is_implicit_kaczmarzpp_on_factor(),
-               lambda: test_converges_to_dense_normal_equations("psd")):
+               lambda: test_converges_to_dense_normal_equations("psd"),
+               lambda: test_online_rate_values_from_section_5_2(),
+               lambda: test_default_eta_values(),
+               lambda: test_refinement_with_half_exact_inner_solve()):
         try:
             fn()
         except (AssertionError, ValueError, ArithmeticError, np.linalg.LinAlgError):
