@@ -24,6 +24,10 @@
  *   - Matrices are row-major FP64 with a leading dimension (lda >= n).
  *   - The caller owns A, b and x; the library never frees them and they must
  *     outlive the kpp_system (or the served request) that refers to them.
+ *     A and b must not change while a kpp_system refers to them: the library
+ *     keeps values derived from them (||b||, the FP32 copy of A, memoized
+ *     factors, the randomized Hadamard transforms); to solve with other
+ *     values, create a new system.
  *     The library owns memo caches, low-precision copies, state and workspaces.
  *   - All work is enqueued on the context's stream (borrowed, never destroyed;
  *     NULL means the device's null stream).  Calls return after that stream's
@@ -181,7 +185,8 @@ typedef struct kpp_result {
   double kernel_seconds;      /* device time of the step kernels (HIP events), all launches */
   double kernel_launches;     /* number of step-kernel launches (fused: one per window)  */
   double seconds_queued;      /* serving: time from submission to admission             */
-  double reserved[1];
+  int32_t team_groups;        /* fused engine: workgroups sharing one step (0: launch-per-phase) */
+  int32_t cols_per_lane;      /* fused engine: columns of x each lane holds (0: launch-per-phase) */
 } kpp_result;
 
 /* Serving statistics (kpp_server_stats). */

@@ -103,12 +103,12 @@ class kpp_result(ctypes.Structure):
         ("kernel_seconds", ctypes.c_double),
         ("kernel_launches", ctypes.c_double),
         ("seconds_queued", ctypes.c_double),
-        ("reserved", ctypes.c_double * 1),
+        ("team_groups", ctypes.c_int32),
+        ("cols_per_lane", ctypes.c_int32),
     ]
 
     def as_dict(self):
-        return {k: (getattr(self, k) if k != "reserved" else None) for k, _ in self._fields_
-                if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class KppError(RuntimeError):

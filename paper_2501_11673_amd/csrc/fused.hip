@@ -664,6 +664,17 @@ void launch_multi_kind(const FusedArgs* args, const int32_t* team_start, int32_t
 }
 
 template <int KIND, typename TA>
+const void* fused_kernel_ptr(int cpl) {
+  switch (cpl) {
+    case 1: return reinterpret_cast<const void*>(&k_fused<KIND, 1, TA>);
+    case 2: return reinterpret_cast<const void*>(&k_fused<KIND, 2, TA>);
+    case 4: return reinterpret_cast<const void*>(&k_fused<KIND, 4, TA>);
+    case 8: return reinterpret_cast<const void*>(&k_fused<KIND, 8, TA>);
+    default: return reinterpret_cast<const void*>(&k_fused<KIND, 16, TA>);
+  }
+}
+
+template <int KIND, typename TA>
 void launch_kind(const FusedArgs& a, int cpl, int G, hipStream_t st) {
   switch (cpl) {
     case 1: hipLaunchKernelGGL((k_fused<KIND, 1, TA>), dim3(G), dim3(kT), 0, st, a); break;
@@ -690,6 +701,14 @@ void launch_fused_multi(int32_t kind, bool a_fp32, const FusedArgs* args, const 
     else
       launch_multi_kind<1, double>(args, team_start, nteams, total_groups, cpl, st);
   }
+}
+
+int32_t fused_blocks_per_cu(int32_t kind, bool a_fp32, int32_t cpl) {
+  const void* f = kind == 0 ? (a_fp32 ? fused_kernel_ptr<0, float>(cpl) : fused_kernel_ptr<0, double>(cpl))
+                            : (a_fp32 ? fused_kernel_ptr<1, float>(cpl) : fused_kernel_ptr<1, double>(cpl));
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kT, 0) != hipSuccess) return 0;
+  return nb;
 }
 
 void launch_fused(int32_t kind, bool a_fp32, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t st) {

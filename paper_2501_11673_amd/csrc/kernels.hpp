@@ -192,6 +192,11 @@ constexpr size_t kPartDoubles = 2 * static_cast<size_t>(kFusedMaxGroups) * kFuse
 
 void launch_fused(int32_t kind, bool a_fp32, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t st);
 
+// Workgroups of the step kernel for (kind, precision, cpl) that one compute
+// unit can hold at once (the occupancy query; 0 if it fails).  A team must be
+// resident as a whole: its workgroups wait for each other every step.
+int32_t fused_blocks_per_cu(int32_t kind, bool a_fp32, int32_t cpl);
+
 // Several independent runs in one launch: team t has the workgroups
 // [team_start[t], team_start[t + 1]) and the arguments args[t] (device
 // memory); every team has the same kind, precision and cpl.  The caller keeps

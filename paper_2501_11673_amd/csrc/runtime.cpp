@@ -81,6 +81,10 @@ struct kpp_context {
   hipStream_t stream = nullptr;   // borrowed: all results are ordered on it
   hipStream_t side = nullptr;     // owned: memo-miss factorizations one window ahead
   int32_t cu_count = 0;
+  // workgroups of k_fused<kind, cpl, precision> per compute unit
+  // ([kind][fp32][log2 cpl]; -1 = not asked yet)
+  int32_t fused_per_cu[2][2][5] = {{{-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1}},
+                                   {{-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1}}};
 };
 
 struct kpp_system {
@@ -443,6 +447,19 @@ bool fused_geometry(int64_t n, int32_t s, int32_t target_groups, bool fp32, int3
   return true;
 }
 
+// Workgroups of the step kernel that can be resident on the context's device
+// at once.
+int64_t fused_resident_groups(kpp_context* ctx, int32_t kind, bool fp32, int32_t cpl) {
+  int lc = 0;
+  while ((1 << lc) < cpl && lc < 4) ++lc;
+  int32_t& per = ctx->fused_per_cu[kind == KPP_CD_PSD ? 1 : 0][fp32 ? 1 : 0][lc];
+  if (per < 0) {
+    (void)hipSetDevice(ctx->device);
+    per = kpp::fused_blocks_per_cu(kind == KPP_CD_PSD ? 1 : 0, fp32, cpl);
+  }
+  return static_cast<int64_t>(per) * std::max(ctx->cu_count, 0);
+}
+
 // The matrix and right-hand side one run of the block iteration works on: the
 // caller's FP64 system, or (mixed precision) the FP32 copy of A with the
 // current outer residual as right-hand side.
@@ -499,6 +516,7 @@ struct CoreStats {
   double true_rel = NAN, t_factor = 0.0, t_kernel = 0.0;
   kpp::DevState hs{};
   int32_t engine = 0;
+  int32_t groups = 0, cpl = 0;   // fused geometry (0 for the launch-per-phase engine)
   bool dual = false;
 };
 
@@ -573,6 +591,16 @@ class CoreRun {
       if (p->engine != 1) fused_ = fused_geometry(n_, s_, p->team_groups, fp32_, &cpl_, &groups_);
       if (p->engine == 2 && !fused_)
         return fail(KPP_ERR_INVALID_ARG, "n=%lld is too wide for the fused engine", (long long)n_);
+    }
+    // every workgroup of a team waits for the others each step, so the whole
+    // team must be resident; otherwise the launch-per-phase engine runs (an
+    // explicit request for the fused engine, a team size or the FP32 inner
+    // solver, which needs the fused engine, is refused)
+    if (fused_ && groups_ > fused_resident_groups(sys->ctx, kind_, fp32_, cpl_)) {
+      if (p->engine == 2 || p->team_groups > 0 || force_cpl > 0 || fp32_)
+        return fail(KPP_ERR_INVALID_ARG, "a team of %d workgroups cannot be resident on this device (%lld)",
+                    groups_, static_cast<long long>(fused_resident_groups(sys->ctx, kind_, fp32_, cpl_)));
+      fused_ = false;
     }
     lsqr_ = p->projection == 1;
     if (lsqr_) {
@@ -919,6 +947,8 @@ class CoreRun {
     cs->t_kernel = t_kernel_;
     cs->hs = hs_;
     cs->engine = fused_ ? 2 : 1;
+    cs->groups = fused_ ? groups_ : 0;
+    cs->cpl = fused_ ? cpl_ : 0;
     cs->dual = dual_;
     return converged_ ? KPP_OK : KPP_NOT_CONVERGED;
   }
@@ -1275,6 +1305,8 @@ void fill_result(kpp_result* res, const kpp_system* sys, const kpp_params* p, in
   res->refinements = rounds;
   res->checkpoints = static_cast<int32_t>(checkpoints);
   res->engine_used = last.engine;
+  res->team_groups = last.groups;
+  res->cols_per_lane = last.cpl;
   res->est_rel_res = est_rel;
   res->true_rel_res = true_rel;
   res->rho_final = rho_final;
@@ -2163,6 +2195,12 @@ kpp_status solve_rht(kpp_system* sys, const kpp_params* p, double* x, kpp_result
   double rn = 0.0;
   KPP_TRY(residual_norm(sys, x, &rn));
   r.true_rel_res = rn / (sys->bnorm > 0.0 ? sys->bnorm : 1.0);
+  // the inner solve confirmed its stop on the transformed system; the result
+  // counts as converged only if the original system agrees
+  if (out == KPP_OK && p->tol > 0.0 && !(r.true_rel_res <= p->tol)) {
+    out = KPP_NOT_CONVERGED;
+    r.converged = 0;
+  }
   // the transforms' additions: A and b when this solve formed them, and for
   // CD++ the iterate in and out
   const double Rd = static_cast<double>(sys->rht_R);

@@ -374,6 +374,8 @@ static void emu_fused(const FusedArgs& a, int32_t cpl, int32_t G, bool fp32) {
 void launch_fused(int32_t, bool a_fp32, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t) {
   emu_fused(a, cpl, groups, a_fp32);
 }
+// the stand-in device holds one step-kernel workgroup per compute unit
+int32_t fused_blocks_per_cu(int32_t, bool, int32_t) { return 1; }
 void launch_fused_multi(int32_t, bool a_fp32, const FusedArgs* args, const int32_t* team_start, int32_t nteams,
                         int32_t total, int32_t cpl, hipStream_t) {
   emu_check(args, sizeof(FusedArgs) * nteams, "multi args");

@@ -79,6 +79,7 @@ def relerr(a, b):
     ("ragged_fixed", 700, 300, 64, 1e-4, 200, "fixed", 8, 0),      # 11 blocks, last of 60 rows
     ("wide", 120, 1500, 24, 1e-4, 150, "online", 8, 0),            # N = 2048
     ("big_block", 900, 350, 160, 1e-6, 60, "fixed", 4, 0),         # factor kernels for s > 128
+    ("s300", 1300, 400, 300, 1e-6, 24, "fixed", 3, 0),             # 257..512 rows: global-memory factor
     ("one_iter_tau", 500, 100, 16, 1e-3, 200, "online", 1, 100),   # t_max = 1, tau given
     ("memo_off", 400, 90, 12, 1e-3, 120, "off", 8, 0),
 ])

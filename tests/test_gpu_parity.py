@@ -106,7 +106,9 @@ def parity_bound(A, b, kind, s, ref, **kw):
 @pytest.mark.parametrize("kind,m,n,s,lam", [
     ("general", 300, 150, 20, 1e-3),
     ("general", 700, 300, 37, 1e-2),     # ragged tiles
-    ("general", 1200, 400, 256, 1e-1),   # factor in global memory (s > 128)
+    ("general", 1200, 400, 256, 1e-1),   # LDS-panel factor and inverse (129..256 rows)
+    ("general", 1500, 400, 384, 1e-1),   # factor in global memory (257..512 rows)
+    ("psd", 1100, 1100, 512, 1e-8),      # the largest block size the library takes
     ("general", 400, 3000, 100, 1e-2),   # wide: Gram split over 47 column chunks, ragged tile
     ("psd", 500, 500, 128, 1e-8),
     ("psd", 300, 300, 1, 1e-8),
@@ -220,6 +222,30 @@ def test_iterates_match_oracle(env, case, engine):
         assert res.iters == Tk
         assert res.memo_misses == ref.factorizations
         assert abs(res.rho_final - ref.rho_final) <= rho_bound
+
+
+@pytest.mark.parametrize("name,kind,m,n,s,lam,mode,T", [
+    # 257..512 rows: global-memory factor kernels, the projection's rows over
+    # 16-row workgroups; a 7-block partition whose last block has 200 rows
+    ("general_s300", "general", 2000, 500, 300, 1e-6, "fixed", 60),
+    ("psd_s384_online", "psd", 900, 900, 384, 1e-8, "online", 40),
+])
+def test_large_blocks_match_oracle(env, name, kind, m, n, s, lam, mode, T):
+    """Blocks above 256 rows run on the launch-per-phase engine only."""
+    sysm = synth.tiny_system(kind, m, n, seed=s, cond=30.0)
+    A, b = sysm.A, sysm.b
+    print(f"[parity] {name} shape={A.shape} s={s} T={T}", flush=True)
+    x, st, res = gpu_solve(env, A, b, kind, s, lam=lam, T=T, mode=mode, seed=19, engine=1)
+    assert res.engine_used == 1 and res.iters == T
+    ref = oracle_solve(A, b, kind, s, lam=lam, T=T, mode=mode, seed=19)
+    bound, nf, rho_bound = parity_bound(A, b, kind, s, ref, lam=lam, T=T, mode=mode, seed=19)
+    err = relerr(x, ref.x)
+    print(f"[parity] {name}: {err:.3e} (noise floor {nf:.3e})", flush=True)
+    assert err <= bound
+    assert res.memo_misses == ref.factorizations
+    assert abs(res.rho_final - ref.rho_final) <= rho_bound
+    with pytest.raises(Exception):   # the fused engine takes at most 256 rows
+        gpu_solve(env, A, b, kind, s, lam=lam, T=T, mode=mode, seed=19, engine=2)
 
 
 def test_converges_like_oracle_c1(env):

@@ -14,6 +14,8 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import kpp as okpp
+from oracle import schedule as osch
 
 pytestmark = pytest.mark.gpu
 
@@ -82,6 +84,25 @@ def serve(env, jobs, *, budget=64 << 30, max_active=16, wait=60.0):
     return [out[i] for i in ids], stats
 
 
+def oracle_of(case, sysm, p, tol, T):
+    """The FP64 oracle on the request's system, parameters and block schedule;
+    also the run with every sum reversed (the FP64 noise floor)."""
+    kind, m, n, s, lam = case[:5]
+    A = sysm.A.cpu().numpy()
+    b = sysm.b.cpu().numpy()
+    N = n if kind == "psd" else m
+    schd = osch.make_schedule("online", N, s, T, int(p.seed), B0=osch.online_rate(kind, m, n, s))
+    prm = dict(s=s, lam=lam, tol=tol, max_iters=T)
+    ref = okpp.solve(A, b, kind, okpp.Params(**prm), schd)
+    alt = okpp.solve(A, b, kind, okpp.Params(reverse_sums=True, **prm), schd)
+    return ref, alt, A, b
+
+
+def relerr(a, b):
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b))) / (nb if nb > 0 else 1.0)
+
+
 def test_served_request_matches_kpp_solve(senv):
     kpp, torch, dev, ctx = senv
     sysm, h, p = make_case(senv, MIX[0])
@@ -119,6 +140,22 @@ def test_mix_equals_alone(senv):
             err = float(torch.linalg.norm(x - sysm.xstar) / torch.linalg.norm(sysm.xstar))
             bound = 1e-2 if p.tol > 1e-8 else 1e-5
             assert err < bound, (case, err)
+        # against the FP64 oracle on the same schedule: an FP64 request stops at
+        # the oracle's step with the oracle's iterate (FP64 parity bar); a
+        # mixed-precision request is within kappa * tol of it (both solve the
+        # system to tol), the distance printed
+        for (case, (sysm, h, p), x_m, (st_m, res_m)) in zip(MIX, built, xs_mix, mix):
+            ref, alt, A, b = oracle_of(case, sysm, p, p.tol, 200_000)
+            assert ref.converged
+            err = relerr(x_m.cpu().numpy(), ref.x)
+            print(f"[serve vs oracle] {case}: served {res_m.iters} steps, oracle {ref.iters}, "
+                  f"|x - x_oracle|/|x_oracle| = {err:.2e}", flush=True)
+            if case[6] == "fp64":
+                assert res_m.iters == ref.iters, case
+                assert err <= max(1e-10, 10.0 * relerr(alt.x, ref.x)), (case, err)
+            else:
+                sp = np.abs(np.asarray(sysm.spectrum))
+                assert err <= 2.0 * float(sp.max() / sp.min()) * p.tol + 1e-12, (case, err)
         for (case, (sysm, h, p), x_m, (st_m, res_m)) in zip(MIX, built, xs_mix, mix):
             x_a = torch.zeros_like(x_m)
             [(st_a, res_a)], stats_a = serve(senv, [(h, p, x_a)])
@@ -127,6 +164,46 @@ def test_mix_equals_alone(senv):
             assert torch.equal(x_a, x_m), (case, float(torch.max(torch.abs(x_a - x_m))))
     finally:
         for _, h, _ in built:
+            kpp.kpp_system_destroy(h)
+
+
+# FP64 requests of different kinds and sizes run for a fixed number of steps
+# (tol = 0): (kind, m, n, s, lam, steps, seed)
+FIXED_MIX = [
+    ("psd", 700, 700, 64, 1e-8, 300, 41),
+    ("general", 900, 350, 50, 1e-6, 250, 42),
+    ("psd", 1500, 1500, 128, 1e-8, 200, 43),
+    ("general", 400, 1200, 64, 1e-4, 150, 44),
+    ("psd", 4096, 4096, 128, 1e-8, 128, 45),
+]
+
+
+def test_served_fixed_steps_match_oracle(senv):
+    """Requests served together (shared persistent launches, one team each)
+    give the oracle's iterates after their step budget, within the FP64
+    parity bar max(1e-10, 10 nf)."""
+    kpp, torch, dev, ctx = senv
+    built = []
+    try:
+        for case in FIXED_MIX:
+            kind, m, n, s, lam, T, seed = case
+            sysm, h, p = make_case(senv, (kind, m, n, s, lam, 0.0, "fp64", seed))
+            p.max_iters = T
+            built.append((case, sysm, h, p))
+        xs = [torch.zeros(c[2], dtype=torch.float64, device=dev) for c, _, _, _ in built]
+        out, stats = serve(senv, [(h, p, x) for (_, _, h, p), x in zip(built, xs)])
+        assert stats["peak_active"] >= 2, stats
+        for (case, sysm, h, p), x, (st, res) in zip(built, xs, out):
+            kind, m, n, s, lam, T, seed = case
+            assert st == kpp.KPP_NOT_CONVERGED and res.iters == T, (case, st, res.iters)
+            ref, alt, A, b = oracle_of(case, sysm, p, 0.0, T)
+            err = relerr(x.cpu().numpy(), ref.x)
+            nf = relerr(alt.x, ref.x)
+            print(f"[serve fixed] {case}: |x - x_oracle|/|x_oracle| = {err:.2e} (noise floor {nf:.2e})", flush=True)
+            assert err <= max(1e-10, 10.0 * nf), (case, err, nf)
+            assert res.memo_misses == ref.factorizations
+    finally:
+        for _, _, h, _ in built:
             kpp.kpp_system_destroy(h)
 
 
