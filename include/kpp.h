@@ -49,7 +49,7 @@ extern "C" {
 #endif
 
 #define KPP_API __attribute__((visibility("default")))
-#define KPP_ABI_VERSION 3
+#define KPP_ABI_VERSION 4
 
 typedef enum kpp_status {
   KPP_OK = 0,
@@ -328,6 +328,27 @@ KPP_API kpp_status kpp_schedule_generate(int32_t kind, int64_t m, int64_t n, con
 KPP_API kpp_status kpp_block_factor(kpp_system* sys, int32_t s, double lambda, int32_t nb,
                                     const int32_t* rows_host, const int32_t* len_host,
                                     double* L_dev);
+
+/* kpp_block_factor for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, layout, results and errors as
+ * kpp_block_factor, but it calls no hipMalloc, hipFree or allocating library
+ * routine.  Its scratch (the staged rows, lengths and slot ids, the
+ * breakdown flag and the split-Gram partial tiles) is one 16 MiB array per
+ * device (KPP_NOALLOC_SCRATCH_BYTES) that the library holds from its first
+ * context on that device until the process ends.  Limits: nb * (s + 2) <=
+ * KPP_NOALLOC_STAGE_ENTRIES (KPP_ERR_INVALID_ARG beyond it); Kaczmarz++
+ * Grams are formed in batches of blocks with fewer column chunks when the
+ * default split would not fit, so factors may differ from kpp_block_factor's
+ * by rounding (they are identical when the default split fits).  Every call
+ * on a device shares that device's array: calls that overlap on one device
+ * (another thread, another context's stream) race and must be serialized by
+ * the caller.  The call returns after its work on the context's stream. */
+#define KPP_NOALLOC_SCRATCH_BYTES (16u << 20)
+#define KPP_NOALLOC_STAGE_ENTRIES 262080
+KPP_API kpp_status kpp_block_factor_noalloc(kpp_system* sys, int32_t s, double lambda, int32_t nb,
+                                            const int32_t* rows_host, const int32_t* len_host,
+                                            double* L_dev);
 
 /* ||A x - b||_2 in FP64 (eq. (residual-error)); x_dev device, result on host. */
 KPP_API kpp_status kpp_residual_norm(kpp_system* sys, const double* x_dev, double* out_host);

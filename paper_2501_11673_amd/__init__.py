@@ -165,6 +165,7 @@ def _load():
         "kpp_schedule_generate": (i32, [i32, i64, i64, P(kpp_params), i64, P(i32), P(i32), P(i32),
                                         i32, P(i32)]),
         "kpp_block_factor": (i32, [vp, i32, f64, i32, P(i32), P(i32), vp]),
+        "kpp_block_factor_noalloc": (i32, [vp, i32, f64, i32, P(i32), P(i32), vp]),
         "kpp_residual_norm": (i32, [vp, vp, P(f64)]),
         "kpp_request_footprint": (i32, [vp, P(kpp_params), P(ctypes.c_uint64)]),
         "kpp_server_create": (i32, [vp, ctypes.c_uint64, i32, P(vp)]),
@@ -190,7 +191,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("kpp_abi_version", "kpp_last_error", "kpp_params_default", "kpp_context_create",
             "kpp_context_destroy", "kpp_system_create", "kpp_system_destroy", "kpp_solve",
-            "kpp_schedule_generate", "kpp_block_factor", "kpp_residual_norm", "kpp_request_footprint", "kpp_server_create",
+            "kpp_schedule_generate", "kpp_block_factor", "kpp_block_factor_noalloc", "kpp_residual_norm", "kpp_request_footprint", "kpp_server_create",
             "kpp_server_submit", "kpp_server_poll", "kpp_server_stats", "kpp_server_destroy",
             "kpp_state_export", "kpp_state_import", "kpp_solve_multi", "kpp_rht_signs", "kpp_rht_general", "kpp_rht_psd",
             "kpp_rht_vector")
@@ -329,6 +330,13 @@ def kpp_block_factor(sys_: int, s: int, lam: float, rows, lens, L_dev: int) -> N
     r = (ctypes.c_int32 * max(nb * s, 1))(*[int(v) for v in rows])
     ln = (ctypes.c_int32 * max(nb, 1))(*[int(v) for v in lens])
     _check(_lib.kpp_block_factor(ctypes.c_void_p(sys_), s, lam, nb, r, ln, ctypes.c_void_p(L_dev)))
+
+
+def kpp_block_factor_noalloc(sys_: int, s: int, lam: float, rows, lens, L_dev: int) -> None:
+    nb = len(lens)
+    r = (ctypes.c_int32 * max(nb * s, 1))(*[int(v) for v in rows])
+    ln = (ctypes.c_int32 * max(nb, 1))(*[int(v) for v in lens])
+    _check(_lib.kpp_block_factor_noalloc(ctypes.c_void_p(sys_), s, lam, nb, r, ln, ctypes.c_void_p(L_dev)))
 
 
 def kpp_residual_norm(sys_: int, x_dev: int) -> float:

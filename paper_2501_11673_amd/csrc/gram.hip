@@ -203,6 +203,19 @@ void launch_gram_syrk(const double* A, int64_t lda, int64_t n, const int32_t* ro
   launch_syrk<double>(A, lda, n, rows, lens, s, nb, lambda, G, stride, slot_of, only, ws, st);
 }
 
+void launch_gram_syrk_capped(const double* A, int64_t lda, int64_t n, const int32_t* rows, const int32_t* lens,
+                             int32_t s, int32_t nb, double lambda, double* G, int64_t stride, const int32_t* slot_of,
+                             double* ws, size_t max_work, hipStream_t st) {
+  if (nb <= 0) return;
+  int32_t nc, nt;
+  int64_t chunk;
+  gram_syrk_plan_capped(s, n, nb, max_work, &nc, &chunk, &nt);
+  hipLaunchKernelGGL(k_gram_syrk<double>, dim3(nc, nt, nb), dim3(kGThreads), 0, st, A, lda, n, rows, lens, s,
+                     nullptr, nc, chunk, nt, ws);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(nt, nb), dim3(kGThreads), 0, st, ws, lens, s, nullptr, nc, nt, lambda, G,
+                     stride, slot_of);
+}
+
 void launch_gram_syrk_f32(const float* A, int64_t lda, int64_t n, const int32_t* rows, const int32_t* lens, int32_t s,
                           int32_t nb, double lambda, double* G, int64_t stride, const int32_t* slot_of,
                           double* ws, hipStream_t st) {

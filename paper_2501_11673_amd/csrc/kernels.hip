@@ -1234,7 +1234,29 @@ __global__ __launch_bounds__(kT) void k_scatter_rows(const int32_t* __restrict__
   if (threadIdx.x == 0) lens[q] = stage_lens[k];
 }
 
+__global__ __launch_bounds__(kT) void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t base, int32_t step) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kT) + threadIdx.x; i < n; i += static_cast<int64_t>(gridDim.x) * kT)
+    p[i] = base + step * static_cast<int32_t>(i);
+}
+
+__global__ __launch_bounds__(kT) void k_zero_f64(double* __restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kT) + threadIdx.x; i < n; i += static_cast<int64_t>(gridDim.x) * kT)
+    p[i] = 0.0;
+}
+
 }  // namespace
+
+void launch_fill_i32(int32_t* p, int64_t n, int32_t base, int32_t step, hipStream_t st) {
+  if (n <= 0) return;
+  const int64_t g = std::min<int64_t>((n + kT - 1) / kT, 4096);
+  hipLaunchKernelGGL(k_fill_i32, dim3(static_cast<unsigned>(g)), dim3(kT), 0, st, p, n, base, step);
+}
+
+void launch_zero_f64(double* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  const int64_t g = std::min<int64_t>((n + kT - 1) / kT, 4096);
+  hipLaunchKernelGGL(k_zero_f64, dim3(static_cast<unsigned>(g)), dim3(kT), 0, st, p, n);
+}
 
 void launch_block_gemv_partial(const double* A, int64_t lda, int64_t n, const int32_t* rows,
                                int32_t sb, const double* x, double* rpart, int32_t P,

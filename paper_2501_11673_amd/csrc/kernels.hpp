@@ -205,6 +205,28 @@ int32_t fused_blocks_per_cu(int32_t kind, bool a_fp32, int32_t cpl);
 void launch_fused_multi(int32_t kind, bool a_fp32, const FusedArgs* args, const int32_t* team_start,
                         int32_t nteams, int32_t total_groups, int32_t cpl, hipStream_t st);
 
+// p[i] = base + step * i for i < n (step 0: a fill; step 1: consecutive ids)
+void launch_fill_i32(int32_t* p, int64_t n, int32_t base, int32_t step, hipStream_t st);
+// p[i] = 0 for i < n (a kernel rather than a memset node)
+void launch_zero_f64(double* p, int64_t n, hipStream_t st);
+
+// Split-Gram plan with at most max_work doubles of partial tiles: fewer
+// column chunks than gram_syrk_plan when its split would not fit (nb blocks
+// must fit with one chunk each: nb * ntiles * 64 * 64 <= max_work).  The
+// launcher forms the same Grams as launch_gram (Kaczmarz++, FP64 A).
+void gram_syrk_plan_capped(int32_t s, int64_t n, int32_t nb, size_t max_work, int32_t* nchunks, int64_t* chunk,
+                           int32_t* ntiles);
+void launch_gram_syrk_capped(const double* A, int64_t lda, int64_t n, const int32_t* rows, const int32_t* lens,
+                             int32_t s, int32_t nb, double lambda, double* G, int64_t stride, const int32_t* slot_of,
+                             double* ws, size_t max_work, hipStream_t st);
+
+// Per-device scratch of the no-allocation entry point (noalloc.hip): a
+// file-scope device array of kNoAllocScratchBytes.  noalloc_scratch returns
+// its device address on `device`, which must be the current device; the
+// address is resolved once per device and kept.
+constexpr size_t kNoAllocScratchBytes = size_t{16} << 20;
+hipError_t noalloc_scratch(int device, void** out);
+
 // Randomized Hadamard transform (rht.hip): out = Do H_M Di X Dc along the row
 // index of a row-major X, where Di, Dc, Do are optional diagonals of signs
 // times a scale, X is zero-padded to M rows (rows >= rows_valid) and ncols

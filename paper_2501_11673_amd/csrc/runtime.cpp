@@ -85,6 +85,8 @@ struct kpp_context {
   // ([kind][fp32][log2 cpl]; -1 = not asked yet)
   int32_t fused_per_cu[2][2][5] = {{{-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1}},
                                    {{-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1}}};
+  // device address of this device's no-allocation scratch (noalloc.hip)
+  unsigned char* scratch = nullptr;
 };
 
 struct kpp_system {
@@ -2566,6 +2568,15 @@ KPP_API kpp_status kpp_context_create(int32_t device, void* hip_stream, kpp_cont
   }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->cu_count = prop.multiProcessorCount;
+  void* scr = nullptr;
+  const hipError_t se = kpp::noalloc_scratch(device, &scr);
+  if (se != hipSuccess || !scr) {
+    (void)hipStreamDestroy(c->side);
+    delete c;
+    return fail(KPP_ERR_HIP, "no device address for the scratch array on device %d: %s", device,
+                hipGetErrorString(se));
+  }
+  c->scratch = static_cast<unsigned char*>(scr);
   *out = c;
   return KPP_OK;
 }
@@ -2830,6 +2841,73 @@ KPP_API kpp_status kpp_block_factor(kpp_system* sys, int32_t s, double lambda, i
   dev_free(d_rows);
   dev_free(d_lens);
   dev_free(d_ids);
+  if (herr) return fail(KPP_ERR_NOT_SPD, "a regularized block Gram has no Cholesky factor");
+  return KPP_OK;
+}
+
+// Scratch layout of kpp_block_factor_noalloc: the breakdown flag, then the
+// staged rows, lengths and slot ids, then the split-Gram workspace.
+constexpr size_t kNaStageOffset = 256;
+constexpr size_t kNaGramOffset = size_t{1} << 20;
+constexpr int64_t kNaStageInts = static_cast<int64_t>((kNaGramOffset - kNaStageOffset) / sizeof(int32_t));
+constexpr size_t kNaGramDoubles = (kpp::kNoAllocScratchBytes - kNaGramOffset) / sizeof(double);
+
+KPP_API kpp_status kpp_block_factor_noalloc(kpp_system* sys, int32_t s, double lambda, int32_t nb,
+                                            const int32_t* rows_host, const int32_t* len_host, double* L_dev) {
+  if (!sys || !rows_host || !len_host || !L_dev || nb < 0) return fail(KPP_ERR_INVALID_ARG, "bad arguments");
+  const int64_t N = sys->kind == KPP_CD_PSD ? sys->n : sys->m;
+  if (s < 1 || s > kpp::kMaxBlock) return fail(KPP_ERR_INVALID_ARG, "block size %d out of range", s);
+  if (!(lambda >= 0.0)) return fail(KPP_ERR_INVALID_ARG, "lambda must be >= 0");
+  if (static_cast<int64_t>(nb) * (s + 2) > kNaStageInts)
+    return fail(KPP_ERR_INVALID_ARG,
+                "nb * (s + 2) = %lld exceeds the %lld entries the no-allocation scratch stages",
+                static_cast<long long>(nb) * (s + 2), static_cast<long long>(kNaStageInts));
+  for (int32_t b = 0; b < nb; ++b) {
+    if (len_host[b] < 1 || len_host[b] > s) return fail(KPP_ERR_INVALID_ARG, "block %d length %d", b, len_host[b]);
+    for (int32_t i = 0; i < len_host[b]; ++i) {
+      const int32_t r = rows_host[static_cast<size_t>(b) * s + i];
+      if (r < 0 || r >= N) return fail(KPP_ERR_INVALID_ARG, "block %d row %d out of range", b, r);
+    }
+  }
+  if (nb == 0) return KPP_OK;
+  const int32_t nt = (s + kpp::kGramTile - 1) / kpp::kGramTile;
+  const size_t per_block = static_cast<size_t>(nt) * (nt + 1) / 2 * kpp::kGramTile * kpp::kGramTile;
+  const int32_t batch = static_cast<int32_t>(std::min<size_t>(static_cast<size_t>(nb), kNaGramDoubles / per_block));
+  if (batch < 1) return fail(KPP_ERR_INVALID_ARG, "block size %d exceeds the no-allocation Gram workspace", s);
+  HIP_TRY(hipSetDevice(sys->ctx->device));
+  unsigned char* base = sys->ctx->scratch;
+  if (!base) return fail(KPP_ERR_HIP, "the context has no scratch address");
+  hipStream_t st = sys->ctx->stream;
+  int32_t* d_err = reinterpret_cast<int32_t*>(base);
+  int32_t* d_rows = reinterpret_cast<int32_t*>(base + kNaStageOffset);
+  int32_t* d_lens = d_rows + static_cast<size_t>(nb) * s;
+  int32_t* d_ids = d_lens + nb;
+  double* ws = reinterpret_cast<double*>(base + kNaGramOffset);
+  HIP_TRY(hipMemcpyAsync(d_rows, rows_host, static_cast<size_t>(nb) * s * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_lens, len_host, nb * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  kpp::launch_fill_i32(d_ids, nb, 0, 1, st);
+  kpp::launch_fill_i32(d_err, 1, 0, 0, st);
+  kpp::launch_zero_f64(L_dev, static_cast<int64_t>(nb) * s * s, st);
+  const int64_t ss = static_cast<int64_t>(s) * s;
+  if (sys->kind == KPP_KACZMARZ) {
+    for (int32_t b0 = 0; b0 < nb; b0 += batch) {
+      const int32_t k = std::min(batch, nb - b0);
+      kpp::launch_gram_syrk_capped(sys->A, sys->lda, sys->n, d_rows + static_cast<size_t>(b0) * s, d_lens + b0, s, k,
+                                   lambda, L_dev, ss, d_ids + b0, ws, kNaGramDoubles, st);
+    }
+  } else {
+    kpp::launch_gram(sys->kind, sys->A, sys->lda, sys->n, d_rows, d_lens, s, nb, lambda, L_dev, ss, d_ids, nullptr,
+                     st);
+  }
+  HIP_TRY(hipGetLastError());
+  if (s <= kpp::kFactorSmallMax)
+    kpp::launch_factor_small(L_dev, ss, s, d_lens, nb, d_ids, 0, d_err, st);
+  else
+    kpp::launch_cholesky(L_dev, s, ss, d_lens, nb, d_ids, d_err, st);
+  HIP_TRY(hipGetLastError());
+  int32_t herr = 0;
+  HIP_TRY(hipMemcpyAsync(&herr, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
   if (herr) return fail(KPP_ERR_NOT_SPD, "a regularized block Gram has no Cholesky factor");
   return KPP_OK;
 }

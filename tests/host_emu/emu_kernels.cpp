@@ -100,6 +100,33 @@ void launch_gram_f32(int32_t kind, const float* A, int64_t lda, int64_t n, const
   for (int k = 0; k < nb; ++k) check_A(A, 4, lda, rows + static_cast<int64_t>(k) * s, lens[k], n, "gram32 A");
   if (kind == 0) emu_check(ws, 8 * gram_syrk_work(s, n, nb), "gram32 ws");
 }
+void launch_gram_syrk_capped(const double* A, int64_t lda, int64_t n, const int32_t* rows, const int32_t* lens,
+                             int32_t s, int32_t nb, double, double* G, int64_t stride, const int32_t* slot_of,
+                             double* ws, size_t max_work, hipStream_t) {
+  if (nb <= 0) return;
+  check_slots(G, stride, s, lens, nb, slot_of, static_cast<int64_t>(s) * s, "gram capped slots");
+  for (int k = 0; k < nb; ++k) check_A(A, 8, lda, rows + static_cast<int64_t>(k) * s, lens[k], n, "gram capped A");
+  int32_t nc, nt;
+  int64_t chunk;
+  gram_syrk_plan_capped(s, n, nb, max_work, &nc, &chunk, &nt);
+  const size_t work = static_cast<size_t>(nb) * nt * nc * kGramTile * kGramTile;
+  if (work > max_work) { std::fprintf(stderr, "EMU: capped gram plan exceeds its cap\n"); std::abort(); }
+  emu_check(ws, 8 * work, "gram capped ws");
+}
+void launch_fill_i32(int32_t* p, int64_t n, int32_t base, int32_t step, hipStream_t) {
+  emu_check(p, 4 * static_cast<size_t>(n), "fill i32");
+  for (int64_t i = 0; i < n; ++i) p[i] = base + step * static_cast<int32_t>(i);
+}
+void launch_zero_f64(double* p, int64_t n, hipStream_t) {
+  emu_check(p, 8 * static_cast<size_t>(n), "zero f64");
+  for (int64_t i = 0; i < n; ++i) p[i] = 0.0;
+}
+hipError_t noalloc_scratch(int, void** out) {
+  static void* p = nullptr;
+  if (!p && hipMalloc(&p, kNoAllocScratchBytes) != hipSuccess) return hipErrorOutOfMemory;
+  *out = p;
+  return hipSuccess;
+}
 void launch_gram_syrk(const double*, int64_t, int64_t, const int32_t*, const int32_t*, int32_t, int32_t, double,
                       double*, int64_t, const int32_t*, const int32_t*, double*, hipStream_t) {}
 void launch_gram_syrk_f32(const float*, int64_t, int64_t, const int32_t*, const int32_t*, int32_t, int32_t, double,
