@@ -1,13 +1,17 @@
 // Regularized block Grams of Kaczmarz++ on the matrix cores (memo miss path,
 // Algorithm 1 and Section 5.2): G = A_S A_S^T + lambda I for nb blocks at once.
 //
-// The s x s lower triangle is cut into 64 x 64 tiles and the n columns into
-// chunks; one workgroup forms one tile over one chunk with 16 x 16 x 4 MFMA
-// products (FP64, or FP32 inputs with FP32 accumulation for the mixed-precision
-// path), staging 64 x 32 panels of both row groups in LDS.  The per-chunk
-// partial tiles go to a workspace in FP64 and a second kernel sums them in
-// chunk order (deterministic), adds lambda on the diagonal and writes the
-// lower triangle of the column-major slot.
+// One workgroup forms every 16 x 16 tile of one block's lower triangle over
+// one chunk of the n columns.  The block's rows are cut into NG groups of 16
+// (s <= 16 NG); per chunk the rows are staged in LDS panels of KC columns
+// (double-buffered: the next panel's loads are in flight while the matrix
+// cores work on the current one), so every entry of A_S is read once.  Tile
+// (i, j) is the 16x16x4 MFMA product of row group i with row group j (FP64,
+// or FP32 inputs with FP32 accumulation for the mixed-precision path); the
+// waves take the tiles round-robin.  The per-chunk partial tiles go to a
+// workspace in FP64 and a second kernel sums them in chunk order
+// (deterministic), adds lambda on the diagonal and writes the lower triangle
+// of the column-major slot.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,10 +20,6 @@
 
 namespace kpp {
 namespace {
-
-constexpr int kGT = kGramTile;    // output tile edge
-constexpr int kKc = kGramPanel;   // columns per LDS panel
-constexpr int kGThreads = 256;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -46,6 +46,19 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
+// Shape of the Gram kernel for NG row groups: waves, panel width, lower tiles,
+// tiles per wave and tile parts (workgroups per block and chunk).
+template <int NG>
+struct GramShape {
+  static constexpr int NW = NG <= 8 ? 4 : 8;
+  static constexpr int KC = NG <= 8 ? 32 : (NG == 16 ? 16 : 8);
+  static constexpr int R = 16 * NG;
+  static constexpr int NTILE = NG * (NG + 1) / 2;
+  static constexpr int TPW = NG <= 16 ? (NTILE + NW - 1) / NW : 17;
+  static constexpr int PARTS = (NTILE + NW * TPW - 1) / (NW * TPW);
+  static constexpr int LOADS = R * KC / (NW * 64);   // panel entries per thread
+};
+
 // t-th tile of the lower triangle in row order -> (ti, tj), ti >= tj
 __device__ __forceinline__ void tile_coords(int t, int& ti, int& tj) {
   int i = 0;
@@ -54,134 +67,152 @@ __device__ __forceinline__ void tile_coords(int t, int& ti, int& tj) {
   tj = t - i * (i + 1) / 2;
 }
 
-// Partial tile P[i][j] = sum_{k in chunk} A[r_i, k] A[r_j, k] for block rows
-// i in tile row ti, j in tile column tj.  The MFMA takes rows of tile tj as
-// its first operand and rows of tile ti as its second, so lane l, register r
-// holds P[i0 + 16x + l % 16][j0 + 16y + row(l, r)] and the column-major tile
-// store is contiguous across lanes.
-template <typename TA>
-__global__ __launch_bounds__(kGThreads) void k_gram_syrk(const TA* __restrict__ A, int64_t lda, int64_t n,
-                                                         const int32_t* __restrict__ rows,
-                                                         const int32_t* __restrict__ lens, int32_t s,
-                                                         const int32_t* __restrict__ only, int32_t nchunks,
-                                                         int64_t chunk, int32_t ntiles, double* __restrict__ ws) {
+// Partial tiles of block blockIdx.z over chunk blockIdx.x (tile part
+// blockIdx.y): ws[((blk * nchunks + ch) * ntiles + t) * 256 + a * 16 + b] =
+// sum_{k in chunk} A[r_{16 ti + a}, k] A[r_{16 tj + b}, k].  Rows past the
+// block and columns past n enter as zeros.
+template <typename TA, int NG>
+__global__ __launch_bounds__(GramShape<NG>::NW * 64) void k_gram_block(
+    const TA* __restrict__ A, int64_t lda, int64_t n, const int32_t* __restrict__ rows,
+    const int32_t* __restrict__ lens, int32_t s, const int32_t* __restrict__ only, int32_t nchunks, int64_t chunk,
+    double* __restrict__ ws) {
+  using Sh = GramShape<NG>;
   using Acc = typename Mfma<TA>::acc_t;
-  __shared__ TA Ps[kGT][kKc + 1];   // rows of tile ti
-  __shared__ TA Qs[kGT][kKc + 1];   // rows of tile tj (unused on diagonal tiles)
-  __shared__ int32_t ri[kGT], rj[kGT];
-  const int ch = blockIdx.x, t = blockIdx.y, blk = blockIdx.z;
+  constexpr int NT = Sh::NW * 64, KC = Sh::KC, LD = KC + 1;
+  __shared__ TA P[2][Sh::R * LD];
+  __shared__ int32_t ri[Sh::R];
+  const int ch = blockIdx.x, part = blockIdx.y, blk = blockIdx.z;
   if (only && !only[blk]) return;
   const int sb = lens[blk];
-  int ti, tj;
-  tile_coords(t, ti, tj);
-  const int i0 = ti * kGT, j0 = tj * kGT;
-  if (i0 >= sb) return;  // uniform over the workgroup
-  const bool diag = ti == tj;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int32_t* R = rows + static_cast<int64_t>(blk) * s;
-  if (tid < kGT) {
-    ri[tid] = R[min(i0 + tid, sb - 1)];
-    rj[tid] = R[min(j0 + tid, sb - 1)];
-  }
+  const int32_t* Rw = rows + static_cast<int64_t>(blk) * s;
+  for (int i = tid; i < Sh::R; i += NT) ri[i] = i < sb ? Rw[i] : -1;
   __syncthreads();
   const int64_t k_begin = static_cast<int64_t>(ch) * chunk;
   const int64_t k_end = min(n, k_begin + chunk);
 
-  // panel element e = tid + 256 q: row e / 32, column e % 32 (a wave reads two
-  // contiguous row segments per load)
-  TA pv[8], qv[8];
+  // panel entry e = tid + NT q: row e / KC, column e % KC (a wave reads
+  // 64 / KC whole row segments per load)
+  TA pv[Sh::LOADS];
   auto fetch = [&](int64_t k0) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int e = tid + kGThreads * q;
-      const int r = e >> 5, c = e & 31;
+    for (int q = 0; q < Sh::LOADS; ++q) {
+      const int e = tid + NT * q;
+      const int r = e / KC, c = e % KC;
       const int64_t k = k0 + c;
-      const bool ok_k = k < k_end;
-      pv[q] = (ok_k && i0 + r < sb) ? A[static_cast<int64_t>(ri[r]) * lda + k] : TA(0);
-      if (!diag) qv[q] = (ok_k && j0 + r < sb) ? A[static_cast<int64_t>(rj[r]) * lda + k] : TA(0);
+      const int32_t row = ri[r];
+      pv[q] = (row >= 0 && k < k_end) ? A[static_cast<int64_t>(row) * lda + k] : TA(0);
     }
   };
-  auto stash = [&]() {
+  auto stash = [&](int b) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int e = tid + kGThreads * q;
-      const int r = e >> 5, c = e & 31;
-      Ps[r][c] = pv[q];
-      if (!diag) Qs[r][c] = qv[q];
+    for (int q = 0; q < Sh::LOADS; ++q) {
+      const int e = tid + NT * q;
+      P[b][(e / KC) * LD + e % KC] = pv[q];
     }
   };
 
-  // wave wv forms the 32 x 32 quadrant (rows 32 (wv >> 1), columns 32 (wv & 1));
-  // on a diagonal tile the strictly upper quadrant is not needed
-  const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
-  const bool active = !(diag && wr < wc);
-  TA(*Qp)[kKc + 1] = diag ? Ps : Qs;
-  Acc acc[2][2];
+  // this wave's tiles: t = part * NW * TPW + wv + NW u; operand rows in LDS
+  int aoff[Sh::TPW], boff[Sh::TPW];
+  bool act[Sh::TPW];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int u = 0; u < Sh::TPW; ++u) {
+    const int t = part * Sh::NW * Sh::TPW + wv + Sh::NW * u;
+    act[u] = t < Sh::NTILE;
+    int ti = 0, tj = 0;
+    if (act[u]) tile_coords(t, ti, tj);
+    aoff[u] = (16 * ti + (lane & 15)) * LD + (lane >> 4);
+    boff[u] = (16 * tj + (lane & 15)) * LD + (lane >> 4);
+  }
+  Acc acc[Sh::TPW];
 #pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = Acc{0, 0, 0, 0};
+  for (int u = 0; u < Sh::TPW; ++u) acc[u] = Acc{0, 0, 0, 0};
 
   fetch(k_begin);
-  for (int64_t k0 = k_begin; k0 < k_end; k0 += kKc) {
-    __syncthreads();  // the previous panel is consumed
-    stash();
-    __syncthreads();
-    if (k0 + kKc < k_end) fetch(k0 + kKc);
-    if (active) {
-      const int li = lane & 15, lk = lane >> 4;
+  stash(0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = k_begin; k0 < k_end; k0 += KC) {
+    const bool more = k0 + KC < k_end;
+    if (more) fetch(k0 + KC);
+    const TA* Pb = P[buf];
 #pragma unroll
-      for (int kk = 0; kk < kKc; kk += 4) {
-        const TA a0 = Qp[wc + li][kk + lk], a1 = Qp[wc + 16 + li][kk + lk];
-        const TA b0 = Ps[wr + li][kk + lk], b1 = Ps[wr + 16 + li][kk + lk];
-        acc[0][0] = Mfma<TA>::step(a0, b0, acc[0][0]);
-        acc[0][1] = Mfma<TA>::step(a1, b0, acc[0][1]);
-        acc[1][0] = Mfma<TA>::step(a0, b1, acc[1][0]);
-        acc[1][1] = Mfma<TA>::step(a1, b1, acc[1][1]);
-      }
+    for (int kk = 0; kk < KC; kk += 4) {
+#pragma unroll
+      for (int u = 0; u < Sh::TPW; ++u)
+        if (act[u]) acc[u] = Mfma<TA>::step(Pb[aoff[u] + kk], Pb[boff[u] + kk], acc[u]);
     }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
   }
-  if (!active) return;
-  // acc[x][y]: rows wr + 16x + (lane % 16), columns wc + 16y + row(lane, r)
-  double* W = ws + ((static_cast<int64_t>(blk) * ntiles + t) * nchunks + ch) * (kGT * kGT);
-  const int li = lane & 15;
+  // acc[u]: entry (row(lane, r), lane % 16) of tile t
+  double* W = ws + (static_cast<int64_t>(blk) * nchunks + ch) * Sh::NTILE * 256;
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int u = 0; u < Sh::TPW; ++u) {
+    if (!act[u]) continue;
+    const int t = part * Sh::NW * Sh::TPW + wv + Sh::NW * u;
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = wr + 16 * x + li, j = wc + 16 * y + Mfma<TA>::row(lane, r);
-        W[j * kGT + i] = static_cast<double>(acc[x][y][r]);
-      }
+    for (int r = 0; r < 4; ++r)
+      W[t * 256 + Mfma<TA>::row(lane, r) * 16 + (lane & 15)] = static_cast<double>(acc[u][r]);
+  }
 }
 
 // G[slot][j * s + i] = sum over chunks of the partial tiles (+ lambda on the
-// diagonal), lower triangle only
-__global__ __launch_bounds__(kGThreads) void k_gram_reduce(const double* __restrict__ ws, const int32_t* __restrict__ lens,
-                                                           int32_t s, const int32_t* __restrict__ only,
-                                                           int32_t nchunks, int32_t ntiles, double lambda,
-                                                           double* __restrict__ G, int64_t stride,
-                                                           const int32_t* __restrict__ slot_of) {
+// diagonal), lower triangle of the block only; chunks summed in order, with
+// eight loads in flight
+__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ ws, const int32_t* __restrict__ lens,
+                                                     int32_t s, const int32_t* __restrict__ only, int32_t nchunks,
+                                                     int32_t ntiles, double lambda, double* __restrict__ G,
+                                                     int64_t stride, const int32_t* __restrict__ slot_of) {
   const int t = blockIdx.x, blk = blockIdx.y;
   if (only && !only[blk]) return;
   const int sb = lens[blk];
   int ti, tj;
   tile_coords(t, ti, tj);
-  const int i0 = ti * kGT, j0 = tj * kGT;
-  if (i0 >= sb) return;
-  const double* W = ws + (static_cast<int64_t>(blk) * ntiles + t) * nchunks * (kGT * kGT);
-  double* Gb = G + static_cast<int64_t>(slot_of[blk]) * stride;
-  for (int e = threadIdx.x; e < kGT * kGT; e += kGThreads) {
-    const int i = i0 + (e & (kGT - 1)), j = j0 + (e >> 6);
-    if (i >= sb || j >= sb || i < j) continue;
-    double acc = 0.0;
-    for (int c = 0; c < nchunks; ++c) acc += W[static_cast<int64_t>(c) * kGT * kGT + e];
-    Gb[static_cast<int64_t>(j) * s + i] = acc + (i == j ? lambda : 0.0);
+  const int e = threadIdx.x;
+  const int i = 16 * ti + (e >> 4), j = 16 * tj + (e & 15);
+  if (i >= sb || j >= sb || i < j) return;
+  const int64_t cs = static_cast<int64_t>(ntiles) * 256;
+  const double* W = ws + static_cast<int64_t>(blk) * nchunks * cs + t * 256 + e;
+  double acc = 0.0;
+  int c = 0;
+  for (; c + 8 <= nchunks; c += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = W[(c + u) * cs];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
   }
+  for (; c < nchunks; ++c) acc += W[c * cs];
+  G[static_cast<int64_t>(slot_of[blk]) * stride + static_cast<int64_t>(j) * s + i] = acc + (i == j ? lambda : 0.0);
 }
 
 }  // namespace
+
+template <typename TA, int NG>
+static void launch_block_grams(const TA* A, int64_t lda, int64_t n, const int32_t* rows, const int32_t* lens, int32_t s,
+                               int32_t nb, const int32_t* only, int32_t nc, int64_t chunk, double* ws, hipStream_t st) {
+  using Sh = GramShape<NG>;
+  hipLaunchKernelGGL((k_gram_block<TA, NG>), dim3(nc, Sh::PARTS, nb), dim3(Sh::NW * 64), 0, st, A, lda, n, rows, lens,
+                     s, only, nc, chunk, ws);
+}
+
+template <typename TA>
+static void launch_syrk_planned(const TA* A, int64_t lda, int64_t n, const int32_t* rows, const int32_t* lens,
+                                int32_t s, int32_t nb, double lambda, double* G, int64_t stride,
+                                const int32_t* slot_of, const int32_t* only, double* ws, int32_t nc, int64_t chunk,
+                                int32_t nt, hipStream_t st) {
+  switch (gram_groups(s)) {
+    case 2: launch_block_grams<TA, 2>(A, lda, n, rows, lens, s, nb, only, nc, chunk, ws, st); break;
+    case 4: launch_block_grams<TA, 4>(A, lda, n, rows, lens, s, nb, only, nc, chunk, ws, st); break;
+    case 8: launch_block_grams<TA, 8>(A, lda, n, rows, lens, s, nb, only, nc, chunk, ws, st); break;
+    case 16: launch_block_grams<TA, 16>(A, lda, n, rows, lens, s, nb, only, nc, chunk, ws, st); break;
+    default: launch_block_grams<TA, 32>(A, lda, n, rows, lens, s, nb, only, nc, chunk, ws, st); break;
+  }
+  hipLaunchKernelGGL(k_gram_reduce, dim3(nt, nb), dim3(256), 0, st, ws, lens, s, only, nc, nt, lambda, G, stride,
+                     slot_of);
+}
 
 template <typename TA>
 static void launch_syrk(const TA* A, int64_t lda, int64_t n, const int32_t* rows, const int32_t* lens, int32_t s,
@@ -190,10 +221,7 @@ static void launch_syrk(const TA* A, int64_t lda, int64_t n, const int32_t* rows
   int32_t nc, nt;
   int64_t chunk;
   gram_syrk_plan(s, n, nb, &nc, &chunk, &nt);
-  hipLaunchKernelGGL(k_gram_syrk<TA>, dim3(nc, nt, nb), dim3(kGThreads), 0, st, A, lda, n, rows, lens, s, only, nc,
-                     chunk, nt, ws);
-  hipLaunchKernelGGL(k_gram_reduce, dim3(nt, nb), dim3(kGThreads), 0, st, ws, lens, s, only, nc, nt, lambda, G,
-                     stride, slot_of);
+  launch_syrk_planned<TA>(A, lda, n, rows, lens, s, nb, lambda, G, stride, slot_of, only, ws, nc, chunk, nt, st);
 }
 
 void launch_gram_syrk(const double* A, int64_t lda, int64_t n, const int32_t* rows, const int32_t* lens, int32_t s,
@@ -210,10 +238,7 @@ void launch_gram_syrk_capped(const double* A, int64_t lda, int64_t n, const int3
   int32_t nc, nt;
   int64_t chunk;
   gram_syrk_plan_capped(s, n, nb, max_work, &nc, &chunk, &nt);
-  hipLaunchKernelGGL(k_gram_syrk<double>, dim3(nc, nt, nb), dim3(kGThreads), 0, st, A, lda, n, rows, lens, s,
-                     nullptr, nc, chunk, nt, ws);
-  hipLaunchKernelGGL(k_gram_reduce, dim3(nt, nb), dim3(kGThreads), 0, st, ws, lens, s, nullptr, nc, nt, lambda, G,
-                     stride, slot_of);
+  launch_syrk_planned<double>(A, lda, n, rows, lens, s, nb, lambda, G, stride, slot_of, nullptr, ws, nc, chunk, nt, st);
 }
 
 void launch_gram_syrk_f32(const float* A, int64_t lda, int64_t n, const int32_t* rows, const int32_t* lens, int32_t s,

@@ -990,225 +990,268 @@ __global__ __launch_bounds__(kT) void k_inverse_blocked(double* __restrict__ slo
 }
 
 // --------------------------------------------------------------------------
-// memo miss for blocks of up to 128 rows, register resident: Cholesky
-// L L^T = G, then L^{-1} by Gauss-Jordan elimination on [L | I] (stored in
-// place), then G^{-1} = L^{-T} L^{-1}.  Thread (ty, tx) of a 16 x 16 grid
-// holds entries (ty + 16a, tx + 16b), a, b < 8, of the block in registers;
-// every phase is s rank-1 updates whose vectors travel through LDS.  The
-// elimination index j = 16 jb + jj is split so that the register column jb
-// is a compile-time index and a step has a single predicated branch.
-// Entries outside the lower triangle or the block are never read back.
+// memo miss for blocks of up to 128 rows (one workgroup per block): the
+// regularized Gram is cut into 16 x 16 tiles of its lower triangle, held in
+// LDS (column-major tiles, column stride 17 so that the matrix-core operand
+// and result patterns hit distinct banks).
+//   Cholesky, right-looking over tile columns p: wave 0 factors the diagonal
+//   tile in registers (lane r holds row r; each column's entries are
+//   broadcast with readlane) and inverts it (lane k forms column k of the
+//   inverse by forward substitution); the tiles below are L_ip = A_ip
+//   L_pp^{-T}, and the trailing tiles are updated A_ij -= L_ip L_jp^T, each
+//   tile product on the FP64 16x16x4 matrix cores, tiles spread over waves.
+//   L^{-1} in place, tile column j from the last to the first:
+//   X_ij = -(sum_{k=j+1..i} X_ik L_kj) X_jj (the X_ik are the columns already
+//   inverted, X_jj the diagonal inverse kept from the factorization).
+//   G^{-1} = X^T X tile by tile (G^{-1}_ij = sum_{k>=i} X_ki^T X_kj), stored
+//   with its mirror image so the result is exactly symmetric.
+// Ragged blocks are padded with the identity up to the next tile edge.
+// Matrix-core layouts (16x16x4 FP64): lane l supplies X[l % 16][l / 16] of
+// the 16 x 4 operand and Y[l / 16][l % 16] of the 4 x 16 one; register q of
+// lane l receives D[l / 16 + 4 q][l % 16].
 // --------------------------------------------------------------------------
+constexpr int kFT = 16;                          // tile edge
+constexpr int kFLd = 17;                         // LDS column stride inside a tile
+constexpr int kFTile = kFT * kFLd;               // doubles per LDS tile
+constexpr int kFMaxT = kFactorSmallMax / kFT;    // tiles per block edge (8)
+constexpr int kFLower = kFMaxT * (kFMaxT + 1) / 2;
+constexpr int kFLdsDoubles = (kFLower + kFMaxT + 4) * kFTile;   // tiles, diagonal inverses, wave scratch
+constexpr size_t kFactorTiledLds = static_cast<size_t>(kFLdsDoubles) * sizeof(double);
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int ftix(int i, int j) { return i * (i + 1) / 2 + j; }
+__device__ __forceinline__ double rdlane(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ f64x4 mma(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// acc += sign * Xt Yt over the tile's 16 columns, where lane l reads operand
+// entries at xa + (kk + l/16) * kFLd + l%16 ("n": X = the tile itself) or
+// xa + (l%16) * kFLd + kk + l/16 ("t": X = the tile transposed).
+template <bool XT, bool YT>
+__device__ __forceinline__ f64x4 tile_mma(const double* xa, const double* yb, f64x4 acc, int lane, double sign) {
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < kFT; kk += 4) {
+    const double a = XT ? xa[lr * kFLd + kk + lk] : xa[(kk + lk) * kFLd + lr];
+    const double b = YT ? yb[lr * kFLd + kk + lk] : yb[(kk + lk) * kFLd + lr];
+    acc = mma(sign * a, b, acc);
+  }
+  return acc;
+}
+__device__ __forceinline__ f64x4 tile_load_d(const double* t, int lane) {
+  const int c = lane & 15, r = lane >> 4;
+  return f64x4{t[c * kFLd + r], t[c * kFLd + r + 4], t[c * kFLd + r + 8], t[c * kFLd + r + 12]};
+}
+__device__ __forceinline__ void tile_store_d(double* t, f64x4 v, int lane) {
+  const int c = lane & 15, r = lane >> 4;
+  t[c * kFLd + r] = v[0];
+  t[c * kFLd + r + 4] = v[1];
+  t[c * kFLd + r + 8] = v[2];
+  t[c * kFLd + r + 12] = v[3];
+}
+
 __global__ __launch_bounds__(kT) void k_factor_small(double* __restrict__ slots, int64_t stride,
                                                      int32_t s, const int32_t* __restrict__ lens,
                                                      const int32_t* __restrict__ slot_of,
                                                      int32_t want_inverse, int32_t* __restrict__ err,
                                                      FactorCheck chk) {
-  __shared__ double colbuf[128];
-  __shared__ double rowbuf[128];
-  __shared__ double piv;
-  __shared__ double dmin[16], dmax[16];
+  extern __shared__ double fl[];
+  double* T = fl;                                  // lower tiles, tile (i, j) at ftix(i, j) * kFTile
+  double* Dv = fl + kFLower * kFTile;              // inverses of the diagonal tiles of L
+  double* Sc = Dv + kFMaxT * kFTile;               // one scratch tile per wave
+  __shared__ double red4[4];
+  __shared__ double norm_g2;
   __shared__ int flag_blk;
   const int blk = blockIdx.x;
   if (chk.only && !chk.only[blk]) return;
   const int sb = lens[blk];
   double* Lc = slots + static_cast<int64_t>(slot_of[blk]) * stride;
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-  double g[8][8];
-#pragma unroll
-  for (int a = 0; a < 8; ++a)
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int i = ty + 16 * a, k = tx + 16 * b;
-      const int ic = min(i, sb - 1), kc = min(k, sb - 1);
-      const double v = Lc[static_cast<int64_t>(kc) * s + ic];
-      g[a][b] = (i < sb && k < sb && i >= k) ? v : 0.0;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nt = (sb + kFT - 1) / kFT;
+  const int nlow = nt * (nt + 1) / 2;
+  // G (lower triangle of the slot) into the tiles, identity past the block
+  double g2 = 0.0;
+  for (int e = tid; e < nlow * 256; e += kT) {
+    const int t = e >> 8, w = e & 255, c = w >> 4, r = w & 15;
+    int ti = 0;
+    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+    const int tj = t - ti * (ti + 1) / 2;
+    const int i = ti * kFT + r, k = tj * kFT + c;
+    double v;
+    if (i < sb && k < sb) {
+      v = i >= k ? Lc[static_cast<int64_t>(k) * s + i] : 0.0;
+      g2 += (i == k ? 1.0 : 2.0) * v * v;
+    } else {
+      v = i == k ? 1.0 : 0.0;
     }
-  __shared__ double red4[4];
-  __shared__ double norm_g2;
-  if (chk.flag) {
-    // ||G||_F^2 of the symmetric Gram (only the lower triangle is held)
-    double acc = 0.0;
-#pragma unroll
-    for (int a = 0; a < 8; ++a)
-#pragma unroll
-      for (int b = 0; b < 8; ++b) acc += ((ty + 16 * a) == (tx + 16 * b) ? 1.0 : 2.0) * g[a][b] * g[a][b];
-    acc = block_sum(acc, red4);
-    if (threadIdx.x == 0) norm_g2 = acc;
+    T[t * kFTile + c * kFLd + r] = v;
   }
+  if (chk.flag) {
+    g2 = block_sum(g2, red4);
+    if (tid == 0) norm_g2 = g2;
+  }
+  __syncthreads();
+
   int bad = 0;
-  // Cholesky, right-looking
+  for (int p = 0; p < nt; ++p) {
+    double* Tp = T + ftix(p, p) * kFTile;
+    double* Dp = Dv + p * kFTile;
+    if (wv == 0) {
+      // the diagonal tile: lane r (mod 16) holds row r
+      const int r = lane & 15;
+      double a[kFT];
 #pragma unroll
-  for (int jb = 0; jb < 8; ++jb) {
-    for (int jj = 0; jj < 16; ++jj) {
-      const int j = 16 * jb + jj;
-      if (j >= sb) break;
-      if (ty == jj && tx == jj) {
-        const double d = g[jb][jb];
+      for (int c = 0; c < kFT; ++c) a[c] = Tp[c * kFLd + r];
+#pragma unroll
+      for (int j = 0; j < kFT; ++j) {
+        const double d = rdlane(a[j], j);
         bad |= !(d > 0.0);
-        g[jb][jb] = sqrt(d);
-        piv = g[jb][jb];
-      }
-      __syncthreads();
-      const double rinv = 1.0 / piv;
-      if (tx == jj) {
+        const double ljj = sqrt(d);
+        const double rl = 1.0 / ljj;
+        a[j] = r > j ? a[j] * rl : (r == j ? ljj : a[j]);
 #pragma unroll
-        for (int a = 0; a < 8; ++a) {
-          const int i = ty + 16 * a;
-          const bool below = i > j && i < sb;
-          const double v = g[a][jb] * rinv;
-          g[a][jb] = below ? v : g[a][jb];
-          colbuf[i] = below ? v : 0.0;
+        for (int k = j + 1; k < kFT; ++k) {
+          const double lk = rdlane(a[j], k);
+          a[k] = r >= k ? fma(-a[j], lk, a[k]) : a[k];
         }
       }
-      __syncthreads();
+      if (lane < kFT) {
 #pragma unroll
-      for (int a = 0; a < 8; ++a) {
-        const double ci = colbuf[ty + 16 * a];
-#pragma unroll
-        for (int b = 0; b < 8; ++b) g[a][b] = fma(-ci, colbuf[tx + 16 * b], g[a][b]);
+        for (int c = 0; c < kFT; ++c)
+          if (c <= r) Tp[c * kFLd + r] = a[c];
       }
-      __syncthreads();
-    }
-  }
+      // its inverse: lane k forms column k by forward substitution, reading
+      // the factor back from LDS (the same address in every lane)
+      const int kc = lane & 15;
+      double x[kFT];
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+      for (int i = 0; i < kFT; ++i) {
+        double acc = 0.0;
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int i = ty + 16 * a, k = tx + 16 * b;
-      if (i < s && k < s) Lc[static_cast<int64_t>(k) * s + i] = (i < sb && k < sb && i >= k) ? g[a][b] : 0.0;
-    }
-  // breakdown, and kappa(G) >= (max L_ii / min L_ii)^2 from the factor's diagonal
-  if (tx == ty) {
-    double lo = 1.0 / 0.0, hi = 0.0;
+        for (int m = 0; m < i; ++m) acc = fma(Tp[m * kFLd + i], x[m], acc);
+        const double inv = 1.0 / Tp[i * kFLd + i];
+        x[i] = i == kc ? inv : (i > kc ? -acc * inv : 0.0);
+      }
+      if (lane < kFT) {
 #pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const int i = ty + 16 * a;
-      if (i < sb) {
-        lo = fmin(lo, g[a][a]);
-        hi = fmax(hi, g[a][a]);
+        for (int i = 0; i < kFT; ++i) Dp[kc * kFLd + i] = x[i];
       }
     }
-    dmin[ty] = lo;
-    dmax[ty] = hi;
-  }
-  if (threadIdx.x == 0) flag_blk = 0;
-  __syncthreads();
-  if (bad) atomicOr(&flag_blk, 1);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double lo = dmin[0], hi = dmax[0];
-    for (int u = 1; u < 16; ++u) {
-      lo = fmin(lo, dmin[u]);
-      hi = fmax(hi, dmax[u]);
-    }
-    const double ratio = hi / lo;
-    const bool ill = !(ratio * ratio <= chk.kappa_max);
-    if (chk.flag) {
-      // low-precision pass: mark the block for an FP64 redo instead of failing
-      const int f = (flag_blk || ill) ? 1 : 0;
-      chk.flag[blk] = f;
-      if (f) atomicAdd(chk.counter, 1);
-      flag_blk = f;
-    } else if (flag_blk) {
-      atomicOr(err, 1);
-    }
-  }
-  __syncthreads();
-  if (chk.flag && flag_blk) return;  // the FP64 pass recomputes this block
-  if (!want_inverse) return;
-  // L^{-1} in place: at step j, row j is scaled by 1/L_jj and eliminated from
-  // the rows below (their left entries in column j are still L's)
-#pragma unroll
-  for (int jb = 0; jb < 8; ++jb) {
-    for (int jj = 0; jj < 16; ++jj) {
-      const int j = 16 * jb + jj;
-      if (j >= sb) break;
-      if (ty == jj && tx == jj) {
-        g[jb][jb] = 1.0 / g[jb][jb];
-        piv = g[jb][jb];
-      }
-      __syncthreads();
-      const double pinv = piv;
-      if (ty == jj) {
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const int k = tx + 16 * b;
-          const double v = g[jb][b] * pinv;
-          g[jb][b] = (k < j) ? v : g[jb][b];
-          rowbuf[k] = (k < j) ? v : (k == j ? pinv : 0.0);
-        }
-      }
-      if (tx == jj) {
-#pragma unroll
-        for (int a = 0; a < 8; ++a) {
-          const int i = ty + 16 * a;
-          colbuf[i] = (i > j && i < sb) ? g[a][jb] : 0.0;
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int a = 0; a < 8; ++a) {
-        const double ci = colbuf[ty + 16 * a];
-#pragma unroll
-        for (int b = 0; b < 8; ++b) g[a][b] = fma(-ci, rowbuf[tx + 16 * b], g[a][b]);
-      }
-      if (tx == jj) {
-#pragma unroll
-        for (int a = 0; a < 8; ++a) {
-          const int i = ty + 16 * a;
-          g[a][jb] = (i > j && i < sb) ? -colbuf[i] * pinv : g[a][jb];
-        }
-      }
-      __syncthreads();
-    }
-  }
-  // G^{-1} = X^T X with X = L^{-1}: rank-1 update per row r of X
-  double h[8][8];
-#pragma unroll
-  for (int a = 0; a < 8; ++a)
-#pragma unroll
-    for (int b = 0; b < 8; ++b) h[a][b] = 0.0;
-#pragma unroll
-  for (int rb = 0; rb < 8; ++rb) {
-    for (int rr = 0; rr < 16; ++rr) {
-      const int r = 16 * rb + rr;
-      if (r >= sb) break;
-      if (ty == rr) {
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const int k = tx + 16 * b;
-          rowbuf[k] = (k <= r) ? g[rb][b] : 0.0;
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int a = 0; a < 8; ++a) {
-        const double xi = rowbuf[ty + 16 * a];
-#pragma unroll
-        for (int b = 0; b < 8; ++b) h[a][b] = fma(xi, rowbuf[tx + 16 * b], h[a][b]);
-      }
-      __syncthreads();
-    }
-  }
-  double* Gi = Lc + static_cast<int64_t>(s) * s;
-#pragma unroll
-  for (int a = 0; a < 8; ++a)
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int i = ty + 16 * a, k = tx + 16 * b;
-      if (i < sb && k < sb) Gi[static_cast<int64_t>(k) * s + i] = h[a][b];
-    }
-  if (chk.flag) {
-    // entries outside the block are zero in h
-    double acc = 0.0;
-#pragma unroll
-    for (int a = 0; a < 8; ++a)
-#pragma unroll
-      for (int b = 0; b < 8; ++b) acc = fma(h[a][b], h[a][b], acc);
     __syncthreads();
-    acc = block_sum(acc, red4);
-    if (threadIdx.x == 0) flag_ill_conditioned(chk, blk, norm_g2, acc);
+    // tiles below the diagonal: L_ip = A_ip L_pp^{-T}
+    for (int i = p + 1 + wv; i < nt; i += 4) {
+      double* Ti = T + ftix(i, p) * kFTile;
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+      acc = tile_mma<false, false>(Ti, Dp, acc, lane, 1.0);
+      tile_store_d(Ti, acc, lane);
+    }
+    __syncthreads();
+    // trailing tiles: A_ij -= L_ip L_jp^T
+    const int mrem = nt - p - 1;
+    for (int u = wv; u < mrem * (mrem + 1) / 2; u += 4) {
+      int ii = 0;
+      while ((ii + 1) * (ii + 2) / 2 <= u) ++ii;
+      const int i = p + 1 + ii, j = p + 1 + (u - ii * (ii + 1) / 2);
+      double* Tij = T + ftix(i, j) * kFTile;
+      f64x4 acc = tile_load_d(Tij, lane);
+      acc = tile_mma<false, false>(T + ftix(i, p) * kFTile, T + ftix(j, p) * kFTile, acc, lane, -1.0);
+      tile_store_d(Tij, acc, lane);
+    }
+    __syncthreads();
+  }
+
+  // breakdown, and kappa(G) >= (max L_ii / min L_ii)^2 from the factor's diagonal
+  if (wv == 0) {
+    double lo = 1.0 / 0.0, hi = 0.0;
+    for (int i = lane; i < sb; i += 64) {
+      const double d = T[ftix(i >> 4, i >> 4) * kFTile + (i & 15) * kFLd + (i & 15)];
+      lo = fmin(lo, d);
+      hi = fmax(hi, d);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      lo = fmin(lo, __shfl_xor(lo, off, 64));
+      hi = fmax(hi, __shfl_xor(hi, off, 64));
+    }
+    if (lane == 0) {
+      const double ratio = hi / lo;
+      const bool ill = !(ratio * ratio <= chk.kappa_max);
+      if (chk.flag) {
+        // low-precision pass: mark the block for an FP64 redo instead of failing
+        const int f = (bad || ill) ? 1 : 0;
+        chk.flag[blk] = f;
+        if (f) atomicAdd(chk.counter, 1);
+        flag_blk = f;
+      } else {
+        if (bad) atomicOr(err, 1);
+        flag_blk = 0;
+      }
+    }
+  }
+  __syncthreads();
+  // L to the slot (column-major, zero outside the block's lower triangle)
+  for (int e = tid; e < s * s; e += kT) {
+    const int i = e % s, k = e / s;
+    Lc[static_cast<int64_t>(k) * s + i] =
+        (i < sb && k < sb && i >= k) ? T[ftix(i >> 4, k >> 4) * kFTile + (k & 15) * kFLd + (i & 15)] : 0.0;
+  }
+  if (flag_blk || !want_inverse) return;   // uniform: the FP64 pass recomputes a flagged block
+
+  // L^{-1} in place, tile columns from the last to the first
+  double* Sw = Sc + wv * kFTile;
+  for (int j = nt - 2; j >= 0; --j) {
+    // X_ij for i = j + 1 + wv and i = j + 5 + wv (a tile column has at most 7)
+    auto column_tile = [&](int i) {
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int k = j + 1; k <= i; ++k) {
+        const double* Xik = k == i ? Dv + i * kFTile : T + ftix(i, k) * kFTile;
+        acc = tile_mma<false, true>(Xik, T + ftix(k, j) * kFTile, acc, lane, 1.0);
+      }
+      tile_store_d(Sw, acc, lane);
+      const f64x4 zero = {0.0, 0.0, 0.0, 0.0};
+      return tile_mma<false, true>(Sw, Dv + j * kFTile, zero, lane, -1.0);
+    };
+    const int i0 = j + 1 + wv, i1 = j + 5 + wv;
+    f64x4 res0 = {0.0, 0.0, 0.0, 0.0}, res1 = {0.0, 0.0, 0.0, 0.0};
+    if (i0 < nt) res0 = column_tile(i0);
+    if (i1 < nt) res1 = column_tile(i1);
+    __syncthreads();
+    if (i0 < nt) tile_store_d(T + ftix(i0, j) * kFTile, res0, lane);
+    if (i1 < nt) tile_store_d(T + ftix(i1, j) * kFTile, res1, lane);
+    __syncthreads();
+  }
+  // G^{-1} = X^T X, lower tiles, stored with their mirror images
+  double* Gi = Lc + static_cast<int64_t>(s) * s;
+  double gi2 = 0.0;
+  for (int u = wv; u < nlow; u += 4) {
+    int i = 0;
+    while ((i + 1) * (i + 2) / 2 <= u) ++i;
+    const int j = u - i * (i + 1) / 2;
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k = i; k < nt; ++k) {
+      const double* Xki = k == i ? Dv + i * kFTile : T + ftix(k, i) * kFTile;
+      const double* Xkj = k == j ? Dv + j * kFTile : T + ftix(k, j) * kFTile;
+      acc = tile_mma<true, true>(Xki, Xkj, acc, lane, 1.0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = i * kFT + (lane >> 4) + 4 * q, col = j * kFT + (lane & 15);
+      if (row < sb && col < sb && (i != j || row >= col)) {
+        const double v = acc[q];
+        Gi[static_cast<int64_t>(col) * s + row] = v;
+        Gi[static_cast<int64_t>(row) * s + col] = v;
+        gi2 += (row == col ? 1.0 : 2.0) * v * v;
+      }
+    }
+  }
+  if (chk.flag) {
+    gi2 = block_sum(gi2, red4);
+    if (tid == 0) flag_ill_conditioned(chk, blk, norm_g2, gi2);
   }
 }
 
@@ -1449,7 +1492,13 @@ void launch_factor_small(double* slots, int64_t stride, int32_t s, const int32_t
                          const int32_t* slot_of, int32_t want_inverse, int32_t* err, hipStream_t st,
                          FactorCheck chk) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL(k_factor_small, dim3(nb), dim3(kT), 0, st, slots, stride, s, lens, slot_of,
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_factor_small),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kFactorTiledLds));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_factor_small, dim3(nb), dim3(kT), kFactorTiledLds, st, slots, stride, s, lens, slot_of,
                      want_inverse, err, chk);
 }
 

@@ -69,12 +69,21 @@ void launch_gram_f32(int32_t kind, const float* A, int64_t lda, int64_t n, const
                      const int32_t* lens, int32_t s, int32_t nb, double lambda, double* G, int64_t stride,
                      const int32_t* slot_of, double* ws, hipStream_t st);
 
-// Kaczmarz++ Grams A_S A_S^T + lambda I on the matrix cores: 64 x 64 lower
-// tiles x column chunks, 16x16x4 MFMA (FP64, or FP32 in / FP32 accumulate),
-// FP64 partial tiles summed in chunk order.  gram_syrk_plan gives the split.
-constexpr int kGramTile = 64;
-constexpr int kGramPanel = 32;
-constexpr int kGramTargetGroups = 1024;
+// Kaczmarz++ Grams A_S A_S^T + lambda I on the matrix cores: a workgroup
+// forms every 16 x 16 tile of a block's lower triangle over one column chunk
+// (16x16x4 MFMA, FP64, or FP32 in / FP32 accumulate), reading the block's
+// rows once; FP64 partial tiles are summed in chunk order.  The rows are cut
+// into gram_groups(s) groups of 16; gram_syrk_plan gives the split (ntiles =
+// lower tiles per block, nchunks column chunks of `chunk` columns).
+constexpr int kGramTile = 16;
+constexpr int kGramTargetGroups = 512;
+constexpr int kGramMinPanels = 8;       // a chunk spans at least this many LDS panels
+inline int32_t gram_groups(int32_t s) {
+  int32_t g = 2;
+  while (16 * g < s) g *= 2;
+  return g;
+}
+inline int32_t gram_panel(int32_t groups) { return groups <= 8 ? 32 : (groups == 16 ? 16 : 8); }
 void gram_syrk_plan(int32_t s, int64_t n, int32_t nb, int32_t* nchunks, int64_t* chunk, int32_t* ntiles);
 size_t gram_syrk_work(int32_t s, int64_t n, int32_t nb);
 void launch_gram_syrk(const double* A, int64_t lda, int64_t n, const int32_t* rows, const int32_t* lens, int32_t s,

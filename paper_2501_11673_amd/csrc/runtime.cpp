@@ -2870,8 +2870,8 @@ KPP_API kpp_status kpp_block_factor_noalloc(kpp_system* sys, int32_t s, double l
     }
   }
   if (nb == 0) return KPP_OK;
-  const int32_t nt = (s + kpp::kGramTile - 1) / kpp::kGramTile;
-  const size_t per_block = static_cast<size_t>(nt) * (nt + 1) / 2 * kpp::kGramTile * kpp::kGramTile;
+  const int32_t ng = kpp::gram_groups(s);
+  const size_t per_block = static_cast<size_t>(ng) * (ng + 1) / 2 * kpp::kGramTile * kpp::kGramTile;
   const int32_t batch = static_cast<int32_t>(std::min<size_t>(static_cast<size_t>(nb), kNaGramDoubles / per_block));
   if (batch < 1) return fail(KPP_ERR_INVALID_ARG, "block size %d exceeds the no-allocation Gram workspace", s);
   HIP_TRY(hipSetDevice(sys->ctx->device));
