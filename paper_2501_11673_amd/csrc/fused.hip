@@ -52,7 +52,8 @@ struct TileElems {
   static constexpr int value = (sizeof(TA) == 4 && CPL >= 4) ? 128 : 64;
 };
 static_assert(kFlagStride * kFusedMaxGroups <= kYFlagOffset, "flag area too small");
-static_assert(kYFlagOffset + kFlagStride * kFusedMaxGroups <= kFlagWordsAlloc, "flag area too small");
+static_assert(kYFlagOffset + 2 * kFlagStride * kFusedMaxGroups <= kFlagWordsAlloc, "flag area too small");
+static_assert(4 * kTwoMaxBlock <= 2 * kFusedMaxBlock, "exchange buffer too small for r and y");
 
 __device__ __forceinline__ double ld_coherent(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -71,6 +72,17 @@ __device__ __forceinline__ uint32_t ld_flag(uint32_t* p) {
 __device__ __forceinline__ void st_flag_after_stores(uint32_t* p, uint32_t v) {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Spin until a flag reaches epoch ep (agent-scope loads); false once the
+// bound is exceeded.
+__device__ __forceinline__ bool wait_flag(uint32_t* f, uint32_t ep, int64_t limit) {
+  int64_t spins = 0;
+  while (static_cast<int32_t>(ld_flag(f) - ep) < 0) {
+    if (KPP_POLL_SLEEP > 0) __builtin_amdgcn_s_sleep(KPP_POLL_SLEEP);
+    if (++spins > limit) return false;
+  }
+  return true;
 }
 
 __device__ __forceinline__ double rho_from_rate(double rhat, int zeta) {
@@ -340,6 +352,8 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     }
     // Kaczmarz++ with y split across the team: this workgroup's rows of y
     const bool ysplit = KIND == 0 && a.ysplit != 0;
+    // Kaczmarz++, large team: two-level exchange of r, y formed locally
+    const bool two = KIND == 0 && a.xchg2 != 0;
     const int yper = (sb + G - 1) / G;
     if (ysplit) {
       lo = min(sb, wg * yper);
@@ -380,6 +394,50 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
       myrow_nn = tile_row_index<CPL, TA, TE>(R2, sb2, wv, lane);
       if (tid < sb2) rown_nn = R2[tid];
     }
+    const int nu = (sb + 63) >> 6;
+    if (two) {
+      // two-level exchange: row owners sum the G partials of their rows and
+      // publish r there; every workgroup then gathers r (2 s doubles instead
+      // of G s).  Wave 0 does all of it; the other waves wait at the barrier.
+      const int rper = (sb + G - 1) / G;
+      const int o0 = min(sb, wg * rper), o1 = min(sb, o0 + rper);
+      const int nown = (sb + rper - 1) / rper;
+      double* Rb = a.ypart + static_cast<size_t>(ep & 1u) * s;
+      uint32_t* f2 = a.flags + kYFlagOffset;
+      if (wv == 0) {
+        bool ok = true;
+        if (o0 < o1) {
+          for (int g = lane; g < G && ok; g += 64) ok = wait_flag(&a.flags[g * kFlagStride], ep, a.spin_limit);
+          if (__all(ok ? 1 : 0)) {   // every lane saw its flags
+            for (int i = o0; i < o1; ++i) {
+              double acc = 0.0;
+              for (int g = lane; g < G; g += 64) acc += ld_coherent(&Pb[static_cast<size_t>(g) * s + i]);
+              acc = wave_sum(acc);
+              if (lane == 0) st_coherent(&Rb[i], acc - a.b[rs[i]]);
+            }
+            if (lane == 0) st_flag_after_stores(&f2[wg * kFlagStride], ep);
+          }
+        }
+        for (int o = lane; o < nown && ok; o += 64) ok = wait_flag(&f2[o * kFlagStride], ep, a.spin_limit);
+        if (!ok) {
+          atomicOr(a.err, 2);
+          abort_flag = 1;
+        }
+      }
+      __syncthreads();
+      KPP_MARK(3)
+      if (abort_flag) break;
+      double rr_w = 0.0;
+      if (tid < sb) {
+        const double ri = ld_coherent(&Rb[tid]);
+        rv[tid] = ri;
+        rr_w = ri * ri;
+      }
+      if (wv < nu) {
+        rr_w = wave_sum(rr_w);
+        if (lane == 0) red[wv] = rr_w;
+      }
+    } else {
     if (tid < G) {
       int64_t spins = 0;
       while (static_cast<int32_t>(ld_flag(&a.flags[tid * kFlagStride]) - ep) < 0) {
@@ -397,7 +455,6 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     // r = sum_g p_g - b_S: wave w sums block rows 64 w .. 64 w + 63, one row
     // per lane, so that every wave's partial loads are a single batch; then
     // the next step's rows and b values (used after this step)
-    const int nu = (sb + 63) >> 6;
     if (wv < nu) {
       const int c = min(tid, sb - 1);   // rows past the block: clamped, sum dropped
       double acc = 0.0;
@@ -426,6 +483,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
       rr_w = wave_sum(rr_w);
       if (lane == 0) red[wv] = rr_w;
     }
+    }
     __syncthreads();
     KPP_MARK(4)
 
@@ -453,8 +511,10 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
         // all-gather of y: publish this workgroup's rows, wait for every
         // workgroup that owns rows, read all of y (the same values everywhere)
         __syncthreads();
-        double* Yb = a.ypart + static_cast<size_t>(ep & 1u) * s;
-        uint32_t* yflags = a.flags + kYFlagOffset;
+        // (after a two-level exchange of r, the y all-gather has buffers and
+        // flags of its own: r's occupy the first ones)
+        double* Yb = a.ypart + (two ? 2 * kTwoMaxBlock : 0) + static_cast<size_t>(ep & 1u) * s;
+        uint32_t* yflags = a.flags + kYFlagOffset + (two ? kFusedMaxGroups * kFlagStride : 0);
         if (wv == 0) {
           for (int i = lo + lane; i < hi; i += 64) st_coherent(&Yb[i], yv[i]);
           if (lane == 0) st_flag_after_stores(&yflags[wg * kFlagStride], ep);

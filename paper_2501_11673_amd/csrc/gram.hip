@@ -48,13 +48,17 @@ struct Mfma<float> {
 
 // Shape of the Gram kernel for NG row groups: waves, panel width, lower tiles,
 // tiles per wave and tile parts (workgroups per block and chunk).
+// The 128-row shape (NG = 8) runs eight waves of 64 registers (16-column
+// panels, three tiles per wave, two workgroups per block and chunk), so that
+// it fits beside a resident step kernel on every SIMD: the memo-miss path
+// runs concurrently with the step kernel.
 template <int NG>
 struct GramShape {
-  static constexpr int NW = NG <= 8 ? 4 : 8;
-  static constexpr int KC = NG <= 8 ? 32 : (NG == 16 ? 16 : 8);
+  static constexpr int NW = NG <= 4 ? 4 : 8;
+  static constexpr int KC = NG <= 4 ? 32 : (NG <= 16 ? 16 : 8);
   static constexpr int R = 16 * NG;
   static constexpr int NTILE = NG * (NG + 1) / 2;
-  static constexpr int TPW = NG <= 16 ? (NTILE + NW - 1) / NW : 17;
+  static constexpr int TPW = NG == 8 ? 3 : (NG <= 16 ? (NTILE + NW - 1) / NW : 17);
   static constexpr int PARTS = (NTILE + NW * TPW - 1) / (NW * TPW);
   static constexpr int LOADS = R * KC / (NW * 64);   // panel entries per thread
 };
@@ -112,12 +116,12 @@ __global__ __launch_bounds__(GramShape<NG>::NW * 64) void k_gram_block(
     }
   };
 
-  // this wave's tiles: t = part * NW * TPW + wv + NW u; operand rows in LDS
+  // this wave's tiles: t = wv + NW (part + PARTS u); operand rows in LDS
   int aoff[Sh::TPW], boff[Sh::TPW];
   bool act[Sh::TPW];
 #pragma unroll
   for (int u = 0; u < Sh::TPW; ++u) {
-    const int t = part * Sh::NW * Sh::TPW + wv + Sh::NW * u;
+    const int t = wv + Sh::NW * (part + Sh::PARTS * u);
     act[u] = t < Sh::NTILE;
     int ti = 0, tj = 0;
     if (act[u]) tile_coords(t, ti, tj);
@@ -136,7 +140,7 @@ __global__ __launch_bounds__(GramShape<NG>::NW * 64) void k_gram_block(
     const bool more = k0 + KC < k_end;
     if (more) fetch(k0 + KC);
     const TA* Pb = P[buf];
-#pragma unroll
+#pragma unroll 1
     for (int kk = 0; kk < KC; kk += 4) {
 #pragma unroll
       for (int u = 0; u < Sh::TPW; ++u)
@@ -151,7 +155,7 @@ __global__ __launch_bounds__(GramShape<NG>::NW * 64) void k_gram_block(
 #pragma unroll
   for (int u = 0; u < Sh::TPW; ++u) {
     if (!act[u]) continue;
-    const int t = part * Sh::NW * Sh::TPW + wv + Sh::NW * u;
+    const int t = wv + Sh::NW * (part + Sh::PARTS * u);
 #pragma unroll
     for (int r = 0; r < 4; ++r)
       W[t * 256 + Mfma<TA>::row(lane, r) * 16 + (lane & 15)] = static_cast<double>(acc[u][r]);

@@ -83,7 +83,7 @@ inline int32_t gram_groups(int32_t s) {
   while (16 * g < s) g *= 2;
   return g;
 }
-inline int32_t gram_panel(int32_t groups) { return groups <= 8 ? 32 : (groups == 16 ? 16 : 8); }
+inline int32_t gram_panel(int32_t groups) { return groups <= 4 ? 32 : (groups <= 16 ? 16 : 8); }
 void gram_syrk_plan(int32_t s, int64_t n, int32_t nb, int32_t* nchunks, int64_t* chunk, int32_t* ntiles);
 size_t gram_syrk_work(int32_t s, int64_t n, int32_t nb);
 void launch_gram_syrk(const double* A, int64_t lda, int64_t n, const int32_t* rows, const int32_t* lens, int32_t s,
@@ -186,8 +186,13 @@ struct FusedArgs {
   // 2 x s doubles, and a second set of flags); 0 = every workgroup forms all of y
   double* ypart;
   int32_t ysplit;
-  int32_t pad1;
+  // Kaczmarz++ with blocks of at most kTwoMaxBlock rows only: 1 = two-level
+  // exchange of r (row owners sum the partials and publish r through the
+  // first 2 s doubles of ypart and the second set of flags; every workgroup
+  // gathers r); a y split then uses the next 2 s doubles and a third set
+  int32_t xchg2;
 };
+constexpr int kTwoMaxBlock = 128;
 
 constexpr int kFusedPhases = 8;
 

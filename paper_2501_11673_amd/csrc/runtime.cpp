@@ -509,6 +509,11 @@ constexpr double kStallRatio = 0.9;
 // team: forming all of y reads the whole s x s inverse in every workgroup
 // (512 KB per workgroup per step at s = 256), one more exchange costs less
 constexpr int32_t kYSplitMinBlock = 128;
+// Kaczmarz++ teams of at least this many workgroups exchange r in two levels
+// (row owners, then an all-gather of r): gathering every workgroup's partials
+// in every workgroup reads G s doubles per workgroup per step (64 MB per step
+// for 256 workgroups of 128-row blocks)
+constexpr int32_t kTwoLevelMinGroups = 128;
 // most sketches of the LSQR projection stacked for one batched factoring
 constexpr int64_t kSketchBatch = 256;
 
@@ -754,6 +759,7 @@ class CoreRun {
     a->mrows = m_;
     a->ypart = sys_->part + 2 * static_cast<size_t>(kpp::kFusedMaxGroups) * kpp::kFusedMaxBlock;
     a->ysplit = (kind_ == KPP_KACZMARZ && s_ >= kYSplitMinBlock && groups_ >= 4) ? 1 : 0;
+    a->xchg2 = (kind_ == KPP_KACZMARZ && s_ <= kpp::kTwoMaxBlock && groups_ >= kTwoLevelMinGroups) ? 1 : 0;
     {
       const size_t esz = fp32_ ? sizeof(float) : sizeof(double);
       a->vec_rows = (reinterpret_cast<uintptr_t>(a->A) % 16 == 0 && (static_cast<size_t>(a->lda) * esz) % 16 == 0) ? 1 : 0;

@@ -366,10 +366,11 @@ static void emu_fused(const FusedArgs& a, int32_t cpl, int32_t G, bool fp32) {
   emu_check(a.mom, 8 * a.n, "fused mom");
   emu_check(a.part, 8 * 2 * static_cast<size_t>(G) * s, "fused part");
   emu_check(a.flags, 4 * static_cast<size_t>(G) * 32, "fused flags");
-  if (a.ysplit) {
+  if (a.ysplit || a.xchg2) {
     emu_check(a.flags + kYFlagOffset, 4 * static_cast<size_t>(G) * 32, "fused y flags");
     emu_check(a.ypart, 8 * 2 * static_cast<size_t>(s), "fused ypart");
   }
+  if (a.xchg2 && (s > kTwoMaxBlock || a.W < 0)) { std::fprintf(stderr, "EMU: two-level exchange with s > %d\n", kTwoMaxBlock); std::abort(); }
   emu_check(a.err, 4, "fused err");
   if (G * 64 * cpl < a.n) { std::fprintf(stderr, "EMU: fused team too small\n"); std::abort(); }
   if (a.vec_rows && (reinterpret_cast<uintptr_t>(a.A) % 16 != 0 || (a.lda * (fp32 ? 4 : 8)) % 16 != 0)) {
