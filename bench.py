@@ -1,29 +1,32 @@
-"""Benchmark: time to a true 1e-10 relative residual and block-iterations/s.
+"""Benchmark: time to a true 1e-10 relative residual and block-iterations/s,
+FP64 vs mixed precision, on the Kaczmarz++ and CD++ workloads.
 
-Workload: CD++ (Algorithm 2, no randomized Hadamard preprocessing) on a dense
-SPD system A = Q diag(lambda) Q^T, n = 4096, Q Haar, 32 eigenvalues log-spaced
-in [1e3, 1e5] and 4064 uniform in [1, 10]; b = A x*, x* ~ N(0, I); block size
-128, lambda = 1e-8, online block memoization (Section 5.2), tolerance 1e-10 on
-||A x - b|| / ||b|| confirmed in FP64.  Inputs are synthetic and seeded and are
-resident in HBM before the timed region.
+Headline workload: Kaczmarz++ (Algorithm 5 with the exact memoized Cholesky
+projection) on the under-determined 2048 x 32768 system A = U diag(sigma) V^T
+(U, V Haar; sigma: 20 outliers log-spaced in [1e3, 1e4], 2028 uniform in
+[0.5, 1]; x* = V g in the row space, b = A x*); block size 128, lambda 1e-4,
+online block memoization (Section 5.2), FP64, tolerance 1e-10 on
+||A x - b|| / ||b|| confirmed in FP64.  One "step" is one full solve from
+x0 = 0 with an empty memo cache (every Gram and factorization is paid inside
+the timed region).  value = block steps per second over the timed solves;
+ms_per_step = time to tolerance per solve.  Inputs are synthetic and seeded
+and are resident in HBM before the timed region.
 
-One "step" is one full solve from x0 = 0 with an empty memo cache (every
-factorization is paid inside the timed region).  value = block steps per
-second over the timed solves; ms_per_step = time to tolerance per solve.
-The same solves are then timed with mixed precision (FP32 block products,
-FP64 factors and iterative refinement) and reported under "mixed", and the
-serving workload (continuous batching of 512 solves arriving at 200/s) is
-replayed in real time and reported under "serving" (p50/p99 latency).  Under
-"rht": the randomized Hadamard preprocessing (Definition d:rht) timed at the
-workloads' shapes, and the same CD++ solve with it.  Under "flops_to_tol": the
-paper's FLOP comparison (Section 6.3) re-run on synthetic kernel matrices.
-Under "lsqr": Kaczmarz++ with the exact and with the LSQR projection.  Under
-"ablation": the four Kaczmarz++ variants of the paper's ablation table.  Under
-"multi_rhs": 16 right-hand sides on the n = 4096 system solved together.
+Under "mixed": the same solves with mixed precision (FP32 block products,
+FP64 factors, FP64 iterative refinement), with the speed-up over FP64 and the
+error against the FP64 solution.  Under "kpp_65536x2048": the over-determined
+65536 x 2048 workload (block 256, fixed partition into 256 blocks), FP64 and
+mixed.  Under "cdpp_n4096": CD++ (Algorithm 2) on the n = 4096 SPD workload,
+FP64 and mixed.  Also: serving (continuous batching of 512 CD++ solves at
+200/s, p50/p99 latency), the randomized Hadamard preprocessing, the paper's
+FLOP comparison on synthetic kernel matrices (Full CD++, w/o RHT, w/o Memo),
+the regularization sweep, Kaczmarz++ with the LSQR projection (t_max 2, 4, 8),
+the ablation table and several right-hand sides.
 
-Also printed: the roofline of the dominant kernel (the step kernel, timed with
-HIP events inside the library on the stream it runs on) and the CPU oracle
-timed on the host on one full solve of the same system.
+Each measured solve carries the roofline of its step kernel (algorithmic bytes
+per launch over the launch time from HIP events inside the library, on the
+stream the kernel runs on) and the CPU oracle is timed on the host on the
+headline workload.
 """
 import argparse
 import json
@@ -46,7 +49,7 @@ def parse():
     ap.add_argument("--engine", type=int, default=0, help="0 auto, 1 one launch per phase, 2 fused")
     ap.add_argument("--team-groups", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--seed", type=int, default=202)
+    ap.add_argument("--seed", type=int, default=202, help="seed of the kernel-matrix sections")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -56,24 +59,31 @@ def parse():
     ap.add_argument("--no-flops", action="store_true")
     ap.add_argument("--no-lsqr", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline workload, FP64 and mixed (for profiling the step kernel)")
     ap.add_argument("--rht-only", action="store_true",
                     help="only the randomized Hadamard transforms (for profiling them)")
     return ap.parse_args()
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_fused_cdpp_n4096_s128_fp64.md")
+# rocprofv3 summaries whose FETCH_SIZE / WRITE_SIZE passes give the step
+# kernel's HBM traffic per launch (by workload)
+TRAFFIC_PROFILES = {
+    "kpp_2048x32768": os.path.join(ROOT, "profiles", "k_fused_kpp_2048x32768_s128_fp64.md"),
+    "cdpp_n4096": os.path.join(ROOT, "profiles", "k_fused_cdpp_n4096_s128_fp64.md"),
+}
 
 
-def measured_traffic(kernel_name):
-    """HBM bytes per launch of the step kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE passes, each scaled by what the counter read for a
+def measured_traffic(profile, kernel_name):
+    """HBM bytes per launch of the step kernel from a committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE pass, each scaled by what the counter read for a
     device copy of known size.  None when the kernel's sources have changed
     since the counters were taken, or for another kernel."""
     import hashlib
     import re
     try:
-        text = open(TRAFFIC_PROFILE).read()
-    except OSError:
+        text = open(profile).read()
+    except (OSError, TypeError):
         return None
     m = re.search(r"```json kpp-traffic\n(.*?)```", text, re.S)
     if not m:
@@ -90,6 +100,110 @@ def measured_traffic(kernel_name):
     return round(fetch + write, 1)
 
 
+def step_kernel_name(kind, cpl, fp32):
+    return f"k_fused<{0 if kind == 'general' else 1}, {cpl}, {'float' if fp32 else 'double'}>"
+
+
+def roofline(results, kind, profile=None):
+    """Roofline of the step kernel over a set of solves: algorithmic bytes per
+    launch (the library's count) over the average launch time from HIP events
+    on the library's stream, against the HBM peak."""
+    ktime = sum(r.kernel_seconds for _, r in results)
+    klaunch = sum(r.kernel_launches for _, r in results)
+    bytes_alg = sum(r.bytes_algorithmic for _, r in results)
+    last = results[-1][1]
+    per_launch_bytes = bytes_alg / max(klaunch, 1)
+    per_launch_s = ktime / max(klaunch, 1)
+    achieved = per_launch_bytes / per_launch_s / 1e9 if per_launch_s > 0 else 0.0
+    fp32 = last.cols_per_lane > 0 and getattr(last, "refinements", 0) > 0
+    name = step_kernel_name(kind, last.cols_per_lane, fp32) if last.engine_used == 2 else "launch-per-phase engine"
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": measured_traffic(profile, name) if (profile and last.engine_used == 2 and not fp32) else None,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "kernel": name, "team_groups": last.team_groups, "cols_per_lane": last.cols_per_lane,
+            "launches": int(klaunch), "avg_launch_us": round(per_launch_s * 1e6, 3),
+            "bytes_per_launch": round(per_launch_bytes, 1),
+            "us_per_step_in_kernel": round(1e6 * ktime / max(sum(r.iters for _, r in results), 1), 3)}
+
+
+def timed_solves(kpp, torch, h, p, x, warmup, steps):
+    """warmup untimed solves, then steps timed ones, each from x0 = 0."""
+    for _ in range(warmup):
+        x.zero_()
+        kpp.kpp_solve(h, p, x.data_ptr())
+    torch.cuda.synchronize()
+    results = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x.zero_()
+        results.append(kpp.kpp_solve(h, p, x.data_ptr()))
+    torch.cuda.synchronize()
+    return results, time.perf_counter() - t0
+
+
+def solve_record(torch, results, elapsed, steps, x, xstar, kind, profile=None, x_ref=None):
+    iters = sum(r.iters for _, r in results)
+    last = results[-1][1]
+    rec = {"time_to_tol_ms": 1e3 * elapsed / steps, "block_iters_per_s": iters / elapsed,
+           "iters_per_solve": iters / steps,
+           "converged": all(st == 0 and r.converged for st, r in results),
+           "true_rel_res": last.true_rel_res,
+           "factorizations_per_solve": last.memo_misses, "factors_fp64": last.factors_fp64,
+           "refinements": last.refinements,
+           "factor_ms_per_solve": 1e3 * last.seconds_factor,
+           "kernel_ms_per_solve": 1e3 * sum(r.kernel_seconds for _, r in results) / steps,
+           "engine": last.engine_used,
+           "rel_err_vs_planted": float(torch.linalg.norm(x - xstar) / torch.linalg.norm(xstar)),
+           "roofline": roofline(results, kind, profile)}
+    if x_ref is not None:
+        rec["rel_diff_vs_fp64_solution"] = float(torch.linalg.norm(x - x_ref) / torch.linalg.norm(x_ref))
+    return rec
+
+
+def copy_params(kpp, kind, p):
+    q = kpp.kpp_params_default(kind)
+    for f, _ in kpp.kpp_params._fields_:
+        setattr(q, f, getattr(p, f))
+    return q
+
+
+def fp64_and_mixed(kpp, torch, dev, ctx, name, warmup, steps, profile=None, engine=0):
+    """One workload (synth config `name`): FP64 solves, then mixed precision."""
+    import synth
+
+    sysm = synth.config(name, device="cuda")
+    cfg = synth.CONFIGS[name]
+    A, b = sysm.A, sysm.b
+    m, n = A.shape
+    kind = kpp.KPP_CD_PSD if cfg["kind"] == "psd" else kpp.KPP_KACZMARZ
+    h = kpp.kpp_system_create(ctx, kind, m, n, A.data_ptr(), n, b.data_ptr())
+    p = kpp.kpp_params_default(kind)
+    p.block_size = cfg["s"]
+    p.lambda_ = cfg["lam"]
+    p.tol = 1e-10
+    p.memo = kpp.KPP_MEMO_FIXED if cfg["memo"] == "fixed" and name != "c2" else kpp.KPP_MEMO_ONLINE
+    p.fixed_partition = 1
+    p.max_iters = 200_000
+    p.seed = cfg["schedule_seed"]
+    p.keep_memo = 0
+    p.engine = engine
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    res64, el64 = timed_solves(kpp, torch, h, p, x, warmup, steps)
+    rec = solve_record(torch, res64, el64, steps, x, sysm.xstar, cfg["kind"], profile)
+    x64 = x.clone()
+    pm = copy_params(kpp, kind, p)
+    pm.precision = kpp.KPP_MIXED_FP32
+    pm.engine = 0
+    resm, elm = timed_solves(kpp, torch, h, pm, x, warmup, steps)
+    mixed = solve_record(torch, resm, elm, steps, x, sysm.xstar, cfg["kind"], None, x64)
+    mixed["speedup_vs_fp64"] = rec["time_to_tol_ms"] / mixed["time_to_tol_ms"]
+    rec["mixed"] = mixed
+    rec["workload"] = {"name": name, "m": m, "n": n, "block": cfg["s"], "lambda": cfg["lam"],
+                       "memo": "fixed partition" if p.memo == kpp.KPP_MEMO_FIXED else "online", "tol": 1e-10}
+    return rec, (sysm, h, p, x64)
+
+
 def blas_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -100,22 +214,64 @@ def blas_threads():
         return 1
 
 
-def cpu_baseline(A, b, s, lam, tol, seed):
-    """The oracle as it stands, one full solve of the same system on the host."""
+def cpu_info():
+    """CPU model and core counts of the host the oracle runs on."""
+    model, phys = "unknown", set()
+    try:
+        cur = {}
+        for line in open("/proc/cpuinfo"):
+            if ":" not in line:
+                if cur.get("physical id") is not None and cur.get("core id") is not None:
+                    phys.add((cur["physical id"], cur["core id"]))
+                cur = {}
+                continue
+            k, v = [x.strip() for x in line.split(":", 1)]
+            cur[k] = v
+            if k == "model name":
+                model = v
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        usable = os.cpu_count() or 1
+    return {"cpu_model": model, "physical_cores": len(phys) or None, "usable_cpus": usable}
+
+
+def cpu_baseline(A, b, s, lam, tol, seed, single_thread_steps=96):
+    """The oracle as it stands on the headline workload: one full Kaczmarz++
+    solve to tol with the BLAS threads of the host, and the first
+    single_thread_steps block steps of the same solve on one thread."""
     from oracle import kpp as okpp
     from oracle import schedule as osch
 
-    n = A.shape[0]
+    m, n = A.shape
     T = 100_000
-    schd = osch.make_schedule("online", n, s, T, seed, B0=osch.online_rate("psd", n, n, s))
+    schd = osch.make_schedule("online", m, s, T, seed, B0=osch.online_rate("general", m, n, s))
     t0 = time.perf_counter()
-    res = okpp.solve(A, b, "psd", okpp.Params(s=s, lam=lam, tol=tol, max_iters=T), schd)
+    res = okpp.solve(A, b, "general", okpp.Params(s=s, lam=lam, tol=tol, max_iters=T), schd)
     dt = time.perf_counter() - t0
-    return {"value": res.iters / dt, "unit": "block-iters/s", "cores": blas_threads(),
-            "kind": "oracle",
-            "sample": f"one full CD++ solve of the n=4096 system to {tol:g} "
-                      f"({res.iters} block steps, {dt:.2f} s, converged={res.converged})",
-            "time_to_tol_s": dt}
+    one = None
+    try:
+        from threadpoolctl import threadpool_limits
+
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            r1 = okpp.solve(A, b, "general", okpp.Params(s=s, lam=lam, tol=0.0, max_iters=single_thread_steps), schd)
+            d1 = time.perf_counter() - t1
+        one = {"block_iters_per_s": r1.iters / d1, "steps": r1.iters, "seconds": d1,
+               "sample": f"the first {r1.iters} block steps of the same solve (every new block's Gram "
+                         f"and Cholesky factor included), BLAS on one thread"}
+    except Exception as e:  # pragma: no cover
+        one = {"error": str(e)}
+    rec = {"value": res.iters / dt, "unit": "block-iters/s", "cores": blas_threads(),
+           "kind": "oracle",
+           "sample": f"one full Kaczmarz++ solve of the 2048 x 32768 system to {tol:g} "
+                     f"({res.iters} block steps, {res.factorizations} factorizations, {dt:.2f} s, "
+                     f"converged={res.converged}); cores = BLAS threads used",
+           "time_to_tol_s": dt, "single_thread": one}
+    rec.update(cpu_info())
+    return rec
 
 
 def serving(kpp, torch, dev, num_requests, seed=5):
@@ -285,46 +441,95 @@ PAPER_TAB_FLOPS = {
 }
 
 
-def flops_to_tol(kpp, torch, dev, ctx, seed):
+def flops_to_tol(kpp, torch, dev, ctx, seed, seeds=3):
     """The paper's FLOP comparison (Section 6.3, Table tab:flops) on synthetic
-    data: CD++ with and without RHT on Gaussian and Laplacian kernel matrices
+    data: Full CD++ (with RHT), CD++ w/o RHT and CD++ w/o Memo (with RHT, a new
+    block and factor every step) on Gaussian and Laplacian kernel matrices
     (gamma 0.1 and 0.01) of n = 4096 seeded points plus 1e-3 I, b ~ N(0, I),
-    s = 200, lambda = 1e-8, online memo; FLOPs counted as the paper counts them
-    (kpp_result.flops, RHT included), next to the range of the paper's own
-    numbers over its 20 matrices (other data, no hardware stated)."""
+    s = 200, lambda = 1e-8; FLOPs counted as the paper counts them
+    (kpp_result.flops, RHT included), averaged over `seeds` schedule and sign
+    seeds, next to the range of the paper's own numbers over its 20 matrices
+    (other data, no hardware stated)."""
     import synth
 
     rows = []
     n, s = 4096, 200
+    methods = (("full_cdpp", 1, kpp.KPP_MEMO_ONLINE), ("cdpp_wo_rht", 0, kpp.KPP_MEMO_ONLINE),
+               ("cdpp_wo_memo", 1, kpp.KPP_MEMO_OFF))
     for kern in ("gaussian", "laplacian"):
         for gamma in (0.1, 0.01):
             sysm = synth.kernel_system(kern, n, gamma, seed=seed, device="cuda")
-            for rht in (1, 0):
+            h = kpp.kpp_system_create(ctx, kpp.KPP_CD_PSD, n, n, sysm.A.data_ptr(), n, sysm.b.data_ptr())
+            for method, rht, memo in methods:
                 for tol in (1e-4, 1e-8):
-                    h = kpp.kpp_system_create(ctx, kpp.KPP_CD_PSD, n, n, sysm.A.data_ptr(), n, sysm.b.data_ptr())
-                    p = kpp.kpp_params_default(kpp.KPP_CD_PSD)
-                    p.block_size = s
-                    p.lambda_ = 1e-8
-                    p.tol = tol
-                    p.max_iters = 400_000
-                    p.seed = seed
-                    p.rht = rht
-                    p.rht_seed = seed + 1
-                    x = torch.zeros(n, dtype=torch.float64, device=dev)
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    st, r = kpp.kpp_solve(h, p, x.data_ptr())
-                    torch.cuda.synchronize()
-                    dt = time.perf_counter() - t0
-                    kpp.kpp_system_destroy(h)
-                    rows.append({"matrix": f"{kern} gamma={gamma:g}", "method": "full_cdpp" if rht else "cdpp_wo_rht",
-                                 "tol": tol, "flops": r.flops, "iters": r.iters, "ms": round(1e3 * dt, 3),
-                                 "converged": bool(st == kpp.KPP_OK and r.converged),
-                                 "true_rel_res": r.true_rel_res})
+                    runs = []
+                    for k in range(seeds):
+                        p = kpp.kpp_params_default(kpp.KPP_CD_PSD)
+                        p.block_size = s
+                        p.lambda_ = 1e-8
+                        p.tol = tol
+                        p.max_iters = 400_000
+                        p.memo = memo
+                        p.seed = seed + 7919 * k
+                        p.rht = rht
+                        p.rht_seed = seed + 1 + 7919 * k
+                        x = torch.zeros(n, dtype=torch.float64, device=dev)
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        st, r = kpp.kpp_solve(h, p, x.data_ptr())
+                        torch.cuda.synchronize()
+                        runs.append((r.flops, r.iters, time.perf_counter() - t0,
+                                     bool(st == kpp.KPP_OK and r.converged), r.true_rel_res))
+                    rows.append({"matrix": f"{kern} gamma={gamma:g}", "method": method, "tol": tol,
+                                 "flops": sum(v[0] for v in runs) / seeds,
+                                 "iters": sum(v[1] for v in runs) / seeds,
+                                 "ms": round(1e3 * sum(v[2] for v in runs) / seeds, 3),
+                                 "runs": seeds, "converged": all(v[3] for v in runs),
+                                 "max_true_rel_res": max(v[4] for v in runs)})
+            kpp.kpp_system_destroy(h)
             del sysm
     return {"workload": "CD++ on n=4096 kernel matrices + 1e-3 I (seeded Gaussian points, d=8), s=200, "
-                        "lambda=1e-8, online memo; b ~ N(0, I)",
+                        "lambda=1e-8; b ~ N(0, I); averages over %d seeds" % seeds,
             "runs": rows, "paper_tab_flops_range": PAPER_TAB_FLOPS}
+
+
+def lambda_sweep(kpp, torch, dev, ctx, seed):
+    """Regularization in the projection (the appendix's test of lambda on Full
+    CD++): lambda in {1e-2, 1e-4, 1e-6, 1e-8, 1e-10, 0} on the Gaussian kernel
+    matrix (gamma 0.1) and the n = 4096 outlier SPD workload, s = 200, RHT,
+    online memo, tolerance 1e-8: steps, FLOPs and time to tolerance."""
+    import synth
+
+    out = {}
+    n, s = 4096, 200
+    for name in ("gaussian_0.1", "spd_outliers_n4096"):
+        if name.startswith("gaussian"):
+            sysm = synth.kernel_system("gaussian", n, 0.1, seed=seed, device="cuda")
+        else:
+            sysm = synth.config("c2", device="cuda")
+        h = kpp.kpp_system_create(ctx, kpp.KPP_CD_PSD, n, n, sysm.A.data_ptr(), n, sysm.b.data_ptr())
+        rec = []
+        for lam in (1e-2, 1e-4, 1e-6, 1e-8, 1e-10, 0.0):
+            p = kpp.kpp_params_default(kpp.KPP_CD_PSD)
+            p.block_size = s
+            p.lambda_ = lam
+            p.tol = 1e-8
+            p.max_iters = 400_000
+            p.seed = seed
+            p.rht = 1
+            p.rht_seed = seed + 1
+            x = torch.zeros(n, dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, r = kpp.kpp_solve(h, p, x.data_ptr())
+            torch.cuda.synchronize()
+            rec.append({"lambda": lam, "iters": r.iters, "flops": r.flops,
+                        "ms": round(1e3 * (time.perf_counter() - t0), 3),
+                        "converged": bool(st == kpp.KPP_OK and r.converged), "true_rel_res": r.true_rel_res})
+        kpp.kpp_system_destroy(h)
+        out[name] = rec
+        del sysm
+    return out
 
 
 def ablation(kpp, torch, dev, ctx):
@@ -394,34 +599,38 @@ def multi_rhs(kpp, torch, dev, ctx, h, A, n, p, k=16):
 
 def lsqr_solves(kpp, torch, dev, ctx):
     """Kaczmarz++ to 1e-10 with the exact projection (the memoized Cholesky
-    factor) and with the sketch-preconditioned LSQR projection (t_max = 8,
-    tau = 2s; Section 4.1) on the 1000 x 200 and 65536 x 2048 workloads."""
+    factor) and with the sketch-preconditioned LSQR projection (tau = 2s;
+    Section 4.1): t_max in {2, 4, 8} on the 1000 x 200 workload ("K++(LSQR-t)"
+    of the appendix), t_max = 8 on 65536 x 2048."""
     import synth
 
     out = {}
-    for name, cfg, s, lam, memo in (("k_1000x200_s20", "c1", 20, 1e-3, 1), ("k_65536x2048_s256", "c3", 256, 1e-8, 2)):
+    for name, cfg, s, lam, memo, tmaxs in (("k_1000x200_s20", "c1", 20, 1e-3, 1, (2, 4, 8)),
+                                            ("k_65536x2048_s256", "c3", 256, 1e-8, 2, (8,))):
         sysm = synth.config(cfg, device="cuda")
         A, b = sysm.A, sysm.b
         m, n = A.shape
         h = kpp.kpp_system_create(ctx, kpp.KPP_KACZMARZ, m, n, A.data_ptr(), n, b.data_ptr())
         rec = {}
-        for proj in (kpp.KPP_PROJ_EXACT, kpp.KPP_PROJ_LSQR):
+        for proj, tmax in [(kpp.KPP_PROJ_EXACT, 0)] + [(kpp.KPP_PROJ_LSQR, t) for t in tmaxs]:
             p = kpp.kpp_params_default(kpp.KPP_KACZMARZ)
             p.block_size = s
             p.lambda_ = lam
             p.tol = 1e-10
             p.memo = memo
             p.fixed_partition = 1
-            p.max_iters = 200_000
+            p.max_iters = 50_000 if proj == kpp.KPP_PROJ_LSQR and tmax < 8 else 200_000
             p.seed = sysm.params["schedule_seed"]
             p.projection = proj
+            if proj == kpp.KPP_PROJ_LSQR:
+                p.lsqr_iters = tmax
             x = torch.zeros(n, dtype=torch.float64, device=dev)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             st, r = kpp.kpp_solve(h, p, x.data_ptr())
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
-            rec["exact" if proj == 0 else "lsqr_t8"] = {
+            rec["exact" if proj == 0 else f"lsqr_t{tmax}"] = {
                 "time_to_tol_ms": round(1e3 * dt, 3), "iters": r.iters, "us_per_step": round(1e6 * dt / max(r.iters, 1), 2),
                 "flops": r.flops, "converged": bool(st == kpp.KPP_OK and r.converged), "true_rel_res": r.true_rel_res,
                 "engine": r.engine_used,
@@ -438,7 +647,6 @@ def main():
         print("bench.py: this build runs on one GPU; --gpus must be 1 "
               "(the multi-GPU design is described in DESIGN.md, not run)", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     import paper_2501_11673_amd as kpp
@@ -446,27 +654,11 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    s, lam, tol = 128, 1e-8, 1e-10
-    sysm = synth.config("c2", device="cuda")
-    A, b = sysm.A, sysm.b
-    n = A.shape[0]
-    torch.cuda.synchronize()
     stream = torch.cuda.current_stream(dev)
     ctx = kpp.kpp_context_create(0, stream.cuda_stream)
-    h = kpp.kpp_system_create(ctx, kpp.KPP_CD_PSD, n, n, A.data_ptr(), n, b.data_ptr())
-    p = kpp.kpp_params_default(kpp.KPP_CD_PSD)
-    p.block_size = s
-    p.lambda_ = lam
-    p.tol = tol
-    p.memo = kpp.KPP_MEMO_ONLINE
-    p.max_iters = 200_000
-    p.seed = args.seed
-    p.keep_memo = 0
-    p.engine = args.engine
-    p.team_groups = args.team_groups
-    x = torch.zeros(n, dtype=torch.float64, device=dev)
     if args.rht_only:
-        rec = {"rht": rht_transforms(kpp, torch, dev, ctx, A, b, reps=args.steps)}
+        sysm = synth.config("c2", device="cuda")
+        rec = {"rht": rht_transforms(kpp, torch, dev, ctx, sysm.A, sysm.b, reps=args.steps)}
         if args.calibrate_copy > 0:
             src = torch.empty(args.calibrate_copy << 20, dtype=torch.uint8, device=dev).fill_(1)
             dst = torch.empty_like(src)
@@ -475,71 +667,33 @@ def main():
             torch.cuda.synchronize()
             rec["copy_calibration_bytes"] = args.calibrate_copy << 20
         print(json.dumps(rec), flush=True)
-        kpp.kpp_system_destroy(h)
         kpp.kpp_context_destroy(ctx)
         return
 
-    def one():
-        x.zero_()
-        st, res = kpp.kpp_solve(h, p, x.data_ptr())
-        return st, res
-
-    for _ in range(args.warmup):
-        one()
-    torch.cuda.synchronize()
-    results = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        results.append(one())
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-
-    iters = sum(r.iters for _, r in results)
-    conv = all(st == kpp.KPP_OK and r.converged for st, r in results)
-    ktime = sum(r.kernel_seconds for _, r in results)
-    klaunch = sum(r.kernel_launches for _, r in results)
-    bytes_alg = sum(r.bytes_algorithmic for _, r in results)
-    xs = x.cpu().numpy()
-    err_vs_xstar = float(np.linalg.norm(xs - sysm.xstar.cpu().numpy()) / np.linalg.norm(sysm.xstar.cpu().numpy()))
-    last = results[-1][1]
-    engine_name = {1: "one launch per phase (block gemv kernel)", 2: "fused persistent step kernel"}[last.engine_used]
-    per_launch_bytes = bytes_alg / max(klaunch, 1)
-    per_launch_s = ktime / max(klaunch, 1)
-    achieved = per_launch_bytes / per_launch_s / 1e9 if per_launch_s > 0 else 0.0
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": measured_traffic("k_fused<1, 2, double>") if last.engine_used == 2 else None,
-                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "kernel": engine_name, "launches": int(klaunch),
-                "avg_launch_us": round(per_launch_s * 1e6, 3),
-                "bytes_per_launch": round(per_launch_bytes, 1)}
-
+    # headline: Kaczmarz++ on 2048 x 32768, FP64, then mixed precision
+    head, (c4, h4, p4, x4) = fp64_and_mixed(kpp, torch, dev, ctx, "c4", args.warmup, args.steps,
+                                            TRAFFIC_PROFILES["kpp_2048x32768"], engine=args.engine)
     line = {
-        "metric": "block-iters/s (CD++ n=4096 SPD, time to true 1e-10 relative residual)",
-        "value": iters / elapsed,
+        "metric": "block-iters/s (Kaczmarz++ 2048x32768, time to true 1e-10 relative residual; FP64 vs mixed)",
+        "value": head["block_iters_per_s"],
         "unit": "block-iters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": head["time_to_tol_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (seeded outlier-spectrum SPD system, generated on device)",
-        "config": {"workload": "cdpp_spd_n4096_s128_online_memo_fp64", "n": n, "block": s,
-                   "lambda": lam, "tol": tol, "memo": "online", "precision": "fp64",
-                   "engine": last.engine_used},
-        "time_to_tol_ms": 1e3 * elapsed / args.steps,
-        "iters_per_solve": iters / args.steps,
-        "converged": conv,
-        "true_rel_res": last.true_rel_res,
-        "rel_err_vs_planted": err_vs_xstar,
-        "factorizations_per_solve": last.memo_misses,
-        "factor_ms_per_solve": 1e3 * last.seconds_factor,
-        "kernel_ms_per_solve": 1e3 * ktime / args.steps,
-        "roofline": roofline,
+        "data": "synthetic (seeded outlier-spectrum 2048 x 32768 system, generated on device)",
+        "config": {"workload": "kpp_2048x32768_s128_online_fp64", "m": 2048, "n": 32768, "block": 128,
+                   "lambda": 1e-4, "tol": 1e-10, "memo": "online", "precision": "fp64", "engine": head["engine"]},
     }
+    for k in ("time_to_tol_ms", "iters_per_solve", "converged", "true_rel_res", "rel_err_vs_planted",
+              "factorizations_per_solve", "factor_ms_per_solve", "kernel_ms_per_solve"):
+        line[k] = head[k]
+    line["roofline"] = head["roofline"]
+    line["mixed"] = head["mixed"]
     if args.calibrate_copy > 0:
         src = torch.empty(args.calibrate_copy << 20, dtype=torch.uint8, device=dev).fill_(1)
         dst = torch.empty_like(src)
@@ -549,64 +703,46 @@ def main():
         torch.cuda.synchronize()
         line["copy_calibration_bytes"] = args.calibrate_copy << 20
         del src, dst
-    # the same workload with mixed precision (FP32 block products, FP64 refinement)
-    x_fp64 = x.clone()
-    pm = kpp.kpp_params_default(kpp.KPP_CD_PSD)
-    for f, _ in kpp.kpp_params._fields_:
-        setattr(pm, f, getattr(p, f))
-    pm.precision = kpp.KPP_MIXED_FP32
-    pm.engine = 0
+    A4h = b4h = None
+    if not args.no_cpu_baseline:
+        A4h, b4h = c4.A.cpu().numpy(), c4.b.cpu().numpy()
+    kpp.kpp_system_destroy(h4)
+    del c4, x4
+    torch.cuda.empty_cache()
+    if args.headline_only:
+        line["cpu_baseline"] = None
+        print(json.dumps(line), flush=True)
+        kpp.kpp_context_destroy(ctx)
+        return
 
-    def one_mixed():
-        x.zero_()
-        return kpp.kpp_solve(h, pm, x.data_ptr())
-
-    for _ in range(args.warmup if not args.no_mixed else 0):
-        one_mixed()
-    torch.cuda.synchronize()
-    mres = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps if not args.no_mixed else 0):
-        mres.append(one_mixed())
-    torch.cuda.synchronize()
-    melapsed = time.perf_counter() - t0
-    miters = sum(r.iters for _, r in mres)
-    mlast = mres[-1][1] if mres else None
-    line["mixed"] = None if not mres else {
-        "time_to_tol_ms": 1e3 * melapsed / args.steps,
-        "block_iters_per_s": miters / melapsed,
-        "iters_per_solve": miters / args.steps,
-        "refinements": mlast.refinements,
-        "converged": all(st == kpp.KPP_OK and r.converged for st, r in mres),
-        "true_rel_res": mlast.true_rel_res,
-        "rel_diff_vs_fp64_solution": float(torch.linalg.norm(x - x_fp64) / torch.linalg.norm(x_fp64)),
-        "rel_err_vs_planted": float(torch.linalg.norm(x - sysm.xstar) / torch.linalg.norm(sysm.xstar)),
-        "factorizations_per_solve": mlast.memo_misses,
-        "factors_redone_fp64": mlast.factors_fp64,
-        "kernel_ms_per_solve": 1e3 * sum(r.kernel_seconds for _, r in mres) / args.steps,
-        "speedup_vs_fp64": (1e3 * elapsed / args.steps) / (1e3 * melapsed / args.steps),
-    }
+    rec3, (c3, h3, _, _) = fp64_and_mixed(kpp, torch, dev, ctx, "c3", args.warmup, args.steps)
+    kpp.kpp_system_destroy(h3)
+    del c3
+    torch.cuda.empty_cache()
+    line["kpp_65536x2048"] = rec3
+    rec2, (c2, h2, p2, x2) = fp64_and_mixed(kpp, torch, dev, ctx, "c2", args.warmup, args.steps,
+                                            TRAFFIC_PROFILES["cdpp_n4096"])
+    line["cdpp_n4096"] = rec2
     if not args.no_multi:
-        line["multi_rhs"] = multi_rhs(kpp, torch, dev, ctx, h, A, n, p)
+        line["multi_rhs"] = multi_rhs(kpp, torch, dev, ctx, h2, c2.A, 4096, p2)
     if not args.no_rht:
-        rh = rht_transforms(kpp, torch, dev, ctx, A, b)
-        rh["cdpp_n4096_with_rht"] = rht_solves(kpp, torch, dev, h, p, x, args.steps)
+        rh = rht_transforms(kpp, torch, dev, ctx, c2.A, c2.b)
+        rh["cdpp_n4096_with_rht"] = rht_solves(kpp, torch, dev, h2, p2, x2, args.steps)
         line["rht"] = rh
+    kpp.kpp_system_destroy(h2)
+    del c2
     if not args.no_flops:
         line["flops_to_tol"] = flops_to_tol(kpp, torch, dev, ctx, args.seed)
+        line["lambda_sweep"] = lambda_sweep(kpp, torch, dev, ctx, args.seed)
     if not args.no_lsqr:
         line["lsqr"] = lsqr_solves(kpp, torch, dev, ctx)
     if not args.no_flops:
         line["ablation"] = ablation(kpp, torch, dev, ctx)
-    kpp.kpp_system_destroy(h)
     kpp.kpp_context_destroy(ctx)
     if not args.no_serving:
         line["serving"] = serving(kpp, torch, dev, args.serve_requests)
     if not args.no_cpu_baseline:
-        Ah = A.cpu().numpy()
-        bh = b.cpu().numpy()
-        del A, b
-        line["cpu_baseline"] = cpu_baseline(Ah, bh, s, lam, tol, args.seed)
+        line["cpu_baseline"] = cpu_baseline(A4h, b4h, 128, 1e-4, 1e-10, synth.CONFIGS["c4"]["schedule_seed"])
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)

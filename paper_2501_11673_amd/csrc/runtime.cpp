@@ -151,6 +151,11 @@ struct kpp_system {
   double* zx = nullptr;    // mixed precision, wide Kaczmarz++: duals of the inner iterate and momentum
   double* zm = nullptr;
   int32_t* fp64_count = nullptr;   // blocks refactored in FP64 (mixed precision)
+  // mixed precision: every FP32 Gram tried on this system failed the
+  // conditioning test, so new blocks go straight to an FP64 Gram and factor
+  bool fp32_gram_futile = false;
+  int64_t fp64_direct = 0;         // blocks factored that way in the current solve
+  int64_t fp32_tried = 0;          // blocks with an FP32 Gram attempt in the current solve
   // randomized Hadamard preprocessing (params.rht): the transformed padded
   // system (its own memo and resume state), the signs and the seed they came
   // from; formed on the first such solve
@@ -839,6 +844,8 @@ class CoreRun {
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(sys_->h_ds, sys_->ds, sizeof(kpp::DevState), hipMemcpyDeviceToHost, st_));
     HIP_TRY(hipMemcpyAsync(sys_->h_err, sys_->err, sizeof(int32_t), hipMemcpyDeviceToHost, st_));
+    if (fp32_ && sys_->fp64_count)
+      HIP_TRY(hipMemcpyAsync(sys_->h_err + 1, sys_->fp64_count, sizeof(int32_t), hipMemcpyDeviceToHost, st_));
     return KPP_OK;
   }
   kpp_status plan_ahead() {
@@ -878,6 +885,10 @@ class CoreRun {
       return fail(KPP_ERR_NOT_SPD, "a regularized block Gram has no Cholesky factor (lambda=%g)", prm_.lambda);
     }
     Window& w = win_[cur_];
+    // every FP32 Gram tried so far (at least 32 blocks) was redone in FP64:
+    // later blocks of this system skip the FP32 attempt
+    if (fp32_ && !sys_->fp32_gram_futile && w.fp32_tried >= 32 && sys_->h_err[1] >= w.fp32_tried)
+      sys_->fp32_gram_futile = true;
     const int64_t ran = hs_.t - t_;
     if (ran < 0 || ran > w.W - w.done) {
       finished_ = true;
@@ -972,6 +983,8 @@ class CoreRun {
   struct Window {
     int64_t t0 = 0, W = 0, done = 0;
     int32_t nb = 0, idx = 0;
+    int64_t fp32_tried = 0;   // new blocks with an FP32 Gram attempt up to this window
+    bool try32 = false;       // this window's new blocks try an FP32 Gram first
     bool on_side = false, waited = false;
     size_t o_len = 0, o_slot = 0, o_step = 0;
     std::vector<int32_t> step_block, step_slot;
@@ -1030,6 +1043,9 @@ class CoreRun {
       t_prof_slots += wall_now() - ts;
     }
     w.nb = static_cast<int32_t>(pending.size());
+    w.try32 = fp32_ && !sys->fp32_gram_futile;
+    if (w.try32) sys->fp32_tried += w.nb;
+    w.fp32_tried = sys->fp32_tried;
     w.o_len = static_cast<size_t>(w.nb) * s;
     w.o_slot = w.o_len + w.nb;
     w.o_step = w.o_slot + w.nb;
@@ -1150,7 +1166,12 @@ class CoreRun {
           kpp::launch_factor_inverse(sys->L, sys->slot_stride, s, d_slens, w.nb, d_sslot, fs, chk, skip);
         }
       };
-      if (fp32_) {
+      if (fp32_ && !w.try32) {
+        kpp::launch_gram(kind_, sys->A, sys->lda, n_, d_srows, d_slens, s, w.nb, prm_.lambda, sys->L,
+                         sys->slot_stride, d_sslot, gws, fs);
+        factor(kpp::FactorCheck(), nullptr);
+        sys->fp64_direct += w.nb;
+      } else if (fp32_) {
         // FP32 Grams; blocks whose factor breaks down or whose kappa(G) exceeds
         // 1e6 are formed again from the FP64 A and factored in FP64
         int32_t* flag = sys->d_stage[idx] + w.o_step + w.W;
@@ -1396,6 +1417,8 @@ kpp_status solve_mixed(kpp_system* sys, const kpp_params* p, double* x, kpp_resu
   if (wide && !sys->zm) KPP_TRY(dev_alloc(&sys->zm, m));
   if (!sys->fp64_count) KPP_TRY(dev_alloc(&sys->fp64_count, 1));
   HIP_TRY(hipMemsetAsync(sys->fp64_count, 0, sizeof(int32_t), st));
+  sys->fp64_direct = 0;
+  sys->fp32_tried = 0;
   int64_t iters = 0, hits = 0, misses = 0, launches = 0, ckpts = 0;
   double t_factor = 0.0, t_kernel = 0.0, rho = p->rho0, true_rel = NAN, est = NAN;
   bool converged = false;
@@ -1457,7 +1480,7 @@ kpp_status solve_mixed(kpp_system* sys, const kpp_params* p, double* x, kpp_resu
   if (res) {
     int32_t nfp64 = 0;
     HIP_TRY(hipMemcpy(&nfp64, sys->fp64_count, sizeof(int32_t), hipMemcpyDeviceToHost));
-    res->factors_fp64 = nfp64;
+    res->factors_fp64 = nfp64 + sys->fp64_direct;
   }
   return converged ? KPP_OK : KPP_NOT_CONVERGED;
 }
@@ -1660,7 +1683,7 @@ void serve_complete(kpp_server* srv, ServeReq* r) {
     if (r->mixed && r->sys->fp64_count) {
       int32_t nfp64 = 0;
       if (hipMemcpy(&nfp64, r->sys->fp64_count, sizeof(int32_t), hipMemcpyDeviceToHost) == hipSuccess)
-        res->factors_fp64 = nfp64;
+        res->factors_fp64 = nfp64 + r->sys->fp64_direct;
     }
   }
   res->seconds_total = now_seconds() - r->t_submit;
@@ -1829,6 +1852,8 @@ bool serve_start(kpp_server* srv, ServeReq* r) {
     }
     if (!sys->fp64_count && dev_alloc(&sys->fp64_count, 1) < 0) return failed(KPP_ERR_OOM);
     if (hipMemsetAsync(sys->fp64_count, 0, sizeof(int32_t), st) != hipSuccess) return failed(KPP_ERR_HIP);
+    sys->fp64_direct = 0;
+    sys->fp32_tried = 0;
     r->rho = r->p.rho0;
   }
   return serve_next_run(srv, r);
@@ -2630,7 +2655,7 @@ KPP_API kpp_status kpp_system_create(kpp_context* ctx, int32_t kind, int64_t m, 
     return stt;
   }
   if (hipHostMalloc(reinterpret_cast<void**>(&sys->h_ds), sizeof(kpp::DevState), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&sys->h_err), sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc(reinterpret_cast<void**>(&sys->h_err), 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
     destroy_buffers(sys.get());
     return fail(KPP_ERR_OOM, "pinned host allocation failed");
   }

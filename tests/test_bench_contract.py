@@ -29,17 +29,15 @@ def test_traffic_scaled_by_copy_calibration(tmp_path):
     digest = hashlib.sha256(open(os.path.join(ROOT, rel), "rb").read()).hexdigest()
     prof = tmp_path / "p.md"
     write_profile(prof, {rel: digest})
-    bench.TRAFFIC_PROFILE = str(prof)
     # FETCH read 512 KiB for a 1 MiB copy (x2), WRITE read 1024 KiB (x1)
-    assert bench.measured_traffic("k_fused<1, 2, double>") == 1000.0 * 2048 + 10.0 * 1024
-    assert bench.measured_traffic("k_fused<1, 1, double>") is None
+    assert bench.measured_traffic(str(prof), "k_fused<1, 2, double>") == 1000.0 * 2048 + 10.0 * 1024
+    assert bench.measured_traffic(str(prof), "k_fused<1, 1, double>") is None
 
 
 def test_traffic_dropped_when_kernel_changed(tmp_path):
     bench = load_bench()
     prof = tmp_path / "p.md"
     write_profile(prof, {"paper_2501_11673_amd/csrc/fused.hip": "0" * 64})
-    bench.TRAFFIC_PROFILE = str(prof)
-    assert bench.measured_traffic("k_fused<1, 2, double>") is None
-    bench.TRAFFIC_PROFILE = str(tmp_path / "missing.md")
-    assert bench.measured_traffic("k_fused<1, 2, double>") is None
+    assert bench.measured_traffic(str(prof), "k_fused<1, 2, double>") is None
+    assert bench.measured_traffic(str(tmp_path / "missing.md"), "k_fused<1, 2, double>") is None
+    assert bench.measured_traffic(None, "k_fused<1, 2, double>") is None
