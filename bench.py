@@ -59,6 +59,10 @@ def parse():
     ap.add_argument("--no-flops", action="store_true")
     ap.add_argument("--no-lsqr", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
+    ap.add_argument("--host-generated", action="store_true",
+                    help="draw the headline system with numpy on the host (for counter-profiler runs)")
+    ap.add_argument("--only", choices=["c2", "c3", "c4"], default=None,
+                    help="only one workload, FP64 and mixed: c2 (CD++ n=4096), c3 (65536 x 2048), c4 (2048 x 32768)")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline workload, FP64 and mixed (for profiling the step kernel)")
     ap.add_argument("--rht-only", action="store_true",
@@ -168,11 +172,19 @@ def copy_params(kpp, kind, p):
     return q
 
 
-def fp64_and_mixed(kpp, torch, dev, ctx, name, warmup, steps, profile=None, engine=0):
-    """One workload (synth config `name`): FP64 solves, then mixed precision."""
+def fp64_and_mixed(kpp, torch, dev, ctx, name, warmup, steps, profile=None, engine=0, host_data=False):
+    """One workload (synth config `name`): FP64 solves, then mixed precision.
+    host_data: draw the system with numpy on the host and copy it to the device
+    (same recipe, another random stream; for runs under a counter profiler)."""
     import synth
 
-    sysm = synth.config(name, device="cuda")
+    if host_data:
+        sysm = synth.config(name)
+        sysm.A = torch.from_numpy(sysm.A).to(dev)
+        sysm.b = torch.from_numpy(sysm.b).to(dev)
+        sysm.xstar = torch.from_numpy(sysm.xstar).to(dev)
+    else:
+        sysm = synth.config(name, device="cuda")
     cfg = synth.CONFIGS[name]
     A, b = sysm.A, sysm.b
     m, n = A.shape
@@ -670,9 +682,20 @@ def main():
         kpp.kpp_context_destroy(ctx)
         return
 
+    if args.only:
+        # one workload's FP64 and mixed solves (the command the step kernel's
+        # profile summaries are taken with)
+        rec, (sysm, h, _, _) = fp64_and_mixed(kpp, torch, dev, ctx, args.only, args.warmup, args.steps,
+                                              host_data=args.host_generated)
+        kpp.kpp_system_destroy(h)
+        kpp.kpp_context_destroy(ctx)
+        print(json.dumps({"only": args.only, **rec}), flush=True)
+        return
+
     # headline: Kaczmarz++ on 2048 x 32768, FP64, then mixed precision
     head, (c4, h4, p4, x4) = fp64_and_mixed(kpp, torch, dev, ctx, "c4", args.warmup, args.steps,
-                                            TRAFFIC_PROFILES["kpp_2048x32768"], engine=args.engine)
+                                            TRAFFIC_PROFILES["kpp_2048x32768"], engine=args.engine,
+                                            host_data=args.host_generated)
     line = {
         "metric": "block-iters/s (Kaczmarz++ 2048x32768, time to true 1e-10 relative residual; FP64 vs mixed)",
         "value": head["block_iters_per_s"],

@@ -1255,14 +1255,37 @@ __global__ __launch_bounds__(kT) void k_factor_small(double* __restrict__ slots,
   }
 }
 
-// d_j = sum_i A_ij z_i: a workgroup owns 256 consecutive columns and walks
-// the rows in order (coalesced row segments, deterministic sums).
-__global__ __launch_bounds__(kT) void k_gemv_t(const double* __restrict__ A, int64_t lda, int64_t m, int64_t n,
-                                               const double* __restrict__ z, double* __restrict__ d) {
+// d_j = sum_i A_ij z_i in two passes: workgroup (c, r) owns 256 consecutive
+// columns and the r-th of `splits` consecutive row ranges, walks its rows in
+// order with eight loads in flight (coalesced row segments) and writes a
+// partial sum; the second pass adds the partials in split order
+// (deterministic).  One split writes d directly.
+__global__ __launch_bounds__(kT) void k_gemv_t_part(const double* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                                    const double* __restrict__ z, int32_t splits,
+                                                    double* __restrict__ out) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+  if (j >= n) return;
+  const int64_t per = (m + splits - 1) / splits;
+  const int64_t r0 = static_cast<int64_t>(blockIdx.y) * per, r1 = min(m, r0 + per);
+  double acc = 0.0;
+  int64_t i = r0;
+  for (; i + 8 <= r1; i += 8) {
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = A[(i + u) * lda + j];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = fma(a[u], z[i + u], acc);
+  }
+  for (; i < r1; ++i) acc = fma(A[i * lda + j], z[i], acc);
+  out[static_cast<int64_t>(blockIdx.y) * n + j] = acc;
+}
+
+__global__ __launch_bounds__(kT) void k_gemv_t_sum(const double* __restrict__ part, int64_t n, int32_t splits,
+                                                   double* __restrict__ d) {
   const int64_t j = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
   if (j >= n) return;
   double acc = 0.0;
-  for (int64_t i = 0; i < m; ++i) acc = fma(A[i * lda + j], z[i], acc);
+  for (int32_t r = 0; r < splits; ++r) acc += part[static_cast<int64_t>(r) * n + j];
   d[j] = acc;
 }
 
@@ -1534,9 +1557,25 @@ void launch_residual_vec(const double* A, int64_t lda, int64_t m, int64_t n, con
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(kT), 0, st, rowsq, m, out);
 }
 
-void launch_gemv_t(const double* A, int64_t lda, int64_t m, int64_t n, const double* z, double* d, hipStream_t st) {
+int32_t gemv_t_splits(int64_t m, int64_t n) {
+  const int64_t cols = (n + kT - 1) / kT;
+  int64_t s = std::max<int64_t>(1, (2048 + cols - 1) / cols);   // about 2048 workgroups
+  s = std::min<int64_t>(s, std::max<int64_t>(1, m / 64));          // at least 64 rows each
+  return static_cast<int32_t>(std::min<int64_t>(s, 64));
+}
+
+void launch_gemv_t(const double* A, int64_t lda, int64_t m, int64_t n, const double* z, double* d, double* ws,
+                   hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_gemv_t, dim3(static_cast<unsigned>((n + kT - 1) / kT)), dim3(kT), 0, st, A, lda, m, n, z, d);
+  const int32_t splits = gemv_t_splits(m, n);
+  const unsigned cols = static_cast<unsigned>((n + kT - 1) / kT);
+  if (splits == 1) {
+    hipLaunchKernelGGL(k_gemv_t_part, dim3(cols, 1), dim3(kT), 0, st, A, lda, m, n, z, 1, d);
+    return;
+  }
+  hipLaunchKernelGGL(k_gemv_t_part, dim3(cols, static_cast<unsigned>(splits)), dim3(kT), 0, st, A, lda, m, n, z,
+                     splits, ws);
+  hipLaunchKernelGGL(k_gemv_t_sum, dim3(cols), dim3(kT), 0, st, ws, n, splits, d);
 }
 
 void launch_axpy1(double* x, const double* d, int64_t n, hipStream_t st) {

@@ -144,8 +144,11 @@ void launch_residual_vec(const double* A, int64_t lda, int64_t m, int64_t n, con
 // x += d  (FP64)
 void launch_axpy1(double* x, const double* d, int64_t n, hipStream_t st);
 
-// d = A^T z (m x n row-major A, FP64, fixed summation order over the rows)
-void launch_gemv_t(const double* A, int64_t lda, int64_t m, int64_t n, const double* z, double* d, hipStream_t st);
+// d = A^T z (m x n row-major A, FP64, fixed summation order over the rows);
+// ws: gemv_t_splits(m, n) * n doubles of partial sums (unused for one split)
+int32_t gemv_t_splits(int64_t m, int64_t n);
+void launch_gemv_t(const double* A, int64_t lda, int64_t m, int64_t n, const double* z, double* d, double* ws,
+                   hipStream_t st);
 
 // Arguments of the fused persistent engine (fused.hip): W block steps of one
 // system per launch, `groups` workgroups each owning 64 * cpl columns.

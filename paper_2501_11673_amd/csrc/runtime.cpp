@@ -148,6 +148,7 @@ struct kpp_system {
   size_t gram_ws_cap[2] = {0, 0};
   double* rvec = nullptr;
   double* dvec = nullptr;
+  double* gemvt_ws = nullptr;      // partial sums of d = A^T z (wide mixed precision)
   double* zx = nullptr;    // mixed precision, wide Kaczmarz++: duals of the inner iterate and momentum
   double* zm = nullptr;
   int32_t* fp64_count = nullptr;   // blocks refactored in FP64 (mixed precision)
@@ -253,6 +254,7 @@ void destroy_buffers(kpp_system* s) {
   }
   dev_free(s->rvec);
   dev_free(s->dvec);
+  dev_free(s->gemvt_ws);
   dev_free(s->zx);
   dev_free(s->zm);
   dev_free(s->fp64_count);
@@ -1413,6 +1415,7 @@ kpp_status solve_mixed(kpp_system* sys, const kpp_params* p, double* x, kpp_resu
   if (!sys->rvec) KPP_TRY(dev_alloc(&sys->rvec, m));
   if (!sys->dvec) KPP_TRY(dev_alloc(&sys->dvec, n));
   const bool wide = sys->kind == KPP_KACZMARZ && m < n;
+  if (wide && !sys->gemvt_ws) KPP_TRY(dev_alloc(&sys->gemvt_ws, static_cast<size_t>(kpp::gemv_t_splits(m, n)) * n));
   if (wide && !sys->zx) KPP_TRY(dev_alloc(&sys->zx, m));
   if (wide && !sys->zm) KPP_TRY(dev_alloc(&sys->zm, m));
   if (!sys->fp64_count) KPP_TRY(dev_alloc(&sys->fp64_count, 1));
@@ -1460,7 +1463,7 @@ kpp_status solve_mixed(kpp_system* sys, const kpp_params* p, double* x, kpp_resu
     KPP_TRY(solve_core(sys, p, src, o, sys->dvec, &cs));
     // a wide system's correction is A^T zx with the FP64 A: in the row space
     // of A, so the refined x converges to the minimum-norm solution
-    if (cs.dual) kpp::launch_gemv_t(sys->A, sys->lda, m, n, sys->zx, sys->dvec, st);
+    if (cs.dual) kpp::launch_gemv_t(sys->A, sys->lda, m, n, sys->zx, sys->dvec, sys->gemvt_ws, st);
     kpp::launch_axpy1(x, sys->dvec, n, st);
     HIP_TRY(hipGetLastError());
     ++rounds;
@@ -1548,7 +1551,11 @@ size_t serve_footprint(const kpp_system* sys, const kpp_params* p, int32_t perio
   else
     blocks = static_cast<int64_t>(4.0 * kpp::online_rate(sys->kind, sys->m, sys->n, s)) + 16;
   size_t bytes = static_cast<size_t>(blocks) * (static_cast<size_t>(kpp::slot_doubles(s)) * 8 + 4 * (s + 1));
-  if (p->precision == KPP_MIXED_FP32) bytes += static_cast<size_t>(sys->m) * sys->n * 4 + 8 * (sys->m + sys->n);
+  if (p->precision == KPP_MIXED_FP32) {
+    bytes += static_cast<size_t>(sys->m) * sys->n * 4 + 8 * (sys->m + sys->n);
+    if (sys->kind == KPP_KACZMARZ && sys->m < sys->n)   // duals and the partial sums of A^T z
+      bytes += 8 * (2 * static_cast<size_t>(sys->m) + static_cast<size_t>(kpp::gemv_t_splits(sys->m, sys->n)) * sys->n);
+  }
   bytes += 8 * static_cast<size_t>(sys->n) * 2 + 2 * 4 * static_cast<size_t>(s) * (4 * periods * zeta + 2 * s);
   return bytes;
 }
@@ -1816,7 +1823,7 @@ bool serve_run_ended(kpp_server* srv, ServeReq* r) {
     return false;
   }
   if (cs.dual)
-    kpp::launch_gemv_t(r->sys->A, r->sys->lda, r->sys->m, r->sys->n, r->sys->zx, r->sys->dvec,
+    kpp::launch_gemv_t(r->sys->A, r->sys->lda, r->sys->m, r->sys->n, r->sys->zx, r->sys->dvec, r->sys->gemvt_ws,
                        r->sys->ctx->stream);
   kpp::launch_axpy1(r->x, r->sys->dvec, r->sys->n, r->sys->ctx->stream);
   if (hipGetLastError() != hipSuccess) {
@@ -1849,6 +1856,9 @@ bool serve_start(kpp_server* srv, ServeReq* r) {
     if (sys->kind == KPP_KACZMARZ && sys->m < sys->n) {
       if (!sys->zx && dev_alloc(&sys->zx, sys->m) < 0) return failed(KPP_ERR_OOM);
       if (!sys->zm && dev_alloc(&sys->zm, sys->m) < 0) return failed(KPP_ERR_OOM);
+      if (!sys->gemvt_ws &&
+          dev_alloc(&sys->gemvt_ws, static_cast<size_t>(kpp::gemv_t_splits(sys->m, sys->n)) * sys->n) < 0)
+        return failed(KPP_ERR_OOM);
     }
     if (!sys->fp64_count && dev_alloc(&sys->fp64_count, 1) < 0) return failed(KPP_ERR_OOM);
     if (hipMemsetAsync(sys->fp64_count, 0, sizeof(int32_t), st) != hipSuccess) return failed(KPP_ERR_HIP);

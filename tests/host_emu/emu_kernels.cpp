@@ -3,6 +3,7 @@
 // of the stand-in runtime, and the solver state evolves with a modelled block
 // residual so that checkpoints, stops and refinement rounds occur.  Nothing
 // here computes the method; parity of the numbers is tested on the GPU.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -330,7 +331,15 @@ void launch_residual_vec(const double* A, int64_t lda, int64_t m, int64_t n, con
   *out = bb * std::pow(1e-4, 2.0 * k);
   if (*out < bb * 1e-30) g_rounds[x] = 0;
 }
-void launch_gemv_t(const double* A, int64_t lda, int64_t m, int64_t n, const double* z, double* d, hipStream_t) {
+int32_t gemv_t_splits(int64_t m, int64_t n) {
+  const int64_t cols = (n + 255) / 256;
+  int64_t s = std::max<int64_t>(1, (2048 + cols - 1) / cols);
+  s = std::min<int64_t>(s, std::max<int64_t>(1, m / 64));
+  return static_cast<int32_t>(std::min<int64_t>(s, 64));
+}
+void launch_gemv_t(const double* A, int64_t lda, int64_t m, int64_t n, const double* z, double* d, double* ws,
+                   hipStream_t) {
+  if (gemv_t_splits(m, n) > 1) emu_check(ws, 8 * static_cast<size_t>(gemv_t_splits(m, n)) * n, "gemv_t ws");
   emu_check(A, 8 * (static_cast<size_t>(m - 1) * lda + n), "gemv_t A");
   emu_check(z, 8 * m, "gemv_t z");
   emu_check(d, 8 * n, "gemv_t d");
