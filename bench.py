@@ -689,6 +689,13 @@ def main():
                                               host_data=args.host_generated)
         kpp.kpp_system_destroy(h)
         kpp.kpp_context_destroy(ctx)
+        if args.calibrate_copy > 0:
+            src = torch.empty(args.calibrate_copy << 20, dtype=torch.uint8, device=dev).fill_(1)
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            rec["copy_calibration_bytes"] = args.calibrate_copy << 20
         print(json.dumps({"only": args.only, **rec}), flush=True)
         return
 
