@@ -74,6 +74,7 @@ def parse():
 # kernel's HBM traffic per launch (by workload)
 TRAFFIC_PROFILES = {
     "kpp_2048x32768": os.path.join(ROOT, "profiles", "k_fused_kpp_2048x32768_s128_fp64.md"),
+    "kpp_65536x2048": os.path.join(ROOT, "profiles", "k_fused_kpp_65536x2048_s256_fp64.md"),
     "cdpp_n4096": os.path.join(ROOT, "profiles", "k_fused_cdpp_n4096_s128_fp64.md"),
 }
 
@@ -685,8 +686,9 @@ def main():
     if args.only:
         # one workload's FP64 and mixed solves (the command the step kernel's
         # profile summaries are taken with)
+        prof = {"c2": "cdpp_n4096", "c3": "kpp_65536x2048", "c4": "kpp_2048x32768"}[args.only]
         rec, (sysm, h, _, _) = fp64_and_mixed(kpp, torch, dev, ctx, args.only, args.warmup, args.steps,
-                                              host_data=args.host_generated)
+                                              TRAFFIC_PROFILES[prof], host_data=args.host_generated)
         kpp.kpp_system_destroy(h)
         kpp.kpp_context_destroy(ctx)
         if args.calibrate_copy > 0:
@@ -745,7 +747,8 @@ def main():
         kpp.kpp_context_destroy(ctx)
         return
 
-    rec3, (c3, h3, _, _) = fp64_and_mixed(kpp, torch, dev, ctx, "c3", args.warmup, args.steps)
+    rec3, (c3, h3, _, _) = fp64_and_mixed(kpp, torch, dev, ctx, "c3", args.warmup, args.steps,
+                                          TRAFFIC_PROFILES["kpp_65536x2048"])
     kpp.kpp_system_destroy(h3)
     del c3
     torch.cuda.empty_cache()
