@@ -49,7 +49,7 @@ extern "C" {
 #endif
 
 #define KPP_API __attribute__((visibility("default")))
-#define KPP_ABI_VERSION 4
+#define KPP_ABI_VERSION 5
 
 typedef enum kpp_status {
   KPP_OK = 0,
@@ -230,6 +230,33 @@ KPP_API kpp_status kpp_context_destroy(kpp_context* ctx);
 KPP_API kpp_status kpp_system_create(kpp_context* ctx, int32_t kind, int64_t m, int64_t n,
                                      const double* A_dev, int64_t lda, const double* b_dev,
                                      kpp_system** out);
+
+/* A sparse system A x = b in compressed sparse rows (the sparse inputs of
+ * Section 1's limitations and of the Conclusions, for which Section 3 lets
+ * the Hadamard preprocessing be dropped).  row_ptr_dev: m + 1 int64 offsets
+ * (row_ptr[0] = 0, row_ptr[m] = nnz, non-decreasing); col_dev, val_dev: nnz
+ * column indices (strictly increasing within each row, in [0, n)) and FP64
+ * values; b_dev: m values.  All device memory owned by the caller and read,
+ * never written, for the system's lifetime; col_dev and val_dev may be NULL
+ * when nnz = 0.  kind = KPP_CD_PSD requires m == n and A symmetric PSD (the
+ * lower triangle of each block's A_SS is read).  The structure is checked on
+ * the device (KPP_ERR_SHAPE) as is finiteness of values and b
+ * (KPP_ERR_NONFINITE); the row pointers are copied to the host, and must not
+ * change afterwards (a solve that finds different block nonzero counts
+ * returns KPP_ERR_INVALID_ARG).
+ *
+ * kpp_solve, kpp_state_export/import, kpp_residual_norm and kpp_block_factor
+ * take such a system; a solve runs in FP64 on the launch-per-phase engine
+ * with the exact projection and without rht (KPP_ERR_INVALID_ARG for other
+ * precision, engine, projection or rht values), and the iterates are those of
+ * the same solve on the dense matrix up to rounding.  A block holds at most
+ * 2^20 nonzeros (KPP_ERR_SHAPE).  kpp_solve_multi, kpp_block_factor_noalloc
+ * and the server take dense systems only.  In kpp_result, bytes_algorithmic
+ * counts every nonzero's column of a Kaczmarz++ block as distinct (an upper
+ * bound on the back-projection's traffic). */
+KPP_API kpp_status kpp_system_create_csr(kpp_context* ctx, int32_t kind, int64_t m, int64_t n, int64_t nnz,
+                                         const int64_t* row_ptr_dev, const int32_t* col_dev,
+                                         const double* val_dev, const double* b_dev, kpp_system** out);
 KPP_API kpp_status kpp_system_destroy(kpp_system* sys);
 
 /* Run the solver from x_dev (in: x0, out: final iterate; n FP64 values).

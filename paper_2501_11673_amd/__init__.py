@@ -160,6 +160,7 @@ def _load():
         "kpp_context_create": (i32, [i32, vp, P(vp)]),
         "kpp_context_destroy": (i32, [vp]),
         "kpp_system_create": (i32, [vp, i32, i64, i64, vp, i64, vp, P(vp)]),
+        "kpp_system_create_csr": (i32, [vp, i32, i64, i64, i64, vp, vp, vp, vp, P(vp)]),
         "kpp_system_destroy": (i32, [vp]),
         "kpp_solve": (i32, [vp, P(kpp_params), vp, P(kpp_result)]),
         "kpp_schedule_generate": (i32, [i32, i64, i64, P(kpp_params), i64, P(i32), P(i32), P(i32),
@@ -190,7 +191,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("kpp_abi_version", "kpp_last_error", "kpp_params_default", "kpp_context_create",
-            "kpp_context_destroy", "kpp_system_create", "kpp_system_destroy", "kpp_solve",
+            "kpp_context_destroy", "kpp_system_create", "kpp_system_create_csr", "kpp_system_destroy", "kpp_solve",
             "kpp_schedule_generate", "kpp_block_factor", "kpp_block_factor_noalloc", "kpp_residual_norm", "kpp_request_footprint", "kpp_server_create",
             "kpp_server_submit", "kpp_server_poll", "kpp_server_stats", "kpp_server_destroy",
             "kpp_state_export", "kpp_state_import", "kpp_solve_multi", "kpp_rht_signs", "kpp_rht_general", "kpp_rht_psd",
@@ -231,6 +232,17 @@ def kpp_system_create(ctx: int, kind: int, m: int, n: int, A_dev: int, lda: int,
     out = ctypes.c_void_p()
     _check(_lib.kpp_system_create(ctypes.c_void_p(ctx), kind, m, n, ctypes.c_void_p(A_dev), lda,
                                   ctypes.c_void_p(b_dev), ctypes.byref(out)))
+    return out.value
+
+
+def kpp_system_create_csr(ctx: int, kind: int, m: int, n: int, nnz: int, row_ptr_dev: int, col_dev: int,
+                          val_dev: int, b_dev: int) -> int:
+    """Sparse system from device CSR arrays (int64 row pointers, int32
+    columns ascending within each row, FP64 values), borrowed for its life."""
+    out = ctypes.c_void_p()
+    _check(_lib.kpp_system_create_csr(ctypes.c_void_p(ctx), kind, m, n, nnz, ctypes.c_void_p(row_ptr_dev),
+                                      ctypes.c_void_p(col_dev), ctypes.c_void_p(val_dev), ctypes.c_void_p(b_dev),
+                                      ctypes.byref(out)))
     return out.value
 
 

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libkpp.so")
 
-SOURCES = ["kernels.hip", "gram.hip", "fused.hip", "rht.hip", "lsqr.hip", "noalloc.hip", "runtime.cpp", "schedule.cpp", "gram_plan.cpp"]
+SOURCES = ["kernels.hip", "gram.hip", "fused.hip", "rht.hip", "lsqr.hip", "noalloc.hip", "sparse.hip", "runtime.cpp", "schedule.cpp", "gram_plan.cpp"]
 
 # -packed-fp32-ops is switched off for device code (hipcc's host pass warns
 # that it does not know the feature; that warning is harmless).

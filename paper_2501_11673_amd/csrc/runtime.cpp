@@ -29,6 +29,7 @@
 #include "multi.hpp"
 #include "kpp.h"
 #include "schedule.hpp"
+#include "sparse.hpp"
 
 namespace {
 
@@ -185,6 +186,27 @@ struct kpp_system {
   int64_t lsqr_cap_n = 0, lsqr_cap_N = 0;
   int32_t lsqr_cap_s = 0, lsqr_cap_tau = 0, lsqr_cap_chunk = 0;
   int32_t sig_proj = 0;
+  // compressed sparse rows (kpp_system_create_csr): the caller's device
+  // arrays (A is NULL), a host copy of the row pointers, the column-compressed
+  // copies of the memoized Kaczmarz++ blocks (one arena, each block at a host-
+  // assigned offset; nu per slot on the device) and the build workspace of
+  // blocks too large for LDS, one per staging buffer
+  bool csr = false;
+  const int64_t* csr_rp = nullptr;
+  const int32_t* csr_ci = nullptr;
+  const double* csr_cv = nullptr;
+  int64_t nnz = 0;
+  std::vector<int64_t> h_rp;
+  kpp::CscArena csc{};
+  int64_t csc_cap = 0;    // entries of each arena array
+  int64_t csc_top = 0;    // memoized blocks: next free entry
+  int64_t csc_half = 0;   // no memo: each staging buffer owns half of the arena
+  int32_t* csc_nu = nullptr;
+  int32_t csc_nu_cap = 0;
+  std::vector<int64_t> slot_csc_off;
+  std::vector<int32_t> slot_csc_z;
+  double* csr_ws[2] = {nullptr, nullptr};
+  size_t csr_ws_cap[2] = {0, 0};
 };
 
 namespace {
@@ -258,6 +280,17 @@ void destroy_buffers(kpp_system* s) {
   dev_free(s->zx);
   dev_free(s->zm);
   dev_free(s->fp64_count);
+  dev_free(s->csc.val);
+  dev_free(s->csc.row);
+  dev_free(s->csc.col);
+  dev_free(s->csc.ptr);
+  dev_free(s->csc_nu);
+  s->csc_cap = s->csc_top = s->csc_half = 0;
+  s->csc_nu_cap = 0;
+  for (int i = 0; i < 2; ++i) {
+    dev_free(s->csr_ws[i]);
+    s->csr_ws_cap[i] = 0;
+  }
   if (s->h_ds) (void)hipHostFree(s->h_ds);
   if (s->h_err) (void)hipHostFree(s->h_err);
   s->h_ds = nullptr;
@@ -357,6 +390,72 @@ kpp_status ensure_gram_ws(kpp_system* sys, int idx, size_t doubles) {
   return KPP_OK;
 }
 
+// Sparse systems: the per-slot column counts of the Kaczmarz++ blocks (kept
+// when the table grows).
+kpp_status ensure_csc_nu(kpp_system* sys, int32_t slots) {
+  if (slots <= sys->csc_nu_cap) return KPP_OK;
+  const int32_t cap = std::max<int32_t>(slots, std::max<int32_t>(16, 2 * sys->csc_nu_cap));
+  int32_t* nu = nullptr;
+  KPP_TRY(dev_alloc(&nu, cap));
+  if (sys->csc_nu_cap > 0) {
+    HIP_TRY(hipStreamSynchronize(sys->ctx->stream));
+    KPP_TRY(wait_side_work(sys));
+    HIP_TRY(hipMemcpy(nu, sys->csc_nu, sys->csc_nu_cap * sizeof(int32_t), hipMemcpyDeviceToDevice));
+  }
+  dev_free(sys->csc_nu);
+  sys->csc_nu = nu;
+  sys->csc_nu_cap = cap;
+  return KPP_OK;
+}
+
+// Sparse systems: grow the column-compressed arena to `need` entries per
+// array, keeping the first `keep` (memoized blocks).  Kernels in flight on
+// either stream may read the old arena, so both are drained first.
+kpp_status ensure_csc(kpp_system* sys, int64_t need, int64_t keep) {
+  if (need <= sys->csc_cap) return KPP_OK;
+  const int64_t cap = std::max<int64_t>(need, std::max<int64_t>(int64_t{1} << 16, 2 * sys->csc_cap));
+  HIP_TRY(hipStreamSynchronize(sys->ctx->stream));
+  KPP_TRY(wait_side_work(sys));
+  kpp::CscArena a;
+  kpp_status stt;
+  if ((stt = dev_alloc(&a.val, cap)) < 0 || (stt = dev_alloc(&a.row, cap)) < 0 || (stt = dev_alloc(&a.col, cap)) < 0 ||
+      (stt = dev_alloc(&a.ptr, cap)) < 0) {
+    dev_free(a.val);
+    dev_free(a.row);
+    dev_free(a.col);
+    dev_free(a.ptr);
+    return stt;
+  }
+  if (keep > 0) {
+    HIP_TRY(hipMemcpy(a.val, sys->csc.val, keep * sizeof(double), hipMemcpyDeviceToDevice));
+    HIP_TRY(hipMemcpy(a.row, sys->csc.row, keep * sizeof(int32_t), hipMemcpyDeviceToDevice));
+    HIP_TRY(hipMemcpy(a.col, sys->csc.col, keep * sizeof(int32_t), hipMemcpyDeviceToDevice));
+    HIP_TRY(hipMemcpy(a.ptr, sys->csc.ptr, keep * sizeof(int32_t), hipMemcpyDeviceToDevice));
+  }
+  dev_free(sys->csc.val);
+  dev_free(sys->csc.row);
+  dev_free(sys->csc.col);
+  dev_free(sys->csc.ptr);
+  sys->csc = a;
+  sys->csc_cap = cap;
+  return KPP_OK;
+}
+
+// Sparse systems: global workspace of the block build for staging buffer idx.
+kpp_status ensure_csr_ws(kpp_system* sys, int idx, size_t doubles) {
+  if (doubles <= sys->csr_ws_cap[idx]) return KPP_OK;
+  const size_t cap = std::max<size_t>(doubles, sys->csr_ws_cap[idx] * 2);
+  if (sys->csr_ws_cap[idx] > 0) {
+    HIP_TRY(hipStreamSynchronize(sys->ctx->stream));
+    KPP_TRY(wait_side_work(sys));
+  }
+  dev_free(sys->csr_ws[idx]);
+  sys->csr_ws_cap[idx] = 0;
+  KPP_TRY(dev_alloc(&sys->csr_ws[idx], cap));
+  sys->csr_ws_cap[idx] = cap;
+  return KPP_OK;
+}
+
 kpp_status check_params(const kpp_system* sys, const kpp_params* p) {
   if (!p) return fail(KPP_ERR_INVALID_ARG, "params is NULL");
   const int64_t rows = sys->kind == KPP_CD_PSD ? sys->n : sys->m;
@@ -400,6 +499,14 @@ kpp_status check_params(const kpp_system* sys, const kpp_params* p) {
     if (N > kpp::kFhtMaxRows) return fail(KPP_ERR_SHAPE, "n is too large for the sketch's Hadamard transform");
   }
   if (p->rht && p->resume) return fail(KPP_ERR_INVALID_ARG, "resume does not combine with rht");
+  if (sys->csr) {
+    // the sparse step runs in FP64 on the launch-per-phase engine, without
+    // the Hadamard preprocessing (it would densify A) or the sketched projection
+    if (p->precision != KPP_FP64) return fail(KPP_ERR_INVALID_ARG, "a sparse system solves in FP64 only");
+    if (p->rht) return fail(KPP_ERR_INVALID_ARG, "the Hadamard preprocessing does not apply to a sparse system");
+    if (p->projection != 0) return fail(KPP_ERR_INVALID_ARG, "a sparse system takes the exact projection only");
+    if (p->engine == 2) return fail(KPP_ERR_INVALID_ARG, "a sparse system runs on the launch-per-phase engine");
+  }
   if (p->schedule) {
     if (p->schedule_len < 0) return fail(KPP_ERR_INVALID_ARG, "schedule_len must be >= 0");
     if (!p->block_rows || p->block_rows_count < 1)
@@ -416,7 +523,10 @@ double default_eta(int32_t kind, int64_t m, int64_t n, int32_t s) {
 
 kpp_status residual_norm(kpp_system* sys, const double* x, double* out) {
   hipStream_t st = sys->ctx->stream;
-  kpp::launch_residual_sq(sys->A, sys->lda, sys->m, sys->n, x, sys->b, sys->rowsq, 0, sys->scal, st);
+  if (sys->csr)
+    kpp::launch_csr_residual_sq(sys->csr_rp, sys->csr_ci, sys->csr_cv, sys->b, sys->m, x, sys->rowsq, sys->scal, st);
+  else
+    kpp::launch_residual_sq(sys->A, sys->lda, sys->m, sys->n, x, sys->b, sys->rowsq, 0, sys->scal, st);
   HIP_TRY(hipGetLastError());
   double v = 0.0;
   HIP_TRY(hipMemcpyAsync(&v, sys->scal, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -532,6 +642,10 @@ struct CoreStats {
   int32_t engine = 0;
   int32_t groups = 0, cpl = 0;   // fused geometry (0 for the launch-per-phase engine)
   bool dual = false;
+  // sparse systems: nonzeros of the stepped blocks, gathered iterate entries
+  // (one or two vectors a nonzero), folds of the deferred momentum form
+  double csr_nnz = 0.0, csr_gathers = 0.0, csr_miss_nnz = 0.0;
+  int64_t csr_folds = 0;
 };
 
 // One run of the block iteration (Algorithm 2 / Algorithm 5 with the exact
@@ -570,6 +684,8 @@ class CoreRun {
     periods_ = std::max<int32_t>(1, periods);
     eta_ = p->eta < 0.0 ? default_eta(kind_, m_, n_, s_) : p->eta;
     if (!p->accel) eta_ = 0.0;
+    csr_ = sys->csr;
+    rho_now_ = o.rho0;
     mode_ = static_cast<kpp::MemoMode>(p->memo);
     max_iters_ = o.max_iters;
     const double B0 = kpp::online_rate(kind_, m_, n_, s_);
@@ -594,6 +710,7 @@ class CoreRun {
       max_iters_ = t_ + o.max_iters;
       if (sch_->is_explicit()) max_iters_ = std::min(max_iters_, sch_->length());
       hs_ = sys->res_ds;
+      rho_now_ = hs_.rho;
     }
     if (force_cpl > 0) {
       fused_ = fused_cpl_fits(s_, fp32_, force_cpl);
@@ -602,7 +719,7 @@ class CoreRun {
       if (groups_ > kpp::kFusedMaxGroups) fused_ = false;
       if (!fused_) return fail(KPP_ERR_INVALID_ARG, "no fused geometry with %d columns per lane", force_cpl);
     } else {
-      if (p->engine != 1) fused_ = fused_geometry(n_, s_, p->team_groups, fp32_, &cpl_, &groups_);
+      if (p->engine != 1 && !csr_) fused_ = fused_geometry(n_, s_, p->team_groups, fp32_, &cpl_, &groups_);
       if (p->engine == 2 && !fused_)
         return fail(KPP_ERR_INVALID_ARG, "n=%lld is too wide for the fused engine", (long long)n_);
     }
@@ -658,9 +775,11 @@ class CoreRun {
       sys->sig_prec = fp32_ ? 1 : 0;
       sys->sig_explicit = sch_->is_explicit();
       sys->sig_proj = lsqr_ ? 1 : 0;
+      sys->csc_top = 0;
     }
+    if (csr_ && kind_ == KPP_KACZMARZ) KPP_TRY(ensure_csc_nu(sys, sys->cap_slots));
     // launch engine: column chunks of the block gemv
-    P_ = static_cast<int32_t>((n_ + kChunk - 1) / kChunk);
+    P_ = csr_ ? 1 : static_cast<int32_t>((n_ + kChunk - 1) / kChunk);
     if (!fused_ && static_cast<int64_t>(s_) * P_ > sys->rpart_cap) {
       dev_free(sys->rpart);
       KPP_TRY(dev_alloc(&sys->rpart, static_cast<size_t>(s_) * P_));
@@ -779,6 +898,7 @@ class CoreRun {
     Window& w = win_[cur_];
     const size_t sd = static_cast<size_t>(sys_->slot_stride);
     if (lsqr_) return launch_lsqr_steps();
+    if (csr_) return launch_csr_steps();
     for (int64_t k = w.done; k < w.W; ++k) {
       const int32_t q = w.step_slot[k];
       const int32_t sb = sch_->len(w.step_block[k]);
@@ -823,6 +943,52 @@ class CoreRun {
       kpp::launch_update(kind_, src_.A64, src_.lda, n_, rows, sb, zx, sys->ds, eta_, x_, sys->mom, st_);
     }
     launches_ += (7 + 5 * lsqr_iters_) * (w.W - w.done);
+    HIP_TRY(hipGetLastError());
+    return KPP_OK;
+  }
+
+  // Sparse steps: block rows, projection, back-projection on the deferred
+  // iterate u + t01 v and momentum t11 v (x_ and the momentum buffer hold u
+  // and v).  rho, hence c, is fixed inside a window (its checkpoint is the
+  // window's last step and revises rho for the next one), so the host keeps
+  // (t01, t11).  u, v are folded back into x, m at the window's end and
+  // whenever 1 / t11 or t01 / t11 would pass kLazyBound: the deferred sums
+  // then stay within a factor kLazyBound of the terms they hold.
+  kpp_status launch_csr_steps() {
+    Window& w = win_[cur_];
+    kpp_system* sys = sys_;
+    const size_t sd = static_cast<size_t>(sys->slot_stride);
+    const double c = (1.0 - rho_now_) / (1.0 + rho_now_);
+    double t01 = 0.0, t11 = 1.0;
+    auto fold = [&]() {
+      kpp::launch_lazy_fold(x_, sys->mom, n_, t01, t11, st_);
+      ++launches_;
+      ++csr_folds_;
+      t01 = 0.0;
+      t11 = 1.0;
+    };
+    for (int64_t k = w.done; k < w.W; ++k) {
+      if (t11 == 0.0 || 1.0 / t11 > kLazyBound || std::fabs(t01 / t11) > kLazyBound) fold();
+      const int32_t q = w.step_slot[k];
+      const int32_t sb = sch_->len(w.step_block[k]);
+      const int32_t* rows = sys->rows + static_cast<size_t>(q) * s_;
+      const int32_t z = sys->slot_csc_z[q];
+      kpp::launch_csr_rows_dot(sys->csr_rp, sys->csr_ci, sys->csr_cv, rows, sb, x_, sys->mom, t01, sys->rpart, st_);
+      kpp::launch_block_project(sys->rpart, 1, src_.b, rows, sb, sys->L + sd * q + static_cast<size_t>(s_) * s_, s_,
+                                sys->y, sys->ds, zeta_, prm_.adaptive_rho, st_);
+      const double au = 1.0 - t01 / t11, av = 1.0 / t11;
+      if (kind_ == KPP_KACZMARZ)
+        kpp::launch_csc_apply(sys->csc, sys->slot_csc_off[q], z, sys->csc_nu, q, sys->y, sb, au, av, x_, sys->mom,
+                              st_);
+      else
+        kpp::launch_rows_apply(rows, sb, sys->y, au, av, x_, sys->mom, st_);
+      csr_nnz_ += z;
+      csr_gathers_ += (t01 != 0.0 ? 2.0 : 1.0) * z;
+      t01 += eta_ * c * t11;
+      t11 *= c;
+    }
+    if (t01 != 0.0 || t11 != 1.0) fold();
+    launches_ += 3 * (w.W - w.done);
     HIP_TRY(hipGetLastError());
     return KPP_OK;
   }
@@ -886,6 +1052,12 @@ class CoreRun {
       finished_ = true;
       return fail(KPP_ERR_NOT_SPD, "a regularized block Gram has no Cholesky factor (lambda=%g)", prm_.lambda);
     }
+    if (herr & 4) {
+      drain();
+      finished_ = true;
+      return fail(KPP_ERR_INVALID_ARG, "the sparse matrix's row pointers changed after the system was created");
+    }
+    rho_now_ = hs_.rho;
     Window& w = win_[cur_];
     // every FP32 Gram tried so far (at least 32 blocks) was redone in FP64:
     // later blocks of this system skip the FP32 attempt
@@ -971,6 +1143,10 @@ class CoreRun {
     cs->groups = fused_ ? groups_ : 0;
     cs->cpl = fused_ ? cpl_ : 0;
     cs->dual = dual_;
+    cs->csr_nnz = csr_nnz_;
+    cs->csr_gathers = csr_gathers_;
+    cs->csr_miss_nnz = csr_miss_nnz_;
+    cs->csr_folds = csr_folds_;
     return converged_ ? KPP_OK : KPP_NOT_CONVERGED;
   }
 
@@ -981,6 +1157,7 @@ class CoreRun {
 
  private:
   static constexpr int64_t kChunk = 2048;
+  static constexpr double kLazyBound = 256.0;
 
   struct Window {
     int64_t t0 = 0, W = 0, done = 0;
@@ -988,7 +1165,8 @@ class CoreRun {
     int64_t fp32_tried = 0;   // new blocks with an FP32 Gram attempt up to this window
     bool try32 = false;       // this window's new blocks try an FP32 Gram first
     bool on_side = false, waited = false;
-    size_t o_len = 0, o_slot = 0, o_step = 0;
+    size_t o_len = 0, o_slot = 0, o_step = 0, o_csc = 0;
+    bool csr_lds = false, csr_global = false;   // sparse Kaczmarz++: build variants this window needs
     std::vector<int32_t> step_block, step_slot;
     std::vector<char> step_new;
   };
@@ -1044,6 +1222,7 @@ class CoreRun {
       KPP_TRY(ensure_slots(sys, sys->used_slots, s));
       t_prof_slots += wall_now() - ts;
     }
+    if (csr_ && kind_ == KPP_KACZMARZ) KPP_TRY(ensure_csc_nu(sys, sys->cap_slots));
     w.nb = static_cast<int32_t>(pending.size());
     w.try32 = fp32_ && !sys->fp32_gram_futile;
     if (w.try32) sys->fp32_tried += w.nb;
@@ -1051,7 +1230,8 @@ class CoreRun {
     w.o_len = static_cast<size_t>(w.nb) * s;
     w.o_slot = w.o_len + w.nb;
     w.o_step = w.o_slot + w.nb;
-    const size_t need = w.o_step + static_cast<size_t>(w.W) + static_cast<size_t>(w.nb);  // + flags
+    w.o_csc = w.o_step + static_cast<size_t>(w.W) + static_cast<size_t>(w.nb);   // after the flags
+    const size_t need = w.o_csc + (csr_ ? static_cast<size_t>(kpp::kCsrMetaInts) * w.nb : 0);
     const double tg = wall_now();
     KPP_TRY(ensure_stage(sys, idx, need));
     t_prof_grow += wall_now() - tg;
@@ -1065,12 +1245,79 @@ class CoreRun {
       stage[w.o_slot + k] = pending_slots[k];
     }
     std::copy(w.step_slot.begin(), w.step_slot.end(), stage + w.o_step);
+    if (csr_) KPP_TRY(plan_csr(w, pending, pending_slots));
     if (lsqr_) {
       // the sketch rows of the new blocks, in step order
       auto& T = lsqr_T_host_[idx];
       T.resize(static_cast<size_t>(w.nb) * tau_);
       for (int32_t k = 0; k < w.nb; ++k) draw_sketch_rows(T.data() + static_cast<size_t>(k) * tau_);
     }
+    return KPP_OK;
+  }
+
+  // Sparse systems: nonzeros of each new block (from the host copy of the row
+  // pointers) and, for Kaczmarz++, its place in the column-compressed arena
+  // (appended for memoized blocks; for runs without memo each staging buffer
+  // fills its own half) and in the build workspace when it exceeds LDS.
+  kpp_status plan_csr(Window& w, const std::vector<int32_t>& pending, const std::vector<int32_t>& slots) {
+    kpp_system* sys = sys_;
+    w.csr_lds = w.csr_global = false;
+    if (w.nb == 0) return KPP_OK;
+    const int32_t maxq = *std::max_element(slots.begin(), slots.end());
+    if (static_cast<int32_t>(sys->slot_csc_z.size()) <= maxq) {
+      sys->slot_csc_z.resize(static_cast<size_t>(maxq) + 1, 0);
+      sys->slot_csc_off.resize(static_cast<size_t>(maxq) + 1, 0);
+    }
+    std::vector<int64_t> zs(w.nb);
+    int64_t total = 0;
+    for (int32_t k = 0; k < w.nb; ++k) {
+      const int32_t b = pending[k];
+      const int32_t* r = sch_->rows(b);
+      const int32_t l = sch_->len(b);
+      int64_t z = 0;
+      for (int32_t i = 0; i < l; ++i) z += sys->h_rp[r[i] + 1] - sys->h_rp[r[i]];
+      if (z > kpp::kCsrMaxBlockNnz)
+        return fail(KPP_ERR_SHAPE, "a block of %d rows holds %lld nonzeros (at most %lld)", l,
+                    static_cast<long long>(z), static_cast<long long>(kpp::kCsrMaxBlockNnz));
+      zs[k] = z;
+      total += z + 1;
+      sys->slot_csc_z[slots[k]] = static_cast<int32_t>(z);
+      csr_miss_nnz_ += static_cast<double>(z);
+    }
+    if (kind_ != KPP_KACZMARZ) return KPP_OK;
+    int64_t base = 0;
+    if (mode_ == kpp::MemoMode::Off) {
+      if (total > sys->csc_half) {
+        KPP_TRY(ensure_csc(sys, 2 * std::max(total, 2 * sys->csc_half), 0));
+        sys->csc_half = sys->csc_cap / 2;
+      }
+      base = w.idx * sys->csc_half;
+    } else {
+      KPP_TRY(ensure_csc(sys, sys->csc_top + total, sys->csc_top));
+      base = sys->csc_top;
+      sys->csc_top += total;
+    }
+    int32_t* meta = sys->h_stage[w.idx] + w.o_csc;
+    size_t wsd = 0;
+    int64_t o = base;
+    for (int32_t k = 0; k < w.nb; ++k) {
+      const int64_t z = zs[k];
+      sys->slot_csc_off[slots[k]] = o;
+      int64_t wso = -1;
+      if (z > kpp::kCsrLdsEntries) {
+        wso = static_cast<int64_t>(wsd);
+        wsd += kpp::csr_build_ws_doubles(z);
+        w.csr_global = true;
+      } else {
+        w.csr_lds = true;
+      }
+      int32_t* mk = meta + static_cast<size_t>(kpp::kCsrMetaInts) * k;
+      kpp::csr_meta_put(mk, o);
+      mk[2] = static_cast<int32_t>(z);
+      kpp::csr_meta_put(mk + 3, wso);
+      o += z + 1;
+    }
+    if (wsd > 0) KPP_TRY(ensure_csr_ws(sys, w.idx, wsd));
     return KPP_OK;
   }
 
@@ -1145,7 +1392,7 @@ class CoreRun {
     kpp_system* sys = sys_;
     const int32_t s = s_;
     const int idx = w.idx;
-    const size_t need = w.o_step + static_cast<size_t>(w.W);
+    const size_t need = csr_ ? w.o_csc + static_cast<size_t>(kpp::kCsrMetaInts) * w.nb : w.o_step + static_cast<size_t>(w.W);
     HIP_TRY(hipMemcpyAsync(sys->d_stage[idx], sys->h_stage[idx], need * sizeof(int32_t), hipMemcpyHostToDevice, fs));
     HIP_TRY(hipEventRecord(sys->ev_fact[idx][0], fs));
     if (w.nb > 0) {
@@ -1155,6 +1402,24 @@ class CoreRun {
       kpp::launch_scatter_rows(d_srows, d_slens, d_sslot, w.nb, s, sys->rows, sys->lens, fs);
       if (lsqr_) {
         KPP_TRY(enqueue_sketch_factor(w, fs));
+        HIP_TRY(hipEventRecord(sys->ev_fact[idx][1], fs));
+        return KPP_OK;
+      }
+      if (csr_) {
+        if (kind_ == KPP_KACZMARZ)
+          kpp::launch_csr_block_build(sys->csr_rp, sys->csr_ci, sys->csr_cv, d_srows, d_slens, d_sslot,
+                                      sys->d_stage[idx] + w.o_csc, w.nb, s, prm_.lambda, sys->L, sys->slot_stride,
+                                      sys->csc, sys->csc_nu, sys->csr_ws[idx], w.csr_lds, w.csr_global, sys->err, fs);
+        else
+          kpp::launch_csr_gram_cd(sys->csr_rp, sys->csr_ci, sys->csr_cv, d_srows, d_slens, d_sslot, w.nb, s,
+                                  prm_.lambda, sys->L, sys->slot_stride, fs);
+        if (s <= kpp::kFactorSmallMax) {
+          kpp::launch_factor_small(sys->L, sys->slot_stride, s, d_slens, w.nb, d_sslot, 1, sys->err, fs);
+        } else {
+          kpp::launch_cholesky(sys->L, s, sys->slot_stride, d_slens, w.nb, d_sslot, sys->err, fs);
+          kpp::launch_factor_inverse(sys->L, sys->slot_stride, s, d_slens, w.nb, d_sslot, fs);
+        }
+        HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(sys->ev_fact[idx][1], fs));
         return KPP_OK;
       }
@@ -1281,6 +1546,11 @@ class CoreRun {
   double true_rel_ = NAN, t_factor_ = 0.0, t_kernel_ = 0.0;
   kpp::DevState hs_{};
   std::vector<double> e1_hist_;
+  // sparse systems
+  bool csr_ = false;
+  double rho_now_ = 0.0;   // rho of the current window's steps
+  double csr_nnz_ = 0.0, csr_gathers_ = 0.0, csr_miss_nnz_ = 0.0;
+  int64_t csr_folds_ = 0;
   // LSQR projection
   bool lsqr_ = false;
   int64_t Nsk_ = 0;
@@ -1359,6 +1629,21 @@ void fill_result(kpp_result* res, const kpp_system* sys, const kpp_params* p, in
   }
   res->bytes_algorithmic =
       static_cast<double>(iters) * (sdb * nn * bytes_per_elem + 0.5 * sdb * (sdb + 1) * 8.0 + 12.0 * sdb);
+  if (sys->csr) {
+    // sparse steps: block rows (index and value of each nonzero, its iterate
+    // entries, row pointers), the projection (s^2 inverse entries), the
+    // back-projection (Kaczmarz++: the column-compressed copy, counting every
+    // nonzero's column as distinct, and u, v read and written there; CD++: s
+    // entries of u and v), and 32 n bytes per fold.  Factors: s^3 / 3 plus
+    // the Gram's s z (Kaczmarz++) per miss.
+    const double it = static_cast<double>(iters);
+    const double z = last.csr_nnz, g = last.csr_gathers, folds = static_cast<double>(last.csr_folds);
+    const bool kz = kind == KPP_KACZMARZ;
+    res->flops = 2.0 * z + it * 2.0 * sdb * sdb + (kz ? 2.0 * z + 4.0 * z : 4.0 * sdb * it) + 3.0 * nn * folds +
+                 static_cast<double>(misses) * sdb * sdb * sdb / 3.0 + (kz ? sdb * last.csr_miss_nnz : 0.0);
+    res->bytes_algorithmic = 12.0 * z + 8.0 * g + it * (16.0 * sdb + 8.0 * sdb * sdb + 28.0 * sdb) +
+                             (kz ? 12.0 * z + 40.0 * z : it * 36.0 * sdb) + 32.0 * nn * folds;
+  }
   res->kernel_seconds = t_kernel;
   res->kernel_launches = static_cast<double>(launches);
 }
@@ -2544,6 +2829,7 @@ kpp_status solve_multi(kpp_system* sys, const kpp_params* p, int32_t k, const do
 KPP_API kpp_status kpp_solve_multi(kpp_system* sys, const kpp_params* p, int32_t k, const double* B_dev, int64_t ldb,
                                    double* X_dev, int64_t ldx, kpp_result* res) {
   if (!sys || !B_dev || !X_dev) return fail(KPP_ERR_INVALID_ARG, "NULL system, B or X");
+  if (sys->csr) return fail(KPP_ERR_INVALID_ARG, "several right-hand sides take a dense system");
   if (k < 1 || k > kpp::kMaxRhs) return fail(KPP_ERR_INVALID_ARG, "k must be in [1, %d]", kpp::kMaxRhs);
   if (ldb < k || ldx < k) return fail(KPP_ERR_INVALID_ARG, "leading dimensions must be >= k");
   KPP_TRY(check_params(sys, p));
@@ -2634,17 +2920,11 @@ KPP_API kpp_status kpp_context_destroy(kpp_context* ctx) {
   return KPP_OK;
 }
 
-KPP_API kpp_status kpp_system_create(kpp_context* ctx, int32_t kind, int64_t m, int64_t n,
-                                     const double* A_dev, int64_t lda, const double* b_dev,
-                                     kpp_system** out) {
-  if (!out) return fail(KPP_ERR_INVALID_ARG, "out is NULL");
-  *out = nullptr;
-  if (!ctx || !A_dev || !b_dev) return fail(KPP_ERR_INVALID_ARG, "NULL context, A or b");
-  if (kind != KPP_KACZMARZ && kind != KPP_CD_PSD) return fail(KPP_ERR_INVALID_ARG, "unknown kind %d", kind);
-  if (m < 1 || n < 1) return fail(KPP_ERR_SHAPE, "empty system (m=%lld, n=%lld)", (long long)m, (long long)n);
-  if (lda < n) return fail(KPP_ERR_SHAPE, "lda=%lld < n=%lld", (long long)lda, (long long)n);
-  if (kind == KPP_CD_PSD && m != n) return fail(KPP_ERR_SHAPE, "CD++ needs a square matrix");
-  if (m > (int64_t{1} << 31) - 1 || n > (int64_t{1} << 31) - 1) return fail(KPP_ERR_SHAPE, "dimension above 2^31-1");
+namespace {
+
+// The buffers every system holds (momentum, state, staging events, flags).
+kpp_status alloc_system(kpp_context* ctx, int32_t kind, int64_t m, int64_t n, const double* b_dev,
+                        std::unique_ptr<kpp_system>* out) {
   HIP_TRY(hipSetDevice(ctx->device));
   std::unique_ptr<kpp_system> sys(new (std::nothrow) kpp_system);
   if (!sys) return fail(KPP_ERR_OOM, "host allocation failed");
@@ -2652,8 +2932,6 @@ KPP_API kpp_status kpp_system_create(kpp_context* ctx, int32_t kind, int64_t m, 
   sys->kind = kind;
   sys->m = m;
   sys->n = n;
-  sys->lda = lda;
-  sys->A = A_dev;
   sys->b = b_dev;
   kpp_status stt;
   if ((stt = dev_alloc(&sys->mom, n)) < 0 || (stt = dev_alloc(&sys->ds, 1)) < 0 ||
@@ -2681,25 +2959,104 @@ KPP_API kpp_status kpp_system_create(kpp_context* ctx, int32_t kind, int64_t m, 
         destroy_buffers(sys.get());
         return fail(KPP_ERR_HIP, "hipEventCreate failed");
       }
+  if (hipMemsetAsync(sys->flags, 0, kFlagWords * sizeof(uint32_t), ctx->stream) != hipSuccess ||
+      hipMemsetAsync(sys->err, 0, sizeof(int32_t), ctx->stream) != hipSuccess) {
+    destroy_buffers(sys.get());
+    return fail(KPP_ERR_HIP, "hipMemsetAsync failed");
+  }
+  *out = std::move(sys);
+  return KPP_OK;
+}
+
+// Frees a system's buffers on every early return of its creation.
+struct SystemGuard {
+  std::unique_ptr<kpp_system>& sys;
+  ~SystemGuard() {
+    if (sys) destroy_buffers(sys.get());
+  }
+};
+
+// ||b|| on the host (b is m doubles on the device).
+kpp_status host_bnorm(kpp_system* sys) {
+  hipStream_t st = sys->ctx->stream;
+  std::vector<double> hb(sys->m);
+  HIP_TRY(hipMemcpyAsync(hb.data(), sys->b, sys->m * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double bb = 0.0;
+  for (double v : hb) bb += v * v;
+  sys->bnorm = std::sqrt(bb);
+  return KPP_OK;
+}
+
+}  // namespace
+
+KPP_API kpp_status kpp_system_create(kpp_context* ctx, int32_t kind, int64_t m, int64_t n,
+                                     const double* A_dev, int64_t lda, const double* b_dev,
+                                     kpp_system** out) {
+  if (!out) return fail(KPP_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!ctx || !A_dev || !b_dev) return fail(KPP_ERR_INVALID_ARG, "NULL context, A or b");
+  if (kind != KPP_KACZMARZ && kind != KPP_CD_PSD) return fail(KPP_ERR_INVALID_ARG, "unknown kind %d", kind);
+  if (m < 1 || n < 1) return fail(KPP_ERR_SHAPE, "empty system (m=%lld, n=%lld)", (long long)m, (long long)n);
+  if (lda < n) return fail(KPP_ERR_SHAPE, "lda=%lld < n=%lld", (long long)lda, (long long)n);
+  if (kind == KPP_CD_PSD && m != n) return fail(KPP_ERR_SHAPE, "CD++ needs a square matrix");
+  if (m > (int64_t{1} << 31) - 1 || n > (int64_t{1} << 31) - 1) return fail(KPP_ERR_SHAPE, "dimension above 2^31-1");
+  std::unique_ptr<kpp_system> sys;
+  KPP_TRY(alloc_system(ctx, kind, m, n, b_dev, &sys));
+  SystemGuard guard{sys};
+  sys->lda = lda;
+  sys->A = A_dev;
   hipStream_t st = ctx->stream;
-  HIP_TRY(hipMemsetAsync(sys->flags, 0, kFlagWords * sizeof(uint32_t), st));
   // finiteness of A and b, and ||b||
-  HIP_TRY(hipMemsetAsync(sys->err, 0, sizeof(int32_t), st));
   kpp::launch_check_finite(A_dev, lda, m, n, b_dev, sys->err, st);
   HIP_TRY(hipGetLastError());
   int32_t bad = 0;
   HIP_TRY(hipMemcpyAsync(&bad, sys->err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  if (bad) {
-    destroy_buffers(sys.get());
-    return fail(KPP_ERR_NONFINITE, "A or b holds NaN or Inf");
-  }
-  std::vector<double> hb(m);
-  HIP_TRY(hipMemcpyAsync(hb.data(), b_dev, m * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (bad) return fail(KPP_ERR_NONFINITE, "A or b holds NaN or Inf");
+  KPP_TRY(host_bnorm(sys.get()));
+  *out = sys.release();
+  return KPP_OK;
+}
+
+KPP_API kpp_status kpp_system_create_csr(kpp_context* ctx, int32_t kind, int64_t m, int64_t n, int64_t nnz,
+                                         const int64_t* row_ptr_dev, const int32_t* col_dev, const double* val_dev,
+                                         const double* b_dev, kpp_system** out) {
+  if (!out) return fail(KPP_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!ctx || !row_ptr_dev || !b_dev) return fail(KPP_ERR_INVALID_ARG, "NULL context, row pointers or b");
+  if (nnz < 0) return fail(KPP_ERR_SHAPE, "nnz=%lld < 0", (long long)nnz);
+  if (nnz > 0 && (!col_dev || !val_dev)) return fail(KPP_ERR_INVALID_ARG, "NULL column indices or values");
+  if (kind != KPP_KACZMARZ && kind != KPP_CD_PSD) return fail(KPP_ERR_INVALID_ARG, "unknown kind %d", kind);
+  if (m < 1 || n < 1) return fail(KPP_ERR_SHAPE, "empty system (m=%lld, n=%lld)", (long long)m, (long long)n);
+  if (kind == KPP_CD_PSD && m != n) return fail(KPP_ERR_SHAPE, "CD++ needs a square matrix");
+  if (m > (int64_t{1} << 31) - 1 || n > (int64_t{1} << 31) - 1) return fail(KPP_ERR_SHAPE, "dimension above 2^31-1");
+  std::unique_ptr<kpp_system> sys;
+  KPP_TRY(alloc_system(ctx, kind, m, n, b_dev, &sys));
+  SystemGuard guard{sys};
+  sys->csr = true;
+  sys->csr_rp = row_ptr_dev;
+  sys->csr_ci = col_dev;
+  sys->csr_cv = val_dev;
+  sys->nnz = nnz;
+  hipStream_t st = ctx->stream;
+  kpp::launch_csr_check(row_ptr_dev, col_dev, val_dev, b_dev, m, n, nnz, sys->err, st);
+  HIP_TRY(hipGetLastError());
+  int32_t bad = 0;
+  HIP_TRY(hipMemcpyAsync(&bad, sys->err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  double bb = 0.0;
-  for (double v : hb) bb += v * v;
-  sys->bnorm = std::sqrt(bb);
+  if (bad & 3)
+    return fail(KPP_ERR_SHAPE, (bad & 1) ? "row pointers are not a CSR layout of nnz entries"
+                                         : "a column index is out of range or not increasing within its row");
+  if (bad) return fail(KPP_ERR_NONFINITE, "the values or b hold NaN or Inf");
+  HIP_TRY(hipMemsetAsync(sys->err, 0, sizeof(int32_t), st));
+  try {
+    sys->h_rp.resize(static_cast<size_t>(m) + 1);
+  } catch (const std::bad_alloc&) {
+    return fail(KPP_ERR_OOM, "host allocation failed");
+  }
+  HIP_TRY(hipMemcpyAsync(sys->h_rp.data(), row_ptr_dev, (m + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  KPP_TRY(host_bnorm(sys.get()));
   *out = sys.release();
   return KPP_OK;
 }
@@ -2853,6 +3210,11 @@ KPP_API kpp_status kpp_block_factor(kpp_system* sys, int32_t s, double lambda, i
       if (r < 0 || r >= N) return fail(KPP_ERR_INVALID_ARG, "block %d row %d out of range", b, r);
     }
   }
+  if (sys->csr && sys->kind == KPP_CD_PSD)
+    for (int32_t b = 0; b < nb; ++b)
+      for (int32_t i = 1; i < len_host[b]; ++i)
+        if (rows_host[static_cast<size_t>(b) * s + i] <= rows_host[static_cast<size_t>(b) * s + i - 1])
+          return fail(KPP_ERR_INVALID_ARG, "block %d: rows of a sparse CD++ block must ascend", b);
   if (nb == 0) return KPP_OK;
   HIP_TRY(hipSetDevice(sys->ctx->device));
   hipStream_t st = sys->ctx->stream;
@@ -2867,9 +3229,55 @@ KPP_API kpp_status kpp_block_factor(kpp_system* sys, int32_t s, double lambda, i
   HIP_TRY(hipMemcpyAsync(d_ids, ids.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemsetAsync(sys->err, 0, sizeof(int32_t), st));
   HIP_TRY(hipMemsetAsync(L_dev, 0, static_cast<size_t>(nb) * s * s * sizeof(double), st));
-  if (sys->kind == KPP_KACZMARZ) KPP_TRY(ensure_gram_ws(sys, 0, kpp::gram_syrk_work(s, sys->n, nb)));
-  kpp::launch_gram(sys->kind, sys->A, sys->lda, sys->n, d_rows, d_lens, s, nb, lambda, L_dev,
-                   static_cast<int64_t>(s) * s, d_ids, sys->gram_ws[0], st);
+  kpp::CscArena ar;
+  int32_t *d_meta = nullptr, *d_nu = nullptr;
+  double* d_ws = nullptr;
+  if (sys->csr && sys->kind == KPP_KACZMARZ) {
+    // the memo-miss kernel of sparse Kaczmarz++ blocks, with an arena and
+    // build workspace of this call's own
+    std::vector<int32_t> meta(static_cast<size_t>(kpp::kCsrMetaInts) * nb);
+    int64_t total = 0;
+    size_t wsd = 0;
+    bool any_lds = false, any_global = false;
+    for (int32_t b = 0; b < nb; ++b) {
+      int64_t z = 0;
+      for (int32_t i = 0; i < len_host[b]; ++i) {
+        const int32_t r = rows_host[static_cast<size_t>(b) * s + i];
+        z += sys->h_rp[r + 1] - sys->h_rp[r];
+      }
+      if (z > kpp::kCsrMaxBlockNnz) return fail(KPP_ERR_SHAPE, "block %d holds %lld nonzeros", b, (long long)z);
+      int64_t wso = -1;
+      if (z > kpp::kCsrLdsEntries) {
+        wso = static_cast<int64_t>(wsd);
+        wsd += kpp::csr_build_ws_doubles(z);
+        any_global = true;
+      } else {
+        any_lds = true;
+      }
+      int32_t* mk = meta.data() + static_cast<size_t>(kpp::kCsrMetaInts) * b;
+      kpp::csr_meta_put(mk, total);
+      mk[2] = static_cast<int32_t>(z);
+      kpp::csr_meta_put(mk + 3, wso);
+      total += z + 1;
+    }
+    KPP_TRY(dev_alloc(&ar.val, total));
+    KPP_TRY(dev_alloc(&ar.row, total));
+    KPP_TRY(dev_alloc(&ar.col, total));
+    KPP_TRY(dev_alloc(&ar.ptr, total));
+    KPP_TRY(dev_alloc(&d_nu, nb));
+    KPP_TRY(dev_alloc(&d_meta, meta.size()));
+    if (wsd > 0) KPP_TRY(dev_alloc(&d_ws, wsd));
+    HIP_TRY(hipMemcpyAsync(d_meta, meta.data(), meta.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    kpp::launch_csr_block_build(sys->csr_rp, sys->csr_ci, sys->csr_cv, d_rows, d_lens, d_ids, d_meta, nb, s, lambda,
+                                L_dev, static_cast<int64_t>(s) * s, ar, d_nu, d_ws, any_lds, any_global, sys->err, st);
+  } else if (sys->csr) {
+    kpp::launch_csr_gram_cd(sys->csr_rp, sys->csr_ci, sys->csr_cv, d_rows, d_lens, d_ids, nb, s, lambda, L_dev,
+                            static_cast<int64_t>(s) * s, st);
+  } else {
+    if (sys->kind == KPP_KACZMARZ) KPP_TRY(ensure_gram_ws(sys, 0, kpp::gram_syrk_work(s, sys->n, nb)));
+    kpp::launch_gram(sys->kind, sys->A, sys->lda, sys->n, d_rows, d_lens, s, nb, lambda, L_dev,
+                     static_cast<int64_t>(s) * s, d_ids, sys->gram_ws[0], st);
+  }
   HIP_TRY(hipGetLastError());
   if (s <= kpp::kFactorSmallMax)
     kpp::launch_factor_small(L_dev, static_cast<int64_t>(s) * s, s, d_lens, nb, d_ids, 0, sys->err, st);
@@ -2882,6 +3290,14 @@ KPP_API kpp_status kpp_block_factor(kpp_system* sys, int32_t s, double lambda, i
   dev_free(d_rows);
   dev_free(d_lens);
   dev_free(d_ids);
+  dev_free(ar.val);
+  dev_free(ar.row);
+  dev_free(ar.col);
+  dev_free(ar.ptr);
+  dev_free(d_nu);
+  dev_free(d_meta);
+  dev_free(d_ws);
+  if (herr & 4) return fail(KPP_ERR_INVALID_ARG, "the sparse matrix's row pointers changed after the system was created");
   if (herr) return fail(KPP_ERR_NOT_SPD, "a regularized block Gram has no Cholesky factor");
   return KPP_OK;
 }
@@ -2896,6 +3312,7 @@ constexpr size_t kNaGramDoubles = (kpp::kNoAllocScratchBytes - kNaGramOffset) / 
 KPP_API kpp_status kpp_block_factor_noalloc(kpp_system* sys, int32_t s, double lambda, int32_t nb,
                                             const int32_t* rows_host, const int32_t* len_host, double* L_dev) {
   if (!sys || !rows_host || !len_host || !L_dev || nb < 0) return fail(KPP_ERR_INVALID_ARG, "bad arguments");
+  if (sys->csr) return fail(KPP_ERR_INVALID_ARG, "the no-allocation factor takes a dense system");
   const int64_t N = sys->kind == KPP_CD_PSD ? sys->n : sys->m;
   if (s < 1 || s > kpp::kMaxBlock) return fail(KPP_ERR_INVALID_ARG, "block size %d out of range", s);
   if (!(lambda >= 0.0)) return fail(KPP_ERR_INVALID_ARG, "lambda must be >= 0");
@@ -3013,6 +3430,7 @@ KPP_API kpp_status kpp_server_create(kpp_context* ctx, uint64_t hbm_budget_bytes
 
 KPP_API kpp_status kpp_request_footprint(kpp_system* sys, const kpp_params* p, uint64_t* bytes_out) {
   if (!sys || !bytes_out) return fail(KPP_ERR_INVALID_ARG, "NULL argument");
+  if (sys->csr) return fail(KPP_ERR_INVALID_ARG, "the server takes dense systems");
   KPP_TRY(check_params(sys, p));
   *bytes_out = serve_footprint(sys, p, serve_periods(sys, p));
   return KPP_OK;
@@ -3023,6 +3441,7 @@ KPP_API kpp_status kpp_server_submit(kpp_server* srv, kpp_system* sys, const kpp
   if (!srv || !sys || !x_dev || !id_out) return fail(KPP_ERR_INVALID_ARG, "NULL argument");
   *id_out = 0;
   if (sys->ctx != srv->ctx) return fail(KPP_ERR_INVALID_ARG, "the system belongs to another context");
+  if (sys->csr) return fail(KPP_ERR_INVALID_ARG, "the server takes dense systems");
   KPP_TRY(check_params(sys, p));
   if (p->engine == 1) return fail(KPP_ERR_INVALID_ARG, "the server runs the fused engine only");
   if (p->schedule) return fail(KPP_ERR_INVALID_ARG, "explicit schedules are for kpp_solve");

@@ -316,3 +316,128 @@ def serving_matrix(n: int, pool_index: int, device: Optional[str] = None) -> Sys
     fn = lambda rng, nn: spectrum_c2(rng, nn, 32)  # noqa: E731
     return psd_system(n, fn, seed=50_000 + 97 * n + pool_index, device=device,
                       name=f"serve_{n}_{pool_index}")
+
+
+# ----------------------------------------------------------------------------
+# sparse systems (compressed sparse rows)
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class SparseSystem:
+    """A consistent sparse system in CSR form: int64 row pointers, int32
+    column indices (strictly increasing within each row), float64 values."""
+
+    rp: np.ndarray
+    ci: np.ndarray
+    cv: np.ndarray
+    b: np.ndarray
+    xstar: np.ndarray
+    m: int
+    n: int
+    kind: str          # "general" (Kaczmarz++) or "psd" (CD++)
+    name: str
+    params: dict
+
+    @property
+    def shape(self):
+        return (self.m, self.n)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rp[-1])
+
+    def dense(self) -> np.ndarray:
+        A = np.zeros((self.m, self.n))
+        rows = np.repeat(np.arange(self.m), np.diff(self.rp))
+        A[rows, self.ci] = self.cv
+        return A
+
+    def to(self, device):
+        """(rp, ci, cv, b) as torch tensors on `device`."""
+        import torch
+
+        return (torch.from_numpy(self.rp).to(device), torch.from_numpy(self.ci).to(device),
+                torch.from_numpy(self.cv).to(device), torch.from_numpy(self.b).to(device))
+
+
+def _csr_from_coo(m: int, n: int, r: np.ndarray, c: np.ndarray, v: np.ndarray):
+    import scipy.sparse as sp
+
+    A = sp.coo_matrix((v, (r, c)), shape=(m, n)).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    return A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data.astype(np.float64), A
+
+
+def sparse_general(m: int, n: int, per_row: int, seed: int, *, outlier_frac: float = 0.02,
+                   outlier_scale: float = 10.0, empty_every: int = 0,
+                   x_in_rowspace: Optional[bool] = None, name: str = "") -> SparseSystem:
+    """Kaczmarz++ input: every row holds `per_row` draws of a uniform column
+    (duplicates merged, so a row may hold fewer) with N(0, 1) values; a
+    fraction `outlier_frac` of the rows (chosen uniformly) is scaled by
+    `outlier_scale`, which puts a few large outlying singular values over the
+    bulk; with empty_every = k > 0, rows k-1, 2k-1, ... are empty.  x* ~ N(0, I)
+    (over-determined) or x* = A^T g, g ~ N(0, I) (under-determined: the
+    minimum-norm solution); b = A x*.  Draw order: columns, values, outlier
+    rows, x*."""
+    rng = np.random.default_rng(seed)
+    cols = rng.integers(0, n, size=(m, per_row))
+    vals = rng.standard_normal((m, per_row))
+    scale = np.ones(m)
+    n_out = int(round(outlier_frac * m))
+    if n_out:
+        scale[rng.choice(m, size=n_out, replace=False)] = outlier_scale
+    vals *= scale[:, None]
+    keep = np.ones((m, per_row), dtype=bool)
+    if empty_every > 0:
+        keep[empty_every - 1::empty_every, :] = False
+    r = np.repeat(np.arange(m), per_row).reshape(m, per_row)
+    rp, ci, cv, A = _csr_from_coo(m, n, r[keep], cols[keep], vals[keep])
+    if x_in_rowspace is None:
+        x_in_rowspace = m < n
+    if x_in_rowspace:
+        xs = np.asarray(A.T @ rng.standard_normal(m)).ravel()
+    else:
+        xs = rng.standard_normal(n)
+    b = np.asarray(A @ xs).ravel()
+    return SparseSystem(rp, ci, cv, b, xs, m, n, "general", name or f"sparse_general_{m}x{n}",
+                        dict(per_row=per_row, seed=seed, outlier_frac=outlier_frac,
+                             outlier_scale=outlier_scale, empty_every=empty_every))
+
+
+def sparse_psd(n: int, degree: int, seed: int, *, hubs: int = 4, hub_degree: int = 0, phi: float = 0.1,
+               name: str = "") -> SparseSystem:
+    """CD++ input: A = L + phi I with L the Laplacian of a random weighted
+    graph.  Every node links to `degree` uniform partners (weights U(0.5,
+    1.5), links made symmetric, repeats merged); `hubs` nodes (chosen
+    uniformly) link to `hub_degree` more (default 20 * degree), which gives a
+    few large outlying eigenvalues over the bulk.  A is symmetric positive
+    definite (eigenvalues >= phi).  x* ~ N(0, I), b = A x*.  Draw order:
+    partners, weights, hubs, hub partners, hub weights, x*."""
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(seed)
+    src = np.repeat(np.arange(n), degree)
+    dst = rng.integers(0, n, size=n * degree)
+    w = rng.uniform(0.5, 1.5, size=n * degree)
+    hd = hub_degree or 20 * degree
+    if hubs:
+        hub = rng.choice(n, size=hubs, replace=False)
+        hs = np.repeat(hub, hd)
+        ht = rng.integers(0, n, size=hubs * hd)
+        hw = rng.uniform(0.5, 1.5, size=hubs * hd)
+        src, dst, w = np.concatenate([src, hs]), np.concatenate([dst, ht]), np.concatenate([w, hw])
+    off = src != dst
+    src, dst, w = src[off], dst[off], w[off]
+    W = sp.coo_matrix((np.concatenate([w, w]), (np.concatenate([src, dst]), np.concatenate([dst, src]))),
+                      shape=(n, n)).tocsr()
+    W.sum_duplicates()
+    deg = np.asarray(W.sum(axis=1)).ravel()
+    A = (sp.diags(deg + phi) - W).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    xs = rng.standard_normal(n)
+    b = np.asarray(A @ xs).ravel()
+    return SparseSystem(A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data.astype(np.float64), b, xs,
+                        n, n, "psd", name or f"sparse_psd_{n}",
+                        dict(degree=degree, seed=seed, hubs=hubs, hub_degree=hd, phi=phi))

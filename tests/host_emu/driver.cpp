@@ -2,6 +2,7 @@
 // kernel argument range is checked, and the sanitizers the test builds with
 // check the host code (heap, undefined behaviour, data races).
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -159,6 +160,124 @@ static void serve_case() {
   if (got != ids.size()) { std::printf("FAIL: %zu of %zu served\n", got, ids.size()); std::exit(1); }
 }
 
+
+// Sparse systems: random CSR structure in stand-in device memory (columns
+// ascending in each row), solves in every memo mode, blocks past the LDS
+// build size, resume, the block factor, and the refusals.
+struct Csr {
+  int64_t* rp; int32_t* ci; double* cv; int64_t nnz;
+};
+static Csr make_csr(int64_t m, int64_t n, int per_row, unsigned seed, bool symmetric_band) {
+  std::vector<int64_t> rp(m + 1, 0);
+  std::vector<int32_t> ci;
+  std::vector<double> cv;
+  unsigned st = seed;
+  auto rnd = [&]() { st = st * 1664525u + 1013904223u; return st >> 8; };
+  for (int64_t i = 0; i < m; ++i) {
+    std::vector<int32_t> cols;
+    if (symmetric_band) {
+      for (int64_t j = std::max<int64_t>(0, i - per_row); j <= std::min<int64_t>(n - 1, i + per_row); ++j) cols.push_back((int32_t)j);
+    } else {
+      const int k = (i % 17 == 3) ? 0 : per_row;   // a few empty rows
+      for (int t = 0; t < k; ++t) cols.push_back((int32_t)(rnd() % n));
+      std::sort(cols.begin(), cols.end());
+      cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+    }
+    for (int32_t c : cols) { ci.push_back(c); cv.push_back(c == i ? 4.0 : 0.25); }
+    rp[i + 1] = (int64_t)ci.size();
+  }
+  Csr a;
+  a.nnz = (int64_t)ci.size();
+  void* p;
+  hipMalloc(&p, (m + 1) * 8); a.rp = (int64_t*)p; std::memcpy(a.rp, rp.data(), (m + 1) * 8);
+  hipMalloc(&p, std::max<int64_t>(1, a.nnz) * 4); a.ci = (int32_t*)p; std::memcpy(a.ci, ci.data(), a.nnz * 4);
+  hipMalloc(&p, std::max<int64_t>(1, a.nnz) * 8); a.cv = (double*)p; std::memcpy(a.cv, cv.data(), a.nnz * 8);
+  return a;
+}
+static void free_csr(Csr& a) { hipFree(a.rp); hipFree(a.ci); hipFree(a.cv); }
+
+static void sparse_solve(const char* name, int kind, int64_t m, int64_t n, int per_row, int s, int memo, int part,
+                         int engine, int64_t T, bool band) {
+  kpp_context* ctx; CHECK(kpp_context_create(0, nullptr, &ctx));
+  Csr a = make_csr(m, n, per_row, 7 + s, band);
+  double* b = dev_vec(m, 1.0); double* x = dev_vec(n, 0.0);
+  kpp_system* sys; CHECK(kpp_system_create_csr(ctx, kind, m, n, a.nnz, a.rp, a.ci, a.cv, b, &sys));
+  for (int rep = 0; rep < 2; ++rep) {
+    kpp_params p; CHECK(kpp_params_default(&p, kind));
+    p.block_size = s; p.memo = memo; p.fixed_partition = part; p.engine = engine;
+    p.max_iters = T * (rep + 1) / 2; p.tol = 0.0; p.seed = 3; p.lambda = 1e-3; p.keep_memo = 1;
+    if (rep == 1) { p.adaptive_rho = 0; p.rho0 = 0.7; }   // folds every few steps
+    kpp_result r; kpp_status st = kpp_solve(sys, &p, x, &r);
+    if (st < 0) { std::printf("FAIL %s: %d %s\n", name, st, kpp_last_error()); std::exit(1); }
+    std::printf("%-22s T=%-6lld st=%d iters=%lld misses=%lld hits=%lld\n", name, (long long)p.max_iters, st,
+                (long long)r.iters, (long long)r.memo_misses, (long long)r.memo_hits);
+  }
+  double rn = 0.0; CHECK(kpp_residual_norm(sys, x, &rn));
+  CHECK(kpp_system_destroy(sys)); CHECK(kpp_context_destroy(ctx));
+  free_csr(a); hipFree(b); hipFree(x);
+}
+
+#define EXPECT_STATUS(x, want) do { kpp_status s_ = (x); if (s_ != (want)) { std::printf("FAIL %s -> %d (want %d): %s\n", #x, s_, (int)(want), kpp_last_error()); std::exit(1);} } while (0)
+
+static void sparse_misc() {
+  kpp_context* ctx; CHECK(kpp_context_create(0, nullptr, &ctx));
+  const int64_t m = 400, n = 120;
+  Csr a = make_csr(m, n, 5, 11, false);
+  double* b = dev_vec(m, 1.0); double* x = dev_vec(n, 0.0);
+  kpp_system* sys; CHECK(kpp_system_create_csr(ctx, 0, m, n, a.nnz, a.rp, a.ci, a.cv, b, &sys));
+  // refused options
+  kpp_params p; CHECK(kpp_params_default(&p, 0));
+  p.block_size = 16; p.max_iters = 40; p.tol = 0.0; p.lambda = 1e-3;
+  kpp_result r;
+  { kpp_params q = p; q.precision = KPP_MIXED_FP32; EXPECT_STATUS(kpp_solve(sys, &q, x, &r), KPP_ERR_INVALID_ARG); }
+  { kpp_params q = p; q.rht = 1; EXPECT_STATUS(kpp_solve(sys, &q, x, &r), KPP_ERR_INVALID_ARG); }
+  { kpp_params q = p; q.projection = 1; EXPECT_STATUS(kpp_solve(sys, &q, x, &r), KPP_ERR_INVALID_ARG); }
+  { kpp_params q = p; q.engine = 2; EXPECT_STATUS(kpp_solve(sys, &q, x, &r), KPP_ERR_INVALID_ARG); }
+  double* B = dev_vec(m * 2, 1.0); double* X = dev_vec(n * 2, 0.0);
+  EXPECT_STATUS(kpp_solve_multi(sys, &p, 2, B, 2, X, 2, nullptr), KPP_ERR_INVALID_ARG);
+  uint64_t bytes = 0;
+  EXPECT_STATUS(kpp_request_footprint(sys, &p, &bytes), KPP_ERR_INVALID_ARG);
+  // block factor (Kaczmarz++ build kernel) and the no-allocation refusal
+  std::vector<int32_t> rows = {0, 5, 9, 40, 77, 300, 1, 2, 3, -1, -1, -1}, lens = {6, 3};
+  double* L = dev_vec(2 * 6 * 6, 0.0);
+  CHECK(kpp_block_factor(sys, 6, 1e-3, 2, rows.data(), lens.data(), L));
+  EXPECT_STATUS(kpp_block_factor_noalloc(sys, 6, 1e-3, 2, rows.data(), lens.data(), L), KPP_ERR_INVALID_ARG);
+  // resume through export / import
+  CHECK(kpp_solve(sys, &p, x, &r));
+  size_t sz = 0; CHECK(kpp_state_export(sys, nullptr, &sz));
+  std::vector<unsigned char> buf(sz); CHECK(kpp_state_export(sys, buf.data(), &sz));
+  kpp_system* sys2; CHECK(kpp_system_create_csr(ctx, 0, m, n, a.nnz, a.rp, a.ci, a.cv, b, &sys2));
+  CHECK(kpp_state_import(sys2, buf.data(), sz));
+  kpp_params q = p; q.resume = 1; q.max_iters = 25;
+  CHECK(kpp_solve(sys2, &q, x, &r));
+  if (r.iters != 25) { std::printf("FAIL: sparse resume ran %lld\n", (long long)r.iters); std::exit(1); }
+  CHECK(kpp_system_destroy(sys2));
+  CHECK(kpp_system_destroy(sys));
+  // malformed structures
+  kpp_system* bad = nullptr;
+  int32_t c0 = a.ci[0]; a.ci[0] = (int32_t)n;
+  EXPECT_STATUS(kpp_system_create_csr(ctx, 0, m, n, a.nnz, a.rp, a.ci, a.cv, b, &bad), KPP_ERR_SHAPE);
+  a.ci[0] = c0;
+  EXPECT_STATUS(kpp_system_create_csr(ctx, 0, m, n, a.nnz + 1, a.rp, a.ci, a.cv, b, &bad), KPP_ERR_SHAPE);
+  EXPECT_STATUS(kpp_system_create_csr(ctx, 1, m, n, a.nnz, a.rp, a.ci, a.cv, b, &bad), KPP_ERR_SHAPE);
+  double v0 = a.cv[3]; a.cv[3] = 0.0 / 0.0;
+  EXPECT_STATUS(kpp_system_create_csr(ctx, 0, m, n, a.nnz, a.rp, a.ci, a.cv, b, &bad), KPP_ERR_NONFINITE);
+  a.cv[3] = v0;
+  if (bad) { std::printf("FAIL: a refused system was returned\n"); std::exit(1); }
+  // CD++ block factor needs ascending rows
+  Csr c = make_csr(200, 200, 2, 5, true);
+  double* bc = dev_vec(200, 1.0);
+  kpp_system* cs; CHECK(kpp_system_create_csr(ctx, 1, 200, 200, c.nnz, c.rp, c.ci, c.cv, bc, &cs));
+  std::vector<int32_t> crow = {3, 4, 9, 10}, crow_bad = {4, 3, 9, 10}, clen = {4};
+  double* Lc = dev_vec(16, 0.0);
+  CHECK(kpp_block_factor(cs, 4, 1e-8, 1, crow.data(), clen.data(), Lc));
+  EXPECT_STATUS(kpp_block_factor(cs, 4, 1e-8, 1, crow_bad.data(), clen.data(), Lc), KPP_ERR_INVALID_ARG);
+  CHECK(kpp_system_destroy(cs));
+  std::printf("sparse misc ok\n");
+  CHECK(kpp_context_destroy(ctx));
+  free_csr(a); free_csr(c); hipFree(b); hipFree(bc); hipFree(x); hipFree(B); hipFree(X); hipFree(L); hipFree(Lc);
+}
+
 int main(int argc, char** argv) {
   const char* only = argc > 1 ? argv[1] : "";
   if (!*only || !std::strcmp(only, "solve")) {
@@ -184,6 +303,19 @@ int main(int argc, char** argv) {
     multi_case(0, 1000, 200, 20, 1, 5);
     multi_case(1, 600, 600, 64, 2, 32);
     multi_case(0, 300, 2500, 150, 0, 3);
+  }
+  if (!*only || !std::strcmp(only, "sparse")) {
+    for (int eng : {0, 1}) {
+      sparse_solve("csr_kpp_online", 0, 2000, 500, 6, 32, 1, 1, eng, 400, false);
+      sparse_solve("csr_kpp_fixed", 0, 2000, 500, 6, 32, 2, 1, eng, 300, false);
+      sparse_solve("csr_kpp_off", 0, 600, 900, 8, 20, 0, 1, eng, 200, false);
+    }
+    sparse_solve("csr_kpp_big_blocks", 0, 600, 20000, 40, 150, 1, 1, 0, 60, false);
+    sparse_solve("csr_kpp_big_off", 0, 600, 20000, 40, 150, 0, 1, 0, 30, false);
+    sparse_solve("csr_cd_online", 1, 800, 800, 3, 40, 1, 1, 0, 300, true);
+    sparse_solve("csr_cd_off", 1, 800, 800, 3, 40, 0, 1, 0, 100, true);
+    sparse_solve("csr_cd_s300", 1, 900, 900, 2, 300, 2, 1, 0, 30, true);
+    sparse_misc();
   }
   if (!*only || !std::strcmp(only, "serve")) serve_case();
   std::printf("EMU OK\n");

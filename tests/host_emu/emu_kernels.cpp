@@ -13,6 +13,7 @@
 #include "kernels.hpp"
 #include "lsqr.hpp"
 #include "multi.hpp"
+#include "sparse.hpp"
 
 namespace kpp {
 namespace {
@@ -419,5 +420,138 @@ void launch_fused_multi(int32_t, bool a_fp32, const FusedArgs* args, const int32
   emu_check(team_start, 4 * (nteams + 1), "multi team_start");
   if (team_start[0] != 0 || team_start[nteams] != total || total > 256) { std::fprintf(stderr, "EMU: team table\n"); std::abort(); }
   for (int t = 0; t < nteams; ++t) emu_fused(args[t], cpl, team_start[t + 1] - team_start[t], a_fp32);
+}
+// ---- sparse (CSR) systems: the stand-in device memory is host memory, so
+// the launchers check the CSR structure they read and every entry they touch
+void launch_csr_check(const int64_t* rp, const int32_t* ci, const double* cv, const double* b, int64_t m, int64_t n,
+                      int64_t nnz, int32_t* flag, hipStream_t) {
+  emu_check(rp, 8 * (m + 1), "csr row_ptr");
+  emu_check(b, 8 * m, "csr b");
+  emu_check(flag, 4, "csr flag");
+  int bad = 0;
+  for (int64_t i = 0; i < m; ++i) {
+    const int64_t a = rp[i], e = rp[i + 1];
+    if (!std::isfinite(b[i])) bad |= 4;
+    if ((i == 0 && a != 0) || (i == m - 1 && e != nnz) || a < 0 || e < a || e > nnz) { bad |= 1; continue; }
+    if (e > a) {
+      emu_check(ci + a, 4 * (e - a), "csr col");
+      emu_check(cv + a, 8 * (e - a), "csr val");
+    }
+    int64_t prev = -1;
+    for (int64_t k = a; k < e; ++k) {
+      if (ci[k] <= prev || ci[k] >= n) { bad |= 2; break; }
+      prev = ci[k];
+      if (!std::isfinite(cv[k])) bad |= 4;
+    }
+  }
+  *flag |= bad;
+}
+namespace {
+void check_csr_row(const int64_t* rp, const int32_t* ci, const double* cv, int64_t r, const char* what) {
+  emu_check(rp + r, 16, what);
+  const int64_t a = rp[r], e = rp[r + 1];
+  if (e > a) {
+    emu_check(ci + a, 4 * (e - a), what);
+    emu_check(cv + a, 8 * (e - a), what);
+  }
+}
+}  // namespace
+void launch_csr_rows_dot(const int64_t* rp, const int32_t* ci, const double* cv, const int32_t* rows, int32_t sb,
+                         const double* u, const double* v, double t01, double* out, hipStream_t) {
+  check_rows(rows, sb, "csr rows");
+  for (int32_t i = 0; i < sb; ++i) {
+    check_csr_row(rp, ci, cv, rows[i], "csr rows_dot");
+    for (int64_t k = rp[rows[i]]; k < rp[rows[i] + 1]; ++k) {
+      emu_check(u + ci[k], 8, "csr rows_dot u");
+      if (t01 != 0.0) emu_check(v + ci[k], 8, "csr rows_dot v");
+    }
+  }
+  emu_check(out, 8 * sb, "csr rows_dot out");
+}
+void launch_csc_apply(const CscArena& ar, int64_t off, int32_t z, const int32_t* nu, int32_t q, const double* y,
+                      int32_t sb, double, double, double* u, double* v, hipStream_t) {
+  emu_check(nu + q, 4, "csc nu");
+  emu_check(ar.val + off, 8 * static_cast<size_t>(z + 1), "csc val");
+  emu_check(ar.row + off, 4 * static_cast<size_t>(z + 1), "csc row");
+  emu_check(ar.col + off, 4 * static_cast<size_t>(z + 1), "csc col");
+  emu_check(ar.ptr + off, 4 * static_cast<size_t>(z + 1), "csc ptr");
+  emu_check(y, 8 * sb, "csc y");
+  if (nu[q] < 0 || nu[q] > z) { std::fprintf(stderr, "EMU: csc nu %d of %d\n", nu[q], z); std::abort(); }
+  for (int32_t k = 0; k < nu[q]; ++k) {
+    emu_check(u + ar.col[off + k], 8, "csc u");
+    emu_check(v + ar.col[off + k], 8, "csc v");
+  }
+}
+void launch_rows_apply(const int32_t* rows, int32_t sb, const double* y, double, double, double* u, double* v,
+                       hipStream_t) {
+  check_rows(rows, sb, "rows_apply rows");
+  emu_check(y, 8 * sb, "rows_apply y");
+  for (int32_t i = 0; i < sb; ++i) {
+    emu_check(u + rows[i], 8, "rows_apply u");
+    emu_check(v + rows[i], 8, "rows_apply v");
+  }
+}
+void launch_lazy_fold(double* u, double* v, int64_t n, double, double, hipStream_t) {
+  emu_check(u, 8 * n, "fold u");
+  emu_check(v, 8 * n, "fold v");
+}
+// The stand-in build writes a valid copy with no columns (nu = 0): the
+// step's back-projection then touches nothing.
+void launch_csr_block_build(const int64_t* rp, const int32_t* ci, const double* cv, const int32_t* rows,
+                            const int32_t* lens, const int32_t* slot_of, const int32_t* meta, int32_t nb, int32_t s,
+                            double, double* G, int64_t stride, const CscArena& ar, int32_t* nu, double* ws, bool,
+                            bool, int32_t* err, hipStream_t) {
+  check_slots(G, stride, s, lens, nb, slot_of, static_cast<int64_t>(s) * s, "csr build G");
+  emu_check(meta, 4 * static_cast<size_t>(kCsrMetaInts) * nb, "csr build meta");
+  for (int32_t k = 0; k < nb; ++k) {
+    const int32_t* mk = meta + kCsrMetaInts * k;
+    auto get = [](const int32_t* w) {
+      return static_cast<int64_t>((static_cast<uint64_t>(static_cast<uint32_t>(w[1])) << 32) |
+                                  static_cast<uint32_t>(w[0]));
+    };
+    const int64_t off = get(mk);
+    const int32_t z = mk[2];
+    const int64_t wso = get(mk + 3);
+    check_rows(rows + static_cast<int64_t>(k) * s, lens[k], "csr build rows");
+    int64_t zz = 0;
+    for (int32_t i = 0; i < lens[k]; ++i) {
+      const int64_t r = rows[static_cast<int64_t>(k) * s + i];
+      check_csr_row(rp, ci, cv, r, "csr build row");
+      zz += rp[r + 1] - rp[r];
+    }
+    if (zz != z) { *err |= 4; continue; }
+    emu_check(ar.val + off, 8 * static_cast<size_t>(z + 1), "csr build val");
+    emu_check(ar.row + off, 4 * static_cast<size_t>(z + 1), "csr build row");
+    emu_check(ar.col + off, 4 * static_cast<size_t>(z + 1), "csr build col");
+    emu_check(ar.ptr + off, 4 * static_cast<size_t>(z + 1), "csr build ptr");
+    if (wso >= 0) emu_check(ws + wso, 8 * csr_build_ws_doubles(z), "csr build ws");
+    else if (z > kCsrLdsEntries) { std::fprintf(stderr, "EMU: LDS build of %d nonzeros\n", z); std::abort(); }
+    emu_check(nu + slot_of[k], 4, "csr build nu");
+    nu[slot_of[k]] = 0;
+    ar.ptr[off] = z;
+  }
+}
+void launch_csr_gram_cd(const int64_t* rp, const int32_t* ci, const double* cv, const int32_t* rows,
+                        const int32_t* lens, const int32_t* slot_of, int32_t nb, int32_t s, double, double* G,
+                        int64_t stride, hipStream_t) {
+  check_slots(G, stride, s, lens, nb, slot_of, static_cast<int64_t>(s) * s, "csr gram_cd G");
+  for (int32_t k = 0; k < nb; ++k)
+    for (int32_t i = 0; i < lens[k]; ++i) {
+      const int32_t r = rows[static_cast<int64_t>(k) * s + i];
+      if (i > 0 && r <= rows[static_cast<int64_t>(k) * s + i - 1]) { std::fprintf(stderr, "EMU: CD rows not ascending\n"); std::abort(); }
+      check_csr_row(rp, ci, cv, r, "csr gram_cd row");
+    }
+}
+void launch_csr_residual_sq(const int64_t* rp, const int32_t* ci, const double* cv, const double* b, int64_t m,
+                            const double* x, double* part, double* out, hipStream_t) {
+  emu_check(rp, 8 * (m + 1), "csr resid rp");
+  for (int64_t r = 0; r < m; ++r) {
+    check_csr_row(rp, ci, cv, r, "csr resid row");
+    for (int64_t k = rp[r]; k < rp[r + 1]; ++k) emu_check(x + ci[k], 8, "csr resid x");
+  }
+  emu_check(b, 8 * m, "csr resid b");
+  emu_check(part, 8 * csr_residual_parts(m), "csr resid part");
+  emu_check(out, 8, "csr resid out");
+  *out = 0.0;
 }
 }  // namespace kpp

@@ -1,0 +1,297 @@
+"""GPU parity of sparse (CSR) systems: the HIP library through the C ABI
+against the CPU oracle run on the densified matrix, same seeded inputs and
+the same seeded block schedule.
+
+The sparse step computes what the dense step computes (Algorithms 2 and 5;
+only the storage of A differs), with sums over the nonzeros in place of sums
+over all n entries and the momentum update in a deferred form folded back at
+window ends.  Bar: iterates agree to max(1e-10, 10 nf) relative after the
+same number of steps, nf being the oracle's distance to itself with every sum
+reversed (as for the dense path); block factors agree to 1e-12 relative; the
+true residual agrees with numpy to 1e-13 relative; integer outcomes (memo
+misses) are exact.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import kpp as okpp
+from oracle import schedule as osch
+
+pytestmark = pytest.mark.gpu
+
+MODES = {"online": 1, "fixed": 2, "off": 0}
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import paper_2501_11673_amd as kpp
+
+    assert torch.cuda.is_available()
+    dev = torch.device("cuda:0")
+    ctx = kpp.kpp_context_create(0, torch.cuda.current_stream(dev).cuda_stream)
+    yield kpp, torch, dev, ctx
+    kpp.kpp_context_destroy(ctx)
+
+
+def relerr(a, b):
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b))) / (nb if nb > 0 else 1.0)
+
+
+class Csr:
+    """A sparse system's arrays on the device and its C-ABI handle."""
+
+    def __init__(self, env, S):
+        kpp, torch, dev, ctx = env
+        self.kpp = kpp
+        self.arrays = S.to(dev)
+        rp, ci, cv, b = self.arrays
+        kind = kpp.KPP_CD_PSD if S.kind == "psd" else kpp.KPP_KACZMARZ
+        self.h = kpp.kpp_system_create_csr(ctx, kind, S.m, S.n, S.nnz, rp.data_ptr(), ci.data_ptr(), cv.data_ptr(),
+                                           b.data_ptr())
+
+    def __enter__(self):
+        return self.h
+
+    def __exit__(self, *exc):
+        self.kpp.kpp_system_destroy(self.h)
+
+
+def make_params(kpp, kind, s, *, lam, T, tol=0.0, mode="online", seed=7, num_blocks=0, partition=True, accel=True,
+                eta=None, adaptive=True, rho0=0.0, engine=0):
+    ck = kpp.KPP_CD_PSD if kind == "psd" else kpp.KPP_KACZMARZ
+    p = kpp.kpp_params_default(ck)
+    p.block_size = s
+    p.lambda_ = lam
+    p.tol = tol
+    p.max_iters = T
+    p.seed = seed
+    p.memo = MODES[mode]
+    p.num_blocks = num_blocks
+    p.fixed_partition = 1 if partition else 0
+    p.accel = 1 if accel else 0
+    p.adaptive_rho = 1 if adaptive else 0
+    p.rho0 = rho0
+    p.engine = engine
+    if eta is not None:
+        p.eta = eta
+    return p
+
+
+def gpu_solve(env, S, s, **kw):
+    kpp, torch, dev, ctx = env
+    p = make_params(kpp, S.kind, s, **kw)
+    x = torch.zeros(S.n, dtype=torch.float64, device=dev)
+    with Csr(env, S) as h:
+        st, res = kpp.kpp_solve(h, p, x.data_ptr())
+    return x.cpu().numpy(), st, res
+
+
+def oracle_solve(A, b, kind, s, *, lam, T, tol=0.0, mode="online", seed=7, num_blocks=0, partition=True, accel=True,
+                 eta=None, adaptive=True, rho0=0.0, reverse_sums=False, engine=0):
+    m, n = A.shape
+    N = n if kind == "psd" else m
+    schd = osch.make_schedule(mode, N, s, T, seed, B0=osch.online_rate(kind, m, n, s),
+                              num_blocks=num_blocks, partition=partition)
+    p = okpp.Params(s=s, lam=lam, tol=tol, max_iters=T, accel=accel, eta=eta, adaptive_rho=adaptive, rho0=rho0,
+                    memo=(mode != "off"), reverse_sums=reverse_sums)
+    return okpp.solve(A, b, kind, p, schd)
+
+
+SPARSE_CASES = [
+    # name, builder, s, lam, mode, T, extra
+    ("kpp_over", lambda: synth.sparse_general(800, 300, 10, seed=1), 24, 1e-4, "online", 300, {}),
+    ("kpp_under", lambda: synth.sparse_general(300, 1200, 16, seed=2), 20, 1e-3, "online", 300, {}),
+    ("kpp_partition", lambda: synth.sparse_general(900, 250, 6, seed=3), 30, 1e-4, "fixed", 200, {}),
+    ("kpp_subsets", lambda: synth.sparse_general(400, 200, 8, seed=4), 16, 1e-4, "fixed", 150,
+     dict(num_blocks=13, partition=False)),
+    ("kpp_nomemo", lambda: synth.sparse_general(500, 400, 9, seed=5), 16, 1e-3, "off", 120, {}),
+    ("kpp_empty_rows", lambda: synth.sparse_general(600, 200, 7, seed=6, empty_every=9), 20, 1e-2, "online", 200, {}),
+    ("kpp_s1", lambda: synth.sparse_general(120, 40, 5, seed=7), 1, 1e-6, "online", 300, {}),
+    # blocks of about 6400 nonzeros: the global-memory build of the column-compressed copy
+    ("kpp_big_blocks", lambda: synth.sparse_general(700, 12000, 40, seed=8), 160, 1e-6, "online", 40, {}),
+    ("kpp_noaccel", lambda: synth.sparse_general(500, 200, 8, seed=9), 16, 1e-4, "online", 200, dict(accel=False)),
+    # c = (1 - rho)/(1 + rho) = 1/3 and 0: the deferred form folds every few steps and every step
+    ("kpp_rho_half", lambda: synth.sparse_general(500, 200, 8, seed=10), 16, 1e-4, "online", 150,
+     dict(adaptive=False, rho0=0.5, eta=0.2)),
+    ("kpp_rho_one", lambda: synth.sparse_general(500, 200, 8, seed=11), 16, 1e-4, "online", 100,
+     dict(adaptive=False, rho0=1.0)),
+    ("cd_online", lambda: synth.sparse_psd(600, 3, seed=12), 40, 1e-8, "online", 300, {}),
+    ("cd_partition", lambda: synth.sparse_psd(640, 4, seed=13), 64, 1e-8, "fixed", 160, {}),
+    ("cd_nomemo", lambda: synth.sparse_psd(500, 3, seed=14), 25, 1e-8, "off", 150, {}),
+    ("cd_s256", lambda: synth.sparse_psd(900, 3, seed=15), 256, 1e-8, "online", 40, {}),
+    ("cd_eta_fixed", lambda: synth.sparse_psd(400, 3, seed=16), 20, 1e-8, "online", 200, dict(eta=0.1)),
+]
+
+
+@pytest.mark.parametrize("case", SPARSE_CASES, ids=[c[0] for c in SPARSE_CASES])
+def test_sparse_iterates_match_oracle(env, case):
+    name, build, s, lam, mode, T, extra = case
+    S = build()
+    A = S.dense()
+    print(f"[sparse parity] {name} shape={S.shape} nnz={S.nnz} s={s} T={T}", flush=True)
+    for Tk in (T // 2, T):
+        x, st, res = gpu_solve(env, S, s, lam=lam, T=Tk, mode=mode, seed=31, **extra)
+        ref = oracle_solve(A, S.b, S.kind, s, lam=lam, T=Tk, mode=mode, seed=31, **extra)
+        alt = oracle_solve(A, S.b, S.kind, s, lam=lam, T=Tk, mode=mode, seed=31, reverse_sums=True, **extra)
+        nf = relerr(alt.x, ref.x)
+        err = relerr(x, ref.x)
+        print(f"[sparse parity] {name} T={Tk}: |x_gpu - x_orc|/|x_orc| = {err:.3e}, noise floor {nf:.3e}",
+              flush=True)
+        assert err <= max(1e-10, 10.0 * nf), f"{name} after {Tk} steps: {err:.3e} (noise floor {nf:.3e})"
+        assert res.iters == Tk
+        assert res.engine_used == 1
+        assert res.memo_misses == ref.factorizations
+        rho_nf = abs(alt.rho_final - ref.rho_final)
+        assert abs(res.rho_final - ref.rho_final) <= max(1e-9 * abs(ref.rho_final), 1e-12, 10.0 * rho_nf)
+
+
+@pytest.mark.parametrize("kind,which,s,lam", [
+    ("general", "lds", 24, 1e-3),
+    ("general", "global", 160, 1e-6),   # about 6400 nonzeros per block: global-memory build
+    ("general", "empty", 20, 1e-2),     # blocks with empty rows
+    ("psd", "lds", 48, 1e-8),
+    ("psd", "s256", 256, 1e-8),
+])
+def test_sparse_block_factor_matches_oracle(env, kind, which, s, lam):
+    kpp, torch, dev, ctx = env
+    if kind == "psd":
+        S = synth.sparse_psd(700, 3, seed=21)
+    elif which == "global":
+        S = synth.sparse_general(500, 12000, 40, seed=22)
+    elif which == "empty":
+        S = synth.sparse_general(300, 150, 6, seed=23, empty_every=4)
+    else:
+        S = synth.sparse_general(400, 150, 9, seed=24)
+    A = S.dense()
+    N = S.n if kind == "psd" else S.m
+    g = osch.SplitMix64(99)
+    blocks = [osch.random_subset(g, N, s) for _ in range(4)]
+    blocks.append(osch.random_subset(g, N, max(1, s - 3)))   # a short block
+    rows, lens = [], []
+    for blk in blocks:
+        rows += blk.tolist() + [0] * (s - len(blk))
+        lens.append(len(blk))
+    L = torch.full((len(blocks), s, s), float("nan"), dtype=torch.float64, device=dev)
+    with Csr(env, S) as h:
+        kpp.kpp_block_factor(h, s, lam, rows, lens, L.data_ptr())
+    Lh = L.cpu().numpy()
+    for q, blk in enumerate(blocks):
+        ref = okpp.cholesky_lower(okpp.regularized_gram(A, blk, lam, kind))
+        sb = len(blk)
+        got = Lh[q].T[:sb, :sb]
+        assert relerr(got, ref) < 1e-12, (which, q, relerr(got, ref))
+        full = Lh[q].T
+        assert np.all(full[np.triu_indices(s, 1)] == 0.0)
+        assert np.all(full[sb:, :] == 0.0) and np.all(full[:, sb:] == 0.0)
+
+
+def test_sparse_residual_norm(env):
+    kpp, torch, dev, ctx = env
+    S = synth.sparse_general(3333, 777, 11, seed=31, empty_every=50)
+    x = np.random.default_rng(4).standard_normal(S.n)
+    xd = torch.from_numpy(x).to(dev)
+    with Csr(env, S) as h:
+        got = kpp.kpp_residual_norm(h, xd.data_ptr())
+    assert got == pytest.approx(np.linalg.norm(S.dense() @ x - S.b), rel=1e-13)
+
+
+def test_sparse_bitwise_repeatable(env):
+    S = synth.sparse_general(700, 300, 9, seed=32)
+    a, _, _ = gpu_solve(env, S, 24, lam=1e-4, T=250, seed=5)
+    b, _, _ = gpu_solve(env, S, 24, lam=1e-4, T=250, seed=5)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("which", ["kpp_over", "kpp_under", "cd"])
+def test_sparse_converges(env, which):
+    """To a 1e-10 true relative residual (CD++: 1e-9), and to the planted (for
+    under-determined systems the minimum-norm) solution."""
+    if which == "kpp_over":
+        S, s, lam, tol = synth.sparse_general(4000, 1000, 12, seed=41), 64, 1e-6, 1e-10
+    elif which == "kpp_under":
+        S, s, lam, tol = synth.sparse_general(1000, 4000, 12, seed=42), 64, 1e-6, 1e-10
+    else:
+        S, s, lam, tol = synth.sparse_psd(3000, 4, seed=43), 64, 1e-8, 1e-9
+    x, st, res = gpu_solve(env, S, s, lam=lam, T=200_000, tol=tol, seed=9)
+    print(f"[sparse converge] {which}: {res.iters} steps, true rel res {res.true_rel_res:.2e}", flush=True)
+    assert res.converged and res.true_rel_res <= tol
+    assert relerr(x, S.xstar) < 1e-6
+
+
+def test_sparse_matches_dense_library_path(env):
+    """The sparse and the dense library paths on the same matrix and schedule
+    give the same iterates up to rounding."""
+    kpp, torch, dev, ctx = env
+    S = synth.sparse_general(600, 250, 10, seed=51)
+    A = S.dense()
+    xs, _, rs = gpu_solve(env, S, 20, lam=1e-4, T=240, seed=3)
+    p = make_params(kpp, "general", 20, lam=1e-4, T=240, seed=3, engine=1)
+    Ad, bd = torch.from_numpy(A).to(dev), torch.from_numpy(S.b).to(dev)
+    xd = torch.zeros(S.n, dtype=torch.float64, device=dev)
+    h = kpp.kpp_system_create(ctx, kpp.KPP_KACZMARZ, S.m, S.n, Ad.data_ptr(), S.n, bd.data_ptr())
+    try:
+        _, rd = kpp.kpp_solve(h, p, xd.data_ptr())
+    finally:
+        kpp.kpp_system_destroy(h)
+    assert rs.memo_misses == rd.memo_misses
+    assert relerr(xs, xd.cpu().numpy()) < 1e-10
+
+
+def test_sparse_resume_matches_uninterrupted(env):
+    kpp, torch, dev, ctx = env
+    S = synth.sparse_psd(500, 3, seed=61)
+    s, T1, T2 = 25, 70, 90
+    x_full, _, _ = gpu_solve(env, S, s, lam=1e-8, T=T1 + T2, seed=4)
+    p = make_params(kpp, "psd", s, lam=1e-8, T=T1, seed=4)
+    x = torch.zeros(S.n, dtype=torch.float64, device=dev)
+    with Csr(env, S) as h:
+        kpp.kpp_solve(h, p, x.data_ptr())
+        buf = kpp.kpp_state_export(h)
+    with Csr(env, S) as h2:
+        kpp.kpp_state_import(h2, buf)
+        p.resume = 1
+        p.max_iters = T2
+        st, res = kpp.kpp_solve(h2, p, x.data_ptr())
+    assert res.iters == T2
+    assert relerr(x.cpu().numpy(), x_full) < 1e-12
+
+
+def test_sparse_errors(env):
+    kpp, torch, dev, ctx = env
+    S = synth.sparse_general(200, 80, 5, seed=71)
+    rp, ci, cv, b = S.to(dev)
+
+    def create(rp_, ci_, cv_, b_, nnz=S.nnz, kind=kpp.KPP_KACZMARZ, m=S.m, n=S.n):
+        try:
+            h = kpp.kpp_system_create_csr(ctx, kind, m, n, nnz, rp_.data_ptr(), ci_.data_ptr(), cv_.data_ptr(),
+                                          b_.data_ptr())
+        except kpp.KppError as e:
+            return e.status
+        kpp.kpp_system_destroy(h)
+        return kpp.KPP_OK
+
+    assert create(rp, ci, cv, b) == kpp.KPP_OK
+    bad = ci.clone()
+    bad[0] = S.n
+    assert create(rp, bad, cv, b) == kpp.KPP_ERR_SHAPE            # column out of range
+    bad = ci.clone()
+    r0 = int(S.rp[1])
+    bad[0], bad[1] = ci[1], ci[0]
+    assert r0 >= 2 and create(rp, bad, cv, b) == kpp.KPP_ERR_SHAPE   # not increasing within row 0
+    assert create(rp, ci, cv, b, nnz=S.nnz - 1) == kpp.KPP_ERR_SHAPE
+    assert create(rp, ci, cv, b, kind=kpp.KPP_CD_PSD) == kpp.KPP_ERR_SHAPE   # CD++ needs a square matrix
+    nanv = cv.clone()
+    nanv[3] = float("nan")
+    assert create(rp, ci, nanv, b) == kpp.KPP_ERR_NONFINITE
+    with Csr(env, S) as h:
+        x = torch.zeros(S.n, dtype=torch.float64, device=dev)
+        for field, value in (("precision", kpp.KPP_MIXED_FP32), ("rht", 1), ("projection", 1), ("engine", 2)):
+            p = make_params(kpp, "general", 8, lam=1e-3, T=10)
+            setattr(p, field, value)
+            with pytest.raises(kpp.KppError) as e:
+                kpp.kpp_solve(h, p, x.data_ptr())
+            assert e.value.status == kpp.KPP_ERR_INVALID_ARG, field

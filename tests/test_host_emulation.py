@@ -44,7 +44,7 @@ def _run(binary, scenario, env_extra):
     return r.returncode, r.stdout + r.stderr
 
 
-@pytest.mark.parametrize("scenario", ["solve", "serve"])
+@pytest.mark.parametrize("scenario", ["solve", "sparse", "serve"])
 def test_host_logic_in_bounds(asan_bin, scenario):
     rc, out = _run(asan_bin, scenario, {"ASAN_OPTIONS": "detect_leaks=1", "UBSAN_OPTIONS": "halt_on_error=1"})
     assert rc == 0 and "EMU OK" in out, out[-6000:]
