@@ -14,6 +14,7 @@
 #include <cmath>
 
 #include "kernels.hpp"
+#include "step_state.hpp"
 #include "lsqr.hpp"
 #include "multi.hpp"
 
@@ -35,11 +36,6 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return r;
 }
 
-__device__ __forceinline__ double rho_from_rate(double rhat, int zeta) {
-  if (!(rhat < 1.0)) return 0.0;
-  double r = 1.0 - pow(rhat, 1.0 / static_cast<double>(zeta));
-  return fmin(1.0, fmax(0.0, r));
-}
 
 // --------------------------------------------------------------------------
 // r-partials: grid (P, sb); workgroup (p, i) sums columns [p*chunk, (p+1)*chunk)
@@ -62,42 +58,9 @@ __global__ __launch_bounds__(kT) void k_block_gemv_partial(
 // --------------------------------------------------------------------------
 // projection through the memoized inverse and checkpoint bookkeeping: one workgroup
 // --------------------------------------------------------------------------
-// One step's scalar bookkeeping (Algorithms 2 and 5): c for this step's
-// momentum, ||r||^2 into the window sums, and at a checkpoint the stop
-// candidate and the revision of rho (eq. (weighted)).
 __device__ void step_state(DevState* ds, double rr, int32_t zeta, int32_t adaptive) {
   DevState s = *ds;
-  const double rho = s.rho;
-  s.c = (1.0 - rho) / (1.0 + rho);
-  const int64_t period = 2 * static_cast<int64_t>(zeta);
-  const int64_t ph = s.t % period;
-  if (ph < zeta)
-    s.E0 += rr;
-  else
-    s.E1 += rr;
-  if (ph == period - 1) {
-    s.ckpts += 1;
-    s.last_E1 = s.E1;
-    s.rho_before = rho;
-    s.cand = (s.E1 <= s.thr) ? 1 : 0;
-    if (adaptive && s.E0 > 0.0) {
-      const double q = s.E1 / s.E0;
-      if (!s.have_rhat) {
-        s.rhat = q;
-        s.have_rhat = 1;
-      } else {
-        const double li = log(static_cast<double>(s.ckpt));
-        const double li1 = log(static_cast<double>(s.ckpt) + 1.0);
-        const double w = exp(li * li - li1 * li1);
-        s.rhat = w * s.rhat + (1.0 - w) * q;
-      }
-      s.ckpt += 1;
-      s.rho = rho_from_rate(s.rhat, zeta);
-    }
-    s.E0 = 0.0;
-    s.E1 = 0.0;
-  }
-  s.t += 1;
+  step_state_update(s, rr, zeta, adaptive);
   *ds = s;
 }
 

@@ -207,6 +207,15 @@ struct kpp_system {
   std::vector<int32_t> slot_csc_z;
   double* csr_ws[2] = {nullptr, nullptr};
   size_t csr_ws_cap[2] = {0, 0};
+  int32_t csr_G = 1;                 // team size of the sparse step kernel (column slices of x)
+  int32_t* csr_team = nullptr;       // per-slot team tables
+  int32_t csr_team_cap = 0, csr_team_s = 0;
+  double* csr_xr = nullptr;          // team exchange: r partials [2][G][s] and y [2][s]
+  double* csr_xy = nullptr;
+  // per-step coefficients of the deferred momentum form (pinned, device)
+  double* h_coef = nullptr;
+  double* d_coef = nullptr;
+  size_t coef_cap = 0;
 };
 
 namespace {
@@ -285,6 +294,14 @@ void destroy_buffers(kpp_system* s) {
   dev_free(s->csc.col);
   dev_free(s->csc.ptr);
   dev_free(s->csc_nu);
+  dev_free(s->csr_team);
+  dev_free(s->csr_xr);
+  dev_free(s->csr_xy);
+  s->csr_team_cap = s->csr_team_s = 0;
+  dev_free(s->d_coef);
+  if (s->h_coef) (void)hipHostFree(s->h_coef);
+  s->h_coef = nullptr;
+  s->coef_cap = 0;
   s->csc_cap = s->csc_top = s->csc_half = 0;
   s->csc_nu_cap = 0;
   for (int i = 0; i < 2; ++i) {
@@ -390,6 +407,30 @@ kpp_status ensure_gram_ws(kpp_system* sys, int idx, size_t doubles) {
   return KPP_OK;
 }
 
+// Sparse systems: the per-slot team tables for block size s (kept when the
+// table grows; a new block size drops them with the slots they belong to).
+kpp_status ensure_csr_team(kpp_system* sys, int32_t slots, int32_t s) {
+  if (sys->csr_team_s != s) {
+    dev_free(sys->csr_team);
+    sys->csr_team_cap = 0;
+    sys->csr_team_s = s;
+  }
+  if (slots <= sys->csr_team_cap) return KPP_OK;
+  const int32_t cap = std::max<int32_t>(slots, std::max<int32_t>(16, 2 * sys->csr_team_cap));
+  const size_t per = static_cast<size_t>(kpp::csr_team_stride(s, sys->csr_G));
+  int32_t* t = nullptr;
+  KPP_TRY(dev_alloc(&t, per * cap));
+  if (sys->csr_team_cap > 0) {
+    HIP_TRY(hipStreamSynchronize(sys->ctx->stream));
+    KPP_TRY(wait_side_work(sys));
+    HIP_TRY(hipMemcpy(t, sys->csr_team, per * sys->csr_team_cap * sizeof(int32_t), hipMemcpyDeviceToDevice));
+  }
+  dev_free(sys->csr_team);
+  sys->csr_team = t;
+  sys->csr_team_cap = cap;
+  return KPP_OK;
+}
+
 // Sparse systems: the per-slot column counts of the Kaczmarz++ blocks (kept
 // when the table grows).
 kpp_status ensure_csc_nu(kpp_system* sys, int32_t slots) {
@@ -456,6 +497,22 @@ kpp_status ensure_csr_ws(kpp_system* sys, int idx, size_t doubles) {
   return KPP_OK;
 }
 
+// Sparse systems: the per-step coefficient table (no launch reading the old
+// one is in flight: every window is waited for before the next is launched).
+kpp_status ensure_coef(kpp_system* sys, size_t doubles) {
+  if (doubles <= sys->coef_cap) return KPP_OK;
+  const size_t cap = std::max<size_t>(doubles, std::max<size_t>(3 * 1024, 2 * sys->coef_cap));
+  HIP_TRY(hipStreamSynchronize(sys->ctx->stream));
+  dev_free(sys->d_coef);
+  if (sys->h_coef) (void)hipHostFree(sys->h_coef);
+  sys->h_coef = nullptr;
+  sys->coef_cap = 0;
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&sys->h_coef), cap * sizeof(double), hipHostMallocDefault));
+  KPP_TRY(dev_alloc(&sys->d_coef, cap));
+  sys->coef_cap = cap;
+  return KPP_OK;
+}
+
 kpp_status check_params(const kpp_system* sys, const kpp_params* p) {
   if (!p) return fail(KPP_ERR_INVALID_ARG, "params is NULL");
   const int64_t rows = sys->kind == KPP_CD_PSD ? sys->n : sys->m;
@@ -480,7 +537,7 @@ kpp_status check_params(const kpp_system* sys, const kpp_params* p) {
     if (p->refine_max_rounds < 1) return fail(KPP_ERR_INVALID_ARG, "refine_max_rounds must be >= 1");
   }
   if (p->engine < 0 || p->engine > 2) return fail(KPP_ERR_INVALID_ARG, "unknown engine %d", p->engine);
-  if (p->engine == 2 && p->block_size > kpp::kFusedMaxBlock)
+  if (p->engine == 2 && p->block_size > kpp::kFusedMaxBlock && !sys->csr)
     return fail(KPP_ERR_INVALID_ARG, "the fused engine takes block_size <= %d", kpp::kFusedMaxBlock);
   if (p->team_groups < 0 || p->team_groups > kpp::kFusedMaxGroups)
     return fail(KPP_ERR_INVALID_ARG, "team_groups must be in [0, %d]", kpp::kFusedMaxGroups);
@@ -500,12 +557,12 @@ kpp_status check_params(const kpp_system* sys, const kpp_params* p) {
   }
   if (p->rht && p->resume) return fail(KPP_ERR_INVALID_ARG, "resume does not combine with rht");
   if (sys->csr) {
-    // the sparse step runs in FP64 on the launch-per-phase engine, without
-    // the Hadamard preprocessing (it would densify A) or the sketched projection
+    // the sparse step runs in FP64 (engine 1: a launch per phase; otherwise
+    // the team kernel), without the Hadamard preprocessing (it would
+    // densify A) or the sketched projection
     if (p->precision != KPP_FP64) return fail(KPP_ERR_INVALID_ARG, "a sparse system solves in FP64 only");
     if (p->rht) return fail(KPP_ERR_INVALID_ARG, "the Hadamard preprocessing does not apply to a sparse system");
     if (p->projection != 0) return fail(KPP_ERR_INVALID_ARG, "a sparse system takes the exact projection only");
-    if (p->engine == 2) return fail(KPP_ERR_INVALID_ARG, "a sparse system runs on the launch-per-phase engine");
   }
   if (p->schedule) {
     if (p->schedule_len < 0) return fail(KPP_ERR_INVALID_ARG, "schedule_len must be >= 0");
@@ -685,6 +742,7 @@ class CoreRun {
     eta_ = p->eta < 0.0 ? default_eta(kind_, m_, n_, s_) : p->eta;
     if (!p->accel) eta_ = 0.0;
     csr_ = sys->csr;
+    csr_window_ = csr_ && p->engine != 1;
     rho_now_ = o.rho0;
     mode_ = static_cast<kpp::MemoMode>(p->memo);
     max_iters_ = o.max_iters;
@@ -720,7 +778,7 @@ class CoreRun {
       if (!fused_) return fail(KPP_ERR_INVALID_ARG, "no fused geometry with %d columns per lane", force_cpl);
     } else {
       if (p->engine != 1 && !csr_) fused_ = fused_geometry(n_, s_, p->team_groups, fp32_, &cpl_, &groups_);
-      if (p->engine == 2 && !fused_)
+      if (p->engine == 2 && !fused_ && !csr_)
         return fail(KPP_ERR_INVALID_ARG, "n=%lld is too wide for the fused engine", (long long)n_);
     }
     // every workgroup of a team waits for the others each step, so the whole
@@ -778,6 +836,7 @@ class CoreRun {
       sys->csc_top = 0;
     }
     if (csr_ && kind_ == KPP_KACZMARZ) KPP_TRY(ensure_csc_nu(sys, sys->cap_slots));
+    if (csr_) KPP_TRY(ensure_csr_team(sys, sys->cap_slots, s_));
     // launch engine: column chunks of the block gemv
     P_ = csr_ ? 1 : static_cast<int32_t>((n_ + kChunk - 1) / kChunk);
     if (!fused_ && static_cast<int64_t>(s_) * P_ > sys->rpart_cap) {
@@ -800,7 +859,7 @@ class CoreRun {
     }
     HIP_TRY(hipGetLastError());
     const char* prof_env = std::getenv("KPP_PHASE_PROFILE");
-    phase_prof_ = fused_ && prof_env && prof_env[0] == '1';
+    phase_prof_ = (fused_ || csr_window_) && prof_env && prof_env[0] == '1';
     if (phase_prof_) {
       if (!sys->phase_ticks) KPP_TRY(dev_alloc(&sys->phase_ticks, kpp::kFusedPhases));
       HIP_TRY(hipMemsetAsync(sys->phase_ticks, 0, kpp::kFusedPhases * sizeof(uint64_t), st_));
@@ -950,45 +1009,116 @@ class CoreRun {
   // Sparse steps: block rows, projection, back-projection on the deferred
   // iterate u + t01 v and momentum t11 v (x_ and the momentum buffer hold u
   // and v).  rho, hence c, is fixed inside a window (its checkpoint is the
-  // window's last step and revises rho for the next one), so the host keeps
-  // (t01, t11).  u, v are folded back into x, m at the window's end and
-  // whenever 1 / t11 or t01 / t11 would pass kLazyBound: the deferred sums
-  // then stay within a factor kLazyBound of the terms they hold.
+  // window's last step and revises rho for the next one), so the host draws
+  // up (t01, au, av) for every step.  u, v are folded back into x, m at the
+  // window's end and before any step at which 1 / t11 or t01 / t11 would pass
+  // kLazyBound: the deferred sums then stay within a factor kLazyBound of the
+  // terms they hold.  The steps between folds run in one launch of the team
+  // kernel, or (engine 1) three launches per step.
   kpp_status launch_csr_steps() {
     Window& w = win_[cur_];
     kpp_system* sys = sys_;
     const size_t sd = static_cast<size_t>(sys->slot_stride);
     const double c = (1.0 - rho_now_) / (1.0 + rho_now_);
+    const int64_t W = w.W - w.done;
+    if (W <= 0) return KPP_OK;
+    KPP_TRY(ensure_coef(sys, static_cast<size_t>(3 * W)));
+    double* cf = sys->h_coef;
+    std::vector<int64_t> cut;              // sub-run boundaries (steps before which u, v are folded)
+    std::vector<double> fold_at;           // (t01, t11) of each fold
     double t01 = 0.0, t11 = 1.0;
-    auto fold = [&]() {
-      kpp::launch_lazy_fold(x_, sys->mom, n_, t01, t11, st_);
-      ++launches_;
-      ++csr_folds_;
-      t01 = 0.0;
-      t11 = 1.0;
-    };
-    for (int64_t k = w.done; k < w.W; ++k) {
-      if (t11 == 0.0 || 1.0 / t11 > kLazyBound || std::fabs(t01 / t11) > kLazyBound) fold();
-      const int32_t q = w.step_slot[k];
-      const int32_t sb = sch_->len(w.step_block[k]);
-      const int32_t* rows = sys->rows + static_cast<size_t>(q) * s_;
-      const int32_t z = sys->slot_csc_z[q];
-      kpp::launch_csr_rows_dot(sys->csr_rp, sys->csr_ci, sys->csr_cv, rows, sb, x_, sys->mom, t01, sys->rpart, st_);
-      kpp::launch_block_project(sys->rpart, 1, src_.b, rows, sb, sys->L + sd * q + static_cast<size_t>(s_) * s_, s_,
-                                sys->y, sys->ds, zeta_, prm_.adaptive_rho, st_);
-      const double au = 1.0 - t01 / t11, av = 1.0 / t11;
-      if (kind_ == KPP_KACZMARZ)
-        kpp::launch_csc_apply(sys->csc, sys->slot_csc_off[q], z, sys->csc_nu, q, sys->y, sb, au, av, x_, sys->mom,
-                              st_);
-      else
-        kpp::launch_rows_apply(rows, sb, sys->y, au, av, x_, sys->mom, st_);
+    for (int64_t k = 0; k < W; ++k) {
+      if (t11 == 0.0 || 1.0 / t11 > kLazyBound || std::fabs(t01 / t11) > kLazyBound) {
+        cut.push_back(k);
+        fold_at.push_back(t01);
+        fold_at.push_back(t11);
+        t01 = 0.0;
+        t11 = 1.0;
+      }
+      cf[3 * k] = t01;
+      cf[3 * k + 1] = 1.0 - t01 / t11;
+      cf[3 * k + 2] = 1.0 / t11;
+      const int32_t z = sys->slot_csc_z[w.step_slot[w.done + k]];
       csr_nnz_ += z;
       csr_gathers_ += (t01 != 0.0 ? 2.0 : 1.0) * z;
       t01 += eta_ * c * t11;
       t11 *= c;
     }
-    if (t01 != 0.0 || t11 != 1.0) fold();
-    launches_ += 3 * (w.W - w.done);
+    cut.push_back(W);
+    fold_at.push_back(t01);
+    fold_at.push_back(t11);
+    auto fold = [&](size_t i) {
+      const double f01 = fold_at[2 * i], f11 = fold_at[2 * i + 1];
+      if (f01 == 0.0 && f11 == 1.0) return;
+      kpp::launch_lazy_fold(x_, sys->mom, n_, f01, f11, st_);
+      ++launches_;
+      ++csr_folds_;
+    };
+    if (csr_window_) {
+      HIP_TRY(hipMemcpyAsync(sys->d_coef, cf, static_cast<size_t>(3 * W) * sizeof(double), hipMemcpyHostToDevice, st_));
+      if (sys->epoch > 0x3fffffffu) {
+        HIP_TRY(hipMemsetAsync(sys->flags, 0, kFlagWords * sizeof(uint32_t), st_));
+        sys->epoch = 0;
+      }
+      int64_t a0 = 0;
+      for (size_t i = 0; i < cut.size(); ++i) {
+        const int64_t a1 = cut[i];
+        if (a1 > a0) {
+          kpp::SparseTeamArgs a;
+          a.rp = sys->csr_rp;
+          a.ci = sys->csr_ci;
+          a.cv = sys->csr_cv;
+          a.b = src_.b;
+          a.rows = sys->rows;
+          a.L = sys->L;
+          a.slot_stride = sys->slot_stride;
+          a.team = sys->csr_team;
+          a.team_stride = kpp::csr_team_stride(s_, sys->csr_G);
+          a.step_info = sys->d_stage[cur_] + w.o_sinfo + static_cast<size_t>(kpp::kSparseStepInts) * (w.done + a0);
+          a.coef = sys->d_coef + 3 * a0;
+          a.ar = sys->csc;
+          a.u = x_;
+          a.v = sys->mom;
+          a.ds = sys->ds;
+          a.xr = sys->csr_xr;
+          a.xy = sys->csr_xy;
+          a.flags = sys->flags;
+          a.epoch = sys->epoch;
+          a.spin_limit = int64_t{1} << 22;
+          a.err = sys->err;
+          a.s = s_;
+          a.W = static_cast<int32_t>(a1 - a0);
+          a.zeta = zeta_;
+          a.adaptive = prm_.adaptive_rho;
+          a.G = sys->csr_G;
+          a.phase_ticks = phase_prof_ ? sys->phase_ticks : nullptr;
+          kpp::launch_sparse_team(kind_, a, st_);
+          sys->epoch += static_cast<uint32_t>(a1 - a0);
+          ++launches_;
+        }
+        fold(i);
+        a0 = a1;
+      }
+    } else {
+      size_t ci = 0;
+      for (int64_t k = 0; k < W; ++k) {
+        if (k == cut[ci]) fold(ci++);
+        const int32_t q = w.step_slot[w.done + k];
+        const int32_t sb = sch_->len(w.step_block[w.done + k]);
+        const int32_t* rows = sys->rows + static_cast<size_t>(q) * s_;
+        kpp::launch_csr_rows_dot(sys->csr_rp, sys->csr_ci, sys->csr_cv, rows, sb, x_, sys->mom, cf[3 * k], sys->rpart,
+                                 st_);
+        kpp::launch_block_project(sys->rpart, 1, src_.b, rows, sb, sys->L + sd * q + static_cast<size_t>(s_) * s_, s_,
+                                  sys->y, sys->ds, zeta_, prm_.adaptive_rho, st_);
+        if (kind_ == KPP_KACZMARZ)
+          kpp::launch_csc_apply(sys->csc, sys->slot_csc_off[q], sys->slot_csc_z[q], sys->csc_nu, q, sys->y, sb,
+                                cf[3 * k + 1], cf[3 * k + 2], x_, sys->mom, st_);
+        else
+          kpp::launch_rows_apply(rows, sb, sys->y, cf[3 * k + 1], cf[3 * k + 2], x_, sys->mom, st_);
+      }
+      fold(cut.size() - 1);
+      launches_ += 3 * W;
+    }
     HIP_TRY(hipGetLastError());
     return KPP_OK;
   }
@@ -1124,9 +1254,11 @@ class CoreRun {
       HIP_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, sys_->ctx->device));
       static const char* names[kpp::kFusedPhases] = {"rows", "tile-dot", "publish", "wait", "reduce-r",
                                                      "solve+scalars", "update", "-"};
+      static const char* sparse_names[kpp::kFusedPhases] = {"slice-rows", "publish+r-wait", "reduce-r", "y-rows",
+                                                            "publish+y-wait", "read-y", "back-projection", "-"};
       std::fprintf(stderr, "[kpp phase profile] %lld steps, workgroup 0, us per step:", static_cast<long long>(t_));
       for (int ph = 0; ph < kpp::kFusedPhases - 1; ++ph)
-        std::fprintf(stderr, " %s=%.3f", names[ph],
+        std::fprintf(stderr, " %s=%.3f", csr_ ? sparse_names[ph] : names[ph],
                      1e3 * static_cast<double>(ticks[ph]) / rate_khz / static_cast<double>(t_));
       std::fprintf(stderr, "\n");
     }
@@ -1139,7 +1271,7 @@ class CoreRun {
     cs->t_factor = t_factor_;
     cs->t_kernel = t_kernel_;
     cs->hs = hs_;
-    cs->engine = fused_ ? 2 : 1;
+    cs->engine = (fused_ || csr_window_) ? 2 : 1;
     cs->groups = fused_ ? groups_ : 0;
     cs->cpl = fused_ ? cpl_ : 0;
     cs->dual = dual_;
@@ -1165,7 +1297,7 @@ class CoreRun {
     int64_t fp32_tried = 0;   // new blocks with an FP32 Gram attempt up to this window
     bool try32 = false;       // this window's new blocks try an FP32 Gram first
     bool on_side = false, waited = false;
-    size_t o_len = 0, o_slot = 0, o_step = 0, o_csc = 0;
+    size_t o_len = 0, o_slot = 0, o_step = 0, o_csc = 0, o_sinfo = 0;
     bool csr_lds = false, csr_global = false;   // sparse Kaczmarz++: build variants this window needs
     std::vector<int32_t> step_block, step_slot;
     std::vector<char> step_new;
@@ -1223,6 +1355,7 @@ class CoreRun {
       t_prof_slots += wall_now() - ts;
     }
     if (csr_ && kind_ == KPP_KACZMARZ) KPP_TRY(ensure_csc_nu(sys, sys->cap_slots));
+    if (csr_) KPP_TRY(ensure_csr_team(sys, sys->cap_slots, s));
     w.nb = static_cast<int32_t>(pending.size());
     w.try32 = fp32_ && !sys->fp32_gram_futile;
     if (w.try32) sys->fp32_tried += w.nb;
@@ -1231,7 +1364,8 @@ class CoreRun {
     w.o_slot = w.o_len + w.nb;
     w.o_step = w.o_slot + w.nb;
     w.o_csc = w.o_step + static_cast<size_t>(w.W) + static_cast<size_t>(w.nb);   // after the flags
-    const size_t need = w.o_csc + (csr_ ? static_cast<size_t>(kpp::kCsrMetaInts) * w.nb : 0);
+    w.o_sinfo = w.o_csc + (csr_ ? static_cast<size_t>(kpp::kCsrMetaInts) * w.nb : 0);
+    const size_t need = w.o_sinfo + (csr_ ? static_cast<size_t>(kpp::kSparseStepInts) * w.W : 0);
     const double tg = wall_now();
     KPP_TRY(ensure_stage(sys, idx, need));
     t_prof_grow += wall_now() - tg;
@@ -1245,7 +1379,18 @@ class CoreRun {
       stage[w.o_slot + k] = pending_slots[k];
     }
     std::copy(w.step_slot.begin(), w.step_slot.end(), stage + w.o_step);
-    if (csr_) KPP_TRY(plan_csr(w, pending, pending_slots));
+    if (csr_) {
+      KPP_TRY(plan_csr(w, pending, pending_slots));
+      // each step's slot, block length, nonzeros and place in the arena
+      for (int64_t k = 0; k < w.W; ++k) {
+        int32_t* in = stage + w.o_sinfo + static_cast<size_t>(kpp::kSparseStepInts) * k;
+        const int32_t q = w.step_slot[k];
+        in[0] = q;
+        in[1] = sch_->len(w.step_block[k]);
+        in[2] = sys->slot_csc_z[q];
+        kpp::csr_meta_put(in + 3, kind_ == KPP_KACZMARZ ? sys->slot_csc_off[q] : 0);
+      }
+    }
     if (lsqr_) {
       // the sketch rows of the new blocks, in step order
       auto& T = lsqr_T_host_[idx];
@@ -1392,7 +1537,8 @@ class CoreRun {
     kpp_system* sys = sys_;
     const int32_t s = s_;
     const int idx = w.idx;
-    const size_t need = csr_ ? w.o_csc + static_cast<size_t>(kpp::kCsrMetaInts) * w.nb : w.o_step + static_cast<size_t>(w.W);
+    const size_t need = csr_ ? w.o_sinfo + static_cast<size_t>(kpp::kSparseStepInts) * w.W
+                             : w.o_step + static_cast<size_t>(w.W);
     HIP_TRY(hipMemcpyAsync(sys->d_stage[idx], sys->h_stage[idx], need * sizeof(int32_t), hipMemcpyHostToDevice, fs));
     HIP_TRY(hipEventRecord(sys->ev_fact[idx][0], fs));
     if (w.nb > 0) {
@@ -1413,6 +1559,9 @@ class CoreRun {
         else
           kpp::launch_csr_gram_cd(sys->csr_rp, sys->csr_ci, sys->csr_cv, d_srows, d_slens, d_sslot, w.nb, s,
                                   prm_.lambda, sys->L, sys->slot_stride, fs);
+        kpp::launch_csr_team_tables(kind_, sys->csr_rp, sys->csr_ci, d_srows, d_slens, d_sslot,
+                                    sys->d_stage[idx] + w.o_csc, sys->csc, sys->csc_nu, w.nb, s, n_, sys->csr_G,
+                                    sys->csr_team, fs);
         if (s <= kpp::kFactorSmallMax) {
           kpp::launch_factor_small(sys->L, sys->slot_stride, s, d_slens, w.nb, d_sslot, 1, sys->err, fs);
         } else {
@@ -1548,6 +1697,7 @@ class CoreRun {
   std::vector<double> e1_hist_;
   // sparse systems
   bool csr_ = false;
+  bool csr_window_ = false;   // one launch of the team kernel per run of steps between folds
   double rho_now_ = 0.0;   // rho of the current window's steps
   double csr_nnz_ = 0.0, csr_gathers_ = 0.0, csr_miss_nnz_ = 0.0;
   int64_t csr_folds_ = 0;
@@ -3039,6 +3189,10 @@ KPP_API kpp_status kpp_system_create_csr(kpp_context* ctx, int32_t kind, int64_t
   sys->csr_ci = col_dev;
   sys->csr_cv = val_dev;
   sys->nnz = nnz;
+  // team of one workgroup per 256 columns, at most kSparseTeamMax
+  sys->csr_G = static_cast<int32_t>(std::min<int64_t>(kpp::kSparseTeamMax, std::max<int64_t>(1, (n + 255) / 256)));
+  KPP_TRY(dev_alloc(&sys->csr_xr, 2 * static_cast<size_t>(sys->csr_G) * kpp::kMaxBlock));
+  KPP_TRY(dev_alloc(&sys->csr_xy, 2 * static_cast<size_t>(kpp::kMaxBlock)));
   hipStream_t st = ctx->stream;
   kpp::launch_csr_check(row_ptr_dev, col_dev, val_dev, b_dev, m, n, nnz, sys->err, st);
   HIP_TRY(hipGetLastError());

@@ -10,7 +10,10 @@
 #include <cmath>
 
 #include "kernels.hpp"
+#include "exchange.hpp"
+#include "lanes.hpp"
 #include "sparse.hpp"
+#include "step_state.hpp"
 
 namespace kpp {
 namespace {
@@ -22,12 +25,6 @@ constexpr uint64_t kKeyMask = (uint64_t{1} << kKeyBits) - 1;
 constexpr int kRowsPerWave = 8;   // rows a wave sums in the true-residual kernel
 static_assert((kST / 64) * kRowsPerWave == kCsrResidRowsPerGroup, "residual partial layout");
 constexpr size_t kBuildLds = static_cast<size_t>(kCsrLdsEntries) * (3 * sizeof(double) + sizeof(int32_t));
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 __device__ __forceinline__ int64_t meta_i64(const int32_t* p) {
   return static_cast<int64_t>((static_cast<uint64_t>(static_cast<uint32_t>(p[1])) << 32) |
@@ -329,6 +326,407 @@ __global__ __launch_bounds__(kST) void k_csr_gram_cd(const int64_t* __restrict__
 }
 
 // --------------------------------------------------------------------------
+// a run of steps in one launch of a team
+// --------------------------------------------------------------------------
+// Phases of a step in workgroup g (layout and protocol in sparse.hpp):
+//   1. p_g[i] = A_i[slice] (u + t01 v)[slice]: one thread per block row over
+//      the slice's nonzeros of the row (a contiguous range: columns ascend);
+//      published, then the r round: r_i = sum_h p_h[i] - b_i, partials added
+//      in team order (the same values in every workgroup)
+//   2. the workgroup's rows of y = G^{-1} r (a wave per row, lanes over k,
+//      the lane sums added by a fixed butterfly); published, then the y round;
+//      workgroup 0 keeps the step's bookkeeping from ||r||^2
+//   3. back-projection on the slice: one thread per compressed column
+//      (Kaczmarz++) or block row (CD++) in the slice, u -= au w, v -= av w
+// The exchange buffers alternate between steps (epoch parity): a workgroup
+// can be at most one step ahead of the slowest (it needs every workgroup's y
+// of the current step to go on), so it never overwrites data still read.
+constexpr int kTT = kSparseTeamThreads;
+
+// What a thread loads ahead for one step (none of it depends on x): the
+// step's slot, length and arena offset; the thread's block row (row tid: its
+// start in the CSR arrays, its b entry and its slice's range, the first
+// kRowPre nonzeros);
+// G^{-1} entries of the workgroup's first rows of y (rows y0 + wave and
+// y0 + wave + 4, lanes over k < 128); and the thread's first compressed
+// column (Kaczmarz++: bounds, column, first nonzero) or block row in the slice
+// (CD++).
+constexpr int kRowPre = 2;
+struct TeamPre {
+  int32_t q, sb, z;
+  int64_t off;
+  int64_t base;
+  double bi;
+  int32_t j0, j1;
+  int32_t ci[kRowPre];
+  double cv[kRowPre];
+  double gi[4];
+  int32_t c0, c1;
+  int32_t p0, p1, col, crow;
+  double cval;
+};
+
+template <int KIND>
+__device__ __forceinline__ void team_pre_a(const SparseTeamArgs& a, int32_t k, TeamPre& n) {
+  const int32_t* in = a.step_info + kSparseStepInts * k;
+  n.q = in[0];
+  n.sb = in[1];
+  n.z = in[2];
+  n.off = meta_i64(in + 3);
+}
+
+// second level: the thread's row index (kept in base until the row pointer
+// arrives) and the slice's column (or row) bounds
+template <int KIND>
+__device__ __forceinline__ void team_pre_b(const SparseTeamArgs& a, int tid, int g, TeamPre& n) {
+  const int32_t* TT = a.team + static_cast<int64_t>(n.q) * a.team_stride;
+  const int T1 = a.G + 1;
+  n.base = tid < n.sb ? a.rows[static_cast<int64_t>(n.q) * a.s + tid] : -1;
+  n.c0 = TT[a.s * T1 + g];
+  n.c1 = TT[a.s * T1 + g + 1];
+}
+
+// third level: row start and slice range, G^{-1} rows, column bounds (or the
+// CD++ row of the slice)
+template <int KIND>
+__device__ __forceinline__ void team_pre_c(const SparseTeamArgs& a, int tid, int g, TeamPre& n) {
+  const int32_t* TT = a.team + static_cast<int64_t>(n.q) * a.team_stride;
+  const int T1 = a.G + 1;
+  if (n.base >= 0) {
+    const int64_t row = n.base;
+    n.base = a.rp[row];
+    n.bi = a.b[row];
+    n.j0 = TT[tid * T1 + g];
+    n.j1 = TT[tid * T1 + g + 1];
+  } else {
+    n.base = 0;
+    n.bi = 0.0;
+    n.j0 = n.j1 = 0;
+  }
+  const int lane = tid & 63, wv = tid >> 6;
+  const int y0 = (g * n.sb) / a.G, y1 = ((g + 1) * n.sb) / a.G;
+  const double* Gb = a.L + static_cast<int64_t>(n.q) * a.slot_stride + static_cast<int64_t>(a.s) * a.s;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int i = y0 + wv + 4 * t;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int kk = lane + 64 * u;
+      n.gi[2 * t + u] = (i < y1 && kk < n.sb) ? Gb[static_cast<int64_t>(i) * a.s + kk] : 0.0;
+    }
+  }
+  const int32_t c = n.c0 + tid;
+  n.p0 = n.p1 = n.col = 0;
+  if (c < n.c1) {
+    if (KIND == 0) {
+      n.p0 = a.ar.ptr[n.off + c];
+      n.p1 = a.ar.ptr[n.off + c + 1];
+      n.col = a.ar.col[n.off + c];
+    } else {
+      n.col = a.rows[static_cast<int64_t>(n.q) * a.s + c];
+    }
+  }
+}
+
+// fourth level: the row's first nonzeros in the slice and the column's first
+// nonzero
+template <int KIND>
+__device__ __forceinline__ void team_pre_d(const SparseTeamArgs& a, int tid, TeamPre& n) {
+#pragma unroll
+  for (int t = 0; t < kRowPre; ++t) {
+    n.ci[t] = 0;
+    n.cv[t] = 0.0;
+    if (n.j0 + t < n.j1) {
+      n.ci[t] = a.ci[n.base + n.j0 + t];
+      n.cv[t] = a.cv[n.base + n.j0 + t];
+    }
+  }
+  n.crow = 0;
+  n.cval = 0.0;
+  if (KIND == 0 && n.c0 + tid < n.c1) {
+    n.crow = a.ar.row[n.off + n.p0];
+    n.cval = a.ar.val[n.off + n.p0];
+  }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kTT) void k_sparse_team(SparseTeamArgs a) {
+  __shared__ double r[kMaxBlock];
+  __shared__ double y[kMaxBlock];
+  __shared__ double red[kTT / 64];
+  __shared__ DevState st;
+  __shared__ int abort_flag;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int g = blockIdx.x, G = a.G, s = a.s, T1 = G + 1;
+  if (tid == 0) {
+    abort_flag = 0;
+    if (g == 0) st = *a.ds;
+  }
+  // optional phase profile (workgroup 0, thread 0): ticks[p] accumulates the
+  // wall-clock time from mark p-1 to mark p
+  const bool prof = a.phase_ticks != nullptr && g == 0 && tid == 0;
+  uint64_t tick_last = 0, ticks[kFusedPhases];
+#pragma unroll
+  for (int p = 0; p < kFusedPhases; ++p) ticks[p] = 0;
+#define KPP_MARK(p)                   \
+  if (prof) {                         \
+    const uint64_t now_ = wall_clock64(); \
+    ticks[p] += now_ - tick_last;     \
+    tick_last = now_;                 \
+  }
+  TeamPre cur;
+  team_pre_a<KIND>(a, 0, cur);
+  team_pre_b<KIND>(a, tid, g, cur);
+  team_pre_c<KIND>(a, tid, g, cur);
+  team_pre_d<KIND>(a, tid, cur);
+  __syncthreads();
+  if (prof) tick_last = wall_clock64();
+  for (int32_t k = 0; k < a.W; ++k) {
+    const uint32_t ep = a.epoch + static_cast<uint32_t>(k) + 1u;
+    const int32_t q = cur.q, sb = cur.sb;
+    const int64_t off = cur.off;
+    const double t01 = a.coef[3 * k], au = a.coef[3 * k + 1], av = a.coef[3 * k + 2];
+    const int32_t* R = a.rows + static_cast<int64_t>(q) * s;
+    const int32_t* TT = a.team + static_cast<int64_t>(q) * a.team_stride;
+    double* Pb = a.xr + static_cast<size_t>(ep & 1u) * G * s;
+    double* Yb = a.xy + static_cast<size_t>(ep & 1u) * s;
+    const bool more = k + 1 < a.W;
+    TeamPre nx = cur;
+    if (more) team_pre_a<KIND>(a, k + 1, nx);
+    // 1. partial r over the slice: the thread's row (prefetched), then rows
+    //    past kTT (blocks of more than kTT rows)
+    if (tid < sb) {
+      double acc = 0.0;
+#pragma unroll
+      for (int t = 0; t < kRowPre; ++t) {
+        if (cur.j0 + t < cur.j1) {
+          const uint32_t c = static_cast<uint32_t>(cur.ci[t]);
+          acc = fma(cur.cv[t], t01 != 0.0 ? fma(t01, a.v[c], a.u[c]) : a.u[c], acc);
+        }
+      }
+      for (int64_t e = cur.base + cur.j0 + kRowPre; e < cur.base + cur.j1; ++e) {
+        const uint32_t c = static_cast<uint32_t>(a.ci[e]);
+        acc = fma(a.cv[e], t01 != 0.0 ? fma(t01, a.v[c], a.u[c]) : a.u[c], acc);
+      }
+      r[tid] = acc;
+    }
+    for (int i = tid + kTT; i < sb; i += kTT) {
+      const int64_t base = a.rp[R[i]];
+      double acc = 0.0;
+      for (int64_t e = base + TT[i * T1 + g]; e < base + TT[i * T1 + g + 1]; ++e) {
+        const uint32_t c = static_cast<uint32_t>(a.ci[e]);
+        acc = fma(a.cv[e], t01 != 0.0 ? fma(t01, a.v[c], a.u[c]) : a.u[c], acc);
+      }
+      r[i] = acc;
+    }
+    __syncthreads();
+    KPP_MARK(0)
+    if (wv == 0) {
+      for (int i = lane; i < sb; i += 64) st_coherent(&Pb[static_cast<size_t>(g) * s + i], r[i]);
+      if (lane == 0) st_flag_after_stores(&a.flags[g * kSparseFlagStride], ep);
+    }
+    if (more) team_pre_b<KIND>(a, tid, g, nx);
+    if (tid < G) {
+      int64_t spins = 0;
+      while (static_cast<int32_t>(ld_flag(&a.flags[tid * kSparseFlagStride]) - ep) < 0) {
+        if (++spins > a.spin_limit) {
+          atomicOr(a.err, 2);
+          abort_flag = 1;
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    KPP_MARK(1)
+    if (abort_flag) break;
+    // the team's partials of row i in one batch of loads, added in team order
+    for (int i = tid; i < sb; i += kTT) {
+      double pv[kSparseTeamMax];
+#pragma unroll
+      for (int h = 0; h < kSparseTeamMax; ++h) pv[h] = h < G ? ld_coherent(&Pb[static_cast<size_t>(h) * s + i]) : 0.0;
+      double acc = 0.0;
+#pragma unroll
+      for (int h = 0; h < kSparseTeamMax; ++h)
+        if (h < G) acc += pv[h];
+      r[i] = acc - (i == tid ? cur.bi : a.b[R[i]]);
+    }
+    __syncthreads();
+    KPP_MARK(2)
+    // 2. this workgroup's rows of y (the first two of each wave from the
+    //    prefetched entries)
+    const int y0 = (g * sb) / G, y1 = ((g + 1) * sb) / G;
+    const double* Gb = a.L + static_cast<int64_t>(q) * a.slot_stride + static_cast<int64_t>(s) * s;
+    {
+      // rows y0 + wv and y0 + wv + 4 from the prefetched entries, summed over
+      // the lanes together (one butterfly for the pair)
+      const int i0 = y0 + wv, i1 = i0 + kTT / 64;
+      double acc0 = 0.0, acc1 = 0.0;
+      const double r0 = lane < sb ? r[lane] : 0.0, r1 = lane + 64 < sb ? r[lane + 64] : 0.0;
+      acc0 = fma(cur.gi[1], r1, cur.gi[0] * r0);
+      acc1 = fma(cur.gi[3], r1, cur.gi[2] * r0);
+      for (int kk = lane + 128; kk < sb; kk += 64) {
+        if (i0 < y1) acc0 = fma(Gb[static_cast<int64_t>(i0) * s + kk], r[kk], acc0);
+        if (i1 < y1) acc1 = fma(Gb[static_cast<int64_t>(i1) * s + kk], r[kk], acc1);
+      }
+      double v = fold(acc0, acc1, 32, (lane & 32) != 0);
+#pragma unroll
+      for (int o = 16; o > 0; o >>= 1) v = fold(v, v, o, false);
+      if (lane == 0 && i0 < y1) y[i0] = v;
+      if (lane == 32 && i1 < y1) y[i1] = v;
+      for (int i = i1 + kTT / 64; i < y1; i += kTT / 64) {   // rows past two a wave
+        double acc = 0.0;
+        for (int kk = lane; kk < sb; kk += 64) acc = fma(Gb[static_cast<int64_t>(i) * s + kk], r[kk], acc);
+        acc = wave_sum(acc);
+        if (lane == 0) y[i] = acc;
+      }
+    }
+    if (g == 0) {
+      double rr = 0.0;
+      for (int i = tid; i < sb; i += kTT) rr = fma(r[i], r[i], rr);
+      rr = wave_sum(rr);
+      if (lane == 0) red[wv] = rr;
+    }
+    __syncthreads();
+    KPP_MARK(3)
+    if (wv == 0) {
+      for (int i = y0 + lane; i < y1; i += 64) st_coherent(&Yb[i], y[i]);
+      if (lane == 0) st_flag_after_stores(&a.flags[kYFlagOffset + g * kSparseFlagStride], ep);
+    }
+    if (g == 0 && tid == 0) {
+      double rr = 0.0;
+      for (int w = 0; w < kTT / 64; ++w) rr += red[w];
+      step_state_update(st, rr, a.zeta, a.adaptive);
+    }
+    if (more) team_pre_c<KIND>(a, tid, g, nx);
+    if (tid < G) {
+      int64_t spins = 0;
+      while (static_cast<int32_t>(ld_flag(&a.flags[kYFlagOffset + tid * kSparseFlagStride]) - ep) < 0) {
+        if (++spins > a.spin_limit) {
+          atomicOr(a.err, 2);
+          abort_flag = 1;
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    KPP_MARK(4)
+    if (abort_flag) break;
+    for (int i = tid; i < sb; i += kTT) y[i] = ld_coherent(&Yb[i]);
+    __syncthreads();
+    KPP_MARK(5)
+    // 3. back-projection on the slice (the thread's first column or row from
+    //    the prefetched entries)
+    if (KIND == 0) {
+      const int32_t* __restrict__ bptr = a.ar.ptr + off;
+      const int32_t* __restrict__ bcol = a.ar.col + off;
+      const int32_t* __restrict__ brow = a.ar.row + off;
+      const double* __restrict__ bval = a.ar.val + off;
+      if (cur.c0 + tid < cur.c1) {
+        double w = fma(cur.cval, y[cur.crow], 0.0);
+        for (int32_t p = cur.p0 + 1; p < cur.p1; ++p) w = fma(bval[p], y[brow[p]], w);
+        const uint32_t j = static_cast<uint32_t>(cur.col);
+        a.u[j] = fma(-au, w, a.u[j]);
+        a.v[j] = fma(-av, w, a.v[j]);
+      }
+      for (int32_t c = cur.c0 + tid + kTT; c < cur.c1; c += kTT) {
+        const int32_t p0 = bptr[c], p1 = bptr[c + 1];
+        double w = 0.0;
+        for (int32_t p = p0; p < p1; ++p) w = fma(bval[p], y[brow[p]], w);
+        const uint32_t j = static_cast<uint32_t>(bcol[c]);
+        a.u[j] = fma(-au, w, a.u[j]);
+        a.v[j] = fma(-av, w, a.v[j]);
+      }
+    } else {
+      if (cur.c0 + tid < cur.c1) {
+        const uint32_t j = static_cast<uint32_t>(cur.col);
+        const double yi = y[cur.c0 + tid];
+        a.u[j] = fma(-au, yi, a.u[j]);
+        a.v[j] = fma(-av, yi, a.v[j]);
+      }
+      for (int i = cur.c0 + tid + kTT; i < cur.c1; i += kTT) {
+        const uint32_t j = static_cast<uint32_t>(R[i]);
+        a.u[j] = fma(-au, y[i], a.u[j]);
+        a.v[j] = fma(-av, y[i], a.v[j]);
+      }
+    }
+    if (more) team_pre_d<KIND>(a, tid, nx);
+    __syncthreads();
+    KPP_MARK(6)
+    cur = nx;
+  }
+#undef KPP_MARK
+  if (prof) {
+#pragma unroll
+    for (int p = 0; p < kFusedPhases; ++p)
+      atomicAdd(reinterpret_cast<unsigned long long*>(&a.phase_ticks[p]), static_cast<unsigned long long>(ticks[p]));
+  }
+  if (g == 0 && tid == 0) *a.ds = st;
+}
+
+// Team tables of new blocks: one workgroup per block.  Row i's slice starts
+// by binary search of each slice's first column among the row's (ascending)
+// columns; the slice boundaries among the compressed columns (Kaczmarz++) or
+// the block rows (CD++, ascending) likewise.
+__global__ __launch_bounds__(kST) void k_csr_team_tables(int32_t kind, const int64_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ ci,
+                                                         const int32_t* __restrict__ rows,
+                                                         const int32_t* __restrict__ lens,
+                                                         const int32_t* __restrict__ slot_of,
+                                                         const int32_t* __restrict__ meta, CscArena ar,
+                                                         const int32_t* __restrict__ nu, int32_t s, int64_t n,
+                                                         int32_t G, int32_t* __restrict__ team) {
+  const int blk = blockIdx.x, tid = threadIdx.x;
+  const int sb = lens[blk];
+  const int32_t* R = rows + static_cast<int64_t>(blk) * s;
+  const int T1 = G + 1;
+  int32_t* TT = team + static_cast<int64_t>(slot_of[blk]) * csr_team_stride(s, G);
+  for (int e = tid; e < sb * T1; e += kST) {
+    const int i = e / T1, g = e - i * T1;
+    const int64_t a0 = rp[R[i]], a1 = rp[R[i] + 1];
+    int64_t lo = a0, hi = a1;   // first nonzero of row i with column >= the slice's first column
+    if (g == G) {
+      lo = a1;
+    } else if (g > 0) {
+      const int64_t c = csr_slice_lo(n, G, g);
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (ci[mid] < c)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+    }
+    TT[e] = static_cast<int32_t>(lo - a0);
+  }
+  for (int g = tid; g < T1; g += kST) {
+    int32_t lo = 0, hi;
+    const int64_t c = g == G ? n : csr_slice_lo(n, G, g);
+    if (kind == 0) {
+      const int64_t off = meta_i64(meta + static_cast<int64_t>(kCsrMetaInts) * blk);
+      const int32_t* col = ar.col + off;
+      hi = nu[slot_of[blk]];
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (col[mid] < c)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+    } else {
+      hi = sb;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (R[mid] < c)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+    }
+    TT[s * T1 + g] = lo;
+  }
+}
+
+// --------------------------------------------------------------------------
 // true residual ||A x - b||^2
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(kST) void k_csr_resid_part(const int64_t* __restrict__ rp,
@@ -428,6 +826,23 @@ void launch_csr_gram_cd(const int64_t* rp, const int32_t* ci, const double* cv, 
   if (nb <= 0) return;
   hipLaunchKernelGGL(k_csr_gram_cd, dim3(nb), dim3(kST), 0, st, rp, ci, cv, rows, lens, slot_of, s, lambda, G,
                      stride);
+}
+
+void launch_sparse_team(int32_t kind, const SparseTeamArgs& a, hipStream_t st) {
+  if (a.W <= 0) return;
+  if (kind == 0)
+    hipLaunchKernelGGL(k_sparse_team<0>, dim3(a.G), dim3(kTT), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_sparse_team<1>, dim3(a.G), dim3(kTT), 0, st, a);
+}
+
+void launch_csr_team_tables(int32_t kind, const int64_t* rp, const int32_t* ci, const int32_t* rows,
+                            const int32_t* lens, const int32_t* slot_of, const int32_t* meta, const CscArena& ar,
+                            const int32_t* nu, int32_t nb, int32_t s, int64_t n, int32_t G, int32_t* team,
+                            hipStream_t st) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_csr_team_tables, dim3(nb), dim3(kST), 0, st, kind, rp, ci, rows, lens, slot_of, meta, ar, nu,
+                     s, n, G, team);
 }
 
 void launch_csr_residual_sq(const int64_t* rp, const int32_t* ci, const double* cv, const double* b, int64_t m,

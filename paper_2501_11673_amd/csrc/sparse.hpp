@@ -24,6 +24,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "kernels.hpp"
+
 namespace kpp {
 
 // Column-compressed copies of the memoized Kaczmarz++ blocks, one arena.  A
@@ -99,6 +101,65 @@ void launch_csr_block_build(const int64_t* rp, const int32_t* ci, const double* 
 void launch_csr_gram_cd(const int64_t* rp, const int32_t* ci, const double* cv, const int32_t* rows,
                         const int32_t* lens, const int32_t* slot_of, int32_t nb, int32_t s, double lambda, double* G,
                         int64_t stride, hipStream_t st);
+
+// A run of sparse steps in one launch of a team of G workgroups
+// (kSparseTeamThreads threads each).  Workgroup g owns the column slice
+// [g n / G, (g + 1) n / G) of u and v.  Per step: partial r over the slice
+// (block rows from the CSR arrays, the slice's part of each row from the
+// block's team table), all-gather of the partials, the workgroup's rows of
+// y = G^{-1} r, all-gather of y, back-projection on the slice (Kaczmarz++:
+// the block's compressed columns in the slice; CD++: the block rows in the
+// slice).  Only the two all-gathers cross workgroups: no workgroup writes
+// another's slice.  coef holds (t01, au, av) of each step; step_info
+// kSparseStepInts words per step: slot, block length, nonzeros z, and
+// (Kaczmarz++) the arena offset as two words.  Workgroup 0 keeps the
+// DevState on chip and writes it back at the end.  Flags: r round at
+// flags[g * kSparseFlagStride], y round at flags[kYFlagOffset + g *
+// kSparseFlagStride], raised to epoch + k + 1 at step k; every wait is
+// bounded by spin_limit polls (then err |= 2 and the team leaves).
+constexpr int kSparseTeamThreads = 256;
+constexpr int kSparseTeamMax = 16;
+constexpr int kSparseStepInts = 5;
+constexpr int kSparseFlagStride = 32;
+// Team table of a slot (int32): row-relative start of each slice in each
+// block row, (s x (G + 1), row-major), then the slice boundaries among the
+// block's compressed columns (Kaczmarz++) or block rows (CD++) (G + 1).
+__host__ __device__ inline int64_t csr_team_stride(int32_t s, int32_t G) { return static_cast<int64_t>(s + 1) * (G + 1); }
+__host__ __device__ inline int64_t csr_slice_lo(int64_t n, int32_t G, int32_t g) { return (static_cast<int64_t>(g) * n) / G; }
+struct SparseTeamArgs {
+  const int64_t* rp = nullptr;
+  const int32_t* ci = nullptr;
+  const double* cv = nullptr;
+  const double* b = nullptr;
+  const int32_t* rows = nullptr;
+  const double* L = nullptr;   // memo slots (G^{-1} at +s*s)
+  int64_t slot_stride = 0;
+  const int32_t* team = nullptr;
+  int64_t team_stride = 0;
+  const int32_t* step_info = nullptr;
+  const double* coef = nullptr;
+  CscArena ar;
+  double* u = nullptr;
+  double* v = nullptr;
+  DevState* ds = nullptr;
+  double* xr = nullptr;   // r partials, [2][G][s]
+  double* xy = nullptr;   // y, [2][s]
+  uint32_t* flags = nullptr;
+  uint32_t epoch = 0;
+  int64_t spin_limit = 0;
+  int32_t* err = nullptr;
+  uint64_t* phase_ticks = nullptr;   // optional profile: workgroup 0's wall-clock ticks per phase
+  int32_t s = 0, W = 0, zeta = 0, adaptive = 0, G = 1;
+};
+void launch_sparse_team(int32_t kind, const SparseTeamArgs& a, hipStream_t st);
+
+// Team tables of nb new blocks (staged rows, lens, slot_of; Kaczmarz++: the
+// arena offsets in meta, after launch_csr_block_build) into team[slot *
+// csr_team_stride(s, G)].
+void launch_csr_team_tables(int32_t kind, const int64_t* rp, const int32_t* ci, const int32_t* rows,
+                            const int32_t* lens, const int32_t* slot_of, const int32_t* meta, const CscArena& ar,
+                            const int32_t* nu, int32_t nb, int32_t s, int64_t n, int32_t G, int32_t* team,
+                            hipStream_t st);
 
 // ||A x - b||^2 into *out (partial sums per workgroup in part, then one
 // workgroup adds them in order); part holds csr_residual_parts(m) doubles.

@@ -232,7 +232,7 @@ static void sparse_misc() {
   { kpp_params q = p; q.precision = KPP_MIXED_FP32; EXPECT_STATUS(kpp_solve(sys, &q, x, &r), KPP_ERR_INVALID_ARG); }
   { kpp_params q = p; q.rht = 1; EXPECT_STATUS(kpp_solve(sys, &q, x, &r), KPP_ERR_INVALID_ARG); }
   { kpp_params q = p; q.projection = 1; EXPECT_STATUS(kpp_solve(sys, &q, x, &r), KPP_ERR_INVALID_ARG); }
-  { kpp_params q = p; q.engine = 2; EXPECT_STATUS(kpp_solve(sys, &q, x, &r), KPP_ERR_INVALID_ARG); }
+  { kpp_params q = p; q.team_groups = 300; EXPECT_STATUS(kpp_solve(sys, &q, x, &r), KPP_ERR_INVALID_ARG); }
   double* B = dev_vec(m * 2, 1.0); double* X = dev_vec(n * 2, 0.0);
   EXPECT_STATUS(kpp_solve_multi(sys, &p, 2, B, 2, X, 2, nullptr), KPP_ERR_INVALID_ARG);
   uint64_t bytes = 0;
@@ -305,7 +305,7 @@ int main(int argc, char** argv) {
     multi_case(0, 300, 2500, 150, 0, 3);
   }
   if (!*only || !std::strcmp(only, "sparse")) {
-    for (int eng : {0, 1}) {
+    for (int eng : {0, 1, 2}) {
       sparse_solve("csr_kpp_online", 0, 2000, 500, 6, 32, 1, 1, eng, 400, false);
       sparse_solve("csr_kpp_fixed", 0, 2000, 500, 6, 32, 2, 1, eng, 300, false);
       sparse_solve("csr_kpp_off", 0, 600, 900, 8, 20, 0, 1, eng, 200, false);

@@ -452,7 +452,7 @@ void check_csr_row(const int64_t* rp, const int32_t* ci, const double* cv, int64
   const int64_t a = rp[r], e = rp[r + 1];
   if (e > a) {
     emu_check(ci + a, 4 * (e - a), what);
-    emu_check(cv + a, 8 * (e - a), what);
+    if (cv) emu_check(cv + a, 8 * (e - a), what);
   }
 }
 }  // namespace
@@ -553,5 +553,99 @@ void launch_csr_residual_sq(const int64_t* rp, const int32_t* ci, const double* 
   emu_check(part, 8 * csr_residual_parts(m), "csr resid part");
   emu_check(out, 8, "csr resid out");
   *out = 0.0;
+}
+// team tables from the stand-in CSR arrays, exactly (binary searches)
+void launch_csr_team_tables(int32_t kind, const int64_t* rp, const int32_t* ci, const int32_t* rows,
+                            const int32_t* lens, const int32_t* slot_of, const int32_t* meta, const CscArena& ar,
+                            const int32_t* nu, int32_t nb, int32_t s, int64_t n, int32_t G, int32_t* team,
+                            hipStream_t) {
+  emu_check(lens, 4 * nb, "team lens");
+  emu_check(slot_of, 4 * nb, "team slot_of");
+  const int64_t ts = csr_team_stride(s, G);
+  for (int32_t k = 0; k < nb; ++k) {
+    const int32_t* R = rows + static_cast<int64_t>(k) * s;
+    check_rows(R, lens[k], "team rows");
+    int32_t* TT = team + static_cast<int64_t>(slot_of[k]) * ts;
+    emu_check(TT, 4 * static_cast<size_t>(ts), "team table");
+    for (int32_t i = 0; i < lens[k]; ++i) {
+      check_csr_row(rp, ci, nullptr, R[i], "team row");
+      const int64_t a0 = rp[R[i]], a1 = rp[R[i] + 1];
+      for (int32_t g = 0; g <= G; ++g) {
+        int64_t e = a0;
+        const int64_t c = g == G ? n : csr_slice_lo(n, G, g);
+        while (e < a1 && ci[e] < c) ++e;
+        TT[i * (G + 1) + g] = static_cast<int32_t>(e - a0);
+      }
+    }
+    for (int32_t g = 0; g <= G; ++g) {
+      const int64_t c = g == G ? n : csr_slice_lo(n, G, g);
+      int32_t lo = 0;
+      if (kind == 0) {
+        emu_check(meta + kCsrMetaInts * k, 4 * kCsrMetaInts, "team meta");
+        const int64_t off = static_cast<int64_t>((static_cast<uint64_t>(static_cast<uint32_t>(meta[kCsrMetaInts * k + 1])) << 32) |
+                                                 static_cast<uint32_t>(meta[kCsrMetaInts * k]));
+        emu_check(nu + slot_of[k], 4, "team nu");
+        while (lo < nu[slot_of[k]] && ar.col[off + lo] < c) ++lo;
+      } else {
+        while (lo < lens[k] && R[lo] < c) ++lo;
+      }
+      TT[s * (G + 1) + g] = lo;
+    }
+  }
+}
+void launch_sparse_team(int32_t kind, const SparseTeamArgs& a, hipStream_t) {
+  if (a.W <= 0) return;
+  if (a.G < 1 || a.G > kSparseTeamMax) { std::fprintf(stderr, "EMU: team size %d\n", a.G); std::abort(); }
+  emu_check(a.coef, 8 * 3 * static_cast<size_t>(a.W), "team coef");
+  emu_check(a.step_info, 4 * kSparseStepInts * static_cast<size_t>(a.W), "team step_info");
+  emu_check(a.xr, 8 * 2 * static_cast<size_t>(a.G) * a.s, "team xr");
+  emu_check(a.xy, 8 * 2 * static_cast<size_t>(a.s), "team xy");
+  emu_check(a.flags, 4 * (kYFlagOffset + a.G * kSparseFlagStride), "team flags");
+  emu_check(a.err, 4, "team err");
+  const int T1 = a.G + 1;
+  for (int32_t k = 0; k < a.W; ++k) {
+    const int32_t* in = a.step_info + kSparseStepInts * k;
+    const int32_t q = in[0], sb = in[1], z = in[2];
+    const int32_t* R = a.rows + static_cast<int64_t>(q) * a.s;
+    check_rows(R, sb, "team rows");
+    const int32_t* TT = a.team + static_cast<int64_t>(q) * a.team_stride;
+    emu_check(TT, 4 * static_cast<size_t>(a.team_stride), "team table");
+    int64_t zz = 0;
+    for (int32_t i = 0; i < sb; ++i) {
+      check_csr_row(a.rp, a.ci, a.cv, R[i], "team row");
+      const int64_t base = a.rp[R[i]], len = a.rp[R[i] + 1] - base;
+      zz += len;
+      for (int g = 0; g < a.G; ++g) {
+        const int32_t j0 = TT[i * T1 + g], j1 = TT[i * T1 + g + 1];
+        if (j0 < 0 || j1 < j0 || j1 > len) { std::fprintf(stderr, "EMU: team row slice %d..%d of %lld\n", j0, j1, (long long)len); std::abort(); }
+        for (int64_t e = base + j0; e < base + j1; ++e) {
+          emu_check(a.u + a.ci[e], 8, "team gather u");
+          if (a.coef[3 * k] != 0.0) emu_check(a.v + a.ci[e], 8, "team gather v");
+        }
+      }
+      emu_check(a.b + R[i], 8, "team b");
+    }
+    if (zz != z) { std::fprintf(stderr, "EMU: team step %d nonzeros %lld vs %d\n", k, (long long)zz, z); std::abort(); }
+    emu_check(a.L + q * a.slot_stride + static_cast<int64_t>(a.s) * a.s, 8 * static_cast<size_t>(a.s) * a.s,
+              "team Ginv");
+    const int32_t c0 = TT[a.s * T1], cG = TT[a.s * T1 + a.G];
+    if (kind == 0) {
+      const int64_t off = static_cast<int64_t>((static_cast<uint64_t>(static_cast<uint32_t>(in[4])) << 32) |
+                                               static_cast<uint32_t>(in[3]));
+      emu_check(a.ar.ptr + off, 4 * static_cast<size_t>(z + 1), "team ptr");
+      if (c0 != 0 || cG < 0 || cG > z) { std::fprintf(stderr, "EMU: team column bounds %d %d\n", c0, cG); std::abort(); }
+      for (int32_t c = 0; c < cG; ++c) {
+        emu_check(a.u + a.ar.col[off + c], 8, "team u");
+        emu_check(a.v + a.ar.col[off + c], 8, "team v");
+      }
+    } else {
+      if (c0 != 0 || cG != sb) { std::fprintf(stderr, "EMU: team row bounds %d %d of %d\n", c0, cG, sb); std::abort(); }
+      for (int32_t i = 0; i < sb; ++i) {
+        emu_check(a.u + R[i], 8, "team u");
+        emu_check(a.v + R[i], 8, "team v");
+      }
+    }
+    emu_step(a.ds, a.zeta, nullptr);
+  }
 }
 }  // namespace kpp

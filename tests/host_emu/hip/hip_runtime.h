@@ -4,6 +4,9 @@
 #pragma once
 #include <cstddef>
 #include <cstdint>
+// device-code qualifiers of shared inline helpers compile as plain host code
+#define __host__
+#define __device__
 typedef int hipError_t;
 enum { hipSuccess = 0, hipErrorOutOfMemory = 2, hipErrorInvalidValue = 1 };
 typedef struct emu_stream* hipStream_t;

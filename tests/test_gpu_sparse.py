@@ -124,17 +124,23 @@ SPARSE_CASES = [
     ("cd_nomemo", lambda: synth.sparse_psd(500, 3, seed=14), 25, 1e-8, "off", 150, {}),
     ("cd_s256", lambda: synth.sparse_psd(900, 3, seed=15), 256, 1e-8, "online", 40, {}),
     ("cd_eta_fixed", lambda: synth.sparse_psd(400, 3, seed=16), 20, 1e-8, "online", 200, dict(eta=0.1)),
+    ("cd_s512", lambda: synth.sparse_psd(1100, 3, seed=17), 512, 1e-8, "fixed", 12, {}),
+    # rows of about 100 nonzeros
+    ("kpp_long_rows", lambda: synth.sparse_general(400, 3000, 100, seed=18), 32, 1e-4, "online", 120, {}),
 ]
 
 
+@pytest.mark.parametrize("engine", [1, 2], ids=["launch", "team"])
 @pytest.mark.parametrize("case", SPARSE_CASES, ids=[c[0] for c in SPARSE_CASES])
-def test_sparse_iterates_match_oracle(env, case):
+def test_sparse_iterates_match_oracle(env, case, engine):
+    """engine 1: three launches per step; engine 2 (the default): the team
+    kernel, one launch for every run of steps between folds."""
     name, build, s, lam, mode, T, extra = case
     S = build()
     A = S.dense()
-    print(f"[sparse parity] {name} shape={S.shape} nnz={S.nnz} s={s} T={T}", flush=True)
+    print(f"[sparse parity] {name} engine={engine} shape={S.shape} nnz={S.nnz} s={s} T={T}", flush=True)
     for Tk in (T // 2, T):
-        x, st, res = gpu_solve(env, S, s, lam=lam, T=Tk, mode=mode, seed=31, **extra)
+        x, st, res = gpu_solve(env, S, s, lam=lam, T=Tk, mode=mode, seed=31, engine=engine, **extra)
         ref = oracle_solve(A, S.b, S.kind, s, lam=lam, T=Tk, mode=mode, seed=31, **extra)
         alt = oracle_solve(A, S.b, S.kind, s, lam=lam, T=Tk, mode=mode, seed=31, reverse_sums=True, **extra)
         nf = relerr(alt.x, ref.x)
@@ -143,7 +149,7 @@ def test_sparse_iterates_match_oracle(env, case):
               flush=True)
         assert err <= max(1e-10, 10.0 * nf), f"{name} after {Tk} steps: {err:.3e} (noise floor {nf:.3e})"
         assert res.iters == Tk
-        assert res.engine_used == 1
+        assert res.engine_used == engine
         assert res.memo_misses == ref.factorizations
         rho_nf = abs(alt.rho_final - ref.rho_final)
         assert abs(res.rho_final - ref.rho_final) <= max(1e-9 * abs(ref.rho_final), 1e-12, 10.0 * rho_nf)
@@ -199,10 +205,11 @@ def test_sparse_residual_norm(env):
     assert got == pytest.approx(np.linalg.norm(S.dense() @ x - S.b), rel=1e-13)
 
 
-def test_sparse_bitwise_repeatable(env):
+@pytest.mark.parametrize("engine", [1, 2])
+def test_sparse_bitwise_repeatable(env, engine):
     S = synth.sparse_general(700, 300, 9, seed=32)
-    a, _, _ = gpu_solve(env, S, 24, lam=1e-4, T=250, seed=5)
-    b, _, _ = gpu_solve(env, S, 24, lam=1e-4, T=250, seed=5)
+    a, _, _ = gpu_solve(env, S, 24, lam=1e-4, T=250, seed=5, engine=engine)
+    b, _, _ = gpu_solve(env, S, 24, lam=1e-4, T=250, seed=5, engine=engine)
     assert np.array_equal(a, b)
 
 
@@ -289,7 +296,7 @@ def test_sparse_errors(env):
     assert create(rp, ci, nanv, b) == kpp.KPP_ERR_NONFINITE
     with Csr(env, S) as h:
         x = torch.zeros(S.n, dtype=torch.float64, device=dev)
-        for field, value in (("precision", kpp.KPP_MIXED_FP32), ("rht", 1), ("projection", 1), ("engine", 2)):
+        for field, value in (("precision", kpp.KPP_MIXED_FP32), ("rht", 1), ("projection", 1)):
             p = make_params(kpp, "general", 8, lam=1e-3, T=10)
             setattr(p, field, value)
             with pytest.raises(kpp.KppError) as e:
