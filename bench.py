@@ -21,7 +21,10 @@ FP64 and mixed.  Also: serving (continuous batching of 512 CD++ solves at
 200/s, p50/p99 latency), the randomized Hadamard preprocessing, the paper's
 FLOP comparison on synthetic kernel matrices (Full CD++, w/o RHT, w/o Memo),
 the regularization sweep, Kaczmarz++ with the LSQR projection (t_max 2, 4, 8),
-the ablation table and several right-hand sides.
+the ablation table, several right-hand sides, and sparse (CSR) systems
+(Kaczmarz++ on a random 262144 x 65536 matrix, CD++ on a random-graph
+Laplacian of order 65536: team kernel vs three launches per step, bytes per
+step against the SpMV roofline).
 
 Each measured solve carries the roofline of its step kernel (algorithmic bytes
 per launch over the launch time from HIP events inside the library, on the
@@ -61,7 +64,8 @@ def parse():
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--host-generated", action="store_true",
                     help="draw the headline system with numpy on the host (for counter-profiler runs)")
-    ap.add_argument("--only", choices=["c2", "c3", "c4"], default=None,
+    ap.add_argument("--no-sparse", action="store_true")
+    ap.add_argument("--only", choices=["c2", "c3", "c4", "sparse_kpp", "sparse_cd"], default=None,
                     help="only one workload, FP64 and mixed: c2 (CD++ n=4096), c3 (65536 x 2048), c4 (2048 x 32768)")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline workload, FP64 and mixed (for profiling the step kernel)")
@@ -76,6 +80,17 @@ TRAFFIC_PROFILES = {
     "kpp_2048x32768": os.path.join(ROOT, "profiles", "k_fused_kpp_2048x32768_s128_fp64.md"),
     "kpp_65536x2048": os.path.join(ROOT, "profiles", "k_fused_kpp_65536x2048_s256_fp64.md"),
     "cdpp_n4096": os.path.join(ROOT, "profiles", "k_fused_cdpp_n4096_s128_fp64.md"),
+    "sparse_kpp": os.path.join(ROOT, "profiles", "k_sparse_team_kpp_262144x65536_d16_s128.md"),
+    "sparse_cd": os.path.join(ROOT, "profiles", "k_sparse_team_cdpp_n65536_d6_s128.md"),
+}
+
+# Sparse workloads (CSR; the paper's sparse setting): Kaczmarz++ on a random
+# 262144 x 65536 matrix with 16 uniform columns per row (N(0, 1) values, 2% of
+# the rows scaled by 10), CD++ on a random-graph Laplacian + 0.1 I of order
+# 65536 (6 partners per node, 4 hubs of 120 more); block 128, online memo.
+SPARSE_WORKLOADS = {
+    "sparse_kpp": dict(kind="general", m=262144, n=65536, per_row=16, seed=71, s=128, lam=1e-6, tol=1e-10),
+    "sparse_cd": dict(kind="psd", m=65536, n=65536, degree=6, seed=72, s=128, lam=1e-8, tol=1e-8),
 }
 
 
@@ -654,6 +669,78 @@ def lsqr_solves(kpp, torch, dev, ctx):
     return out
 
 
+def sparse_solves(kpp, torch, dev, ctx, names, reps=1, engines=(2, 1)):
+    """Sparse systems to tolerance: the team kernel (engine 2: one launch per
+    window, workgroups owning column slices of x) and three launches per step
+    (engine 1).  Bytes per step are the library's count (block rows with
+    their nonzeros and gathered iterate entries, G^{-1}, the column-compressed
+    copy with every nonzero's column counted as distinct, u and v on the
+    updated columns, the folds); the SpMV roofline is that traffic at the HBM
+    peak."""
+    import synth
+
+    out = {}
+    for name in names:
+        w = SPARSE_WORKLOADS[name]
+        if w["kind"] == "general":
+            S = synth.sparse_general(w["m"], w["n"], w["per_row"], seed=w["seed"])
+            kind = kpp.KPP_KACZMARZ
+        else:
+            S = synth.sparse_psd(w["n"], w["degree"], seed=w["seed"])
+            kind = kpp.KPP_CD_PSD
+        rp, ci, cv, b = S.to(dev)
+        xs = torch.from_numpy(S.xstar).to(dev)
+        h = kpp.kpp_system_create_csr(ctx, kind, S.m, S.n, S.nnz, rp.data_ptr(), ci.data_ptr(), cv.data_ptr(),
+                                      b.data_ptr())
+        rec = {"workload": {"m": S.m, "n": S.n, "nnz": S.nnz, "block": w["s"], "lambda": w["lam"], "tol": w["tol"],
+                            "memo": "online", "recipe": {k: v for k, v in S.params.items()}}}
+        for engine in engines:
+            p = kpp.kpp_params_default(kind)
+            p.block_size = w["s"]
+            p.lambda_ = w["lam"]
+            p.tol = w["tol"]
+            p.max_iters = 1_000_000
+            p.seed = 11
+            p.engine = engine
+            x = torch.zeros(S.n, dtype=torch.float64, device=dev)
+            results, elapsed = timed_solves(kpp, torch, h, p, x, 1 if engine == 2 else 0, reps)
+            last = results[-1][1]
+            iters = sum(r.iters for _, r in results)
+            ksec = sum(r.kernel_seconds for _, r in results)
+            bytes_step = sum(r.bytes_algorithmic for _, r in results) / max(iters, 1)
+            us_step = 1e6 * ksec / max(iters, 1)
+            achieved = bytes_step / (us_step * 1e3) if us_step > 0 else 0.0
+            e = {"time_to_tol_ms": 1e3 * elapsed / reps, "block_iters_per_s": iters / elapsed,
+                 "iters_per_solve": iters / reps, "us_per_step_in_kernel": round(us_step, 3),
+                 "converged": all(st == 0 and r.converged for st, r in results),
+                 "true_rel_res": last.true_rel_res,
+                 "rel_err_vs_planted": float(torch.linalg.norm(x - xs) / torch.linalg.norm(xs)),
+                 "factorizations_per_solve": last.memo_misses, "factor_ms_per_solve": 1e3 * last.seconds_factor,
+                 "engine": last.engine_used, "launches_per_solve": last.kernel_launches,
+                 "bytes_per_step": round(bytes_step, 1),
+                 "spmv_roofline_us_per_step": round(bytes_step / (HBM_PEAK_GBS * 1e3), 4)}
+            if engine == 2:
+                kname = f"k_sparse_team<{0 if kind == kpp.KPP_KACZMARZ else 1}>"
+                per_launch = bytes_step * iters / max(sum(r.kernel_launches for _, r in results), 1)
+                e["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": round(achieved / HBM_PEAK_GBS, 6),
+                                 "traffic": measured_traffic(TRAFFIC_PROFILES.get(name), kname),
+                                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                                 "copy-calibrated)",
+                                 "kernel": kname, "bytes_per_launch": round(per_launch, 1)}
+                rec["team"] = e
+            else:
+                rec["launch_per_phase"] = e
+        if "team" in rec and "launch_per_phase" in rec:
+            rec["team"]["speedup_vs_launch_per_phase"] = (rec["launch_per_phase"]["time_to_tol_ms"] /
+                                                          rec["team"]["time_to_tol_ms"])
+        kpp.kpp_system_destroy(h)
+        out[name] = rec
+        del S, rp, ci, cv, b, xs
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -683,6 +770,18 @@ def main():
         kpp.kpp_context_destroy(ctx)
         return
 
+    if args.only in ("sparse_kpp", "sparse_cd"):
+        rec = sparse_solves(kpp, torch, dev, ctx, [args.only], reps=max(1, args.steps), engines=(2,))
+        kpp.kpp_context_destroy(ctx)
+        if args.calibrate_copy > 0:
+            src = torch.empty(args.calibrate_copy << 20, dtype=torch.uint8, device=dev).fill_(1)
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            rec["copy_calibration_bytes"] = args.calibrate_copy << 20
+        print(json.dumps({"only": args.only, **rec}), flush=True)
+        return
     if args.only:
         # one workload's FP64 and mixed solves (the command the step kernel's
         # profile summaries are taken with)
@@ -771,6 +870,8 @@ def main():
         line["lsqr"] = lsqr_solves(kpp, torch, dev, ctx)
     if not args.no_flops:
         line["ablation"] = ablation(kpp, torch, dev, ctx)
+    if not args.no_sparse:
+        line["sparse"] = sparse_solves(kpp, torch, dev, ctx, ["sparse_kpp", "sparse_cd"])
     kpp.kpp_context_destroy(ctx)
     if not args.no_serving:
         line["serving"] = serving(kpp, torch, dev, args.serve_requests)

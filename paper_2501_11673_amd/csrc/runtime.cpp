@@ -1050,8 +1050,7 @@ class CoreRun {
     auto fold = [&](size_t i) {
       const double f01 = fold_at[2 * i], f11 = fold_at[2 * i + 1];
       if (f01 == 0.0 && f11 == 1.0) return;
-      kpp::launch_lazy_fold(x_, sys->mom, n_, f01, f11, st_);
-      ++launches_;
+      kpp::launch_lazy_fold(x_, sys->mom, n_, f01, f11, st_);   // not counted as a step-kernel launch
       ++csr_folds_;
     };
     if (csr_window_) {
