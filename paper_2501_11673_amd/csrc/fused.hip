@@ -332,31 +332,31 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     if (two) {
       // two-level exchange: row owners sum the G partials of their rows and
       // publish r there; every workgroup then gathers r (2 s doubles instead
-      // of G s).  Wave 0 does all of it; the other waves wait at the barrier.
+      // of G s).  Each flag is polled by a thread of its own (the polls are in
+      // flight together); wave 0 forms and publishes the owned rows.
       const int rper = (sb + G - 1) / G;
       const int o0 = min(sb, wg * rper), o1 = min(sb, o0 + rper);
       const int nown = (sb + rper - 1) / rper;
       double* Rb = a.ypart + static_cast<size_t>(ep & 1u) * s;
       uint32_t* f2 = a.flags + kYFlagOffset;
-      if (wv == 0) {
-        bool ok = true;
-        if (o0 < o1) {
-          for (int g = lane; g < G && ok; g += 64) ok = wait_flag(&a.flags[g * kFlagStride], ep, a.spin_limit);
-          if (__all(ok ? 1 : 0)) {   // every lane saw its flags
-            for (int i = o0; i < o1; ++i) {
-              double acc = 0.0;
-              for (int g = lane; g < G; g += 64) acc += ld_coherent(&Pb[static_cast<size_t>(g) * s + i]);
-              acc = wave_sum(acc);
-              if (lane == 0) st_coherent(&Rb[i], acc - a.b[rs[i]]);
-            }
-            if (lane == 0) st_flag_after_stores(&f2[wg * kFlagStride], ep);
-          }
+      if (o0 < o1 && tid < G && !wait_flag(&a.flags[tid * kFlagStride], ep, a.spin_limit)) {
+        atomicOr(a.err, 2);
+        abort_flag = 1;
+      }
+      __syncthreads();
+      if (abort_flag) break;
+      if (wv == 0 && o0 < o1) {
+        for (int i = o0; i < o1; ++i) {
+          double acc = 0.0;
+          for (int g = lane; g < G; g += 64) acc += ld_coherent(&Pb[static_cast<size_t>(g) * s + i]);
+          acc = wave_sum(acc);
+          if (lane == 0) st_coherent(&Rb[i], acc - a.b[rs[i]]);
         }
-        for (int o = lane; o < nown && ok; o += 64) ok = wait_flag(&f2[o * kFlagStride], ep, a.spin_limit);
-        if (!ok) {
-          atomicOr(a.err, 2);
-          abort_flag = 1;
-        }
+        if (lane == 0) st_flag_after_stores(&f2[wg * kFlagStride], ep);
+      }
+      if (tid < nown && !wait_flag(&f2[tid * kFlagStride], ep, a.spin_limit)) {
+        atomicOr(a.err, 2);
+        abort_flag = 1;
       }
       __syncthreads();
       KPP_MARK(3)
