@@ -14,7 +14,10 @@ and are resident in HBM before the timed region.
 
 Under "mixed": the same solves with mixed precision (FP32 block products,
 FP64 factors, FP64 iterative refinement), with the speed-up over FP64 and the
-error against the FP64 solution.  Under "kpp_65536x2048": the over-determined
+error against the FP64 solution; under "bf16" one solve with bfloat16
+storage of A (reported whether or not it converges), and under
+"precisions_well_conditioned" FP64, FP32 and bfloat16 on a kappa = 10 system
+of the headline's shape.  Under "kpp_65536x2048": the over-determined
 65536 x 2048 workload (block 256, fixed partition into 256 blocks), FP64 and
 mixed.  Under "cdpp_n4096": CD++ (Algorithm 2) on the n = 4096 SPD workload,
 FP64 and mixed.  Also: serving (continuous batching of 512 CD++ solves at
@@ -188,7 +191,7 @@ def copy_params(kpp, kind, p):
     return q
 
 
-def fp64_and_mixed(kpp, torch, dev, ctx, name, warmup, steps, profile=None, engine=0, host_data=False):
+def fp64_and_mixed(kpp, torch, dev, ctx, name, warmup, steps, profile=None, engine=0, host_data=False, bf16=False):
     """One workload (synth config `name`): FP64 solves, then mixed precision.
     host_data: draw the system with numpy on the host and copy it to the device
     (same recipe, another random stream; for runs under a counter profiler)."""
@@ -227,6 +230,17 @@ def fp64_and_mixed(kpp, torch, dev, ctx, name, warmup, steps, profile=None, engi
     mixed = solve_record(torch, resm, elm, steps, x, sysm.xstar, cfg["kind"], None, x64)
     mixed["speedup_vs_fp64"] = rec["time_to_tol_ms"] / mixed["time_to_tol_ms"]
     rec["mixed"] = mixed
+    if bf16:
+        # bfloat16 storage of A: one solve, reported whether or not it converges
+        pb = copy_params(kpp, kind, pm)
+        pb.precision = kpp.KPP_MIXED_BF16
+        resb, elb = timed_solves(kpp, torch, h, pb, x, 0, 1)
+        rb = resb[-1][1]
+        rec["bf16"] = {"converged": bool(resb[-1][0] == kpp.KPP_OK and rb.converged),
+                       "true_rel_res": rb.true_rel_res, "refinements": rb.refinements, "iters": rb.iters,
+                       "time_ms": 1e3 * elb,
+                       "note": "a diverging refinement ends early and returns the iterate with the lowest true "
+                               "residual (kappa(A) 2^-8 >= 1 on this system)"}
     rec["workload"] = {"name": name, "m": m, "n": n, "block": cfg["s"], "lambda": cfg["lam"],
                        "memo": "fixed partition" if p.memo == kpp.KPP_MEMO_FIXED else "online", "tol": 1e-10}
     return rec, (sysm, h, p, x64)
@@ -669,6 +683,43 @@ def lsqr_solves(kpp, torch, dev, ctx):
     return out
 
 
+def precisions_well_conditioned(kpp, torch, dev, ctx, reps=3):
+    """FP64, FP32 and bfloat16 storage of A on a well-conditioned system of
+    the headline's shape (2048 x 32768, singular values log-spaced in [1, 10],
+    x* in the row space), block 128, lambda 1e-4, online memo, to 1e-10."""
+    import numpy as np
+
+    import synth
+
+    sysm = synth.svd_system(2048, 32768, lambda rng, r: np.geomspace(1.0, 10.0, r), 91, x_in_rowspace=True,
+                            device="cuda", name="kpp_2048x32768_kappa10")
+    A, b = sysm.A, sysm.b
+    m, n = A.shape
+    h = kpp.kpp_system_create(ctx, kpp.KPP_KACZMARZ, m, n, A.data_ptr(), n, b.data_ptr())
+    out = {"workload": {"m": m, "n": n, "kappa": 10.0, "block": 128, "lambda": 1e-4, "tol": 1e-10,
+                        "memo": "online"}}
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    for name, prec in (("fp64", kpp.KPP_FP64), ("mixed_fp32", kpp.KPP_MIXED_FP32), ("mixed_bf16", kpp.KPP_MIXED_BF16)):
+        p = kpp.kpp_params_default(kpp.KPP_KACZMARZ)
+        p.block_size = 128
+        p.lambda_ = 1e-4
+        p.tol = 1e-10
+        p.max_iters = 200_000
+        p.seed = 5
+        p.precision = prec
+        results, elapsed = timed_solves(kpp, torch, h, p, x, 1, reps)
+        last = results[-1][1]
+        out[name] = {"time_to_tol_ms": 1e3 * elapsed / reps, "iters": last.iters, "refinements": last.refinements,
+                     "converged": all(st == kpp.KPP_OK and r.converged for st, r in results),
+                     "true_rel_res": last.true_rel_res,
+                     "us_per_step_in_kernel": round(1e6 * last.kernel_seconds / max(last.iters, 1), 3),
+                     "rel_err_vs_planted": float(torch.linalg.norm(x - sysm.xstar) / torch.linalg.norm(sysm.xstar))}
+    kpp.kpp_system_destroy(h)
+    del sysm, A, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def sparse_solves(kpp, torch, dev, ctx, names, reps=1, engines=(2, 1)):
     """Sparse systems to tolerance: the team kernel (engine 2: one launch per
     window, workgroups owning column slices of x) and three launches per step
@@ -803,7 +854,7 @@ def main():
     # headline: Kaczmarz++ on 2048 x 32768, FP64, then mixed precision
     head, (c4, h4, p4, x4) = fp64_and_mixed(kpp, torch, dev, ctx, "c4", args.warmup, args.steps,
                                             TRAFFIC_PROFILES["kpp_2048x32768"], engine=args.engine,
-                                            host_data=args.host_generated)
+                                            host_data=args.host_generated, bf16=not args.headline_only)
     line = {
         "metric": "block-iters/s (Kaczmarz++ 2048x32768, time to true 1e-10 relative residual; FP64 vs mixed)",
         "value": head["block_iters_per_s"],
@@ -825,6 +876,8 @@ def main():
         line[k] = head[k]
     line["roofline"] = head["roofline"]
     line["mixed"] = head["mixed"]
+    if "bf16" in head:
+        line["bf16"] = head["bf16"]
     if args.calibrate_copy > 0:
         src = torch.empty(args.calibrate_copy << 20, dtype=torch.uint8, device=dev).fill_(1)
         dst = torch.empty_like(src)
@@ -872,6 +925,8 @@ def main():
         line["ablation"] = ablation(kpp, torch, dev, ctx)
     if not args.no_sparse:
         line["sparse"] = sparse_solves(kpp, torch, dev, ctx, ["sparse_kpp", "sparse_cd"])
+    if not args.no_mixed:
+        line["precisions_well_conditioned"] = precisions_well_conditioned(kpp, torch, dev, ctx)
     kpp.kpp_context_destroy(ctx)
     if not args.no_serving:
         line["serving"] = serving(kpp, torch, dev, args.serve_requests)

@@ -82,7 +82,14 @@ typedef enum kpp_precision {
   KPP_MIXED_FP32 = 1,         /* FP32 block products and Grams, FP64 residual, factor
                                  of ill-conditioned blocks and x accumulation, with
                                  iterative refinement (outer loop FP64)                  */
-  KPP_MIXED_BF16 = 2          /* as MIXED_FP32 with BF16 storage of A (FP32 accumulate)  */
+  KPP_MIXED_BF16 = 2          /* as MIXED_FP32 with a bfloat16 copy of A for the block
+                                 products (widened to FP32, FP32 accumulation) and FP64
+                                 Grams; converges only when kappa(A) is well below
+                                 2^8; kpp_solve only.  Both mixed modes end a
+                                 diverging refinement early (a true residual not
+                                 finite or 10x its lowest) and return, when they do
+                                 not converge, the iterate with the lowest true
+                                 residual (KPP_NOT_CONVERGED)                            */
 } kpp_precision;
 
 /* Solver parameters.  kpp_params_default() fills every field. */

@@ -53,6 +53,23 @@ template <typename TA, int CPL>
 struct TileElems {
   static constexpr int value = (sizeof(TA) == 4 && CPL >= 4) ? 128 : 64;
 };
+// Storage of A as the kernel reads it (TS) and the type its tile and products
+// use (TC): FP64 and FP32 as they are; Bf16 reads bfloat16 (the high 16 bits
+// of an FP32) and widens it to FP32 as the tile is loaded.
+struct Bf16 {};
+template <typename TA>
+struct AStore {
+  using TC = TA;
+  using TS = TA;
+};
+template <>
+struct AStore<Bf16> {
+  using TC = float;
+  using TS = uint16_t;
+};
+__device__ __forceinline__ double widen(double v) { return v; }
+__device__ __forceinline__ float widen(float v) { return v; }
+__device__ __forceinline__ float widen(uint16_t v) { return __uint_as_float(static_cast<uint32_t>(v) << 16); }
 static_assert(kFlagStride * kFusedMaxGroups <= kYFlagOffset, "flag area too small");
 static_assert(kYFlagOffset + 2 * kFlagStride * kFusedMaxGroups <= kFlagWordsAlloc, "flag area too small");
 static_assert(4 * kTwoMaxBlock <= 2 * kFusedMaxBlock, "exchange buffer too small for r and y");
@@ -95,14 +112,14 @@ __device__ __forceinline__ int32_t tile_row_index(const int32_t* __restrict__ ro
 // instead of masking them: those entries always meet a zero (x is zero beyond
 // n, y is zero beyond the block), and A is finite (checked when the system is
 // created), so they contribute nothing.
-template <int CPL, typename TA, int TE>
-__device__ __forceinline__ void load_tile(TA (&tile)[TE], const TA* __restrict__ A, int64_t lda, int64_t n,
+template <int CPL, typename TC, typename TS, int TE>
+__device__ __forceinline__ void load_tile(TC (&tile)[TE], const TS* __restrict__ A, int64_t lda, int64_t n,
                                           int32_t myrow, int64_t col0, bool vec) {
   constexpr int RMAX = TE / CPL;
-  constexpr int V = (CPL < 16 / static_cast<int>(sizeof(TA))) ? CPL : 16 / static_cast<int>(sizeof(TA));
+  constexpr int V = (CPL < 16 / static_cast<int>(sizeof(TS))) ? CPL : 16 / static_cast<int>(sizeof(TS));
   if constexpr (V > 1) {
     if (vec) {
-      typedef TA vec_t __attribute__((ext_vector_type(V)));
+      typedef TS vec_t __attribute__((ext_vector_type(V)));
 #pragma unroll
       for (int r = 0; r < RMAX; ++r) {
         const int row = __builtin_amdgcn_readlane(myrow, r);
@@ -111,7 +128,7 @@ __device__ __forceinline__ void load_tile(TA (&tile)[TE], const TA* __restrict__
         for (int e = 0; e < CPL / V; ++e) {
           const vec_t t = Ai[e];
 #pragma unroll
-          for (int j = 0; j < V; ++j) tile[r * CPL + e * V + j] = t[j];
+          for (int j = 0; j < V; ++j) tile[r * CPL + e * V + j] = widen(t[j]);
         }
       }
       return;
@@ -120,9 +137,9 @@ __device__ __forceinline__ void load_tile(TA (&tile)[TE], const TA* __restrict__
 #pragma unroll
   for (int r = 0; r < RMAX; ++r) {
     const int row = __builtin_amdgcn_readlane(myrow, r);
-    const TA* Ai = A + static_cast<int64_t>(row) * lda;
+    const TS* Ai = A + static_cast<int64_t>(row) * lda;
 #pragma unroll
-    for (int e = 0; e < CPL; ++e) tile[r * CPL + e] = Ai[min(col0 + e, n - 1)];
+    for (int e = 0; e < CPL; ++e) tile[r * CPL + e] = widen(Ai[min(col0 + e, n - 1)]);
   }
 }
 
@@ -133,7 +150,9 @@ __device__ __forceinline__ void load_tile(TA (&tile)[TE], const TA* __restrict__
 // at a checkpoint); wg is this workgroup's index in the team.
 template <int KIND, int CPL, typename TA>
 __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, const int wg) {
-  const TA* __restrict__ Amat = static_cast<const TA*>(a.A);
+  using TC = typename AStore<TA>::TC;
+  using TS = typename AStore<TA>::TS;
+  const TS* __restrict__ Amat = static_cast<const TS*>(a.A);
   // optional phase profile (workgroup 0, thread 0): ticks[p] accumulates the
   // wall-clock time from mark p-1 to mark p
   uint64_t tick_last = 0, ticks[kFusedPhases];
@@ -146,7 +165,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     ticks[p] += now_ - tick_last;                     \
     tick_last = now_;                                 \
   }
-  constexpr int TE = TileElems<TA, CPL>::value;
+  constexpr int TE = TileElems<TC, CPL>::value;
   constexpr int RMAX = TE / CPL;   // rows per wave held in registers (power of two, <= 64)
   constexpr int RSHIFT = (RMAX == 64) ? 0 : (RMAX == 32) ? 1 : (RMAX == 16) ? 2 : (RMAX == 8) ? 3 : 4;
   static_assert(RMAX >= 4 && RMAX <= 64, "rows per wave");
@@ -198,19 +217,19 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     st = *a.ds;
     abort_flag = 0;
   }
-  TA tile[TE];
+  TC tile[TE];
   int q = a.step_slot[0];
   int sb = a.lens[q];
   int cur = 0;
   // row indices run ahead of their use: myrow_c / myrow_n are this lane's
   // tile row index for the current and the next step, rown_n thread tid's
   // block row of the next step
-  int32_t myrow_c = tile_row_index<CPL, TA, TE>(a.rows + static_cast<int64_t>(q) * s, sb, wv, lane);
+  int32_t myrow_c = tile_row_index<CPL, TC, TE>(a.rows + static_cast<int64_t>(q) * s, sb, wv, lane);
   int32_t myrow_n = 0, rown_n = 0;
   if (a.W > 1) {
     const int q1 = a.step_slot[1];
     const int sb1 = a.lens[q1];
-    myrow_n = tile_row_index<CPL, TA, TE>(a.rows + static_cast<int64_t>(q1) * s, sb1, wv, lane);
+    myrow_n = tile_row_index<CPL, TC, TE>(a.rows + static_cast<int64_t>(q1) * s, sb1, wv, lane);
     if (tid < sb1) rown_n = a.rows[static_cast<int64_t>(q1) * s + tid];
   }
   load_tile<CPL>(tile, Amat, a.lda, n, myrow_c, col0, vec);
@@ -231,16 +250,16 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     KPP_MARK(0)
 
     // 1. partial residuals of this wave's rows, butterfly across the lanes
-    TA xt[CPL];
+    TC xt[CPL];
 #pragma unroll
-    for (int e = 0; e < CPL; ++e) xt[e] = static_cast<TA>(xr[e]);
-    // the lane's products are summed in TA, the sums across lanes in FP64:
+    for (int e = 0; e < CPL; ++e) xt[e] = static_cast<TC>(xr[e]);
+    // the lane's products are summed in TC, the sums across lanes in FP64:
     // each butterfly stage halves the rows a lane holds, until lane l holds
     // row l >> RSHIFT of the wave (summed over lanes with the same row)
     double v[RMAX];
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) {
-      TA acc = 0;
+      TC acc = 0;
 #pragma unroll
       for (int e = 0; e < CPL; ++e) acc = fma(tile[r * CPL + e], xt[e], acc);
       v[r] = static_cast<double>(acc);
@@ -325,7 +344,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
       const int q2 = a.step_slot[k + 2];
       const int sb2 = a.lens[q2];
       const int32_t* R2 = a.rows + static_cast<int64_t>(q2) * s;
-      myrow_nn = tile_row_index<CPL, TA, TE>(R2, sb2, wv, lane);
+      myrow_nn = tile_row_index<CPL, TC, TE>(R2, sb2, wv, lane);
       if (tid < sb2) rown_nn = R2[tid];
     }
     const int nu = (sb + 63) >> 6;
@@ -531,13 +550,13 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
 #pragma unroll
     for (int e = 0; e < CPL; ++e) w[e] = 0.0;
     if (KIND == 0) {
-      TA wt[CPL];
+      TC wt[CPL];
 #pragma unroll
       for (int e = 0; e < CPL; ++e) wt[e] = 0;
 #pragma unroll
       for (int r = 0; r < RMAX; ++r) {
         const int i = wv + 4 * r;
-        const TA yi = static_cast<TA>((i < sb) ? yv[i] : 0.0);
+        const TC yi = static_cast<TC>((i < sb) ? yv[i] : 0.0);
 #pragma unroll
         for (int e = 0; e < CPL; ++e) wt[e] = fma(tile[r * CPL + e], yi, wt[e]);
       }
@@ -697,22 +716,29 @@ void launch_fused_multi(int32_t kind, bool a_fp32, const FusedArgs* args, const 
   }
 }
 
-int32_t fused_blocks_per_cu(int32_t kind, bool a_fp32, int32_t cpl) {
-  const void* f = kind == 0 ? (a_fp32 ? fused_kernel_ptr<0, float>(cpl) : fused_kernel_ptr<0, double>(cpl))
-                            : (a_fp32 ? fused_kernel_ptr<1, float>(cpl) : fused_kernel_ptr<1, double>(cpl));
+int32_t fused_blocks_per_cu(int32_t kind, int32_t prec, int32_t cpl) {
+  const void* f = nullptr;
+  if (kind == 0)
+    f = prec == 2 ? fused_kernel_ptr<0, Bf16>(cpl) : prec == 1 ? fused_kernel_ptr<0, float>(cpl) : fused_kernel_ptr<0, double>(cpl);
+  else
+    f = prec == 2 ? fused_kernel_ptr<1, Bf16>(cpl) : prec == 1 ? fused_kernel_ptr<1, float>(cpl) : fused_kernel_ptr<1, double>(cpl);
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kT, 0) != hipSuccess) return 0;
   return nb;
 }
 
-void launch_fused(int32_t kind, bool a_fp32, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t st) {
+void launch_fused(int32_t kind, int32_t prec, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t st) {
   if (kind == 0) {
-    if (a_fp32)
+    if (prec == 2)
+      launch_kind<0, Bf16>(a, cpl, groups, st);
+    else if (prec == 1)
       launch_kind<0, float>(a, cpl, groups, st);
     else
       launch_kind<0, double>(a, cpl, groups, st);
   } else {
-    if (a_fp32)
+    if (prec == 2)
+      launch_kind<1, Bf16>(a, cpl, groups, st);
+    else if (prec == 1)
       launch_kind<1, float>(a, cpl, groups, st);
     else
       launch_kind<1, double>(a, cpl, groups, st);

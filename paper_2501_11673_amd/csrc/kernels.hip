@@ -518,6 +518,17 @@ __global__ __launch_bounds__(kT) void k_convert_f32(const double* __restrict__ A
   }
 }
 
+__global__ __launch_bounds__(kT) void k_convert_bf16(const double* __restrict__ A, int64_t lda, int64_t m,
+                                                     int64_t n, uint16_t* __restrict__ out) {
+  const int64_t total = m * n;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x; e < total;
+       e += static_cast<int64_t>(gridDim.x) * kT) {
+    const int64_t i = e / n, j = e - i * n;
+    const uint32_t f = __float_as_uint(static_cast<float>(A[i * lda + j]));
+    out[e] = static_cast<uint16_t>((f + 0x7fffu + ((f >> 16) & 1u)) >> 16);   // A is finite
+  }
+}
+
 // r = b - A x, one wave per row
 __global__ __launch_bounds__(kT) void k_residual_vec(const double* __restrict__ A, int64_t lda, int64_t m,
                                                      int64_t n, const double* __restrict__ x,
@@ -1511,6 +1522,12 @@ void launch_convert_f32(const double* A, int64_t lda, int64_t m, int64_t n, floa
   const int64_t total = m * n;
   const unsigned g = static_cast<unsigned>(std::min<int64_t>((total + kT - 1) / kT, 65536));
   hipLaunchKernelGGL(k_convert_f32, dim3(g), dim3(kT), 0, st, A, lda, m, n, out);
+}
+
+void launch_convert_bf16(const double* A, int64_t lda, int64_t m, int64_t n, uint16_t* out, hipStream_t st) {
+  const int64_t total = m * n;
+  const unsigned g = static_cast<unsigned>(std::min<int64_t>((total + kT - 1) / kT, 65536));
+  hipLaunchKernelGGL(k_convert_bf16, dim3(g), dim3(kT), 0, st, A, lda, m, n, out);
 }
 
 void launch_residual_vec(const double* A, int64_t lda, int64_t m, int64_t n, const double* x,

@@ -136,6 +136,9 @@ void launch_state_init(DevState* ds, double rho0, double thr, hipStream_t st);
 
 // out[i * n + j] = (float) A[i * lda + j]   (row-major FP32 copy, leading dimension n)
 void launch_convert_f32(const double* A, int64_t lda, int64_t m, int64_t n, float* out, hipStream_t st);
+// bfloat16 copy (leading dimension n): each entry rounded to FP32, then to
+// the nearest bfloat16 (ties to even), kept as its 16 bits
+void launch_convert_bf16(const double* A, int64_t lda, int64_t m, int64_t n, uint16_t* out, hipStream_t st);
 
 // r = b - A x (FP64), rowsq[i] = r_i^2, *out = sum_i rowsq[i] in a fixed order
 void launch_residual_vec(const double* A, int64_t lda, int64_t m, int64_t n, const double* x,
@@ -207,12 +210,13 @@ constexpr int kYFlagOffset = kFlagWordsAlloc / 2;
 // exchange buffer per system: partial residuals, then the y all-gather
 constexpr size_t kPartDoubles = 2 * static_cast<size_t>(kFusedMaxGroups) * kFusedMaxBlock + 2 * kFusedMaxBlock;
 
-void launch_fused(int32_t kind, bool a_fp32, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t st);
+// prec: 0 FP64 A, 1 FP32 A, 2 bfloat16 A (widened to FP32 in the tile)
+void launch_fused(int32_t kind, int32_t prec, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t st);
 
 // Workgroups of the step kernel for (kind, precision, cpl) that one compute
 // unit can hold at once (the occupancy query; 0 if it fails).  A team must be
 // resident as a whole: its workgroups wait for each other every step.
-int32_t fused_blocks_per_cu(int32_t kind, bool a_fp32, int32_t cpl);
+int32_t fused_blocks_per_cu(int32_t kind, int32_t prec, int32_t cpl);
 
 // Several independent runs in one launch: team t has the workgroups
 // [team_start[t], team_start[t + 1]) and the arguments args[t] (device

@@ -84,8 +84,9 @@ struct kpp_context {
   int32_t cu_count = 0;
   // workgroups of k_fused<kind, cpl, precision> per compute unit
   // ([kind][fp32][log2 cpl]; -1 = not asked yet)
-  int32_t fused_per_cu[2][2][5] = {{{-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1}},
-                                   {{-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1}}};
+  // ([kind][precision of A: FP64, FP32, BF16][log2 cpl]; -1 = not asked yet)
+  int32_t fused_per_cu[2][3][5] = {{{-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1}},
+                                   {{-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1}}};
   // device address of this device's no-allocation scratch (noalloc.hip)
   unsigned char* scratch = nullptr;
 };
@@ -145,10 +146,12 @@ struct kpp_system {
   uint64_t* phase_ticks = nullptr;   // KPP_PHASE_PROFILE=1: fused-engine phase profile
   // mixed precision: FP32 copy of A (leading dimension n), outer residual, correction
   float* A32 = nullptr;
+  uint16_t* A16 = nullptr;   // mixed precision with bfloat16 storage: the bfloat16 copy of A
   double* gram_ws[2] = {nullptr, nullptr};   // split-Gram partial tiles, one per staging buffer
   size_t gram_ws_cap[2] = {0, 0};
   double* rvec = nullptr;
   double* dvec = nullptr;
+  double* xsave = nullptr;   // mixed precision: the iterate with the lowest true residual so far
   double* gemvt_ws = nullptr;      // partial sums of d = A^T z (wide mixed precision)
   double* zx = nullptr;    // mixed precision, wide Kaczmarz++: duals of the inner iterate and momentum
   double* zm = nullptr;
@@ -279,12 +282,14 @@ void destroy_buffers(kpp_system* s) {
   dev_free(s->flags);
   dev_free(s->phase_ticks);
   dev_free(s->A32);
+  dev_free(s->A16);
   for (int i = 0; i < 2; ++i) {
     dev_free(s->gram_ws[i]);
     s->gram_ws_cap[i] = 0;
   }
   dev_free(s->rvec);
   dev_free(s->dvec);
+  dev_free(s->xsave);
   dev_free(s->gemvt_ws);
   dev_free(s->zx);
   dev_free(s->zm);
@@ -527,9 +532,9 @@ kpp_status check_params(const kpp_system* sys, const kpp_params* p) {
   if (p->memo == KPP_MEMO_FIXED && !p->fixed_partition && p->num_blocks < 1)
     return fail(KPP_ERR_INVALID_ARG, "fixed collection needs num_blocks >= 1");
   if (!(p->rho0 >= 0.0 && p->rho0 <= 1.0)) return fail(KPP_ERR_INVALID_ARG, "rho0 must be in [0, 1]");
-  if (p->precision != KPP_FP64 && p->precision != KPP_MIXED_FP32)
-    return fail(KPP_ERR_INVALID_ARG, "precision %d is not available in this build", p->precision);
-  if (p->precision == KPP_MIXED_FP32) {
+  if (p->precision != KPP_FP64 && p->precision != KPP_MIXED_FP32 && p->precision != KPP_MIXED_BF16)
+    return fail(KPP_ERR_INVALID_ARG, "unknown precision %d", p->precision);
+  if (p->precision != KPP_FP64) {
     if (p->engine == 1) return fail(KPP_ERR_INVALID_ARG, "mixed precision runs on the fused engine");
     if (p->block_size > kpp::kFusedMaxBlock)
       return fail(KPP_ERR_INVALID_ARG, "mixed precision takes block_size <= %d", kpp::kFusedMaxBlock);
@@ -625,13 +630,13 @@ bool fused_geometry(int64_t n, int32_t s, int32_t target_groups, bool fp32, int3
 
 // Workgroups of the step kernel that can be resident on the context's device
 // at once.
-int64_t fused_resident_groups(kpp_context* ctx, int32_t kind, bool fp32, int32_t cpl) {
+int64_t fused_resident_groups(kpp_context* ctx, int32_t kind, int32_t prec, int32_t cpl) {
   int lc = 0;
   while ((1 << lc) < cpl && lc < 4) ++lc;
-  int32_t& per = ctx->fused_per_cu[kind == KPP_CD_PSD ? 1 : 0][fp32 ? 1 : 0][lc];
+  int32_t& per = ctx->fused_per_cu[kind == KPP_CD_PSD ? 1 : 0][prec][lc];
   if (per < 0) {
     (void)hipSetDevice(ctx->device);
-    per = kpp::fused_blocks_per_cu(kind == KPP_CD_PSD ? 1 : 0, fp32, cpl);
+    per = kpp::fused_blocks_per_cu(kind == KPP_CD_PSD ? 1 : 0, prec, cpl);
   }
   return static_cast<int64_t>(per) * std::max(ctx->cu_count, 0);
 }
@@ -642,6 +647,7 @@ int64_t fused_resident_groups(kpp_context* ctx, int32_t kind, bool fp32, int32_t
 struct Source {
   const double* A64 = nullptr;
   const float* A32 = nullptr;
+  const uint16_t* A16 = nullptr;   // bfloat16 storage (then A32 is null)
   int64_t lda = 0;
   const double* b = nullptr;
   double bnorm = 0.0;
@@ -730,7 +736,8 @@ class CoreRun {
     x_ = x;
     st_ = sys->ctx->stream;
     side_ = sys->ctx->side;
-    fp32_ = src.A32 != nullptr;
+    bf16_ = src.A16 != nullptr;
+    fp32_ = src.A32 != nullptr || bf16_;
     kind_ = sys->kind;
     m_ = sys->m;
     n_ = sys->n;
@@ -785,10 +792,10 @@ class CoreRun {
     // team must be resident; otherwise the launch-per-phase engine runs (an
     // explicit request for the fused engine, a team size or the FP32 inner
     // solver, which needs the fused engine, is refused)
-    if (fused_ && groups_ > fused_resident_groups(sys->ctx, kind_, fp32_, cpl_)) {
+    if (fused_ && groups_ > fused_resident_groups(sys->ctx, kind_, prec(), cpl_)) {
       if (p->engine == 2 || p->team_groups > 0 || force_cpl > 0 || fp32_)
         return fail(KPP_ERR_INVALID_ARG, "a team of %d workgroups cannot be resident on this device (%lld)",
-                    groups_, static_cast<long long>(fused_resident_groups(sys->ctx, kind_, fp32_, cpl_)));
+                    groups_, static_cast<long long>(fused_resident_groups(sys->ctx, kind_, prec(), cpl_)));
       fused_ = false;
     }
     lsqr_ = p->projection == 1;
@@ -818,7 +825,7 @@ class CoreRun {
     const bool same_sig = sys->memo_valid && (o.keep_memo || o.resume) && sys->sig_s == s_ && sys->sig_memo == p->memo &&
                           sys->sig_nb == p->num_blocks && sys->sig_part == p->fixed_partition &&
                           sys->sig_seed == p->seed && sys->sig_lambda == p->lambda &&
-                          sys->sig_prec == (fp32_ ? 1 : 0) && mode_ != kpp::MemoMode::Off &&
+                          sys->sig_prec == prec() && mode_ != kpp::MemoMode::Off &&
                           !sch_->is_explicit() && !sys->sig_explicit && !lsqr_ && sys->sig_proj == 0;
     if (!same_sig) {
       sys->slot_of_block.clear();
@@ -830,7 +837,7 @@ class CoreRun {
       sys->sig_part = p->fixed_partition;
       sys->sig_seed = p->seed;
       sys->sig_lambda = p->lambda;
-      sys->sig_prec = fp32_ ? 1 : 0;
+      sys->sig_prec = prec();
       sys->sig_explicit = sch_->is_explicit();
       sys->sig_proj = lsqr_ ? 1 : 0;
       sys->csc_top = 0;
@@ -892,6 +899,7 @@ class CoreRun {
   bool dual() const { return dual_; }
   bool fused() const { return fused_; }
   bool fp32() const { return fp32_; }
+  int32_t prec() const { return bf16_ ? 2 : (fp32_ ? 1 : 0); }   // storage of A in the step kernel
   int32_t kind() const { return kind_; }
   int32_t cpl() const { return cpl_; }
   int32_t groups() const { return groups_; }
@@ -915,7 +923,8 @@ class CoreRun {
       sys_->epoch = 0;
     }
     *a = kpp::FusedArgs{};
-    a->A = fp32_ ? static_cast<const void*>(src_.A32) : static_cast<const void*>(src_.A64);
+    a->A = bf16_ ? static_cast<const void*>(src_.A16)
+                 : fp32_ ? static_cast<const void*>(src_.A32) : static_cast<const void*>(src_.A64);
     a->lda = src_.lda;
     a->n = n_;
     a->b = src_.b;
@@ -946,7 +955,7 @@ class CoreRun {
     a->ysplit = (kind_ == KPP_KACZMARZ && s_ >= kYSplitMinBlock && groups_ >= 4) ? 1 : 0;
     a->xchg2 = (kind_ == KPP_KACZMARZ && s_ <= kpp::kTwoMaxBlock && groups_ >= kTwoLevelMinGroups) ? 1 : 0;
     {
-      const size_t esz = fp32_ ? sizeof(float) : sizeof(double);
+      const size_t esz = bf16_ ? sizeof(uint16_t) : fp32_ ? sizeof(float) : sizeof(double);
       a->vec_rows = (reinterpret_cast<uintptr_t>(a->A) % 16 == 0 && (static_cast<size_t>(a->lda) * esz) % 16 == 0) ? 1 : 0;
     }
     return KPP_OK;
@@ -1356,7 +1365,7 @@ class CoreRun {
     if (csr_ && kind_ == KPP_KACZMARZ) KPP_TRY(ensure_csc_nu(sys, sys->cap_slots));
     if (csr_) KPP_TRY(ensure_csr_team(sys, sys->cap_slots, s));
     w.nb = static_cast<int32_t>(pending.size());
-    w.try32 = fp32_ && !sys->fp32_gram_futile;
+    w.try32 = fp32_ && !bf16_ && !sys->fp32_gram_futile;   // bfloat16 storage: FP64 Grams
     if (w.try32) sys->fp32_tried += w.nb;
     w.fp32_tried = sys->fp32_tried;
     w.o_len = static_cast<size_t>(w.nb) * s;
@@ -1679,7 +1688,7 @@ class CoreRun {
   CoreOpts o_{};
   double* x_ = nullptr;
   hipStream_t st_ = nullptr, side_ = nullptr;
-  bool fp32_ = false, fused_ = false, phase_prof_ = false, stop_on_cand_ = false, begun_ = false;
+  bool fp32_ = false, bf16_ = false, fused_ = false, phase_prof_ = false, stop_on_cand_ = false, begun_ = false;
   int32_t chunk_ = 1;   // sketches per batched factoring (LSQR projection)
   int32_t kind_ = 0, s_ = 0, zeta_ = 0, periods_ = 1, cpl_ = 0, groups_ = 0, P_ = 0;
   int64_t m_ = 0, n_ = 0, N_ = 0, period_ = 0, max_iters_ = 0;
@@ -1719,7 +1728,7 @@ kpp_status solve_core(kpp_system* sys, const kpp_params* p, const Source& src, c
     KPP_TRY(run.prepare(&a));
     HIP_TRY(hipEventRecord(sys->ev[0], st));
     if (run.fused()) {
-      kpp::launch_fused(run.kind(), run.fp32(), a, run.cpl(), run.groups(), st);
+      kpp::launch_fused(run.kind(), run.prec(), a, run.cpl(), run.groups(), st);
       run.count_fused_launch();
     } else {
       KPP_TRY(run.launch_unfused());
@@ -1833,21 +1842,31 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
 // Mixed precision: classical iterative refinement.  The outer loop is FP64 --
 // r = b - A x over the caller's FP64 A, x += d -- and each correction d comes
 // from the block iteration on A32 d = r (FP32 A_S products and Grams, FP64
-// factors, FP64 momentum and iterate) run to the relative tolerance inner_tol.
-// The memo cache of block factors carries over from round to round.
+// factors, FP64 momentum and iterate) run to the relative tolerance inner_tol;
+// with bfloat16 storage the inner products read the bfloat16 copy of A and
+// the Grams are formed in FP64.  The memo cache of block factors carries over
+// from round to round.  A diverging refinement ends early; an unconverged
+// solve returns the iterate with the lowest true residual it saw.
 kpp_status solve_mixed(kpp_system* sys, const kpp_params* p, double* x, kpp_result* res) {
   sys->res_valid = false;   // the inner runs reuse the momentum buffer
   using clock = std::chrono::steady_clock;
   const auto t0 = clock::now();
   hipStream_t st = sys->ctx->stream;
   const int64_t m = sys->m, n = sys->n;
-  if (!sys->A32) {
+  const bool bf16 = p->precision == KPP_MIXED_BF16;
+  if (bf16 && !sys->A16) {
+    KPP_TRY(dev_alloc(&sys->A16, static_cast<size_t>(m) * n));
+    kpp::launch_convert_bf16(sys->A, sys->lda, m, n, sys->A16, st);
+    HIP_TRY(hipGetLastError());
+  }
+  if (!bf16 && !sys->A32) {
     KPP_TRY(dev_alloc(&sys->A32, static_cast<size_t>(m) * n));
     kpp::launch_convert_f32(sys->A, sys->lda, m, n, sys->A32, st);
     HIP_TRY(hipGetLastError());
   }
   if (!sys->rvec) KPP_TRY(dev_alloc(&sys->rvec, m));
   if (!sys->dvec) KPP_TRY(dev_alloc(&sys->dvec, n));
+  if (!sys->xsave) KPP_TRY(dev_alloc(&sys->xsave, n));
   const bool wide = sys->kind == KPP_KACZMARZ && m < n;
   if (wide && !sys->gemvt_ws) KPP_TRY(dev_alloc(&sys->gemvt_ws, static_cast<size_t>(kpp::gemv_t_splits(m, n)) * n));
   if (wide && !sys->zx) KPP_TRY(dev_alloc(&sys->zx, m));
@@ -1861,6 +1880,12 @@ kpp_status solve_mixed(kpp_system* sys, const kpp_params* p, double* x, kpp_resu
   bool converged = false;
   int32_t rounds = 0;
   CoreStats last;
+  // the iterate with the lowest true residual is kept (xsave); a residual that
+  // is not finite or has grown past kRefineDiverge times that lowest one ends
+  // the refinement (the inner precision cannot resolve the system:
+  // kappa(A) u_inner >= 1), and an unconverged solve returns that iterate
+  constexpr double kRefineDiverge = 10.0;
+  double best_rn = INFINITY;
   for (;;) {
     kpp::launch_residual_vec(sys->A, sys->lda, m, n, x, sys->b, sys->rvec, sys->rowsq, sys->scal, st);
     HIP_TRY(hipGetLastError());
@@ -1868,19 +1893,34 @@ kpp_status solve_mixed(kpp_system* sys, const kpp_params* p, double* x, kpp_resu
     HIP_TRY(hipMemcpyAsync(&rr, sys->scal, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     const double rn = std::sqrt(rr);
+    if (rn < best_rn) {
+      best_rn = rn;
+      HIP_TRY(hipMemcpyAsync(sys->xsave, x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
     true_rel = sys->bnorm > 0 ? rn / sys->bnorm : rn;
+    const bool diverged = !(rn <= kRefineDiverge * best_rn);
     if (rn <= p->tol * sys->bnorm) {
       converged = true;
       break;
     }
-    if (rounds >= p->refine_max_rounds || iters >= p->max_iters) break;
+    if (diverged || rounds >= p->refine_max_rounds || iters >= p->max_iters) {
+      if (!(rn <= best_rn)) {   // return the best iterate seen
+        HIP_TRY(hipMemcpyAsync(x, sys->xsave, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        true_rel = sys->bnorm > 0 ? best_rn / sys->bnorm : best_rn;
+      }
+      break;
+    }
     HIP_TRY(hipMemsetAsync(sys->dvec, 0, n * sizeof(double), st));
     if (wide) {
       HIP_TRY(hipMemsetAsync(sys->zx, 0, m * sizeof(double), st));
       HIP_TRY(hipMemsetAsync(sys->zm, 0, m * sizeof(double), st));
     }
     Source src;
-    src.A32 = sys->A32;
+    if (bf16)
+      src.A16 = sys->A16;
+    else
+      src.A32 = sys->A32;
     src.lda = n;
     src.b = sys->rvec;
     src.bnorm = rn;
@@ -1913,7 +1953,8 @@ kpp_status solve_mixed(kpp_system* sys, const kpp_params* p, double* x, kpp_resu
     last = cs;
   }
   fill_result(res, sys, p, iters, hits, misses, converged, rounds, last, true_rel, est, rho,
-              std::chrono::duration<double>(clock::now() - t0).count(), t_factor, t_kernel, launches, ckpts, 4.0);
+              std::chrono::duration<double>(clock::now() - t0).count(), t_factor, t_kernel, launches, ckpts,
+              bf16 ? 2.0 : 4.0);
   if (res) {
     int32_t nfp64 = 0;
     HIP_TRY(hipMemcpy(&nfp64, sys->fp64_count, sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -3230,7 +3271,7 @@ KPP_API kpp_status kpp_solve(kpp_system* sys, const kpp_params* p, double* x_dev
   HIP_TRY(hipSetDevice(sys->ctx->device));
   try {
     if (p->rht) return solve_rht(sys, p, x_dev, res);
-    if (p->precision == KPP_MIXED_FP32) return solve_mixed(sys, p, x_dev, res);
+    if (p->precision != KPP_FP64) return solve_mixed(sys, p, x_dev, res);
     return solve_fp64(sys, p, x_dev, res);
   } catch (const std::bad_alloc&) {
     return fail(KPP_ERR_OOM, "host allocation failed");
@@ -3585,6 +3626,7 @@ KPP_API kpp_status kpp_request_footprint(kpp_system* sys, const kpp_params* p, u
   if (!sys || !bytes_out) return fail(KPP_ERR_INVALID_ARG, "NULL argument");
   if (sys->csr) return fail(KPP_ERR_INVALID_ARG, "the server takes dense systems");
   KPP_TRY(check_params(sys, p));
+  if (p->precision == KPP_MIXED_BF16) return fail(KPP_ERR_INVALID_ARG, "bfloat16 storage is for kpp_solve");
   *bytes_out = serve_footprint(sys, p, serve_periods(sys, p));
   return KPP_OK;
 }
@@ -3601,6 +3643,7 @@ KPP_API kpp_status kpp_server_submit(kpp_server* srv, kpp_system* sys, const kpp
   if (p->resume) return fail(KPP_ERR_INVALID_ARG, "resume is for kpp_solve");
   if (p->rht) return fail(KPP_ERR_INVALID_ARG, "rht is for kpp_solve (submit a system transformed by kpp_rht_psd)");
   if (p->projection) return fail(KPP_ERR_INVALID_ARG, "the LSQR projection is for kpp_solve");
+  if (p->precision == KPP_MIXED_BF16) return fail(KPP_ERR_INVALID_ARG, "bfloat16 storage is for kpp_solve");
   sys->res_valid = false;
   auto* r = new (std::nothrow) ServeReq;
   if (!r) return fail(KPP_ERR_OOM, "host allocation failed");

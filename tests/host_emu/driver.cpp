@@ -292,6 +292,9 @@ int main(int argc, char** argv) {
     }
     solve_case("mixed_c3_small", 0, 6000, 700, 256, 2, 1, 0, 0, 1, 20000, 1e-10);
     solve_case("mixed_psd", 1, 1000, 1000, 128, 1, 1, 0, 0, 1, 20000, 1e-10);
+    solve_case("bf16_c3_small", 0, 6000, 700, 256, 2, 1, 0, 0, 2, 20000, 1e-10);
+    solve_case("bf16_c4_small", 0, 300, 5000, 64, 1, 1, 0, 0, 2, 20000, 1e-10);
+    solve_case("bf16_psd", 1, 1000, 1000, 128, 1, 1, 0, 0, 2, 20000, 1e-10);
     resume_case(1, 600, 600, 64);
     resume_case(0, 900, 300, 40);
     rht_case(0, 5000, 12, 16);

@@ -317,6 +317,10 @@ void launch_convert_f32(const double* A, int64_t lda, int64_t m, int64_t n, floa
   emu_check(A, 8 * (static_cast<size_t>(m - 1) * lda + n), "convert A");
   emu_check(out, 4 * static_cast<size_t>(m) * n, "convert out");
 }
+void launch_convert_bf16(const double* A, int64_t lda, int64_t m, int64_t n, uint16_t* out, hipStream_t) {
+  emu_check(A, 8 * (static_cast<size_t>(m - 1) * lda + n), "convert A");
+  emu_check(out, 2 * static_cast<size_t>(m) * n, "convert out");
+}
 static std::map<const double*, int> g_rounds;
 void launch_residual_vec(const double* A, int64_t lda, int64_t m, int64_t n, const double* x, const double* b,
                          double* r, double* rowsq, double* out, hipStream_t) {
@@ -369,7 +373,7 @@ static void check_epoch(const FusedArgs& a, int64_t steps_run) {
   g_next_epoch[a.flags] = a.epoch + static_cast<uint32_t>(steps_run);
 }
 
-static void emu_fused(const FusedArgs& a, int32_t cpl, int32_t G, bool fp32) {
+static void emu_fused(const FusedArgs& a, int32_t cpl, int32_t G, size_t esz) {
   const int64_t s = a.s;
   emu_check(a.step_slot, 4 * static_cast<size_t>(a.W), "fused step_slot");
   emu_check(a.x, 8 * a.n, "fused x");
@@ -383,7 +387,7 @@ static void emu_fused(const FusedArgs& a, int32_t cpl, int32_t G, bool fp32) {
   if (a.xchg2 && (s > kTwoMaxBlock || a.W < 0)) { std::fprintf(stderr, "EMU: two-level exchange with s > %d\n", kTwoMaxBlock); std::abort(); }
   emu_check(a.err, 4, "fused err");
   if (G * 64 * cpl < a.n) { std::fprintf(stderr, "EMU: fused team too small\n"); std::abort(); }
-  if (a.vec_rows && (reinterpret_cast<uintptr_t>(a.A) % 16 != 0 || (a.lda * (fp32 ? 4 : 8)) % 16 != 0)) {
+  if (a.vec_rows && (reinterpret_cast<uintptr_t>(a.A) % 16 != 0 || (a.lda * esz) % 16 != 0)) {
     std::fprintf(stderr, "EMU: vector tile loads on unaligned rows\n");
     std::abort();
   }
@@ -399,7 +403,7 @@ static void emu_fused(const FusedArgs& a, int32_t cpl, int32_t G, bool fp32) {
     const int sb = a.lens[q];
     if (sb < 1 || sb > s) { std::fprintf(stderr, "EMU: fused sb %d (slot %d, step %d)\n", sb, q, k); std::abort(); }
     emu_check(a.rows + q * s, 4 * sb, "fused rows");
-    check_A(a.A, fp32 ? 4 : 8, a.lda, a.rows + q * s, sb, a.n, "fused A");
+    check_A(a.A, esz, a.lda, a.rows + q * s, sb, a.n, "fused A");
     for (int i = 0; i < sb; ++i) emu_check(a.b + a.rows[q * s + i], 8, "fused b");
     emu_check(a.L + q * a.slot_stride + s * s, 8 * static_cast<size_t>(s) * s, "fused Ginv");
     bool stop = false;
@@ -409,17 +413,17 @@ static void emu_fused(const FusedArgs& a, int32_t cpl, int32_t G, bool fp32) {
   }
   check_epoch(a, ran);
 }
-void launch_fused(int32_t, bool a_fp32, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t) {
-  emu_fused(a, cpl, groups, a_fp32);
+void launch_fused(int32_t, int32_t prec, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t) {
+  emu_fused(a, cpl, groups, prec == 2 ? 2 : prec == 1 ? 4 : 8);
 }
 // the stand-in device holds one step-kernel workgroup per compute unit
-int32_t fused_blocks_per_cu(int32_t, bool, int32_t) { return 1; }
+int32_t fused_blocks_per_cu(int32_t, int32_t, int32_t) { return 1; }
 void launch_fused_multi(int32_t, bool a_fp32, const FusedArgs* args, const int32_t* team_start, int32_t nteams,
                         int32_t total, int32_t cpl, hipStream_t) {
   emu_check(args, sizeof(FusedArgs) * nteams, "multi args");
   emu_check(team_start, 4 * (nteams + 1), "multi team_start");
   if (team_start[0] != 0 || team_start[nteams] != total || total > 256) { std::fprintf(stderr, "EMU: team table\n"); std::abort(); }
-  for (int t = 0; t < nteams; ++t) emu_fused(args[t], cpl, team_start[t + 1] - team_start[t], a_fp32);
+  for (int t = 0; t < nteams; ++t) emu_fused(args[t], cpl, team_start[t + 1] - team_start[t], a_fp32 ? 4 : 8);
 }
 // ---- sparse (CSR) systems: the stand-in device memory is host memory, so
 // the launchers check the CSR structure they read and every entry they touch
