@@ -302,3 +302,83 @@ def test_sparse_errors(env):
             with pytest.raises(kpp.KppError) as e:
                 kpp.kpp_solve(h, p, x.data_ptr())
             assert e.value.status == kpp.KPP_ERR_INVALID_ARG, field
+
+
+# ---------------------------------------------------------------------------
+# the benchmark's sparse workloads at full size
+# ---------------------------------------------------------------------------
+
+FULL = {
+    "kpp": lambda: synth.sparse_general(262144, 65536, 16, seed=71),
+    "cd": lambda: synth.sparse_psd(65536, 6, seed=72),
+}
+
+
+@pytest.mark.parametrize("which", ["kpp", "cd"])
+def test_sparse_full_size_first_steps_match_oracle(env, which):
+    """The first steps of the team kernel on the full-size workload (block
+    128, lambda as the benchmark, the library's own seeded schedule) against
+    the oracle run on the rows they touch: a step reads only its block's rows
+    (and, for CD++, changes x only on them), so the oracle on those rows, with
+    eta taken from the full system and no checkpoint in between, computes
+    the same iterate."""
+    import scipy.sparse as sp
+
+    kpp, torch, dev, ctx = env
+    S = FULL[which]()
+    kind = "general" if which == "kpp" else "psd"
+    s, lam, T = 128, (1e-6 if which == "kpp" else 1e-8), (4 if which == "kpp" else 6)
+    ck = kpp.KPP_KACZMARZ if which == "kpp" else kpp.KPP_CD_PSD
+    p = make_params(kpp, kind, s, lam=lam, T=T, seed=11, engine=2)
+    steps, table, lens = kpp.kpp_schedule_generate(ck, S.m, S.n, p, T, 16)
+    blocks = [np.asarray(table[b][:lens[b]], dtype=np.int64) for b in range(len(lens))]
+    used = sorted(set(steps))
+    U = np.unique(np.concatenate([blocks[b] for b in used]))
+    A = sp.csr_matrix((S.cv, S.ci, S.rp), shape=(S.m, S.n))
+    if which == "kpp":
+        D = A[U].toarray()                 # the touched rows, every column
+    else:
+        D = A[U][:, U].toarray()           # CD++: x stays on the touched coordinates
+    local = [np.searchsorted(U, blk) for blk in blocks]
+    first = np.zeros(T, dtype=bool)
+    seen = set()
+    for t, b in enumerate(steps):
+        first[t] = b not in seen
+        seen.add(b)
+    schd = osch.Schedule(blocks=local, step_block=np.asarray(steps, dtype=np.int64), new_block=first)
+    eta = okpp.default_eta(kind, S.m, S.n, s)
+    prm = okpp.Params(s=s, lam=lam, tol=0.0, max_iters=T, eta=eta)
+    ref = okpp.solve(D, S.b[U], kind, prm, schd)
+    alt = okpp.solve(D, S.b[U], kind, okpp.Params(s=s, lam=lam, tol=0.0, max_iters=T, eta=eta, reverse_sums=True),
+                     schd)
+    x, st, res = gpu_solve(env, S, s, lam=lam, T=T, seed=11, engine=2)
+    if which == "kpp":
+        xr, xa = ref.x, alt.x
+    else:
+        xr, xa = np.zeros(S.n), np.zeros(S.n)
+        xr[U], xa[U] = ref.x, alt.x
+    nf = relerr(xa, xr)
+    err = relerr(x, xr)
+    print(f"[sparse full] {which}: {T} steps, {len(U)} rows touched, |x_gpu - x_orc|/|x_orc| = {err:.3e}, "
+          f"noise floor {nf:.3e}", flush=True)
+    assert res.iters == T and res.engine_used == 2
+    assert err <= max(1e-10, 10.0 * nf)
+
+
+@pytest.mark.parametrize("which", ["kpp", "cd"])
+def test_sparse_full_size_engines_agree(env, which):
+    """One checkpoint window (2 zeta steps) of the full-size workload on the
+    team kernel and on three launches per step: the same iterate up to
+    rounding, the same memo misses, the same rho."""
+    S = FULL[which]()
+    s = 128
+    lam = 1e-6 if which == "kpp" else 1e-8
+    T = 2 * -(-(S.m if which == "kpp" else S.n) // s)
+    xa, _, ra = gpu_solve(env, S, s, lam=lam, T=T, seed=11, engine=2)
+    xb, _, rb = gpu_solve(env, S, s, lam=lam, T=T, seed=11, engine=1)
+    err = relerr(xa, xb)
+    print(f"[sparse full] {which}: {T} steps, team vs launch-per-phase {err:.3e}", flush=True)
+    assert ra.iters == rb.iters == T
+    assert ra.memo_misses == rb.memo_misses
+    assert err <= 1e-10
+    assert abs(ra.rho_final - rb.rho_final) <= 1e-9 * max(abs(rb.rho_final), 1e-3)
