@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "exchange.hpp"
 #include "lanes.hpp"
@@ -175,6 +176,10 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
   __shared__ double stage[256];
   __shared__ double wred[KIND == 0 ? 4 * 64 * CPL : 1];
   __shared__ double red[4];
+  __shared__ double wpart[4 * kOwnRows];   // two-round exchange: the owner's wave sums,
+  __shared__ double rloc[kOwnRows];        // its rows of r,
+  __shared__ double rrk[kOwnMax];          // every owner's ||r_{R_k}||^2,
+  __shared__ double yh[kTwoMaxBlock];      // and the sum of the later owners' parts of y
   __shared__ double bc_c;
   __shared__ int bc_stop;
   __shared__ int abort_flag;
@@ -188,6 +193,11 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
   const int64_t slice1 = min(n, slice0 + 64 * CPL);
   const int64_t col0 = slice0 + static_cast<int64_t>(lane) * CPL;
   const bool vec = a.vec_rows != 0 && slice1 == slice0 + 64 * CPL;   // uniform over the workgroup
+  // Kaczmarz++, large team: exchange through row owners in two rounds (every
+  // workgroup then sums the owners' parts of y; no y split)
+  const bool two = KIND == 0 && a.xchg2 != 0;
+  // Kaczmarz++ with y split across the team
+  const bool ysplit = KIND == 0 && a.ysplit != 0 && !two;
 
   double xr[CPL], mr[CPL];
 #pragma unroll
@@ -196,10 +206,11 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     xr[e] = j < n ? a.x[j] : 0.0;
     mr[e] = j < n ? a.mom[j] : 0.0;
   }
-  // dual slice (Kaczmarz++ with m < n): rows d0 + tid + 256 u of [d0, d1)
+  // dual slice (Kaczmarz++ with m < n, the low-precision inner solver only):
+  // rows d0 + tid + 256 u of [d0, d1)
   constexpr int DU = 4;
   double zxr[DU], zmr[DU];
-  const bool dual = KIND == 0 && a.zx != nullptr;
+  const bool dual = KIND == 0 && !std::is_same<TA, double>::value && a.zx != nullptr;
   int64_t d0 = 0, d1 = 0;
   if (dual) {
     const int64_t per = (a.mrows + G - 1) / G;   // at most 256 DU (checked by the host)
@@ -276,6 +287,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
       const int row = wv + 4 * (lane >> RSHIFT);
       if ((lane & ((1 << RSHIFT) - 1)) == 0 && row < sb) stage[row] = v[0];
     }
+    if (two && tid < sb) rv[tid] = bval;
     __syncthreads();
     KPP_MARK(1)
 
@@ -303,10 +315,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
       }
       hi = l;
     }
-    // Kaczmarz++ with y split across the team: this workgroup's rows of y
-    const bool ysplit = KIND == 0 && a.ysplit != 0;
-    // Kaczmarz++, large team: two-level exchange of r, y formed locally
-    const bool two = KIND == 0 && a.xchg2 != 0;
+    // split Kaczmarz++: this workgroup's rows of y
     const int yper = (sb + G - 1) / G;
     if (ysplit) {
       lo = min(sb, wg * yper);
@@ -324,6 +333,14 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     // the wait do not queue behind a tile.
     // CD++: slice rows lo + wv and lo + wv + 4 (lanes hold entries kk = lane + 64 u)
     double grow0[4] = {0.0, 0.0, 0.0, 0.0}, grow1[4] = {0.0, 0.0, 0.0, 0.0};
+    const int own0 = wg * kOwnRows, own1 = min(sb, own0 + kOwnRows);
+    if (two && own0 < sb && tid < sb) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (own0 + u < own1) grow0[u] = Ginv[static_cast<int64_t>(own0 + u) * s + tid];
+        if (own0 + 4 + u < own1) grow1[u] = Ginv[static_cast<int64_t>(own0 + 4 + u) * s + tid];
+      }
+    }
     if (KIND == 1 || ysplit) {
       const int i0 = lo + wv, i1 = lo + wv + 4;
 #pragma unroll
@@ -349,29 +366,63 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
     }
     const int nu = (sb + 63) >> 6;
     if (two) {
-      // two-level exchange: row owners sum the G partials of their rows and
-      // publish r there; every workgroup then gathers r (2 s doubles instead
-      // of G s).  Each flag is polled by a thread of its own (the polls are in
-      // flight together); wave 0 forms and publishes the owned rows.
-      const int rper = (sb + G - 1) / G;
-      const int o0 = min(sb, wg * rper), o1 = min(sb, o0 + rper);
-      const int nown = (sb + rper - 1) / rper;
-      double* Rb = a.ypart + static_cast<size_t>(ep & 1u) * s;
+      // round 1: owner k waits for every partial, sums those of its rows R_k
+      // (thread g < G loads workgroup g's, an 8-row butterfly per wave, the
+      // four waves in order), subtracts b, and publishes c_k = G^{-1}[:, R_k]
+      // r_{R_k} (thread j forms entry j from the G^{-1} column it prefetched)
+      // and ||r_{R_k}||^2.  Round 2: every workgroup waits for the owners and
+      // sums the c_k in owner order: the same y everywhere.  Each flag is
+      // polled by a thread of its own.
+      const int nown = (sb + kOwnRows - 1) / kOwnRows;
+      double* Cb = a.ypart + kOwnOffset + static_cast<size_t>(ep & 1u) * kOwnMax * kOwnStride;
       uint32_t* f2 = a.flags + kYFlagOffset;
-      if (o0 < o1 && tid < G && !wait_flag(&a.flags[tid * kFlagStride], ep, a.spin_limit)) {
+      const bool owner = own0 < sb;
+      if (owner && tid < G && !wait_flag(&a.flags[tid * kFlagStride], ep, a.spin_limit)) {
         atomicOr(a.err, 2);
         abort_flag = 1;
       }
       __syncthreads();
       if (abort_flag) break;
-      if (wv == 0 && o0 < o1) {
-        for (int i = o0; i < o1; ++i) {
-          double acc = 0.0;
-          for (int g = lane; g < G; g += 64) acc += ld_coherent(&Pb[static_cast<size_t>(g) * s + i]);
-          acc = wave_sum(acc);
-          if (lane == 0) st_coherent(&Rb[i], acc - a.b[rs[i]]);
+      if (owner) {
+        double pv[kOwnRows];
+#pragma unroll
+        for (int u = 0; u < kOwnRows; ++u)
+          pv[u] = (tid < G && own0 + u < own1) ? ld_coherent(&Pb[static_cast<size_t>(tid) * s + own0 + u]) : 0.0;
+#pragma unroll
+        for (int cnt = kOwnRows, o = 32; cnt > 1; cnt >>= 1, o >>= 1) {
+          const bool up = (lane & o) != 0;
+#pragma unroll
+          for (int r = 0; r < cnt / 2; ++r) pv[r] = fold(pv[r], pv[r + cnt / 2], o, up);
         }
-        if (lane == 0) st_flag_after_stores(&f2[wg * kFlagStride], ep);
+#pragma unroll
+        for (int o = 32 / kOwnRows; o >= 1; o >>= 1) pv[0] = fold(pv[0], pv[0], o, false);
+        if ((lane & (64 / kOwnRows - 1)) == 0) wpart[wv * kOwnRows + lane / (64 / kOwnRows)] = pv[0];
+        __syncthreads();
+        if (tid < kOwnRows) {
+          const int i = own0 + tid;
+          rloc[tid] = (i < own1) ? (((wpart[tid] + wpart[kOwnRows + tid]) + wpart[2 * kOwnRows + tid]) +
+                                    wpart[3 * kOwnRows + tid]) - rv[i]
+                                 : 0.0;
+        }
+        __syncthreads();
+        if (tid < sb) {
+          double acc = 0.0;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc = fma(grow0[u], rloc[u], acc);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc = fma(grow1[u], rloc[4 + u], acc);
+          st_coherent(&Cb[static_cast<size_t>(wg) * kOwnStride + tid], acc);
+        }
+        if (tid == kT - 1) {
+          double q2 = 0.0;
+#pragma unroll
+          for (int u = 0; u < kOwnRows; ++u) q2 = fma(rloc[u], rloc[u], q2);
+          st_coherent(&Cb[static_cast<size_t>(wg) * kOwnStride + kTwoMaxBlock], q2);
+        }
+        // every wave's stores complete before the flag
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (tid == 0) st_flag_after_stores(&f2[wg * kFlagStride], ep);
       }
       if (tid < nown && !wait_flag(&f2[tid * kFlagStride], ep, a.spin_limit)) {
         atomicOr(a.err, 2);
@@ -380,16 +431,23 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
       __syncthreads();
       KPP_MARK(3)
       if (abort_flag) break;
-      double rr_w = 0.0;
-      if (tid < sb) {
-        const double ri = ld_coherent(&Rb[tid]);
-        rv[tid] = ri;
-        rr_w = ri * ri;
+      // entry j: threads j and j + 128 sum owners 0..7 and 8..15 (added
+      // after the barrier below)
+      static_assert(kT == 2 * kTwoMaxBlock && kOwnMax == 16, "two-round exchange layout");
+      const int j = tid & (kTwoMaxBlock - 1), h = tid >> 7;
+      if (j < sb) {
+        double cv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int k2 = 8 * h + u;
+          cv[u] = (k2 < nown) ? ld_coherent(&Cb[static_cast<size_t>(k2) * kOwnStride + j]) : 0.0;
+        }
+        double acc = cv[0];
+#pragma unroll
+        for (int u = 1; u < 8; ++u) acc += cv[u];
+        if (h == 0) yv[j] = acc; else yh[j] = acc;
       }
-      if (wv < nu) {
-        rr_w = wave_sum(rr_w);
-        if (lane == 0) red[wv] = rr_w;
-      }
+      if (tid < nown) rrk[tid] = ld_coherent(&Cb[static_cast<size_t>(tid) * kOwnStride + kTwoMaxBlock]);
     } else {
     if (tid < G) {
       int64_t spins = 0;
@@ -487,6 +545,8 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
         if (abort_flag) break;
         if (tid < sb) yv[tid] = ld_coherent(&Yb[tid]);
       }
+    } else if (two) {
+      if (tid < sb) yv[tid] += yh[tid];
     } else if (tid < sb) {
       double acc = 0.0;
       int kk = 0;
@@ -503,8 +563,13 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
 
     // 5. scalars: c for this step, window sums, checkpoint
     if (tid == 0) {
-      double rr = red[0];
-      for (int w = 1; w < ((sb + 63) >> 6); ++w) rr += red[w];
+      double rr = 0.0;
+      if (two) {
+        for (int k2 = 0; k2 < (sb + kOwnRows - 1) / kOwnRows; ++k2) rr += rrk[k2];
+      } else {
+        rr = red[0];
+        for (int w = 1; w < ((sb + 63) >> 6); ++w) rr += red[w];
+      }
       const double rho = st.rho;
       st.c = (1.0 - rho) / (1.0 + rho);
       bc_c = st.c;

@@ -162,6 +162,121 @@ __global__ __launch_bounds__(GramShape<NG>::NW * 64) void k_gram_block(
   }
 }
 
+// The 128-row shape in FP64 (NG = 8) as the memo-miss path runs it beside the
+// resident step kernel: four waves (one per SIMD, at most 128 registers each:
+// the step kernel leaves 136) and every tile of the block in one workgroup,
+// so each entry of A_S is read once; 8-column panels keep the next panel's
+// loads within that budget.  The tiles go to the waves by
+// row groups: wave 0 takes the 10 lower tiles among groups 0-3, wave 1 those
+// among groups 4-7, waves 2 and 3 the cross tiles of groups 4-5 and 6-7 with
+// groups 0-3 (8 each).  A wave reads one operand per row group it touches (4
+// or 6 per k step) and uses it on both sides: lane l holds A[r_{16 g + l %
+// 16}, k + l / 16], the X operand for g = ti and the Y operand for g = tj.
+// Same workspace layout and arguments as k_gram_block<TA, 8> (one tile part).
+template <typename TA>
+__global__ __launch_bounds__(256) void k_gram_block128(const TA* __restrict__ A, int64_t lda, int64_t n,
+                                                       const int32_t* __restrict__ rows,
+                                                       const int32_t* __restrict__ lens, int32_t s,
+                                                       const int32_t* __restrict__ only, int32_t nchunks,
+                                                       int64_t chunk, double* __restrict__ ws) {
+  using Acc = typename Mfma<TA>::acc_t;
+  constexpr int NT = 256, KC = 8, LD = KC + 1, R = 128, NTILE = 36, LOADS = R * KC / NT;
+  __shared__ TA P[2][R * LD];
+  __shared__ int32_t ri[R];
+  const int ch = blockIdx.x, blk = blockIdx.z;
+  if (only && !only[blk]) return;
+  const int sb = lens[blk];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int32_t* Rw = rows + static_cast<int64_t>(blk) * s;
+  for (int i = tid; i < R; i += NT) ri[i] = i < sb ? Rw[i] : -1;
+  __syncthreads();
+  const int64_t k_begin = static_cast<int64_t>(ch) * chunk;
+  const int64_t k_end = min(n, k_begin + chunk);
+
+  TA pa[LOADS];
+  auto fetch = [&](TA(&pv)[LOADS], int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < LOADS; ++q) {
+      const int e = tid + NT * q;
+      const int r = e / KC, c = e % KC;
+      const int64_t k = k0 + c;
+      const int32_t row = ri[r];
+      pv[q] = (row >= 0 && k < k_end) ? A[static_cast<int64_t>(row) * lda + k] : TA(0);
+    }
+  };
+  auto stash = [&](TA(&pv)[LOADS], int b) {
+#pragma unroll
+    for (int q = 0; q < LOADS; ++q) {
+      const int e = tid + NT * q;
+      P[b][(e / KC) * LD + e % KC] = pv[q];
+    }
+  };
+
+  // operand f of this wave: row group gof(f)
+  const bool tri = wv < 2;
+  int foff[6];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const int g = tri ? (f < 4 ? 4 * wv + f : 0) : (f < 2 ? 4 + 2 * (wv - 2) + f : f - 2);
+    foff[f] = (16 * g + (lane & 15)) * LD + (lane >> 4);
+  }
+  Acc acc[10];
+#pragma unroll
+  for (int u = 0; u < 10; ++u) acc[u] = Acc{0, 0, 0, 0};
+
+  auto mma = [&](const TA* Pb) {
+#pragma unroll 1
+    for (int kk = 0; kk < KC; kk += 4) {
+      TA F[6];
+#pragma unroll
+      for (int f = 0; f < 6; ++f) F[f] = Pb[foff[f] + kk];
+      if (tri) {
+        // (i, j), 0 <= j <= i < 4, in row order
+#pragma unroll
+        for (int i = 0, u = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j <= i; ++j, ++u) acc[u] = Mfma<TA>::step(F[i], F[j], acc[u]);
+      } else {
+        // (i, j), i < 2 (operands 0, 1), j < 4 (operands 2..5)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[4 * i + j] = Mfma<TA>::step(F[i], F[2 + j], acc[4 * i + j]);
+      }
+    }
+  };
+  // panel p (columns k_begin + KC p ...) sits in LDS buffer p % 2 while the
+  // loads of panel p + 1 are in flight
+  const int np = static_cast<int>((k_end - k_begin + KC - 1) / KC);
+  fetch(pa, k_begin);
+  stash(pa, 0);
+  __syncthreads();
+  for (int p = 0; p < np; ++p) {
+    if (p + 1 < np) fetch(pa, k_begin + static_cast<int64_t>(p + 1) * KC);
+    mma(P[p & 1]);
+    if (p + 1 < np) stash(pa, (p + 1) & 1);
+    __syncthreads();
+  }
+  double* W = ws + (static_cast<int64_t>(blk) * nchunks + ch) * NTILE * 256;
+  auto put = [&](int u, int ti, int tj) {
+    const int t = ti * (ti + 1) / 2 + tj;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      W[t * 256 + Mfma<TA>::row(lane, r) * 16 + (lane & 15)] = static_cast<double>(acc[u][r]);
+  };
+  if (tri) {
+#pragma unroll
+    for (int i = 0, u = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j <= i; ++j, ++u) put(u, 4 * wv + i, 4 * wv + j);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) put(4 * i + j, 4 + 2 * (wv - 2) + i, j);
+  }
+}
+
 // G[slot][j * s + i] = sum over chunks of the partial tiles (+ lambda on the
 // diagonal), lower triangle of the block only; chunks summed in order, with
 // eight loads in flight
@@ -198,6 +313,11 @@ template <typename TA, int NG>
 static void launch_block_grams(const TA* A, int64_t lda, int64_t n, const int32_t* rows, const int32_t* lens, int32_t s,
                                int32_t nb, const int32_t* only, int32_t nc, int64_t chunk, double* ws, hipStream_t st) {
   using Sh = GramShape<NG>;
+  if constexpr (NG == 8 && sizeof(TA) == 8) {
+    hipLaunchKernelGGL((k_gram_block128<TA>), dim3(nc, 1, nb), dim3(256), 0, st, A, lda, n, rows, lens, s, only, nc,
+                       chunk, ws);
+    return;
+  }
   hipLaunchKernelGGL((k_gram_block<TA, NG>), dim3(nc, Sh::PARTS, nb), dim3(Sh::NW * 64), 0, st, A, lda, n, rows, lens,
                      s, only, nc, chunk, ws);
 }

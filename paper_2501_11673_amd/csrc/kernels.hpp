@@ -192,13 +192,19 @@ struct FusedArgs {
   // 2 x s doubles, and a second set of flags); 0 = every workgroup forms all of y
   double* ypart;
   int32_t ysplit;
-  // Kaczmarz++ with blocks of at most kTwoMaxBlock rows only: 1 = two-level
-  // exchange of r (row owners sum the partials and publish r through the
-  // first 2 s doubles of ypart and the second set of flags; every workgroup
-  // gathers r); a y split then uses the next 2 s doubles and a third set
+  // Kaczmarz++ with blocks of at most kTwoMaxBlock rows only: 1 = exchange
+  // through row owners in two rounds.  Owner k (workgroup k) sums the G
+  // partials of block rows R_k = [kOwnRows k, kOwnRows (k + 1)), forms its
+  // part of y, c_k = G^{-1}[:, R_k] r_{R_k}, and ||r_{R_k}||^2, and publishes
+  // them (kOwnStride doubles at ypart + kOwnOffset, double-buffered by step
+  // parity) under the second set of flags; every workgroup sums the c_k in
+  // owner order.  ysplit is then ignored.
   int32_t xchg2;
 };
 constexpr int kTwoMaxBlock = 128;
+constexpr int kOwnRows = 8;
+constexpr int kOwnMax = kTwoMaxBlock / kOwnRows;
+constexpr int kOwnStride = kTwoMaxBlock + 8;   // c_k, then ||r_{R_k}||^2 at kTwoMaxBlock
 
 constexpr int kFusedPhases = 8;
 
@@ -208,7 +214,10 @@ constexpr int kFlagWordsAlloc = 1024 * kFusedMaxGroups;   // up to 4 KB between 
 // the y all-gather's flags start this many words into the flag area
 constexpr int kYFlagOffset = kFlagWordsAlloc / 2;
 // exchange buffer per system: partial residuals, then the y all-gather
-constexpr size_t kPartDoubles = 2 * static_cast<size_t>(kFusedMaxGroups) * kFusedMaxBlock + 2 * kFusedMaxBlock;
+// (ypart), then the owners' contributions of the two-round exchange
+constexpr size_t kOwnOffset = 2 * kFusedMaxBlock;   // from ypart
+constexpr size_t kPartDoubles = 2 * static_cast<size_t>(kFusedMaxGroups) * kFusedMaxBlock + kOwnOffset +
+                                2 * static_cast<size_t>(kOwnMax) * kOwnStride;
 
 // prec: 0 FP64 A, 1 FP32 A, 2 bfloat16 A (widened to FP32 in the tile)
 void launch_fused(int32_t kind, int32_t prec, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t st);

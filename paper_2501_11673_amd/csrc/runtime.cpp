@@ -803,7 +803,7 @@ class CoreRun {
       fused_ = false;
       KPP_TRY(setup_lsqr(p));
     }
-    dual_ = o.zx != nullptr && o.zm != nullptr && kind_ == KPP_KACZMARZ && fused_ && groups_ > 0 &&
+    dual_ = o.zx != nullptr && o.zm != nullptr && kind_ == KPP_KACZMARZ && fused_ && fp32_ && groups_ > 0 &&
             (m_ + groups_ - 1) / groups_ <= kDualRowsPerGroup;
     // memo cache: reuse only for an identical schedule definition.  The slot
     // table and the staging buffers are sized for the whole run before any

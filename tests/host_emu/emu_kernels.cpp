@@ -385,6 +385,11 @@ static void emu_fused(const FusedArgs& a, int32_t cpl, int32_t G, size_t esz) {
     emu_check(a.ypart, 8 * 2 * static_cast<size_t>(s), "fused ypart");
   }
   if (a.xchg2 && (s > kTwoMaxBlock || a.W < 0)) { std::fprintf(stderr, "EMU: two-level exchange with s > %d\n", kTwoMaxBlock); std::abort(); }
+  if (a.xchg2) {
+    // owners are workgroups 0 .. ceil(s / kOwnRows) - 1, each thread of one a partial
+    if (G < kOwnMax || G > 256) { std::fprintf(stderr, "EMU: two-round exchange on %d workgroups\n", G); std::abort(); }
+    emu_check(a.ypart + kOwnOffset, 8 * 2 * static_cast<size_t>(kOwnMax) * kOwnStride, "fused owner parts");
+  }
   emu_check(a.err, 4, "fused err");
   if (G * 64 * cpl < a.n) { std::fprintf(stderr, "EMU: fused team too small\n"); std::abort(); }
   if (a.vec_rows && (reinterpret_cast<uintptr_t>(a.A) % 16 != 0 || (a.lda * esz) % 16 != 0)) {
