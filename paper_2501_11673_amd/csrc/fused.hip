@@ -711,7 +711,30 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
       }
     }
   }
-  if (wg == 0 && tid == 0) *a.ds = st;
+  if (wg == 0 && tid == 0) {
+    *a.ds = st;
+    if (a.mirror) {
+      // the state, then the error words, then the sequence number (a release
+      // at system scope orders the stores before it)
+      static_assert(sizeof(DevState) % 8 == 0, "DevState in 8-byte words");
+      uint64_t wds[sizeof(DevState) / 8];
+      __builtin_memcpy(wds, &st, sizeof(DevState));
+      uint64_t* hw = reinterpret_cast<uint64_t*>(&a.mirror->ds);
+#pragma unroll
+      for (int i = 0; i < static_cast<int>(sizeof(DevState) / 8); ++i)
+        __hip_atomic_store(&hw[i], wds[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      const uint32_t e = __hip_atomic_load(reinterpret_cast<uint32_t*>(a.err), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t f = a.fp64_count ? __hip_atomic_load(const_cast<uint32_t*>(reinterpret_cast<const uint32_t*>(
+                                                              a.fp64_count)),
+                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                      : 0u;
+      __hip_atomic_store(reinterpret_cast<uint64_t*>(&a.mirror->err),
+                         static_cast<uint64_t>(e) | (static_cast<uint64_t>(f) << 32), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(&a.mirror->seq, a.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
 }
 
 template <int KIND, int CPL, typename TA>

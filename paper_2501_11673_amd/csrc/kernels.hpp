@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 
 namespace kpp {
@@ -28,6 +29,18 @@ struct DevState {
 
 constexpr int kMaxBlock = 512;      // largest supported block size s
 constexpr int kLdsCholMax = 128;    // blocks up to this size are factored in LDS
+
+// Host-visible copy of a launch's end state (pinned, coherent host memory).
+struct HostMirror {
+  DevState ds;
+  int32_t err;
+  int32_t fp64_count;
+  uint32_t seq;   // raised last
+  uint32_t pad;
+};
+static_assert(sizeof(DevState) % 8 == 0 && offsetof(HostMirror, err) % 8 == 0 &&
+                  offsetof(HostMirror, fp64_count) == offsetof(HostMirror, err) + 4,
+              "HostMirror: the error words are stored as one 8-byte word");
 
 // Factor-time checks.  only: process just the blocks with only[k] != 0.
 // flag (low-precision pass): instead of failing, set flag[k] = 1 when the
@@ -200,6 +213,13 @@ struct FusedArgs {
   // parity) under the second set of flags; every workgroup sums the c_k in
   // owner order.  ysplit is then ignored.
   int32_t xchg2;
+  // optional (nullptr = off; single teams only): at the end of the launch
+  // workgroup 0 writes the DevState, *err and *fp64_count (when given) to this
+  // host-visible mirror with system-scope stores and then raises mirror->seq
+  // to seq, so that the host can read the state without a copy
+  HostMirror* mirror;
+  const int32_t* fp64_count;
+  uint32_t seq;
 };
 constexpr int kTwoMaxBlock = 128;
 constexpr int kOwnRows = 8;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -138,6 +139,11 @@ struct kpp_system {
   hipEvent_t ev_fact[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};  // start, end, ready
   kpp::DevState* h_ds = nullptr;
   int32_t* h_err = nullptr;
+  // end state of a single-team step-kernel launch, written by the kernel
+  // (pinned coherent host memory; d_mirror is its device address)
+  kpp::HostMirror* h_mirror = nullptr;
+  kpp::HostMirror* d_mirror = nullptr;
+  uint32_t mirror_seq = 0;
   // fused engine
   double* part = nullptr;
   uint32_t* flags = nullptr;
@@ -315,8 +321,11 @@ void destroy_buffers(kpp_system* s) {
   }
   if (s->h_ds) (void)hipHostFree(s->h_ds);
   if (s->h_err) (void)hipHostFree(s->h_err);
+  if (s->h_mirror) (void)hipHostFree(s->h_mirror);
   s->h_ds = nullptr;
   s->h_err = nullptr;
+  s->h_mirror = nullptr;
+  s->d_mirror = nullptr;
   for (auto& e : s->ev)
     if (e) {
       (void)hipEventDestroy(e);
@@ -1133,12 +1142,54 @@ class CoreRun {
 
   void count_fused_launch() { ++launches_; }
 
+  // Single-team fused launches: the kernel writes its end state to the
+  // system's host mirror (no copy-back; the host waits on the mirror).
+  void mirror_args(kpp::FusedArgs* a) {
+    mirrored_ = false;
+    if (!fused_ || csr_ || !sys_->d_mirror) return;
+    a->mirror = sys_->d_mirror;
+    a->fp64_count = (fp32_ && sys_->fp64_count) ? sys_->fp64_count : nullptr;
+    a->seq = ++sys_->mirror_seq;
+    mirror_expect_ = a->seq;
+    mirrored_ = true;
+  }
+
   // After the launch is enqueued: state copy-back, and the next window planned
   // and factored on the side stream while this one runs.
   kpp_status after_launch() {
-    KPP_TRY(copy_back());
+    if (!mirrored_) KPP_TRY(copy_back());
     KPP_TRY(plan_ahead());
     return enqueue_ahead();
+  }
+
+  // Wait for the launch's end state: spin on the host mirror (the stream may
+  // still be retiring the kernel), else drain the main stream.  A stream that
+  // went idle without the mirror raised falls back to a copy.
+  kpp_status wait_launch() {
+    if (!mirrored_) {
+      HIP_TRY(hipStreamSynchronize(st_));
+      return KPP_OK;
+    }
+    mirrored_ = false;
+    const volatile uint32_t* seq = &sys_->h_mirror->seq;
+    for (;;) {
+      for (int i = 0; i < 4096; ++i)
+        if (*seq == mirror_expect_) {
+          std::atomic_thread_fence(std::memory_order_acquire);
+          const kpp::HostMirror* hm = sys_->h_mirror;
+          std::memcpy(sys_->h_ds, const_cast<const kpp::DevState*>(&hm->ds), sizeof(kpp::DevState));
+          sys_->h_err[0] = hm->err;
+          if (fp32_ && sys_->fp64_count) sys_->h_err[1] = hm->fp64_count;
+          return KPP_OK;
+        }
+      const hipError_t q = hipStreamQuery(st_);
+      if (q == hipSuccess && *seq != mirror_expect_) {
+        KPP_TRY(copy_back());
+        HIP_TRY(hipStreamSynchronize(st_));
+        return KPP_OK;
+      }
+      if (q != hipSuccess && q != hipErrorNotReady) return fail(KPP_ERR_HIP, "HIP error: %s", hipGetErrorString(q));
+    }
   }
 
   // The three parts of after_launch, for callers that plan several runs at
@@ -1700,6 +1751,8 @@ class CoreRun {
   bool have_next_ = false;
   int64_t t_ = 0, t_start_ = 0, hits_ = 0, misses_ = 0, launches_ = 0;
   bool converged_ = false, finished_ = false, stalled_ = false, planned_ = false, dual_ = false;
+  bool mirrored_ = false;
+  uint32_t mirror_expect_ = 0;
   double true_rel_ = NAN, t_factor_ = 0.0, t_kernel_ = 0.0;
   kpp::DevState hs_{};
   std::vector<double> e1_hist_;
@@ -1723,25 +1776,39 @@ kpp_status solve_core(kpp_system* sys, const kpp_params* p, const Source& src, c
   hipStream_t st = sys->ctx->stream;
   CoreRun run;
   KPP_TRY(run.begin(sys, p, src, o, x, 1, 0));
+  // launch k is timed by the event pair ev[2 (k % 2)], ev[2 (k % 2) + 1],
+  // read once launch k + 1 is enqueued (launch k has then retired or is
+  // retiring: the host may see its end state before the stream does)
+  int pair = 0;
+  bool pending = false;
+  auto take_time = [&](int pr) -> kpp_status {
+    float ms = 0.0f;
+    HIP_TRY(hipEventSynchronize(sys->ev[2 * pr + 1]));
+    HIP_TRY(hipEventElapsedTime(&ms, sys->ev[2 * pr], sys->ev[2 * pr + 1]));
+    run.add_kernel_seconds(1e-3 * ms);
+    return KPP_OK;
+  };
   while (!run.finished()) {
     kpp::FusedArgs a;
     KPP_TRY(run.prepare(&a));
-    HIP_TRY(hipEventRecord(sys->ev[0], st));
+    HIP_TRY(hipEventRecord(sys->ev[2 * pair], st));
     if (run.fused()) {
+      run.mirror_args(&a);
       kpp::launch_fused(run.kind(), run.prec(), a, run.cpl(), run.groups(), st);
       run.count_fused_launch();
     } else {
       KPP_TRY(run.launch_unfused());
     }
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipEventRecord(sys->ev[1], st));
+    HIP_TRY(hipEventRecord(sys->ev[2 * pair + 1], st));
+    if (pending) KPP_TRY(take_time(pair ^ 1));
+    pending = true;
     KPP_TRY(run.after_launch());
-    HIP_TRY(hipStreamSynchronize(st));
-    float ms = 0.0f;
-    HIP_TRY(hipEventElapsedTime(&ms, sys->ev[0], sys->ev[1]));
-    run.add_kernel_seconds(1e-3 * ms);
+    KPP_TRY(run.wait_launch());
     KPP_TRY(run.finish());
+    pair ^= 1;
   }
+  if (pending) KPP_TRY(take_time(pair ^ 1));
   KPP_TRY(run.end(cs));
   if (o.keep_state) run.keep_state();
   return KPP_OK;
@@ -3133,9 +3200,16 @@ kpp_status alloc_system(kpp_context* ctx, int32_t kind, int64_t m, int64_t n, co
     return stt;
   }
   if (hipHostMalloc(reinterpret_cast<void**>(&sys->h_ds), sizeof(kpp::DevState), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&sys->h_err), 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc(reinterpret_cast<void**>(&sys->h_err), 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&sys->h_mirror), sizeof(kpp::HostMirror),
+                    hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
     destroy_buffers(sys.get());
     return fail(KPP_ERR_OOM, "pinned host allocation failed");
+  }
+  std::memset(sys->h_mirror, 0, sizeof(kpp::HostMirror));
+  if (hipHostGetDevicePointer(reinterpret_cast<void**>(&sys->d_mirror), sys->h_mirror, 0) != hipSuccess) {
+    destroy_buffers(sys.get());
+    return fail(KPP_ERR_HIP, "hipHostGetDevicePointer failed");
   }
   for (auto& e : sys->ev) {
     if (hipEventCreate(&e) != hipSuccess) {

@@ -45,6 +45,7 @@ hipError_t hipMalloc(void** p, size_t bytes) { *p = alloc(bytes); return hipSucc
 hipError_t hipFree(void* p) { release(p); return hipSuccess; }
 hipError_t hipHostMalloc(void** p, size_t bytes, unsigned) { *p = alloc(bytes); return hipSuccess; }
 hipError_t hipHostFree(void* p) { release(p); return hipSuccess; }
+hipError_t hipHostGetDevicePointer(void** d, void* h, unsigned) { emu_check(h, 1, "host pointer"); *d = h; return hipSuccess; }
 hipError_t hipMemcpyAsync(void* d, const void* s, size_t bytes, hipMemcpyKind k, hipStream_t) {
   if (k != hipMemcpyDeviceToHost) emu_check(d, bytes, "memcpy dst");
   if (k != hipMemcpyHostToDevice) emu_check(s, bytes, "memcpy src");
@@ -60,6 +61,8 @@ hipError_t hipMemsetAsync(void* d, int v, size_t bytes, hipStream_t) {
   return hipSuccess;
 }
 hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+// launches run synchronously: a stream is always idle
+hipError_t hipStreamQuery(hipStream_t) { return hipSuccess; }
 hipError_t hipStreamCreateWithFlags(hipStream_t* st, unsigned) { *st = reinterpret_cast<hipStream_t>(new char[8]); return hipSuccess; }
 hipError_t hipStreamDestroy(hipStream_t st) { delete[] reinterpret_cast<char*>(st); return hipSuccess; }
 hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) { return hipSuccess; }

@@ -417,6 +417,16 @@ static void emu_fused(const FusedArgs& a, int32_t cpl, int32_t G, size_t esz) {
     if (a.stop_on_cand && stop) break;
   }
   check_epoch(a, ran);
+  if (a.mirror) {
+    // the kernel's end-state mirror: state, error words, then the sequence number
+    emu_check(a.mirror, sizeof(HostMirror), "fused host mirror");
+    emu_check(a.err, 4, "fused err");
+    a.mirror->ds = *a.ds;
+    a.mirror->err = *a.err;
+    if (a.fp64_count) emu_check(a.fp64_count, 4, "fused fp64 count");
+    a.mirror->fp64_count = a.fp64_count ? *a.fp64_count : 0;
+    a.mirror->seq = a.seq;
+  }
 }
 void launch_fused(int32_t, int32_t prec, const FusedArgs& a, int32_t cpl, int32_t groups, hipStream_t) {
   emu_fused(a, cpl, groups, prec == 2 ? 2 : prec == 1 ? 4 : 8);

@@ -8,11 +8,11 @@
 #define __host__
 #define __device__
 typedef int hipError_t;
-enum { hipSuccess = 0, hipErrorOutOfMemory = 2, hipErrorInvalidValue = 1 };
+enum { hipSuccess = 0, hipErrorOutOfMemory = 2, hipErrorInvalidValue = 1, hipErrorNotReady = 600 };
 typedef struct emu_stream* hipStream_t;
 typedef struct emu_event* hipEvent_t;
 enum hipMemcpyKind { hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice, hipMemcpyHostToHost };
-enum { hipStreamNonBlocking = 1, hipHostMallocDefault = 0 };
+enum { hipStreamNonBlocking = 1, hipHostMallocDefault = 0, hipHostMallocMapped = 2, hipHostMallocCoherent = 0x40000000 };
 enum hipDeviceAttribute_t { hipDeviceAttributeWallClockRate = 1 };
 struct hipDeviceProp_t { int multiProcessorCount; };
 struct dim3 { unsigned x, y, z; dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {} };
@@ -20,10 +20,12 @@ hipError_t hipMalloc(void** p, size_t bytes);
 hipError_t hipFree(void* p);
 hipError_t hipHostMalloc(void** p, size_t bytes, unsigned flags);
 hipError_t hipHostFree(void* p);
+hipError_t hipHostGetDevicePointer(void** d, void* h, unsigned flags);
 hipError_t hipMemcpyAsync(void* d, const void* s, size_t bytes, hipMemcpyKind k, hipStream_t st);
 hipError_t hipMemcpy(void* d, const void* s, size_t bytes, hipMemcpyKind k);
 hipError_t hipMemsetAsync(void* d, int v, size_t bytes, hipStream_t st);
 hipError_t hipStreamSynchronize(hipStream_t st);
+hipError_t hipStreamQuery(hipStream_t st);
 hipError_t hipStreamCreateWithFlags(hipStream_t* st, unsigned flags);
 hipError_t hipStreamDestroy(hipStream_t st);
 hipError_t hipStreamWaitEvent(hipStream_t st, hipEvent_t e, unsigned flags);
