@@ -923,7 +923,12 @@ class CoreRun {
   kpp_status prepare(kpp::FusedArgs* a) {
     Window& w = win_[cur_];
     if (w.on_side && !w.waited) {
-      HIP_TRY(hipStreamWaitEvent(st_, sys_->ev_fact[cur_][1], 0));
+      // (nothing to order after factors that have completed already)
+      const hipError_t q = hipEventQuery(sys_->ev_fact[cur_][1]);
+      if (q == hipErrorNotReady)
+        HIP_TRY(hipStreamWaitEvent(st_, sys_->ev_fact[cur_][1], 0));
+      else
+        HIP_TRY(q);
       w.waited = true;
     }
     if (!fused_) return KPP_OK;
