@@ -49,7 +49,7 @@ extern "C" {
 #endif
 
 #define KPP_API __attribute__((visibility("default")))
-#define KPP_ABI_VERSION 5
+#define KPP_ABI_VERSION 6
 
 typedef enum kpp_status {
   KPP_OK = 0,
@@ -146,7 +146,11 @@ typedef struct kpp_params {
    * true_rel_res is recomputed on the original system.  R <= 2^24.  resume
    * and kpp_server_submit reject rht = 1 (KPP_ERR_INVALID_ARG). */
   int32_t rht;
-  int32_t reserved2;
+  /* 1: kpp_solve does not time its step-kernel launches: no HIP event pair
+   * goes to the stream around each launch (each pair adds a few microseconds
+   * between consecutive launches) and kernel_seconds reports 0.  Default 0:
+   * every launch is timed (kernel_seconds). */
+  int32_t no_launch_timing;
   uint64_t rht_seed;
   /* Kaczmarz++ projection (Section 4.1).  0: exact, w = A_S^T (A_S A_S^T +
    * lambda I)^{-1} r through the memoized Cholesky factor.  1: the inexact
@@ -189,7 +193,8 @@ typedef struct kpp_result {
                                  projection 1: per step 4sn + 5n + s^2 + t_max (4sn + 2n
                                  + 4s^2), per factor s N log2 N + s^2 tau + 2 s^3 / 3 */
   double bytes_algorithmic;   /* per step: s n b_A (A_S) + s(s+1)/2 * 8 (factor) + 12 s (b_S, rows) */
-  double kernel_seconds;      /* device time of the step kernels (HIP events), all launches */
+  double kernel_seconds;      /* device time of the step kernels (HIP events), all launches;
+                                 0 with params.no_launch_timing */
   double kernel_launches;     /* number of step-kernel launches (fused: one per window)  */
   double seconds_queued;      /* serving: time from submission to admission             */
   int32_t team_groups;        /* fused engine: workgroups sharing one step (0: launch-per-phase) */

@@ -73,7 +73,7 @@ class kpp_params(ctypes.Structure):
         ("block_rows_count", ctypes.c_int32),
         ("resume", ctypes.c_int32),
         ("rht", ctypes.c_int32),
-        ("reserved2", ctypes.c_int32),
+        ("no_launch_timing", ctypes.c_int32),
         ("rht_seed", ctypes.c_uint64),
         ("projection", ctypes.c_int32),
         ("lsqr_iters", ctypes.c_int32),

@@ -144,6 +144,26 @@ __device__ __forceinline__ void load_tile(TC (&tile)[TE], const TS* __restrict__
   }
 }
 
+// The launch's end state to the host mirror: the state, then the error words,
+// then the sequence number (a release at system scope orders the stores
+// before it).  One thread.
+__device__ __forceinline__ void publish_mirror(const FusedArgs& a, const DevState& st) {
+  static_assert(sizeof(DevState) % 8 == 0, "DevState in 8-byte words");
+  uint64_t wds[sizeof(DevState) / 8];
+  __builtin_memcpy(wds, &st, sizeof(DevState));
+  uint64_t* hw = reinterpret_cast<uint64_t*>(&a.mirror->ds);
+#pragma unroll
+  for (int i = 0; i < static_cast<int>(sizeof(DevState) / 8); ++i)
+    __hip_atomic_store(&hw[i], wds[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  const uint32_t e = __hip_atomic_load(reinterpret_cast<uint32_t*>(a.err), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t f = a.fp64_count ? __hip_atomic_load(const_cast<uint32_t*>(reinterpret_cast<const uint32_t*>(a.fp64_count)),
+                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                  : 0u;
+  __hip_atomic_store(reinterpret_cast<uint64_t*>(&a.mirror->err), static_cast<uint64_t>(e) | (static_cast<uint64_t>(f) << 32),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(&a.mirror->seq, a.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // TA: storage and product type of A (double; float for the mixed-precision
 // inner solver: the tile, the partial residuals and the direction are formed in
 // FP32 with FP32 accumulation, everything else stays FP64).
@@ -154,6 +174,19 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
   using TC = typename AStore<TA>::TC;
   using TS = typename AStore<TA>::TS;
   const TS* __restrict__ Amat = static_cast<const TS*>(a.A);
+  // a launch enqueued ahead runs nothing after a checkpoint whose stop test
+  // passed (every workgroup reads the same word, written by the previous
+  // launch); a launch of no step reads nothing (the first step's slot is read
+  // before the step loop)
+  if (a.W <= 0 || (a.skip_on_cand &&
+                   __hip_atomic_load(&a.ds->cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+    if (wg == 0 && threadIdx.x == 0 && a.mirror) {
+      DevState st0;
+      __builtin_memcpy(&st0, a.ds, sizeof(DevState));
+      publish_mirror(a, st0);
+    }
+    return;
+  }
   // optional phase profile (workgroup 0, thread 0): ticks[p] accumulates the
   // wall-clock time from mark p-1 to mark p
   uint64_t tick_last = 0, ticks[kFusedPhases];
@@ -713,27 +746,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs& a, const int G, cons
   }
   if (wg == 0 && tid == 0) {
     *a.ds = st;
-    if (a.mirror) {
-      // the state, then the error words, then the sequence number (a release
-      // at system scope orders the stores before it)
-      static_assert(sizeof(DevState) % 8 == 0, "DevState in 8-byte words");
-      uint64_t wds[sizeof(DevState) / 8];
-      __builtin_memcpy(wds, &st, sizeof(DevState));
-      uint64_t* hw = reinterpret_cast<uint64_t*>(&a.mirror->ds);
-#pragma unroll
-      for (int i = 0; i < static_cast<int>(sizeof(DevState) / 8); ++i)
-        __hip_atomic_store(&hw[i], wds[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      const uint32_t e = __hip_atomic_load(reinterpret_cast<uint32_t*>(a.err), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-      const uint32_t f = a.fp64_count ? __hip_atomic_load(const_cast<uint32_t*>(reinterpret_cast<const uint32_t*>(
-                                                              a.fp64_count)),
-                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                      : 0u;
-      __hip_atomic_store(reinterpret_cast<uint64_t*>(&a.mirror->err),
-                         static_cast<uint64_t>(e) | (static_cast<uint64_t>(f) << 32), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_SYSTEM);
-      __hip_atomic_store(&a.mirror->seq, a.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
+    if (a.mirror) publish_mirror(a, st);
   }
 }
 

@@ -220,6 +220,11 @@ struct FusedArgs {
   HostMirror* mirror;
   const int32_t* fp64_count;
   uint32_t seq;
+  // 1: a launch enqueued before the previous one ended: it runs no step when
+  // the previous launch ended at a checkpoint whose stop test passed
+  // (DevState::cand), leaving the state as it is (the host then confirms the
+  // stop, or launches the window again with skip_on_cand = 0)
+  int32_t skip_on_cand;
 };
 constexpr int kTwoMaxBlock = 128;
 constexpr int kOwnRows = 8;

@@ -139,11 +139,15 @@ struct kpp_system {
   hipEvent_t ev_fact[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};  // start, end, ready
   kpp::DevState* h_ds = nullptr;
   int32_t* h_err = nullptr;
-  // end state of a single-team step-kernel launch, written by the kernel
-  // (pinned coherent host memory; d_mirror is its device address)
+  // end state of single-team step-kernel launches, written by the kernel
+  // (pinned coherent host memory, two of them: launch number q writes
+  // h_mirror[q % 2]; d_mirror is the device address)
   kpp::HostMirror* h_mirror = nullptr;
   kpp::HostMirror* d_mirror = nullptr;
   uint32_t mirror_seq = 0;
+  // recorded after each step-kernel launch of the window held in staging
+  // buffer i; that buffer's next window is uploaded after it
+  hipEvent_t ev_win[2] = {nullptr, nullptr};
   // fused engine
   double* part = nullptr;
   uint32_t* flags = nullptr;
@@ -327,6 +331,11 @@ void destroy_buffers(kpp_system* s) {
   s->h_mirror = nullptr;
   s->d_mirror = nullptr;
   for (auto& e : s->ev)
+    if (e) {
+      (void)hipEventDestroy(e);
+      e = nullptr;
+    }
+  for (auto& e : s->ev_win)
     if (e) {
       (void)hipEventDestroy(e);
       e = nullptr;
@@ -674,6 +683,8 @@ struct CoreOpts {
   // kStallRatio times its value kStallWindows window ends earlier (an inner
   // low-precision solve at its precision floor); 0 = never
   int32_t stop_on_stall = 0;
+  // time each step-kernel launch with a pair of HIP events (kernel seconds)
+  bool time_launches = true;
   // duals of the iterate and momentum (m entries each, zero on entry), kept
   // by the fused engine for Kaczmarz++ when every workgroup's share of the m
   // rows fits its registers; CoreStats::dual says whether they were
@@ -921,21 +932,57 @@ class CoreRun {
   // Order the main stream after the current window's factors and, for the
   // fused engine, fill the step-kernel arguments for the rest of the window.
   kpp_status prepare(kpp::FusedArgs* a) {
-    Window& w = win_[cur_];
-    if (w.on_side && !w.waited) {
-      // (nothing to order after factors that have completed already)
-      const hipError_t q = hipEventQuery(sys_->ev_fact[cur_][1]);
-      if (q == hipErrorNotReady)
-        HIP_TRY(hipStreamWaitEvent(st_, sys_->ev_fact[cur_][1], 0));
-      else
-        HIP_TRY(q);
-      w.waited = true;
-    }
+    KPP_TRY(order_after_factors(cur_));
     if (!fused_) return KPP_OK;
     if (sys_->epoch > 0x3fffffffu) {
       HIP_TRY(hipMemsetAsync(sys_->flags, 0, kFlagWords * sizeof(uint32_t), st_));
       sys_->epoch = 0;
     }
+    fill_args(a, cur_, sys_->epoch);
+    return KPP_OK;
+  }
+
+  // The main stream waits for window i's factors (nothing to order after
+  // factors that have completed already).
+  kpp_status order_after_factors(int i) {
+    Window& w = win_[i];
+    if (w.on_side && !w.waited) {
+      const hipError_t q = hipEventQuery(sys_->ev_fact[i][1]);
+      if (q == hipErrorNotReady)
+        HIP_TRY(hipStreamWaitEvent(st_, sys_->ev_fact[i][1], 0));
+      else
+        HIP_TRY(q);
+      w.waited = true;
+    }
+    return KPP_OK;
+  }
+
+  // Launches enqueued ahead (solve_core): the next window's launch goes to the
+  // stream before the current one ends, so that no host round trip separates
+  // them.  It runs no step if the current launch ends at a checkpoint whose
+  // stop test passes; the host then confirms the stop or launches the window
+  // again.  Only single teams whose state comes back through the mirror, full
+  // windows (no stop inside a launch), no stall test (it is decided on the
+  // host after the launch) and one launch in flight.
+  bool can_launch_ahead() const {
+    if (!fused_ || csr_ || lsqr_ || !sys_->d_mirror || o_.stop_on_stall || stop_on_cand_) return false;
+    if (!have_next_ || planned_ || finished_ || launches_in_flight_.size() != 1) return false;
+    const Window& w = win_[cur_];
+    const Window& nw = win_[cur_ ^ 1];
+    return nw.t0 == w.t0 + w.W && sys_->epoch + static_cast<uint64_t>(w.W - w.done) + static_cast<uint64_t>(nw.W) <=
+                                      0x3fffffffu;
+  }
+  kpp_status prepare_ahead(kpp::FusedArgs* a) {
+    KPP_TRY(order_after_factors(cur_ ^ 1));
+    const Window& w = win_[cur_];
+    fill_args(a, cur_ ^ 1, sys_->epoch + static_cast<uint32_t>(w.W - w.done));
+    a->skip_on_cand = 1;
+    return KPP_OK;
+  }
+  int cur_window() const { return cur_; }
+
+  void fill_args(kpp::FusedArgs* a, int wi, uint32_t epoch) {
+    const Window& w = win_[wi];
     *a = kpp::FusedArgs{};
     a->A = bf16_ ? static_cast<const void*>(src_.A16)
                  : fp32_ ? static_cast<const void*>(src_.A32) : static_cast<const void*>(src_.A64);
@@ -948,12 +995,12 @@ class CoreRun {
     a->slot_stride = sys_->slot_stride;
     a->s = s_;
     a->W = static_cast<int32_t>(w.W - w.done);
-    a->step_slot = sys_->d_stage[cur_] + w.o_step + w.done;
+    a->step_slot = sys_->d_stage[wi] + w.o_step + w.done;
     a->x = x_;
     a->mom = sys_->mom;
     a->part = sys_->part;
     a->flags = sys_->flags;
-    a->epoch = sys_->epoch;
+    a->epoch = epoch;
     a->zeta = zeta_;
     a->adaptive = prm_.adaptive_rho;
     a->eta = eta_;
@@ -972,7 +1019,6 @@ class CoreRun {
       const size_t esz = bf16_ ? sizeof(uint16_t) : fp32_ ? sizeof(float) : sizeof(double);
       a->vec_rows = (reinterpret_cast<uintptr_t>(a->A) % 16 == 0 && (static_cast<size_t>(a->lda) * esz) % 16 == 0) ? 1 : 0;
     }
-    return KPP_OK;
   }
 
   // One launch per phase for the rest of the window (engine 1).
@@ -1149,46 +1195,62 @@ class CoreRun {
 
   // Single-team fused launches: the kernel writes its end state to the
   // system's host mirror (no copy-back; the host waits on the mirror).
+  // Record a launch of window wi that solve_core enqueued: its end state
+  // comes back through the host mirror (single fused teams) or by a copy, and
+  // the window's staging buffer is free again once the stream passes the
+  // event recorded here.
   void mirror_args(kpp::FusedArgs* a) {
-    mirrored_ = false;
     if (!fused_ || csr_ || !sys_->d_mirror) return;
-    a->mirror = sys_->d_mirror;
-    a->fp64_count = (fp32_ && sys_->fp64_count) ? sys_->fp64_count : nullptr;
     a->seq = ++sys_->mirror_seq;
-    mirror_expect_ = a->seq;
-    mirrored_ = true;
+    a->mirror = sys_->d_mirror + (a->seq & 1u);
+    a->fp64_count = (fp32_ && sys_->fp64_count) ? sys_->fp64_count : nullptr;
+  }
+  kpp_status note_launch(const kpp::FusedArgs& a, int wi) {
+    launches_in_flight_.push_back(Launch{a.mirror != nullptr, a.seq});
+    HIP_TRY(hipEventRecord(sys_->ev_win[wi], st_));
+    return KPP_OK;
   }
 
   // After the launch is enqueued: state copy-back, and the next window planned
   // and factored on the side stream while this one runs.
   kpp_status after_launch() {
-    if (!mirrored_) KPP_TRY(copy_back());
+    if (launches_in_flight_.empty() || !launches_in_flight_.back().mirrored) KPP_TRY(copy_back());
     KPP_TRY(plan_ahead());
     return enqueue_ahead();
   }
 
-  // Wait for the launch's end state: spin on the host mirror (the stream may
-  // still be retiring the kernel), else drain the main stream.  A stream that
-  // went idle without the mirror raised falls back to a copy.
+  // Wait for the oldest launch's end state: spin on its host mirror (the
+  // stream may still be retiring the kernel), else drain the main stream.
+  // A stream that went idle without the mirror raised falls back to a copy
+  // (an error when a later launch has changed the state since).
   kpp_status wait_launch() {
-    if (!mirrored_) {
+    if (launches_in_flight_.empty()) {
       HIP_TRY(hipStreamSynchronize(st_));
       return KPP_OK;
     }
-    mirrored_ = false;
-    const volatile uint32_t* seq = &sys_->h_mirror->seq;
+    const Launch l = launches_in_flight_.front();
+    launches_in_flight_.pop_front();
+    if (!l.mirrored) {
+      HIP_TRY(hipStreamSynchronize(st_));
+      return KPP_OK;
+    }
+    const kpp::HostMirror* hm = sys_->h_mirror + (l.seq & 1u);
+    const volatile uint32_t* seq = &hm->seq;
     for (;;) {
       for (int i = 0; i < 4096; ++i)
-        if (*seq == mirror_expect_) {
+        if (*seq == l.seq) {
           std::atomic_thread_fence(std::memory_order_acquire);
-          const kpp::HostMirror* hm = sys_->h_mirror;
           std::memcpy(sys_->h_ds, const_cast<const kpp::DevState*>(&hm->ds), sizeof(kpp::DevState));
           sys_->h_err[0] = hm->err;
           if (fp32_ && sys_->fp64_count) sys_->h_err[1] = hm->fp64_count;
           return KPP_OK;
         }
       const hipError_t q = hipStreamQuery(st_);
-      if (q == hipSuccess && *seq != mirror_expect_) {
+      if (q == hipSuccess && *seq != l.seq) {
+        if (!launches_in_flight_.empty()) {
+          finished_ = true;
+          return fail(KPP_ERR_DEVICE, "a step-kernel launch ended without reporting its state");
+        }
         KPP_TRY(copy_back());
         HIP_TRY(hipStreamSynchronize(st_));
         return KPP_OK;
@@ -1196,6 +1258,9 @@ class CoreRun {
       if (q != hipSuccess && q != hipErrorNotReady) return fail(KPP_ERR_HIP, "HIP error: %s", hipGetErrorString(q));
     }
   }
+  // Steps the last finish() took (0: a launch enqueued ahead that ran none).
+  int64_t last_ran() const { return last_ran_; }
+  size_t launches_in_flight() const { return launches_in_flight_.size(); }
 
   // The three parts of after_launch, for callers that plan several runs at
   // once: the state copy-back (HIP calls on the main stream), the next
@@ -1258,6 +1323,7 @@ class CoreRun {
     if (fp32_ && !sys_->fp32_gram_futile && w.fp32_tried >= 32 && sys_->h_err[1] >= w.fp32_tried)
       sys_->fp32_gram_futile = true;
     const int64_t ran = hs_.t - t_;
+    last_ran_ = ran;
     if (ran < 0 || ran > w.W - w.done) {
       finished_ = true;
       return fail(KPP_ERR_DEVICE, "step count out of range after a launch");
@@ -1603,6 +1669,10 @@ class CoreRun {
     const int idx = w.idx;
     const size_t need = csr_ ? w.o_sinfo + static_cast<size_t>(kpp::kSparseStepInts) * w.W
                              : w.o_step + static_cast<size_t>(w.W);
+    // the window that last used this staging buffer (and, without memo, this
+    // half of the slot table) has left the main stream: the host may move on
+    // once a launch's state is mirrored, before the kernel has retired
+    HIP_TRY(hipStreamWaitEvent(fs, sys->ev_win[idx], 0));
     HIP_TRY(hipMemcpyAsync(sys->d_stage[idx], sys->h_stage[idx], need * sizeof(int32_t), hipMemcpyHostToDevice, fs));
     HIP_TRY(hipEventRecord(sys->ev_fact[idx][0], fs));
     if (w.nb > 0) {
@@ -1756,8 +1826,12 @@ class CoreRun {
   bool have_next_ = false;
   int64_t t_ = 0, t_start_ = 0, hits_ = 0, misses_ = 0, launches_ = 0;
   bool converged_ = false, finished_ = false, stalled_ = false, planned_ = false, dual_ = false;
-  bool mirrored_ = false;
-  uint32_t mirror_expect_ = 0;
+  struct Launch {
+    bool mirrored;
+    uint32_t seq;
+  };
+  std::deque<Launch> launches_in_flight_;
+  int64_t last_ran_ = 0;
   double true_rel_ = NAN, t_factor_ = 0.0, t_kernel_ = 0.0;
   kpp::DevState hs_{};
   std::vector<double> e1_hist_;
@@ -1781,39 +1855,81 @@ kpp_status solve_core(kpp_system* sys, const kpp_params* p, const Source& src, c
   hipStream_t st = sys->ctx->stream;
   CoreRun run;
   KPP_TRY(run.begin(sys, p, src, o, x, 1, 0));
-  // launch k is timed by the event pair ev[2 (k % 2)], ev[2 (k % 2) + 1],
-  // read once launch k + 1 is enqueued (launch k has then retired or is
-  // retiring: the host may see its end state before the stream does)
-  int pair = 0;
-  bool pending = false;
-  auto take_time = [&](int pr) -> kpp_status {
-    float ms = 0.0f;
-    HIP_TRY(hipEventSynchronize(sys->ev[2 * pr + 1]));
-    HIP_TRY(hipEventElapsedTime(&ms, sys->ev[2 * pr], sys->ev[2 * pr + 1]));
-    run.add_kernel_seconds(1e-3 * ms);
-    return KPP_OK;
-  };
-  while (!run.finished()) {
-    kpp::FusedArgs a;
-    KPP_TRY(run.prepare(&a));
-    HIP_TRY(hipEventRecord(sys->ev[2 * pair], st));
+  // Each launch is timed by an event pair (ev[0..1] or ev[2..3], in turn),
+  // read when the host retires the launch, unless the caller turned launch
+  // timing off; a launch enqueued ahead that ran no step is neither timed
+  // nor counted.
+  std::deque<int> pairs;   // event pair of each launch in flight, oldest first
+  int next_pair = 0;
+  auto launch = [&](bool ahead) -> kpp_status {
+    kpp::FusedArgs a{};
+    const int wi = ahead ? (run.cur_window() ^ 1) : run.cur_window();
+    if (ahead)
+      KPP_TRY(run.prepare_ahead(&a));
+    else
+      KPP_TRY(run.prepare(&a));
+    const int pr = next_pair;
+    next_pair ^= 1;
+    if (o.time_launches) HIP_TRY(hipEventRecord(sys->ev[2 * pr], st));
     if (run.fused()) {
       run.mirror_args(&a);
       kpp::launch_fused(run.kind(), run.prec(), a, run.cpl(), run.groups(), st);
-      run.count_fused_launch();
     } else {
       KPP_TRY(run.launch_unfused());
     }
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipEventRecord(sys->ev[2 * pair + 1], st));
-    if (pending) KPP_TRY(take_time(pair ^ 1));
-    pending = true;
-    KPP_TRY(run.after_launch());
+    if (o.time_launches) HIP_TRY(hipEventRecord(sys->ev[2 * pr + 1], st));
+    KPP_TRY(run.note_launch(a, wi));
+    pairs.push_back(pr);
+    return KPP_OK;
+  };
+  // the oldest launch: its end state, the checkpoint, its time
+  auto retire = [&]() -> kpp_status {
     KPP_TRY(run.wait_launch());
+    const int pr = pairs.front();
+    pairs.pop_front();
     KPP_TRY(run.finish());
-    pair ^= 1;
+    if (run.last_ran() > 0) {
+      if (o.time_launches) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventSynchronize(sys->ev[2 * pr + 1]));
+        HIP_TRY(hipEventElapsedTime(&ms, sys->ev[2 * pr], sys->ev[2 * pr + 1]));
+        run.add_kernel_seconds(1e-3 * ms);
+      }
+      if (run.fused()) run.count_fused_launch();
+    }
+    return KPP_OK;
+  };
+  // (a run can be over before its first window: max_iters reached already)
+  if (!run.finished()) {
+    KPP_TRY(launch(false));
+    KPP_TRY(run.after_launch());
   }
-  if (pending) KPP_TRY(take_time(pair ^ 1));
+  while (!run.finished()) {
+    // the next window goes to the stream before this one ends
+    const bool ahead = run.can_launch_ahead();
+    if (ahead) KPP_TRY(launch(true));
+    KPP_TRY(retire());
+    if (run.finished()) break;
+    if (ahead) {
+      if (run.state().cand) {
+        // the stop test passed but the true residual did not confirm it:
+        // the launch enqueued ahead ran no step; launch the window again
+        KPP_TRY(retire());
+        if (run.finished()) break;
+        KPP_TRY(launch(false));
+      }
+      KPP_TRY(run.after_launch());
+      continue;
+    }
+    KPP_TRY(launch(false));
+    KPP_TRY(run.after_launch());
+  }
+  // a launch enqueued ahead of the stop ran no step: let it leave the stream
+  while (run.launches_in_flight() > 0) {
+    KPP_TRY(run.wait_launch());
+    pairs.pop_front();
+  }
   KPP_TRY(run.end(cs));
   if (o.keep_state) run.keep_state();
   return KPP_OK;
@@ -1894,6 +2010,7 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
   o.max_iters = p->max_iters;
   o.resume = p->resume != 0;
   o.keep_state = true;
+  o.time_launches = p->no_launch_timing == 0;
   if (!o.resume) sys->res_valid = false;
   CoreStats cs;
   KPP_TRY(solve_core(sys, p, src, o, x, &cs));
@@ -2002,6 +2119,7 @@ kpp_status solve_mixed(kpp_system* sys, const kpp_params* p, double* x, kpp_resu
     o.tol = p->inner_tol;
     o.confirm = 0;
     o.stop_on_stall = 1;
+    o.time_launches = p->no_launch_timing == 0;
     o.rho0 = rho;
     o.keep_memo = rounds > 0 ? 1 : p->keep_memo;
     o.max_iters = p->max_iters - iters;
@@ -3206,17 +3324,23 @@ kpp_status alloc_system(kpp_context* ctx, int32_t kind, int64_t m, int64_t n, co
   }
   if (hipHostMalloc(reinterpret_cast<void**>(&sys->h_ds), sizeof(kpp::DevState), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&sys->h_err), 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&sys->h_mirror), sizeof(kpp::HostMirror),
+      hipHostMalloc(reinterpret_cast<void**>(&sys->h_mirror), 2 * sizeof(kpp::HostMirror),
                     hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
     destroy_buffers(sys.get());
     return fail(KPP_ERR_OOM, "pinned host allocation failed");
   }
-  std::memset(sys->h_mirror, 0, sizeof(kpp::HostMirror));
+  std::memset(sys->h_mirror, 0, 2 * sizeof(kpp::HostMirror));
   if (hipHostGetDevicePointer(reinterpret_cast<void**>(&sys->d_mirror), sys->h_mirror, 0) != hipSuccess) {
     destroy_buffers(sys.get());
     return fail(KPP_ERR_HIP, "hipHostGetDevicePointer failed");
   }
   for (auto& e : sys->ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      destroy_buffers(sys.get());
+      return fail(KPP_ERR_HIP, "hipEventCreate failed");
+    }
+  }
+  for (auto& e : sys->ev_win) {
     if (hipEventCreate(&e) != hipSuccess) {
       destroy_buffers(sys.get());
       return fail(KPP_ERR_HIP, "hipEventCreate failed");

@@ -278,6 +278,44 @@ static void sparse_misc() {
   free_csr(a); free_csr(c); hipFree(b); hipFree(bc); hipFree(x); hipFree(B); hipFree(X); hipFree(L); hipFree(Lc);
 }
 
+namespace kpp {
+extern int g_emu_refuse_confirms;
+extern int64_t g_emu_ahead_launches, g_emu_skipped_launches;
+}
+
+// Launches enqueued ahead of the current one: a FP64 solve to a tolerance
+// enqueues the next window before the current one ends; when the host turns
+// down a stop candidate (its true residual is too large) the launch enqueued
+// ahead has run no step and the window is launched again, so the solve goes on
+// to a later checkpoint and ends there.
+static void ahead_case(int kind, int64_t m, int64_t n, int s) {
+  kpp_context* ctx; CHECK(kpp_context_create(0, nullptr, &ctx));
+  double* A = dev_vec(m * n, 0.5); double* b = dev_vec(m, 1.0); double* x = dev_vec(n, 0.0);
+  kpp_system* sys; CHECK(kpp_system_create(ctx, kind, m, n, A, n, b, &sys));
+  int64_t iters[2] = {0, 0}, skipped[2] = {0, 0}, ahead[2] = {0, 0};
+  for (int refuse = 0; refuse < 2; ++refuse) {
+    kpp_params p; CHECK(kpp_params_default(&p, kind));
+    p.block_size = s; p.engine = 2; p.max_iters = 20000; p.tol = 1e-10; p.seed = 31; p.lambda = 1e-3;
+    kpp::g_emu_refuse_confirms = refuse ? 2 : 0;
+    kpp::g_emu_ahead_launches = kpp::g_emu_skipped_launches = 0;
+    for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+    kpp_result r; CHECK(kpp_solve(sys, &p, x, &r));
+    if (!r.converged) { std::printf("FAIL ahead: not converged (refuse %d)\n", refuse); std::exit(1); }
+    iters[refuse] = r.iters; skipped[refuse] = kpp::g_emu_skipped_launches; ahead[refuse] = kpp::g_emu_ahead_launches;
+    std::printf("ahead kind=%d refuse=%d iters=%lld launches=%lld ahead=%lld skipped=%lld\n", kind, refuse,
+                (long long)r.iters, (long long)r.kernel_launches, (long long)ahead[refuse], (long long)skipped[refuse]);
+  }
+  // every launch but the first is enqueued ahead; one skip at the stop, and
+  // one more for each turned-down candidate
+  if (ahead[0] < 2 || skipped[0] != 1 || skipped[1] != 3 || iters[1] <= iters[0]) {
+    std::printf("FAIL ahead: iters %lld / %lld, skipped %lld / %lld\n", (long long)iters[0], (long long)iters[1],
+                (long long)skipped[0], (long long)skipped[1]);
+    std::exit(1);
+  }
+  CHECK(kpp_system_destroy(sys)); CHECK(kpp_context_destroy(ctx));
+  hipFree(A); hipFree(b); hipFree(x);
+}
+
 int main(int argc, char** argv) {
   const char* only = argc > 1 ? argv[1] : "";
   if (!*only || !std::strcmp(only, "solve")) {
@@ -295,6 +333,10 @@ int main(int argc, char** argv) {
     solve_case("bf16_c3_small", 0, 6000, 700, 256, 2, 1, 0, 0, 2, 20000, 1e-10);
     solve_case("bf16_c4_small", 0, 300, 5000, 64, 1, 1, 0, 0, 2, 20000, 1e-10);
     solve_case("bf16_psd", 1, 1000, 1000, 128, 1, 1, 0, 0, 2, 20000, 1e-10);
+    // no step at all (max_iters = 0): nothing is launched
+    solve_case("zero_steps", 0, 40, 10, 4, 1, 1, 0, 2, 0, 0, 0.0);
+    ahead_case(0, 300, 5000, 64);
+    ahead_case(1, 1000, 1000, 128);
     resume_case(1, 600, 600, 64);
     resume_case(0, 900, 300, 40);
     rht_case(0, 5000, 12, 16);

@@ -168,6 +168,12 @@ void launch_scatter_rows(const int32_t* stage_rows, const int32_t* stage_lens, c
     lens[slot_of[k]] = stage_lens[k];
   }
 }
+// scenario switches (set by the driver): the next g_emu_refuse_confirms true
+// residuals come out huge, so that the host turns down that many stop
+// candidates; counts of step-kernel launches enqueued ahead and of those that
+// ran no step
+int g_emu_refuse_confirms = 0;
+int64_t g_emu_ahead_launches = 0, g_emu_skipped_launches = 0;
 void launch_residual_sq(const double* A, int64_t lda, int64_t m, int64_t n, const double* x, const double* b,
                         double* part, int32_t, double* out, hipStream_t) {
   emu_check(A, 8 * (static_cast<size_t>(m - 1) * lda + n), "residual A");
@@ -176,6 +182,10 @@ void launch_residual_sq(const double* A, int64_t lda, int64_t m, int64_t n, cons
   emu_check(part, 8 * m, "residual rowsq");
   emu_check(out, 8, "residual out");
   *out = 0.0;
+  if (g_emu_refuse_confirms > 0) {
+    --g_emu_refuse_confirms;
+    *out = 1e300;
+  }
 }
 void launch_check_finite(const double* A, int64_t lda, int64_t m, int64_t n, const double* b, int32_t* flag,
                          hipStream_t) {
@@ -375,7 +385,13 @@ static void check_epoch(const FusedArgs& a, int64_t steps_run) {
 
 static void emu_fused(const FusedArgs& a, int32_t cpl, int32_t G, size_t esz) {
   const int64_t s = a.s;
-  emu_check(a.step_slot, 4 * static_cast<size_t>(a.W), "fused step_slot");
+  // the kernel reads the first step's slot (and its length) before its step
+  // loop, whatever W is, unless it is a launch enqueued ahead that skips
+  emu_check(a.ds, sizeof(DevState), "fused ds");
+  if (a.W > 0 && !(a.skip_on_cand && a.ds->cand)) {
+    emu_check(a.step_slot, 4 * static_cast<size_t>(a.W), "fused step_slot");
+    emu_check(a.lens + a.step_slot[0], 4, "fused first lens");
+  }
   emu_check(a.x, 8 * a.n, "fused x");
   emu_check(a.mom, 8 * a.n, "fused mom");
   emu_check(a.part, 8 * 2 * static_cast<size_t>(G) * s, "fused part");
@@ -402,7 +418,12 @@ static void emu_fused(const FusedArgs& a, int32_t cpl, int32_t G, size_t esz) {
     if ((a.mrows + G - 1) / G > 1024) { std::fprintf(stderr, "EMU: dual slice too long\n"); std::abort(); }
   }
   int64_t ran = 0;
-  for (int k = 0; k < a.W; ++k) {
+  // a launch enqueued ahead runs no step after a checkpoint whose stop test passed
+  emu_check(a.ds, sizeof(DevState), "fused ds");
+  const int W = (a.skip_on_cand && a.ds->cand) ? 0 : a.W;
+  if (a.skip_on_cand) ++g_emu_ahead_launches;
+  if (a.skip_on_cand && W == 0) ++g_emu_skipped_launches;
+  for (int k = 0; k < W; ++k) {
     const int q = a.step_slot[k];
     emu_check(a.lens + q, 4, "fused lens");
     const int sb = a.lens[q];

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(kpp):
     for name in syms:
         assert hasattr(raw, name), name
     assert set(syms) == set(kpp.EXPORTED)
-    assert kpp.kpp_abi_version() == 5
+    assert kpp.kpp_abi_version() == 6
 
 
 def test_params_default_and_validation(kpp):

@@ -576,3 +576,40 @@ def test_mixed_inner_round_ends_at_precision_floor(env):
           flush=True)
     assert st == kpp.KPP_OK and res.true_rel_res <= 1e-10
     assert res.iters < 50_000
+
+
+@pytest.mark.parametrize("name,kind,s,lam", [("c2_small", "psd", 128, 1e-8), ("c4_small", "general", 64, 1e-4)])
+def test_untimed_launches_change_nothing(env, name, kind, s, lam):
+    """Solves to a tolerance with the next window's launch enqueued before the
+    current one ends, with and without per-launch HIP events: the same iterate
+    bit for bit, the same steps and launches; without events no kernel time."""
+    kpp, torch, dev, ctx = env
+    sysm = synth.config(name)
+    m, n = sysm.A.shape
+    ck = kpp.KPP_CD_PSD if kind == "psd" else kpp.KPP_KACZMARZ
+    Ad = torch.from_numpy(np.ascontiguousarray(sysm.A)).to(dev)
+    bd = torch.from_numpy(np.ascontiguousarray(sysm.b)).to(dev)
+    h = kpp.kpp_system_create(ctx, ck, m, n, Ad.data_ptr(), n, bd.data_ptr())
+    try:
+        out = []
+        for untimed in (0, 1, 0):
+            p = kpp.kpp_params_default(ck)
+            p.block_size = s
+            p.lambda_ = lam
+            p.tol = 1e-10
+            p.max_iters = 50000
+            p.seed = 5
+            p.engine = 2
+            p.no_launch_timing = untimed
+            xd = torch.zeros(n, dtype=torch.float64, device=dev)
+            st, res = kpp.kpp_solve(h, p, xd.data_ptr())
+            torch.cuda.synchronize()
+            out.append((st, res, xd.cpu().numpy()))
+        for st, res, _ in out:
+            assert st == 0 and res.converged == 1 and res.engine_used == 2
+        (_, r0, x0), (_, r1, x1), (_, r2, x2) = out
+        assert np.array_equal(x0, x1) and np.array_equal(x0, x2)
+        assert r0.iters == r1.iters == r2.iters and r0.kernel_launches == r1.kernel_launches
+        assert r1.kernel_seconds == 0.0 and r0.kernel_seconds > 0.0 and r2.kernel_seconds > 0.0
+    finally:
+        kpp.kpp_system_destroy(h)
