@@ -1039,6 +1039,7 @@ __global__ __launch_bounds__(kT) void k_factor_small(double* __restrict__ slots,
   double* Dv = fl + kFLower * kFTile;              // inverses of the diagonal tiles of L
   double* Sc = Dv + kFMaxT * kFTile;               // one scratch tile per wave
   __shared__ double red4[4];
+  __shared__ double rdiag[kFT];   // 1 / L_jj of the diagonal tile being inverted
   __shared__ double norm_g2;
   __shared__ int flag_blk;
   const int blk = blockIdx.x;
@@ -1048,22 +1049,45 @@ __global__ __launch_bounds__(kT) void k_factor_small(double* __restrict__ slots,
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nt = (sb + kFT - 1) / kFT;
   const int nlow = nt * (nt + 1) / 2;
-  // G (lower triangle of the slot) into the tiles, identity past the block
+  // G (lower triangle of the slot) into the tiles, identity past the block:
+  // thread tid holds entry (r, c) = (tid % 16, tid / 16) of every tile; the
+  // loads of kGB tiles go out together (one after the other they are a chain
+  // of global round trips)
   double g2 = 0.0;
-  for (int e = tid; e < nlow * 256; e += kT) {
-    const int t = e >> 8, w = e & 255, c = w >> 4, r = w & 15;
-    int ti = 0;
-    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-    const int tj = t - ti * (ti + 1) / 2;
-    const int i = ti * kFT + r, k = tj * kFT + c;
-    double v;
-    if (i < sb && k < sb) {
-      v = i >= k ? Lc[static_cast<int64_t>(k) * s + i] : 0.0;
-      g2 += (i == k ? 1.0 : 2.0) * v * v;
-    } else {
-      v = i == k ? 1.0 : 0.0;
+  {
+    constexpr int kGB = 12;
+    const int c = tid >> 4, r = tid & 15;
+    for (int t0 = 0; t0 < nlow; t0 += kGB) {
+      double v[kGB];
+      int ti = 0;
+      while ((ti + 1) * (ti + 2) / 2 <= t0) ++ti;
+      int tj = t0 - ti * (ti + 1) / 2;
+#pragma unroll
+      for (int u = 0; u < kGB; ++u) {
+        const int i = ti * kFT + r, k = tj * kFT + c;
+        const bool in = t0 + u < nlow && i < sb && k < sb;
+        v[u] = (in && i >= k) ? Lc[static_cast<int64_t>(k) * s + i] : ((i == k && !(i < sb && k < sb)) ? 1.0 : 0.0);
+        if (++tj > ti) {
+          ++ti;
+          tj = 0;
+        }
+      }
+      ti = 0;
+      while ((ti + 1) * (ti + 2) / 2 <= t0) ++ti;
+      tj = t0 - ti * (ti + 1) / 2;
+#pragma unroll
+      for (int u = 0; u < kGB; ++u) {
+        const int i = ti * kFT + r, k = tj * kFT + c;
+        if (t0 + u < nlow) {
+          if (i < sb && k < sb) g2 += (i == k ? 1.0 : 2.0) * v[u] * v[u];
+          T[(t0 + u) * kFTile + c * kFLd + r] = v[u];
+        }
+        if (++tj > ti) {
+          ++ti;
+          tj = 0;
+        }
+      }
     }
-    T[t * kFTile + c * kFLd + r] = v;
   }
   if (chk.flag) {
     g2 = block_sum(g2, red4);
@@ -1087,6 +1111,7 @@ __global__ __launch_bounds__(kT) void k_factor_small(double* __restrict__ slots,
         bad |= !(d > 0.0);
         const double ljj = sqrt(d);
         const double rl = 1.0 / ljj;
+        if (lane == 0) rdiag[j] = rl;
         a[j] = r > j ? a[j] * rl : (r == j ? ljj : a[j]);
 #pragma unroll
         for (int k = j + 1; k < kFT; ++k) {
@@ -1108,7 +1133,7 @@ __global__ __launch_bounds__(kT) void k_factor_small(double* __restrict__ slots,
         double acc = 0.0;
 #pragma unroll
         for (int m = 0; m < i; ++m) acc = fma(Tp[m * kFLd + i], x[m], acc);
-        const double inv = 1.0 / Tp[i * kFLd + i];
+        const double inv = rdiag[i];   // the same 1 / L_ii the factorization formed
         x[i] = i == kc ? inv : (i > kc ? -acc * inv : 0.0);
       }
       if (lane < kFT) {
@@ -1169,6 +1194,7 @@ __global__ __launch_bounds__(kT) void k_factor_small(double* __restrict__ slots,
   }
   __syncthreads();
   // L to the slot (column-major, zero outside the block's lower triangle)
+#pragma unroll 8
   for (int e = tid; e < s * s; e += kT) {
     const int i = e % s, k = e / s;
     Lc[static_cast<int64_t>(k) * s + i] =
