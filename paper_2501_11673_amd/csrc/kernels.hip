@@ -669,33 +669,90 @@ __global__ __launch_bounds__(kT) void k_factor_inverse(double* __restrict__ slot
 // memo miss for blocks of kLdsCholMax+1 .. kFusedMaxBlock rows, blocked in LDS.
 //
 // k_cholesky_panel: left-looking Cholesky in panels of kPanel columns.  The
-// panel (rows p0 .. sb-1 of columns p0 .. p0+pw-1) and the rows of L it
-// depends on (L(p0 + c, k), k < p0) sit in LDS; thread i brings panel row i
-// up to date with the finished columns of L (read from the slot, coalesced
-// over i, against LDS broadcasts), then the panel is factored column by
-// column in LDS and written back.  With chk.flag it leaves ||G||_F^2 in the
-// first entry of the slot's last third.
+// panel (rows p0 .. sb-1 of columns p0 .. p0+pw-1) sits in LDS; the matrix
+// cores bring it up to date with the finished columns of L (read from the
+// slot), then the panel is factored column by column in LDS and written back.
+// With chk.flag it leaves ||G||_F^2 in the first entry of the slot's last
+// third.
 // --------------------------------------------------------------------------
 constexpr int kPanel = 32;
 constexpr int kPanelLd = kPanel + 1;
 
-// acc[c] += f * row[c], c < 32, with the LDS row read in 16-byte loads issued
-// together (row 16-byte aligned)
-__device__ __forceinline__ void axpy_row32(double (&acc)[32], double f, const double* row) {
-  const double2* r2 = reinterpret_cast<const double2*>(row);
-  double2 v[16];
+constexpr size_t kCholPanelLds = static_cast<size_t>(kFusedMaxBlock) * kPanelLd * sizeof(double);
+// diagonal blocks of L in LDS for the inverse, 32 x 32 each, two doubles of
+// padding between blocks so that the two blocks a wave reads sit in different banks
+constexpr int kLdBlock = kPanel * kPanel + 2;
+static_assert(kPanel == 32, "the inverse's LDS staging indexes blocks of 32 x 32 with shifts");
+constexpr size_t kInverseBlockedLds = static_cast<size_t>(kFusedMaxBlock / kPanel) * kLdBlock * sizeof(double);
+
+// The panel update of the Cholesky on the matrix cores (FP64 16x16x4, the
+// operand layout of k_block_gemm_mfma): P(i, c) -= sum_{k < p0} L(p0 + i, k)
+// L(p0 + c, k) for the R rows and pw columns of the panel, both operands read
+// from the finished columns of L in the slot (column-major, 16 consecutive
+// rows a lane group), the sums started from the panel in LDS.  Wave wv owns
+// row tiles wv, wv + 4, ... (at most four: R <= kFusedMaxBlock - kPanel) and
+// both column tiles; k advances 16 at a time with the next 16 in flight.
+__device__ __forceinline__ void chol_panel_update(double* P, const double* Gb, int32_t s, int p0, int R, int pw,
+                                                  int lane, int wv) {
+  const int cl = lane & 15, kq = lane >> 4;
+  const int NTr = (R + 15) >> 4;
+  v4d_m acc[4][2];
 #pragma unroll
-  for (int c = 0; c < 16; ++c) v[c] = r2[c];
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    acc[2 * c] = fma(f, v[c].x, acc[2 * c]);
-    acc[2 * c + 1] = fma(f, v[c].y, acc[2 * c + 1]);
+    for (int tc = 0; tc < 2; ++tc)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * (wv + 4 * t) + 4 * r + kq, c = 16 * tc + cl;
+        acc[t][tc][r] = (i < R && c < pw) ? P[i * kPanelLd + c] : 0.0;
+      }
+  double av[2][4][4], bv[2][4][2];
+  auto fetch = [&](int b, int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double* Lk = Gb + static_cast<int64_t>(k0 + 4 * q + kq) * s + p0;   // L(p0 + i, k) at Lk[i]
+#pragma unroll
+      for (int tc = 0; tc < 2; ++tc) bv[b][q][tc] = 16 * tc + cl < pw ? Lk[16 * tc + cl] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int i = 16 * (wv + 4 * t) + cl;
+        av[b][q][t] = i < R ? -Lk[i] : 0.0;
+      }
+    }
+  };
+  fetch(0, 0);
+  for (int k0 = 0; k0 < p0; k0 += 32) {   // p0 is a multiple of kPanel
+    if (k0 + 16 < p0) fetch(1, k0 + 16);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (wv + 4 * t < NTr)
+#pragma unroll
+          for (int tc = 0; tc < 2; ++tc)
+            acc[t][tc] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0][q][t], bv[0][q][tc], acc[t][tc], 0, 0, 0);
+    if (k0 + 32 < p0) fetch(0, k0 + 32);
+    if (k0 + 16 < p0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (wv + 4 * t < NTr)
+#pragma unroll
+            for (int tc = 0; tc < 2; ++tc)
+              acc[t][tc] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1][q][t], bv[1][q][tc], acc[t][tc], 0, 0, 0);
+    }
   }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int tc = 0; tc < 2; ++tc)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * (wv + 4 * t) + 4 * r + kq, c = 16 * tc + cl;
+        if (i < R && c < pw) P[i * kPanelLd + c] = acc[t][tc][r];
+      }
 }
-constexpr size_t kCholPanelLds =
-    (static_cast<size_t>(kFusedMaxBlock) * kPanelLd + static_cast<size_t>(kFusedMaxBlock) * kPanel) * sizeof(double);
-constexpr size_t kInverseBlockedLds =
-    (static_cast<size_t>(kPanel) * kFusedMaxBlock + static_cast<size_t>(kPanel) * kPanelLd) * sizeof(double);
 
 __global__ __launch_bounds__(kT) void k_cholesky_panel(double* __restrict__ G, int32_t s, int64_t stride,
                                                        const int32_t* __restrict__ lens,
@@ -703,8 +760,8 @@ __global__ __launch_bounds__(kT) void k_cholesky_panel(double* __restrict__ G, i
                                                        int32_t* __restrict__ err, FactorCheck chk) {
   extern __shared__ double lds[];
   double* P = lds;                                  // P[i * kPanelLd + c] = G(p0 + i, p0 + c)
-  double* Lt = lds + kFusedMaxBlock * kPanelLd;     // Lt[k * kPanel + c] = L(p0 + c, k), k < p0
   __shared__ double red4[4];
+  __shared__ double diag_hi[4];
   __shared__ double colbuf[kPanel];
   __shared__ double piv;
   __shared__ int bad_any;
@@ -731,32 +788,16 @@ __global__ __launch_bounds__(kT) void k_cholesky_panel(double* __restrict__ G, i
   int bad = 0;
   for (int p0 = 0; p0 < sb; p0 += kPanel) {
     const int pw = min(kPanel, sb - p0), R = sb - p0;
-    for (int e = tid; e < R * pw; e += kT) {
-      const int c = e / R, i = e - c * R;
-      P[i * kPanelLd + c] = Gb[static_cast<int64_t>(p0 + c) * s + p0 + i];
-    }
-    for (int e = tid; e < p0 * pw; e += kT) {
-      const int k = e / pw, c = e - k * pw;
-      Lt[k * kPanel + c] = Gb[static_cast<int64_t>(k) * s + p0 + c];
+    if (tid < R) {
+      // panel row tid, its loads all in flight (coalesced over the threads)
+      double v[kPanel];
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c) v[c] = c < pw ? Gb[static_cast<int64_t>(p0 + c) * s + p0 + tid] : 0.0;
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c) P[tid * kPanelLd + c] = v[c];
     }
     __syncthreads();
-    if (p0 > 0 && tid < R) {
-      double acc[kPanel];
-#pragma unroll
-      for (int c = 0; c < kPanel; ++c) acc[c] = c < pw ? P[tid * kPanelLd + c] : 0.0;
-      const double* Lrow = Gb + p0 + tid;
-      // p0 is a multiple of kPanel: eight entries of this row of L in flight
-      for (int k0 = 0; k0 < p0; k0 += 8) {
-        double l8[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) l8[q] = Lrow[static_cast<int64_t>(k0 + q) * s];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) axpy_row32(acc, -l8[q], Lt + (k0 + q) * kPanel);
-      }
-#pragma unroll
-      for (int c = 0; c < kPanel; ++c)
-        if (c < pw) P[tid * kPanelLd + c] = acc[c];
-    }
+    if (p0 > 0) chol_panel_update(P, Gb, s, p0, R, pw, tid & 63, tid >> 6);
     __syncthreads();
     // factor the panel with row tid in registers: per column, the pivot and
     // the column's entries in the panel's first rows go through LDS
@@ -788,14 +829,26 @@ __global__ __launch_bounds__(kT) void k_cholesky_panel(double* __restrict__ G, i
     __syncthreads();
   }
   if (bad) atomicOr(&bad_any, 1);
+  // smallest and largest diagonal entry of L (fmin / fmax: any order gives the same result)
+  double lo = 1.0 / 0.0, hi = 0.0;
+  if (tid < sb) {
+    const double d = Gb[static_cast<int64_t>(tid) * s + tid];
+    lo = d;
+    hi = d;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_down(lo, off, 64));
+    hi = fmax(hi, __shfl_down(hi, off, 64));
+  }
+  if ((tid & 63) == 0) {
+    red4[tid >> 6] = lo;
+    diag_hi[tid >> 6] = hi;
+  }
   __syncthreads();
   if (tid == 0) {
-    double lo = 1.0 / 0.0, hi = 0.0;
-    for (int i = 0; i < sb; ++i) {
-      const double d = Gb[static_cast<int64_t>(i) * s + i];
-      lo = fmin(lo, d);
-      hi = fmax(hi, d);
-    }
+    lo = fmin(fmin(red4[0], red4[1]), fmin(red4[2], red4[3]));
+    hi = fmax(fmax(diag_hi[0], diag_hi[1]), fmax(diag_hi[2], diag_hi[3]));
     const double ratio = hi / lo;
     const bool ill = !(ratio * ratio <= chk.kappa_max);
     if (chk.flag) {
@@ -806,102 +859,207 @@ __global__ __launch_bounds__(kT) void k_cholesky_panel(double* __restrict__ G, i
       atomicOr(err, 1);
     }
   }
-  // zero strict upper triangle and padding
-  for (int e = tid; e < s * s; e += kT) {
-    const int k = e / s, i = e - k * s;
-    if (!(i < sb && k < sb && i >= k)) Gb[static_cast<int64_t>(k) * s + i] = 0.0;
-  }
+  // zero strict upper triangle and padding: thread i clears row i (s <= kT)
+  if (tid < s)
+    for (int k = 0; k < s; ++k)
+      if (tid >= sb || k >= sb || k > tid) Gb[static_cast<int64_t>(k) * s + tid] = 0.0;
 }
 
 // --------------------------------------------------------------------------
-// G^{-1} = L^{-T} L^{-1} of a block of kLdsCholMax+1 .. kFusedMaxBlock rows,
-// blocked in LDS.  X = L^{-1} is formed one block row of kPanel rows at a time
-// (X_rr = L_rr^{-1} by substitution in LDS; X_rq = -X_rr sum_k L_rk X_kq for
-// the columns to the left: thread j owns column j, reads it from the slot's
-// last third, where X is kept row-major, and the block row of L from LDS);
-// then G^{-1}(i, j) = sum_{k >= max(i, j)} X(k, i) X(k, j) with the columns of
-// X for 32 rows i at a time staged in LDS.  Entries (i, j) and (j, i) are summed
-// in the same order, so the stored inverse is exactly symmetric.  With chk.flag
-// the Frobenius condition number is tested as in k_factor_inverse.
+// G^{-1} = L^{-T} L^{-1} of a block of kLdsCholMax+1 .. kFusedMaxBlock rows.
+// X = L^{-1}: first the diagonal blocks X_rr = L_rr^{-1} of kPanel rows, all
+// at once by substitution (thread (r, c) forms column c of block r from the
+// block staged in LDS); then one block row at a time the columns to the left,
+// X_rq = -X_rr T with T = sum_k L_rk X_kq, on the matrix cores (FP64
+// 16x16x4, the operand layout of k_block_gemm_mfma).  X is kept row-major in
+// the slot's last third.  Then G^{-1}(i, j) = sum_{k >= max(i, j)}
+// X(k, i) X(k, j), the 16 x 16 tiles of the lower triangle on the matrix cores
+// and each stored with its mirror image, so the inverse is exactly symmetric.
+// Entries of X above the diagonal and past the block are never read (the
+// loads are masked).  With chk.flag the Frobenius condition number is tested
+// as in k_factor_inverse.
 // --------------------------------------------------------------------------
+
+// Column tile jt of X_rq (rows r0 .. r0 + w - 1, columns 16 jt .. 16 jt + 15,
+// r0 > 0 a multiple of kPanel).  T(a, j) = sum_{k = j}^{r0 - 1} L(r0 + a, k)
+// X(k, j) for the block row's two 16-row tiles, k advancing 16 at a time with
+// the next 16 in flight; then X(r0 + a, j) = -sum_b X_rr(a, b) T(b, j), where
+// register q of T's tile is the 4 x 16 operand of the q-th k step as it stands.
+__device__ __forceinline__ void inv_xrq_tile(double* X, const double* Lc, int32_t s, int r0, int w, int jt,
+                                             int lane) {
+  const int cl = lane & 15, kq = lane >> 4;
+  const int cb = 16 * jt + cl;
+  v4d_m t0 = {0.0, 0.0, 0.0, 0.0}, t1 = {0.0, 0.0, 0.0, 0.0};
+  double a0[2][4], a1[2][4], bx[2][4];
+  auto fetch = [&](int b, int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + 4 * q + kq;
+      const double* Lk = Lc + static_cast<int64_t>(k) * s + r0;   // L(r0 + a, k) at Lk[a]
+      a0[b][q] = cl < w ? Lk[cl] : 0.0;
+      a1[b][q] = 16 + cl < w ? Lk[16 + cl] : 0.0;
+      bx[b][q] = cb <= k ? X[static_cast<int64_t>(k) * s + cb] : 0.0;
+    }
+  };
+  auto mma = [&](int b) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      t0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[b][q], bx[b][q], t0, 0, 0, 0);
+      t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[b][q], bx[b][q], t1, 0, 0, 0);
+    }
+  };
+  // r0 - 16 jt is a multiple of 16
+  int k0 = 16 * jt;
+  fetch(0, k0);
+  for (; k0 + 16 < r0; k0 += 32) {
+    fetch(1, k0 + 16);
+    mma(0);
+    if (k0 + 32 < r0) fetch(0, k0 + 32);
+    mma(1);
+  }
+  if (k0 < r0) mma(0);
+  v4d_m o0 = {0.0, 0.0, 0.0, 0.0}, o1 = {0.0, 0.0, 0.0, 0.0};
+  const double* Xr0 = X + static_cast<int64_t>(r0 + cl) * s + r0;        // X(r0 + a, r0 + b) at Xr0[b], a = cl
+  const double* Xr1 = X + static_cast<int64_t>(r0 + 16 + cl) * s + r0;   // a = 16 + cl
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int b0 = 4 * q + kq, b1 = 16 + 4 * q + kq;
+    const double x00 = cl < w && b0 < w ? Xr0[b0] : 0.0;
+    const double x10 = 16 + cl < w && b0 < w ? Xr1[b0] : 0.0;
+    const double x01 = cl < w && b1 < w ? Xr0[b1] : 0.0;
+    const double x11 = 16 + cl < w && b1 < w ? Xr1[b1] : 0.0;
+    o0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x00, t0[q], o0, 0, 0, 0);
+    o1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x10, t0[q], o1, 0, 0, 0);
+    o0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x01, t1[q], o0, 0, 0, 0);
+    o1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x11, t1[q], o1, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int a = 4 * r + kq;
+    if (a < w) X[static_cast<int64_t>(r0 + a) * s + cb] = -o0[r];
+    if (16 + a < w) X[static_cast<int64_t>(r0 + 16 + a) * s + cb] = -o1[r];
+  }
+}
+
+// Tiles (ti, tj0 .. tj0 + CNT - 1), tj0 + CNT - 1 <= ti, of G^{-1} = X^T X:
+// sum over k = 16 ti .. sb - 1 of X(k, 16 ti + a) X(k, 16 tj + b) (the terms
+// with k < 16 ti vanish: X is lower triangular), k advancing 16 at a time with
+// the next 16 in flight.  Lower entries and their mirror images are stored;
+// on a diagonal tile only a >= b.
+template <int CNT>
+__device__ __forceinline__ void ginv_tiles(double* Gi, const double* X, int32_t s, int sb, int ti, int tj0, int lane) {
+  const int cl = lane & 15, kq = lane >> 4;
+  const int ca = 16 * ti + cl;
+  v4d_m acc[CNT];
+#pragma unroll
+  for (int t = 0; t < CNT; ++t) acc[t] = v4d_m{0.0, 0.0, 0.0, 0.0};
+  double av[2][4], bv[2][4][CNT];
+  auto fetch = [&](int b, int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + 4 * q + kq;
+      const bool kin = k < sb;
+      const double* Xk = X + static_cast<int64_t>(k) * s;
+      av[b][q] = kin && ca <= k ? Xk[ca] : 0.0;
+#pragma unroll
+      for (int t = 0; t < CNT; ++t) {
+        const int cb = 16 * (tj0 + t) + cl;
+        bv[b][q][t] = kin && cb <= k ? Xk[cb] : 0.0;
+      }
+    }
+  };
+  auto mma = [&](int b) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < CNT; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[b][q], bv[b][q][t], acc[t], 0, 0, 0);
+  };
+  int k0 = 16 * ti;
+  fetch(0, k0);
+  for (; k0 + 16 < sb; k0 += 32) {
+    fetch(1, k0 + 16);
+    mma(0);
+    if (k0 + 32 < sb) fetch(0, k0 + 32);
+    mma(1);
+  }
+  if (k0 < sb) mma(0);
+#pragma unroll
+  for (int t = 0; t < CNT; ++t) {
+    const int tj = tj0 + t;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int a = 4 * r + kq;
+      const int i = 16 * ti + a, j = 16 * tj + cl;
+      if (i < sb && j < sb && (tj < ti || a >= cl)) {
+        Gi[static_cast<int64_t>(i) * s + j] = acc[t][r];
+        Gi[static_cast<int64_t>(j) * s + i] = acc[t][r];
+      }
+    }
+  }
+}
+
 template <bool LINV = false>
 __global__ __launch_bounds__(kT) void k_inverse_blocked(double* __restrict__ slots, int64_t stride, int32_t s,
                                                         const int32_t* __restrict__ lens,
                                                         const int32_t* __restrict__ slot_of, FactorCheck chk,
                                                         const int32_t* __restrict__ skip) {
-  extern __shared__ double lds[];
-  double* Lr = lds;                                 // Lr[k * kPanel + a] = L(r0 + a, k), k < r0 + w; later Xt
-  double* Xd = lds + kPanel * kFusedMaxBlock;       // Xd[a * kPanelLd + c] = X(r0 + a, r0 + c)
+  extern __shared__ double lds[];                   // diagonal blocks of L, kLdBlock doubles apart
   __shared__ double red4[4];
   const int blk = blockIdx.x;
   if ((chk.only && !chk.only[blk]) || (skip && skip[blk])) return;
   const int sb = lens[blk];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t ss = static_cast<int64_t>(s) * s;
   double* base = slots + static_cast<int64_t>(slot_of[blk]) * stride;
   const double* Lc = base;                          // L(i, k) at Lc[k * s + i]
   double* Gi = base + ss;
   double* X = base + 2 * ss;                        // X(i, j) at X[i * s + j]
   const double norm_g2 = chk.flag ? X[0] : 0.0;     // left by the Cholesky, overwritten below
+  const int npan = (sb + kPanel - 1) / kPanel;
+  // block r of LDS: Ld[k * kPanel + a] = L(32 r + a, 32 r + k), zero past the block
+  for (int e = tid; e < npan * kPanel * kPanel; e += kT) {
+    const int r = e >> 10, k = (e >> 5) & 31, a = e & 31;
+    const int r0 = r * kPanel, w = min(kPanel, sb - r0);
+    lds[r * kLdBlock + k * kPanel + a] = (a < w && k < w) ? Lc[static_cast<int64_t>(r0 + k) * s + r0 + a] : 0.0;
+  }
   __syncthreads();
-  const int j = tid;
-  for (int r0 = 0; r0 < sb; r0 += kPanel) {
-    const int w = min(kPanel, sb - r0);
-    for (int e = tid; e < kPanel * (r0 + w); e += kT) {
-      const int k = e / kPanel, a = e - k * kPanel;
-      Lr[k * kPanel + a] = a < w ? Lc[static_cast<int64_t>(k) * s + r0 + a] : 0.0;
-    }
-    // X_rr = L_rr^{-1}: thread c < w substitutes down column c
-    for (int e = tid; e < w * w; e += kT) {
-      const int a = e / w, c = e - a * w;
-      Xd[a * kPanelLd + c] = 0.0;
-    }
-    __syncthreads();
-    if (tid < w) {
-      // column c of X_rr in registers, rows i > c by substitution
-      const int c = tid;
+  {
+    // X_rr = L_rr^{-1}: column c of diagonal block r in registers, rows i > c
+    // by substitution; the block row's w x w corner of X is written whole
+    const int r = tid >> 5, c = tid & 31;
+    const int r0 = r * kPanel, w = min(kPanel, sb - r0);
+    const double* Ld = lds + r * kLdBlock;
+    if (r < npan && c < w) {
       double xc[kPanel];
 #pragma unroll
       for (int i = 0; i < kPanel; ++i) {
         double v = 0.0;
         if (i == c) {
-          v = 1.0 / Lr[(r0 + i) * kPanel + i];
+          v = 1.0 / Ld[i * kPanel + i];
         } else if (i > c && i < w) {
           double acc = 0.0;
 #pragma unroll
           for (int k = 0; k < i; ++k)
-            if (k >= c) acc = fma(Lr[(r0 + k) * kPanel + i], xc[k], acc);
-          v = -acc / Lr[(r0 + i) * kPanel + i];
+            if (k >= c) acc = fma(Ld[k * kPanel + i], xc[k], acc);
+          v = -acc / Ld[i * kPanel + i];
         }
         xc[i] = v;
       }
 #pragma unroll
       for (int i = 0; i < kPanel; ++i)
-        if (i < w) Xd[i * kPanelLd + c] = xc[i];
+        if (i < w) X[static_cast<int64_t>(r0 + i) * s + r0 + c] = xc[i];
     }
-    __syncthreads();
-    if (j < r0) {
-      // T(a) = sum_{k = j}^{r0 - 1} L(r0 + a, k) X(k, j), then X(r0 + a, j) = -sum_b X_rr(a, b) T(b)
-      double t[kPanel];
-#pragma unroll
-      for (int a = 0; a < kPanel; ++a) t[a] = 0.0;
-      for (int k0 = j; k0 < r0; k0 += 8) {
-        double x8[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) x8[q] = k0 + q < r0 ? X[static_cast<int64_t>(k0 + q) * s + j] : 0.0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-          if (k0 + q < r0) axpy_row32(t, x8[q], Lr + (k0 + q) * kPanel);
-      }
-      for (int a = 0; a < w; ++a) {
-        double acc = 0.0;
-#pragma unroll
-        for (int b = 0; b < kPanel; ++b)
-          if (b <= a) acc = fma(Xd[a * kPanelLd + b], t[b], acc);
-        X[static_cast<int64_t>(r0 + a) * s + j] = -acc;
-      }
-    } else if (j < r0 + w) {
-      for (int a = 0; a < w; ++a) X[static_cast<int64_t>(r0 + a) * s + j] = Xd[a * kPanelLd + (j - r0)];
+  }
+  __syncthreads();
+  for (int r0 = kPanel; r0 < sb; r0 += kPanel) {
+    const int w = min(kPanel, sb - r0);
+    // column tiles of X_rq, four to a wave in the order that evens out their lengths
+    const int ntc = r0 >> 4;
+#pragma unroll 1
+    for (int u = 0; u < 4; ++u) {
+      const int jt = (u & 1) ? 8 * ((u + 1) >> 1) - 1 - wv : 8 * (u >> 1) + wv;
+      if (jt < ntc) inv_xrq_tile(X, Lc, s, r0, w, jt, lane);
     }
     __syncthreads();
   }
@@ -919,37 +1077,39 @@ __global__ __launch_bounds__(kT) void k_inverse_blocked(double* __restrict__ slo
     }
     return;
   }
-  // G^{-1}(i, j) for rows i0 .. i0 + 31, thread j; Xt[k * kPanel + a] = X(k, i0 + a)
-  double* Xt = lds;
-  for (int i0 = 0; i0 < sb; i0 += kPanel) {
-    const int w = min(kPanel, sb - i0);
-    for (int e = tid; e < (sb - i0) * kPanel; e += kT) {
-      const int k = i0 + e / kPanel, a = e % kPanel;
-      Xt[k * kPanel + a] = (a < w && k >= i0 + a) ? X[static_cast<int64_t>(k) * s + i0 + a] : 0.0;
-    }
-    __syncthreads();
-    if (j < sb) {
-      double acc[kPanel];
-#pragma unroll
-      for (int a = 0; a < kPanel; ++a) acc[a] = 0.0;
-      for (int k0 = max(i0, j); k0 < sb; k0 += 8) {
-        double x8[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) x8[q] = k0 + q < sb ? X[static_cast<int64_t>(k0 + q) * s + j] : 0.0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-          if (k0 + q < sb) axpy_row32(acc, x8[q], Xt + (k0 + q) * kPanel);
+  // G^{-1}: jobs of up to four tiles of one tile row, dealt to the waves by the
+  // same greedy rule in every wave (the least loaded wave takes the next job)
+  {
+    const int nt = (sb + 15) >> 4;
+    int l0 = 0, l1 = 0, l2 = 0, l3 = 0;   // work dealt to each wave so far
+#pragma unroll 1
+    for (int ti = 0; ti < nt; ++ti) {
+#pragma unroll 1
+      for (int tj0 = 0; tj0 <= ti; tj0 += 4) {
+        const int cnt = min(4, ti + 1 - tj0);
+        int who = 0, lw = l0;
+        if (l1 < lw) { who = 1; lw = l1; }
+        if (l2 < lw) { who = 2; lw = l2; }
+        if (l3 < lw) who = 3;
+        const int cost = (nt - ti) * (cnt + 1);
+        l0 += who == 0 ? cost : 0;
+        l1 += who == 1 ? cost : 0;
+        l2 += who == 2 ? cost : 0;
+        l3 += who == 3 ? cost : 0;
+        if (who != wv) continue;
+        switch (cnt) {
+          case 1: ginv_tiles<1>(Gi, X, s, sb, ti, tj0, lane); break;
+          case 2: ginv_tiles<2>(Gi, X, s, sb, ti, tj0, lane); break;
+          case 3: ginv_tiles<3>(Gi, X, s, sb, ti, tj0, lane); break;
+          default: ginv_tiles<4>(Gi, X, s, sb, ti, tj0, lane); break;
+        }
       }
-#pragma unroll
-      for (int a = 0; a < kPanel; ++a)
-        if (a < w) Gi[static_cast<int64_t>(i0 + a) * s + j] = acc[a];
     }
-    __syncthreads();
   }
-  for (int e = tid; e < s * s; e += kT) {
-    const int i = e / s, jj = e - i * s;
-    if (i >= sb || jj >= sb) Gi[e] = 0.0;
-  }
+  // padding: thread j clears column j past the block (s <= kT)
+  if (tid < s)
+    for (int i = 0; i < s; ++i)
+      if (i >= sb || tid >= sb) Gi[static_cast<int64_t>(i) * s + tid] = 0.0;
   if (chk.flag) {
     __syncthreads();
     double acc = 0.0;
