@@ -163,15 +163,17 @@ __global__ __launch_bounds__(GramShape<NG>::NW * 64) void k_gram_block(
 }
 
 // The 128-row shape in FP64 (NG = 8) as the memo-miss path runs it beside the
-// resident step kernel: four waves (one per SIMD, at most 128 registers each:
-// the step kernel leaves 136) and every tile of the block in one workgroup,
-// so each entry of A_S is read once; 8-column panels keep the next panel's
-// loads within that budget.  The tiles go to the waves by
-// row groups: wave 0 takes the 10 lower tiles among groups 0-3, wave 1 those
-// among groups 4-7, waves 2 and 3 the cross tiles of groups 4-5 and 6-7 with
-// groups 0-3 (8 each).  A wave reads one operand per row group it touches (4
-// or 6 per k step) and uses it on both sides: lane l holds A[r_{16 g + l %
-// 16}, k + l / 16], the X operand for g = ti and the Y operand for g = tj.
+// resident step kernel: four waves (one per SIMD, at most 136 registers each:
+// what the step kernel leaves) and every tile of the block in one workgroup,
+// so each entry of A_S is read once; 8-column panels keep the loads of the
+// next two panels within that budget.  The tiles go to the waves by row
+// groups, nine each: wave 0 takes the lower tiles among groups 0-3 but
+// (3, 3), wave 1 those among groups 4-7 but (7, 7), waves 2 and 3 the cross
+// tiles of groups 4-5 and 6-7 with groups 0-3 and the tile (3, 3) or (7, 7),
+// whose operand they hold.  A wave reads one operand per row group it
+// touches (4 or 6 per k step) and uses it on both sides: lane l holds
+// A[r_{16 g + l % 16}, k + l / 16], the X operand for g = ti and the Y
+// operand for g = tj.
 // Same workspace layout and arguments as k_gram_block<TA, 8> (one tile part).
 template <typename TA>
 __global__ __launch_bounds__(256) void k_gram_block128(const TA* __restrict__ A, int64_t lda, int64_t n,
@@ -220,9 +222,9 @@ __global__ __launch_bounds__(256) void k_gram_block128(const TA* __restrict__ A,
     const int g = tri ? (f < 4 ? 4 * wv + f : 0) : (f < 2 ? 4 + 2 * (wv - 2) + f : f - 2);
     foff[f] = (16 * g + (lane & 15)) * LD + (lane >> 4);
   }
-  Acc acc[10];
+  Acc acc[9];
 #pragma unroll
-  for (int u = 0; u < 10; ++u) acc[u] = Acc{0, 0, 0, 0};
+  for (int u = 0; u < 9; ++u) acc[u] = Acc{0, 0, 0, 0};
 
   auto mma = [&](const TA* Pb) {
 #pragma unroll 1
@@ -231,32 +233,46 @@ __global__ __launch_bounds__(256) void k_gram_block128(const TA* __restrict__ A,
 #pragma unroll
       for (int f = 0; f < 6; ++f) F[f] = Pb[foff[f] + kk];
       if (tri) {
-        // (i, j), 0 <= j <= i < 4, in row order
+        // (i, j), 0 <= j <= i < 4, in row order, but (3, 3)
 #pragma unroll
         for (int i = 0, u = 0; i < 4; ++i)
 #pragma unroll
-          for (int j = 0; j <= i; ++j, ++u) acc[u] = Mfma<TA>::step(F[i], F[j], acc[u]);
+          for (int j = 0; j <= i && u < 9; ++j, ++u) acc[u] = Mfma<TA>::step(F[i], F[j], acc[u]);
       } else {
-        // (i, j), i < 2 (operands 0, 1), j < 4 (operands 2..5)
+        // (i, j), i < 2 (operands 0, 1), j < 4 (operands 2..5); then group 3
+        // (operand 5, wave 2) or group 7 (operand 1, wave 3) with itself
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
           for (int j = 0; j < 4; ++j) acc[4 * i + j] = Mfma<TA>::step(F[i], F[2 + j], acc[4 * i + j]);
+        const TA d = wv == 2 ? F[5] : F[1];
+        acc[8] = Mfma<TA>::step(d, d, acc[8]);
       }
     }
   };
   // panel p (columns k_begin + KC p ...) sits in LDS buffer p % 2 while the
-  // loads of panel p + 1 are in flight
+  // loads of panels p + 1 and p + 2 are in flight, in pa and pb by turns
+  // (eight registers more than one panel ahead: 136 in all, what the step
+  // kernel leaves)
   const int np = static_cast<int>((k_end - k_begin + KC - 1) / KC);
+  auto col = [&](int q) { return k_begin + static_cast<int64_t>(q) * KC; };
+  TA pb[LOADS];
   fetch(pa, k_begin);
   stash(pa, 0);
+  if (np > 1) fetch(pa, col(1));
   __syncthreads();
-  for (int p = 0; p < np; ++p) {
-    if (p + 1 < np) fetch(pa, k_begin + static_cast<int64_t>(p + 1) * KC);
-    mma(P[p & 1]);
-    if (p + 1 < np) stash(pa, (p + 1) & 1);
+  int p = 0;
+  for (; p + 1 < np; p += 2) {
+    if (p + 2 < np) fetch(pb, col(p + 2));
+    mma(P[0]);
+    stash(pa, 1);
+    __syncthreads();
+    if (p + 3 < np) fetch(pa, col(p + 3));
+    mma(P[1]);
+    if (p + 2 < np) stash(pb, 0);
     __syncthreads();
   }
+  if (p < np) mma(P[0]);
   double* W = ws + (static_cast<int64_t>(blk) * nchunks + ch) * NTILE * 256;
   auto put = [&](int u, int ti, int tj) {
     const int t = ti * (ti + 1) / 2 + tj;
@@ -268,12 +284,14 @@ __global__ __launch_bounds__(256) void k_gram_block128(const TA* __restrict__ A,
 #pragma unroll
     for (int i = 0, u = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j <= i; ++j, ++u) put(u, 4 * wv + i, 4 * wv + j);
+      for (int j = 0; j <= i && u < 9; ++j, ++u) put(u, 4 * wv + i, 4 * wv + j);
   } else {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) put(4 * i + j, 4 + 2 * (wv - 2) + i, j);
+    const int gd = wv == 2 ? 3 : 7;
+    put(8, gd, gd);
   }
 }
 
