@@ -295,6 +295,125 @@ __global__ __launch_bounds__(256) void k_gram_block128(const TA* __restrict__ A,
   }
 }
 
+// The 256-row shape (NG = 16): eight waves, every tile of the block in one
+// workgroup, 16-column panels double-buffered in LDS.  The tiles go to the
+// waves by 4 x 4 super-blocks of row groups, so that a wave reads 8 operands
+// per k step for 16 or 20 products: waves 0-5 take the off-diagonal
+// super-blocks (I, J) = (1, 0), (2, 0), (2, 1), (3, 0), (3, 1), (3, 2) (16
+// tiles each), waves 6 and 7 the lower tiles of the diagonal super-blocks 0
+// and 1, and 2 and 3 (20 each).  Same operand layout, workspace layout and
+// arguments as k_gram_block<TA, 16>.
+template <typename TA>
+__global__ __launch_bounds__(512) void k_gram_block256(const TA* __restrict__ A, int64_t lda, int64_t n,
+                                                       const int32_t* __restrict__ rows,
+                                                       const int32_t* __restrict__ lens, int32_t s,
+                                                       const int32_t* __restrict__ only, int32_t nchunks,
+                                                       int64_t chunk, double* __restrict__ ws) {
+  using Acc = typename Mfma<TA>::acc_t;
+  constexpr int NT = 512, KC = 16, LD = KC + 1, R = 256, NTILE = 136, LOADS = R * KC / NT;
+  __shared__ TA P[2][R * LD];
+  __shared__ int32_t ri[R];
+  const int ch = blockIdx.x, blk = blockIdx.z;
+  if (only && !only[blk]) return;
+  const int sb = lens[blk];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int32_t* Rw = rows + static_cast<int64_t>(blk) * s;
+  for (int i = tid; i < R; i += NT) ri[i] = i < sb ? Rw[i] : -1;
+  __syncthreads();
+  const int64_t k_begin = static_cast<int64_t>(ch) * chunk;
+  const int64_t k_end = min(n, k_begin + chunk);
+
+  TA pa[LOADS];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < LOADS; ++q) {
+      const int e = tid + NT * q;
+      const int r = e / KC, c = e % KC;
+      const int64_t k = k0 + c;
+      const int32_t row = ri[r];
+      pa[q] = (row >= 0 && k < k_end) ? A[static_cast<int64_t>(row) * lda + k] : TA(0);
+    }
+  };
+  auto stash = [&](int b) {
+#pragma unroll
+    for (int q = 0; q < LOADS; ++q) {
+      const int e = tid + NT * q;
+      P[b][(e / KC) * LD + e % KC] = pa[q];
+    }
+  };
+
+  // operand f of this wave: row group gop(f)
+  const bool diag = wv >= 6;
+  const int I = wv < 1 ? 1 : (wv < 3 ? 2 : 3);
+  const int J = wv - I * (I - 1) / 2;
+  int foff[8];
+#pragma unroll
+  for (int f = 0; f < 8; ++f) {
+    const int g = diag ? 8 * (wv - 6) + f : (f < 4 ? 4 * I + f : 4 * J + f - 4);
+    foff[f] = (16 * g + (lane & 15)) * LD + (lane >> 4);
+  }
+  Acc acc[20];
+#pragma unroll
+  for (int u = 0; u < 20; ++u) acc[u] = Acc{0, 0, 0, 0};
+
+  auto mma = [&](const TA* Pb) {
+#pragma unroll 1
+    for (int kk = 0; kk < KC; kk += 4) {
+      TA F[8];
+#pragma unroll
+      for (int f = 0; f < 8; ++f) F[f] = Pb[foff[f] + kk];
+      if (diag) {
+        // (i, j), 0 <= j <= i < 4, of both diagonal super-blocks, in row order
+#pragma unroll
+        for (int h = 0, u = 0; h < 2; ++h)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j <= i; ++j, ++u) acc[u] = Mfma<TA>::step(F[4 * h + i], F[4 * h + j], acc[u]);
+      } else {
+        // (4 I + a, 4 J + b)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[4 * a + b] = Mfma<TA>::step(F[a], F[4 + b], acc[4 * a + b]);
+      }
+    }
+  };
+  const int np = static_cast<int>((k_end - k_begin + KC - 1) / KC);
+  fetch(k_begin);
+  stash(0);
+  __syncthreads();
+  for (int p = 0; p < np; ++p) {
+    if (p + 1 < np) fetch(k_begin + static_cast<int64_t>(p + 1) * KC);
+    mma(P[p & 1]);
+    if (p + 1 < np) stash((p + 1) & 1);
+    __syncthreads();
+  }
+  double* W = ws + (static_cast<int64_t>(blk) * nchunks + ch) * NTILE * 256;
+  auto put = [&](int u, int ti, int tj) {
+    const int t = ti * (ti + 1) / 2 + tj;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      W[t * 256 + Mfma<TA>::row(lane, r) * 16 + (lane & 15)] = static_cast<double>(acc[u][r]);
+  };
+  if (diag) {
+#pragma unroll
+    for (int h = 0, u = 0; h < 2; ++h)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j, ++u) {
+          const int g0 = 8 * (wv - 6) + 4 * h;
+          put(u, g0 + i, g0 + j);
+        }
+  } else {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) put(4 * a + b, 4 * I + a, 4 * J + b);
+  }
+}
+
 // G[slot][j * s + i] = sum over chunks of the partial tiles (+ lambda on the
 // diagonal), lower triangle of the block only; chunks summed in order, with
 // eight loads in flight
@@ -333,6 +452,11 @@ static void launch_block_grams(const TA* A, int64_t lda, int64_t n, const int32_
   using Sh = GramShape<NG>;
   if constexpr (NG == 8 && sizeof(TA) == 8) {
     hipLaunchKernelGGL((k_gram_block128<TA>), dim3(nc, 1, nb), dim3(256), 0, st, A, lda, n, rows, lens, s, only, nc,
+                       chunk, ws);
+    return;
+  }
+  if constexpr (NG == 16) {
+    hipLaunchKernelGGL((k_gram_block256<TA>), dim3(nc, 1, nb), dim3(512), 0, st, A, lda, n, rows, lens, s, only, nc,
                        chunk, ws);
     return;
   }
