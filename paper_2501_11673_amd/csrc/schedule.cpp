@@ -20,20 +20,35 @@ BlockSchedule::BlockSchedule(MemoMode mode, int64_t N, int32_t s, uint64_t seed,
     : mode_(mode), N_(N), s_(s), B0_(B0), g_(seed) {
   if (s < 1 || N < s) throw std::invalid_argument("block size must satisfy 1 <= s <= rows");
   perm_.resize(static_cast<size_t>(N));
+  if (N <= kBitmapMaxRows) bits_.assign(static_cast<size_t>((N + 63) / 64), 0);
   if (mode_ == MemoMode::Fixed) {
     if (partition) {
       std::iota(perm_.begin(), perm_.end(), 0);
-      for (int64_t j = 0; j + 1 < N; ++j) {
-        int64_t k = j + static_cast<int64_t>(g_.bounded(static_cast<uint64_t>(N - j)));
-        std::swap(perm_[j], perm_[k]);
+      // the swap targets depend on the draws alone: each batch is drawn first
+      // and its targets prefetched, then swapped in order
+      constexpr int64_t kBatch = 32;
+      int64_t kb[kBatch];
+      for (int64_t j0 = 0; j0 + 1 < N; j0 += kBatch) {
+        const int64_t nj = std::min<int64_t>(kBatch, N - 1 - j0);
+        for (int64_t u = 0; u < nj; ++u) {
+          kb[u] = j0 + u + static_cast<int64_t>(g_.bounded(static_cast<uint64_t>(N - j0 - u)));
+          __builtin_prefetch(&perm_[kb[u]], 1);
+        }
+        for (int64_t u = 0; u < nj; ++u) std::swap(perm_[j0 + u], perm_[kb[u]]);
       }
-      for (int64_t lo = 0; lo < N; lo += s) {
-        int32_t l = static_cast<int32_t>(std::min<int64_t>(s, N - lo));
-        size_t base = rows_.size();
-        rows_.resize(base + s, -1);
-        std::copy(perm_.begin() + lo, perm_.begin() + lo + l, rows_.begin() + base);
-        std::sort(rows_.begin() + base, rows_.begin() + base + l);
-        len_.push_back(l);
+      // chunk c is positions c s .. c s + l - 1 of the permutation, its rows in
+      // ascending order: one pass over the rows, each to the chunk of its position
+      const int64_t nchunks = (N + s - 1) / s;
+      rows_.assign(static_cast<size_t>(nchunks * s), -1);
+      len_.resize(static_cast<size_t>(nchunks));
+      for (int64_t c = 0; c < nchunks; ++c) len_[c] = static_cast<int32_t>(std::min<int64_t>(s, N - c * s));
+      std::vector<int32_t> chunk_of(static_cast<size_t>(N));
+      for (int64_t c = 0; c < nchunks; ++c)
+        for (int64_t j = c * s; j < c * s + len_[c]; ++j) chunk_of[perm_[j]] = static_cast<int32_t>(c);
+      std::vector<int32_t> fill(static_cast<size_t>(nchunks), 0);
+      for (int64_t r = 0; r < N; ++r) {
+        const int64_t c = chunk_of[r];
+        rows_[static_cast<size_t>(c * s + fill[c]++)] = static_cast<int32_t>(r);
       }
     } else {
       if (num_blocks < 1) throw std::invalid_argument("fixed collection needs num_blocks >= 1");
@@ -48,7 +63,7 @@ BlockSchedule::BlockSchedule(MemoMode mode, int64_t N, int32_t s, uint64_t seed,
 
 // Partial Fisher-Yates on the identity permutation (perm_ is the identity on
 // entry and on exit: only the positions the draws touched are put back, so a
-// subset costs O(s log s), not O(N)).
+// subset costs O(s log s), or O(s + N / 64) with the bitmap, not O(N)).
 void BlockSchedule::add_subset() {
   touched_.clear();
   for (int32_t j = 0; j < s_; ++j) {
@@ -58,8 +73,27 @@ void BlockSchedule::add_subset() {
   }
   size_t base = rows_.size();
   rows_.resize(base + s_);
-  std::copy(perm_.begin(), perm_.begin() + s_, rows_.begin() + base);
-  std::sort(rows_.begin() + base, rows_.end());
+  int32_t* out = rows_.data() + base;
+  if (!bits_.empty()) {
+    // the rows are distinct: set their bits, then read them back in order
+    for (int32_t j = 0; j < s_; ++j) {
+      const int32_t r = perm_[j];
+      bits_[static_cast<size_t>(r) >> 6] |= uint64_t{1} << (r & 63);
+    }
+    int32_t o = 0;
+    for (size_t w = 0; o < s_; ++w) {
+      uint64_t v = bits_[w];
+      if (v == 0) continue;
+      bits_[w] = 0;
+      do {
+        out[o++] = static_cast<int32_t>(w * 64 + static_cast<size_t>(__builtin_ctzll(v)));
+        v &= v - 1;
+      } while (v != 0);
+    }
+  } else {
+    std::copy(perm_.begin(), perm_.begin() + s_, out);
+    std::sort(out, out + s_);
+  }
   len_.push_back(s_);
   for (int32_t j = 0; j < s_; ++j) perm_[j] = static_cast<int32_t>(j);
   for (int64_t k : touched_) perm_[k] = static_cast<int32_t>(k);

@@ -54,6 +54,10 @@ class SplitMix64 {
 
 enum class MemoMode : int32_t { Off = 0, Online = 1, Fixed = 2 };
 
+// Row counts up to this order a new subset's rows through a bitmap of all rows
+// (a scan of N / 64 words) instead of a comparison sort.
+constexpr int64_t kBitmapMaxRows = int64_t{1} << 18;
+
 // Sequential schedule generator: next() yields the block of step 0, 1, 2, ...
 class BlockSchedule {
  public:
@@ -95,6 +99,7 @@ class BlockSchedule {
   std::vector<uint8_t> used_;
   std::vector<int32_t> perm_;
   std::vector<int64_t> touched_;
+  std::vector<uint64_t> bits_;   // one bit per row (N <= kBitmapMaxRows): a subset's rows in order
   bool explicit_ = false;
   std::vector<int32_t> seq_;
 };
