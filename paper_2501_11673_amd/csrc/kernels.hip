@@ -468,6 +468,26 @@ __global__ __launch_bounds__(kT) void k_cholesky(double* __restrict__ G, int32_t
 // --------------------------------------------------------------------------
 // ||A x - b||^2: one wave per row, 4 rows per workgroup; then a fixed-order sum
 // --------------------------------------------------------------------------
+// sum_j A_i[j] x[j] over this lane's entries j = lane, lane + 64, ... in that
+// order (one FMA chain), with eight entries of each operand in flight
+__device__ __forceinline__ double row_dot_lane(const double* __restrict__ Ai, const double* __restrict__ x, int64_t n,
+                                               int lane) {
+  double acc = 0.0;
+  int64_t j = lane;
+  for (; j + 7 * 64 < n; j += 8 * 64) {
+    double a[8], v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a[u] = Ai[j + 64 * u];
+      v[u] = x[j + 64 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = fma(a[u], v[u], acc);
+  }
+  for (; j < n; j += 64) acc = fma(Ai[j], x[j], acc);
+  return acc;
+}
+
 __global__ __launch_bounds__(kT) void k_residual_rows(const double* __restrict__ A, int64_t lda,
                                                       int64_t m, int64_t n,
                                                       const double* __restrict__ x,
@@ -476,9 +496,7 @@ __global__ __launch_bounds__(kT) void k_residual_rows(const double* __restrict__
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= m) return;
-  const double* Ai = A + i * lda;
-  double acc = 0.0;
-  for (int64_t j = lane; j < n; j += 64) acc = fma(Ai[j], x[j], acc);
+  double acc = row_dot_lane(A + i * lda, x, n, lane);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) {
@@ -490,8 +508,17 @@ __global__ __launch_bounds__(kT) void k_residual_rows(const double* __restrict__
 __global__ __launch_bounds__(kT) void k_sum(const double* __restrict__ v, int64_t len,
                                             double* __restrict__ out) {
   __shared__ double red[4];
+  // thread t adds v[t], v[t + kT], ... in order, eight loads in flight
   double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < len; i += kT) acc += v[i];
+  int64_t i = threadIdx.x;
+  for (; i + 7 * kT < len; i += 8 * kT) {
+    double w[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) w[u] = v[i + static_cast<int64_t>(kT) * u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += w[u];
+  }
+  for (; i < len; i += kT) acc += v[i];
   acc = block_sum(acc, red);
   if (threadIdx.x == 0) *out = acc;
 }
@@ -537,9 +564,7 @@ __global__ __launch_bounds__(kT) void k_residual_vec(const double* __restrict__ 
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= m) return;
-  const double* Ai = A + i * lda;
-  double acc = 0.0;
-  for (int64_t j = lane; j < n; j += 64) acc = fma(Ai[j], x[j], acc);
+  double acc = row_dot_lane(A + i * lda, x, n, lane);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) {
