@@ -301,8 +301,8 @@ __global__ __launch_bounds__(256) void k_gram_block128(const TA* __restrict__ A,
 // per k step for 16 or 20 products: waves 0-5 take the off-diagonal
 // super-blocks (I, J) = (1, 0), (2, 0), (2, 1), (3, 0), (3, 1), (3, 2) (16
 // tiles each), waves 6 and 7 the lower tiles of the diagonal super-blocks 0
-// and 1, and 2 and 3 (20 each).  Same operand layout, workspace layout and
-// arguments as k_gram_block<TA, 16>.
+// and 1, and 2 and 3 (20 each).  Same operand layout, workspace layout
+// (136 tiles per block and chunk) and arguments as k_gram_block.
 template <typename TA>
 __global__ __launch_bounds__(512) void k_gram_block256(const TA* __restrict__ A, int64_t lda, int64_t n,
                                                        const int32_t* __restrict__ rows,
@@ -453,15 +453,13 @@ static void launch_block_grams(const TA* A, int64_t lda, int64_t n, const int32_
   if constexpr (NG == 8 && sizeof(TA) == 8) {
     hipLaunchKernelGGL((k_gram_block128<TA>), dim3(nc, 1, nb), dim3(256), 0, st, A, lda, n, rows, lens, s, only, nc,
                        chunk, ws);
-    return;
-  }
-  if constexpr (NG == 16) {
+  } else if constexpr (NG == 16) {
     hipLaunchKernelGGL((k_gram_block256<TA>), dim3(nc, 1, nb), dim3(512), 0, st, A, lda, n, rows, lens, s, only, nc,
                        chunk, ws);
-    return;
+  } else {
+    hipLaunchKernelGGL((k_gram_block<TA, NG>), dim3(nc, Sh::PARTS, nb), dim3(Sh::NW * 64), 0, st, A, lda, n, rows,
+                       lens, s, only, nc, chunk, ws);
   }
-  hipLaunchKernelGGL((k_gram_block<TA, NG>), dim3(nc, Sh::PARTS, nb), dim3(Sh::NW * 64), 0, st, A, lda, n, rows, lens,
-                     s, only, nc, chunk, ws);
 }
 
 template <typename TA>

@@ -579,13 +579,30 @@ __global__ __launch_bounds__(kT) void k_axpy1(double* __restrict__ x, const doub
   if (j < n) x[j] += d[j];
 }
 
-__global__ void k_state_init(DevState* ds, double rho0, double thr) {
-  DevState s{};
-  s.rho = rho0;
-  s.c = (1.0 - rho0) / (1.0 + rho0);
-  s.thr = thr;
-  s.rho_before = rho0;
-  *ds = s;
+// A run's starting state (rho = rho0, c from rho0, the stop threshold), its
+// error flag cleared and its momentum zeroed, in one launch.
+__global__ __launch_bounds__(kT) void k_state_init(DevState* __restrict__ ds, double rho0, double thr,
+                                                   int32_t* __restrict__ err, double* __restrict__ mom, int64_t n) {
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
+  for (int64_t i = i0; i < n; i += static_cast<int64_t>(gridDim.x) * kT) mom[i] = 0.0;
+  if (i0 == 0) {
+    DevState s{};
+    s.rho = rho0;
+    s.c = (1.0 - rho0) / (1.0 + rho0);
+    s.thr = thr;
+    s.rho_before = rho0;
+    *ds = s;
+    *err = 0;
+  }
+}
+
+// Up to three vectors zeroed in one launch (length 0 skips one).
+__global__ __launch_bounds__(kT) void k_zero3(double* __restrict__ a, int64_t na, double* __restrict__ b, int64_t nb,
+                                              double* __restrict__ c, int64_t nc) {
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x, step = static_cast<int64_t>(gridDim.x) * kT;
+  for (int64_t i = i0; i < na; i += step) a[i] = 0.0;
+  for (int64_t i = i0; i < nb; i += step) b[i] = 0.0;
+  for (int64_t i = i0; i < nc; i += step) c[i] = 0.0;
 }
 
 
@@ -1773,8 +1790,16 @@ void launch_axpy1(double* x, const double* d, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_axpy1, dim3(static_cast<unsigned>((n + kT - 1) / kT)), dim3(kT), 0, st, x, d, n);
 }
 
-void launch_state_init(DevState* ds, double rho0, double thr, hipStream_t st) {
-  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, st, ds, rho0, thr);
+void launch_state_init(DevState* ds, double rho0, double thr, int32_t* err, double* mom, int64_t n, hipStream_t st) {
+  const int64_t g = std::max<int64_t>(1, std::min<int64_t>((n + kT - 1) / kT, 1024));
+  hipLaunchKernelGGL(k_state_init, dim3(static_cast<unsigned>(g)), dim3(kT), 0, st, ds, rho0, thr, err, mom, n);
+}
+
+void launch_zero3(double* a, int64_t na, double* b, int64_t nb, double* c, int64_t nc, hipStream_t st) {
+  const int64_t n = std::max(na, std::max(nb, nc));
+  if (n <= 0) return;
+  const int64_t g = std::min<int64_t>((n + kT - 1) / kT, 1024);
+  hipLaunchKernelGGL(k_zero3, dim3(static_cast<unsigned>(g)), dim3(kT), 0, st, a, na, b, nb, c, nc);
 }
 
 }  // namespace kpp

@@ -145,7 +145,10 @@ void launch_residual_sq(const double* A, int64_t lda, int64_t m, int64_t n, cons
 void launch_check_finite(const double* A, int64_t lda, int64_t m, int64_t n, const double* b,
                          int32_t* flag, hipStream_t st);
 
-void launch_state_init(DevState* ds, double rho0, double thr, hipStream_t st);
+// the run's starting state, *err = 0 and mom[0..n) = 0, in one launch
+void launch_state_init(DevState* ds, double rho0, double thr, int32_t* err, double* mom, int64_t n, hipStream_t st);
+// a[0..na), b[0..nb), c[0..nc) = 0 in one launch
+void launch_zero3(double* a, int64_t na, double* b, int64_t nb, double* c, int64_t nc, hipStream_t st);
 
 // out[i * n + j] = (float) A[i * lda + j]   (row-major FP32 copy, leading dimension n)
 void launch_convert_f32(const double* A, int64_t lda, int64_t m, int64_t n, float* out, hipStream_t st);

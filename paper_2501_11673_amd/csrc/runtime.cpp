@@ -871,9 +871,9 @@ class CoreRun {
       KPP_TRY(dev_alloc(&sys->rpart, static_cast<size_t>(s_) * P_));
       sys->rpart_cap = static_cast<int64_t>(s_) * P_;
     }
-    HIP_TRY(hipMemsetAsync(sys->err, 0, sizeof(int32_t), st_));
     const double thr = o.tol * o.tol * src.bnorm * src.bnorm;
     if (o.resume) {
+      HIP_TRY(hipMemsetAsync(sys->err, 0, sizeof(int32_t), st_));
       // the momentum is still (or was imported) on the device
       kpp::DevState d = hs_;
       d.thr = thr;
@@ -881,8 +881,7 @@ class CoreRun {
       HIP_TRY(hipMemcpyAsync(sys->ds, sys->h_ds, sizeof(kpp::DevState), hipMemcpyHostToDevice, st_));
       HIP_TRY(hipStreamSynchronize(st_));
     } else {
-      HIP_TRY(hipMemsetAsync(sys->mom, 0, n_ * sizeof(double), st_));
-      kpp::launch_state_init(sys->ds, o.rho0, thr, st_);
+      kpp::launch_state_init(sys->ds, o.rho0, thr, sys->err, sys->mom, n_, st_);
     }
     HIP_TRY(hipGetLastError());
     const char* prof_env = std::getenv("KPP_PHASE_PROFILE");
@@ -2100,11 +2099,7 @@ kpp_status solve_mixed(kpp_system* sys, const kpp_params* p, double* x, kpp_resu
       }
       break;
     }
-    HIP_TRY(hipMemsetAsync(sys->dvec, 0, n * sizeof(double), st));
-    if (wide) {
-      HIP_TRY(hipMemsetAsync(sys->zx, 0, m * sizeof(double), st));
-      HIP_TRY(hipMemsetAsync(sys->zm, 0, m * sizeof(double), st));
-    }
+    kpp::launch_zero3(sys->dvec, n, sys->zx, wide ? m : 0, sys->zm, wide ? m : 0, st);
     Source src;
     if (bf16)
       src.A16 = sys->A16;

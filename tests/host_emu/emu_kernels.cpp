@@ -317,11 +317,21 @@ void launch_column(const double* X, int64_t ldx, int64_t n, int32_t c, double* o
   emu_check(out, 8 * static_cast<size_t>(n), "column out");
 }
 
-void launch_state_init(DevState* ds, double rho0, double thr, hipStream_t) {
+void launch_state_init(DevState* ds, double rho0, double thr, int32_t* err, double* mom, int64_t n, hipStream_t) {
   emu_check(ds, sizeof(DevState), "state init");
+  emu_check(err, sizeof(int32_t), "state init err");
+  emu_check(mom, 8 * static_cast<size_t>(n), "state init mom");
   DevState s{};
   s.rho = rho0; s.c = (1 - rho0) / (1 + rho0); s.thr = thr; s.rho_before = rho0;
   *ds = s;
+  *err = 0;
+  for (int64_t i = 0; i < n; ++i) mom[i] = 0.0;
+}
+void launch_zero3(double* a, int64_t na, double* b, int64_t nb, double* c, int64_t nc, hipStream_t) {
+  emu_check(a, 8 * static_cast<size_t>(na), "zero3 a");
+  for (int64_t i = 0; i < na; ++i) a[i] = 0.0;
+  if (nb > 0) { emu_check(b, 8 * static_cast<size_t>(nb), "zero3 b"); for (int64_t i = 0; i < nb; ++i) b[i] = 0.0; }
+  if (nc > 0) { emu_check(c, 8 * static_cast<size_t>(nc), "zero3 c"); for (int64_t i = 0; i < nc; ++i) c[i] = 0.0; }
 }
 void launch_convert_f32(const double* A, int64_t lda, int64_t m, int64_t n, float* out, hipStream_t) {
   emu_check(A, 8 * (static_cast<size_t>(m - 1) * lda + n), "convert A");
