@@ -13,8 +13,11 @@ ms_per_step = time to tolerance per solve.  Inputs are synthetic and seeded
 and are resident in HBM before the timed region.
 
 Under "mixed": the same solves with mixed precision (FP32 block products,
-FP64 factors, FP64 iterative refinement), with the speed-up over FP64 and the
-error against the FP64 solution; under "bf16" one solve with bfloat16
+FP64 factors, FP64 iterative refinement, the library's default inner
+tolerance), with the speed-up over FP64 and the error against the FP64
+solution, and under "mixed"/"seeds" FP64 and mixed on the same system for two
+further schedule seeds (the step count to tolerance of either depends on the
+seed) with the means over the three; under "bf16" one solve with bfloat16
 storage of A (reported whether or not it converges), and under
 "precisions_well_conditioned" FP64, FP32 and bfloat16 on a kappa = 10 system
 of the headline's shape.  Under "kpp_65536x2048": the over-determined
@@ -260,6 +263,32 @@ def fp64_and_mixed(kpp, torch, dev, ctx, name, warmup, steps, profile=None, engi
     rec["workload"] = {"name": name, "m": m, "n": n, "block": cfg["s"], "lambda": cfg["lam"],
                        "memo": "fixed partition" if p.memo == kpp.KPP_MEMO_FIXED else "online", "tol": 1e-10}
     return rec, (sysm, h, p, x64)
+
+
+def seed_comparison(kpp, torch, h, p, x, head, seeds=(11, 12345), reps=2):
+    """FP64 against mixed precision on the headline system for further
+    schedule seeds (the step count to 1e-10 of either depends on the seed):
+    time to tolerance per seed (mean of `reps` timed solves after one warm-up)
+    and the means over these seeds and the headline's."""
+    rows = [{"seed": int(p.seed), "fp64_ms": head["time_to_tol_ms"], "mixed_ms": head["mixed"]["time_to_tol_ms"],
+             "fp64_iters": head["iters_per_solve"], "mixed_iters": head["mixed"]["iters_per_solve"]}]
+    for sd in seeds:
+        row = {"seed": sd}
+        for tag, prec in (("fp64", kpp.KPP_FP64), ("mixed", kpp.KPP_MIXED_FP32)):
+            q = copy_params(kpp, None, p)
+            q.seed = sd
+            q.precision = prec
+            q.engine = 0
+            q.no_launch_timing = 1
+            results, elapsed = timed_solves(kpp, torch, h, q, x, 1, reps)
+            row[f"{tag}_ms"] = 1e3 * elapsed / reps
+            row[f"{tag}_iters"] = results[-1][1].iters
+            row[f"{tag}_converged"] = all(st == kpp.KPP_OK and r.converged for st, r in results)
+        rows.append(row)
+    f = sum(r["fp64_ms"] for r in rows) / len(rows)
+    mx = sum(r["mixed_ms"] for r in rows) / len(rows)
+    return {"per_seed": rows, "fp64_mean_ms": f, "mixed_mean_ms": mx, "speedup_of_means": f / mx,
+            "inner_tol": p.inner_tol}
 
 
 def blas_threads():
@@ -892,6 +921,8 @@ def main():
         line[k] = head[k]
     line["roofline"] = head["roofline"]
     line["mixed"] = head["mixed"]
+    if not args.headline_only:
+        line["mixed"]["seeds"] = seed_comparison(kpp, torch, h4, p4, x4, head)
     if "bf16" in head:
         line["bf16"] = head["bf16"]
     if args.calibrate_copy > 0:

@@ -112,8 +112,9 @@ typedef struct kpp_params {
                                  schedule settings; 0: start with an empty cache          */
   int32_t refine_max_rounds;  /* mixed precision: outer refinement rounds (default 40)   */
   double inner_tol;           /* mixed precision: relative tolerance of each inner solve
-                                 (default 1e-2); an inner solve also ends when its
-                                 residual estimate stalls (FP32 precision floor)    */
+                                 (default 1e-3 for Kaczmarz++, 1e-2 for CD++); an inner
+                                 solve also ends when its residual estimate stalls
+                                 (FP32 precision floor)                               */
   int32_t engine;             /* 0: auto, 1: one launch per phase, 2: fused persistent  */
   int32_t team_groups;        /* fused engine: workgroups sharing one step (0: auto)    */
   /* Optional caller-given block schedule (host memory, read during kpp_solve;
