@@ -685,6 +685,11 @@ struct CoreOpts {
   int32_t stop_on_stall = 0;
   // time each step-kernel launch with a pair of HIP events (kernel seconds)
   bool time_launches = true;
+  // leave Grams and factors enqueued ahead on the side stream in flight when
+  // the run ends (a run that follows on the same system orders its first
+  // step after them through its own first window's factor event; the caller
+  // waits for them before it returns)
+  bool defer_side_wait = false;
   // duals of the iterate and momentum (m entries each, zero on entry), kept
   // by the fused engine for Kaczmarz++ when every workgroup's share of the m
   // rows fits its registers; CoreStats::dual says whether they were
@@ -1370,7 +1375,10 @@ class CoreRun {
   // Wait for the system's side-stream work (factorizations planned past the
   // stop included) and report the run.
   kpp_status end(CoreStats* cs) {
-    KPP_TRY(wait_side_work(sys_));
+    if (o_.defer_side_wait)
+      side_deferred_ = true;
+    else
+      KPP_TRY(wait_side_work(sys_));
     if (o_.confirm && (!converged_ || std::isnan(true_rel_))) {
       double rn = 0.0;
       KPP_TRY(residual_norm(sys_, x_, &rn));
@@ -1413,7 +1421,7 @@ class CoreRun {
 
   // Wait for this system's side-stream work (used on every exit path).
   void drain() {
-    if (begun_) (void)wait_side_work(sys_);
+    if (begun_ && !side_deferred_) (void)wait_side_work(sys_);
   }
 
  private:
@@ -1498,6 +1506,9 @@ class CoreRun {
     const double tg = wall_now();
     KPP_TRY(ensure_stage(sys, idx, need));
     t_prof_grow += wall_now() - tg;
+    // the copy out of this host buffer that an earlier run left in flight on
+    // the side stream has been read before the buffer is written again
+    HIP_TRY(hipEventSynchronize(sys->ev_fact[idx][0]));
     int32_t* stage = sys->h_stage[idx];
     for (int32_t k = 0; k < w.nb; ++k) {
       const int32_t b = pending[k];
@@ -1814,6 +1825,7 @@ class CoreRun {
   double* x_ = nullptr;
   hipStream_t st_ = nullptr, side_ = nullptr;
   bool fp32_ = false, bf16_ = false, fused_ = false, phase_prof_ = false, stop_on_cand_ = false, begun_ = false;
+  bool side_deferred_ = false;   // end() left the side stream's work in flight (CoreOpts::defer_side_wait)
   int32_t chunk_ = 1;   // sketches per batched factoring (LSQR projection)
   int32_t kind_ = 0, s_ = 0, zeta_ = 0, periods_ = 1, cpl_ = 0, groups_ = 0, P_ = 0;
   int64_t m_ = 0, n_ = 0, N_ = 0, period_ = 0, max_iters_ = 0;
@@ -2037,6 +2049,12 @@ kpp_status solve_fp64(kpp_system* sys, const kpp_params* p, double* x, kpp_resul
 // solve returns the iterate with the lowest true residual it saw.
 kpp_status solve_mixed(kpp_system* sys, const kpp_params* p, double* x, kpp_result* res) {
   sys->res_valid = false;   // the inner runs reuse the momentum buffer
+  // the inner runs leave their factors enqueued ahead in flight; every exit
+  // waits for them
+  struct SideWait {
+    kpp_system* s;
+    ~SideWait() { (void)wait_side_work(s); }
+  } side_wait{sys};
   using clock = std::chrono::steady_clock;
   const auto t0 = clock::now();
   hipStream_t st = sys->ctx->stream;
@@ -2115,6 +2133,7 @@ kpp_status solve_mixed(kpp_system* sys, const kpp_params* p, double* x, kpp_resu
     o.confirm = 0;
     o.stop_on_stall = 1;
     o.time_launches = p->no_launch_timing == 0;
+    o.defer_side_wait = true;
     o.rho0 = rho;
     o.keep_memo = rounds > 0 ? 1 : p->keep_memo;
     o.max_iters = p->max_iters - iters;
@@ -2137,6 +2156,9 @@ kpp_status solve_mixed(kpp_system* sys, const kpp_params* p, double* x, kpp_resu
     est = rn > 0 ? std::sqrt(cs.hs.last_E1) / rn : 0.0;
     last = cs;
   }
+  // the last inner run's Grams and factors enqueued ahead (they fill slots
+  // that later solves may use, and the FP64-redo counter)
+  KPP_TRY(wait_side_work(sys));
   fill_result(res, sys, p, iters, hits, misses, converged, rounds, last, true_rel, est, rho,
               std::chrono::duration<double>(clock::now() - t0).count(), t_factor, t_kernel, launches, ckpts,
               bf16 ? 2.0 : 4.0);
@@ -3459,6 +3481,7 @@ KPP_API kpp_status kpp_system_destroy(kpp_system* sys) {
   if (!sys) return KPP_OK;
   if (sys->ctx) (void)hipSetDevice(sys->ctx->device);
   if (sys->ctx) (void)hipStreamSynchronize(sys->ctx->stream);
+  if (sys->ctx && sys->ctx->side) (void)hipStreamSynchronize(sys->ctx->side);
   destroy_buffers(sys);
   delete sys;
   return KPP_OK;
