@@ -97,6 +97,11 @@ CASES = [
     ("general", 500, 40, "fixed", 7, 400, 9, 33, False),
     ("psd", 97, 97, "off", 5, 120, 3, 0, True),
     ("psd", 1, 1, "fixed", 1, 10, 1, 0, True),
+    # row counts on both sides of the library's bitmap ordering of a subset
+    # (up to 2^18 rows) and a partition far above it
+    ("general", 262144, 64, "online", 128, 120, 79, 0, True),
+    ("general", 300000, 64, "online", 64, 200, 77, 0, True),
+    ("general", 300000, 64, "fixed", 256, 100, 78, 0, True),
 ]
 
 
