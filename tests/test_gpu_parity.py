@@ -248,6 +248,28 @@ def test_large_blocks_match_oracle(env, name, kind, m, n, s, lam, mode, T):
         gpu_solve(env, A, b, kind, s, lam=lam, T=T, mode=mode, seed=19, engine=2)
 
 
+@pytest.mark.parametrize("kind,m,n", [("general", 1100, 300), ("psd", 700, 700)])
+@pytest.mark.parametrize("s", [129, 176, 255])
+def test_panel_factor_block_sizes_match_oracle(env, kind, m, n, s):
+    """Blocks of 129..256 rows (the LDS-panel Cholesky and the matrix-core
+    inverse), at sizes that are not multiples of the 32-row panels or the
+    16-row tiles, with a ragged last block of the partition, on the fused
+    engine."""
+    sysm = synth.tiny_system(kind, m, n, seed=s + 7, cond=30.0)
+    A, b = sysm.A, sysm.b
+    lam, T = 1e-6, 60
+    print(f"[parity] panel factor kind={kind} shape={A.shape} s={s} T={T}", flush=True)
+    x, st, res = gpu_solve(env, A, b, kind, s, lam=lam, T=T, mode="fixed", seed=23)
+    assert res.iters == T
+    ref = oracle_solve(A, b, kind, s, lam=lam, T=T, mode="fixed", seed=23)
+    bound, nf, rho_bound = parity_bound(A, b, kind, s, ref, lam=lam, T=T, mode="fixed", seed=23)
+    err = relerr(x, ref.x)
+    print(f"[parity] panel factor s={s}: {err:.3e} (noise floor {nf:.3e})", flush=True)
+    assert err <= bound
+    assert res.memo_misses == ref.factorizations
+    assert abs(res.rho_final - ref.rho_final) <= rho_bound
+
+
 def test_converges_like_oracle_c1(env):
     sysm = synth.config("c1")
     A, b = sysm.A, sysm.b
