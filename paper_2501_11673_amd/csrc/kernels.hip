@@ -917,9 +917,10 @@ __global__ __launch_bounds__(kT) void k_cholesky_panel(double* __restrict__ G, i
 // the slot's last third.  Then G^{-1}(i, j) = sum_{k >= max(i, j)}
 // X(k, i) X(k, j), the 16 x 16 tiles of the lower triangle on the matrix cores
 // and each stored with its mirror image, so the inverse is exactly symmetric.
-// Entries of X above the diagonal and past the block are never read (the
-// loads are masked).  With chk.flag the Frobenius condition number is tested
-// as in k_factor_inverse.
+// The diagonal blocks of X are written whole (zeros above their diagonal);
+// other entries above the diagonal, and entries past the block, are never
+// read (the loads are masked).  With chk.flag the Frobenius condition number
+// is tested as in k_factor_inverse.
 // --------------------------------------------------------------------------
 
 // Column tile jt of X_rq (rows r0 .. r0 + w - 1, columns 16 jt .. 16 jt + 15,
